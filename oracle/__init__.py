@@ -1,0 +1,207 @@
+"""FP64 CPU oracle for the lattice-kinetic MHD step (arXiv 2112.13930).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg are the only callers.  The product library never imports,
+links or executes anything here, and this package imports nothing from it.
+
+Contents
+  lks_oracle.c   plain C reference step (pull stream, wall closures, moments,
+                 coupled u/J solve, BGK collisions) -- built into
+                 liblks_oracle.so by :func:`build`.
+  analytic.py    closed-form Hartmann (Chang-Lundgren) and Hartmann-Couette
+                 profiles of Sec. VIII and App. C.
+  derive.py      lattice parameters (nu, eta, a, B0, F_x, theta) from the
+                 physical ones, per Secs. IV, V, VI and VIII.
+  steady.py      run-to-steady driver with the residual used for stopping.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "lks_oracle.c")
+LIB = os.path.join(HERE, "liblks_oracle.so")
+
+LINK, MOMENT = 0, 1
+NPLANES = 19
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (-O2, no contraction, no fast-math)."""
+    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
+        return LIB
+    tmp = LIB + ".tmp"
+    cmd = ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math",
+           "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra", "-o", tmp, SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("bc", ctypes.c_int32),
+        ("pad_", ctypes.c_int32),
+        ("tau_f", ctypes.c_double), ("tau_m", ctypes.c_double),
+        ("b0", ctypes.c_double), ("fx", ctypes.c_double), ("fy", ctypes.c_double),
+        ("c_lo", ctypes.c_double), ("c_hi", ctypes.c_double),
+        ("u_lo", ctypes.c_double), ("u_hi", ctypes.c_double),
+        ("a", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        pp = ctypes.POINTER(_Params)
+        L.orc_feq.argtypes = [ctypes.c_double] * 3 + [dp]
+        L.orc_geq.argtypes = [ctypes.c_double] * 4 + [dp, dp]
+        L.orc_source.argtypes = [ctypes.c_double] * 5 + [dp, dp]
+        L.orc_local_solve.argtypes = [ctypes.c_double] * 10 + [dp]
+        L.orc_link_closure.argtypes = [pp, ctypes.c_int, dp, dp, dp, dp]
+        L.orc_moment_closure.argtypes = [pp, ctypes.c_int, dp, dp, dp]
+        L.orc_init.argtypes = [pp, ctypes.c_double, dp]
+        L.orc_step.argtypes = [pp, dp, dp, ctypes.c_int]
+        L.orc_run.argtypes = [pp, dp, dp, ctypes.c_int64, ctypes.c_int]
+        L.orc_observe.argtypes = [pp, dp, dp, dp, dp, dp, dp, dp]
+        L.orc_gather.argtypes = [pp, dp, ctypes.c_int, ctypes.c_int, dp]
+        for fn in ("orc_feq", "orc_geq", "orc_source", "orc_local_solve",
+                   "orc_link_closure", "orc_moment_closure", "orc_init",
+                   "orc_step", "orc_run", "orc_observe", "orc_gather"):
+            getattr(L, fn).restype = None
+        _lib = L
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+@dataclass
+class Params:
+    """Lattice parameters of one channel (lattice units, rho0 = 1).
+
+    ``c_lo``/``c_hi`` may be ``math.inf``; ``a`` is the half-width H = a used in
+    the wall-conductance terms.  Use :mod:`oracle.derive` to obtain them from
+    (Ha, c_w, u_max) the way Sec. VIII defines the problem.
+    """
+    nx: int
+    ny: int
+    bc: int = LINK
+    tau_f: float = 0.8
+    tau_m: float = 0.8
+    b0: float = 0.0
+    fx: float = 0.0
+    fy: float = 0.0
+    c_lo: float = 0.0
+    c_hi: float = 0.0
+    u_lo: float = 0.0
+    u_hi: float = 0.0
+    a: float = float("nan")
+    rho0: float = 1.0
+    extra: dict = field(default_factory=dict)
+
+    def half_width(self) -> float:
+        if not math.isnan(self.a):
+            return self.a
+        return self.ny / 2.0 if self.bc == LINK else (self.ny - 1) / 2.0
+
+    def c_struct(self) -> _Params:
+        return _Params(self.nx, self.ny, self.bc, 0, self.tau_f, self.tau_m,
+                       self.b0, self.fx, self.fy, self.c_lo, self.c_hi,
+                       self.u_lo, self.u_hi, self.half_width())
+
+
+def init_state(p: Params) -> np.ndarray:
+    s = np.empty((NPLANES, p.ny, p.nx), dtype=np.float64)
+    cp = p.c_struct()
+    lib().orc_init(ctypes.byref(cp), p.rho0, _dp(s))
+    return s
+
+
+def step(p: Params, state: np.ndarray, nthreads: int = 1) -> np.ndarray:
+    out = np.empty_like(state)
+    cp = p.c_struct()
+    lib().orc_step(ctypes.byref(cp), _dp(state), _dp(out), nthreads)
+    return out
+
+
+def run(p: Params, state: np.ndarray, nsteps: int, nthreads: int = 1,
+        scratch: np.ndarray | None = None) -> np.ndarray:
+    """Advance ``state`` in place by ``nsteps`` steps and return it."""
+    assert state.shape == (NPLANES, p.ny, p.nx)
+    if scratch is None:
+        scratch = np.empty_like(state)
+    cp = p.c_struct()
+    lib().orc_run(ctypes.byref(cp), _dp(state), _dp(scratch), int(nsteps), nthreads)
+    return state
+
+
+def observe(p: Params, state: np.ndarray) -> dict:
+    """rho, ux, uy, bx, by, jz of the state (the fields the next step uses)."""
+    out = {k: np.empty((p.ny, p.nx), dtype=np.float64)
+           for k in ("rho", "ux", "uy", "bx", "by", "jz")}
+    cp = p.c_struct()
+    lib().orc_observe(ctypes.byref(cp), _dp(state), *(_dp(out[k]) for k in
+                      ("rho", "ux", "uy", "bx", "by", "jz")))
+    return out
+
+
+def gather(p: Params, state: np.ndarray, x: int, y: int) -> np.ndarray:
+    """Post-streaming, post-closure populations of node (x, y)."""
+    out = np.empty(NPLANES, dtype=np.float64)
+    cp = p.c_struct()
+    lib().orc_gather(ctypes.byref(cp), _dp(state), x, y, _dp(out))
+    return out
+
+
+def feq(rho, ux, uy) -> np.ndarray:
+    out = np.empty(9)
+    lib().orc_feq(rho, ux, uy, _dp(out))
+    return out
+
+
+def geq(bx, by, ux, uy):
+    gx, gy = np.empty(5), np.empty(5)
+    lib().orc_geq(bx, by, ux, uy, _dp(gx), _dp(gy))
+    return gx, gy
+
+
+def source(rho, ux, uy, Fx, Fy, feq_):
+    out = np.empty(9)
+    lib().orc_source(rho, ux, uy, Fx, Fy, _dp(np.ascontiguousarray(feq_, dtype=np.float64)), _dp(out))
+    return out
+
+
+def local_solve(rho, mx, my, bx, by, lxy, lyx, tau_m, fex=0.0, fey=0.0):
+    out = np.empty(3)
+    lib().orc_local_solve(rho, mx, my, bx, by, lxy, lyx, tau_m, fex, fey, _dp(out))
+    return out
+
+
+def link_closure(p: Params, wall: int, own: np.ndarray, f, gx, gy):
+    f, gx, gy = (np.array(v, dtype=np.float64) for v in (f, gx, gy))
+    cp = p.c_struct()
+    lib().orc_link_closure(ctypes.byref(cp), wall, _dp(np.ascontiguousarray(own, dtype=np.float64)),
+                           _dp(f), _dp(gx), _dp(gy))
+    return f, gx, gy
+
+
+def moment_closure(p: Params, wall: int, f, gx, gy):
+    f, gx, gy = (np.array(v, dtype=np.float64) for v in (f, gx, gy))
+    cp = p.c_struct()
+    lib().orc_moment_closure(ctypes.byref(cp), wall, _dp(f), _dp(gx), _dp(gy))
+    return f, gx, gy

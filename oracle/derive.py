@@ -1,0 +1,71 @@
+"""Lattice parameters from the physical problem statement (TEST INFRASTRUCTURE).
+
+Lattice units: dx = dt = 1, rho0 = 1, mu_m = 1.
+  nu  = cs2 (tau_f - 1/2)                       (Sec. V)
+  eta = cs2m (tau_m - 1/2)                      (Sec. IV)
+  Ha  = B0 a sqrt(sigma/(rho nu)), sigma = 1/(eta mu_m)   (Sec. VIII)
+      => B0 = Ha sqrt(rho nu eta) / a
+  U_ref = a^2 F_x / (rho nu)                    (Sec. VIII) => F_x from u_max
+  B_ref = a^2 F_x mu_m sqrt(sigma/(rho nu))     (Sec. VIII)
+  Couette scale of B: U_w sqrt(rho nu sigma) mu_m         (App. C)
+"""
+from __future__ import annotations
+
+import math
+
+from . import LINK, Params
+from .analytic import chang_lundgren_centre
+
+
+def nu_of(tau_f: float) -> float:
+    return (tau_f - 0.5) / 3.0
+
+
+def eta_of(tau_m: float) -> float:
+    return (tau_m - 0.5) / 3.0
+
+
+def half_width(ny: int, bc: int) -> float:
+    return ny / 2.0 if bc == LINK else (ny - 1) / 2.0
+
+
+def b0_of(ha: float, tau_f: float, tau_m: float, a: float, rho: float = 1.0) -> float:
+    return ha * math.sqrt(rho * nu_of(tau_f) * eta_of(tau_m)) / a
+
+
+def fx_for_umax(u_max: float, ha: float, c: float, tau_f: float, a: float,
+                rho: float = 1.0) -> float:
+    """Body force whose Chang-Lundgren centreline velocity is u_max."""
+    return u_max * rho * nu_of(tau_f) / (a * a * chang_lundgren_centre(ha, c))
+
+
+def b_ref_hartmann(fx: float, tau_f: float, tau_m: float, a: float, rho: float = 1.0) -> float:
+    return a * a * fx / math.sqrt(rho * nu_of(tau_f) * eta_of(tau_m))
+
+
+def u_ref_hartmann(fx: float, tau_f: float, a: float, rho: float = 1.0) -> float:
+    return a * a * fx / (rho * nu_of(tau_f))
+
+
+def b_ref_couette(u_w: float, tau_f: float, tau_m: float, rho: float = 1.0) -> float:
+    return u_w * math.sqrt(rho * nu_of(tau_f) / eta_of(tau_m))
+
+
+def hartmann_params(nx: int, ny: int, bc: int, tau_f: float, tau_m: float,
+                    ha: float, c: float, u_max: float) -> Params:
+    """Body-force-driven Hartmann channel with equal wall conductance c."""
+    a = half_width(ny, bc)
+    return Params(nx=nx, ny=ny, bc=bc, tau_f=tau_f, tau_m=tau_m,
+                  b0=b0_of(ha, tau_f, tau_m, a),
+                  fx=fx_for_umax(u_max, ha, c, tau_f, a),
+                  c_lo=c, c_hi=c, a=a, extra={"ha": ha, "u_max": u_max})
+
+
+def couette_params(nx: int, ny: int, bc: int, tau_f: float, tau_m: float,
+                   ha: float, c_lo: float, c_hi: float, u_w: float) -> Params:
+    """Shear-driven Hartmann-Couette channel, upper wall moving at u_w."""
+    a = half_width(ny, bc)
+    return Params(nx=nx, ny=ny, bc=bc, tau_f=tau_f, tau_m=tau_m,
+                  b0=b0_of(ha, tau_f, tau_m, a), fx=0.0,
+                  c_lo=c_lo, c_hi=c_hi, u_lo=0.0, u_hi=u_w, a=a,
+                  extra={"ha": ha, "u_w": u_w})

@@ -1,0 +1,453 @@
+/*
+ * FP64 CPU oracle for the lattice-kinetic MHD time step with Shercliff
+ * thin-conducting-wall closures (Yahia & Premnath, arXiv 2112.13930).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file; only the test suite, the smoke check and the benchmark's
+ * CPU-baseline leg use it.  It shares no code, header or table with the HIP
+ * library: the lattice constants below are typed in here from the paper.
+ *
+ * It is deliberately plain: separate pull-stream, wall-closure, moment,
+ * local-solve and collision stages per node, double precision throughout,
+ * built with -O2 -ffp-contract=off (no fused multiply-add, no fast-math).
+ * Rows may be split over OpenMP threads; every node is computed from the
+ * previous state only, so the result does not depend on the thread count.
+ *
+ * State layout: post-collision populations in one array of 19 planes,
+ * plane-major, each plane [ny][nx] with x fastest:
+ *   planes 0..8   f_alpha        (D2Q9, Sec. V)
+ *   planes 9..13  g_{alpha x}    (D2Q5 vector distribution, x component)
+ *   planes 14..18 g_{alpha y}    (D2Q5, y component)
+ * x is periodic; the walls bound y: row 0 is the lower wall side (y = -a),
+ * row ny-1 the upper wall side (y = +a).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define NQ9 9
+#define NQ5 5
+#define NPLANES 19
+
+/* D2Q9 velocity set.  The paper's lattice figure is missing from the text; the
+ * numbering is fixed by the moment sums of App. A (Pi_10, Pi_01, Pi_20 in terms
+ * of f_1..f_8) and by the lower-wall unknowns being {2,5,6}. */
+static const int EX9[NQ9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+static const int EY9[NQ9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+/* Weights of Sec. V. */
+static const double W9[NQ9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,
+                               1.0 / 9.0,  1.0 / 9.0,  1.0 / 36.0,
+                               1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+static const int OPP9[NQ9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+
+/* D2Q5 velocity set for the vector distribution (Sec. IV); numbering fixed by
+ * Lambda_yx = g_2x - g_4x in the moment closure (Sec. VII) and e_4y = -1
+ * (App. B.1). */
+static const int EX5[NQ5] = {0, 1, 0, -1, 0};
+static const int EY5[NQ5] = {0, 0, 1, 0, -1};
+static const double W5[NQ5] = {1.0 / 3.0, 1.0 / 6.0, 1.0 / 6.0, 1.0 / 6.0,
+                               1.0 / 6.0};
+static const int OPP5[NQ5] = {0, 3, 4, 1, 2};
+
+static const double CS2 = 1.0 / 3.0;  /* c_s^2, Sec. V */
+static const double CSM2 = 1.0 / 3.0; /* c_sm^2, Sec. IV */
+
+enum { ORC_LINK = 0, ORC_MOMENT = 1 };
+enum { ORC_LOWER = 0, ORC_UPPER = 1 };
+
+typedef struct {
+  int32_t nx, ny, bc, pad_;
+  double tau_f, tau_m; /* relaxation times of f and g */
+  double b0;           /* imposed field, along +y */
+  double fx, fy;       /* external body force F_ext */
+  double c_lo, c_hi;   /* wall conductance ratios c_w (0 .. INFINITY) */
+  double u_lo, u_hi;   /* wall velocities along x */
+  double a;            /* half-width H = a entering theta and 1/(c_w a) */
+} orc_params;
+
+/* ---------------------------------------------------------------------- */
+/* Equilibria and source (Secs. IV and V)                                 */
+/* ---------------------------------------------------------------------- */
+
+/* f^eq of Sec. V: w rho [1 + e.u/cs2 + (e.u)^2/(2 cs2^2) - u.u/(2 cs2)]. */
+void orc_feq(double rho, double ux, double uy, double *feq) {
+  const double uu = ux * ux + uy * uy;
+  for (int q = 0; q < NQ9; ++q) {
+    const double eu = EX9[q] * ux + EY9[q] * uy;
+    feq[q] = W9[q] * rho *
+             (1.0 + eu / CS2 + (eu * eu) / (2.0 * CS2 * CS2) - uu / (2.0 * CS2));
+  }
+}
+
+/* g^eq of Sec. IV, Eq. (geqmagneticfield):
+ *   g^eq_{alpha i} = W_alpha { B_i + e_{alpha j} (u_j B_i - B_j u_i) / cs2m }
+ * written with the sum over j spelled out. */
+void orc_geq(double bx, double by, double ux, double uy, double *geqx,
+             double *geqy) {
+  const double u[2] = {ux, uy};
+  const double b[2] = {bx, by};
+  for (int q = 0; q < NQ5; ++q) {
+    const int e[2] = {EX5[q], EY5[q]};
+    double out[2];
+    for (int i = 0; i < 2; ++i) {
+      double flux = 0.0;
+      for (int j = 0; j < 2; ++j) flux += e[j] * (u[j] * b[i] - b[j] * u[i]);
+      out[i] = W5[q] * (b[i] + flux / CSM2);
+    }
+    geqx[q] = out[0];
+    geqy[q] = out[1];
+  }
+}
+
+/* Source of Sec. V: S_alpha = (e_alpha - u).F f^eq_alpha / (rho cs2). */
+void orc_source(double rho, double ux, double uy, double Fx, double Fy,
+                const double *feq, double *S) {
+  for (int q = 0; q < NQ9; ++q) {
+    const double dot = (EX9[q] - ux) * Fx + (EY9[q] - uy) * Fy;
+    S[q] = dot * feq[q] / (rho * CS2);
+  }
+}
+
+/* ---------------------------------------------------------------------- */
+/* Coupled local solve for u and J_z                                      */
+/* ---------------------------------------------------------------------- */
+/*
+ * The velocity uses the half-force correction rho u = sum f e + F/2 (Sec. V),
+ * the force contains the Lorentz part J x B (Sec. II), and J_z comes from the
+ * non-equilibrium part of Lambda (Sec. IV):
+ *   J_z = dB_y/dx - dB_x/dy
+ *       = -(1/(tau_m cs2m)) [ (Lambda_xy - L0_xy) - (Lambda_yx - L0_yx) ],
+ *   L0_ji = u_j B_i - B_j u_i.
+ * The paper does not say how the implicit u <-> J dependence is resolved; this
+ * oracle takes the three relations as simultaneous linear equations in
+ * (u_x, u_y, J_z) and solves them by Gaussian elimination with partial
+ * pivoting:
+ *   rho u_x + (B_y/2) J_z                    = m_x + F_ext,x/2
+ *   rho u_y - (B_x/2) J_z                    = m_y + F_ext,y/2
+ *   -2k B_y u_x + 2k B_x u_y + J_z           = -k (Lambda_xy - Lambda_yx)
+ * with k = 1/(tau_m cs2m).
+ */
+void orc_local_solve(double rho, double mx, double my, double bx, double by,
+                     double lxy, double lyx, double tau_m, double fex,
+                     double fey, double *out /* ux, uy, jz */) {
+  const double k = 1.0 / (tau_m * CSM2);
+  double M[3][4] = {
+      {rho, 0.0, by / 2.0, mx + fex / 2.0},
+      {0.0, rho, -bx / 2.0, my + fey / 2.0},
+      {-2.0 * k * by, 2.0 * k * bx, 1.0, -k * (lxy - lyx)},
+  };
+  for (int c = 0; c < 3; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < 3; ++r)
+      if (fabs(M[r][c]) > fabs(M[piv][c])) piv = r;
+    if (piv != c)
+      for (int k2 = 0; k2 < 4; ++k2) {
+        const double t = M[c][k2];
+        M[c][k2] = M[piv][k2];
+        M[piv][k2] = t;
+      }
+    for (int r = c + 1; r < 3; ++r) {
+      const double fac = M[r][c] / M[c][c];
+      for (int k2 = c; k2 < 4; ++k2) M[r][k2] -= fac * M[c][k2];
+    }
+  }
+  double x[3];
+  for (int r = 2; r >= 0; --r) {
+    double s = M[r][3];
+    for (int k2 = r + 1; k2 < 3; ++k2) s -= M[r][k2] * x[k2];
+    x[r] = s / M[r][r];
+  }
+  out[0] = x[0];
+  out[1] = x[1];
+  out[2] = x[2];
+}
+
+/* ---------------------------------------------------------------------- */
+/* Wall closures                                                          */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * Link-based closures (Sec. VI, App. B.1).  The wall sits half-way between
+ * the wall-row node x_f and the ghost node.  `own` holds the node's own
+ * post-collision populations of the previous step (all 19 planes); the
+ * incoming populations (those whose upstream node is the ghost) are set in
+ * f, gx, gy.
+ *   f:    half-way bounce-back with the moving-wall momentum term of App. B.1,
+ *         f_alpha = f~_abar + 2 w_alpha e_{alpha x} U_w / cs2.
+ *   g_x:  Shercliff closure, Eq. (movingwalllinkbasedclosure):
+ *         g_alpha = ((theta-1)/(theta+1)) g~_abar
+ *                   - (2 theta/(theta+1)) W_alpha (e_{alpha y}/cs2m) B0 U_w,
+ *         theta = c_w a / (tau_m - 1/2)   (Eq. weightingfactor, H = a);
+ *         c_w = INFINITY takes the perfectly conducting limit of App. B.1(b).
+ *   g_y:  Dirichlet B_y = B0 from Eq. (magneticfieldanditsgradientrelation1):
+ *         g_alpha = -g~_abar + 2 W_alpha B0.  (The upper-wall example prints
+ *         the outgoing population as g~_4y; the outgoing direction at the
+ *         upper wall is 2, so g~_2y is used.)
+ */
+void orc_link_closure(const orc_params *p, int wall, const double *own,
+                      double *f, double *gx, double *gy) {
+  const int ey_in = (wall == ORC_LOWER) ? +1 : -1; /* incoming e_y */
+  const double cw = (wall == ORC_LOWER) ? p->c_lo : p->c_hi;
+  const double uw = (wall == ORC_LOWER) ? p->u_lo : p->u_hi;
+  for (int q = 0; q < NQ9; ++q) {
+    if (EY9[q] != ey_in) continue;
+    f[q] = own[OPP9[q]] + 2.0 * W9[q] * EX9[q] * uw / CS2;
+  }
+  for (int q = 0; q < NQ5; ++q) {
+    if (EY5[q] != ey_in) continue;
+    const double gbar_x = own[9 + OPP5[q]];
+    const double gbar_y = own[14 + OPP5[q]];
+    const double moving = W5[q] * (EY5[q] / CSM2) * p->b0 * uw;
+    if (isinf(cw)) {
+      gx[q] = gbar_x - 2.0 * moving;
+    } else {
+      const double theta = cw * p->a / (p->tau_m - 0.5);
+      gx[q] = ((theta - 1.0) / (theta + 1.0)) * gbar_x -
+              (2.0 * theta / (theta + 1.0)) * moving;
+    }
+    gy[q] = -gbar_y + 2.0 * W5[q] * p->b0;
+  }
+}
+
+/*
+ * On-node ("wet") moment-based closures (Sec. VII, App. A, App. B.2).
+ * f, gx, gy hold the post-streaming populations at the wall node; the
+ * unknowns are overwritten.
+ *   f:   constraints Pi_10 = rho U_w, Pi_01 = 0, Pi_20 = rho (cs2 + U_w^2)
+ *        with rho from the known populations; closures of App. A (stationary)
+ *        and App. B.2 (moving upper wall).  App. B.2 prints the first two
+ *        constraints with Pi_10 and Pi_01 swapped; the printed closures satisfy
+ *        the reading used here.  The moving lower wall is the mirror image.
+ *   g_x: Shercliff constraint with Lambda_yx = g_2x - g_4x:
+ *          lower:  A (g_2x - g_4x + B0 U) + C sum_a g_ax = 0
+ *          upper: -A (g_2x - g_4x + B0 U) + C sum_a g_ax = 0
+ *        A = 1/(tau_m cs2m), C = 1/(c_w a), solved for the unknown as in
+ *        Eqs. (momentbasedBCslowerboundary), (momentbasedBCsupperboundary) and
+ *        (momentbasedclosureformovingwall); c_w = 0 and c_w = INFINITY take the
+ *        limits printed after them.
+ *   g_y: sum_a g_ay = B0.
+ */
+void orc_moment_closure(const orc_params *p, int wall, double *f, double *gx,
+                        double *gy) {
+  const double cw = (wall == ORC_LOWER) ? p->c_lo : p->c_hi;
+  const double U = (wall == ORC_LOWER) ? p->u_lo : p->u_hi;
+  const double A = 1.0 / (p->tau_m * CSM2);
+  if (wall == ORC_LOWER) {
+    const double rho = f[0] + f[1] + f[3] + 2.0 * (f[4] + f[7] + f[8]);
+    f[2] = -rho * (CS2 + U * U) + f[1] + f[3] + f[4] + 2.0 * (f[7] + f[8]);
+    f[5] = 0.5 * rho * (CS2 + U * U + U) - (f[1] + f[8]);
+    f[6] = 0.5 * rho * (CS2 + U * U - U) - (f[3] + f[7]);
+    const double others = gx[0] + gx[1] + gx[3];
+    if (cw == 0.0) {
+      gx[2] = -(others + gx[4]);
+    } else if (isinf(cw)) {
+      gx[2] = gx[4] - p->b0 * U;
+    } else {
+      const double C = 1.0 / (cw * p->a);
+      gx[2] = ((A - C) * gx[4] - C * others - A * p->b0 * U) / (A + C);
+    }
+    gy[2] = p->b0 - (gy[0] + gy[1] + gy[3] + gy[4]);
+  } else {
+    const double rho = f[0] + f[1] + f[3] + 2.0 * (f[2] + f[5] + f[6]);
+    f[4] = -rho * (CS2 + U * U) + f[1] + f[2] + f[3] + 2.0 * (f[5] + f[6]);
+    f[7] = 0.5 * rho * (CS2 + U * U - U) - (f[3] + f[6]);
+    f[8] = 0.5 * rho * (CS2 + U * U + U) - (f[1] + f[5]);
+    const double others = gx[0] + gx[1] + gx[3];
+    if (cw == 0.0) {
+      gx[4] = -(others + gx[2]);
+    } else if (isinf(cw)) {
+      gx[4] = gx[2] + p->b0 * U;
+    } else {
+      const double C = 1.0 / (cw * p->a);
+      gx[4] = ((A - C) * gx[2] - C * others + A * p->b0 * U) / (A + C);
+    }
+    gy[4] = p->b0 - (gy[0] + gy[1] + gy[2] + gy[3]);
+  }
+}
+
+/* ---------------------------------------------------------------------- */
+/* One node: stream, close, moments, solve; optionally collide            */
+/* ---------------------------------------------------------------------- */
+
+static inline size_t idx(const orc_params *p, int plane, int y, int x) {
+  return ((size_t)plane * (size_t)p->ny + (size_t)y) * (size_t)p->nx + (size_t)x;
+}
+
+typedef struct {
+  double f[NQ9], gx[NQ5], gy[NQ5];
+  double rho, ux, uy, bx, by, jz, Fx, Fy;
+} node_t;
+
+static void gather_node(const orc_params *p, const double *in, int x, int y,
+                        node_t *n) {
+  /* S1: pull streaming, f_alpha(x) = f~_alpha(x - e_alpha) (Eqs.
+   * LBMforflowfield, LKSformagneticfield); x periodic. */
+  for (int q = 0; q < NQ9; ++q) {
+    const int sy = y - EY9[q];
+    const int sx = ((x - EX9[q]) % p->nx + p->nx) % p->nx;
+    n->f[q] = (sy >= 0 && sy < p->ny) ? in[idx(p, q, sy, sx)] : NAN;
+  }
+  for (int q = 0; q < NQ5; ++q) {
+    const int sy = y - EY5[q];
+    const int sx = ((x - EX5[q]) % p->nx + p->nx) % p->nx;
+    const int ok = (sy >= 0 && sy < p->ny);
+    n->gx[q] = ok ? in[idx(p, 9 + q, sy, sx)] : NAN;
+    n->gy[q] = ok ? in[idx(p, 14 + q, sy, sx)] : NAN;
+  }
+  /* S2: wall closures. */
+  const int nwall = (y == 0) + (y == p->ny - 1);
+  if (nwall) {
+    double own[NPLANES];
+    for (int k = 0; k < NPLANES; ++k) own[k] = in[idx(p, k, y, x)];
+    if (y == 0) {
+      if (p->bc == ORC_LINK)
+        orc_link_closure(p, ORC_LOWER, own, n->f, n->gx, n->gy);
+      else
+        orc_moment_closure(p, ORC_LOWER, n->f, n->gx, n->gy);
+    }
+    if (y == p->ny - 1) {
+      if (p->bc == ORC_LINK)
+        orc_link_closure(p, ORC_UPPER, own, n->f, n->gx, n->gy);
+      else
+        orc_moment_closure(p, ORC_UPPER, n->f, n->gx, n->gy);
+    }
+  }
+  /* S3: moments (Secs. IV, V). */
+  double rho = 0.0, mx = 0.0, my = 0.0;
+  for (int q = 0; q < NQ9; ++q) {
+    rho += n->f[q];
+    mx += n->f[q] * EX9[q];
+    my += n->f[q] * EY9[q];
+  }
+  double bx = 0.0, by = 0.0, lam[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+  for (int q = 0; q < NQ5; ++q) {
+    const int e[2] = {EX5[q], EY5[q]};
+    const double g[2] = {n->gx[q], n->gy[q]};
+    bx += g[0];
+    by += g[1];
+    for (int j = 0; j < 2; ++j)
+      for (int i = 0; i < 2; ++i) lam[j][i] += e[j] * g[i]; /* Lambda_ji */
+  }
+  n->rho = rho;
+  n->bx = bx;
+  n->by = by;
+  if (nwall && p->bc == ORC_MOMENT) {
+    /* Wet wall node: the closure has fixed its velocity through the moments,
+     * sum f e = rho (U_w, 0) (App. A, App. B.2).  It is a Dirichlet node: no
+     * force enters its collision, u = sum f e / rho, and J_z follows from the
+     * non-equilibrium part of Lambda with that u (Sec. IV). */
+    const double k = 1.0 / (p->tau_m * CSM2);
+    n->ux = mx / rho;
+    n->uy = my / rho;
+    const double l0xy = n->ux * by - bx * n->uy; /* u_x B_y - B_x u_y */
+    const double l0yx = n->uy * bx - by * n->ux; /* u_y B_x - B_y u_x */
+    n->jz = -k * ((lam[0][1] - l0xy) - (lam[1][0] - l0yx));
+    n->Fx = 0.0;
+    n->Fy = 0.0;
+    return;
+  }
+  /* S4: coupled local solve and total force. */
+  double sol[3];
+  orc_local_solve(rho, mx, my, bx, by, lam[0][1], lam[1][0], p->tau_m, p->fx,
+                  p->fy, sol);
+  n->ux = sol[0];
+  n->uy = sol[1];
+  n->jz = sol[2];
+  n->Fx = p->fx - sol[2] * by; /* (J x B)_x = -J_z B_y */
+  n->Fy = p->fy + sol[2] * bx; /* (J x B)_y = +J_z B_x */
+}
+
+static void step_rows(const orc_params *p, const double *in, double *out,
+                      int y0, int y1) {
+  for (int y = y0; y < y1; ++y) {
+    for (int x = 0; x < p->nx; ++x) {
+      node_t n;
+      gather_node(p, in, x, y, &n);
+      /* S5: collide (Eqs. LBMforflowfield and LKSformagneticfield). */
+      double feq[NQ9], S[NQ9], geqx[NQ5], geqy[NQ5];
+      orc_feq(n.rho, n.ux, n.uy, feq);
+      orc_source(n.rho, n.ux, n.uy, n.Fx, n.Fy, feq, S);
+      orc_geq(n.bx, n.by, n.ux, n.uy, geqx, geqy);
+      for (int q = 0; q < NQ9; ++q)
+        out[idx(p, q, y, x)] = n.f[q] - (n.f[q] - feq[q]) / p->tau_f +
+                               (1.0 - 1.0 / (2.0 * p->tau_f)) * S[q];
+      for (int q = 0; q < NQ5; ++q) {
+        out[idx(p, 9 + q, y, x)] = n.gx[q] - (n.gx[q] - geqx[q]) / p->tau_m;
+        out[idx(p, 14 + q, y, x)] = n.gy[q] - (n.gy[q] - geqy[q]) / p->tau_m;
+      }
+    }
+  }
+}
+
+/* Initial state: equilibrium at rest with density rho0 and B = (0, B0),
+ * i.e. zero induced field; stored as post-collision populations. */
+void orc_init(const orc_params *p, double rho0, double *state) {
+  double feq[NQ9], gex[NQ5], gey[NQ5];
+  orc_feq(rho0, 0.0, 0.0, feq);
+  orc_geq(0.0, p->b0, 0.0, 0.0, gex, gey);
+  for (int y = 0; y < p->ny; ++y)
+    for (int x = 0; x < p->nx; ++x) {
+      for (int q = 0; q < NQ9; ++q) state[idx(p, q, y, x)] = feq[q];
+      for (int q = 0; q < NQ5; ++q) {
+        state[idx(p, 9 + q, y, x)] = gex[q];
+        state[idx(p, 14 + q, y, x)] = gey[q];
+      }
+    }
+}
+
+/* One time step in -> out (distinct buffers). */
+void orc_step(const orc_params *p, const double *in, double *out,
+              int nthreads) {
+#if defined(_OPENMP)
+#pragma omp parallel for schedule(static) num_threads(nthreads > 0 ? nthreads : 1)
+#endif
+  for (int y = 0; y < p->ny; ++y) step_rows(p, in, out, y, y + 1);
+  (void)nthreads;
+}
+
+/* nsteps time steps in place on `state`, using `scratch` (same size). */
+void orc_run(const orc_params *p, double *state, double *scratch,
+             int64_t nsteps, int nthreads) {
+  const size_t n = (size_t)NPLANES * (size_t)p->nx * (size_t)p->ny;
+  double *a = state, *b = scratch;
+  for (int64_t s = 0; s < nsteps; ++s) {
+    orc_step(p, a, b, nthreads);
+    double *t = a;
+    a = b;
+    b = t;
+  }
+  if (a != state) memcpy(state, a, n * sizeof(double));
+}
+
+/* Observables of a stored state: S1-S4 without the collision, i.e. the
+ * fields the next step collides with.  Any output may be NULL. */
+void orc_observe(const orc_params *p, const double *state, double *rho,
+                 double *ux, double *uy, double *bx, double *by, double *jz) {
+  for (int y = 0; y < p->ny; ++y)
+    for (int x = 0; x < p->nx; ++x) {
+      node_t n;
+      gather_node(p, state, x, y, &n);
+      const size_t k = (size_t)y * p->nx + x;
+      if (rho) rho[k] = n.rho;
+      if (ux) ux[k] = n.ux;
+      if (uy) uy[k] = n.uy;
+      if (bx) bx[k] = n.bx;
+      if (by) by[k] = n.by;
+      if (jz) jz[k] = n.jz;
+    }
+}
+
+/* Post-streaming, post-closure populations of one node (for closure tests). */
+void orc_gather(const orc_params *p, const double *state, int x, int y,
+                double *pops19) {
+  node_t n;
+  gather_node(p, state, x, y, &n);
+  for (int q = 0; q < NQ9; ++q) pops19[q] = n.f[q];
+  for (int q = 0; q < NQ5; ++q) {
+    pops19[9 + q] = n.gx[q];
+    pops19[14 + q] = n.gy[q];
+  }
+}
+
+int orc_abi_version(void) { return 1; }

@@ -1,0 +1,53 @@
+"""Write the stored expected values under tests/golden/ (calls only oracle/).
+
+config1_hartmann_link.json
+    The plain body-force Hartmann channel: 8 x 64 nodes, link-based walls,
+    tau_f = tau_m = 0.8, Ha = 10, c = 0.1 on both walls, F_x set for
+    u_max = 0.05, 20000 steps from rest.  Stores the derived lattice
+    parameters and the oracle's u_x and B_x rows after 20000 steps (every
+    column is identical, so one column is stored), plus the Chang-Lundgren
+    profile at the same rows for reference.
+
+Run:  python tests/golden/make_golden.py
+"""
+import json
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import numpy as np  # noqa: E402
+
+import oracle  # noqa: E402
+from oracle import analytic, derive  # noqa: E402
+
+
+def config1():
+    p = derive.hartmann_params(8, 64, oracle.LINK, 0.8, 0.8, 10.0, 0.1, 0.05)
+    s = oracle.init_state(p)
+    oracle.run(p, s, 20000, nthreads=1)
+    o = oracle.observe(p, s)
+    xi = analytic.node_xi(64, oracle.LINK)
+    ua, ba = analytic.chang_lundgren(xi, 10.0, 0.1)
+    return {
+        "description": "Hartmann channel 8x64, link-based, tau_f=tau_m=0.8, Ha=10, c=0.1, "
+                       "u_max=0.05, 20000 steps from rest; oracle FP64 observables (one column)",
+        "params": {"nx": 8, "ny": 64, "bc": "link", "tau_f": 0.8, "tau_m": 0.8, "ha": 10.0,
+                   "c": 0.1, "u_max": 0.05, "steps": 20000, "a": p.a, "b0": p.b0, "fx": p.fx,
+                   "theta": 0.1 * p.a / (0.8 - 0.5)},
+        "ux": o["ux"][:, 0].tolist(),
+        "bx": o["bx"][:, 0].tolist(),
+        "rho": o["rho"][:, 0].tolist(),
+        "chang_lundgren_u_star": ua.tolist(),
+        "chang_lundgren_b_star": ba.tolist(),
+        "u_ref": derive.u_ref_hartmann(p.fx, 0.8, p.a),
+        "b_ref": derive.b_ref_hartmann(p.fx, 0.8, 0.8, p.a),
+    }
+
+
+if __name__ == "__main__":
+    out = os.path.join(HERE, "config1_hartmann_link.json")
+    with open(out, "w") as fh:
+        json.dump(config1(), fh, indent=1)
+    print("wrote", out)

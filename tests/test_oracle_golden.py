@@ -1,0 +1,39 @@
+"""The stored config-1 fixture (tests/golden/, written by make_golden.py from
+the oracle alone) still matches the oracle, and is close to Chang-Lundgren.
+
+The fixture guards against unnoticed changes of the oracle's arithmetic; any
+intended change must regenerate it in a commit that names the passage of the
+paper (or the reading of it) that justifies the change.
+"""
+import json
+import os
+
+import numpy as np
+
+import oracle
+from oracle import derive
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "config1_hartmann_link.json")
+
+
+def test_config1_fixture_matches_oracle(orc):
+    g = json.load(open(GOLD))
+    p = derive.hartmann_params(8, 64, oracle.LINK, 0.8, 0.8, 10.0, 0.1, 0.05)
+    assert abs(p.b0 - g["params"]["b0"]) < 1e-18 and abs(p.fx - g["params"]["fx"]) < 1e-20
+    s = orc.init_state(p)
+    orc.run(p, s, 20000, nthreads=2)
+    o = orc.observe(p, s)
+    assert np.abs(o["ux"][:, 0] - np.array(g["ux"])).max() < 1e-15
+    assert np.abs(o["bx"][:, 0] - np.array(g["bx"])).max() < 1e-15
+    # all columns identical (x-invariant run)
+    assert np.array_equal(o["ux"], np.repeat(o["ux"][:, :1], 8, axis=1))
+
+
+def test_config1_close_to_chang_lundgren():
+    g = json.load(open(GOLD))
+    u = np.array(g["ux"]) / g["u_ref"]
+    b = np.array(g["bx"]) / g["b_ref"]
+    ua, ba = np.array(g["chang_lundgren_u_star"]), np.array(g["chang_lundgren_b_star"])
+    # 20000 steps from rest at a = 32 is close to, not at, the steady state
+    assert np.sqrt(np.mean((u - ua) ** 2)) / np.abs(ua).max() < 2e-2
+    assert np.sqrt(np.mean((b - ba) ** 2)) / np.abs(ba).max() < 2e-2
