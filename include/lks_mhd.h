@@ -1,0 +1,282 @@
+/*
+ * lks_mhd -- fused lattice-kinetic MHD time step for MI355X (gfx950).
+ *
+ * The method is the one of E. Yahia & K. N. Premnath, "On Boundary Conditions
+ * for Lattice Kinetic Schemes for Magnetohydrodynamics Bounded by Walls with
+ * Finite Electrical Conductivities" (arXiv 2112.13930):
+ *   - D2Q9 BGK flow distribution f with the forcing source of Sec. V
+ *     (Lorentz force J x B of Sec. II plus an external body force);
+ *   - D2Q5 vector magnetic distribution g of Dellar's lattice kinetic scheme
+ *     (Sec. IV), J_z from the non-equilibrium part of its first moment;
+ *   - Shercliff thin-conducting-wall closures at the two channel walls
+ *     (Sec. III condition): the link-based weighted bounce-back/anti-bounce-
+ *     back closure (Sec. VI, moving walls App. B.1) with half-way bounce-back
+ *     of f, or the on-node moment-based closure (Sec. VII, App. A, moving
+ *     walls App. B.2).
+ * The channel is periodic in x and bounded by walls at y = -a (row 0) and
+ * y = +a (row ny-1); the imposed field B0 points along +y.
+ *
+ * Conventions for every entry point:
+ *   - Return value: LKS_OK (0) or a negative lks_status; the reason is kept
+ *     in a thread-local message returned by lks_mhd_last_error().
+ *   - Device pointers are HIP device addresses on the current device; host
+ *     pointers are ordinary process memory.  Field arrays are FP64, row-major
+ *     [ny][nx] (x fastest).  Population arrays are FP64 [19][ny][nx] with the
+ *     plane order f_0..f_8, g_0x..g_4x, g_0y..g_4y and raw (not shifted)
+ *     population values.
+ *   - Lattice numbering: D2Q9 e = (0,0),(1,0),(0,1),(-1,0),(0,-1),(1,1),
+ *     (-1,1),(-1,-1),(1,-1); D2Q5 e = (0,0),(1,0),(0,1),(-1,0),(0,-1).
+ *   - Work is enqueued on the HIP stream given at create time; entry points
+ *     documented as synchronous wait for that stream before returning.
+ *   - A handle is used by one host thread at a time; separate handles are
+ *     independent.  Nothing here allocates device memory except where stated.
+ */
+#ifndef LKS_MHD_H
+#define LKS_MHD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LKS_MHD_ABI_VERSION 1
+
+typedef struct lks_mhd lks_mhd_t;             /* one channel, library-owned */
+typedef struct lks_mhd_batch lks_mhd_batch_t; /* many channels, library-owned */
+
+enum lks_bc { LKS_BC_LINK = 0, LKS_BC_MOMENT = 1 };
+
+/* Storage precision of the populations.  FP64: stored and computed in FP64.
+ * FP32: stored and computed in FP32.  FP16_STORE: stored as IEEE binary16
+ * (round to nearest even) and computed in FP32.  In every mode the flow
+ * populations are stored as deviations f_alpha - w_alpha from the rest
+ * equilibrium at unit density; the magnetic populations are stored as
+ * values.  Steady-state reductions are FP64 in every mode. */
+enum lks_precision { LKS_FP64 = 0, LKS_FP32 = 1, LKS_FP16_STORE = 2 };
+
+enum lks_status {
+  LKS_OK = 0,
+  LKS_EINVAL = -1,    /* invalid argument or parameter set */
+  LKS_ENOMEM = -2,    /* caller buffer or pool too small */
+  LKS_EDEVICE = -3,   /* a HIP call failed */
+  LKS_EUNSTABLE = -4, /* a non-finite density, velocity or field appeared */
+  LKS_ENOTCONV = -5   /* max_steps reached without meeting the tolerance */
+};
+
+/*
+ * Physical and lattice parameters of one channel (lattice units, dx = dt = 1,
+ * mu_m = 1).  Defaults that the helper lks_mhd_default_params() fills are
+ * given in brackets.
+ *   nx, ny      nodes; x periodic; ny >= 2 (link) or >= 3 (moment);
+ *               nx * ny <= 2^31 / 19.
+ *   bc          LKS_BC_LINK or LKS_BC_MOMENT.
+ *   precision   lks_precision.
+ *   tau_f       BGK relaxation time of f, > 1/2: nu = (tau_f - 1/2)/3 (Sec. V).
+ *   tau_m       relaxation time of g, > 1/2: eta = (tau_m - 1/2)/3 (Sec. IV).
+ *   ha          Hartmann number (Sec. VIII).  If finite and >= 0, the imposed
+ *               field is B0 = ha * sqrt(rho0 nu eta) / a, where the half-width
+ *               is a = ny/2 for link-based walls (half-way between nodes) and
+ *               a = (ny-1)/2 for on-node walls.  NaN: b0 is used as given.
+ *   b0          imposed field along +y; must be NaN or equal to the derived
+ *               value when ha is given.
+ *   c_lower,    wall conductance ratios c_w of Sec. III at y = -a and y = +a,
+ *   c_upper     in [0, +INFINITY]; 0 is an insulating wall, INFINITY a
+ *               perfectly conducting one.  H = a in theta and 1/(c_w a).
+ *   u_lower,    wall velocities along x (App. B).
+ *   u_upper
+ *   fx, fy      external body force.  fx = NaN derives it from u_max through
+ *               the Chang-Lundgren centreline velocity (Sec. VIII), which
+ *               needs c_lower == c_upper.
+ *   u_max       target centreline velocity when fx is NaN.
+ *   rho0        initial density [1]; the state starts at rest at rho0 with
+ *               B = (0, B0) (zero induced field).
+ */
+typedef struct {
+  int32_t nx, ny;
+  int32_t bc;
+  int32_t precision;
+  double tau_f, tau_m;
+  double ha;
+  double b0;
+  double c_lower, c_upper;
+  double u_lower, u_upper;
+  double fx, fy;
+  double u_max;
+  double rho0;
+} lks_mhd_params;
+
+/* Lattice quantities derived from a parameter set (host FP64). */
+typedef struct {
+  double nu, eta, a, b0, fx, fy;
+  double theta_lower, theta_upper; /* link: theta = c_w a / (tau_m - 1/2), Eq. (weightingfactor) */
+  double phi_lower, phi_upper;     /* moment: c_w a / (tau_m cs2m), from Eq. (momentbasedBCslowerboundary) */
+} lks_mhd_derived;
+
+/* ABI version of the loaded library (LKS_MHD_ABI_VERSION). */
+int lks_mhd_abi_version(void);
+
+/* Thread-local message for the last failing call on this thread ("" if none). */
+const char *lks_mhd_last_error(void);
+
+/* Fill *p with defaults (see lks_mhd_params) for an nx x ny channel. */
+void lks_mhd_default_params(lks_mhd_params *p, int32_t nx, int32_t ny);
+
+/* Host-only validation; no device work.  LKS_EINVAL with a message if the
+ * set is invalid (tau <= 1/2, c < 0 or NaN, ny too small, Ha and B0
+ * inconsistent, fx NaN with unequal walls, ...). */
+int lks_mhd_validate(const lks_mhd_params *p);
+
+/* Host-only derivation of the lattice quantities; validates first. */
+int lks_mhd_derive(const lks_mhd_params *p, lks_mhd_derived *out);
+
+/* Device bytes a channel needs in the caller's buffer (two population
+ * buffers, a record buffer for the residual, reduction scratch); 0 if the
+ * parameters are invalid. */
+size_t lks_mhd_state_bytes(const lks_mhd_params *p);
+
+/*
+ * Create a channel on the current device.  dev_buf (>= lks_mhd_state_bytes,
+ * 256-byte aligned) is caller-owned device memory that must outlive the
+ * handle; the library carves its buffers from it and allocates no device
+ * memory.  hip_stream is the hipStream_t all work is enqueued on (NULL: the
+ * default stream).  The state is initialised (asynchronously) to the rest
+ * equilibrium described above.  *out receives the handle.
+ */
+int lks_mhd_create(const lks_mhd_params *p, void *dev_buf, size_t bytes,
+                   void *hip_stream, lks_mhd_t **out);
+
+/* Release the handle (device memory stays the caller's).  NULL is a no-op. */
+int lks_mhd_destroy(lks_mhd_t *h);
+
+/* Enqueue nsteps >= 0 fused time steps (pull stream, wall closure, moments,
+ * coupled J/u solve, collide, store).  Asynchronous. */
+int lks_mhd_step(lks_mhd_t *h, int64_t nsteps);
+
+/* Replay step sequences from a captured HIP graph of steps_per_graph (even,
+ * >= 2) kernels when lks_mhd_step is given at least that many steps; 0
+ * switches graphs off (the default).  The stream must not be the legacy
+ * default stream.  Captures lazily on first use. */
+int lks_mhd_set_graph(lks_mhd_t *h, int32_t steps_per_graph);
+
+/* Launch shape of the plain step kernel (tuning): 0 = 256x1 threads in
+ * hardware dispatch order (the default, fastest measured on MI355X);
+ * 1 = 64x4 and 2 = 128x2 and 3 = 256x1 with consecutive tiles kept on one
+ * XCD; 4 = 64x4 in dispatch order.  Results are identical for every shape. */
+int lks_mhd_set_launch_shape(lks_mhd_t *h, int32_t shape);
+
+/* Steps taken since create (or since the last load_state). */
+int64_t lks_mhd_steps_done(const lks_mhd_t *h);
+
+/*
+ * Advance until the steady-state residual falls below tol.  Every
+ * check_every (>= 2) steps the residual
+ *   R = max over phi in {u_x, B_x} of ||phi(n) - phi(n-1)||_2 / ||phi(n)||_2
+ * is reduced in FP64 (fixed order, deterministic), where phi(n) is the field
+ * the step after n collides with and n = steps_done - 1.  Stops at R < tol
+ * (LKS_OK), at max_steps (LKS_ENOTCONV) or on a non-finite value
+ * (LKS_EUNSTABLE).  Synchronous.  *steps_done and *residual (either may be
+ * NULL) receive the totals reached in every case; *flow_rate (may be NULL)
+ * receives sum(u_x)/nx of phi(n).
+ */
+int lks_mhd_run_to_steady(lks_mhd_t *h, double tol, int64_t check_every,
+                          int64_t max_steps, int64_t *steps_done,
+                          double *residual, double *flow_rate);
+
+/*
+ * Observables of the current state: the density, velocity, magnetic field and
+ * current density J_z that the next step collides with (after streaming and
+ * wall closure), in FP64.  Each pointer is a device array of nx*ny doubles or
+ * NULL to skip.  Asynchronous.
+ */
+int lks_mhd_moments(lks_mhd_t *h, double *rho, double *ux, double *uy,
+                    double *bx, double *by, double *jz);
+
+/* Copy the state out to / in from a device FP64 array [19][ny][nx] of raw
+ * population values (checkpoint, resume, parity tests).  load_state resets
+ * steps_done to `steps`.  Asynchronous. */
+int lks_mhd_save_state(lks_mhd_t *h, double *dev_pops);
+int lks_mhd_load_state(lks_mhd_t *h, const double *dev_pops, int64_t steps);
+
+/* Algorithmic HBM bytes of one step per node (19 populations read and
+ * written) for a precision: 304, 152 or 76. */
+int lks_mhd_bytes_per_node(int32_t precision);
+
+/* ------------------------------------------------------------------------ */
+/* Batched channels: many independent channels of any size in one launch.   */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Create a batch over a caller-owned device pool (>= 256-byte aligned).  All
+ * channels share one precision (LKS_FP32 or LKS_FP16_STORE or LKS_FP64).
+ * max_channels bounds the slot table.  The library allocates no device
+ * memory: slot table, tile list and reduction scratch are carved from the
+ * pool's front (lks_mhd_batch_overhead_bytes), channel states from the rest.
+ */
+size_t lks_mhd_batch_overhead_bytes(int32_t max_channels, int64_t max_nodes);
+int lks_mhd_batch_create(int32_t precision, int32_t max_channels,
+                         int64_t max_nodes, void *dev_pool, size_t pool_bytes,
+                         void *hip_stream, lks_mhd_batch_t **out);
+int lks_mhd_batch_destroy(lks_mhd_batch_t *b);
+
+/* Device bytes one channel's state takes in the pool. */
+size_t lks_mhd_batch_channel_bytes(const lks_mhd_params *p, int32_t precision);
+
+/* Admit a channel (its precision field is ignored; the batch's is used).
+ * Allocates its state from the pool (first fit) and initialises it at rest.
+ * LKS_ENOMEM if the pool, the slot table or max_nodes is full.  *slot
+ * receives the slot id.  Asynchronous. */
+int lks_mhd_batch_admit(lks_mhd_batch_t *b, const lks_mhd_params *p,
+                        int32_t *slot);
+
+/* Remove a channel and free its pool region. */
+int lks_mhd_batch_retire(lks_mhd_batch_t *b, int32_t slot);
+
+/* Number of active channels, and the total nodes they hold. */
+int32_t lks_mhd_batch_active(const lks_mhd_batch_t *b);
+int64_t lks_mhd_batch_nodes(const lks_mhd_batch_t *b);
+
+/* Tile shape (tile_w x tile_h nodes, tile_w a multiple of 64 or one of
+ * 8, 16, 32 with tile_w * tile_h = 256) used for channels of a width class:
+ * class k holds channels with nx in (2^(k+2), 2^(k+3)] (k = 0..6, nx <= 8 in
+ * class 0, nx > 256 in class 6). */
+int lks_mhd_batch_set_tile(lks_mhd_batch_t *b, int32_t width_class,
+                           int32_t tile_w, int32_t tile_h);
+
+/* Time every candidate tile shape per width class on the current channel
+ * mix (trial_steps each) and keep the fastest.  The trial steps are real
+ * steps: every active channel advances by them and its steps_done grows.
+ * Synchronous.  The chosen shapes are written to tiles_out[7][2] if non-NULL. */
+int lks_mhd_batch_autotune(lks_mhd_batch_t *b, int32_t trial_steps,
+                           int32_t *tiles_out);
+
+/* Enqueue nsteps steps of every active channel in one persistent launch per
+ * step (captured in a HIP graph of two launches when use_graph != 0).
+ * Asynchronous. */
+int lks_mhd_batch_step(lks_mhd_batch_t *b, int64_t nsteps, int32_t use_graph);
+
+/* Advance nsteps >= 2 steps, the last two recording and reducing the
+ * per-channel residual (definition as in lks_mhd_run_to_steady).  Writes
+ * per-slot residuals to residuals[max_channels] and per-slot flags (1 =
+ * non-finite) to unstable[max_channels] (host arrays; entries of empty slots
+ * are NaN / 0).  Synchronous. */
+int lks_mhd_batch_step_check(lks_mhd_batch_t *b, int64_t nsteps,
+                             int32_t use_graph, double *residuals,
+                             int32_t *unstable);
+
+/* Steps the slot has taken since admission. */
+int64_t lks_mhd_batch_steps_done(const lks_mhd_batch_t *b, int32_t slot);
+
+/* Observables and state of one slot (device pointers as for one channel). */
+int lks_mhd_batch_moments(lks_mhd_batch_t *b, int32_t slot, double *rho,
+                          double *ux, double *uy, double *bx, double *by,
+                          double *jz);
+int lks_mhd_batch_save_state(lks_mhd_batch_t *b, int32_t slot,
+                             double *dev_pops);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LKS_MHD_H */

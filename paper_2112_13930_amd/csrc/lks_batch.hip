@@ -1,0 +1,820 @@
+// Batched channels: many independent channels of uneven size advanced by one
+// persistent launch per step over a packed device tile list.
+//
+// Pool layout (caller-owned device memory):
+//   [channel descriptors][tile list][tile count][per-tile partials]
+//   [per-slot sums][channel states ...]
+// A channel's region holds its two population buffers and its record buffer.
+// The step kernel reads the tile count and the descriptors from device
+// memory, so admitting or retiring channels rewrites that memory and never
+// needs a new launch configuration: a captured two-step graph stays valid.
+//
+// Every node is updated by the same node_update() as the single-channel
+// kernel, so a channel's populations are bitwise those of a solo run with the
+// same precision and step count.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "lks_aux.hpp"
+#include "lks_common.hpp"
+
+namespace lks {
+
+struct ChanDesc {
+  void *buf[2];
+  double *rec;
+  Geom g;
+  int bc;
+  int phase;      // buffer holding the state when the global parity is 0
+  int tile_first; // first tile of this channel in the list
+  int tile_count;
+  Coef<float> kf;
+  Coef<double> kd;
+};
+
+struct Tile {
+  int chan;
+  int x0, y0;
+  int w, h; // w * h == 256
+  int pad[3];
+};
+
+constexpr int kTileThreads = 256;
+constexpr int kWidthClasses = 7;
+constexpr int NREDB = 6;
+
+template <typename C> __device__ __forceinline__ const Coef<C> &coef_of(const ChanDesc &c);
+template <> __device__ __forceinline__ const Coef<float> &coef_of<float>(const ChanDesc &c) { return c.kf; }
+template <> __device__ __forceinline__ const Coef<double> &coef_of<double>(const ChanDesc &c) { return c.kd; }
+
+template <typename S, typename C, int MODE>
+__global__ __launch_bounds__(kTileThreads) void k_batch_step(
+    const ChanDesc *__restrict__ chans, const Tile *__restrict__ tiles,
+    const int *__restrict__ ntiles_dev, int parity, double *__restrict__ partials) {
+  const int nt = *ntiles_dev;
+  __shared__ double lds[(kTileThreads / 64) * NREDB];
+  for (int t = blockIdx.x; t < nt; t += gridDim.x) { // uniform per block
+    const Tile tl = tiles[t];
+    const ChanDesc &c = chans[tl.chan];
+    const int lx = (int)threadIdx.x % tl.w;
+    const int ly = (int)threadIdx.x / tl.w;
+    const int x = tl.x0 + lx, y = tl.y0 + ly;
+    const bool act = (ly < tl.h) && (x < c.g.nx) && (y < c.g.ny);
+    const int cur = parity ^ c.phase;
+    const S *src = static_cast<const S *>(c.buf[cur]);
+    S *dst = static_cast<S *>(c.buf[cur ^ 1]);
+    NodeObs<C> o{};
+    if (act) {
+      if (c.bc == BC_LINK)
+        node_update<S, C, BC_LINK, MODE>(c.g, coef_of<C>(c), src, dst, x, y, o);
+      else
+        node_update<S, C, BC_MOMENT, MODE>(c.g, coef_of<C>(c), src, dst, x, y, o);
+    }
+    const long long n = (long long)c.g.nx * c.g.ny;
+    const long long i = (long long)y * c.g.nx + x;
+    if constexpr (MODE == MODE_RECORD) {
+      if (act) {
+        c.rec[i] = (double)o.ux;
+        c.rec[n + i] = (double)o.bx;
+      }
+    }
+    if constexpr (MODE == MODE_RESIDUAL) {
+      double v[NREDB] = {0, 0, 0, 0, 0, 0};
+      if (act) {
+        const double u = (double)o.ux, b = (double)o.bx;
+        const double du = u - c.rec[i], db = b - c.rec[n + i];
+        v[0] = du * du;
+        v[1] = u * u;
+        v[2] = db * db;
+        v[3] = b * b;
+        v[4] = u;
+        const bool ok = isfinite((double)o.rho) && isfinite(u) && isfinite((double)o.uy) &&
+                        isfinite(b) && isfinite((double)o.by) && (double)o.rho > 0.0;
+        v[5] = ok ? 0.0 : 1.0;
+      }
+      block_sum<NREDB, kTileThreads>(v, lds);
+      if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < NREDB; ++j) partials[(long long)t * 8 + j] = v[j];
+      }
+      __syncthreads(); // lds is reused by the next tile
+    }
+  }
+}
+
+// Per-slot fixed-order sums of the slot's tile partials (one block per slot).
+__global__ __launch_bounds__(64) void k_batch_finalize(const ChanDesc *__restrict__ chans,
+                                                       const int *__restrict__ active,
+                                                       const double *__restrict__ partials,
+                                                       double *__restrict__ sums) {
+  const int slot = blockIdx.x;
+  if (!active[slot]) return;
+  const ChanDesc &c = chans[slot];
+  double v[NREDB] = {0, 0, 0, 0, 0, 0};
+  for (int t = threadIdx.x; t < c.tile_count; t += 64)
+#pragma unroll
+    for (int j = 0; j < NREDB; ++j) v[j] += partials[(long long)(c.tile_first + t) * 8 + j];
+  wave_sum<NREDB>(v);
+  if (threadIdx.x == 0)
+    for (int j = 0; j < NREDB; ++j) sums[(long long)slot * 8 + j] = v[j];
+}
+
+// Observables of one channel (no collision), FP64 outputs.
+struct ObsOutB {
+  double *rho, *ux, *uy, *bx, *by, *jz;
+};
+
+template <typename S, typename C, int BC>
+__global__ __launch_bounds__(256) void k_chan_moments(Geom g, Coef<C> k, const S *__restrict__ src,
+                                                      ObsOutB oo) {
+  const long long n = (long long)g.nx * g.ny;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int y = (int)(i / g.nx), x = (int)(i - (long long)y * g.nx);
+  NodeObs<C> o{};
+  node_update<S, C, BC, MODE_MOMENTS>(g, k, src, nullptr, x, y, o);
+  if (oo.rho) oo.rho[i] = 1.0 + (double)o.rhop;
+  if (oo.ux) oo.ux[i] = (double)o.ux;
+  if (oo.uy) oo.uy[i] = (double)o.uy;
+  if (oo.bx) oo.bx[i] = (double)o.bx;
+  if (oo.by) oo.by[i] = (double)o.by;
+  if (oo.jz) oo.jz[i] = (double)o.jz;
+}
+
+} // namespace lks
+
+using namespace lks;
+
+namespace {
+
+struct Slot {
+  bool used = false;
+  Channel ch;
+  size_t offset = 0, bytes = 0; // region in the pool
+  int64_t admit_step = 0;        // global step count at admission
+  int width_class = 0;
+};
+
+struct Region {
+  size_t offset, bytes;
+};
+
+} // namespace
+
+struct lks_mhd_batch {
+  int precision = LKS_FP32;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int max_channels = 0;
+  int64_t max_nodes = 0;
+  int max_tiles = 0;
+  char *pool = nullptr;
+  size_t pool_bytes = 0;
+  // carved device arrays
+  ChanDesc *d_chans = nullptr;
+  Tile *d_tiles = nullptr;
+  int *d_ntiles = nullptr;
+  int *d_active = nullptr;
+  double *d_partials = nullptr;
+  double *d_sums = nullptr;
+  size_t heap_begin = 0;
+  std::vector<Region> free_list; // sorted by offset
+  std::vector<Slot> slots;
+  std::vector<ChanDesc> h_chans;
+  std::vector<Tile> h_tiles;
+  std::vector<int> h_active;
+  int tile_w[kWidthClasses] = {8, 16, 32, 64, 128, 256, 256};
+  int64_t global_steps = 0;
+  int parity = 0;
+  int64_t nodes = 0;
+  int nactive = 0;
+  int grid = 0;
+  bool dirty = false;
+  hipGraphExec_t gexec = nullptr;
+};
+
+namespace {
+
+size_t overhead(int max_channels, int max_tiles) {
+  size_t b = 0;
+  b += align256((size_t)max_channels * sizeof(ChanDesc));
+  b += align256((size_t)max_tiles * sizeof(Tile));
+  b += 256;                                            // tile count
+  b += align256((size_t)max_channels * sizeof(int));   // active flags
+  b += align256((size_t)max_tiles * 8 * sizeof(double));
+  b += align256((size_t)max_channels * 8 * sizeof(double));
+  return b;
+}
+
+int tiles_for(int64_t max_nodes, int max_channels) {
+  // Every tile of a channel except its last column / row of tiles is full;
+  // 32 nodes per tile on average is a safe lower bound for any shape table.
+  const int64_t t = max_nodes / 32 + 8LL * max_channels + 64;
+  return (int)std::min<int64_t>(t, (1LL << 30));
+}
+
+int width_class_of(int nx) {
+  int k = 0;
+  int lim = 8;
+  while (k < kWidthClasses - 1 && nx > lim) {
+    lim *= 2;
+    ++k;
+  }
+  return k;
+}
+
+size_t channel_region_bytes(const Channel &c, int precision) {
+  const long long plane = plane_elems(c.p.nx, c.p.ny, precision);
+  const size_t state = align256((size_t)19 * plane * elem_bytes(precision));
+  const size_t rec = align256((size_t)2 * c.p.nx * c.p.ny * sizeof(double));
+  return 2 * state + rec;
+}
+
+template <typename F>
+int with_device(lks_mhd_batch *b, F &&fn) {
+  int prev = 0;
+  if (hipGetDevice(&prev) != hipSuccess) prev = b->device;
+  if (prev != b->device) LKS_HIP_CHECK(hipSetDevice(b->device));
+  const int rc = fn();
+  if (prev != b->device) (void)hipSetDevice(prev);
+  return rc;
+}
+
+bool pool_alloc(lks_mhd_batch *b, size_t bytes, size_t *off) {
+  for (size_t i = 0; i < b->free_list.size(); ++i) {
+    Region &r = b->free_list[i];
+    if (r.bytes >= bytes) {
+      *off = r.offset;
+      r.offset += bytes;
+      r.bytes -= bytes;
+      if (r.bytes == 0) b->free_list.erase(b->free_list.begin() + i);
+      return true;
+    }
+  }
+  return false;
+}
+
+void pool_free(lks_mhd_batch *b, size_t off, size_t bytes) {
+  auto it = std::lower_bound(b->free_list.begin(), b->free_list.end(), off,
+                             [](const Region &r, size_t o) { return r.offset < o; });
+  it = b->free_list.insert(it, Region{off, bytes});
+  // merge with neighbours
+  const size_t i = it - b->free_list.begin();
+  if (i + 1 < b->free_list.size() &&
+      b->free_list[i].offset + b->free_list[i].bytes == b->free_list[i + 1].offset) {
+    b->free_list[i].bytes += b->free_list[i + 1].bytes;
+    b->free_list.erase(b->free_list.begin() + i + 1);
+  }
+  if (i > 0 && b->free_list[i - 1].offset + b->free_list[i - 1].bytes == b->free_list[i].offset) {
+    b->free_list[i - 1].bytes += b->free_list[i].bytes;
+    b->free_list.erase(b->free_list.begin() + i);
+  }
+}
+
+// Tiles of one channel for a tile width (height = 256 / width).
+int count_tiles(int nx, int ny, int w) {
+  const int h = kTileThreads / w;
+  return ((nx + w - 1) / w) * ((ny + h - 1) / h);
+}
+
+int total_tiles(const lks_mhd_batch *b, const int *tile_w) {
+  long long t = 0;
+  for (const Slot &s : b->slots)
+    if (s.used) t += count_tiles(s.ch.p.nx, s.ch.p.ny, tile_w[s.width_class]);
+  return t > (1LL << 30) ? (1 << 30) : (int)t;
+}
+
+// Rebuild descriptors' tile ranges and the tile list; upload both.
+int rebuild(lks_mhd_batch *b) {
+  b->h_tiles.clear();
+  for (int s = 0; s < b->max_channels; ++s) {
+    Slot &sl = b->slots[s];
+    ChanDesc &d = b->h_chans[s];
+    if (!sl.used) {
+      d.tile_first = 0;
+      d.tile_count = 0;
+      continue;
+    }
+    const int w = b->tile_w[sl.width_class];
+    const int h = kTileThreads / w;
+    d.tile_first = (int)b->h_tiles.size();
+    for (int y0 = 0; y0 < sl.ch.p.ny; y0 += h)
+      for (int x0 = 0; x0 < sl.ch.p.nx; x0 += w) b->h_tiles.push_back(Tile{s, x0, y0, w, h, {0, 0, 0}});
+    d.tile_count = (int)b->h_tiles.size() - d.tile_first;
+  }
+  if ((int)b->h_tiles.size() > b->max_tiles) {
+    set_error("tile list of %zu tiles exceeds the capacity %d", b->h_tiles.size(), b->max_tiles);
+    return LKS_ENOMEM;
+  }
+  const int nt = (int)b->h_tiles.size();
+  LKS_HIP_CHECK(hipMemcpyAsync(b->d_chans, b->h_chans.data(), b->max_channels * sizeof(ChanDesc),
+                               hipMemcpyHostToDevice, b->stream));
+  if (nt > 0)
+    LKS_HIP_CHECK(hipMemcpyAsync(b->d_tiles, b->h_tiles.data(), nt * sizeof(Tile),
+                                 hipMemcpyHostToDevice, b->stream));
+  LKS_HIP_CHECK(hipMemcpyAsync(b->d_ntiles, &nt, sizeof(int), hipMemcpyHostToDevice, b->stream));
+  LKS_HIP_CHECK(hipMemcpyAsync(b->d_active, b->h_active.data(), b->max_channels * sizeof(int),
+                               hipMemcpyHostToDevice, b->stream));
+  LKS_HIP_CHECK(hipStreamSynchronize(b->stream)); // host vectors may change next
+  b->dirty = false;
+  return LKS_OK;
+}
+
+template <int MODE>
+hipError_t launch_batch(lks_mhd_batch *b, int parity) {
+  switch (b->precision) {
+  case LKS_FP64:
+    hipLaunchKernelGGL((k_batch_step<double, double, MODE>), dim3(b->grid), dim3(kTileThreads), 0,
+                       b->stream, b->d_chans, b->d_tiles, b->d_ntiles, parity, b->d_partials);
+    break;
+  case LKS_FP32:
+    hipLaunchKernelGGL((k_batch_step<float, float, MODE>), dim3(b->grid), dim3(kTileThreads), 0,
+                       b->stream, b->d_chans, b->d_tiles, b->d_ntiles, parity, b->d_partials);
+    break;
+  default:
+    hipLaunchKernelGGL((k_batch_step<_Float16, float, MODE>), dim3(b->grid), dim3(kTileThreads), 0,
+                       b->stream, b->d_chans, b->d_tiles, b->d_ntiles, parity, b->d_partials);
+  }
+  return hipGetLastError();
+}
+
+int batch_one(lks_mhd_batch *b, int mode) {
+  hipError_t e;
+  switch (mode) {
+  case MODE_STEP: e = launch_batch<MODE_STEP>(b, b->parity); break;
+  case MODE_RECORD: e = launch_batch<MODE_RECORD>(b, b->parity); break;
+  default: e = launch_batch<MODE_RESIDUAL>(b, b->parity); break;
+  }
+  if (e != hipSuccess) {
+    set_error("batched step launch failed: %s", hipGetErrorString(e));
+    return LKS_EDEVICE;
+  }
+  b->parity ^= 1;
+  b->global_steps += 1;
+  return LKS_OK;
+}
+
+int capture(lks_mhd_batch *b) {
+  hipGraph_t graph = nullptr;
+  LKS_HIP_CHECK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+  const int p0 = b->parity;
+  const int64_t s0 = b->global_steps;
+  b->parity = 0;
+  int rc = batch_one(b, MODE_STEP);
+  if (rc == LKS_OK) rc = batch_one(b, MODE_STEP);
+  b->parity = p0;
+  b->global_steps = s0;
+  hipError_t e = hipStreamEndCapture(b->stream, &graph);
+  if (rc != LKS_OK) return rc;
+  if (e != hipSuccess) {
+    set_error("hipStreamEndCapture failed: %s", hipGetErrorString(e));
+    return LKS_EDEVICE;
+  }
+  e = hipGraphInstantiate(&b->gexec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    set_error("hipGraphInstantiate failed: %s", hipGetErrorString(e));
+    return LKS_EDEVICE;
+  }
+  return LKS_OK;
+}
+
+int batch_steps(lks_mhd_batch *b, int64_t n, bool use_graph) {
+  if (b->dirty) {
+    const int rc = rebuild(b);
+    if (rc != LKS_OK) return rc;
+  }
+  if (b->nactive == 0) {
+    b->global_steps += n; // nothing to advance; keep parity bookkeeping
+    b->parity ^= (int)(n & 1);
+    return LKS_OK;
+  }
+  if (use_graph && b->stream == nullptr) {
+    set_error("graph capture needs a non-default stream");
+    return LKS_EINVAL;
+  }
+  while (n > 0) {
+    if (use_graph && n >= 2 && b->parity == 0) {
+      if (!b->gexec) {
+        const int rc = capture(b);
+        if (rc != LKS_OK) return rc;
+      }
+      LKS_HIP_CHECK(hipGraphLaunch(b->gexec, b->stream));
+      b->global_steps += 2;
+      n -= 2;
+    } else {
+      const int rc = batch_one(b, MODE_STEP);
+      if (rc != LKS_OK) return rc;
+      n -= 1;
+    }
+  }
+  return LKS_OK;
+}
+
+template <typename S>
+void launch_init(lks_mhd_batch *b, const Slot &s, void *buf) {
+  const long long n = (long long)s.ch.p.nx * s.ch.p.ny;
+  const Geom g{s.ch.p.nx, s.ch.p.ny, s.ch.p.nx, plane_elems(s.ch.p.nx, s.ch.p.ny, b->precision)};
+  hipLaunchKernelGGL(k_init<S>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, b->stream, g,
+                     s.ch.p.rho0, s.ch.d.b0, static_cast<S *>(buf));
+}
+
+} // namespace
+
+extern "C" {
+
+size_t lks_mhd_batch_overhead_bytes(int32_t max_channels, int64_t max_nodes) {
+  if (max_channels <= 0 || max_nodes <= 0) return 0;
+  return overhead(max_channels, tiles_for(max_nodes, max_channels));
+}
+
+size_t lks_mhd_batch_channel_bytes(const lks_mhd_params *p, int32_t precision) {
+  clear_error();
+  Channel c;
+  if (derive_channel(p, &c) != LKS_OK) return 0;
+  if (precision < LKS_FP64 || precision > LKS_FP16_STORE) return 0;
+  return channel_region_bytes(c, precision);
+}
+
+int lks_mhd_batch_create(int32_t precision, int32_t max_channels, int64_t max_nodes,
+                         void *dev_pool, size_t pool_bytes, void *hip_stream,
+                         lks_mhd_batch_t **out) {
+  clear_error();
+  if (!out || max_channels <= 0 || max_nodes <= 0 || precision < LKS_FP64 ||
+      precision > LKS_FP16_STORE) {
+    set_error("invalid batch arguments");
+    return LKS_EINVAL;
+  }
+  *out = nullptr;
+  if (!dev_pool || (reinterpret_cast<uintptr_t>(dev_pool) & 255u)) {
+    set_error("dev_pool must be a non-NULL 256-byte aligned device pointer");
+    return LKS_EINVAL;
+  }
+  const int max_tiles = tiles_for(max_nodes, max_channels);
+  const size_t ov = overhead(max_channels, max_tiles);
+  if (pool_bytes < ov) {
+    set_error("pool holds %zu bytes, the batch tables alone need %zu", pool_bytes, ov);
+    return LKS_ENOMEM;
+  }
+  lks_mhd_batch *b = new (std::nothrow) lks_mhd_batch();
+  if (!b) {
+    set_error("host allocation failed");
+    return LKS_ENOMEM;
+  }
+  b->precision = precision;
+  if (hipGetDevice(&b->device) != hipSuccess) b->device = 0;
+  b->stream = static_cast<hipStream_t>(hip_stream);
+  b->max_channels = max_channels;
+  b->max_nodes = max_nodes;
+  b->max_tiles = max_tiles;
+  b->pool = static_cast<char *>(dev_pool);
+  b->pool_bytes = pool_bytes;
+  char *p = b->pool;
+  b->d_chans = reinterpret_cast<ChanDesc *>(p);
+  p += align256((size_t)max_channels * sizeof(ChanDesc));
+  b->d_tiles = reinterpret_cast<Tile *>(p);
+  p += align256((size_t)max_tiles * sizeof(Tile));
+  b->d_ntiles = reinterpret_cast<int *>(p);
+  p += 256;
+  b->d_active = reinterpret_cast<int *>(p);
+  p += align256((size_t)max_channels * sizeof(int));
+  b->d_partials = reinterpret_cast<double *>(p);
+  p += align256((size_t)max_tiles * 8 * sizeof(double));
+  b->d_sums = reinterpret_cast<double *>(p);
+  p += align256((size_t)max_channels * 8 * sizeof(double));
+  b->heap_begin = (size_t)(p - b->pool);
+  if (pool_bytes > b->heap_begin) b->free_list.push_back(Region{b->heap_begin, pool_bytes - b->heap_begin});
+  b->slots.resize(max_channels);
+  b->h_chans.resize(max_channels);
+  std::memset(b->h_chans.data(), 0, b->h_chans.size() * sizeof(ChanDesc));
+  b->h_active.assign(max_channels, 0);
+  int cus = 256;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, b->device) == hipSuccess && prop.multiProcessorCount > 0)
+    cus = prop.multiProcessorCount;
+  b->grid = cus * 8; // persistent: 8 blocks of 256 threads per CU
+  const int rc = with_device(b, [&]() -> int { return rebuild(b); });
+  if (rc != LKS_OK) {
+    delete b;
+    return rc;
+  }
+  *out = b;
+  return LKS_OK;
+}
+
+int lks_mhd_batch_destroy(lks_mhd_batch_t *b) {
+  clear_error();
+  if (!b) return LKS_OK;
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  delete b;
+  return LKS_OK;
+}
+
+int lks_mhd_batch_admit(lks_mhd_batch_t *b, const lks_mhd_params *p, int32_t *slot) {
+  clear_error();
+  if (!b || !p || !slot) {
+    set_error("invalid batch, parameters or slot pointer");
+    return LKS_EINVAL;
+  }
+  lks_mhd_params q = *p;
+  q.precision = b->precision;
+  Channel c;
+  int rc = derive_channel(&q, &c);
+  if (rc != LKS_OK) return rc;
+  const int64_t n = (int64_t)q.nx * q.ny;
+  if (b->nodes + n > b->max_nodes) {
+    set_error("batch node capacity %lld exceeded", (long long)b->max_nodes);
+    return LKS_ENOMEM;
+  }
+  int s = -1;
+  for (int i = 0; i < b->max_channels; ++i)
+    if (!b->slots[i].used) {
+      s = i;
+      break;
+    }
+  if (s < 0) {
+    set_error("all %d slots are in use", b->max_channels);
+    return LKS_ENOMEM;
+  }
+  Slot sl;
+  sl.used = true;
+  sl.ch = c;
+  sl.width_class = width_class_of(q.nx);
+  // tile capacity check for the current shape table
+  {
+    int tw[kWidthClasses];
+    std::memcpy(tw, b->tile_w, sizeof tw);
+    if ((long long)total_tiles(b, tw) + count_tiles(q.nx, q.ny, tw[sl.width_class]) > b->max_tiles) {
+      set_error("tile list capacity exceeded");
+      return LKS_ENOMEM;
+    }
+  }
+  sl.bytes = channel_region_bytes(c, b->precision);
+  if (!pool_alloc(b, sl.bytes, &sl.offset)) {
+    set_error("pool has no free region of %zu bytes", sl.bytes);
+    return LKS_ENOMEM;
+  }
+  const long long plane = plane_elems(q.nx, q.ny, b->precision);
+  const size_t state = align256((size_t)19 * plane * elem_bytes(b->precision));
+  char *base = b->pool + sl.offset;
+  ChanDesc d{};
+  d.buf[0] = base;
+  d.buf[1] = base + state;
+  d.rec = reinterpret_cast<double *>(base + 2 * state);
+  d.g = Geom{q.nx, q.ny, q.nx, plane};
+  d.bc = q.bc == LKS_BC_LINK ? BC_LINK : BC_MOMENT;
+  // the initial state goes to buf[0]; at the next step the global parity is
+  // b->parity, and the channel must read buf[0] then: phase = parity.
+  d.phase = b->parity;
+  d.kf = make_coef<float>(c);
+  d.kd = make_coef<double>(c);
+  sl.admit_step = b->global_steps;
+  rc = with_device(b, [&]() -> int {
+    switch (b->precision) {
+    case LKS_FP64: launch_init<double>(b, sl, d.buf[0]); break;
+    case LKS_FP32: launch_init<float>(b, sl, d.buf[0]); break;
+    default: launch_init<_Float16>(b, sl, d.buf[0]);
+    }
+    LKS_HIP_CHECK(hipGetLastError());
+    return LKS_OK;
+  });
+  if (rc != LKS_OK) {
+    pool_free(b, sl.offset, sl.bytes);
+    return rc;
+  }
+  b->slots[s] = sl;
+  b->h_chans[s] = d;
+  b->h_active[s] = 1;
+  b->nodes += n;
+  b->nactive += 1;
+  b->dirty = true;
+  *slot = s;
+  return LKS_OK;
+}
+
+int lks_mhd_batch_retire(lks_mhd_batch_t *b, int32_t slot) {
+  clear_error();
+  if (!b || slot < 0 || slot >= b->max_channels || !b->slots[slot].used) {
+    set_error("invalid batch or slot");
+    return LKS_EINVAL;
+  }
+  Slot &sl = b->slots[slot];
+  // the pool region may be reused by the next admission: finish pending work
+  const int rc = with_device(b, [&]() -> int {
+    LKS_HIP_CHECK(hipStreamSynchronize(b->stream));
+    return LKS_OK;
+  });
+  if (rc != LKS_OK) return rc;
+  pool_free(b, sl.offset, sl.bytes);
+  b->nodes -= (int64_t)sl.ch.p.nx * sl.ch.p.ny;
+  b->nactive -= 1;
+  sl = Slot();
+  std::memset(&b->h_chans[slot], 0, sizeof(ChanDesc));
+  b->h_active[slot] = 0;
+  b->dirty = true;
+  return LKS_OK;
+}
+
+int32_t lks_mhd_batch_active(const lks_mhd_batch_t *b) { return b ? b->nactive : -1; }
+int64_t lks_mhd_batch_nodes(const lks_mhd_batch_t *b) { return b ? b->nodes : -1; }
+
+int lks_mhd_batch_set_tile(lks_mhd_batch_t *b, int32_t width_class, int32_t tile_w, int32_t tile_h) {
+  clear_error();
+  const bool ok_w = tile_w == 8 || tile_w == 16 || tile_w == 32 || tile_w == 64 ||
+                    tile_w == 128 || tile_w == 256;
+  if (!b || width_class < 0 || width_class >= kWidthClasses || !ok_w ||
+      tile_w * tile_h != kTileThreads) {
+    set_error("invalid width class or tile shape (w in {8..256}, w*h = 256)");
+    return LKS_EINVAL;
+  }
+  int tw[kWidthClasses];
+  std::memcpy(tw, b->tile_w, sizeof tw);
+  tw[width_class] = tile_w;
+  if (total_tiles(b, tw) > b->max_tiles) {
+    set_error("tile list capacity exceeded by this shape");
+    return LKS_ENOMEM;
+  }
+  b->tile_w[width_class] = tile_w;
+  b->dirty = true;
+  return LKS_OK;
+}
+
+int lks_mhd_batch_step(lks_mhd_batch_t *b, int64_t nsteps, int32_t use_graph) {
+  clear_error();
+  if (!b || nsteps < 0) {
+    set_error("invalid batch or negative step count");
+    return LKS_EINVAL;
+  }
+  return with_device(b, [&]() -> int { return batch_steps(b, nsteps, use_graph != 0); });
+}
+
+int lks_mhd_batch_step_check(lks_mhd_batch_t *b, int64_t nsteps, int32_t use_graph,
+                             double *residuals, int32_t *unstable) {
+  clear_error();
+  if (!b || nsteps < 2) {
+    set_error("invalid batch or nsteps < 2");
+    return LKS_EINVAL;
+  }
+  std::vector<double> sums((size_t)b->max_channels * 8, 0.0);
+  const int rc = with_device(b, [&]() -> int {
+    int r = batch_steps(b, nsteps - 2, use_graph != 0);
+    if (r != LKS_OK) return r;
+    if (b->nactive > 0) {
+      if ((r = batch_one(b, MODE_RECORD)) != LKS_OK) return r;
+      if ((r = batch_one(b, MODE_RESIDUAL)) != LKS_OK) return r;
+      hipLaunchKernelGGL(k_batch_finalize, dim3(b->max_channels), dim3(64), 0, b->stream,
+                         b->d_chans, b->d_active, b->d_partials, b->d_sums);
+      LKS_HIP_CHECK(hipGetLastError());
+      LKS_HIP_CHECK(hipMemcpyAsync(sums.data(), b->d_sums, sums.size() * sizeof(double),
+                                   hipMemcpyDeviceToHost, b->stream));
+    } else {
+      b->global_steps += 2;
+    }
+    LKS_HIP_CHECK(hipStreamSynchronize(b->stream));
+    return LKS_OK;
+  });
+  if (rc != LKS_OK) return rc;
+  for (int s = 0; s < b->max_channels; ++s) {
+    double r = NAN;
+    int bad = 0;
+    if (b->slots[s].used) {
+      const double *v = &sums[(size_t)s * 8];
+      const double ru = std::sqrt(v[0]) / std::fmax(std::sqrt(v[1]), 1e-300);
+      const double rb = std::sqrt(v[2]) / std::fmax(std::sqrt(v[3]), 1e-300);
+      r = std::fmax(ru, rb);
+      bad = (v[5] != 0.0 || !std::isfinite(r)) ? 1 : 0;
+    }
+    if (residuals) residuals[s] = r;
+    if (unstable) unstable[s] = bad;
+  }
+  return LKS_OK;
+}
+
+int64_t lks_mhd_batch_steps_done(const lks_mhd_batch_t *b, int32_t slot) {
+  if (!b || slot < 0 || slot >= b->max_channels || !b->slots[slot].used) return -1;
+  return b->global_steps - b->slots[slot].admit_step;
+}
+
+int lks_mhd_batch_moments(lks_mhd_batch_t *b, int32_t slot, double *rho, double *ux,
+                          double *uy, double *bx, double *by, double *jz) {
+  clear_error();
+  if (!b || slot < 0 || slot >= b->max_channels || !b->slots[slot].used) {
+    set_error("invalid batch or slot");
+    return LKS_EINVAL;
+  }
+  const ChanDesc &d = b->h_chans[slot];
+  const int cur = b->parity ^ d.phase;
+  const ObsOutB oo{rho, ux, uy, bx, by, jz};
+  const long long n = (long long)d.g.nx * d.g.ny;
+  const dim3 grid((unsigned)((n + 255) / 256));
+  return with_device(b, [&]() -> int {
+    const bool link = d.bc == BC_LINK;
+    switch (b->precision) {
+    case LKS_FP64:
+      if (link) hipLaunchKernelGGL((k_chan_moments<double, double, BC_LINK>), grid, dim3(256), 0, b->stream, d.g, d.kd, (const double *)d.buf[cur], oo);
+      else hipLaunchKernelGGL((k_chan_moments<double, double, BC_MOMENT>), grid, dim3(256), 0, b->stream, d.g, d.kd, (const double *)d.buf[cur], oo);
+      break;
+    case LKS_FP32:
+      if (link) hipLaunchKernelGGL((k_chan_moments<float, float, BC_LINK>), grid, dim3(256), 0, b->stream, d.g, d.kf, (const float *)d.buf[cur], oo);
+      else hipLaunchKernelGGL((k_chan_moments<float, float, BC_MOMENT>), grid, dim3(256), 0, b->stream, d.g, d.kf, (const float *)d.buf[cur], oo);
+      break;
+    default:
+      if (link) hipLaunchKernelGGL((k_chan_moments<_Float16, float, BC_LINK>), grid, dim3(256), 0, b->stream, d.g, d.kf, (const _Float16 *)d.buf[cur], oo);
+      else hipLaunchKernelGGL((k_chan_moments<_Float16, float, BC_MOMENT>), grid, dim3(256), 0, b->stream, d.g, d.kf, (const _Float16 *)d.buf[cur], oo);
+    }
+    LKS_HIP_CHECK(hipGetLastError());
+    return LKS_OK;
+  });
+}
+
+int lks_mhd_batch_save_state(lks_mhd_batch_t *b, int32_t slot, double *dev_pops) {
+  clear_error();
+  if (!b || !dev_pops || slot < 0 || slot >= b->max_channels || !b->slots[slot].used) {
+    set_error("invalid batch, slot or destination");
+    return LKS_EINVAL;
+  }
+  const ChanDesc &d = b->h_chans[slot];
+  const int cur = b->parity ^ d.phase;
+  const long long n = (long long)d.g.nx * d.g.ny;
+  const dim3 grid((unsigned)((n + 255) / 256));
+  return with_device(b, [&]() -> int {
+    switch (b->precision) {
+    case LKS_FP64: hipLaunchKernelGGL(k_save<double>, grid, dim3(256), 0, b->stream, d.g, (const double *)d.buf[cur], dev_pops); break;
+    case LKS_FP32: hipLaunchKernelGGL(k_save<float>, grid, dim3(256), 0, b->stream, d.g, (const float *)d.buf[cur], dev_pops); break;
+    default: hipLaunchKernelGGL(k_save<_Float16>, grid, dim3(256), 0, b->stream, d.g, (const _Float16 *)d.buf[cur], dev_pops);
+    }
+    LKS_HIP_CHECK(hipGetLastError());
+    return LKS_OK;
+  });
+}
+
+int lks_mhd_batch_autotune(lks_mhd_batch_t *b, int32_t trial_steps, int32_t *tiles_out) {
+  clear_error();
+  if (!b || trial_steps < 1) {
+    set_error("invalid batch or trial_steps < 1");
+    return LKS_EINVAL;
+  }
+  const int cands[6] = {8, 16, 32, 64, 128, 256};
+  const int rc = with_device(b, [&]() -> int {
+    bool present[kWidthClasses] = {false};
+    for (const Slot &s : b->slots)
+      if (s.used) present[s.width_class] = true;
+    hipEvent_t e0, e1;
+    LKS_HIP_CHECK(hipEventCreate(&e0));
+    LKS_HIP_CHECK(hipEventCreate(&e1));
+    int result = LKS_OK;
+    for (int k = 0; k < kWidthClasses && result == LKS_OK; ++k) {
+      if (!present[k]) continue;
+      // widths no wider than twice the class's upper width bound
+      const int upper = (k == kWidthClasses - 1) ? 1 << 30 : (8 << k);
+      float best = 1e30f;
+      int best_w = b->tile_w[k];
+      for (int w : cands) {
+        if (w > 2 * upper && w != 8) continue;
+        int tw[kWidthClasses];
+        std::memcpy(tw, b->tile_w, sizeof tw);
+        tw[k] = w;
+        if (total_tiles(b, tw) > b->max_tiles) continue;
+        b->tile_w[k] = w;
+        b->dirty = true;
+        // the trial steps advance every channel; an even count keeps the
+        // parity, and the steps are counted like any other
+        int r = batch_steps(b, 2, false); // warm-up
+        if (r == LKS_OK) r = (hipEventRecord(e0, b->stream) == hipSuccess) ? LKS_OK : LKS_EDEVICE;
+        if (r == LKS_OK) r = batch_steps(b, 2 * ((trial_steps + 1) / 2), false);
+        if (r == LKS_OK) r = (hipEventRecord(e1, b->stream) == hipSuccess) ? LKS_OK : LKS_EDEVICE;
+        if (r == LKS_OK) r = (hipEventSynchronize(e1) == hipSuccess) ? LKS_OK : LKS_EDEVICE;
+        float ms = 0.f;
+        if (r == LKS_OK) r = (hipEventElapsedTime(&ms, e0, e1) == hipSuccess) ? LKS_OK : LKS_EDEVICE;
+        if (r != LKS_OK) {
+          if (r == LKS_EDEVICE) set_error("autotune timing failed");
+          result = r;
+          break;
+        }
+        if (ms < best) {
+          best = ms;
+          best_w = w;
+        }
+      }
+      b->tile_w[k] = best_w;
+      b->dirty = true;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return result;
+  });
+  if (tiles_out)
+    for (int k = 0; k < kWidthClasses; ++k) {
+      tiles_out[2 * k] = b->tile_w[k];
+      tiles_out[2 * k + 1] = kTileThreads / b->tile_w[k];
+    }
+  return rc;
+}
+
+} // extern "C"

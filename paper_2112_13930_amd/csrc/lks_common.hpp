@@ -1,0 +1,75 @@
+// Host-side helpers shared by the single-channel and batched entry points:
+// thread-local error reporting, HIP error checks, parameter validation and
+// derivation, and the FP64 wall-closure coefficients.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+
+#include "lks_mhd.h"
+#include "lks_node.hpp"
+
+namespace lks {
+
+void set_error(const char *fmt, ...);
+void clear_error();
+
+#define LKS_HIP_CHECK(call)                                                   \
+  do {                                                                        \
+    hipError_t e_ = (call);                                                   \
+    if (e_ != hipSuccess) {                                                   \
+      ::lks::set_error("%s failed: %s", #call, hipGetErrorString(e_));        \
+      return LKS_EDEVICE;                                                     \
+    }                                                                         \
+  } while (0)
+
+// Validated parameter set with the derived lattice quantities.
+struct Channel {
+  lks_mhd_params p;
+  lks_mhd_derived d;
+};
+
+// Validate and derive; LKS_OK or LKS_EINVAL with a message.
+int derive_channel(const lks_mhd_params *p, Channel *out);
+
+// FP64 closure coefficients of both walls (see Wall<C> in lks_node.hpp).
+struct WallD {
+  double r, s, t, u, uw6;
+};
+void wall_coefficients(const Channel &c, WallD *lo, WallD *hi);
+
+template <typename C>
+Coef<C> make_coef(const Channel &c) {
+  WallD lo, hi;
+  wall_coefficients(c, &lo, &hi);
+  Coef<C> k;
+  k.omega_f = C(1.0 / c.p.tau_f);
+  k.kappa_f = C(1.0 - 0.5 / c.p.tau_f);
+  k.omega_m = C(1.0 / c.p.tau_m);
+  k.k_m = C(3.0 / c.p.tau_m);
+  k.b0 = C(c.d.b0);
+  k.fex = C(c.d.fx);
+  k.fey = C(c.d.fy);
+  k.lo = Wall<C>{C(lo.r), C(lo.s), C(lo.t), C(lo.u), C(lo.uw6)};
+  k.hi = Wall<C>{C(hi.r), C(hi.s), C(hi.t), C(hi.u), C(hi.uw6)};
+  return k;
+}
+
+inline size_t elem_bytes(int precision) {
+  return precision == LKS_FP64 ? 8 : (precision == LKS_FP32 ? 4 : 2);
+}
+
+// Elements per plane, rounded up so that every plane starts 256-byte aligned.
+inline long long plane_elems(int nx, int ny, int precision) {
+  const long long n = (long long)nx * ny;
+  const long long per256 = 256 / (long long)elem_bytes(precision);
+  return (n + per256 - 1) / per256 * per256;
+}
+
+inline size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+} // namespace lks

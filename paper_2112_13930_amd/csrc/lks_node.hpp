@@ -1,0 +1,296 @@
+// Per-node fused update of the lattice-kinetic MHD step for gfx950.
+//
+// One call updates one lattice node: pull the 19 post-collision populations
+// of the previous step from the node's neighbours (structure-of-arrays
+// planes, x contiguous), close the populations that would come from behind a
+// wall (link-based or on-node moment-based Shercliff closures), take the
+// moments, solve the local u <-> J_z coupling in closed form, collide f and g
+// (BGK) and store the 19 new populations.  Every stored value of the previous
+// step is read exactly once per step, so the step streams 19 reads and 19
+// writes per node through HBM.
+//
+// Storage: S is the stored type (double, float or _Float16), C the compute
+// type (double for double storage, float otherwise).  Flow populations are
+// stored as deviations f_alpha - w_alpha from the rest equilibrium at unit
+// density; magnetic populations as values.
+//
+// Method references (Yahia & Premnath, arXiv 2112.13930):
+//   equilibria, source, moments: Secs. IV, V;  J_z: Sec. IV;  F = J x B: Sec. II
+//   link-based closures: Sec. VI (Eq. linkbasedBCschemefinal), App. B.1
+//   moment-based closures: Sec. VII, App. A, App. B.2
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lks {
+
+enum { BC_LINK = 0, BC_MOMENT = 1 };
+enum { MODE_STEP = 0, MODE_RECORD = 1, MODE_RESIDUAL = 2, MODE_MOMENTS = 3 };
+
+// Closure coefficients of one wall (computed on the host in FP64).
+//   link:   g_in,x = r * g~_out,x + t                 (Eq. movingwalllinkbasedclosure)
+//           r = (theta-1)/(theta+1), t = -/+ theta/(theta+1) B0 U_w (lower/upper)
+//   moment: g_in,x = r * g_opp,x - s * (g_0x+g_1x+g_3x) + t
+//           r = (phi-1)/(phi+1), s = 1/(phi+1), t = -/+ phi/(phi+1) B0 U_w,
+//           phi = c_w a / (tau_m cs2m)   (Sec. VII, App. B.2, both limits exact)
+//   uw6 = U_w/6 is Ladd's moving-wall term 2 w e_x U_w / cs2 of the diagonals.
+template <typename C>
+struct Wall {
+  C r, s, t, u, uw6;
+};
+
+template <typename C>
+struct Coef {
+  C omega_f;  // 1/tau_f
+  C kappa_f;  // 1 - 1/(2 tau_f)
+  C omega_m;  // 1/tau_m
+  C k_m;      // 1/(tau_m cs2m)
+  C b0;       // imposed field (along +y)
+  C fex, fey; // external body force
+  Wall<C> lo, hi;
+};
+
+// Geometry of one channel's planes (element units).
+struct Geom {
+  int nx, ny;
+  int pitch;          // elements between rows
+  long long plane;    // elements between planes
+};
+
+// Observables a mode may need.
+template <typename C>
+struct NodeObs {
+  C rho, rhop, ux, uy, bx, by, jz; // rhop = rho - 1 as accumulated from the deviations
+};
+
+template <typename S, typename C>
+__device__ __forceinline__ C ld(const S *__restrict__ p) {
+  return static_cast<C>(*p);
+}
+
+template <typename S, typename C>
+__device__ __forceinline__ void st(S *__restrict__ p, C v) {
+  __builtin_nontemporal_store(static_cast<S>(v), p);
+}
+
+// Weights (Secs. IV and V).
+template <typename C> struct W {
+  static constexpr C w0 = C(4) / C(9), w1 = C(1) / C(9), w5 = C(1) / C(36);
+  static constexpr C W0 = C(1) / C(3), W1 = C(1) / C(6);
+};
+
+// Post-collision update of f_alpha in deviation form (Sec. V):
+//   f~' = f' + omega (feq' - f') + kappa S,
+//   feq' = w (rho' + rho poly),  S = 3 w (e.F - u.F) (1 + poly),
+//   poly = 3 e.u + 4.5 (e.u)^2 - 1.5 u.u.
+template <typename C>
+__device__ __forceinline__ C collide_f(C f, C w, C ex, C ey, C rhop, C rho,
+                                       C ux, C uy, C usq15, C Fx, C Fy, C uF,
+                                       C omega, C kappa) {
+  const C eu = ex * ux + ey * uy;
+  const C poly = C(3) * eu + C(4.5) * eu * eu - usq15;
+  const C feq = w * (rhop + rho * poly);
+  const C S = C(3) * w * (ex * Fx + ey * Fy - uF) * (C(1) + poly);
+  return f + omega * (feq - f) + kappa * S;
+}
+
+template <typename S, typename C, int BC, int MODE>
+__device__ __forceinline__ void node_update(const Geom &g, const Coef<C> &k,
+                                            const S *__restrict__ src,
+                                            S *__restrict__ dst, int x, int y,
+                                            NodeObs<C> &obs) {
+  const int nx = g.nx;
+  const long long P = g.plane;
+  const int xm = (x == 0) ? nx - 1 : x - 1;
+  const int xp = (x == nx - 1) ? 0 : x + 1;
+  const bool lo = (y == 0);
+  const bool hi = (y == g.ny - 1);
+  const long long r0 = (long long)y * g.pitch;
+  const long long rm = r0 - g.pitch;
+  const long long rp = r0 + g.pitch;
+
+  // ---- pull streaming: f_a(x) = f~_a(x - e_a) ----
+  C f[9], gx[5], gy[5];
+  f[0] = ld<S, C>(src + r0 + x);
+  f[1] = ld<S, C>(src + 1 * P + r0 + xm);
+  f[3] = ld<S, C>(src + 3 * P + r0 + xp);
+  gx[0] = ld<S, C>(src + 9 * P + r0 + x);
+  gx[1] = ld<S, C>(src + 10 * P + r0 + xm);
+  gx[3] = ld<S, C>(src + 12 * P + r0 + xp);
+  gy[0] = ld<S, C>(src + 14 * P + r0 + x);
+  gy[1] = ld<S, C>(src + 15 * P + r0 + xm);
+  gy[3] = ld<S, C>(src + 17 * P + r0 + xp);
+  if (!lo) {
+    f[2] = ld<S, C>(src + 2 * P + rm + x);
+    f[5] = ld<S, C>(src + 5 * P + rm + xm);
+    f[6] = ld<S, C>(src + 6 * P + rm + xp);
+    gx[2] = ld<S, C>(src + 11 * P + rm + x);
+    gy[2] = ld<S, C>(src + 16 * P + rm + x);
+  }
+  if (!hi) {
+    f[4] = ld<S, C>(src + 4 * P + rp + x);
+    f[7] = ld<S, C>(src + 7 * P + rp + xp);
+    f[8] = ld<S, C>(src + 8 * P + rp + xm);
+    gx[4] = ld<S, C>(src + 13 * P + rp + x);
+    gy[4] = ld<S, C>(src + 18 * P + rp + x);
+  }
+
+  // ---- wall closures for the populations entering from a wall ----
+  if (BC == BC_LINK) {
+    // Half-way bounce-back of f with Ladd's moving-wall term; theta-weighted
+    // bounce-back/anti-bounce-back of g_x; anti-bounce-back to B_y = B0 for
+    // g_y.  All from the node's own post-collision values.
+    const C b0_3 = k.b0 * (C(1) / C(3)); // 2 W_alpha B0 with W = 1/6
+    if (lo) {
+      f[2] = ld<S, C>(src + 4 * P + r0 + x);
+      f[5] = ld<S, C>(src + 7 * P + r0 + x) + k.lo.uw6;
+      f[6] = ld<S, C>(src + 8 * P + r0 + x) - k.lo.uw6;
+      gx[2] = k.lo.r * ld<S, C>(src + 13 * P + r0 + x) + k.lo.t;
+      gy[2] = b0_3 - ld<S, C>(src + 18 * P + r0 + x);
+    }
+    if (hi) {
+      f[4] = ld<S, C>(src + 2 * P + r0 + x);
+      f[7] = ld<S, C>(src + 5 * P + r0 + x) - k.hi.uw6;
+      f[8] = ld<S, C>(src + 6 * P + r0 + x) + k.hi.uw6;
+      gx[4] = k.hi.r * ld<S, C>(src + 11 * P + r0 + x) + k.hi.t;
+      gy[4] = b0_3 - ld<S, C>(src + 16 * P + r0 + x);
+    }
+  } else {
+    // On-node closures from the moment constraints, written for the
+    // deviations f' = f - w (the weights of each relation sum out).
+    if (lo) {
+      const C U = k.lo.u;
+      const C rhop = f[0] + f[1] + f[3] + C(2) * (f[4] + f[7] + f[8]);
+      const C rho = C(1) + rhop;
+      f[2] = -rhop * (C(1) / C(3)) - rho * U * U +
+             (f[1] + f[3] + f[4] + C(2) * (f[7] + f[8]));
+      f[5] = rhop * (C(1) / C(6)) + C(0.5) * rho * (U * U + U) - (f[1] + f[8]);
+      f[6] = rhop * (C(1) / C(6)) + C(0.5) * rho * (U * U - U) - (f[3] + f[7]);
+      gx[2] = k.lo.r * gx[4] - k.lo.s * (gx[0] + gx[1] + gx[3]) + k.lo.t;
+      gy[2] = k.b0 - (gy[0] + gy[1] + gy[3] + gy[4]);
+    }
+    if (hi) {
+      const C U = k.hi.u;
+      const C rhop = f[0] + f[1] + f[3] + C(2) * (f[2] + f[5] + f[6]);
+      const C rho = C(1) + rhop;
+      f[4] = -rhop * (C(1) / C(3)) - rho * U * U +
+             (f[1] + f[2] + f[3] + C(2) * (f[5] + f[6]));
+      f[7] = rhop * (C(1) / C(6)) + C(0.5) * rho * (U * U - U) - (f[3] + f[6]);
+      f[8] = rhop * (C(1) / C(6)) + C(0.5) * rho * (U * U + U) - (f[1] + f[5]);
+      gx[4] = k.hi.r * gx[2] - k.hi.s * (gx[0] + gx[1] + gx[3]) + k.hi.t;
+      gy[4] = k.b0 - (gy[0] + gy[1] + gy[2] + gy[3]);
+    }
+  }
+
+  // ---- moments ----
+  const C rhop = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+  const C rho = C(1) + rhop;
+  const C mx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+  const C my = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+  const C bx = (gx[0] + gx[1]) + (gx[2] + gx[3]) + gx[4];
+  const C by = (gy[0] + gy[1]) + (gy[2] + gy[3]) + gy[4];
+  const C D = (gy[1] - gy[3]) - (gx[2] - gx[4]); // Lambda_xy - Lambda_yx
+
+  // ---- coupled local solve ----
+  C ux, uy, jz, Fx, Fy;
+  const C inv_rho = C(1) / rho;
+  if (BC == BC_MOMENT && (lo || hi)) {
+    // wet wall node: velocity fixed by the closure, no force
+    ux = mx * inv_rho;
+    uy = my * inv_rho;
+    jz = -k.k_m * (D - C(2) * (ux * by - uy * bx));
+    Fx = C(0);
+    Fy = C(0);
+  } else {
+    // rho u = m + F/2, F = F_ext + J_z (-B_y, B_x),
+    // J_z = -k [(L_xy - L0_xy) - (L_yx - L0_yx)], L0_xy = -L0_yx = u_x B_y - u_y B_x
+    //  => J_z = k (2P - rho D) / (rho + k |B|^2),
+    //     P = (m_x + Fe_x/2) B_y - (m_y + Fe_y/2) B_x.
+    const C px = mx + C(0.5) * k.fex;
+    const C py = my + C(0.5) * k.fey;
+    const C Pm = px * by - py * bx;
+    jz = k.k_m * (C(2) * Pm - rho * D) / (rho + k.k_m * (bx * bx + by * by));
+    Fx = k.fex - jz * by;
+    Fy = k.fey + jz * bx;
+    ux = (mx + C(0.5) * Fx) * inv_rho;
+    uy = (my + C(0.5) * Fy) * inv_rho;
+  }
+  obs.rho = rho;
+  obs.rhop = rhop;
+  obs.ux = ux;
+  obs.uy = uy;
+  obs.bx = bx;
+  obs.by = by;
+  obs.jz = jz;
+  if (MODE == MODE_MOMENTS) return;
+
+  // ---- collide and store ----
+  const long long o = r0 + x;
+  const C om = k.omega_f, ka = k.kappa_f;
+  const C usq15 = C(1.5) * (ux * ux + uy * uy);
+  const C uF = ux * Fx + uy * Fy;
+  const C w0 = W<C>::w0, w1 = W<C>::w1, w5 = W<C>::w5;
+  st<S, C>(dst + o, collide_f(f[0], w0, C(0), C(0), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka));
+  st<S, C>(dst + 1 * P + o, collide_f(f[1], w1, C(1), C(0), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka));
+  st<S, C>(dst + 2 * P + o, collide_f(f[2], w1, C(0), C(1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka));
+  st<S, C>(dst + 3 * P + o, collide_f(f[3], w1, C(-1), C(0), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka));
+  st<S, C>(dst + 4 * P + o, collide_f(f[4], w1, C(0), C(-1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka));
+  st<S, C>(dst + 5 * P + o, collide_f(f[5], w5, C(1), C(1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka));
+  st<S, C>(dst + 6 * P + o, collide_f(f[6], w5, C(-1), C(1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka));
+  st<S, C>(dst + 7 * P + o, collide_f(f[7], w5, C(-1), C(-1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka));
+  st<S, C>(dst + 8 * P + o, collide_f(f[8], w5, C(1), C(-1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka));
+
+  // g^eq_{a i} = W_a [B_i + e_aj (u_j B_i - B_j u_i) / cs2m]  (Sec. IV):
+  // with E = u_x B_y - u_y B_x only g_2x, g_4x (-/+ 3E) and g_1y, g_3y (+/- 3E)
+  // carry the flux term.
+  const C E3 = C(3) * (ux * by - uy * bx);
+  const C wm = k.omega_m;
+  const C W0 = W<C>::W0, W1 = W<C>::W1;
+  st<S, C>(dst + 9 * P + o, gx[0] + wm * (W0 * bx - gx[0]));
+  st<S, C>(dst + 10 * P + o, gx[1] + wm * (W1 * bx - gx[1]));
+  st<S, C>(dst + 11 * P + o, gx[2] + wm * (W1 * (bx - E3) - gx[2]));
+  st<S, C>(dst + 12 * P + o, gx[3] + wm * (W1 * bx - gx[3]));
+  st<S, C>(dst + 13 * P + o, gx[4] + wm * (W1 * (bx + E3) - gx[4]));
+  st<S, C>(dst + 14 * P + o, gy[0] + wm * (W0 * by - gy[0]));
+  st<S, C>(dst + 15 * P + o, gy[1] + wm * (W1 * (by + E3) - gy[1]));
+  st<S, C>(dst + 16 * P + o, gy[2] + wm * (W1 * by - gy[2]));
+  st<S, C>(dst + 17 * P + o, gy[3] + wm * (W1 * (by - E3) - gy[3]));
+  st<S, C>(dst + 18 * P + o, gy[4] + wm * (W1 * by - gy[4]));
+}
+
+// ---- FP64 block reduction (deterministic: fixed shuffle and LDS order) ----
+template <int NV>
+__device__ __forceinline__ void wave_sum(double (&v)[NV]) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] += __shfl_xor(v[i], off, 64);
+  }
+}
+
+// Sums v over the block; thread 0 of the block returns the totals in v.
+template <int NV, int NTHREADS>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double *lds) {
+  constexpr int NW = NTHREADS / 64;
+  const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+  wave_sum<NV>(v);
+  if constexpr (NW > 1) {
+    const int lane = tid & 63, wid = tid >> 6;
+    if (lane == 0) {
+#pragma unroll
+      for (int i = 0; i < NV; ++i) lds[wid * NV + i] = v[i];
+    }
+    __syncthreads();
+    if (tid == 0) {
+#pragma unroll
+      for (int i = 0; i < NV; ++i) {
+        double s = 0.0;
+        for (int w = 0; w < NW; ++w) s += lds[w * NV + i];
+        v[i] = s;
+      }
+    }
+  }
+}
+
+} // namespace lks

@@ -1,0 +1,511 @@
+// Single-channel entry points: the fused step kernel over one channel, the
+// record/residual/moments variants of it, init/save/load, FP64 residual
+// reduction and hipGraph replay of step sequences.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "lks_aux.hpp"
+#include "lks_common.hpp"
+
+namespace lks {
+
+struct ObsOut {
+  double *rho, *ux, *uy, *bx, *by, *jz;
+};
+
+constexpr int NRED = 6; // du2, u2, db2, b2, sum_u, nonfinite
+
+// Launch shapes of the step kernel: BX x BY threads per block cover a tile
+// of BX x BY nodes; REMAP maps consecutive tiles onto the same XCD (the
+// hardware deals workgroups round-robin to the 8 XCDs).
+struct Shape {
+  int bx, by;
+  bool remap;
+};
+constexpr Shape kShapes[] = {{256, 1, false}, {64, 4, true}, {128, 2, true},
+                             {256, 1, true}, {64, 4, false}};
+constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
+constexpr int kRedShape = 1; // shape used by record/residual/moments kernels
+
+__device__ __forceinline__ int map_tile(bool remap) {
+  const int id = blockIdx.x;
+  if (!remap) return id;
+  const int per = gridDim.x >> 3; // grid is a multiple of 8 when remapping
+  return (id & 7) * per + (id >> 3);
+}
+
+template <typename S, typename C, int BC, int MODE, int BX, int BY, bool REMAP>
+__global__ __launch_bounds__(BX *BY) void k_step(Geom g, Coef<C> k,
+                                                 const S *__restrict__ src,
+                                                 S *__restrict__ dst,
+                                                 int tiles_x, int ntiles,
+                                                 double *__restrict__ rec,
+                                                 double *__restrict__ partials,
+                                                 ObsOut oo) {
+  const int tile = map_tile(REMAP);
+  if (tile >= ntiles) return; // uniform per block
+  const int ty = tile / tiles_x;
+  const int tx = tile - ty * tiles_x;
+  const int x = tx * BX + (int)threadIdx.x;
+  const int y = ty * BY + (int)threadIdx.y;
+  const bool act = (x < g.nx) && (y < g.ny);
+  NodeObs<C> o{};
+  if (act) node_update<S, C, BC, MODE>(g, k, src, dst, x, y, o);
+  const long long n = (long long)g.nx * g.ny;
+  const long long i = (long long)y * g.nx + x;
+  if constexpr (MODE == MODE_RECORD) {
+    if (act) {
+      rec[i] = (double)o.ux;
+      rec[n + i] = (double)o.bx;
+    }
+  }
+  if constexpr (MODE == MODE_MOMENTS) {
+    if (act) {
+      if (oo.rho) oo.rho[i] = 1.0 + (double)o.rhop;
+      if (oo.ux) oo.ux[i] = (double)o.ux;
+      if (oo.uy) oo.uy[i] = (double)o.uy;
+      if (oo.bx) oo.bx[i] = (double)o.bx;
+      if (oo.by) oo.by[i] = (double)o.by;
+      if (oo.jz) oo.jz[i] = (double)o.jz;
+    }
+  }
+  if constexpr (MODE == MODE_RESIDUAL) {
+    __shared__ double lds[(BX * BY / 64) * NRED];
+    double v[NRED] = {0, 0, 0, 0, 0, 0};
+    if (act) {
+      const double u = (double)o.ux, b = (double)o.bx;
+      const double du = u - rec[i], db = b - rec[n + i];
+      v[0] = du * du;
+      v[1] = u * u;
+      v[2] = db * db;
+      v[3] = b * b;
+      v[4] = u;
+      const bool ok = isfinite((double)o.rho) && isfinite(u) && isfinite((double)o.uy) &&
+                      isfinite(b) && isfinite((double)o.by) && (double)o.rho > 0.0;
+      v[5] = ok ? 0.0 : 1.0;
+    }
+    block_sum<NRED, BX * BY>(v, lds);
+    if (threadIdx.x == 0 && threadIdx.y == 0) {
+#pragma unroll
+      for (int j = 0; j < NRED; ++j) partials[(long long)tile * 8 + j] = v[j];
+    }
+  }
+}
+
+// Fixed-order sum of per-tile partials (one block of 256 threads).
+__global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ partials,
+                                                  int ntiles, double *__restrict__ out) {
+  __shared__ double lds[4 * NRED];
+  double v[NRED] = {0, 0, 0, 0, 0, 0};
+  for (int t = threadIdx.x; t < ntiles; t += 256)
+#pragma unroll
+    for (int j = 0; j < NRED; ++j) v[j] += partials[(long long)t * 8 + j];
+  block_sum<NRED, 256>(v, lds);
+  if (threadIdx.x == 0)
+    for (int j = 0; j < NRED; ++j) out[j] = v[j];
+}
+
+} // namespace lks
+
+using namespace lks;
+
+struct lks_mhd {
+  Channel ch;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  Geom geom{};
+  void *buf[2] = {nullptr, nullptr};
+  double *rec = nullptr;
+  double *partials = nullptr;
+  double *result = nullptr;
+  int cur = 0;
+  int64_t steps = 0;
+  int shape = 0;
+  int red_tiles_x = 0, red_ntiles = 0, red_grid = 0;
+  Coef<double> kd{};
+  Coef<float> kf{};
+  int graph_steps = 0;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+};
+
+namespace {
+
+struct Layout {
+  long long plane;
+  size_t state_bytes, rec_bytes, part_bytes, total;
+  int red_tiles_x, red_ntiles;
+};
+
+Layout layout_of(const Channel &c) {
+  Layout L;
+  const int prec = c.p.precision;
+  L.plane = plane_elems(c.p.nx, c.p.ny, prec);
+  L.state_bytes = align256((size_t)19 * L.plane * elem_bytes(prec));
+  L.rec_bytes = align256((size_t)2 * c.p.nx * c.p.ny * sizeof(double));
+  const Shape s = kShapes[kRedShape];
+  L.red_tiles_x = (c.p.nx + s.bx - 1) / s.bx;
+  L.red_ntiles = L.red_tiles_x * ((c.p.ny + s.by - 1) / s.by);
+  L.part_bytes = align256((size_t)L.red_ntiles * 8 * sizeof(double));
+  L.total = 2 * L.state_bytes + L.rec_bytes + L.part_bytes + 256;
+  return L;
+}
+
+int grid_for(int ntiles, bool remap) { return remap ? (ntiles + 7) / 8 * 8 : ntiles; }
+
+template <typename C> const Coef<C> &coef_of(const lks_mhd *h);
+template <> const Coef<double> &coef_of<double>(const lks_mhd *h) { return h->kd; }
+template <> const Coef<float> &coef_of<float>(const lks_mhd *h) { return h->kf; }
+
+template <typename S, typename C, int BC, int MODE, int SH>
+hipError_t launch_shape(lks_mhd *h, const void *src, void *dst, ObsOut oo) {
+  constexpr Shape s = kShapes[SH];
+  const int tiles_x = (h->geom.nx + s.bx - 1) / s.bx;
+  const int ntiles = tiles_x * ((h->geom.ny + s.by - 1) / s.by);
+  const int grid = grid_for(ntiles, s.remap);
+  const Coef<C> &k = coef_of<C>(h);
+  hipLaunchKernelGGL((k_step<S, C, BC, MODE, s.bx, s.by, s.remap>), dim3(grid),
+                     dim3(s.bx, s.by), 0, h->stream, h->geom, k,
+                     static_cast<const S *>(src), static_cast<S *>(dst), tiles_x,
+                     ntiles, h->rec, h->partials, oo);
+  return hipGetLastError();
+}
+
+template <typename S, typename C, int BC, int MODE>
+hipError_t launch_bc(lks_mhd *h, int shape, const void *src, void *dst, ObsOut oo) {
+  switch (shape) {
+  case 0: return launch_shape<S, C, BC, MODE, 0>(h, src, dst, oo);
+  case 1: return launch_shape<S, C, BC, MODE, 1>(h, src, dst, oo);
+  case 2: return launch_shape<S, C, BC, MODE, 2>(h, src, dst, oo);
+  case 3: return launch_shape<S, C, BC, MODE, 3>(h, src, dst, oo);
+  default: return launch_shape<S, C, BC, MODE, 4>(h, src, dst, oo);
+  }
+}
+
+template <int MODE>
+hipError_t launch_mode(lks_mhd *h, int shape, const void *src, void *dst, ObsOut oo) {
+  const bool link = h->ch.p.bc == LKS_BC_LINK;
+  switch (h->ch.p.precision) {
+  case LKS_FP64:
+    return link ? launch_bc<double, double, BC_LINK, MODE>(h, shape, src, dst, oo)
+                : launch_bc<double, double, BC_MOMENT, MODE>(h, shape, src, dst, oo);
+  case LKS_FP32:
+    return link ? launch_bc<float, float, BC_LINK, MODE>(h, shape, src, dst, oo)
+                : launch_bc<float, float, BC_MOMENT, MODE>(h, shape, src, dst, oo);
+  default:
+    return link ? launch_bc<_Float16, float, BC_LINK, MODE>(h, shape, src, dst, oo)
+                : launch_bc<_Float16, float, BC_MOMENT, MODE>(h, shape, src, dst, oo);
+  }
+}
+
+// One step from buf[cur] into buf[cur^1].
+int one_step(lks_mhd *h, int mode) {
+  const void *src = h->buf[h->cur];
+  void *dst = h->buf[h->cur ^ 1];
+  ObsOut oo{};
+  hipError_t e;
+  switch (mode) {
+  case MODE_STEP: e = launch_mode<MODE_STEP>(h, h->shape, src, dst, oo); break;
+  case MODE_RECORD: e = launch_mode<MODE_RECORD>(h, kRedShape, src, dst, oo); break;
+  default: e = launch_mode<MODE_RESIDUAL>(h, kRedShape, src, dst, oo); break;
+  }
+  if (e != hipSuccess) {
+    set_error("step kernel launch failed: %s", hipGetErrorString(e));
+    return LKS_EDEVICE;
+  }
+  h->cur ^= 1;
+  h->steps += 1;
+  return LKS_OK;
+}
+
+int capture_graph(lks_mhd *h, int parity) {
+  hipGraph_t graph = nullptr;
+  const int saved_cur = h->cur;
+  const int64_t saved_steps = h->steps;
+  h->cur = parity;
+  LKS_HIP_CHECK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+  int rc = LKS_OK;
+  for (int i = 0; i < h->graph_steps && rc == LKS_OK; ++i) rc = one_step(h, MODE_STEP);
+  hipError_t e = hipStreamEndCapture(h->stream, &graph);
+  h->cur = saved_cur;
+  h->steps = saved_steps;
+  if (rc != LKS_OK) return rc;
+  if (e != hipSuccess) {
+    set_error("hipStreamEndCapture failed: %s", hipGetErrorString(e));
+    return LKS_EDEVICE;
+  }
+  e = hipGraphInstantiate(&h->gexec[parity], graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    set_error("hipGraphInstantiate failed: %s", hipGetErrorString(e));
+    return LKS_EDEVICE;
+  }
+  return LKS_OK;
+}
+
+void drop_graphs(lks_mhd *h) {
+  for (auto &g : h->gexec)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+}
+
+template <typename F>
+int with_device(lks_mhd *h, F &&fn) {
+  int prev = 0;
+  if (hipGetDevice(&prev) != hipSuccess) prev = h->device;
+  if (prev != h->device) LKS_HIP_CHECK(hipSetDevice(h->device));
+  const int rc = fn();
+  if (prev != h->device) (void)hipSetDevice(prev);
+  return rc;
+}
+
+int elementwise_grid(const lks_mhd *h) {
+  const long long n = (long long)h->geom.nx * h->geom.ny;
+  return (int)((n + 255) / 256);
+}
+
+} // namespace
+
+extern "C" {
+
+size_t lks_mhd_state_bytes(const lks_mhd_params *p) {
+  clear_error();
+  Channel c;
+  if (derive_channel(p, &c) != LKS_OK) return 0;
+  return layout_of(c).total;
+}
+
+int lks_mhd_create(const lks_mhd_params *p, void *dev_buf, size_t bytes,
+                   void *hip_stream, lks_mhd_t **out) {
+  clear_error();
+  if (!out) {
+    set_error("out must not be NULL");
+    return LKS_EINVAL;
+  }
+  *out = nullptr;
+  Channel c;
+  int rc = derive_channel(p, &c);
+  if (rc != LKS_OK) return rc;
+  const Layout L = layout_of(c);
+  if (!dev_buf || (reinterpret_cast<uintptr_t>(dev_buf) & 255u)) {
+    set_error("dev_buf must be a non-NULL 256-byte aligned device pointer");
+    return LKS_EINVAL;
+  }
+  if (bytes < L.total) {
+    set_error("dev_buf holds %zu bytes, %zu needed", bytes, L.total);
+    return LKS_ENOMEM;
+  }
+  lks_mhd *h = new (std::nothrow) lks_mhd();
+  if (!h) {
+    set_error("host allocation failed");
+    return LKS_ENOMEM;
+  }
+  h->ch = c;
+  if (hipGetDevice(&h->device) != hipSuccess) h->device = 0;
+  h->stream = static_cast<hipStream_t>(hip_stream);
+  h->geom = Geom{c.p.nx, c.p.ny, c.p.nx, L.plane};
+  char *base = static_cast<char *>(dev_buf);
+  h->buf[0] = base;
+  h->buf[1] = base + L.state_bytes;
+  h->rec = reinterpret_cast<double *>(base + 2 * L.state_bytes);
+  h->partials = reinterpret_cast<double *>(base + 2 * L.state_bytes + L.rec_bytes);
+  h->result = reinterpret_cast<double *>(base + 2 * L.state_bytes + L.rec_bytes + L.part_bytes);
+  h->red_tiles_x = L.red_tiles_x;
+  h->red_ntiles = L.red_ntiles;
+  h->kd = make_coef<double>(c);
+  h->kf = make_coef<float>(c);
+  h->shape = 0;
+  rc = with_device(h, [&]() -> int {
+    const int grid = elementwise_grid(h);
+    switch (c.p.precision) {
+    case LKS_FP64:
+      hipLaunchKernelGGL(k_init<double>, dim3(grid), dim3(256), 0, h->stream, h->geom, c.p.rho0, c.d.b0, (double *)h->buf[0]);
+      break;
+    case LKS_FP32:
+      hipLaunchKernelGGL(k_init<float>, dim3(grid), dim3(256), 0, h->stream, h->geom, c.p.rho0, c.d.b0, (float *)h->buf[0]);
+      break;
+    default:
+      hipLaunchKernelGGL(k_init<_Float16>, dim3(grid), dim3(256), 0, h->stream, h->geom, c.p.rho0, c.d.b0, (_Float16 *)h->buf[0]);
+    }
+    LKS_HIP_CHECK(hipGetLastError());
+    return LKS_OK;
+  });
+  if (rc != LKS_OK) {
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return LKS_OK;
+}
+
+int lks_mhd_destroy(lks_mhd_t *h) {
+  clear_error();
+  if (!h) return LKS_OK;
+  drop_graphs(h);
+  delete h;
+  return LKS_OK;
+}
+
+int lks_mhd_set_launch_shape(lks_mhd_t *h, int32_t shape) {
+  clear_error();
+  if (!h || shape < 0 || shape >= kNumShapes) {
+    set_error("shape must be in [0, %d)", kNumShapes);
+    return LKS_EINVAL;
+  }
+  if (h->shape != shape) drop_graphs(h);
+  h->shape = shape;
+  return LKS_OK;
+}
+
+int lks_mhd_set_graph(lks_mhd_t *h, int32_t steps_per_graph) {
+  clear_error();
+  if (!h || steps_per_graph < 0 || (steps_per_graph % 2) != 0) {
+    set_error("steps_per_graph must be an even number >= 0");
+    return LKS_EINVAL;
+  }
+  if (steps_per_graph != 0 && h->stream == nullptr) {
+    set_error("graph capture needs a non-default stream");
+    return LKS_EINVAL;
+  }
+  drop_graphs(h);
+  h->graph_steps = steps_per_graph;
+  return LKS_OK;
+}
+
+int64_t lks_mhd_steps_done(const lks_mhd_t *h) { return h ? h->steps : -1; }
+
+int lks_mhd_step(lks_mhd_t *h, int64_t nsteps) {
+  clear_error();
+  if (!h || nsteps < 0) {
+    set_error("invalid handle or negative step count");
+    return LKS_EINVAL;
+  }
+  return with_device(h, [&]() -> int {
+    int64_t n = nsteps;
+    while (n > 0) {
+      if (h->graph_steps >= 2 && n >= h->graph_steps) {
+        if (!h->gexec[h->cur]) {
+          const int rc = capture_graph(h, h->cur);
+          if (rc != LKS_OK) return rc;
+        }
+        LKS_HIP_CHECK(hipGraphLaunch(h->gexec[h->cur], h->stream));
+        h->steps += h->graph_steps;
+        n -= h->graph_steps;
+      } else {
+        const int rc = one_step(h, MODE_STEP);
+        if (rc != LKS_OK) return rc;
+        n -= 1;
+      }
+    }
+    return LKS_OK;
+  });
+}
+
+int lks_mhd_run_to_steady(lks_mhd_t *h, double tol, int64_t check_every,
+                          int64_t max_steps, int64_t *steps_done,
+                          double *residual, double *flow_rate) {
+  clear_error();
+  if (!h || check_every < 2 || max_steps < 0 || !(tol >= 0.0)) {
+    set_error("invalid handle, check_every < 2, max_steps < 0 or tol < 0");
+    return LKS_EINVAL;
+  }
+  double res = NAN, q = NAN;
+  int status = LKS_ENOTCONV;
+  const int rc = with_device(h, [&]() -> int {
+    int64_t done = 0;
+    while (done + check_every <= max_steps) {
+      int rc2 = lks_mhd_step(h, check_every - 2);
+      if (rc2 != LKS_OK) return rc2;
+      if ((rc2 = one_step(h, MODE_RECORD)) != LKS_OK) return rc2;
+      if ((rc2 = one_step(h, MODE_RESIDUAL)) != LKS_OK) return rc2;
+      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, h->stream, h->partials, h->red_ntiles, h->result);
+      LKS_HIP_CHECK(hipGetLastError());
+      double sums[NRED];
+      LKS_HIP_CHECK(hipMemcpyAsync(sums, h->result, sizeof sums, hipMemcpyDeviceToHost, h->stream));
+      LKS_HIP_CHECK(hipStreamSynchronize(h->stream));
+      done += check_every;
+      const double ru = std::sqrt(sums[0]) / std::fmax(std::sqrt(sums[1]), 1e-300);
+      const double rb = std::sqrt(sums[2]) / std::fmax(std::sqrt(sums[3]), 1e-300);
+      res = std::fmax(ru, rb);
+      q = sums[4] / h->geom.nx;
+      if (sums[5] != 0.0 || !std::isfinite(res)) {
+        status = LKS_EUNSTABLE;
+        set_error("non-finite or non-positive density/velocity/field after %lld steps",
+                  (long long)h->steps);
+        return LKS_OK;
+      }
+      if (res < tol) {
+        status = LKS_OK;
+        return LKS_OK;
+      }
+    }
+    status = LKS_ENOTCONV;
+    set_error("residual %.3e above tolerance %.3e after %lld steps", res, tol, (long long)h->steps);
+    return LKS_OK;
+  });
+  if (steps_done) *steps_done = h->steps;
+  if (residual) *residual = res;
+  if (flow_rate) *flow_rate = q;
+  return rc != LKS_OK ? rc : status;
+}
+
+int lks_mhd_moments(lks_mhd_t *h, double *rho, double *ux, double *uy,
+                    double *bx, double *by, double *jz) {
+  clear_error();
+  if (!h) {
+    set_error("invalid handle");
+    return LKS_EINVAL;
+  }
+  return with_device(h, [&]() -> int {
+    ObsOut oo{rho, ux, uy, bx, by, jz};
+    hipError_t e = launch_mode<MODE_MOMENTS>(h, kRedShape, h->buf[h->cur], nullptr, oo);
+    if (e != hipSuccess) {
+      set_error("moments kernel launch failed: %s", hipGetErrorString(e));
+      return LKS_EDEVICE;
+    }
+    return LKS_OK;
+  });
+}
+
+int lks_mhd_save_state(lks_mhd_t *h, double *dev_pops) {
+  clear_error();
+  if (!h || !dev_pops) {
+    set_error("invalid handle or NULL destination");
+    return LKS_EINVAL;
+  }
+  return with_device(h, [&]() -> int {
+    const int grid = elementwise_grid(h);
+    switch (h->ch.p.precision) {
+    case LKS_FP64: hipLaunchKernelGGL(k_save<double>, dim3(grid), dim3(256), 0, h->stream, h->geom, (const double *)h->buf[h->cur], dev_pops); break;
+    case LKS_FP32: hipLaunchKernelGGL(k_save<float>, dim3(grid), dim3(256), 0, h->stream, h->geom, (const float *)h->buf[h->cur], dev_pops); break;
+    default: hipLaunchKernelGGL(k_save<_Float16>, dim3(grid), dim3(256), 0, h->stream, h->geom, (const _Float16 *)h->buf[h->cur], dev_pops);
+    }
+    LKS_HIP_CHECK(hipGetLastError());
+    return LKS_OK;
+  });
+}
+
+int lks_mhd_load_state(lks_mhd_t *h, const double *dev_pops, int64_t steps) {
+  clear_error();
+  if (!h || !dev_pops || steps < 0) {
+    set_error("invalid handle, NULL source or negative step count");
+    return LKS_EINVAL;
+  }
+  return with_device(h, [&]() -> int {
+    const int grid = elementwise_grid(h);
+    switch (h->ch.p.precision) {
+    case LKS_FP64: hipLaunchKernelGGL(k_load<double>, dim3(grid), dim3(256), 0, h->stream, h->geom, dev_pops, (double *)h->buf[h->cur]); break;
+    case LKS_FP32: hipLaunchKernelGGL(k_load<float>, dim3(grid), dim3(256), 0, h->stream, h->geom, dev_pops, (float *)h->buf[h->cur]); break;
+    default: hipLaunchKernelGGL(k_load<_Float16>, dim3(grid), dim3(256), 0, h->stream, h->geom, dev_pops, (_Float16 *)h->buf[h->cur]);
+    }
+    LKS_HIP_CHECK(hipGetLastError());
+    h->steps = steps;
+    return LKS_OK;
+  });
+}
+
+} // extern "C"

@@ -1,0 +1,55 @@
+"""Shared helpers for the GPU parity tests (oracle on the CPU, HIP path
+through the C ABI).  Both sides get the same raw lattice inputs."""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+import oracle
+from oracle import Params
+
+
+def lib_kwargs(p: Params, precision: str) -> dict:
+    """make_params keywords giving the library exactly the oracle's inputs."""
+    return dict(bc="link" if p.bc == oracle.LINK else "moment", precision=precision,
+                tau_f=p.tau_f, tau_m=p.tau_m, b0=p.b0, fx=p.fx, fy=p.fy,
+                c_lower=p.c_lo, c_upper=p.c_hi, u_lower=p.u_lo, u_upper=p.u_hi)
+
+
+def rel_l2(a, b) -> float:
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def field_errors(gpu: dict, orc: dict, b0: float) -> dict:
+    """Relative L2 errors of the observables: u_x, B_x, B_y and J_z against
+    their own norms; u_y against ||u_x||; rho against its dynamic scale
+    max(||u_x||, ||rho - 1||) (rho itself is ~1 and would hide errors)."""
+    nu = max(np.linalg.norm(orc["ux"]), 1e-300)
+    nr = max(nu, np.linalg.norm(orc["rho"] - 1.0))
+    return {
+        "ux": rel_l2(gpu["ux"], orc["ux"]),
+        "bx": rel_l2(gpu["bx"], orc["bx"]),
+        "uy": float(np.linalg.norm(gpu["uy"] - orc["uy"]) / nu),
+        "by": rel_l2(gpu["by"], orc["by"]),
+        "rho": float(np.linalg.norm(gpu["rho"] - orc["rho"]) / nr),
+        "jz": rel_l2(gpu["jz"], orc["jz"]) if np.linalg.norm(orc["jz"]) > 1e-30 else 0.0,
+    }
+
+
+def to_numpy(d: dict) -> dict:
+    return {k: v.detach().cpu().numpy() for k, v in d.items()}
+
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5, "fp16": 2e-3}
+
+
+def assert_close(errs: dict, tol: float, keys=("ux", "bx", "uy", "by", "rho")):
+    bad = {k: v for k, v in errs.items() if k in keys and not (v <= tol)}
+    assert not bad, f"errors above {tol:g}: {bad} (all: {errs})"
+
+
+def isinf(c):
+    return math.isinf(c)

@@ -1,0 +1,133 @@
+"""The C-ABI library loads on a machine without a GPU, exports every entry
+point include/lks_mhd.h declares, and its host-only paths (validation,
+derivation, sizing, argument checks) behave as documented.  No compute call
+is made here."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+import oracle
+from oracle import derive as od
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lks_mhd.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2112_13930_amd import _lib
+    return _lib
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lks_mhd_\w+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = declared_functions()
+    assert len(names) >= 30
+    lib = L.lib()
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    # and the binding knows every one of them
+    assert set(names) <= set(L.SIGNATURES), set(names) - set(L.SIGNATURES)
+
+
+def test_abi_version(L):
+    assert L.lib().lks_mhd_abi_version() == 1
+
+
+def _v(L, **kw):
+    nx = kw.pop("nx", 16)
+    ny = kw.pop("ny", 16)
+    p = L.make_params(nx, ny, **kw)
+    return L.lib().lks_mhd_validate(ctypes.byref(p)), p
+
+
+@pytest.mark.parametrize("kw", [
+    dict(tau_f=0.5), dict(tau_m=0.49), dict(tau_f=float("nan")),
+    dict(c_lower=-0.1), dict(c_upper=float("nan")),
+    dict(ny=1), dict(ny=2, bc="moment"), dict(nx=0),
+    dict(nx=20000, ny=20000),
+    dict(ha=10.0, b0=0.5),                       # inconsistent
+    dict(u_max=0.05, c_lower=0.1, c_upper=0.2),  # fx from u_max needs equal walls
+    dict(u_upper=float("inf")), dict(rho0=0.0), dict(precision=7), dict(bc=5),
+])
+def test_validate_rejects(L, kw):
+    rc, p = _v(L, **kw)
+    assert rc == L.LKS_EINVAL
+    assert L.last_error()
+    assert L.lib().lks_mhd_state_bytes(ctypes.byref(p)) == 0
+
+
+@pytest.mark.parametrize("kw", [
+    dict(), dict(ny=2), dict(ny=3, bc="moment"), dict(c_lower=math.inf, c_upper=0.0),
+    dict(ha=10.0, u_max=0.05, c_lower=0.1), dict(ha=0.0, u_max=0.05),
+    dict(ha=5.0, c_lower=math.inf, u_max=0.01, bc="moment"),
+    dict(precision="fp64"), dict(precision="fp16"),
+])
+def test_validate_accepts(L, kw):
+    rc, p = _v(L, **kw)
+    assert rc == L.LKS_OK, L.last_error()
+    assert L.lib().lks_mhd_state_bytes(ctypes.byref(p)) > 0
+
+
+@pytest.mark.parametrize("bc", [oracle.LINK, oracle.MOMENT])
+@pytest.mark.parametrize("ha,c", [(10.0, 0.1), (20.0, 0.0), (5.0, math.inf), (0.0, 1.0)])
+def test_derivation_agrees_with_oracle(L, bc, ha, c):
+    """The library's host derivation is written separately from the oracle's;
+    both follow Secs. IV, V, VI and VIII."""
+    ny = 64
+    q = od.hartmann_params(8, ny, bc, 0.8, 0.9, ha, c, 0.05)
+    p = L.make_params(8, ny, bc="link" if bc == oracle.LINK else "moment", tau_f=0.8,
+                      tau_m=0.9, ha=ha, u_max=0.05, c_lower=c, c_upper=c)
+    d = L.derive(p)
+    assert d.a == q.a
+    assert math.isclose(d.b0, q.b0, rel_tol=1e-14, abs_tol=1e-300)
+    assert math.isclose(d.fx, q.fx, rel_tol=1e-13)
+    assert math.isclose(d.nu, od.nu_of(0.8), rel_tol=1e-15)
+    assert math.isclose(d.eta, od.eta_of(0.9), rel_tol=1e-15)
+    theta = math.inf if math.isinf(c) else c * q.a / (0.9 - 0.5)
+    assert d.theta_lower == pytest.approx(theta, rel=1e-15)
+
+
+def test_bytes_per_node(L):
+    f = L.lib().lks_mhd_bytes_per_node
+    assert (f(0), f(1), f(2), f(9)) == (304, 152, 76, 0)
+
+
+def test_state_bytes_cover_two_buffers(L):
+    for prec, b in (("fp64", 8), ("fp32", 4), ("fp16", 2)):
+        p = L.make_params(4096, 4096, precision=prec)
+        assert L.lib().lks_mhd_state_bytes(ctypes.byref(p)) >= 2 * 19 * 4096 * 4096 * b
+
+
+def test_create_argument_checks_need_no_device(L):
+    p = L.make_params(16, 16)
+    h = ctypes.c_void_p()
+    lib = L.lib()
+    assert lib.lks_mhd_create(ctypes.byref(p), None, 1 << 20, None, ctypes.byref(h)) == L.LKS_EINVAL
+    assert lib.lks_mhd_create(ctypes.byref(p), ctypes.c_void_p(256 + 8), 1 << 20, None,
+                              ctypes.byref(h)) == L.LKS_EINVAL
+    assert lib.lks_mhd_create(ctypes.byref(p), ctypes.c_void_p(4096), 16, None,
+                              ctypes.byref(h)) == L.LKS_ENOMEM
+    assert not h.value
+    assert lib.lks_mhd_destroy(None) == L.LKS_OK
+
+
+def test_batch_sizing(L):
+    lib = L.lib()
+    assert lib.lks_mhd_batch_overhead_bytes(256, 1 << 24) > 0
+    assert lib.lks_mhd_batch_overhead_bytes(0, 1 << 24) == 0
+    p = L.make_params(100, 50)
+    assert lib.lks_mhd_batch_channel_bytes(ctypes.byref(p), 1) >= 2 * 19 * 100 * 50 * 4
+    h = ctypes.c_void_p()
+    assert lib.lks_mhd_batch_create(1, 0, 100, ctypes.c_void_p(4096), 1 << 20, None,
+                                    ctypes.byref(h)) == L.LKS_EINVAL
+    assert lib.lks_mhd_batch_create(1, 4, 1000, ctypes.c_void_p(4096), 64, None,
+                                    ctypes.byref(h)) == L.LKS_ENOMEM
