@@ -1,0 +1,415 @@
+#!/usr/bin/env python3
+"""Benchmark of the fused lattice-kinetic MHD step on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--quick]
+
+A step is one fused FP32 time step (pull stream, Shercliff wall closure,
+moments, coupled u/J solve, collide, store) of the shear-driven
+Hartmann-Couette channel on a 4096 x 4096 grid: upper wall moving at 0.05,
+Ha = 50, wall conductance ratio 1 on both walls, link-based closures,
+tau_f = 0.7, tau_m = 0.9.  Inputs are synthetic (the channel starts at rest)
+and resident in HBM before the timed region.  The K timed steps are bracketed
+by device synchronisation; the value is nodes x K / wall time in MLUPS.
+
+Printed as one JSON line with, besides the contract fields:
+  roofline      algorithmic HBM bytes of the step kernel (152 B per node in
+                FP32) over its average duration from HIP events on the stream
+                it runs on, against 8 TB/s; traffic from the committed
+                rocprofv3 counter summary when the kernel source is unchanged.
+  cpu_baseline  the FP64 CPU oracle timed on the host cores over a bounded
+                sample of the same grid.
+  extras        the 30-case sweep (Ha x c x closure), FP16-storage and FP64
+                rates, the batched launch over 256 uneven channels against
+                sequential single-channel launches, and the continuous-
+                batching solve service against sequential solves.
+
+Profiling helpers (used to write profiles/*):
+  --profile-run     only warm-up + timed steps of the headline, plus a copy of
+                    known size for counter scaling (for rocprofv3 runs)
+  --summarize DIR   turn rocprofv3 outputs into profiles/ summaries
+"""
+from __future__ import annotations
+
+import argparse
+import glob
+import hashlib
+import json
+import math
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MHD MLUPS + % HBM roofline; batched solves/s and p99 latency vs plain"
+PEAK_HBM_GBS = 8000.0
+HEADLINE = dict(nx=4096, ny=4096, bc="link", precision="fp32", tau_f=0.7, tau_m=0.9,
+                ha=50.0, c_lower=1.0, c_upper=1.0, u_upper=0.05)
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+TRAFFIC_FILE = os.path.join(PROFILE_DIR, "fp32_step_4096_traffic.json")
+COPY_REF_BYTES = 1 << 30
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("lks_node.hpp", "lks_single.hip"):
+        with open(os.path.join(ROOT, "paper_2112_13930_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# GPU legs
+# ---------------------------------------------------------------------------
+
+def time_channel(torch, Channel, kw, steps, warmup, shape=None):
+    """(wall seconds for `steps`, event seconds per step, channel)."""
+    ch = Channel(**kw)
+    if shape is not None:
+        ch.set_launch_shape(shape)
+    ch.step(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(ch.stream)
+    ch.step(steps)
+    e1.record(ch.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, e0.elapsed_time(e1) / 1e3 / steps, ch
+
+
+def headline(torch, args):
+    from paper_2112_13930_amd.channel import Channel
+    wall, per_step, ch = time_channel(torch, Channel, HEADLINE, args.steps, args.warmup)
+    nodes = HEADLINE["nx"] * HEADLINE["ny"]
+    m = ch.moments()
+    torch.cuda.synchronize()
+    finite = bool(torch.isfinite(m["ux"]).all().item())
+    umax = float(m["ux"].abs().max().item())
+    ch.close()
+    return {"wall": wall, "per_step": per_step, "nodes": nodes, "finite": finite, "umax": umax}
+
+
+def sweep(torch, steps=100, warmup=10):
+    """Config sweep: Ha in {10, 50, 100} x c in {0, 1e-2, 1, 1e2, inf} x link/moment."""
+    from paper_2112_13930_amd.channel import Channel
+    rows = []
+    for bc in ("link", "moment"):
+        for ha in (10.0, 50.0, 100.0):
+            for c in (0.0, 1e-2, 1.0, 1e2, math.inf):
+                kw = dict(HEADLINE, bc=bc, ha=ha, c_lower=c, c_upper=c)
+                _, per_step, ch = time_channel(torch, Channel, kw, steps, warmup)
+                ch.close()
+                rows.append({"bc": bc, "ha": ha, "c": "inf" if math.isinf(c) else c,
+                             "mlups": round(4096 * 4096 / per_step / 1e6, 1)})
+    vals = [r["mlups"] for r in rows]
+    return {"steps_each": steps, "cases": len(rows), "mlups_min": min(vals),
+            "mlups_median": statistics.median(vals), "mlups_max": max(vals), "rows": rows}
+
+
+def other_precisions(torch, steps=200, warmup=20):
+    from paper_2112_13930_amd.channel import Channel
+    out = {}
+    for prec, bpn in (("fp16", 76), ("fp64", 304)):
+        _, per_step, ch = time_channel(torch, Channel, dict(HEADLINE, precision=prec), steps, warmup)
+        ch.close()
+        gbs = bpn * 4096 * 4096 / per_step / 1e9
+        out[prec] = {"mlups": round(4096 * 4096 / per_step / 1e6, 1), "gbs": round(gbs, 1),
+                     "frac_hbm": round(gbs / PEAK_HBM_GBS, 3), "bytes_per_node": bpn}
+    return out
+
+
+def stable_mix(n, seed):
+    """Config-4 channel draws, rejecting draws whose imposed field exceeds
+    0.1 (Alfven speed near the lattice limit; equivalently a Hartmann layer
+    thinner than one node at tau = 0.8).  Returns (draws, rejected)."""
+    from paper_2112_13930_amd._lib import derive, make_params
+    from paper_2112_13930_amd.workloads import channel_mix
+    draws, rejected, k = [], 0, 0
+    while len(draws) < n:
+        for d in channel_mix(n, seed + 7919 * k):
+            if len(draws) == n:
+                break
+            p = make_params(d.nx, d.ny, precision="fp32", **d.kwargs())
+            if derive(p).b0 > 0.1:
+                rejected += 1
+                continue
+            draws.append(d)
+        k += 1
+    return draws, rejected
+
+
+def batched(torch, steps=1000, warmup=20, seed=2024):
+    from paper_2112_13930_amd._lib import make_params
+    from paper_2112_13930_amd.batch import Batch
+    from paper_2112_13930_amd.channel import Channel
+    draws, rejected = stable_mix(256, seed)
+    nodes = sum(d.nx * d.ny for d in draws)
+    b = Batch("fp32", max_channels=256, max_nodes=nodes + 1024)
+    for d in draws:
+        b.admit(make_params(d.nx, d.ny, precision="fp32", **d.kwargs()))
+    tiles = b.autotune(trial_steps=20)
+    b.step(warmup, graph=True)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(b.stream)
+    b.step(steps, graph=True)
+    e1.record(b.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per_step = e0.elapsed_time(e1) / 1e3 / steps
+    b.close()
+    # baseline: the same channels advanced one after another by the plain
+    # single-channel path (each its own launches), same step count
+    seq_steps = max(10, steps // 10)
+    chans = [Channel(d.nx, d.ny, precision="fp32", stream=torch.cuda.current_stream(), **d.kwargs())
+             for d in draws]
+    for c in chans:
+        c.step(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c in chans:
+        c.step(seq_steps)
+    torch.cuda.synchronize()
+    seq_wall = (time.perf_counter() - t0) / seq_steps
+    for c in chans:
+        c.close()
+    gbs = 152 * nodes / per_step / 1e9
+    return {"channels": len(draws), "rejected_draws": rejected, "nodes": nodes,
+            "steps": steps, "ms_per_step": round(per_step * 1e3, 4),
+            "mlups": round(nodes / per_step / 1e6, 1), "wall_mlups": round(nodes * steps / wall / 1e6, 1),
+            "gbs": round(gbs, 1), "frac_hbm": round(gbs / PEAK_HBM_GBS, 3),
+            "sequential_ms_per_step": round(seq_wall * 1e3, 3),
+            "sequential_mlups": round(nodes / seq_wall / 1e6, 1),
+            "speedup_vs_sequential": round(seq_wall / per_step, 2),
+            "tiles": tiles}
+
+
+def serving(torch, n_requests=48, rate=200.0, seed=5):
+    from paper_2112_13930_amd.serve import serve_benchmark
+    return serve_benchmark(n_requests=n_requests, rate=rate, seed=seed, log=log)
+
+
+def profile_run(torch, args):
+    """Headline steps only, plus a device copy of known size (counter scale)."""
+    from paper_2112_13930_amd.channel import Channel
+    a = torch.empty(COPY_REF_BYTES // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    _, per_step, ch = time_channel(torch, Channel, HEADLINE, args.steps, args.warmup)
+    ch.close()
+    print(json.dumps({"profile_run": True, "steps": args.steps, "per_step_ms": per_step * 1e3}))
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the oracle on a bounded sample of the same grid
+# ---------------------------------------------------------------------------
+
+def cpu_baseline(target_s=15.0):
+    import numpy as np
+
+    import oracle
+    from oracle import Params
+    oracle.build()
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, 16))
+    nx = ny = 4096
+    p = Params(nx=nx, ny=ny, bc=oracle.LINK, tau_f=0.7, tau_m=0.9, c_lo=1.0, c_hi=1.0,
+               u_hi=0.05, b0=0.0)
+    from oracle import derive as od
+    p.b0 = od.b0_of(50.0, 0.7, 0.9, p.half_width())
+    s = oracle.init_state(p)
+    scratch = np.empty_like(s)
+    t0 = time.perf_counter()
+    oracle.run(p, s, 1, nthreads=cores, scratch=scratch)
+    one = time.perf_counter() - t0
+    n_more = max(0, int(target_s / max(one, 1e-3)) - 1)
+    t0 = time.perf_counter()
+    oracle.run(p, s, n_more, nthreads=cores, scratch=scratch)
+    dt = time.perf_counter() - t0
+    steps = n_more + 1
+    total = one + dt
+    return {"value": round(nx * ny * steps / total / 1e6, 3), "unit": "MLUPS", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{nx}x{ny} grid, {steps} FP64 steps of the same channel from rest "
+                      f"({total:.1f} s, OpenMP over rows)"}
+
+
+# ---------------------------------------------------------------------------
+# rocprofv3 summaries
+# ---------------------------------------------------------------------------
+
+def _read_csv(path):
+    import csv
+    with open(path) as fh:
+        return list(csv.DictReader(fh))
+
+
+def summarize(dirs):
+    """Write profiles/ summaries from rocprofv3 output directories:
+    kernel stats (--kernel-trace --stats) and counter runs (--pmc)."""
+    out = {"source_hash": kernel_source_hash()}
+    lines = []
+    for d in dirs:
+        for f in sorted(glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)):
+            rows = _read_csv(f)
+            for r in rows:
+                name = r.get("Name", "")
+                if "k_step" in name or "copy" in name.lower() or "elementwise" in name.lower():
+                    lines.append((name[:140], r.get("Calls"), r.get("AverageNs"), r.get("Percentage")))
+                    if "k_step" in name and "MODE" not in name:
+                        out.setdefault("step_avg_ns", float(r["AverageNs"]))
+                        out.setdefault("step_calls", int(r["Calls"]))
+        for f in sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)):
+            rows = _read_csv(f)
+            acc = {}
+            for r in rows:
+                name = r.get("Kernel_Name", r.get("Kernel-Name", ""))
+                cn = r.get("Counter_Name", r.get("Counter-Name", ""))
+                val = float(r.get("Counter_Value", r.get("Counter-Value", "nan")))
+                key = ("step" if "k_step" in name else "copy" if ("copy" in name.lower() or "elementwise" in name.lower()) else None)
+                if key is None:
+                    continue
+                acc.setdefault((key, cn), []).append(val)
+            for (key, cn), vals in acc.items():
+                out[f"{key}_{cn}_kib_per_dispatch"] = statistics.median(vals)
+    return out, lines
+
+
+def write_summary(dirs, command):
+    out, lines = summarize(dirs)
+    fetch_s = out.get("step_FETCH_SIZE_kib_per_dispatch")
+    write_s = out.get("step_WRITE_SIZE_kib_per_dispatch")
+    fetch_c = out.get("copy_FETCH_SIZE_kib_per_dispatch")
+    write_c = out.get("copy_WRITE_SIZE_kib_per_dispatch")
+    if fetch_c and write_c:
+        # a copy of COPY_REF_BYTES reads and writes that many bytes
+        out["fetch_scale"] = fetch_c * 1024 / COPY_REF_BYTES
+        out["write_scale"] = write_c * 1024 / COPY_REF_BYTES
+    if fetch_s and write_s and "fetch_scale" in out:
+        out["step_hbm_bytes_per_dispatch"] = (fetch_s * 1024 / out["fetch_scale"] +
+                                              write_s * 1024 / out["write_scale"])
+        out["algorithmic_bytes_per_dispatch"] = 152 * 4096 * 4096
+    out["command"] = command
+    os.makedirs(PROFILE_DIR, exist_ok=True)
+    if fetch_s or write_s:
+        with open(TRAFFIC_FILE, "w") as fh:
+            json.dump(out, fh, indent=1)
+    return out, lines
+
+
+# ---------------------------------------------------------------------------
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--quick", action="store_true", help="headline only, no extras")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--profile-run", action="store_true")
+    ap.add_argument("--summarize", nargs="*")
+    ap.add_argument("--command", default="")
+    args = ap.parse_args()
+
+    if args.summarize:
+        out, lines = write_summary(args.summarize, args.command)
+        print(json.dumps(out, indent=1))
+        for ln in lines:
+            print(ln)
+        return 0
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the channel path does not "
+              "shard across GPUs in this build.", file=sys.stderr)
+        return 2
+    if os.environ.get("WORLD_SIZE", "1") not in ("", "1"):
+        print("bench.py runs as a single process on one GPU", file=sys.stderr)
+        return 2
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    from paper_2112_13930_amd import lib
+    lib()  # fails loudly if the HIP library is not built
+
+    if args.profile_run:
+        profile_run(torch, args)
+        return 0
+
+    h = headline(torch, args)
+    nodes, K = h["nodes"], args.steps
+    value = nodes * K / h["wall"] / 1e6
+    achieved = 152 * nodes / h["per_step"] / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        tr = json.load(open(TRAFFIC_FILE))
+        if tr.get("source_hash") == kernel_source_hash() and tr.get("step_hbm_bytes_per_dispatch"):
+            traffic = tr["step_hbm_bytes_per_dispatch"]
+    line = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(h["wall"] / K * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (channel started at rest, resident in HBM)",
+        "config": {"workload": "hartmann-couette 4096x4096, link-based Shercliff walls, "
+                               "Ha=50, c_w=1 both walls, upper wall U=0.05, tau_f=0.7, tau_m=0.9, "
+                               "populations stored as binary32 (152 B/node), arithmetic in FP64 "
+                               "with stochastic rounding to storage",
+                   "nx": 4096, "ny": 4096, "precision": "fp32", "bc": "link", "ha": 50.0,
+                   "c_wall": 1.0, "u_wall": 0.05, "parallelism": "single-gpu"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": traffic,
+                     "kernel": "k_step<float,float,link,step,256,1>",
+                     "algorithmic_bytes_per_launch": 152 * nodes,
+                     "avg_launch_ms": round(h["per_step"] * 1e3, 4)},
+        "finite": h["finite"],
+    }
+    if not args.quick:
+        extras = {}
+        log("sweep ...")
+        extras["config_sweep_fp32"] = sweep(torch)
+        log("precisions ...")
+        extras["precisions"] = other_precisions(torch)
+        log("batched ...")
+        extras["batched_256_channels"] = batched(torch)
+        if not args.no_serve:
+            log("serving ...")
+            try:
+                extras["serving"] = serving(torch)
+            except Exception as e:  # report, do not hide the headline
+                extras["serving"] = {"error": repr(e)}
+        line["extras"] = extras
+    if not args.no_cpu:
+        log("cpu baseline ...")
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

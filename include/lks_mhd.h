@@ -48,12 +48,19 @@ typedef struct lks_mhd_batch lks_mhd_batch_t; /* many channels, library-owned */
 
 enum lks_bc { LKS_BC_LINK = 0, LKS_BC_MOMENT = 1 };
 
-/* Storage precision of the populations.  FP64: stored and computed in FP64.
- * FP32: stored and computed in FP32.  FP16_STORE: stored as IEEE binary16
- * (round to nearest even) and computed in FP32.  In every mode the flow
- * populations are stored as deviations f_alpha - w_alpha from the rest
- * equilibrium at unit density; the magnetic populations are stored as
- * values.  Steady-state reductions are FP64 in every mode. */
+/* Storage precision of the populations.
+ *   FP64        stored as binary64, computed in FP64, rounded to nearest.
+ *   FP32        stored as binary32 and computed in FP64; each stored value is
+ *               rounded stochastically to one of its two binary32 neighbours.
+ *   FP16_STORE  stored as binary16 and computed in FP32, rounded
+ *               stochastically to binary16.
+ * Every population is stored as its deviation from the rest state at unit
+ * density with B = (0, B0): f_alpha - w_alpha, g_alpha,x and
+ * g_alpha,y - W_alpha B0.  The random bits of stochastic rounding are a
+ * counter-based hash of (step since create or load, node, plane): a run is
+ * reproducible bit for bit and does not depend on launch shape or on the
+ * other channels of a batch.  Steady-state reductions are FP64 in every
+ * mode. */
 enum lks_precision { LKS_FP64 = 0, LKS_FP32 = 1, LKS_FP16_STORE = 2 };
 
 enum lks_status {
@@ -170,11 +177,15 @@ int lks_mhd_set_launch_shape(lks_mhd_t *h, int32_t shape);
 int64_t lks_mhd_steps_done(const lks_mhd_t *h);
 
 /*
- * Advance until the steady-state residual falls below tol.  Every
- * check_every (>= 2) steps the residual
- *   R = max over phi in {u_x, B_x} of ||phi(n) - phi(n-1)||_2 / ||phi(n)||_2
- * is reduced in FP64 (fixed order, deterministic), where phi(n) is the field
- * the step after n collides with and n = steps_done - 1.  Stops at R < tol
+ * Advance until the steady-state residual falls below tol.  Steps go in
+ * windows of K = check_every (>= 2) steps; the first step of a window
+ * records phi = (u_x, B_x), the last one compares and reduces in FP64 (fixed
+ * order, deterministic)
+ *   R = max over phi of ||phi(n) - phi(n-K+1)||_2 / ((K-1) ||phi(n)||_2),
+ * the mean change per step over the window, where phi(n) is the field the
+ * step after n collides with and n = steps_done - 1.  (Averaging over the
+ * window keeps the rounding noise of stochastically rounded storage, which
+ * does not accumulate, from masking a steady state.)  Stops at R < tol
  * (LKS_OK), at max_steps (LKS_ENOTCONV) or on a non-finite value
  * (LKS_EUNSTABLE).  Synchronous.  *steps_done and *residual (either may be
  * NULL) receive the totals reached in every case; *flow_rate (may be NULL)
@@ -256,8 +267,9 @@ int lks_mhd_batch_autotune(lks_mhd_batch_t *b, int32_t trial_steps,
  * Asynchronous. */
 int lks_mhd_batch_step(lks_mhd_batch_t *b, int64_t nsteps, int32_t use_graph);
 
-/* Advance nsteps >= 2 steps, the last two recording and reducing the
- * per-channel residual (definition as in lks_mhd_run_to_steady).  Writes
+/* Advance nsteps >= 2 steps as one residual window (the first step records,
+ * the last reduces the per-channel residual; definition as in
+ * lks_mhd_run_to_steady with K = nsteps).  Writes
  * per-slot residuals to residuals[max_channels] and per-slot flags (1 =
  * non-finite) to unstable[max_channels] (host arrays; entries of empty slots
  * are NaN / 0).  Synchronous. */

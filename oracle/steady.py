@@ -14,11 +14,16 @@ from . import Params, init_state, observe, run, step
 
 
 def residual(prev: dict, cur: dict) -> float:
+    """max over u_x, B_x of the relative step change; NaN if anything is
+    non-finite (NaN is propagated, not dropped by the max)."""
     r = 0.0
     for k in ("ux", "bx"):
         num = float(np.linalg.norm(cur[k] - prev[k]))
         den = max(float(np.linalg.norm(cur[k])), 1e-300)
-        r = max(r, num / den)
+        q = num / den
+        if not np.isfinite(q):
+            return float("nan")
+        r = max(r, q)
     return r
 
 

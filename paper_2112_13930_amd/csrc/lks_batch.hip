@@ -34,6 +34,7 @@ struct ChanDesc {
   int phase;      // buffer holding the state when the global parity is 0
   int tile_first; // first tile of this channel in the list
   int tile_count;
+  uint32_t step_base; // global step count at admission
   Coef<float> kf;
   Coef<double> kd;
 };
@@ -53,10 +54,16 @@ template <typename C> __device__ __forceinline__ const Coef<C> &coef_of(const Ch
 template <> __device__ __forceinline__ const Coef<float> &coef_of<float>(const ChanDesc &c) { return c.kf; }
 template <> __device__ __forceinline__ const Coef<double> &coef_of<double>(const ChanDesc &c) { return c.kd; }
 
+// gctr[2]: global step counters as in the single-channel kernel; a channel's
+// own step index is gctr[parity] - step_base.
 template <typename S, typename C, int MODE>
 __global__ __launch_bounds__(kTileThreads) void k_batch_step(
     const ChanDesc *__restrict__ chans, const Tile *__restrict__ tiles,
-    const int *__restrict__ ntiles_dev, int parity, double *__restrict__ partials) {
+    const int *__restrict__ ntiles_dev, int parity, double *__restrict__ partials,
+    uint32_t *__restrict__ gctr) {
+  constexpr bool SR = kUseSR<S, C>;
+  const uint32_t gstep = gctr[parity];
+  if (blockIdx.x == 0 && threadIdx.x == 0) gctr[parity ^ 1] = gstep + 1u;
   const int nt = *ntiles_dev;
   __shared__ double lds[(kTileThreads / 64) * NREDB];
   for (int t = blockIdx.x; t < nt; t += gridDim.x) { // uniform per block
@@ -70,11 +77,12 @@ __global__ __launch_bounds__(kTileThreads) void k_batch_step(
     const S *src = static_cast<const S *>(c.buf[cur]);
     S *dst = static_cast<S *>(c.buf[cur ^ 1]);
     NodeObs<C> o{};
+    const uint32_t sseed = SR ? step_seed(gstep - c.step_base) : 0u;
     if (act) {
       if (c.bc == BC_LINK)
-        node_update<S, C, BC_LINK, MODE>(c.g, coef_of<C>(c), src, dst, x, y, o);
+        node_update<S, C, BC_LINK, MODE, SR>(c.g, coef_of<C>(c), src, dst, x, y, o, sseed);
       else
-        node_update<S, C, BC_MOMENT, MODE>(c.g, coef_of<C>(c), src, dst, x, y, o);
+        node_update<S, C, BC_MOMENT, MODE, SR>(c.g, coef_of<C>(c), src, dst, x, y, o, sseed);
     }
     const long long n = (long long)c.g.nx * c.g.ny;
     const long long i = (long long)y * c.g.nx + x;
@@ -138,7 +146,7 @@ __global__ __launch_bounds__(256) void k_chan_moments(Geom g, Coef<C> k, const S
   if (i >= n) return;
   const int y = (int)(i / g.nx), x = (int)(i - (long long)y * g.nx);
   NodeObs<C> o{};
-  node_update<S, C, BC, MODE_MOMENTS>(g, k, src, nullptr, x, y, o);
+  node_update<S, C, BC, MODE_MOMENTS, false>(g, k, src, nullptr, x, y, o, 0u);
   if (oo.rho) oo.rho[i] = 1.0 + (double)o.rhop;
   if (oo.ux) oo.ux[i] = (double)o.ux;
   if (oo.uy) oo.uy[i] = (double)o.uy;
@@ -183,6 +191,7 @@ struct lks_mhd_batch {
   int *d_active = nullptr;
   double *d_partials = nullptr;
   double *d_sums = nullptr;
+  uint32_t *d_gctr = nullptr;
   size_t heap_begin = 0;
   std::vector<Region> free_list; // sorted by offset
   std::vector<Slot> slots;
@@ -209,6 +218,7 @@ size_t overhead(int max_channels, int max_tiles) {
   b += align256((size_t)max_channels * sizeof(int));   // active flags
   b += align256((size_t)max_tiles * 8 * sizeof(double));
   b += align256((size_t)max_channels * 8 * sizeof(double));
+  b += 256; // global step counters
   return b;
 }
 
@@ -235,6 +245,10 @@ size_t channel_region_bytes(const Channel &c, int precision) {
   const size_t rec = align256((size_t)2 * c.p.nx * c.p.ny * sizeof(double));
   return 2 * state + rec;
 }
+
+template <typename C> const Coef<C> &coef_host(const ChanDesc &d);
+template <> const Coef<float> &coef_host<float>(const ChanDesc &d) { return d.kf; }
+template <> const Coef<double> &coef_host<double>(const ChanDesc &d) { return d.kd; }
 
 template <typename F>
 int with_device(lks_mhd_batch *b, F &&fn) {
@@ -331,15 +345,15 @@ hipError_t launch_batch(lks_mhd_batch *b, int parity) {
   switch (b->precision) {
   case LKS_FP64:
     hipLaunchKernelGGL((k_batch_step<double, double, MODE>), dim3(b->grid), dim3(kTileThreads), 0,
-                       b->stream, b->d_chans, b->d_tiles, b->d_ntiles, parity, b->d_partials);
+                       b->stream, b->d_chans, b->d_tiles, b->d_ntiles, parity, b->d_partials, b->d_gctr);
     break;
   case LKS_FP32:
-    hipLaunchKernelGGL((k_batch_step<float, float, MODE>), dim3(b->grid), dim3(kTileThreads), 0,
-                       b->stream, b->d_chans, b->d_tiles, b->d_ntiles, parity, b->d_partials);
+    hipLaunchKernelGGL((k_batch_step<float, Fp32Compute, MODE>), dim3(b->grid), dim3(kTileThreads), 0,
+                       b->stream, b->d_chans, b->d_tiles, b->d_ntiles, parity, b->d_partials, b->d_gctr);
     break;
   default:
     hipLaunchKernelGGL((k_batch_step<_Float16, float, MODE>), dim3(b->grid), dim3(kTileThreads), 0,
-                       b->stream, b->d_chans, b->d_tiles, b->d_ntiles, parity, b->d_partials);
+                       b->stream, b->d_chans, b->d_tiles, b->d_ntiles, parity, b->d_partials, b->d_gctr);
   }
   return hipGetLastError();
 }
@@ -385,6 +399,15 @@ int capture(lks_mhd_batch *b) {
   return LKS_OK;
 }
 
+// Write the global step count into the device counter the next launch reads
+// (used when steps are counted without a launch).
+int sync_counter(lks_mhd_batch *b) {
+  const uint32_t v[2] = {(uint32_t)b->global_steps, (uint32_t)b->global_steps};
+  LKS_HIP_CHECK(hipMemcpyAsync(b->d_gctr, v, sizeof v, hipMemcpyHostToDevice, b->stream));
+  LKS_HIP_CHECK(hipStreamSynchronize(b->stream));
+  return LKS_OK;
+}
+
 int batch_steps(lks_mhd_batch *b, int64_t n, bool use_graph) {
   if (b->dirty) {
     const int rc = rebuild(b);
@@ -393,7 +416,7 @@ int batch_steps(lks_mhd_batch *b, int64_t n, bool use_graph) {
   if (b->nactive == 0) {
     b->global_steps += n; // nothing to advance; keep parity bookkeeping
     b->parity ^= (int)(n & 1);
-    return LKS_OK;
+    return sync_counter(b);
   }
   if (use_graph && b->stream == nullptr) {
     set_error("graph capture needs a non-default stream");
@@ -422,7 +445,7 @@ void launch_init(lks_mhd_batch *b, const Slot &s, void *buf) {
   const long long n = (long long)s.ch.p.nx * s.ch.p.ny;
   const Geom g{s.ch.p.nx, s.ch.p.ny, s.ch.p.nx, plane_elems(s.ch.p.nx, s.ch.p.ny, b->precision)};
   hipLaunchKernelGGL(k_init<S>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, b->stream, g,
-                     s.ch.p.rho0, s.ch.d.b0, static_cast<S *>(buf));
+                     s.ch.p.rho0, static_cast<S *>(buf));
 }
 
 } // namespace
@@ -488,6 +511,8 @@ int lks_mhd_batch_create(int32_t precision, int32_t max_channels, int64_t max_no
   p += align256((size_t)max_tiles * 8 * sizeof(double));
   b->d_sums = reinterpret_cast<double *>(p);
   p += align256((size_t)max_channels * 8 * sizeof(double));
+  b->d_gctr = reinterpret_cast<uint32_t *>(p);
+  p += 256;
   b->heap_begin = (size_t)(p - b->pool);
   if (pool_bytes > b->heap_begin) b->free_list.push_back(Region{b->heap_begin, pool_bytes - b->heap_begin});
   b->slots.resize(max_channels);
@@ -499,7 +524,11 @@ int lks_mhd_batch_create(int32_t precision, int32_t max_channels, int64_t max_no
   if (hipGetDeviceProperties(&prop, b->device) == hipSuccess && prop.multiProcessorCount > 0)
     cus = prop.multiProcessorCount;
   b->grid = cus * 8; // persistent: 8 blocks of 256 threads per CU
-  const int rc = with_device(b, [&]() -> int { return rebuild(b); });
+  const int rc = with_device(b, [&]() -> int {
+    const uint32_t z[2] = {0u, 0u};
+    LKS_HIP_CHECK(hipMemcpyAsync(b->d_gctr, z, sizeof z, hipMemcpyHostToDevice, b->stream));
+    return rebuild(b);
+  });
   if (rc != LKS_OK) {
     delete b;
     return rc;
@@ -572,6 +601,7 @@ int lks_mhd_batch_admit(lks_mhd_batch_t *b, const lks_mhd_params *p, int32_t *sl
   // the initial state goes to buf[0]; at the next step the global parity is
   // b->parity, and the channel must read buf[0] then: phase = parity.
   d.phase = b->parity;
+  d.step_base = (uint32_t)b->global_steps;
   d.kf = make_coef<float>(c);
   d.kd = make_coef<double>(c);
   sl.admit_step = b->global_steps;
@@ -663,10 +693,12 @@ int lks_mhd_batch_step_check(lks_mhd_batch_t *b, int64_t nsteps, int32_t use_gra
   }
   std::vector<double> sums((size_t)b->max_channels * 8, 0.0);
   const int rc = with_device(b, [&]() -> int {
-    int r = batch_steps(b, nsteps - 2, use_graph != 0);
-    if (r != LKS_OK) return r;
+    int r = LKS_OK;
+    if (b->dirty && (r = rebuild(b)) != LKS_OK) return r;
     if (b->nactive > 0) {
+      // the first step of the window records phi, the last compares
       if ((r = batch_one(b, MODE_RECORD)) != LKS_OK) return r;
+      if ((r = batch_steps(b, nsteps - 2, use_graph != 0)) != LKS_OK) return r;
       if ((r = batch_one(b, MODE_RESIDUAL)) != LKS_OK) return r;
       hipLaunchKernelGGL(k_batch_finalize, dim3(b->max_channels), dim3(64), 0, b->stream,
                          b->d_chans, b->d_active, b->d_partials, b->d_sums);
@@ -674,7 +706,9 @@ int lks_mhd_batch_step_check(lks_mhd_batch_t *b, int64_t nsteps, int32_t use_gra
       LKS_HIP_CHECK(hipMemcpyAsync(sums.data(), b->d_sums, sums.size() * sizeof(double),
                                    hipMemcpyDeviceToHost, b->stream));
     } else {
-      b->global_steps += 2;
+      b->global_steps += nsteps;
+      b->parity ^= (int)(nsteps & 1);
+      if ((r = sync_counter(b)) != LKS_OK) return r;
     }
     LKS_HIP_CHECK(hipStreamSynchronize(b->stream));
     return LKS_OK;
@@ -685,8 +719,9 @@ int lks_mhd_batch_step_check(lks_mhd_batch_t *b, int64_t nsteps, int32_t use_gra
     int bad = 0;
     if (b->slots[s].used) {
       const double *v = &sums[(size_t)s * 8];
-      const double ru = std::sqrt(v[0]) / std::fmax(std::sqrt(v[1]), 1e-300);
-      const double rb = std::sqrt(v[2]) / std::fmax(std::sqrt(v[3]), 1e-300);
+      const double win = (double)(nsteps - 1);
+      const double ru = std::sqrt(v[0]) / std::fmax(std::sqrt(v[1]), 1e-300) / win;
+      const double rb = std::sqrt(v[2]) / std::fmax(std::sqrt(v[3]), 1e-300) / win;
       r = std::fmax(ru, rb);
       bad = (v[5] != 0.0 || !std::isfinite(r)) ? 1 : 0;
     }
@@ -721,8 +756,8 @@ int lks_mhd_batch_moments(lks_mhd_batch_t *b, int32_t slot, double *rho, double 
       else hipLaunchKernelGGL((k_chan_moments<double, double, BC_MOMENT>), grid, dim3(256), 0, b->stream, d.g, d.kd, (const double *)d.buf[cur], oo);
       break;
     case LKS_FP32:
-      if (link) hipLaunchKernelGGL((k_chan_moments<float, float, BC_LINK>), grid, dim3(256), 0, b->stream, d.g, d.kf, (const float *)d.buf[cur], oo);
-      else hipLaunchKernelGGL((k_chan_moments<float, float, BC_MOMENT>), grid, dim3(256), 0, b->stream, d.g, d.kf, (const float *)d.buf[cur], oo);
+      if (link) hipLaunchKernelGGL((k_chan_moments<float, Fp32Compute, BC_LINK>), grid, dim3(256), 0, b->stream, d.g, coef_host<Fp32Compute>(d), (const float *)d.buf[cur], oo);
+      else hipLaunchKernelGGL((k_chan_moments<float, Fp32Compute, BC_MOMENT>), grid, dim3(256), 0, b->stream, d.g, coef_host<Fp32Compute>(d), (const float *)d.buf[cur], oo);
       break;
     default:
       if (link) hipLaunchKernelGGL((k_chan_moments<_Float16, float, BC_LINK>), grid, dim3(256), 0, b->stream, d.g, d.kf, (const _Float16 *)d.buf[cur], oo);
@@ -745,9 +780,9 @@ int lks_mhd_batch_save_state(lks_mhd_batch_t *b, int32_t slot, double *dev_pops)
   const dim3 grid((unsigned)((n + 255) / 256));
   return with_device(b, [&]() -> int {
     switch (b->precision) {
-    case LKS_FP64: hipLaunchKernelGGL(k_save<double>, grid, dim3(256), 0, b->stream, d.g, (const double *)d.buf[cur], dev_pops); break;
-    case LKS_FP32: hipLaunchKernelGGL(k_save<float>, grid, dim3(256), 0, b->stream, d.g, (const float *)d.buf[cur], dev_pops); break;
-    default: hipLaunchKernelGGL(k_save<_Float16>, grid, dim3(256), 0, b->stream, d.g, (const _Float16 *)d.buf[cur], dev_pops);
+    case LKS_FP64: hipLaunchKernelGGL(k_save<double>, grid, dim3(256), 0, b->stream, d.g, b->slots[slot].ch.d.b0, (const double *)d.buf[cur], dev_pops); break;
+    case LKS_FP32: hipLaunchKernelGGL(k_save<float>, grid, dim3(256), 0, b->stream, d.g, b->slots[slot].ch.d.b0, (const float *)d.buf[cur], dev_pops); break;
+    default: hipLaunchKernelGGL(k_save<_Float16>, grid, dim3(256), 0, b->stream, d.g, b->slots[slot].ch.d.b0, (const _Float16 *)d.buf[cur], dev_pops);
     }
     LKS_HIP_CHECK(hipGetLastError());
     return LKS_OK;

@@ -10,9 +10,10 @@
 // writes per node through HBM.
 //
 // Storage: S is the stored type (double, float or _Float16), C the compute
-// type (double for double storage, float otherwise).  Flow populations are
-// stored as deviations f_alpha - w_alpha from the rest equilibrium at unit
-// density; magnetic populations as values.
+// type.  Every population is stored as its deviation from the rest state at
+// unit density and B = (0, B0): f_alpha - w_alpha, g_alpha,x, and
+// g_alpha,y - W_alpha B0, so stored values carry only what the flow and the
+// induced field put into them.
 //
 // Method references (Yahia & Premnath, arXiv 2112.13930):
 //   equilibria, source, moments: Secs. IV, V;  J_z: Sec. IV;  F = J x B: Sec. II
@@ -22,6 +23,24 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+// Arithmetic of the reduced-precision modes (compile-time; the defaults are
+// the product configuration):
+//   LKS_FP32_COMPUTE_DOUBLE  FP32-stored populations are computed in FP64.
+//                            The step is HBM-bound, so this costs no time,
+//                            and FP32 arithmetic leaves a rounding residual
+//                            that slow modes of a steady channel amplify.
+//   LKS_SR_FP32, LKS_SR_FP16 stored values are rounded stochastically (needs a
+//                            compute type wider than the storage type).
+#ifndef LKS_FP32_COMPUTE_DOUBLE
+#define LKS_FP32_COMPUTE_DOUBLE 1
+#endif
+#ifndef LKS_SR_FP32
+#define LKS_SR_FP32 1
+#endif
+#ifndef LKS_SR_FP16
+#define LKS_SR_FP16 1
+#endif
 
 namespace lks {
 
@@ -74,6 +93,82 @@ __device__ __forceinline__ void st(S *__restrict__ p, C v) {
   __builtin_nontemporal_store(static_cast<S>(v), p);
 }
 
+// ---- stochastic rounding of the stored populations ----
+// Round-to-nearest storage leaves the same rounding residual in every step
+// once the flow is steady, and slow modes integrate it; rounding to one of
+// the two neighbouring representable values with probabilities given by the
+// distances makes the residual change from step to step.  The random bits are
+// a counter-based hash of (channel-local step, node, plane), so a run is
+// reproducible bit for bit and independent of launch shape or batch mix.
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352dU;
+  x ^= x >> 15;
+  x *= 0x846ca68bU;
+  x ^= x >> 16;
+  return x;
+}
+
+__device__ __forceinline__ uint32_t step_seed(uint32_t step) { return mix32(step * 0x9E3779B1U + 0x632BE5ABU); }
+
+__device__ __forceinline__ uint32_t node_seed(uint32_t sseed, uint32_t idx) {
+  return mix32(idx * 0x85EBCA77U ^ sseed);
+}
+
+__device__ __forceinline__ uint32_t plane_bits(uint32_t nseed, int plane) {
+  return mix32(nseed + (uint32_t)plane * 0xC2B2AE3DU);
+}
+
+template <typename T> struct BitsOf;
+template <> struct BitsOf<float> { using U = uint32_t; };
+template <> struct BitsOf<_Float16> { using U = uint16_t; };
+
+// Neighbour of h one unit in the last place up (+) or down (-).
+template <typename T>
+__device__ __forceinline__ T next_toward(T h, bool up) {
+  using U = typename BitsOf<T>::U;
+  constexpr U sign = U(U(1) << (sizeof(U) * 8 - 1));
+  U b = __builtin_bit_cast(U, h);
+  if (U(b & U(~sign)) == 0) return __builtin_bit_cast(T, U(up ? U(1) : U(sign | U(1))));
+  const bool neg = (b & sign) != 0;
+  b = (up != neg) ? U(b + 1) : U(b - 1);
+  return __builtin_bit_cast(T, b);
+}
+
+// v (wider type W) rounded stochastically to T with 24 random bits of r.
+template <typename T, typename W>
+__device__ __forceinline__ T round_sr(W v, uint32_t r) {
+  const T h = static_cast<T>(v); // nearest
+  const W a = static_cast<W>(h);
+  if (a == v || !__builtin_isfinite(a)) return h;
+  const bool up = v > a;
+  const T o = next_toward(h, up);
+  const W g = __builtin_fabs(static_cast<W>(o) - a); // a power of two
+  const W d = __builtin_fabs(v - a);                  // exact (Sterbenz)
+  const W u = static_cast<W>(r >> 8) * W(1.0 / 16777216.0);
+  return (u * g < d) ? o : h;                         // P(o) = d / g
+}
+
+template <typename S, typename C, bool SR>
+__device__ __forceinline__ void store(S *__restrict__ p, C v, uint32_t nseed, int plane) {
+  if constexpr (SR) {
+    __builtin_nontemporal_store(round_sr<S, C>(v, plane_bits(nseed, plane)), p);
+  } else {
+    (void)nseed;
+    (void)plane;
+    __builtin_nontemporal_store(static_cast<S>(v), p);
+  }
+}
+
+// Stochastic rounding applies when the compute type is wider than storage.
+template <typename S, typename C>
+constexpr bool kUseSR = (sizeof(C) > sizeof(S)) &&
+                        ((sizeof(S) == 4 && LKS_SR_FP32) || (sizeof(S) == 2 && LKS_SR_FP16));
+
+template <bool D> struct Fp32ComputeSel { using type = float; };
+template <> struct Fp32ComputeSel<true> { using type = double; };
+using Fp32Compute = Fp32ComputeSel<(LKS_FP32_COMPUTE_DOUBLE != 0)>::type;
+
 // Weights (Secs. IV and V).
 template <typename C> struct W {
   static constexpr C w0 = C(4) / C(9), w1 = C(1) / C(9), w5 = C(1) / C(36);
@@ -95,11 +190,11 @@ __device__ __forceinline__ C collide_f(C f, C w, C ex, C ey, C rhop, C rho,
   return f + omega * (feq - f) + kappa * S;
 }
 
-template <typename S, typename C, int BC, int MODE>
+template <typename S, typename C, int BC, int MODE, bool SR>
 __device__ __forceinline__ void node_update(const Geom &g, const Coef<C> &k,
                                             const S *__restrict__ src,
                                             S *__restrict__ dst, int x, int y,
-                                            NodeObs<C> &obs) {
+                                            NodeObs<C> &obs, uint32_t sseed) {
   const int nx = g.nx;
   const long long P = g.plane;
   const int xm = (x == 0) ? nx - 1 : x - 1;
@@ -140,21 +235,21 @@ __device__ __forceinline__ void node_update(const Geom &g, const Coef<C> &k,
   if (BC == BC_LINK) {
     // Half-way bounce-back of f with Ladd's moving-wall term; theta-weighted
     // bounce-back/anti-bounce-back of g_x; anti-bounce-back to B_y = B0 for
-    // g_y.  All from the node's own post-collision values.
-    const C b0_3 = k.b0 * (C(1) / C(3)); // 2 W_alpha B0 with W = 1/6
+    // g_y, which for the deviations g_y - W B0 is g'_in = -g~'_out.  All from
+    // the node's own post-collision values.
     if (lo) {
       f[2] = ld<S, C>(src + 4 * P + r0 + x);
       f[5] = ld<S, C>(src + 7 * P + r0 + x) + k.lo.uw6;
       f[6] = ld<S, C>(src + 8 * P + r0 + x) - k.lo.uw6;
       gx[2] = k.lo.r * ld<S, C>(src + 13 * P + r0 + x) + k.lo.t;
-      gy[2] = b0_3 - ld<S, C>(src + 18 * P + r0 + x);
+      gy[2] = -ld<S, C>(src + 18 * P + r0 + x);
     }
     if (hi) {
       f[4] = ld<S, C>(src + 2 * P + r0 + x);
       f[7] = ld<S, C>(src + 5 * P + r0 + x) - k.hi.uw6;
       f[8] = ld<S, C>(src + 6 * P + r0 + x) + k.hi.uw6;
       gx[4] = k.hi.r * ld<S, C>(src + 11 * P + r0 + x) + k.hi.t;
-      gy[4] = b0_3 - ld<S, C>(src + 16 * P + r0 + x);
+      gy[4] = -ld<S, C>(src + 16 * P + r0 + x);
     }
   } else {
     // On-node closures from the moment constraints, written for the
@@ -168,7 +263,7 @@ __device__ __forceinline__ void node_update(const Geom &g, const Coef<C> &k,
       f[5] = rhop * (C(1) / C(6)) + C(0.5) * rho * (U * U + U) - (f[1] + f[8]);
       f[6] = rhop * (C(1) / C(6)) + C(0.5) * rho * (U * U - U) - (f[3] + f[7]);
       gx[2] = k.lo.r * gx[4] - k.lo.s * (gx[0] + gx[1] + gx[3]) + k.lo.t;
-      gy[2] = k.b0 - (gy[0] + gy[1] + gy[3] + gy[4]);
+      gy[2] = -(gy[0] + gy[1] + gy[3] + gy[4]); // sum g_y = B0
     }
     if (hi) {
       const C U = k.hi.u;
@@ -179,7 +274,7 @@ __device__ __forceinline__ void node_update(const Geom &g, const Coef<C> &k,
       f[7] = rhop * (C(1) / C(6)) + C(0.5) * rho * (U * U - U) - (f[3] + f[6]);
       f[8] = rhop * (C(1) / C(6)) + C(0.5) * rho * (U * U + U) - (f[1] + f[5]);
       gx[4] = k.hi.r * gx[2] - k.hi.s * (gx[0] + gx[1] + gx[3]) + k.hi.t;
-      gy[4] = k.b0 - (gy[0] + gy[1] + gy[2] + gy[3]);
+      gy[4] = -(gy[0] + gy[1] + gy[2] + gy[3]); // sum g_y = B0
     }
   }
 
@@ -189,7 +284,8 @@ __device__ __forceinline__ void node_update(const Geom &g, const Coef<C> &k,
   const C mx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
   const C my = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
   const C bx = (gx[0] + gx[1]) + (gx[2] + gx[3]) + gx[4];
-  const C by = (gy[0] + gy[1]) + (gy[2] + gy[3]) + gy[4];
+  const C byp = (gy[0] + gy[1]) + (gy[2] + gy[3]) + gy[4]; // B_y - B0
+  const C by = k.b0 + byp;
   const C D = (gy[1] - gy[3]) - (gx[2] - gx[4]); // Lambda_xy - Lambda_yx
 
   // ---- coupled local solve ----
@@ -227,19 +323,20 @@ __device__ __forceinline__ void node_update(const Geom &g, const Coef<C> &k,
 
   // ---- collide and store ----
   const long long o = r0 + x;
+  const uint32_t ns = SR ? node_seed(sseed, (uint32_t)(y * nx + x)) : 0u;
   const C om = k.omega_f, ka = k.kappa_f;
   const C usq15 = C(1.5) * (ux * ux + uy * uy);
   const C uF = ux * Fx + uy * Fy;
   const C w0 = W<C>::w0, w1 = W<C>::w1, w5 = W<C>::w5;
-  st<S, C>(dst + o, collide_f(f[0], w0, C(0), C(0), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka));
-  st<S, C>(dst + 1 * P + o, collide_f(f[1], w1, C(1), C(0), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka));
-  st<S, C>(dst + 2 * P + o, collide_f(f[2], w1, C(0), C(1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka));
-  st<S, C>(dst + 3 * P + o, collide_f(f[3], w1, C(-1), C(0), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka));
-  st<S, C>(dst + 4 * P + o, collide_f(f[4], w1, C(0), C(-1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka));
-  st<S, C>(dst + 5 * P + o, collide_f(f[5], w5, C(1), C(1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka));
-  st<S, C>(dst + 6 * P + o, collide_f(f[6], w5, C(-1), C(1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka));
-  st<S, C>(dst + 7 * P + o, collide_f(f[7], w5, C(-1), C(-1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka));
-  st<S, C>(dst + 8 * P + o, collide_f(f[8], w5, C(1), C(-1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka));
+  store<S, C, SR>(dst + o, collide_f(f[0], w0, C(0), C(0), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), ns, 0);
+  store<S, C, SR>(dst + 1 * P + o, collide_f(f[1], w1, C(1), C(0), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), ns, 1);
+  store<S, C, SR>(dst + 2 * P + o, collide_f(f[2], w1, C(0), C(1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), ns, 2);
+  store<S, C, SR>(dst + 3 * P + o, collide_f(f[3], w1, C(-1), C(0), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), ns, 3);
+  store<S, C, SR>(dst + 4 * P + o, collide_f(f[4], w1, C(0), C(-1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), ns, 4);
+  store<S, C, SR>(dst + 5 * P + o, collide_f(f[5], w5, C(1), C(1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), ns, 5);
+  store<S, C, SR>(dst + 6 * P + o, collide_f(f[6], w5, C(-1), C(1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), ns, 6);
+  store<S, C, SR>(dst + 7 * P + o, collide_f(f[7], w5, C(-1), C(-1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), ns, 7);
+  store<S, C, SR>(dst + 8 * P + o, collide_f(f[8], w5, C(1), C(-1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), ns, 8);
 
   // g^eq_{a i} = W_a [B_i + e_aj (u_j B_i - B_j u_i) / cs2m]  (Sec. IV):
   // with E = u_x B_y - u_y B_x only g_2x, g_4x (-/+ 3E) and g_1y, g_3y (+/- 3E)
@@ -247,16 +344,16 @@ __device__ __forceinline__ void node_update(const Geom &g, const Coef<C> &k,
   const C E3 = C(3) * (ux * by - uy * bx);
   const C wm = k.omega_m;
   const C W0 = W<C>::W0, W1 = W<C>::W1;
-  st<S, C>(dst + 9 * P + o, gx[0] + wm * (W0 * bx - gx[0]));
-  st<S, C>(dst + 10 * P + o, gx[1] + wm * (W1 * bx - gx[1]));
-  st<S, C>(dst + 11 * P + o, gx[2] + wm * (W1 * (bx - E3) - gx[2]));
-  st<S, C>(dst + 12 * P + o, gx[3] + wm * (W1 * bx - gx[3]));
-  st<S, C>(dst + 13 * P + o, gx[4] + wm * (W1 * (bx + E3) - gx[4]));
-  st<S, C>(dst + 14 * P + o, gy[0] + wm * (W0 * by - gy[0]));
-  st<S, C>(dst + 15 * P + o, gy[1] + wm * (W1 * (by + E3) - gy[1]));
-  st<S, C>(dst + 16 * P + o, gy[2] + wm * (W1 * by - gy[2]));
-  st<S, C>(dst + 17 * P + o, gy[3] + wm * (W1 * (by - E3) - gy[3]));
-  st<S, C>(dst + 18 * P + o, gy[4] + wm * (W1 * by - gy[4]));
+  store<S, C, SR>(dst + 9 * P + o, gx[0] + wm * (W0 * bx - gx[0]), ns, 9);
+  store<S, C, SR>(dst + 10 * P + o, gx[1] + wm * (W1 * bx - gx[1]), ns, 10);
+  store<S, C, SR>(dst + 11 * P + o, gx[2] + wm * (W1 * (bx - E3) - gx[2]), ns, 11);
+  store<S, C, SR>(dst + 12 * P + o, gx[3] + wm * (W1 * bx - gx[3]), ns, 12);
+  store<S, C, SR>(dst + 13 * P + o, gx[4] + wm * (W1 * (bx + E3) - gx[4]), ns, 13);
+  store<S, C, SR>(dst + 14 * P + o, gy[0] + wm * (W0 * byp - gy[0]), ns, 14);
+  store<S, C, SR>(dst + 15 * P + o, gy[1] + wm * (W1 * (byp + E3) - gy[1]), ns, 15);
+  store<S, C, SR>(dst + 16 * P + o, gy[2] + wm * (W1 * byp - gy[2]), ns, 16);
+  store<S, C, SR>(dst + 17 * P + o, gy[3] + wm * (W1 * (byp - E3) - gy[3]), ns, 17);
+  store<S, C, SR>(dst + 18 * P + o, gy[4] + wm * (W1 * byp - gy[4]), ns, 18);
 }
 
 // ---- FP64 block reduction (deterministic: fixed shuffle and LDS order) ----

@@ -37,6 +37,9 @@ __device__ __forceinline__ int map_tile(bool remap) {
   return (id & 7) * per + (id >> 3);
 }
 
+// ctr[2]: the channel-local index of the step in flight is ctr[parity]; the
+// first block of a step writes ctr[parity ^ 1] = ctr[parity] + 1 for the next
+// step, which reads the other slot, so no launch reads what it writes.
 template <typename S, typename C, int BC, int MODE, int BX, int BY, bool REMAP>
 __global__ __launch_bounds__(BX *BY) void k_step(Geom g, Coef<C> k,
                                                  const S *__restrict__ src,
@@ -44,7 +47,15 @@ __global__ __launch_bounds__(BX *BY) void k_step(Geom g, Coef<C> k,
                                                  int tiles_x, int ntiles,
                                                  double *__restrict__ rec,
                                                  double *__restrict__ partials,
-                                                 ObsOut oo) {
+                                                 ObsOut oo, uint32_t *__restrict__ ctr,
+                                                 int parity) {
+  constexpr bool SR = kUseSR<S, C> && MODE != MODE_MOMENTS;
+  uint32_t sseed = 0;
+  if constexpr (MODE != MODE_MOMENTS) {
+    const uint32_t step = ctr[parity];
+    if (blockIdx.x == 0 && threadIdx.x == 0 && threadIdx.y == 0) ctr[parity ^ 1] = step + 1u;
+    if constexpr (SR) sseed = step_seed(step);
+  }
   const int tile = map_tile(REMAP);
   if (tile >= ntiles) return; // uniform per block
   const int ty = tile / tiles_x;
@@ -53,7 +64,7 @@ __global__ __launch_bounds__(BX *BY) void k_step(Geom g, Coef<C> k,
   const int y = ty * BY + (int)threadIdx.y;
   const bool act = (x < g.nx) && (y < g.ny);
   NodeObs<C> o{};
-  if (act) node_update<S, C, BC, MODE>(g, k, src, dst, x, y, o);
+  if (act) node_update<S, C, BC, MODE, SR>(g, k, src, dst, x, y, o, sseed);
   const long long n = (long long)g.nx * g.ny;
   const long long i = (long long)y * g.nx + x;
   if constexpr (MODE == MODE_RECORD) {
@@ -121,6 +132,7 @@ struct lks_mhd {
   double *rec = nullptr;
   double *partials = nullptr;
   double *result = nullptr;
+  uint32_t *ctr = nullptr; // step counters [2] (device)
   int cur = 0;
   int64_t steps = 0;
   int shape = 0;
@@ -149,7 +161,7 @@ Layout layout_of(const Channel &c) {
   L.red_tiles_x = (c.p.nx + s.bx - 1) / s.bx;
   L.red_ntiles = L.red_tiles_x * ((c.p.ny + s.by - 1) / s.by);
   L.part_bytes = align256((size_t)L.red_ntiles * 8 * sizeof(double));
-  L.total = 2 * L.state_bytes + L.rec_bytes + L.part_bytes + 256;
+  L.total = 2 * L.state_bytes + L.rec_bytes + L.part_bytes + 256 + 256;
   return L;
 }
 
@@ -169,7 +181,7 @@ hipError_t launch_shape(lks_mhd *h, const void *src, void *dst, ObsOut oo) {
   hipLaunchKernelGGL((k_step<S, C, BC, MODE, s.bx, s.by, s.remap>), dim3(grid),
                      dim3(s.bx, s.by), 0, h->stream, h->geom, k,
                      static_cast<const S *>(src), static_cast<S *>(dst), tiles_x,
-                     ntiles, h->rec, h->partials, oo);
+                     ntiles, h->rec, h->partials, oo, h->ctr, h->cur);
   return hipGetLastError();
 }
 
@@ -192,8 +204,8 @@ hipError_t launch_mode(lks_mhd *h, int shape, const void *src, void *dst, ObsOut
     return link ? launch_bc<double, double, BC_LINK, MODE>(h, shape, src, dst, oo)
                 : launch_bc<double, double, BC_MOMENT, MODE>(h, shape, src, dst, oo);
   case LKS_FP32:
-    return link ? launch_bc<float, float, BC_LINK, MODE>(h, shape, src, dst, oo)
-                : launch_bc<float, float, BC_MOMENT, MODE>(h, shape, src, dst, oo);
+    return link ? launch_bc<float, Fp32Compute, BC_LINK, MODE>(h, shape, src, dst, oo)
+                : launch_bc<float, Fp32Compute, BC_MOMENT, MODE>(h, shape, src, dst, oo);
   default:
     return link ? launch_bc<_Float16, float, BC_LINK, MODE>(h, shape, src, dst, oo)
                 : launch_bc<_Float16, float, BC_MOMENT, MODE>(h, shape, src, dst, oo);
@@ -263,6 +275,14 @@ int with_device(lks_mhd *h, F &&fn) {
   return rc;
 }
 
+// Set the step counter of the current buffer (outside any graph capture).
+int set_counter(lks_mhd *h, int64_t steps) {
+  const uint32_t v[2] = {(uint32_t)steps, (uint32_t)steps};
+  LKS_HIP_CHECK(hipMemcpyAsync(h->ctr, v, sizeof v, hipMemcpyHostToDevice, h->stream));
+  LKS_HIP_CHECK(hipStreamSynchronize(h->stream));
+  return LKS_OK;
+}
+
 int elementwise_grid(const lks_mhd *h) {
   const long long n = (long long)h->geom.nx * h->geom.ny;
   return (int)((n + 255) / 256);
@@ -314,6 +334,7 @@ int lks_mhd_create(const lks_mhd_params *p, void *dev_buf, size_t bytes,
   h->rec = reinterpret_cast<double *>(base + 2 * L.state_bytes);
   h->partials = reinterpret_cast<double *>(base + 2 * L.state_bytes + L.rec_bytes);
   h->result = reinterpret_cast<double *>(base + 2 * L.state_bytes + L.rec_bytes + L.part_bytes);
+  h->ctr = reinterpret_cast<uint32_t *>(base + 2 * L.state_bytes + L.rec_bytes + L.part_bytes + 256);
   h->red_tiles_x = L.red_tiles_x;
   h->red_ntiles = L.red_ntiles;
   h->kd = make_coef<double>(c);
@@ -323,16 +344,16 @@ int lks_mhd_create(const lks_mhd_params *p, void *dev_buf, size_t bytes,
     const int grid = elementwise_grid(h);
     switch (c.p.precision) {
     case LKS_FP64:
-      hipLaunchKernelGGL(k_init<double>, dim3(grid), dim3(256), 0, h->stream, h->geom, c.p.rho0, c.d.b0, (double *)h->buf[0]);
+      hipLaunchKernelGGL(k_init<double>, dim3(grid), dim3(256), 0, h->stream, h->geom, c.p.rho0, (double *)h->buf[0]);
       break;
     case LKS_FP32:
-      hipLaunchKernelGGL(k_init<float>, dim3(grid), dim3(256), 0, h->stream, h->geom, c.p.rho0, c.d.b0, (float *)h->buf[0]);
+      hipLaunchKernelGGL(k_init<float>, dim3(grid), dim3(256), 0, h->stream, h->geom, c.p.rho0, (float *)h->buf[0]);
       break;
     default:
-      hipLaunchKernelGGL(k_init<_Float16>, dim3(grid), dim3(256), 0, h->stream, h->geom, c.p.rho0, c.d.b0, (_Float16 *)h->buf[0]);
+      hipLaunchKernelGGL(k_init<_Float16>, dim3(grid), dim3(256), 0, h->stream, h->geom, c.p.rho0, (_Float16 *)h->buf[0]);
     }
     LKS_HIP_CHECK(hipGetLastError());
-    return LKS_OK;
+    return set_counter(h, 0);
   });
   if (rc != LKS_OK) {
     delete h;
@@ -418,9 +439,11 @@ int lks_mhd_run_to_steady(lks_mhd_t *h, double tol, int64_t check_every,
   const int rc = with_device(h, [&]() -> int {
     int64_t done = 0;
     while (done + check_every <= max_steps) {
-      int rc2 = lks_mhd_step(h, check_every - 2);
+      // window of check_every steps: the first records phi, the last
+      // compares phi with the record check_every - 1 steps later
+      int rc2 = one_step(h, MODE_RECORD);
       if (rc2 != LKS_OK) return rc2;
-      if ((rc2 = one_step(h, MODE_RECORD)) != LKS_OK) return rc2;
+      if ((rc2 = lks_mhd_step(h, check_every - 2)) != LKS_OK) return rc2;
       if ((rc2 = one_step(h, MODE_RESIDUAL)) != LKS_OK) return rc2;
       hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, h->stream, h->partials, h->red_ntiles, h->result);
       LKS_HIP_CHECK(hipGetLastError());
@@ -428,8 +451,9 @@ int lks_mhd_run_to_steady(lks_mhd_t *h, double tol, int64_t check_every,
       LKS_HIP_CHECK(hipMemcpyAsync(sums, h->result, sizeof sums, hipMemcpyDeviceToHost, h->stream));
       LKS_HIP_CHECK(hipStreamSynchronize(h->stream));
       done += check_every;
-      const double ru = std::sqrt(sums[0]) / std::fmax(std::sqrt(sums[1]), 1e-300);
-      const double rb = std::sqrt(sums[2]) / std::fmax(std::sqrt(sums[3]), 1e-300);
+      const double win = (double)(check_every - 1);
+      const double ru = std::sqrt(sums[0]) / std::fmax(std::sqrt(sums[1]), 1e-300) / win;
+      const double rb = std::sqrt(sums[2]) / std::fmax(std::sqrt(sums[3]), 1e-300) / win;
       res = std::fmax(ru, rb);
       q = sums[4] / h->geom.nx;
       if (sums[5] != 0.0 || !std::isfinite(res)) {
@@ -480,9 +504,9 @@ int lks_mhd_save_state(lks_mhd_t *h, double *dev_pops) {
   return with_device(h, [&]() -> int {
     const int grid = elementwise_grid(h);
     switch (h->ch.p.precision) {
-    case LKS_FP64: hipLaunchKernelGGL(k_save<double>, dim3(grid), dim3(256), 0, h->stream, h->geom, (const double *)h->buf[h->cur], dev_pops); break;
-    case LKS_FP32: hipLaunchKernelGGL(k_save<float>, dim3(grid), dim3(256), 0, h->stream, h->geom, (const float *)h->buf[h->cur], dev_pops); break;
-    default: hipLaunchKernelGGL(k_save<_Float16>, dim3(grid), dim3(256), 0, h->stream, h->geom, (const _Float16 *)h->buf[h->cur], dev_pops);
+    case LKS_FP64: hipLaunchKernelGGL(k_save<double>, dim3(grid), dim3(256), 0, h->stream, h->geom, h->ch.d.b0, (const double *)h->buf[h->cur], dev_pops); break;
+    case LKS_FP32: hipLaunchKernelGGL(k_save<float>, dim3(grid), dim3(256), 0, h->stream, h->geom, h->ch.d.b0, (const float *)h->buf[h->cur], dev_pops); break;
+    default: hipLaunchKernelGGL(k_save<_Float16>, dim3(grid), dim3(256), 0, h->stream, h->geom, h->ch.d.b0, (const _Float16 *)h->buf[h->cur], dev_pops);
     }
     LKS_HIP_CHECK(hipGetLastError());
     return LKS_OK;
@@ -498,13 +522,13 @@ int lks_mhd_load_state(lks_mhd_t *h, const double *dev_pops, int64_t steps) {
   return with_device(h, [&]() -> int {
     const int grid = elementwise_grid(h);
     switch (h->ch.p.precision) {
-    case LKS_FP64: hipLaunchKernelGGL(k_load<double>, dim3(grid), dim3(256), 0, h->stream, h->geom, dev_pops, (double *)h->buf[h->cur]); break;
-    case LKS_FP32: hipLaunchKernelGGL(k_load<float>, dim3(grid), dim3(256), 0, h->stream, h->geom, dev_pops, (float *)h->buf[h->cur]); break;
-    default: hipLaunchKernelGGL(k_load<_Float16>, dim3(grid), dim3(256), 0, h->stream, h->geom, dev_pops, (_Float16 *)h->buf[h->cur]);
+    case LKS_FP64: hipLaunchKernelGGL(k_load<double>, dim3(grid), dim3(256), 0, h->stream, h->geom, h->ch.d.b0, dev_pops, (double *)h->buf[h->cur]); break;
+    case LKS_FP32: hipLaunchKernelGGL(k_load<float>, dim3(grid), dim3(256), 0, h->stream, h->geom, h->ch.d.b0, dev_pops, (float *)h->buf[h->cur]); break;
+    default: hipLaunchKernelGGL(k_load<_Float16>, dim3(grid), dim3(256), 0, h->stream, h->geom, h->ch.d.b0, dev_pops, (_Float16 *)h->buf[h->cur]);
     }
     LKS_HIP_CHECK(hipGetLastError());
     h->steps = steps;
-    return LKS_OK;
+    return set_counter(h, steps);
   });
 }
 

@@ -1,0 +1,280 @@
+"""Continuous-batching solve service for channel steady states on one GPU.
+
+Requests (one channel parameter set each) arrive over time.  The scheduler
+admits them into a shared batch in arrival order as soon as their state fits
+(HBM footprint, slot table and node budget), advances every resident channel
+together with the batched persistent kernel, checks the per-channel FP64
+residual every `check_every` steps, and retires a request when it converges
+(residual < tol), stagnates (no new minimum 1% below the previous one within
+`stagnation_checks` checks: a precision floor, or a mode too slow for the
+budget), becomes non-finite, or reaches `max_steps` (see :func:`stop_status`).  Admissions and retirements
+happen only at check boundaries, so every channel is checked at multiples of
+`check_every` steps after its own admission and its result does not depend on
+what else is resident.
+
+The scheduler drives an executor with the interface of batch.Batch
+(try_admit, retire, step_check, steps_done, fetch); the GPU executor is
+:class:`GpuExecutor`.
+"""
+from __future__ import annotations
+
+import math
+import statistics
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+
+CONVERGED, STAGNATED, UNSTABLE, MAX_STEPS = "converged", "stagnated", "unstable", "max_steps"
+
+
+@dataclass
+class Request:
+    rid: int
+    params: object           # LksParams (or anything the executor accepts)
+    arrival: float = 0.0     # seconds after the service starts
+    status: str = "pending"
+    steps: int = 0
+    residual: float = math.nan
+    t_admit: float = math.nan
+    t_done: float = math.nan
+    slot: int = -1
+    result: object = None
+    history: list = field(default_factory=list)
+
+    @property
+    def latency(self) -> float:
+        return self.t_done - self.arrival
+
+
+def stop_status(history, steps, tol, max_steps, stagnation_checks):
+    """Stopping decision after a check (None: keep going)."""
+    r = history[-1]
+    if not math.isfinite(r):
+        return UNSTABLE
+    if r < tol:
+        return CONVERGED
+    if steps >= max_steps:
+        return MAX_STEPS
+    n = stagnation_checks
+    if len(history) > n and min(history[-n:]) > 0.99 * min(history[:-n]):
+        return STAGNATED
+    return None
+
+
+class Server:
+    def __init__(self, executor, tol: float = 1e-8, check_every: int = 200,
+                 max_steps: int = 2_000_000, stagnation_checks: int = 20,
+                 keep_result: bool = False, clock=time.perf_counter, sleep=time.sleep):
+        if check_every < 2:
+            raise ValueError("check_every must be >= 2")
+        self.ex = executor
+        self.tol = tol
+        self.K = check_every
+        self.max_steps = max_steps
+        self.stag = stagnation_checks
+        self.keep_result = keep_result
+        self.clock = clock
+        self.sleep = sleep
+        self.queue: deque[Request] = deque()
+        self.active: dict[int, Request] = {}
+        self.done: list[Request] = []
+
+    def submit(self, req: Request):
+        self.queue.append(req)
+
+    def _admit(self, now: float):
+        # FIFO: the head of the queue blocks later arrivals (no overtaking)
+        while self.queue and self.queue[0].arrival <= now:
+            req = self.queue[0]
+            slot = self.ex.try_admit(req.params)
+            if slot is None:
+                break
+            self.queue.popleft()
+            req.slot = slot
+            req.t_admit = now
+            req.status = "running"
+            self.active[slot] = req
+
+    def _retire(self, req: Request, status: str, now: float):
+        if self.keep_result:
+            req.result = self.ex.fetch(req.slot)
+        self.ex.retire(req.slot)
+        req.status = status
+        req.t_done = now
+        del self.active[req.slot]
+        self.done.append(req)
+
+    def run(self):
+        """Serve until every submitted request is done; returns them."""
+        t0 = self.clock()
+        while self.queue or self.active:
+            now = self.clock() - t0
+            self._admit(now)
+            if not self.active:
+                wait = self.queue[0].arrival - now
+                if wait > 0:
+                    self.sleep(wait)
+                    continue
+                raise RuntimeError("a queued request can never be admitted (too large for the pool)")
+            res, bad = self.ex.step_check(self.K)
+            now = self.clock() - t0
+            for slot, req in list(self.active.items()):
+                req.steps = self.ex.steps_done(slot)
+                r = math.nan if bad[slot] else float(res[slot])
+                req.residual = r
+                req.history.append(r)
+                st = stop_status(req.history, req.steps, self.tol, self.max_steps, self.stag)
+                if st is not None:
+                    self._retire(req, st, now)
+        return sorted(self.done, key=lambda q: q.rid)
+
+
+class GpuExecutor:
+    """The batched HIP path behind the scheduler's executor interface."""
+
+    def __init__(self, precision: str = "fp32", max_channels: int = 256,
+                 max_nodes: int = 1 << 24, pool_bytes: int | None = None,
+                 tiles=None, use_graph: bool = True):
+        from .batch import Batch
+        self.batch = Batch(precision, max_channels=max_channels, max_nodes=max_nodes,
+                           pool_bytes=pool_bytes)
+        self.max_channels = max_channels
+        self.use_graph = use_graph
+        if tiles is not None:
+            for k, (w, h) in enumerate(tiles):
+                self.batch.set_tile(k, w, h)
+
+    def try_admit(self, params):
+        return self.batch.try_admit(params)
+
+    def retire(self, slot):
+        self.batch.retire(slot)
+
+    def step_check(self, n):
+        return self.batch.step_check(n, graph=self.use_graph)
+
+    def steps_done(self, slot):
+        return self.batch.steps_done(slot)
+
+    def fetch(self, slot):
+        st = self.batch.save_state(slot)
+        m = self.batch.moments(slot)
+        return {"state": st.cpu(), "ux": m["ux"].cpu().numpy(), "bx": m["bx"].cpu().numpy()}
+
+    def close(self):
+        self.batch.close()
+
+
+def percentile(vals, q):
+    if not vals:
+        return math.nan
+    return float(np.percentile(np.asarray(vals), q))
+
+
+def sequential_baseline(requests, precision="fp32", tol=1e-8, check_every=200,
+                        max_steps=2_000_000, stagnation_checks=20, graph_steps=32, log=None):
+    """The same requests solved one after another by the plain single-channel
+    path (arrival order; a solve starts when the GPU is free and the request
+    has arrived), with the service's own stopping rule: each check window is
+    one run_to_steady call of check_every steps.  Returns per-request
+    (status, steps, residual, latency) and the makespan."""
+    import torch
+
+    from ._lib import LKS_EUNSTABLE
+    from .channel import Channel
+    out = []
+    t0 = time.perf_counter()
+    for req in requests:
+        now = time.perf_counter() - t0
+        if req.arrival > now:
+            time.sleep(req.arrival - now)
+        p = req.params
+        p.precision = {"fp64": 0, "fp32": 1, "fp16": 2}[precision]
+        ch = Channel(params=p, stream=torch.cuda.Stream())
+        ch.set_graph(graph_steps)
+        hist, status, steps, res = [], None, 0, math.nan
+        while status is None:
+            rc, steps, res, _ = ch.run_to_steady(tol=0.0, check_every=check_every,
+                                                 max_steps=check_every)
+            hist.append(math.nan if rc == LKS_EUNSTABLE else res)
+            status = stop_status(hist, steps, tol, max_steps, stagnation_checks)
+        ch.close()
+        t_done = time.perf_counter() - t0
+        out.append({"rid": req.rid, "status": status, "steps": steps, "residual": res,
+                    "latency": t_done - req.arrival})
+        if log and (req.rid % 8 == 7):
+            log(f"sequential: {req.rid + 1} requests solved, {t_done:.2f} s")
+    return out, time.perf_counter() - t0
+
+
+def serve_requests_from_mix(n, seed, nx_range=(4, 32), ny_range=(16, 48), ha_range=(2.0, 30.0),
+                            precision="fp32", rate=200.0, c_range=(1e-3, 1.0)):
+    """Requests drawn with the uneven-channel generator on a sub-range whose
+    steady solves take thousands (not millions) of steps: small channels and
+    c <= 1 (no perfectly conducting walls, whose shear-driven case has no
+    steady state and whose large-c slow modes take ~c a^2 / eta steps)."""
+    from ._lib import derive, make_params
+    from .workloads import channel_mix, poisson_arrivals
+    draws = channel_mix(4 * n, seed, nx_range=nx_range, ny_range=ny_range, ha_range=ha_range,
+                        c_range=c_range, p_zero=0.1, p_inf=0.0)
+    arr = poisson_arrivals(rate, n, seed + 1)
+    reqs = []
+    for d in draws:
+        if len(reqs) == n:
+            break
+        p = make_params(d.nx, d.ny, precision=precision, **d.kwargs())
+        if derive(p).b0 > 0.1:
+            continue
+        reqs.append(Request(rid=len(reqs), params=p, arrival=float(arr[len(reqs)])))
+    return reqs
+
+
+def serve_benchmark(n_requests=48, rate=200.0, seed=5, precision="fp32", tol=1e-8,
+                    check_every=200, max_steps=200_000, log=None):
+    """Serve a fixed number of Poisson-arriving requests with continuous
+    batching, then solve the same requests sequentially; report solves/s and
+    p50/p99 latency for both."""
+    import torch
+    reqs = serve_requests_from_mix(n_requests, seed, precision=precision, rate=rate)
+    ex = GpuExecutor(precision, max_channels=max(64, n_requests), max_nodes=1 << 22)
+    srv = Server(ex, tol=tol, check_every=check_every, max_steps=max_steps)
+    for r in reqs:
+        srv.submit(r)
+    t0 = time.perf_counter()
+    done = srv.run()
+    torch.cuda.synchronize()
+    makespan = time.perf_counter() - t0
+    ex.close()
+    lat = [r.latency for r in done]
+    if log:
+        log(f"serving: batched makespan {makespan:.2f} s for {len(done)} requests")
+    seq_reqs = serve_requests_from_mix(n_requests, seed, precision=precision, rate=rate)
+    seq, seq_span = sequential_baseline(seq_reqs, precision=precision, tol=tol,
+                                        check_every=check_every, max_steps=max_steps, log=log)
+    seq_lat = [s["latency"] for s in seq]
+    same_steps = sum(1 for a, b in zip(done, seq) if a.steps == b["steps"])
+    statuses, seq_statuses = {}, {}
+    for r in done:
+        statuses[r.status] = statuses.get(r.status, 0) + 1
+    for r in seq:
+        seq_statuses[r["status"]] = seq_statuses.get(r["status"], 0) + 1
+    return {
+        "requests": len(done), "arrival_rate_per_s": rate, "precision": precision,
+        "tol": tol, "check_every": check_every,
+        "workload": "uneven channels nx 4-32, ny 16-48, Ha 2-30, c = 0 (10%) or "
+                    "log-uniform in [1e-3, 1], body or shear driven, link or moment walls; "
+                    "Poisson arrivals",
+        "batched": {"makespan_s": round(makespan, 3), "solves_per_s": round(len(done) / makespan, 2),
+                    "p50_latency_s": round(percentile(lat, 50), 4),
+                    "p99_latency_s": round(percentile(lat, 99), 4), "statuses": statuses},
+        "sequential": {"makespan_s": round(seq_span, 3),
+                       "solves_per_s": round(len(seq) / seq_span, 2),
+                       "p50_latency_s": round(percentile(seq_lat, 50), 4),
+                       "p99_latency_s": round(percentile(seq_lat, 99), 4),
+                       "statuses": seq_statuses},
+        "speedup_solves_per_s": round(seq_span / makespan, 2),
+        "same_stop_step": f"{same_steps}/{len(done)}",
+        "mean_steps": round(statistics.mean(r.steps for r in done), 1),
+    }

@@ -50,11 +50,12 @@ class ChannelDraw:
 
 
 def channel_mix(n: int, seed: int, nx_range=(4, 256), ny_range=(32, 2048),
-                ha_range=(1.0, 200.0), c_range=(1e-3, 1e3)) -> list[ChannelDraw]:
+                ha_range=(1.0, 200.0), c_range=(1e-3, 1e3), p_zero=0.1,
+                p_inf=0.1) -> list[ChannelDraw]:
     """Independent channels drawn in this order per channel: Nx uniform
     integer in nx_range; Ny = round(exp(U(ln lo, ln hi))); Ha log-uniform;
-    c = 0 (10%), inf (10%), else log-uniform in c_range; drive body/shear 50/50;
-    wall treatment link/moment 50/50."""
+    c = 0 (p_zero), inf (p_inf), else log-uniform in c_range; drive
+    body/shear 50/50; wall treatment link/moment 50/50."""
     rng = np.random.default_rng(seed)
     out = []
     for _ in range(n):
@@ -62,9 +63,9 @@ def channel_mix(n: int, seed: int, nx_range=(4, 256), ny_range=(32, 2048),
         ny = int(round(math.exp(rng.uniform(math.log(ny_range[0]), math.log(ny_range[1])))))
         ha = float(math.exp(rng.uniform(math.log(ha_range[0]), math.log(ha_range[1]))))
         r = rng.uniform()
-        if r < 0.1:
+        if r < p_zero:
             c = 0.0
-        elif r < 0.2:
+        elif r < p_zero + p_inf:
             c = math.inf
         else:
             c = float(math.exp(rng.uniform(math.log(c_range[0]), math.log(c_range[1]))))

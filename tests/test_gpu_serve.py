@@ -1,0 +1,51 @@
+"""Continuous batching on the GPU: each request's result is the same alone
+and in a mix (bitwise: same stop step and same populations), and equals the
+plain single-channel path at that step count."""
+import pytest
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2112_13930_amd as P
+    assert torch.cuda.is_available()
+    P.lib()
+    return P
+
+
+def serve(reqs, precision):
+    from paper_2112_13930_amd.serve import GpuExecutor, Server
+    ex = GpuExecutor(precision, max_channels=32, max_nodes=1 << 20)
+    srv = Server(ex, tol=1e-7, check_every=100, max_steps=60_000, keep_result=True)
+    for r in reqs:
+        srv.submit(r)
+    done = srv.run()
+    ex.close()
+    return {r.rid: r for r in done}
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+def test_alone_equals_in_mix(P, precision):
+    from paper_2112_13930_amd.channel import Channel
+    from paper_2112_13930_amd.serve import serve_requests_from_mix
+    mix = serve_requests_from_mix(12, seed=3, nx_range=(4, 24), ny_range=(12, 32),
+                                  ha_range=(2.0, 20.0), precision=precision, rate=2000.0)
+    mixed = serve(mix, precision)
+    for rid in (0, 5, 11):
+        alone_req = serve_requests_from_mix(12, seed=3, nx_range=(4, 24), ny_range=(12, 32),
+                                            ha_range=(2.0, 20.0), precision=precision,
+                                            rate=2000.0)[rid]
+        alone_req.arrival = 0.0
+        alone = serve([alone_req], precision)[rid]
+        a, m = alone, mixed[rid]
+        assert a.status == m.status and a.steps == m.steps, (rid, a.status, m.status, a.steps, m.steps)
+        assert a.residual == m.residual
+        assert torch.equal(a.result["state"], m.result["state"])
+        # the plain single-channel path reaches the same populations
+        ch = Channel(params=alone_req.params)
+        ch.step(a.steps)
+        assert torch.equal(ch.save_state().cpu(), a.result["state"])
+    assert all(r.status != "unstable" for r in mixed.values()), \
+        {r.rid: r.status for r in mixed.values()}

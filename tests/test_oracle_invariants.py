@@ -158,3 +158,12 @@ def test_limits_of_c_in_whole_run(orc):
             orc.run(pa, sa, 500)
             orc.run(pb, sb, 500)
             assert np.abs(sa - sb).max() < 1e-9
+
+
+def test_steady_driver_reports_blow_up(orc):
+    """An unstable parameter set (strong forcing at a tiny viscosity) must be
+    reported, not mistaken for a steady state."""
+    from oracle import steady
+    p = Params(nx=1, ny=16, bc=LINK, tau_f=0.5005, tau_m=0.5005, b0=0.8, fx=0.02)
+    with pytest.raises(FloatingPointError):
+        steady.run_to_steady(p, tol=1e-12, check_every=100, max_steps=200_000)
