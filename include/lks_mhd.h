@@ -248,10 +248,13 @@ int lks_mhd_batch_retire(lks_mhd_batch_t *b, int32_t slot);
 int32_t lks_mhd_batch_active(const lks_mhd_batch_t *b);
 int64_t lks_mhd_batch_nodes(const lks_mhd_batch_t *b);
 
-/* Tile shape (tile_w x tile_h nodes, tile_w a multiple of 64 or one of
- * 8, 16, 32 with tile_w * tile_h = 256) used for channels of a width class:
- * class k holds channels with nx in (2^(k+2), 2^(k+3)] (k = 0..6, nx <= 8 in
- * class 0, nx > 256 in class 6). */
+/* Tile shape used for channels of a width class (class k holds channels with
+ * nx in (2^(k+2), 2^(k+3)], k = 0..6; nx <= 8 in class 0, nx > 256 in
+ * class 6).  One tile is the work of one 256-thread block:
+ *   tile_w in {8, 16, 32, 64, 128, 256}, tile_w * tile_h = 256: a tile_w x
+ *     tile_h rectangle of the channel;
+ *   tile_w = 0, tile_h in {1, 2, 4}: 256 * tile_h consecutive nodes of the
+ *     channel's row-major planes (the default, with tile_h = 1). */
 int lks_mhd_batch_set_tile(lks_mhd_batch_t *b, int32_t width_class,
                            int32_t tile_w, int32_t tile_h);
 

@@ -92,6 +92,7 @@ class Batch:
         return int(lib().lks_mhd_batch_steps_done(self._h, int(slot)))
 
     def set_tile(self, width_class: int, w: int, h: int):
+        """w x h rectangle (w * h = 256) or, with w = 0, 256 * h consecutive nodes."""
         check(lib().lks_mhd_batch_set_tile(self._h, int(width_class), int(w), int(h)),
               "lks_mhd_batch_set_tile")
 

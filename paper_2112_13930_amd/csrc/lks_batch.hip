@@ -39,10 +39,15 @@ struct ChanDesc {
   Coef<double> kd;
 };
 
+// A tile is the work of one 256-thread block: either a w x h rectangle of a
+// channel (w * h == 256, x0/y0 its corner) or, with w == 0, a run of 256 * h
+// consecutive nodes of the channel's [ny][nx] planes starting at node x0
+// (each thread takes h nodes 256 apart).  Linear tiles keep every wavefront
+// on 64 consecutive addresses whatever the channel width.
 struct Tile {
   int chan;
   int x0, y0;
-  int w, h; // w * h == 256
+  int w, h;
   int pad[3];
 };
 
@@ -69,43 +74,51 @@ __global__ __launch_bounds__(kTileThreads) void k_batch_step(
   for (int t = blockIdx.x; t < nt; t += gridDim.x) { // uniform per block
     const Tile tl = tiles[t];
     const ChanDesc &c = chans[tl.chan];
-    const int lx = (int)threadIdx.x % tl.w;
-    const int ly = (int)threadIdx.x / tl.w;
-    const int x = tl.x0 + lx, y = tl.y0 + ly;
-    const bool act = (ly < tl.h) && (x < c.g.nx) && (y < c.g.ny);
     const int cur = parity ^ c.phase;
     const S *src = static_cast<const S *>(c.buf[cur]);
     S *dst = static_cast<S *>(c.buf[cur ^ 1]);
-    NodeObs<C> o{};
     const uint32_t sseed = SR ? step_seed(gstep - c.step_base) : 0u;
-    if (act) {
+    const long long n = (long long)c.g.nx * c.g.ny;
+    double v[NREDB] = {0, 0, 0, 0, 0, 0};
+    auto one = [&](int x, int y) {
+      NodeObs<C> o{};
       if (c.bc == BC_LINK)
         node_update<S, C, BC_LINK, MODE, SR>(c.g, coef_of<C>(c), src, dst, x, y, o, sseed);
       else
         node_update<S, C, BC_MOMENT, MODE, SR>(c.g, coef_of<C>(c), src, dst, x, y, o, sseed);
-    }
-    const long long n = (long long)c.g.nx * c.g.ny;
-    const long long i = (long long)y * c.g.nx + x;
-    if constexpr (MODE == MODE_RECORD) {
-      if (act) {
+      const long long i = (long long)y * c.g.nx + x;
+      if constexpr (MODE == MODE_RECORD) {
         c.rec[i] = (double)o.ux;
         c.rec[n + i] = (double)o.bx;
       }
-    }
-    if constexpr (MODE == MODE_RESIDUAL) {
-      double v[NREDB] = {0, 0, 0, 0, 0, 0};
-      if (act) {
+      if constexpr (MODE == MODE_RESIDUAL) {
         const double u = (double)o.ux, b = (double)o.bx;
         const double du = u - c.rec[i], db = b - c.rec[n + i];
-        v[0] = du * du;
-        v[1] = u * u;
-        v[2] = db * db;
-        v[3] = b * b;
-        v[4] = u;
+        v[0] += du * du;
+        v[1] += u * u;
+        v[2] += db * db;
+        v[3] += b * b;
+        v[4] += u;
         const bool ok = isfinite((double)o.rho) && isfinite(u) && isfinite((double)o.uy) &&
                         isfinite(b) && isfinite((double)o.by) && (double)o.rho > 0.0;
-        v[5] = ok ? 0.0 : 1.0;
+        v[5] += ok ? 0.0 : 1.0;
       }
+    };
+    if (tl.w == 0) {
+      for (int j = 0; j < tl.h; ++j) {
+        const int i = tl.x0 + (int)threadIdx.x + j * kTileThreads;
+        if (i < n) {
+          const int y = i / c.g.nx;
+          one(i - y * c.g.nx, y);
+        }
+      }
+    } else {
+      const int lx = (int)threadIdx.x % tl.w;
+      const int ly = (int)threadIdx.x / tl.w;
+      const int x = tl.x0 + lx, y = tl.y0 + ly;
+      if ((ly < tl.h) && (x < c.g.nx) && (y < c.g.ny)) one(x, y);
+    }
+    if constexpr (MODE == MODE_RESIDUAL) {
       block_sum<NREDB, kTileThreads>(v, lds);
       if (threadIdx.x == 0) {
 #pragma unroll
@@ -198,7 +211,9 @@ struct lks_mhd_batch {
   std::vector<ChanDesc> h_chans;
   std::vector<Tile> h_tiles;
   std::vector<int> h_active;
-  int tile_w[kWidthClasses] = {8, 16, 32, 64, 128, 256, 256};
+  // tile shape per width class: (w, h) as in Tile; default linear, 256 nodes
+  int tile_w[kWidthClasses] = {0, 0, 0, 0, 0, 0, 0};
+  int tile_h[kWidthClasses] = {1, 1, 1, 1, 1, 1, 1};
   int64_t global_steps = 0;
   int parity = 0;
   int64_t nodes = 0;
@@ -291,16 +306,20 @@ void pool_free(lks_mhd_batch *b, size_t off, size_t bytes) {
   }
 }
 
-// Tiles of one channel for a tile width (height = 256 / width).
-int count_tiles(int nx, int ny, int w) {
-  const int h = kTileThreads / w;
+// Tiles of one channel for a tile shape (w, h) (w == 0: linear).
+int count_tiles(int nx, int ny, int w, int h) {
+  if (w == 0) {
+    const long long per = (long long)kTileThreads * h;
+    return (int)(((long long)nx * ny + per - 1) / per);
+  }
   return ((nx + w - 1) / w) * ((ny + h - 1) / h);
 }
 
-int total_tiles(const lks_mhd_batch *b, const int *tile_w) {
+int total_tiles(const lks_mhd_batch *b, const int *tile_w, const int *tile_h) {
   long long t = 0;
   for (const Slot &s : b->slots)
-    if (s.used) t += count_tiles(s.ch.p.nx, s.ch.p.ny, tile_w[s.width_class]);
+    if (s.used)
+      t += count_tiles(s.ch.p.nx, s.ch.p.ny, tile_w[s.width_class], tile_h[s.width_class]);
   return t > (1LL << 30) ? (1 << 30) : (int)t;
 }
 
@@ -316,10 +335,16 @@ int rebuild(lks_mhd_batch *b) {
       continue;
     }
     const int w = b->tile_w[sl.width_class];
-    const int h = kTileThreads / w;
+    const int h = b->tile_h[sl.width_class];
     d.tile_first = (int)b->h_tiles.size();
-    for (int y0 = 0; y0 < sl.ch.p.ny; y0 += h)
-      for (int x0 = 0; x0 < sl.ch.p.nx; x0 += w) b->h_tiles.push_back(Tile{s, x0, y0, w, h, {0, 0, 0}});
+    if (w == 0) {
+      const long long nn = (long long)sl.ch.p.nx * sl.ch.p.ny;
+      for (long long i0 = 0; i0 < nn; i0 += (long long)kTileThreads * h)
+        b->h_tiles.push_back(Tile{s, (int)i0, 0, 0, h, {0, 0, 0}});
+    } else {
+      for (int y0 = 0; y0 < sl.ch.p.ny; y0 += h)
+        for (int x0 = 0; x0 < sl.ch.p.nx; x0 += w) b->h_tiles.push_back(Tile{s, x0, y0, w, h, {0, 0, 0}});
+    }
     d.tile_count = (int)b->h_tiles.size() - d.tile_first;
   }
   if ((int)b->h_tiles.size() > b->max_tiles) {
@@ -577,9 +602,9 @@ int lks_mhd_batch_admit(lks_mhd_batch_t *b, const lks_mhd_params *p, int32_t *sl
   sl.width_class = width_class_of(q.nx);
   // tile capacity check for the current shape table
   {
-    int tw[kWidthClasses];
-    std::memcpy(tw, b->tile_w, sizeof tw);
-    if ((long long)total_tiles(b, tw) + count_tiles(q.nx, q.ny, tw[sl.width_class]) > b->max_tiles) {
+    if ((long long)total_tiles(b, b->tile_w, b->tile_h) +
+            count_tiles(q.nx, q.ny, b->tile_w[sl.width_class], b->tile_h[sl.width_class]) >
+        b->max_tiles) {
       set_error("tile list capacity exceeded");
       return LKS_ENOMEM;
     }
@@ -654,23 +679,29 @@ int lks_mhd_batch_retire(lks_mhd_batch_t *b, int32_t slot) {
 int32_t lks_mhd_batch_active(const lks_mhd_batch_t *b) { return b ? b->nactive : -1; }
 int64_t lks_mhd_batch_nodes(const lks_mhd_batch_t *b) { return b ? b->nodes : -1; }
 
+static bool valid_shape(int w, int h) {
+  if (w == 0) return h == 1 || h == 2 || h == 4;
+  const bool ok_w = w == 8 || w == 16 || w == 32 || w == 64 || w == 128 || w == 256;
+  return ok_w && w * h == kTileThreads;
+}
+
 int lks_mhd_batch_set_tile(lks_mhd_batch_t *b, int32_t width_class, int32_t tile_w, int32_t tile_h) {
   clear_error();
-  const bool ok_w = tile_w == 8 || tile_w == 16 || tile_w == 32 || tile_w == 64 ||
-                    tile_w == 128 || tile_w == 256;
-  if (!b || width_class < 0 || width_class >= kWidthClasses || !ok_w ||
-      tile_w * tile_h != kTileThreads) {
-    set_error("invalid width class or tile shape (w in {8..256}, w*h = 256)");
+  if (!b || width_class < 0 || width_class >= kWidthClasses || !valid_shape(tile_w, tile_h)) {
+    set_error("invalid width class or tile shape (w in {8..256} with w*h = 256, or w = 0 with h in {1, 2, 4})");
     return LKS_EINVAL;
   }
-  int tw[kWidthClasses];
+  int tw[kWidthClasses], th[kWidthClasses];
   std::memcpy(tw, b->tile_w, sizeof tw);
+  std::memcpy(th, b->tile_h, sizeof th);
   tw[width_class] = tile_w;
-  if (total_tiles(b, tw) > b->max_tiles) {
+  th[width_class] = tile_h;
+  if (total_tiles(b, tw, th) > b->max_tiles) {
     set_error("tile list capacity exceeded by this shape");
     return LKS_ENOMEM;
   }
   b->tile_w[width_class] = tile_w;
+  b->tile_h[width_class] = tile_h;
   b->dirty = true;
   return LKS_OK;
 }
@@ -795,7 +826,8 @@ int lks_mhd_batch_autotune(lks_mhd_batch_t *b, int32_t trial_steps, int32_t *til
     set_error("invalid batch or trial_steps < 1");
     return LKS_EINVAL;
   }
-  const int cands[6] = {8, 16, 32, 64, 128, 256};
+  const int cand_w[9] = {0, 0, 0, 8, 16, 32, 64, 128, 256};
+  const int cand_h[9] = {1, 2, 4, 32, 16, 8, 4, 2, 1};
   const int rc = with_device(b, [&]() -> int {
     bool present[kWidthClasses] = {false};
     for (const Slot &s : b->slots)
@@ -806,17 +838,24 @@ int lks_mhd_batch_autotune(lks_mhd_batch_t *b, int32_t trial_steps, int32_t *til
     int result = LKS_OK;
     for (int k = 0; k < kWidthClasses && result == LKS_OK; ++k) {
       if (!present[k]) continue;
-      // widths no wider than twice the class's upper width bound
+      // rectangles no wider than twice the class's upper width bound
       const int upper = (k == kWidthClasses - 1) ? 1 << 30 : (8 << k);
+      // the incumbent shape is timed first; a candidate replaces the best so
+      // far only if it is at least 3% faster (trial timings are noisy)
       float best = 1e30f;
-      int best_w = b->tile_w[k];
-      for (int w : cands) {
+      int best_w = b->tile_w[k], best_h = b->tile_h[k];
+      for (int ci = -1; ci < 9; ++ci) {
+        const int w = ci < 0 ? best_w : cand_w[ci], h = ci < 0 ? best_h : cand_h[ci];
+        if (ci >= 0 && w == best_w && h == best_h) continue;
         if (w > 2 * upper && w != 8) continue;
-        int tw[kWidthClasses];
+        int tw[kWidthClasses], th[kWidthClasses];
         std::memcpy(tw, b->tile_w, sizeof tw);
+        std::memcpy(th, b->tile_h, sizeof th);
         tw[k] = w;
-        if (total_tiles(b, tw) > b->max_tiles) continue;
+        th[k] = h;
+        if (total_tiles(b, tw, th) > b->max_tiles) continue;
         b->tile_w[k] = w;
+        b->tile_h[k] = h;
         b->dirty = true;
         // the trial steps advance every channel; an even count keeps the
         // parity, and the steps are counted like any other
@@ -832,12 +871,14 @@ int lks_mhd_batch_autotune(lks_mhd_batch_t *b, int32_t trial_steps, int32_t *til
           result = r;
           break;
         }
-        if (ms < best) {
+        if (ms < 0.97f * best) {
           best = ms;
           best_w = w;
+          best_h = h;
         }
       }
       b->tile_w[k] = best_w;
+      b->tile_h[k] = best_h;
       b->dirty = true;
     }
     (void)hipEventDestroy(e0);
@@ -847,7 +888,7 @@ int lks_mhd_batch_autotune(lks_mhd_batch_t *b, int32_t trial_steps, int32_t *til
   if (tiles_out)
     for (int k = 0; k < kWidthClasses; ++k) {
       tiles_out[2 * k] = b->tile_w[k];
-      tiles_out[2 * k + 1] = kTileThreads / b->tile_w[k];
+      tiles_out[2 * k + 1] = b->tile_h[k];
     }
   return rc;
 }

@@ -126,16 +126,19 @@ def test_autotune_and_tile_shapes_keep_results(P):
     from paper_2112_13930_amd._lib import make_params
     from paper_2112_13930_amd.batch import Batch
     outs = []
-    for mode in ("default", "tuned", "narrow"):
+    for mode in ("default", "tuned", "narrow", "wide-linear"):
         b = Batch("fp32", max_channels=16, max_nodes=300_000)
         slots = [b.admit(make_params(mix_params(i).nx, mix_params(i).ny, **lib_kwargs(mix_params(i), "fp32")))
                  for i in range(len(MIX))]
         if mode == "tuned":
             tiles = b.autotune(trial_steps=4)
-            assert all(w * h == 256 for w, h in tiles)
+            assert all(w * h == 256 or (w == 0 and h in (1, 2, 4)) for w, h in tiles)
         if mode == "narrow":
             for k in range(7):
                 b.set_tile(k, 8, 32)
+        if mode == "wide-linear":
+            for k in range(7):
+                b.set_tile(k, 0, 4)
         b.step(12, graph=True)
         n = b.steps_done(slots[0])
         torch.cuda.synchronize()
