@@ -168,9 +168,12 @@ int lks_mhd_step(lks_mhd_t *h, int64_t nsteps);
 int lks_mhd_set_graph(lks_mhd_t *h, int32_t steps_per_graph);
 
 /* Launch shape of the plain step kernel (tuning): 0 = 256x1 threads in
- * hardware dispatch order (the default, fastest measured on MI355X);
- * 1 = 64x4 and 2 = 128x2 and 3 = 256x1 with consecutive tiles kept on one
- * XCD; 4 = 64x4 in dispatch order.  Results are identical for every shape. */
+ * hardware dispatch order; 1 = 64x4, 2 = 128x2 and 3 = 256x1 with
+ * consecutive tiles kept on one XCD; 4 = 64x4 in dispatch order; 5 and 6 =
+ * 256x1 threads with 2 and 4 consecutive nodes per thread and vector loads
+ * and stores (LKS_EINVAL unless nx is a multiple of 2 resp. 4).  Results are
+ * bitwise identical for every shape.  Default: 5 for FP16_STORE with even
+ * nx, else 0. */
 int lks_mhd_set_launch_shape(lks_mhd_t *h, int32_t shape);
 
 /* Steps taken since create (or since the last load_state). */

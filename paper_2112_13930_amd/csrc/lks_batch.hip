@@ -51,6 +51,14 @@ struct Tile {
   int pad[3];
 };
 
+// Grid of the persistent launch: the next power of two above the tile count,
+// at most LKS_BATCH_BLOCKS_PER_CU blocks per CU (measured: more resident
+// blocks balance uneven tiles better; power-of-two buckets keep a captured
+// graph valid while channels come and go).
+#ifndef LKS_BATCH_BLOCKS_PER_CU
+#define LKS_BATCH_BLOCKS_PER_CU 64
+#endif
+
 constexpr int kTileThreads = 256;
 constexpr int kWidthClasses = 7;
 constexpr int NREDB = 6;
@@ -218,7 +226,7 @@ struct lks_mhd_batch {
   int parity = 0;
   int64_t nodes = 0;
   int nactive = 0;
-  int grid = 0;
+  int grid = 0, grid_cap = 0;
   bool dirty = false;
   hipGraphExec_t gexec = nullptr;
 };
@@ -362,6 +370,16 @@ int rebuild(lks_mhd_batch *b) {
                                hipMemcpyHostToDevice, b->stream));
   LKS_HIP_CHECK(hipStreamSynchronize(b->stream)); // host vectors may change next
   b->dirty = false;
+  int grid = 1;
+  while (grid < nt && grid < b->grid_cap) grid *= 2;
+  if (grid > b->grid_cap) grid = b->grid_cap;
+  if (grid != b->grid) {
+    b->grid = grid; // the captured graph holds the old launch size
+    if (b->gexec) {
+      (void)hipGraphExecDestroy(b->gexec);
+      b->gexec = nullptr;
+    }
+  }
   return LKS_OK;
 }
 
@@ -548,7 +566,8 @@ int lks_mhd_batch_create(int32_t precision, int32_t max_channels, int64_t max_no
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, b->device) == hipSuccess && prop.multiProcessorCount > 0)
     cus = prop.multiProcessorCount;
-  b->grid = cus * 8; // persistent: 8 blocks of 256 threads per CU
+  b->grid_cap = cus * LKS_BATCH_BLOCKS_PER_CU; // persistent blocks of 256 threads
+  b->grid = 1;
   const int rc = with_device(b, [&]() -> int {
     const uint32_t z[2] = {0u, 0u};
     LKS_HIP_CHECK(hipMemcpyAsync(b->d_gctr, z, sizeof z, hipMemcpyHostToDevice, b->stream));

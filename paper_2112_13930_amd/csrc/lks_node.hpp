@@ -150,6 +150,17 @@ __device__ __forceinline__ T round_sr(W v, uint32_t r) {
 }
 
 template <typename S, typename C, bool SR>
+__device__ __forceinline__ S to_store(C v, uint32_t nseed, int plane) {
+  if constexpr (SR) {
+    return round_sr<S, C>(v, plane_bits(nseed, plane));
+  } else {
+    (void)nseed;
+    (void)plane;
+    return static_cast<S>(v);
+  }
+}
+
+template <typename S, typename C, bool SR>
 __device__ __forceinline__ void store(S *__restrict__ p, C v, uint32_t nseed, int plane) {
   if constexpr (SR) {
     __builtin_nontemporal_store(round_sr<S, C>(v, plane_bits(nseed, plane)), p);
@@ -190,47 +201,21 @@ __device__ __forceinline__ C collide_f(C f, C w, C ex, C ey, C rhop, C rho,
   return f + omega * (feq - f) + kappa * S;
 }
 
+// Everything after streaming for one node: wall closure, moments, coupled
+// solve, collision.  f, gx, gy hold the pulled (post-streaming) populations;
+// those that would come from behind a wall are set by the closure (the
+// link-based closure reads the node's own previous values from src).  The
+// 19 new stored values (rounded to S) are returned in out (not for
+// MODE_MOMENTS).
 template <typename S, typename C, int BC, int MODE, bool SR>
-__device__ __forceinline__ void node_update(const Geom &g, const Coef<C> &k,
-                                            const S *__restrict__ src,
-                                            S *__restrict__ dst, int x, int y,
-                                            NodeObs<C> &obs, uint32_t sseed) {
-  const int nx = g.nx;
+__device__ __forceinline__ void node_finish(const Geom &g, const Coef<C> &k,
+                                            const S *__restrict__ src, int x, int y,
+                                            C (&f)[9], C (&gx)[5], C (&gy)[5],
+                                            NodeObs<C> &obs, uint32_t sseed, S (&out)[19]) {
   const long long P = g.plane;
-  const int xm = (x == 0) ? nx - 1 : x - 1;
-  const int xp = (x == nx - 1) ? 0 : x + 1;
   const bool lo = (y == 0);
   const bool hi = (y == g.ny - 1);
   const long long r0 = (long long)y * g.pitch;
-  const long long rm = r0 - g.pitch;
-  const long long rp = r0 + g.pitch;
-
-  // ---- pull streaming: f_a(x) = f~_a(x - e_a) ----
-  C f[9], gx[5], gy[5];
-  f[0] = ld<S, C>(src + r0 + x);
-  f[1] = ld<S, C>(src + 1 * P + r0 + xm);
-  f[3] = ld<S, C>(src + 3 * P + r0 + xp);
-  gx[0] = ld<S, C>(src + 9 * P + r0 + x);
-  gx[1] = ld<S, C>(src + 10 * P + r0 + xm);
-  gx[3] = ld<S, C>(src + 12 * P + r0 + xp);
-  gy[0] = ld<S, C>(src + 14 * P + r0 + x);
-  gy[1] = ld<S, C>(src + 15 * P + r0 + xm);
-  gy[3] = ld<S, C>(src + 17 * P + r0 + xp);
-  if (!lo) {
-    f[2] = ld<S, C>(src + 2 * P + rm + x);
-    f[5] = ld<S, C>(src + 5 * P + rm + xm);
-    f[6] = ld<S, C>(src + 6 * P + rm + xp);
-    gx[2] = ld<S, C>(src + 11 * P + rm + x);
-    gy[2] = ld<S, C>(src + 16 * P + rm + x);
-  }
-  if (!hi) {
-    f[4] = ld<S, C>(src + 4 * P + rp + x);
-    f[7] = ld<S, C>(src + 7 * P + rp + xp);
-    f[8] = ld<S, C>(src + 8 * P + rp + xm);
-    gx[4] = ld<S, C>(src + 13 * P + rp + x);
-    gy[4] = ld<S, C>(src + 18 * P + rp + x);
-  }
-
   // ---- wall closures for the populations entering from a wall ----
   if (BC == BC_LINK) {
     // Half-way bounce-back of f with Ladd's moving-wall term; theta-weighted
@@ -322,21 +307,20 @@ __device__ __forceinline__ void node_update(const Geom &g, const Coef<C> &k,
   if (MODE == MODE_MOMENTS) return;
 
   // ---- collide and store ----
-  const long long o = r0 + x;
-  const uint32_t ns = SR ? node_seed(sseed, (uint32_t)(y * nx + x)) : 0u;
+  const uint32_t ns = SR ? node_seed(sseed, (uint32_t)(y * g.nx + x)) : 0u;
   const C om = k.omega_f, ka = k.kappa_f;
   const C usq15 = C(1.5) * (ux * ux + uy * uy);
   const C uF = ux * Fx + uy * Fy;
   const C w0 = W<C>::w0, w1 = W<C>::w1, w5 = W<C>::w5;
-  store<S, C, SR>(dst + o, collide_f(f[0], w0, C(0), C(0), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), ns, 0);
-  store<S, C, SR>(dst + 1 * P + o, collide_f(f[1], w1, C(1), C(0), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), ns, 1);
-  store<S, C, SR>(dst + 2 * P + o, collide_f(f[2], w1, C(0), C(1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), ns, 2);
-  store<S, C, SR>(dst + 3 * P + o, collide_f(f[3], w1, C(-1), C(0), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), ns, 3);
-  store<S, C, SR>(dst + 4 * P + o, collide_f(f[4], w1, C(0), C(-1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), ns, 4);
-  store<S, C, SR>(dst + 5 * P + o, collide_f(f[5], w5, C(1), C(1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), ns, 5);
-  store<S, C, SR>(dst + 6 * P + o, collide_f(f[6], w5, C(-1), C(1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), ns, 6);
-  store<S, C, SR>(dst + 7 * P + o, collide_f(f[7], w5, C(-1), C(-1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), ns, 7);
-  store<S, C, SR>(dst + 8 * P + o, collide_f(f[8], w5, C(1), C(-1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), ns, 8);
+  out[0] = to_store<S, C, SR>(collide_f(f[0], w0, C(0), C(0), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), ns, 0);
+  out[1] = to_store<S, C, SR>(collide_f(f[1], w1, C(1), C(0), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), ns, 1);
+  out[2] = to_store<S, C, SR>(collide_f(f[2], w1, C(0), C(1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), ns, 2);
+  out[3] = to_store<S, C, SR>(collide_f(f[3], w1, C(-1), C(0), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), ns, 3);
+  out[4] = to_store<S, C, SR>(collide_f(f[4], w1, C(0), C(-1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), ns, 4);
+  out[5] = to_store<S, C, SR>(collide_f(f[5], w5, C(1), C(1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), ns, 5);
+  out[6] = to_store<S, C, SR>(collide_f(f[6], w5, C(-1), C(1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), ns, 6);
+  out[7] = to_store<S, C, SR>(collide_f(f[7], w5, C(-1), C(-1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), ns, 7);
+  out[8] = to_store<S, C, SR>(collide_f(f[8], w5, C(1), C(-1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), ns, 8);
 
   // g^eq_{a i} = W_a [B_i + e_aj (u_j B_i - B_j u_i) / cs2m]  (Sec. IV):
   // with E = u_x B_y - u_y B_x only g_2x, g_4x (-/+ 3E) and g_1y, g_3y (+/- 3E)
@@ -344,16 +328,70 @@ __device__ __forceinline__ void node_update(const Geom &g, const Coef<C> &k,
   const C E3 = C(3) * (ux * by - uy * bx);
   const C wm = k.omega_m;
   const C W0 = W<C>::W0, W1 = W<C>::W1;
-  store<S, C, SR>(dst + 9 * P + o, gx[0] + wm * (W0 * bx - gx[0]), ns, 9);
-  store<S, C, SR>(dst + 10 * P + o, gx[1] + wm * (W1 * bx - gx[1]), ns, 10);
-  store<S, C, SR>(dst + 11 * P + o, gx[2] + wm * (W1 * (bx - E3) - gx[2]), ns, 11);
-  store<S, C, SR>(dst + 12 * P + o, gx[3] + wm * (W1 * bx - gx[3]), ns, 12);
-  store<S, C, SR>(dst + 13 * P + o, gx[4] + wm * (W1 * (bx + E3) - gx[4]), ns, 13);
-  store<S, C, SR>(dst + 14 * P + o, gy[0] + wm * (W0 * byp - gy[0]), ns, 14);
-  store<S, C, SR>(dst + 15 * P + o, gy[1] + wm * (W1 * (byp + E3) - gy[1]), ns, 15);
-  store<S, C, SR>(dst + 16 * P + o, gy[2] + wm * (W1 * byp - gy[2]), ns, 16);
-  store<S, C, SR>(dst + 17 * P + o, gy[3] + wm * (W1 * (byp - E3) - gy[3]), ns, 17);
-  store<S, C, SR>(dst + 18 * P + o, gy[4] + wm * (W1 * byp - gy[4]), ns, 18);
+  out[9] = to_store<S, C, SR>(gx[0] + wm * (W0 * bx - gx[0]), ns, 9);
+  out[10] = to_store<S, C, SR>(gx[1] + wm * (W1 * bx - gx[1]), ns, 10);
+  out[11] = to_store<S, C, SR>(gx[2] + wm * (W1 * (bx - E3) - gx[2]), ns, 11);
+  out[12] = to_store<S, C, SR>(gx[3] + wm * (W1 * bx - gx[3]), ns, 12);
+  out[13] = to_store<S, C, SR>(gx[4] + wm * (W1 * (bx + E3) - gx[4]), ns, 13);
+  out[14] = to_store<S, C, SR>(gy[0] + wm * (W0 * byp - gy[0]), ns, 14);
+  out[15] = to_store<S, C, SR>(gy[1] + wm * (W1 * (byp + E3) - gy[1]), ns, 15);
+  out[16] = to_store<S, C, SR>(gy[2] + wm * (W1 * byp - gy[2]), ns, 16);
+  out[17] = to_store<S, C, SR>(gy[3] + wm * (W1 * (byp - E3) - gy[3]), ns, 17);
+  out[18] = to_store<S, C, SR>(gy[4] + wm * (W1 * byp - gy[4]), ns, 18);
+}
+
+
+template <typename S, typename C, int BC, int MODE, bool SR>
+__device__ __forceinline__ void node_update(const Geom &g, const Coef<C> &k,
+                                            const S *__restrict__ src,
+                                            S *__restrict__ dst, int x, int y,
+                                            NodeObs<C> &obs, uint32_t sseed) {
+  const int nx = g.nx;
+  const long long P = g.plane;
+  const int xm = (x == 0) ? nx - 1 : x - 1;
+  const int xp = (x == nx - 1) ? 0 : x + 1;
+  const bool lo = (y == 0);
+  const bool hi = (y == g.ny - 1);
+  const long long r0 = (long long)y * g.pitch;
+  const long long rm = r0 - g.pitch;
+  const long long rp = r0 + g.pitch;
+
+  // ---- pull streaming: f_a(x) = f~_a(x - e_a) ----
+  C f[9], gx[5], gy[5];
+  f[0] = ld<S, C>(src + r0 + x);
+  f[1] = ld<S, C>(src + 1 * P + r0 + xm);
+  f[3] = ld<S, C>(src + 3 * P + r0 + xp);
+  gx[0] = ld<S, C>(src + 9 * P + r0 + x);
+  gx[1] = ld<S, C>(src + 10 * P + r0 + xm);
+  gx[3] = ld<S, C>(src + 12 * P + r0 + xp);
+  gy[0] = ld<S, C>(src + 14 * P + r0 + x);
+  gy[1] = ld<S, C>(src + 15 * P + r0 + xm);
+  gy[3] = ld<S, C>(src + 17 * P + r0 + xp);
+  if (!lo) {
+    f[2] = ld<S, C>(src + 2 * P + rm + x);
+    f[5] = ld<S, C>(src + 5 * P + rm + xm);
+    f[6] = ld<S, C>(src + 6 * P + rm + xp);
+    gx[2] = ld<S, C>(src + 11 * P + rm + x);
+    gy[2] = ld<S, C>(src + 16 * P + rm + x);
+  }
+  if (!hi) {
+    f[4] = ld<S, C>(src + 4 * P + rp + x);
+    f[7] = ld<S, C>(src + 7 * P + rp + xp);
+    f[8] = ld<S, C>(src + 8 * P + rp + xm);
+    gx[4] = ld<S, C>(src + 13 * P + rp + x);
+    gy[4] = ld<S, C>(src + 18 * P + rp + x);
+  }
+
+  NodeObs<C> &o_ = obs;
+  S out[19];
+  node_finish<S, C, BC, MODE, SR>(g, k, src, x, y, f, gx, gy, o_, sseed, out);
+  if constexpr (MODE != MODE_MOMENTS) {
+    const long long o = r0 + x;
+#pragma unroll
+    for (int q = 0; q < 19; ++q) __builtin_nontemporal_store(out[q], dst + q * P + o);
+  } else {
+    (void)dst;
+  }
 }
 
 // ---- FP64 block reduction (deterministic: fixed shuffle and LDS order) ----

@@ -21,12 +21,16 @@ constexpr int NRED = 6; // du2, u2, db2, b2, sum_u, nonfinite
 // Launch shapes of the step kernel: BX x BY threads per block cover a tile
 // of BX x BY nodes; REMAP maps consecutive tiles onto the same XCD (the
 // hardware deals workgroups round-robin to the 8 XCDs).
+// vx > 1: each thread updates vx consecutive nodes of a row with vector loads
+// and stores (needs nx % vx == 0; only the plain step uses these shapes).
 struct Shape {
   int bx, by;
   bool remap;
+  int vx;
 };
-constexpr Shape kShapes[] = {{256, 1, false}, {64, 4, true}, {128, 2, true},
-                             {256, 1, true}, {64, 4, false}};
+constexpr Shape kShapes[] = {{256, 1, false, 1}, {64, 4, true, 1}, {128, 2, true, 1},
+                             {256, 1, true, 1},  {64, 4, false, 1}, {256, 1, false, 2},
+                             {256, 1, false, 4}};
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 constexpr int kRedShape = 1; // shape used by record/residual/moments kernels
 
@@ -106,6 +110,95 @@ __global__ __launch_bounds__(BX *BY) void k_step(Geom g, Coef<C> k,
   }
 }
 
+// Plain step with VX consecutive nodes per thread: the unshifted planes are
+// read and all planes written as VX-wide vectors; an x-shifted plane needs
+// one more element beyond the vector (x0 - 1 or x0 + VX, wrapped), read as a
+// scalar.  Per node the arithmetic is node_finish, as in k_step, so the
+// results are bitwise those of the scalar kernel.
+template <typename S, typename C, int BC, int VX>
+__global__ __launch_bounds__(256) void k_step_vec(Geom g, Coef<C> k, const S *__restrict__ src,
+                                                  S *__restrict__ dst, int tiles_x, int ntiles,
+                                                  uint32_t *__restrict__ ctr, int parity) {
+  using V = S __attribute__((ext_vector_type(VX)));
+  constexpr bool SR = kUseSR<S, C>;
+  const uint32_t step = ctr[parity];
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctr[parity ^ 1] = step + 1u;
+  const uint32_t sseed = SR ? step_seed(step) : 0u;
+  const int tile = blockIdx.x;
+  if (tile >= ntiles) return;
+  const int y = tile / tiles_x;
+  const int tx = tile - y * tiles_x;
+  const int x0 = (tx * 256 + (int)threadIdx.x) * VX;
+  if (x0 >= g.nx) return;
+  const int nx = g.nx;
+  const long long P = g.plane;
+  const bool lo = (y == 0), hi = (y == g.ny - 1);
+  const long long r0 = (long long)y * g.pitch, rm = r0 - g.pitch, rp = r0 + g.pitch;
+  const int xm0 = (x0 == 0) ? nx - 1 : x0 - 1;     // x - 1 of the first node
+  const int xpe = (x0 + VX == nx) ? 0 : x0 + VX;    // x + 1 of the last node
+  auto vld = [&](long long off) { return *reinterpret_cast<const V *>(src + off); };
+  const V a0 = vld(r0 + x0), a1 = vld(P + r0 + x0), a3 = vld(3 * P + r0 + x0);
+  const S e1 = src[P + r0 + xm0], e3 = src[3 * P + r0 + xpe];
+  const V b0 = vld(9 * P + r0 + x0), b1 = vld(10 * P + r0 + x0), b3 = vld(12 * P + r0 + x0);
+  const S eb1 = src[10 * P + r0 + xm0], eb3 = src[12 * P + r0 + xpe];
+  const V c0 = vld(14 * P + r0 + x0), c1 = vld(15 * P + r0 + x0), c3 = vld(17 * P + r0 + x0);
+  const S ec1 = src[15 * P + r0 + xm0], ec3 = src[17 * P + r0 + xpe];
+  V a2{}, a5{}, a6{}, b2{}, c2{}, a4{}, a7{}, a8{}, b4{}, c4{};
+  S e5{}, e6{}, e7{}, e8{};
+  if (!lo) {
+    a2 = vld(2 * P + rm + x0);
+    a5 = vld(5 * P + rm + x0);
+    a6 = vld(6 * P + rm + x0);
+    e5 = src[5 * P + rm + xm0];
+    e6 = src[6 * P + rm + xpe];
+    b2 = vld(11 * P + rm + x0);
+    c2 = vld(16 * P + rm + x0);
+  }
+  if (!hi) {
+    a4 = vld(4 * P + rp + x0);
+    a7 = vld(7 * P + rp + x0);
+    a8 = vld(8 * P + rp + x0);
+    e7 = src[7 * P + rp + xpe];
+    e8 = src[8 * P + rp + xm0];
+    b4 = vld(13 * P + rp + x0);
+    c4 = vld(18 * P + rp + x0);
+  }
+  V outv[19];
+#pragma unroll
+  for (int v = 0; v < VX; ++v) {
+    // pulled populations of node x0 + v: x - 1 planes take element v - 1
+    // (or the extra scalar for v = 0), x + 1 planes element v + 1
+    C f[9], gx[5], gy[5];
+    f[0] = (C)a0[v];
+    f[1] = (C)(v == 0 ? e1 : a1[v > 0 ? v - 1 : 0]);
+    f[3] = (C)(v == VX - 1 ? e3 : a3[v < VX - 1 ? v + 1 : 0]);
+    f[2] = (C)a2[v];
+    f[5] = (C)(v == 0 ? e5 : a5[v > 0 ? v - 1 : 0]);
+    f[6] = (C)(v == VX - 1 ? e6 : a6[v < VX - 1 ? v + 1 : 0]);
+    f[4] = (C)a4[v];
+    f[7] = (C)(v == VX - 1 ? e7 : a7[v < VX - 1 ? v + 1 : 0]);
+    f[8] = (C)(v == 0 ? e8 : a8[v > 0 ? v - 1 : 0]);
+    gx[0] = (C)b0[v];
+    gx[1] = (C)(v == 0 ? eb1 : b1[v > 0 ? v - 1 : 0]);
+    gx[3] = (C)(v == VX - 1 ? eb3 : b3[v < VX - 1 ? v + 1 : 0]);
+    gx[2] = (C)b2[v];
+    gx[4] = (C)b4[v];
+    gy[0] = (C)c0[v];
+    gy[1] = (C)(v == 0 ? ec1 : c1[v > 0 ? v - 1 : 0]);
+    gy[3] = (C)(v == VX - 1 ? ec3 : c3[v < VX - 1 ? v + 1 : 0]);
+    gy[2] = (C)c2[v];
+    gy[4] = (C)c4[v];
+    NodeObs<C> o{};
+    S out[19];
+    node_finish<S, C, BC, MODE_STEP, SR>(g, k, src, x0 + v, y, f, gx, gy, o, sseed, out);
+#pragma unroll
+    for (int q = 0; q < 19; ++q) outv[q][v] = out[q];
+  }
+#pragma unroll
+  for (int q = 0; q < 19; ++q)
+    __builtin_nontemporal_store(outv[q], reinterpret_cast<V *>(dst + q * P + r0 + x0));
+}
+
 // Fixed-order sum of per-tile partials (one block of 256 threads).
 __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ partials,
                                                   int ntiles, double *__restrict__ out) {
@@ -174,10 +267,18 @@ template <> const Coef<float> &coef_of<float>(const lks_mhd *h) { return h->kf; 
 template <typename S, typename C, int BC, int MODE, int SH>
 hipError_t launch_shape(lks_mhd *h, const void *src, void *dst, ObsOut oo) {
   constexpr Shape s = kShapes[SH];
+  const Coef<C> &k = coef_of<C>(h);
+  if constexpr (s.vx > 1 && MODE == MODE_STEP) {
+    const int tiles_x = (h->geom.nx + s.bx * s.vx - 1) / (s.bx * s.vx);
+    const int ntiles = tiles_x * h->geom.ny;
+    hipLaunchKernelGGL((k_step_vec<S, C, BC, s.vx>), dim3(ntiles), dim3(s.bx), 0, h->stream,
+                       h->geom, k, static_cast<const S *>(src), static_cast<S *>(dst), tiles_x,
+                       ntiles, h->ctr, h->cur);
+    return hipGetLastError();
+  }
   const int tiles_x = (h->geom.nx + s.bx - 1) / s.bx;
   const int ntiles = tiles_x * ((h->geom.ny + s.by - 1) / s.by);
   const int grid = grid_for(ntiles, s.remap);
-  const Coef<C> &k = coef_of<C>(h);
   hipLaunchKernelGGL((k_step<S, C, BC, MODE, s.bx, s.by, s.remap>), dim3(grid),
                      dim3(s.bx, s.by), 0, h->stream, h->geom, k,
                      static_cast<const S *>(src), static_cast<S *>(dst), tiles_x,
@@ -192,7 +293,9 @@ hipError_t launch_bc(lks_mhd *h, int shape, const void *src, void *dst, ObsOut o
   case 1: return launch_shape<S, C, BC, MODE, 1>(h, src, dst, oo);
   case 2: return launch_shape<S, C, BC, MODE, 2>(h, src, dst, oo);
   case 3: return launch_shape<S, C, BC, MODE, 3>(h, src, dst, oo);
-  default: return launch_shape<S, C, BC, MODE, 4>(h, src, dst, oo);
+  case 4: return launch_shape<S, C, BC, MODE, 4>(h, src, dst, oo);
+  case 5: return launch_shape<S, C, BC, MODE, 5>(h, src, dst, oo);
+  default: return launch_shape<S, C, BC, MODE, 6>(h, src, dst, oo);
   }
 }
 
@@ -339,7 +442,8 @@ int lks_mhd_create(const lks_mhd_params *p, void *dev_buf, size_t bytes,
   h->red_ntiles = L.red_ntiles;
   h->kd = make_coef<double>(c);
   h->kf = make_coef<float>(c);
-  h->shape = 0;
+  // binary16 planes: two nodes per thread (4-byte accesses) measured fastest
+  h->shape = (c.p.precision == LKS_FP16_STORE && c.p.nx % 2 == 0) ? 5 : 0;
   rc = with_device(h, [&]() -> int {
     const int grid = elementwise_grid(h);
     switch (c.p.precision) {
@@ -375,6 +479,11 @@ int lks_mhd_set_launch_shape(lks_mhd_t *h, int32_t shape) {
   clear_error();
   if (!h || shape < 0 || shape >= kNumShapes) {
     set_error("shape must be in [0, %d)", kNumShapes);
+    return LKS_EINVAL;
+  }
+  if (h->ch.p.nx % kShapes[shape].vx != 0) {
+    set_error("shape %d updates %d nodes per thread and needs nx %% %d == 0", shape,
+              kShapes[shape].vx, kShapes[shape].vx);
     return LKS_EINVAL;
   }
   if (h->shape != shape) drop_graphs(h);

@@ -117,7 +117,7 @@ def test_launch_shapes_and_graph_bitwise(P, precision):
                c_lo=0.2, c_hi=math.inf, u_hi=0.03)
     s0 = torch.from_numpy(random_populations(300, 37, seed=11))
     ref = None
-    for shape in range(5):
+    for shape in range(7):
         ch = gpu_channel(P, p, precision, stream=torch.cuda.Stream())
         ch.set_launch_shape(shape)
         ch.load_state(s0)
