@@ -49,19 +49,27 @@ typedef struct lks_mhd_batch lks_mhd_batch_t; /* many channels, library-owned */
 enum lks_bc { LKS_BC_LINK = 0, LKS_BC_MOMENT = 1 };
 
 /* Storage precision of the populations.
- *   FP64        stored as binary64, computed in FP64, rounded to nearest.
- *   FP32        stored as binary32 and computed in FP64; each stored value is
- *               rounded stochastically to one of its two binary32 neighbours.
- *   FP16_STORE  stored as binary16 and computed in FP32, rounded
- *               stochastically to binary16.
+ *   FP64           stored as binary64, computed in FP64, rounded to nearest.
+ *   FP32           stored as binary32 and computed in FP64; each stored value
+ *                  is rounded stochastically to one of its two binary32
+ *                  neighbours.
+ *   FP16_STORE     stored as binary16 and computed in FP64, rounded
+ *                  stochastically to binary16.
+ *   FP16_STORE_F32 stored as binary16 and computed in FP32 (faster; the FP32
+ *                  arithmetic leaves a systematic residual that slow modes of
+ *                  strongly coupled channels amplify beyond 2e-3 relative).
  * Every population is stored as its deviation from the rest state at unit
  * density with B = (0, B0): f_alpha - w_alpha, g_alpha,x and
- * g_alpha,y - W_alpha B0.  The random bits of stochastic rounding are a
+ * g_alpha,y - W_alpha B0.  Binary16 storage further subtracts a per-row
+ * reference R[y][alpha] held in the compute type, zero until a rebase
+ * (lks_mhd_rebase) moves each row's mean over x into it, so binary16 then
+ * carries only the x-variation and the change since the last rebase.  The random bits of stochastic
+ * rounding are a
  * counter-based hash of (step since create or load, node, plane): a run is
  * reproducible bit for bit and does not depend on launch shape or on the
  * other channels of a batch.  Steady-state reductions are FP64 in every
  * mode. */
-enum lks_precision { LKS_FP64 = 0, LKS_FP32 = 1, LKS_FP16_STORE = 2 };
+enum lks_precision { LKS_FP64 = 0, LKS_FP32 = 1, LKS_FP16_STORE = 2, LKS_FP16_STORE_F32 = 3 };
 
 enum lks_status {
   LKS_OK = 0,
@@ -190,7 +198,8 @@ int64_t lks_mhd_steps_done(const lks_mhd_t *h);
  * window keeps the rounding noise of stochastically rounded storage, which
  * does not accumulate, from masking a steady state.)  Stops at R < tol
  * (LKS_OK), at max_steps (LKS_ENOTCONV) or on a non-finite value
- * (LKS_EUNSTABLE).  Synchronous.  *steps_done and *residual (either may be
+ * (LKS_EUNSTABLE).  FP16_STORE states are rebased (lks_mhd_rebase) at the
+ * start of every window.  Synchronous.  *steps_done and *residual (either may be
  * NULL) receive the totals reached in every case; *flow_rate (may be NULL)
  * receives sum(u_x)/nx of phi(n).
  */
@@ -213,6 +222,21 @@ int lks_mhd_moments(lks_mhd_t *h, double *rho, double *ux, double *uy,
 int lks_mhd_save_state(lks_mhd_t *h, double *dev_pops);
 int lks_mhd_load_state(lks_mhd_t *h, const double *dev_pops, int64_t steps);
 
+/* Rebase a binary16 state: for each row y and plane alpha, move the mean
+ * over x of the stored values into the row reference and re-encode the row
+ * against it (stochastic rounding; the random bits hash the steps taken and
+ * the node).  The populations the state decodes to change only by that
+ * rounding.  A no-op for FP64 and FP32 storage.  Asynchronous. */
+int lks_mhd_rebase(lks_mhd_t *h);
+
+/* lks_mhd_step rebases a binary16 state before a step whenever steps_done is
+ * a multiple of `every` (default 1000; 0 switches this off; graph replays
+ * stop at those points).  run_to_steady does not apply this interval: it
+ * rebases at the start of each of its windows instead.  With every = K,
+ * plain stepping reproduces bit for bit the states of run_to_steady or batch
+ * windows of K steps.  Ignored for FP64 and FP32 storage. */
+int lks_mhd_set_rebase(lks_mhd_t *h, int64_t every);
+
 /* Algorithmic HBM bytes of one step per node (19 populations read and
  * written) for a precision: 304, 152 or 76. */
 int lks_mhd_bytes_per_node(int32_t precision);
@@ -223,8 +247,8 @@ int lks_mhd_bytes_per_node(int32_t precision);
 
 /*
  * Create a batch over a caller-owned device pool (>= 256-byte aligned).  All
- * channels share one precision (LKS_FP32 or LKS_FP16_STORE or LKS_FP64).
- * max_channels bounds the slot table.  The library allocates no device
+ * channels share one precision (any lks_precision).
+ * max_channels (1..65535) bounds the slot table.  The library allocates no device
  * memory: slot table, tile list and reduction scratch are carved from the
  * pool's front (lks_mhd_batch_overhead_bytes), channel states from the rest.
  */
@@ -275,13 +299,18 @@ int lks_mhd_batch_step(lks_mhd_batch_t *b, int64_t nsteps, int32_t use_graph);
 
 /* Advance nsteps >= 2 steps as one residual window (the first step records,
  * the last reduces the per-channel residual; definition as in
- * lks_mhd_run_to_steady with K = nsteps).  Writes
+ * lks_mhd_run_to_steady with K = nsteps; binary16 states are rebased at the
+ * window's start).  Writes
  * per-slot residuals to residuals[max_channels] and per-slot flags (1 =
  * non-finite) to unstable[max_channels] (host arrays; entries of empty slots
  * are NaN / 0).  Synchronous. */
 int lks_mhd_batch_step_check(lks_mhd_batch_t *b, int64_t nsteps,
                              int32_t use_graph, double *residuals,
                              int32_t *unstable);
+
+/* Rebase every active binary16 channel (as lks_mhd_rebase; no-op for the
+ * other precisions).  Asynchronous. */
+int lks_mhd_batch_rebase(lks_mhd_batch_t *b);
 
 /* Steps the slot has taken since admission. */
 int64_t lks_mhd_batch_steps_done(const lks_mhd_batch_t *b, int32_t slot);

@@ -14,11 +14,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblks_mhd.so")
 
 LKS_BC_LINK, LKS_BC_MOMENT = 0, 1
-LKS_FP64, LKS_FP32, LKS_FP16_STORE = 0, 1, 2
+LKS_FP64, LKS_FP32, LKS_FP16_STORE, LKS_FP16_STORE_F32 = 0, 1, 2, 3
 LKS_OK, LKS_EINVAL, LKS_ENOMEM, LKS_EDEVICE, LKS_EUNSTABLE, LKS_ENOTCONV = 0, -1, -2, -3, -4, -5
 STATUS_NAMES = {0: "LKS_OK", -1: "LKS_EINVAL", -2: "LKS_ENOMEM", -3: "LKS_EDEVICE",
                 -4: "LKS_EUNSTABLE", -5: "LKS_ENOTCONV"}
-PRECISIONS = {"fp64": LKS_FP64, "fp32": LKS_FP32, "fp16": LKS_FP16_STORE}
+# binary16 storage computed in FP64 ("fp16") or in FP32 ("fp16_f32")
+PRECISIONS = {"fp64": LKS_FP64, "fp32": LKS_FP32, "fp16": LKS_FP16_STORE,
+              "fp16_f32": LKS_FP16_STORE_F32}
+STORE_BYTES = {"fp64": 8, "fp32": 4, "fp16": 2, "fp16_f32": 2}
 BCS = {"link": LKS_BC_LINK, "moment": LKS_BC_MOMENT}
 
 
@@ -73,6 +76,8 @@ SIGNATURES = {
     "lks_mhd_moments": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "lks_mhd_save_state": (_c.c_int, [_vp, _vp]),
     "lks_mhd_load_state": (_c.c_int, [_vp, _vp, _c.c_int64]),
+    "lks_mhd_rebase": (_c.c_int, [_vp]),
+    "lks_mhd_set_rebase": (_c.c_int, [_vp, _c.c_int64]),
     "lks_mhd_bytes_per_node": (_c.c_int, [_c.c_int32]),
     "lks_mhd_batch_overhead_bytes": (_c.c_size_t, [_c.c_int32, _c.c_int64]),
     "lks_mhd_batch_create": (_c.c_int, [_c.c_int32, _c.c_int32, _c.c_int64, _vp, _c.c_size_t, _vp,
@@ -87,6 +92,7 @@ SIGNATURES = {
     "lks_mhd_batch_autotune": (_c.c_int, [_vp, _c.c_int32, _i32p]),
     "lks_mhd_batch_step": (_c.c_int, [_vp, _c.c_int64, _c.c_int32]),
     "lks_mhd_batch_step_check": (_c.c_int, [_vp, _c.c_int64, _c.c_int32, _dp, _i32p]),
+    "lks_mhd_batch_rebase": (_c.c_int, [_vp]),
     "lks_mhd_batch_steps_done": (_c.c_int64, [_vp, _c.c_int32]),
     "lks_mhd_batch_moments": (_c.c_int, [_vp, _c.c_int32, _vp, _vp, _vp, _vp, _vp, _vp]),
     "lks_mhd_batch_save_state": (_c.c_int, [_vp, _c.c_int32, _vp]),

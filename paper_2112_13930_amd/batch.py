@@ -10,7 +10,7 @@ import ctypes
 import numpy as np
 import torch
 
-from ._lib import PRECISIONS, LksParams, check, lib, make_params
+from ._lib import PRECISIONS, STORE_BYTES, LksParams, check, lib, make_params
 
 
 def _ptr(t):
@@ -27,8 +27,9 @@ class Batch:
         self.device = torch.device(device)
         overhead = lib().lks_mhd_batch_overhead_bytes(self.max_channels, int(max_nodes))
         if pool_bytes is None:
-            per_node = 2 * 19 * {"fp64": 8, "fp32": 4, "fp16": 2}[precision] + 16
+            per_node = 2 * 19 * STORE_BYTES[precision] + 16
             pool_bytes = overhead + int(max_nodes) * per_node + self.max_channels * 4 * 256 * 19
+            pool_bytes += int(max_nodes) * 19 * 8 // 4 + self.max_channels * 256  # row references
         self.pool_bytes = int(pool_bytes)
         self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
         self._pool = torch.empty(self.pool_bytes, dtype=torch.uint8, device=self.device)
@@ -103,6 +104,10 @@ class Batch:
 
     def step(self, n: int, graph: bool = True):
         check(lib().lks_mhd_batch_step(self._h, int(n), int(bool(graph))), "lks_mhd_batch_step")
+
+    def rebase(self):
+        """Row rebase of every active binary16 channel (no-op otherwise)."""
+        check(lib().lks_mhd_batch_rebase(self._h), "lks_mhd_batch_rebase")
 
     def step_check(self, n: int, graph: bool = True):
         """Advance n >= 2 steps; returns (residuals, unstable) per slot."""

@@ -70,6 +70,15 @@ class Channel:
     def set_graph(self, steps_per_graph: int):
         check(lib().lks_mhd_set_graph(self._h, int(steps_per_graph)), "lks_mhd_set_graph")
 
+    def rebase(self):
+        """Move each row's x-mean of a binary16 state into its FP32 row
+        reference (no-op for FP64/FP32 storage)."""
+        check(lib().lks_mhd_rebase(self._h), "lks_mhd_rebase")
+
+    def set_rebase(self, every: int):
+        """Rebase binary16 states before steps at multiples of `every` (0: off)."""
+        check(lib().lks_mhd_set_rebase(self._h, int(every)), "lks_mhd_set_rebase")
+
     def set_launch_shape(self, shape: int):
         check(lib().lks_mhd_set_launch_shape(self._h, int(shape)), "lks_mhd_set_launch_shape")
 

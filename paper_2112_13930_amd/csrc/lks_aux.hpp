@@ -1,6 +1,6 @@
-// Element-wise helper kernels shared by the single-channel and batched
-// paths: rest-state initialisation and conversion between the stored state
-// and raw FP64 populations [19][ny][nx].
+// Helper kernels shared by the single-channel and batched paths: rest-state
+// initialisation, conversion between the stored state and raw FP64
+// populations [19][ny][nx], and the row rebase of binary16 states.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -27,8 +27,9 @@ __global__ void k_init(Geom g, double rho0, S *__restrict__ dst) {
 }
 
 // Stored state <-> raw FP64 populations [19][ny][nx].
-template <typename S>
-__global__ void k_save(Geom g, double b0, const S *__restrict__ src, double *__restrict__ out) {
+template <typename S, typename C>
+__global__ void k_save(Geom g, double b0, const S *__restrict__ src, const C *__restrict__ D,
+                       double *__restrict__ out) {
   const long long n = (long long)g.nx * g.ny;
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -37,7 +38,7 @@ __global__ void k_save(Geom g, double b0, const S *__restrict__ src, double *__r
   const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
   const double Wm[5] = {1.0 / 3, 1.0 / 6, 1.0 / 6, 1.0 / 6, 1.0 / 6};
   for (int q = 0; q < 19; ++q) {
-    const double v = (double)src[q * g.plane + o];
+    const double v = (double)dec<S, C>((C)src[q * g.plane + o], D + (long long)y * 19, q);
     out[q * n + i] = q < 9 ? v + w[q] : (q < 14 ? v : v + Wm[q - 14] * b0);
   }
 }
@@ -55,6 +56,66 @@ __global__ void k_load(Geom g, double b0, const double *__restrict__ in, S *__re
     const double v = in[q * n + i];
     dst[q * g.plane + o] = (S)(q < 9 ? v - w[q] : (q < 14 ? v : v - Wm[q - 14] * b0));
   }
+}
+
+template <typename T>
+__global__ void k_zero(T *__restrict__ p, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = T(0);
+}
+
+// Rebase one row of a binary16 state: move the x-mean of every plane's
+// stored values into the row's reference (compute type) and re-encode the
+// row against it.  Decoded populations keep their values up to one rounding
+// of stored values that no longer carry the row's mean, so the storage
+// precision is spent on the x-variation alone.  One 256-thread block;
+// lds holds 4 * 19 + 19 doubles.
+template <typename S, typename C, bool SR>
+__device__ __forceinline__ void rebase_row(S *__restrict__ buf, C *__restrict__ Drow,
+                                           const Geom &g, int y, uint32_t seed, double *lds) {
+  const int tid = threadIdx.x;
+  const long long r0 = (long long)y * g.pitch;
+  double acc[19];
+#pragma unroll
+  for (int q = 0; q < 19; ++q) acc[q] = 0.0;
+  for (int x = tid; x < g.nx; x += 256)
+#pragma unroll
+    for (int q = 0; q < 19; ++q) acc[q] += (double)buf[q * g.plane + r0 + x];
+  wave_sum<19>(acc);
+  if ((tid & 63) == 0)
+#pragma unroll
+    for (int q = 0; q < 19; ++q) lds[(tid >> 6) * 19 + q] = acc[q];
+  __syncthreads();
+  if (tid < 19) {
+    // new reference and the shift it represents, both in the compute type
+    const C m = (C)(((lds[tid] + lds[19 + tid]) + (lds[38 + tid] + lds[57 + tid])) / g.nx);
+    const C Dn = Drow[tid] + m;
+    const C shift = Dn - Drow[tid];
+    Drow[tid] = Dn;
+    lds[76 + tid] = (double)shift;
+  }
+  __syncthreads();
+  C sh[19];
+#pragma unroll
+  for (int q = 0; q < 19; ++q) sh[q] = (C)lds[76 + q];
+  for (int x = tid; x < g.nx; x += 256) {
+    const uint32_t ns = SR ? node_seed(seed, (uint32_t)(y * g.nx + x)) : 0u;
+#pragma unroll
+    for (int q = 0; q < 19; ++q) {
+      S *p = buf + q * g.plane + r0 + x;
+      *p = to_store<S, C, SR>((C)*p - sh[q], ns, q);
+    }
+  }
+  __syncthreads(); // lds is reused by the next row
+}
+
+// Single channel: one block per row.
+template <typename S, typename C>
+__global__ __launch_bounds__(256) void k_rebase_rows(Geom g, S *__restrict__ buf,
+                                                     C *__restrict__ D, uint32_t step) {
+  __shared__ double lds[5 * 19];
+  rebase_row<S, C, kUseSR<S, C>>(buf, D + (long long)blockIdx.x * 19, g, (int)blockIdx.x,
+                                 rebase_seed(step), lds);
 }
 
 } // namespace lks

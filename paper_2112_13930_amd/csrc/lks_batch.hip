@@ -4,7 +4,8 @@
 // Pool layout (caller-owned device memory):
 //   [channel descriptors][tile list][tile count][per-tile partials]
 //   [per-slot sums][channel states ...]
-// A channel's region holds its two population buffers and its record buffer.
+// A channel's region holds its two population buffers, its record buffer and
+// its row references.
 // The step kernel reads the tile count and the descriptors from device
 // memory, so admitting or retiring channels rewrites that memory and never
 // needs a new launch configuration: a captured two-step graph stays valid.
@@ -29,6 +30,7 @@ namespace lks {
 struct ChanDesc {
   void *buf[2];
   double *rec;
+  void *ref; // row references [ny][19] of the compute type
   Geom g;
   int bc;
   int phase;      // buffer holding the state when the global parity is 0
@@ -90,10 +92,11 @@ __global__ __launch_bounds__(kTileThreads) void k_batch_step(
     double v[NREDB] = {0, 0, 0, 0, 0, 0};
     auto one = [&](int x, int y) {
       NodeObs<C> o{};
+      const C *ref = static_cast<const C *>(c.ref);
       if (c.bc == BC_LINK)
-        node_update<S, C, BC_LINK, MODE, SR>(c.g, coef_of<C>(c), src, dst, x, y, o, sseed);
+        node_update<S, C, BC_LINK, MODE, SR>(c.g, coef_of<C>(c), src, ref, dst, x, y, o, sseed);
       else
-        node_update<S, C, BC_MOMENT, MODE, SR>(c.g, coef_of<C>(c), src, dst, x, y, o, sseed);
+        node_update<S, C, BC_MOMENT, MODE, SR>(c.g, coef_of<C>(c), src, ref, dst, x, y, o, sseed);
       const long long i = (long long)y * c.g.nx + x;
       if constexpr (MODE == MODE_RECORD) {
         c.rec[i] = (double)o.ux;
@@ -161,19 +164,35 @@ struct ObsOutB {
 
 template <typename S, typename C, int BC>
 __global__ __launch_bounds__(256) void k_chan_moments(Geom g, Coef<C> k, const S *__restrict__ src,
-                                                      ObsOutB oo) {
+                                                      const C *__restrict__ ref, ObsOutB oo) {
   const long long n = (long long)g.nx * g.ny;
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int y = (int)(i / g.nx), x = (int)(i - (long long)y * g.nx);
   NodeObs<C> o{};
-  node_update<S, C, BC, MODE_MOMENTS, false>(g, k, src, nullptr, x, y, o, 0u);
+  node_update<S, C, BC, MODE_MOMENTS, false>(g, k, src, ref, nullptr, x, y, o, 0u);
   if (oo.rho) oo.rho[i] = 1.0 + (double)o.rhop;
   if (oo.ux) oo.ux[i] = (double)o.ux;
   if (oo.uy) oo.uy[i] = (double)o.uy;
   if (oo.bx) oo.bx[i] = (double)o.bx;
   if (oo.by) oo.by[i] = (double)o.by;
   if (oo.jz) oo.jz[i] = (double)o.jz;
+}
+
+// Row rebase of every active binary16 channel: block (row, slot).
+template <typename S, typename C>
+__global__ __launch_bounds__(256) void k_batch_rebase(const ChanDesc *__restrict__ chans,
+                                                      const int *__restrict__ active, int parity,
+                                                      const uint32_t *__restrict__ gctr) {
+  __shared__ double lds[5 * 19];
+  const int slot = blockIdx.y, y = blockIdx.x;
+  if (!active[slot]) return;
+  const ChanDesc &c = chans[slot];
+  if (y >= c.g.ny) return;
+  const int cur = parity ^ c.phase;
+  rebase_row<S, C, kUseSR<S, C>>(static_cast<S *>(c.buf[cur]),
+                                 static_cast<C *>(c.ref) + (long long)y * 19, c.g, y,
+                                 rebase_seed(gctr[parity] - c.step_base), lds);
 }
 
 } // namespace lks
@@ -266,7 +285,8 @@ size_t channel_region_bytes(const Channel &c, int precision) {
   const long long plane = plane_elems(c.p.nx, c.p.ny, precision);
   const size_t state = align256((size_t)19 * plane * elem_bytes(precision));
   const size_t rec = align256((size_t)2 * c.p.nx * c.p.ny * sizeof(double));
-  return 2 * state + rec;
+  const size_t ref = align256((size_t)c.p.ny * 19 * sizeof(double));
+  return 2 * state + rec + ref;
 }
 
 template <typename C> const Coef<C> &coef_host(const ChanDesc &d);
@@ -385,19 +405,12 @@ int rebuild(lks_mhd_batch *b) {
 
 template <int MODE>
 hipError_t launch_batch(lks_mhd_batch *b, int parity) {
-  switch (b->precision) {
-  case LKS_FP64:
-    hipLaunchKernelGGL((k_batch_step<double, double, MODE>), dim3(b->grid), dim3(kTileThreads), 0,
-                       b->stream, b->d_chans, b->d_tiles, b->d_ntiles, parity, b->d_partials, b->d_gctr);
-    break;
-  case LKS_FP32:
-    hipLaunchKernelGGL((k_batch_step<float, Fp32Compute, MODE>), dim3(b->grid), dim3(kTileThreads), 0,
-                       b->stream, b->d_chans, b->d_tiles, b->d_ntiles, parity, b->d_partials, b->d_gctr);
-    break;
-  default:
-    hipLaunchKernelGGL((k_batch_step<_Float16, float, MODE>), dim3(b->grid), dim3(kTileThreads), 0,
-                       b->stream, b->d_chans, b->d_tiles, b->d_ntiles, parity, b->d_partials, b->d_gctr);
-  }
+  dispatch_precision(b->precision, [&](auto t) {
+    using S = typename decltype(t)::S;
+    using C = typename decltype(t)::C;
+    hipLaunchKernelGGL((k_batch_step<S, C, MODE>), dim3(b->grid), dim3(kTileThreads), 0, b->stream,
+                       b->d_chans, b->d_tiles, b->d_ntiles, parity, b->d_partials, b->d_gctr);
+  });
   return hipGetLastError();
 }
 
@@ -448,6 +461,30 @@ int sync_counter(lks_mhd_batch *b) {
   const uint32_t v[2] = {(uint32_t)b->global_steps, (uint32_t)b->global_steps};
   LKS_HIP_CHECK(hipMemcpyAsync(b->d_gctr, v, sizeof v, hipMemcpyHostToDevice, b->stream));
   LKS_HIP_CHECK(hipStreamSynchronize(b->stream));
+  return LKS_OK;
+}
+
+// Row rebase of every active channel (binary16 storage only).
+int batch_rebase(lks_mhd_batch *b) {
+  if (!is_binary16(b->precision) || b->nactive == 0) return LKS_OK;
+  if (b->dirty) {
+    const int rc = rebuild(b);
+    if (rc != LKS_OK) return rc;
+  }
+  int max_ny = 1, top = 0;
+  for (int s = 0; s < b->max_channels; ++s)
+    if (b->slots[s].used) {
+      max_ny = std::max(max_ny, b->slots[s].ch.p.ny);
+      top = s + 1;
+    }
+  dispatch_precision(b->precision, [&](auto t) {
+    using S = typename decltype(t)::S;
+    using C = typename decltype(t)::C;
+    if constexpr (kRowRef<S>)
+      hipLaunchKernelGGL((k_batch_rebase<S, C>), dim3(max_ny, top), dim3(256), 0, b->stream,
+                         b->d_chans, b->d_active, b->parity, b->d_gctr);
+  });
+  LKS_HIP_CHECK(hipGetLastError());
   return LKS_OK;
 }
 
@@ -504,7 +541,7 @@ size_t lks_mhd_batch_channel_bytes(const lks_mhd_params *p, int32_t precision) {
   clear_error();
   Channel c;
   if (derive_channel(p, &c) != LKS_OK) return 0;
-  if (precision < LKS_FP64 || precision > LKS_FP16_STORE) return 0;
+  if (!valid_precision(precision)) return 0;
   return channel_region_bytes(c, precision);
 }
 
@@ -512,8 +549,8 @@ int lks_mhd_batch_create(int32_t precision, int32_t max_channels, int64_t max_no
                          void *dev_pool, size_t pool_bytes, void *hip_stream,
                          lks_mhd_batch_t **out) {
   clear_error();
-  if (!out || max_channels <= 0 || max_nodes <= 0 || precision < LKS_FP64 ||
-      precision > LKS_FP16_STORE) {
+  if (!out || max_channels <= 0 || max_channels > 65535 || max_nodes <= 0 ||
+      !valid_precision(precision)) {
     set_error("invalid batch arguments");
     return LKS_EINVAL;
   }
@@ -640,6 +677,7 @@ int lks_mhd_batch_admit(lks_mhd_batch_t *b, const lks_mhd_params *p, int32_t *sl
   d.buf[0] = base;
   d.buf[1] = base + state;
   d.rec = reinterpret_cast<double *>(base + 2 * state);
+  d.ref = base + 2 * state + align256((size_t)2 * q.nx * q.ny * sizeof(double));
   d.g = Geom{q.nx, q.ny, q.nx, plane};
   d.bc = q.bc == LKS_BC_LINK ? BC_LINK : BC_MOMENT;
   // the initial state goes to buf[0]; at the next step the global parity is
@@ -650,11 +688,13 @@ int lks_mhd_batch_admit(lks_mhd_batch_t *b, const lks_mhd_params *p, int32_t *sl
   d.kd = make_coef<double>(c);
   sl.admit_step = b->global_steps;
   rc = with_device(b, [&]() -> int {
-    switch (b->precision) {
-    case LKS_FP64: launch_init<double>(b, sl, d.buf[0]); break;
-    case LKS_FP32: launch_init<float>(b, sl, d.buf[0]); break;
-    default: launch_init<_Float16>(b, sl, d.buf[0]);
-    }
+    dispatch_precision(b->precision, [&](auto t) {
+      launch_init<typename decltype(t)::S>(b, sl, d.buf[0]);
+    });
+    LKS_HIP_CHECK(hipGetLastError());
+    const long long nr = (long long)q.ny * 19;
+    hipLaunchKernelGGL(k_zero<double>, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, b->stream,
+                       static_cast<double *>(d.ref), nr);
     LKS_HIP_CHECK(hipGetLastError());
     return LKS_OK;
   });
@@ -746,7 +786,9 @@ int lks_mhd_batch_step_check(lks_mhd_batch_t *b, int64_t nsteps, int32_t use_gra
     int r = LKS_OK;
     if (b->dirty && (r = rebuild(b)) != LKS_OK) return r;
     if (b->nactive > 0) {
-      // the first step of the window records phi, the last compares
+      // the first step of the window records phi, the last compares;
+      // binary16 states are rebased at the start of every window
+      if ((r = batch_rebase(b)) != LKS_OK) return r;
       if ((r = batch_one(b, MODE_RECORD)) != LKS_OK) return r;
       if ((r = batch_steps(b, nsteps - 2, use_graph != 0)) != LKS_OK) return r;
       if ((r = batch_one(b, MODE_RESIDUAL)) != LKS_OK) return r;
@@ -781,6 +823,15 @@ int lks_mhd_batch_step_check(lks_mhd_batch_t *b, int64_t nsteps, int32_t use_gra
   return LKS_OK;
 }
 
+int lks_mhd_batch_rebase(lks_mhd_batch_t *b) {
+  clear_error();
+  if (!b) {
+    set_error("invalid batch");
+    return LKS_EINVAL;
+  }
+  return with_device(b, [&]() -> int { return batch_rebase(b); });
+}
+
 int64_t lks_mhd_batch_steps_done(const lks_mhd_batch_t *b, int32_t slot) {
   if (!b || slot < 0 || slot >= b->max_channels || !b->slots[slot].used) return -1;
   return b->global_steps - b->slots[slot].admit_step;
@@ -800,19 +851,18 @@ int lks_mhd_batch_moments(lks_mhd_batch_t *b, int32_t slot, double *rho, double 
   const dim3 grid((unsigned)((n + 255) / 256));
   return with_device(b, [&]() -> int {
     const bool link = d.bc == BC_LINK;
-    switch (b->precision) {
-    case LKS_FP64:
-      if (link) hipLaunchKernelGGL((k_chan_moments<double, double, BC_LINK>), grid, dim3(256), 0, b->stream, d.g, d.kd, (const double *)d.buf[cur], oo);
-      else hipLaunchKernelGGL((k_chan_moments<double, double, BC_MOMENT>), grid, dim3(256), 0, b->stream, d.g, d.kd, (const double *)d.buf[cur], oo);
-      break;
-    case LKS_FP32:
-      if (link) hipLaunchKernelGGL((k_chan_moments<float, Fp32Compute, BC_LINK>), grid, dim3(256), 0, b->stream, d.g, coef_host<Fp32Compute>(d), (const float *)d.buf[cur], oo);
-      else hipLaunchKernelGGL((k_chan_moments<float, Fp32Compute, BC_MOMENT>), grid, dim3(256), 0, b->stream, d.g, coef_host<Fp32Compute>(d), (const float *)d.buf[cur], oo);
-      break;
-    default:
-      if (link) hipLaunchKernelGGL((k_chan_moments<_Float16, float, BC_LINK>), grid, dim3(256), 0, b->stream, d.g, d.kf, (const _Float16 *)d.buf[cur], oo);
-      else hipLaunchKernelGGL((k_chan_moments<_Float16, float, BC_MOMENT>), grid, dim3(256), 0, b->stream, d.g, d.kf, (const _Float16 *)d.buf[cur], oo);
-    }
+    dispatch_precision(b->precision, [&](auto t) {
+      using S = typename decltype(t)::S;
+      using C = typename decltype(t)::C;
+      const S *src = static_cast<const S *>(d.buf[cur]);
+      const C *ref = static_cast<const C *>(d.ref);
+      if (link)
+        hipLaunchKernelGGL((k_chan_moments<S, C, BC_LINK>), grid, dim3(256), 0, b->stream, d.g,
+                           coef_host<C>(d), src, ref, oo);
+      else
+        hipLaunchKernelGGL((k_chan_moments<S, C, BC_MOMENT>), grid, dim3(256), 0, b->stream, d.g,
+                           coef_host<C>(d), src, ref, oo);
+    });
     LKS_HIP_CHECK(hipGetLastError());
     return LKS_OK;
   });
@@ -829,11 +879,13 @@ int lks_mhd_batch_save_state(lks_mhd_batch_t *b, int32_t slot, double *dev_pops)
   const long long n = (long long)d.g.nx * d.g.ny;
   const dim3 grid((unsigned)((n + 255) / 256));
   return with_device(b, [&]() -> int {
-    switch (b->precision) {
-    case LKS_FP64: hipLaunchKernelGGL(k_save<double>, grid, dim3(256), 0, b->stream, d.g, b->slots[slot].ch.d.b0, (const double *)d.buf[cur], dev_pops); break;
-    case LKS_FP32: hipLaunchKernelGGL(k_save<float>, grid, dim3(256), 0, b->stream, d.g, b->slots[slot].ch.d.b0, (const float *)d.buf[cur], dev_pops); break;
-    default: hipLaunchKernelGGL(k_save<_Float16>, grid, dim3(256), 0, b->stream, d.g, b->slots[slot].ch.d.b0, (const _Float16 *)d.buf[cur], dev_pops);
-    }
+    dispatch_precision(b->precision, [&](auto t) {
+      using S = typename decltype(t)::S;
+      using C = typename decltype(t)::C;
+      hipLaunchKernelGGL((k_save<S, C>), grid, dim3(256), 0, b->stream, d.g,
+                         b->slots[slot].ch.d.b0, static_cast<const S *>(d.buf[cur]),
+                         static_cast<const C *>(d.ref), dev_pops);
+    });
     LKS_HIP_CHECK(hipGetLastError());
     return LKS_OK;
   });

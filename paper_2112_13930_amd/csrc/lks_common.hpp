@@ -59,8 +59,33 @@ Coef<C> make_coef(const Channel &c) {
   return k;
 }
 
+inline bool valid_precision(int precision) {
+  return precision >= LKS_FP64 && precision <= LKS_FP16_STORE_F32;
+}
+
+inline bool is_binary16(int precision) {
+  return precision == LKS_FP16_STORE || precision == LKS_FP16_STORE_F32;
+}
+
 inline size_t elem_bytes(int precision) {
   return precision == LKS_FP64 ? 8 : (precision == LKS_FP32 ? 4 : 2);
+}
+
+// Storage type S and compute type C of a precision mode.
+template <typename S_, typename C_> struct Types {
+  using S = S_;
+  using C = C_;
+};
+
+// Calls f(Types<S, C>{}) for the precision's types.
+template <typename F>
+decltype(auto) dispatch_precision(int precision, F &&f) {
+  switch (precision) {
+  case LKS_FP64: return f(Types<double, double>{});
+  case LKS_FP32: return f(Types<float, Fp32Compute>{});
+  case LKS_FP16_STORE: return f(Types<_Float16, double>{});
+  default: return f(Types<_Float16, float>{});
+  }
 }
 
 // Elements per plane, rounded up so that every plane starts 256-byte aligned.

@@ -11,9 +11,12 @@
 //
 // Storage: S is the stored type (double, float or _Float16), C the compute
 // type.  Every population is stored as its deviation from the rest state at
-// unit density and B = (0, B0): f_alpha - w_alpha, g_alpha,x, and
-// g_alpha,y - W_alpha B0, so stored values carry only what the flow and the
-// induced field put into them.
+// unit density and B = (0, B0) -- f_alpha - w_alpha, g_alpha,x and
+// g_alpha,y - W_alpha B0 -- minus a per-row reference D[y][plane] kept in the
+// compute type (zero until a rebase moves each row's x-mean into it), so the
+// stored values carry only what the flow, the induced field and their
+// x-variation put into them.  A pulled value is decoded with the reference of
+// the row it comes from; a stored value is encoded with its own row's.
 //
 // Method references (Yahia & Premnath, arXiv 2112.13930):
 //   equilibria, source, moments: Secs. IV, V;  J_z: Sec. IV;  F = J x B: Sec. II
@@ -111,6 +114,10 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
 
 __device__ __forceinline__ uint32_t step_seed(uint32_t step) { return mix32(step * 0x9E3779B1U + 0x632BE5ABU); }
 
+// Seed of the re-encoding done by a rebase after `step` steps (a stream of
+// random bits distinct from the steps').
+__device__ __forceinline__ uint32_t rebase_seed(uint32_t step) { return mix32(step * 0x27D4EB2FU + 0x165667B1U); }
+
 __device__ __forceinline__ uint32_t node_seed(uint32_t sseed, uint32_t idx) {
   return mix32(idx * 0x85EBCA77U ^ sseed);
 }
@@ -135,10 +142,22 @@ __device__ __forceinline__ T next_toward(T h, bool up) {
   return __builtin_bit_cast(T, b);
 }
 
+// A neighbour of v in T (v of the wider type W): the nearest, or for double
+// to binary16 the nearest to v rounded to binary32 first.  Every binary16
+// value is a binary32 value, so that rounding cannot cross a binary16 grid
+// point and the result is one of the two binary16 neighbours of v -- all that
+// stochastic rounding needs -- while hardware conversions replace the long
+// exact double-to-half sequence.
+template <typename T, typename W>
+__device__ __forceinline__ T neighbour(W v) {
+  if constexpr (sizeof(T) == 2 && sizeof(W) == 8) return static_cast<T>(static_cast<float>(v));
+  else return static_cast<T>(v);
+}
+
 // v (wider type W) rounded stochastically to T with 24 random bits of r.
 template <typename T, typename W>
 __device__ __forceinline__ T round_sr(W v, uint32_t r) {
-  const T h = static_cast<T>(v); // nearest
+  const T h = neighbour<T, W>(v);
   const W a = static_cast<W>(h);
   if (a == v || !__builtin_isfinite(a)) return h;
   const bool up = v > a;
@@ -176,9 +195,20 @@ template <typename S, typename C>
 constexpr bool kUseSR = (sizeof(C) > sizeof(S)) &&
                         ((sizeof(S) == 4 && LKS_SR_FP32) || (sizeof(S) == 2 && LKS_SR_FP16));
 
-template <bool D> struct Fp32ComputeSel { using type = float; };
-template <> struct Fp32ComputeSel<true> { using type = double; };
-using Fp32Compute = Fp32ComputeSel<(LKS_FP32_COMPUTE_DOUBLE != 0)>::type;
+// Binary16 storage keeps a per-row reference D[y][plane] (compute type) that
+// a rebase fills with each row's x-mean; wider storage keeps none.
+template <typename S> constexpr bool kRowRef = sizeof(S) == 2;
+
+// Decode a stored value with the reference row it belongs to.
+template <typename S, typename C>
+__device__ __forceinline__ C dec(C v, const C *__restrict__ row, int plane) {
+  if constexpr (kRowRef<S>) return v + row[plane];
+  else return v;
+}
+
+template <bool D> struct ComputeSel { using type = float; };
+template <> struct ComputeSel<true> { using type = double; };
+using Fp32Compute = ComputeSel<(LKS_FP32_COMPUTE_DOUBLE != 0)>::type;
 
 // Weights (Secs. IV and V).
 template <typename C> struct W {
@@ -209,13 +239,15 @@ __device__ __forceinline__ C collide_f(C f, C w, C ex, C ey, C rhop, C rho,
 // MODE_MOMENTS).
 template <typename S, typename C, int BC, int MODE, bool SR>
 __device__ __forceinline__ void node_finish(const Geom &g, const Coef<C> &k,
-                                            const S *__restrict__ src, int x, int y,
+                                            const S *__restrict__ src,
+                                            const C *__restrict__ ref, int x, int y,
                                             C (&f)[9], C (&gx)[5], C (&gy)[5],
                                             NodeObs<C> &obs, uint32_t sseed, S (&out)[19]) {
   const long long P = g.plane;
   const bool lo = (y == 0);
   const bool hi = (y == g.ny - 1);
   const long long r0 = (long long)y * g.pitch;
+  const C *__restrict__ Dy = ref + (long long)y * 19; // reference of this row
   // ---- wall closures for the populations entering from a wall ----
   if (BC == BC_LINK) {
     // Half-way bounce-back of f with Ladd's moving-wall term; theta-weighted
@@ -223,18 +255,18 @@ __device__ __forceinline__ void node_finish(const Geom &g, const Coef<C> &k,
     // g_y, which for the deviations g_y - W B0 is g'_in = -g~'_out.  All from
     // the node's own post-collision values.
     if (lo) {
-      f[2] = ld<S, C>(src + 4 * P + r0 + x);
-      f[5] = ld<S, C>(src + 7 * P + r0 + x) + k.lo.uw6;
-      f[6] = ld<S, C>(src + 8 * P + r0 + x) - k.lo.uw6;
-      gx[2] = k.lo.r * ld<S, C>(src + 13 * P + r0 + x) + k.lo.t;
-      gy[2] = -ld<S, C>(src + 18 * P + r0 + x);
+      f[2] = dec<S>(ld<S, C>(src + 4 * P + r0 + x), Dy, 4);
+      f[5] = dec<S>(ld<S, C>(src + 7 * P + r0 + x), Dy, 7) + k.lo.uw6;
+      f[6] = dec<S>(ld<S, C>(src + 8 * P + r0 + x), Dy, 8) - k.lo.uw6;
+      gx[2] = k.lo.r * dec<S>(ld<S, C>(src + 13 * P + r0 + x), Dy, 13) + k.lo.t;
+      gy[2] = -dec<S>(ld<S, C>(src + 18 * P + r0 + x), Dy, 18);
     }
     if (hi) {
-      f[4] = ld<S, C>(src + 2 * P + r0 + x);
-      f[7] = ld<S, C>(src + 5 * P + r0 + x) - k.hi.uw6;
-      f[8] = ld<S, C>(src + 6 * P + r0 + x) + k.hi.uw6;
-      gx[4] = k.hi.r * ld<S, C>(src + 11 * P + r0 + x) + k.hi.t;
-      gy[4] = -ld<S, C>(src + 16 * P + r0 + x);
+      f[4] = dec<S>(ld<S, C>(src + 2 * P + r0 + x), Dy, 2);
+      f[7] = dec<S>(ld<S, C>(src + 5 * P + r0 + x), Dy, 5) - k.hi.uw6;
+      f[8] = dec<S>(ld<S, C>(src + 6 * P + r0 + x), Dy, 6) + k.hi.uw6;
+      gx[4] = k.hi.r * dec<S>(ld<S, C>(src + 11 * P + r0 + x), Dy, 11) + k.hi.t;
+      gy[4] = -dec<S>(ld<S, C>(src + 16 * P + r0 + x), Dy, 16);
     }
   } else {
     // On-node closures from the moment constraints, written for the
@@ -308,19 +340,24 @@ __device__ __forceinline__ void node_finish(const Geom &g, const Coef<C> &k,
 
   // ---- collide and store ----
   const uint32_t ns = SR ? node_seed(sseed, (uint32_t)(y * g.nx + x)) : 0u;
+  // encode a post-collision value against this row's reference
+  auto put = [&](C v, int plane) -> S {
+    if constexpr (kRowRef<S>) v -= Dy[plane];
+    return to_store<S, C, SR>(v, ns, plane);
+  };
   const C om = k.omega_f, ka = k.kappa_f;
   const C usq15 = C(1.5) * (ux * ux + uy * uy);
   const C uF = ux * Fx + uy * Fy;
   const C w0 = W<C>::w0, w1 = W<C>::w1, w5 = W<C>::w5;
-  out[0] = to_store<S, C, SR>(collide_f(f[0], w0, C(0), C(0), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), ns, 0);
-  out[1] = to_store<S, C, SR>(collide_f(f[1], w1, C(1), C(0), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), ns, 1);
-  out[2] = to_store<S, C, SR>(collide_f(f[2], w1, C(0), C(1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), ns, 2);
-  out[3] = to_store<S, C, SR>(collide_f(f[3], w1, C(-1), C(0), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), ns, 3);
-  out[4] = to_store<S, C, SR>(collide_f(f[4], w1, C(0), C(-1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), ns, 4);
-  out[5] = to_store<S, C, SR>(collide_f(f[5], w5, C(1), C(1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), ns, 5);
-  out[6] = to_store<S, C, SR>(collide_f(f[6], w5, C(-1), C(1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), ns, 6);
-  out[7] = to_store<S, C, SR>(collide_f(f[7], w5, C(-1), C(-1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), ns, 7);
-  out[8] = to_store<S, C, SR>(collide_f(f[8], w5, C(1), C(-1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), ns, 8);
+  out[0] = put(collide_f(f[0], w0, C(0), C(0), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), 0);
+  out[1] = put(collide_f(f[1], w1, C(1), C(0), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), 1);
+  out[2] = put(collide_f(f[2], w1, C(0), C(1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), 2);
+  out[3] = put(collide_f(f[3], w1, C(-1), C(0), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), 3);
+  out[4] = put(collide_f(f[4], w1, C(0), C(-1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), 4);
+  out[5] = put(collide_f(f[5], w5, C(1), C(1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), 5);
+  out[6] = put(collide_f(f[6], w5, C(-1), C(1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), 6);
+  out[7] = put(collide_f(f[7], w5, C(-1), C(-1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), 7);
+  out[8] = put(collide_f(f[8], w5, C(1), C(-1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), 8);
 
   // g^eq_{a i} = W_a [B_i + e_aj (u_j B_i - B_j u_i) / cs2m]  (Sec. IV):
   // with E = u_x B_y - u_y B_x only g_2x, g_4x (-/+ 3E) and g_1y, g_3y (+/- 3E)
@@ -328,22 +365,23 @@ __device__ __forceinline__ void node_finish(const Geom &g, const Coef<C> &k,
   const C E3 = C(3) * (ux * by - uy * bx);
   const C wm = k.omega_m;
   const C W0 = W<C>::W0, W1 = W<C>::W1;
-  out[9] = to_store<S, C, SR>(gx[0] + wm * (W0 * bx - gx[0]), ns, 9);
-  out[10] = to_store<S, C, SR>(gx[1] + wm * (W1 * bx - gx[1]), ns, 10);
-  out[11] = to_store<S, C, SR>(gx[2] + wm * (W1 * (bx - E3) - gx[2]), ns, 11);
-  out[12] = to_store<S, C, SR>(gx[3] + wm * (W1 * bx - gx[3]), ns, 12);
-  out[13] = to_store<S, C, SR>(gx[4] + wm * (W1 * (bx + E3) - gx[4]), ns, 13);
-  out[14] = to_store<S, C, SR>(gy[0] + wm * (W0 * byp - gy[0]), ns, 14);
-  out[15] = to_store<S, C, SR>(gy[1] + wm * (W1 * (byp + E3) - gy[1]), ns, 15);
-  out[16] = to_store<S, C, SR>(gy[2] + wm * (W1 * byp - gy[2]), ns, 16);
-  out[17] = to_store<S, C, SR>(gy[3] + wm * (W1 * (byp - E3) - gy[3]), ns, 17);
-  out[18] = to_store<S, C, SR>(gy[4] + wm * (W1 * byp - gy[4]), ns, 18);
+  out[9] = put(gx[0] + wm * (W0 * bx - gx[0]), 9);
+  out[10] = put(gx[1] + wm * (W1 * bx - gx[1]), 10);
+  out[11] = put(gx[2] + wm * (W1 * (bx - E3) - gx[2]), 11);
+  out[12] = put(gx[3] + wm * (W1 * bx - gx[3]), 12);
+  out[13] = put(gx[4] + wm * (W1 * (bx + E3) - gx[4]), 13);
+  out[14] = put(gy[0] + wm * (W0 * byp - gy[0]), 14);
+  out[15] = put(gy[1] + wm * (W1 * (byp + E3) - gy[1]), 15);
+  out[16] = put(gy[2] + wm * (W1 * byp - gy[2]), 16);
+  out[17] = put(gy[3] + wm * (W1 * (byp - E3) - gy[3]), 17);
+  out[18] = put(gy[4] + wm * (W1 * byp - gy[4]), 18);
 }
 
 
 template <typename S, typename C, int BC, int MODE, bool SR>
 __device__ __forceinline__ void node_update(const Geom &g, const Coef<C> &k,
                                             const S *__restrict__ src,
+                                            const C *__restrict__ ref,
                                             S *__restrict__ dst, int x, int y,
                                             NodeObs<C> &obs, uint32_t sseed) {
   const int nx = g.nx;
@@ -357,34 +395,38 @@ __device__ __forceinline__ void node_update(const Geom &g, const Coef<C> &k,
   const long long rp = r0 + g.pitch;
 
   // ---- pull streaming: f_a(x) = f~_a(x - e_a) ----
+  // stored values are decoded with the reference of the row they come from
+  const C *__restrict__ Dy = ref + (long long)y * 19;
+  const C *__restrict__ Dm = lo ? Dy : Dy - 19; // row y - 1 (used only off the lower wall)
+  const C *__restrict__ Dp = hi ? Dy : Dy + 19; // row y + 1 (used only off the upper wall)
   C f[9], gx[5], gy[5];
-  f[0] = ld<S, C>(src + r0 + x);
-  f[1] = ld<S, C>(src + 1 * P + r0 + xm);
-  f[3] = ld<S, C>(src + 3 * P + r0 + xp);
-  gx[0] = ld<S, C>(src + 9 * P + r0 + x);
-  gx[1] = ld<S, C>(src + 10 * P + r0 + xm);
-  gx[3] = ld<S, C>(src + 12 * P + r0 + xp);
-  gy[0] = ld<S, C>(src + 14 * P + r0 + x);
-  gy[1] = ld<S, C>(src + 15 * P + r0 + xm);
-  gy[3] = ld<S, C>(src + 17 * P + r0 + xp);
+  f[0] = dec<S>(ld<S, C>(src + r0 + x), Dy, 0);
+  f[1] = dec<S>(ld<S, C>(src + 1 * P + r0 + xm), Dy, 1);
+  f[3] = dec<S>(ld<S, C>(src + 3 * P + r0 + xp), Dy, 3);
+  gx[0] = dec<S>(ld<S, C>(src + 9 * P + r0 + x), Dy, 9);
+  gx[1] = dec<S>(ld<S, C>(src + 10 * P + r0 + xm), Dy, 10);
+  gx[3] = dec<S>(ld<S, C>(src + 12 * P + r0 + xp), Dy, 12);
+  gy[0] = dec<S>(ld<S, C>(src + 14 * P + r0 + x), Dy, 14);
+  gy[1] = dec<S>(ld<S, C>(src + 15 * P + r0 + xm), Dy, 15);
+  gy[3] = dec<S>(ld<S, C>(src + 17 * P + r0 + xp), Dy, 17);
   if (!lo) {
-    f[2] = ld<S, C>(src + 2 * P + rm + x);
-    f[5] = ld<S, C>(src + 5 * P + rm + xm);
-    f[6] = ld<S, C>(src + 6 * P + rm + xp);
-    gx[2] = ld<S, C>(src + 11 * P + rm + x);
-    gy[2] = ld<S, C>(src + 16 * P + rm + x);
+    f[2] = dec<S>(ld<S, C>(src + 2 * P + rm + x), Dm, 2);
+    f[5] = dec<S>(ld<S, C>(src + 5 * P + rm + xm), Dm, 5);
+    f[6] = dec<S>(ld<S, C>(src + 6 * P + rm + xp), Dm, 6);
+    gx[2] = dec<S>(ld<S, C>(src + 11 * P + rm + x), Dm, 11);
+    gy[2] = dec<S>(ld<S, C>(src + 16 * P + rm + x), Dm, 16);
   }
   if (!hi) {
-    f[4] = ld<S, C>(src + 4 * P + rp + x);
-    f[7] = ld<S, C>(src + 7 * P + rp + xp);
-    f[8] = ld<S, C>(src + 8 * P + rp + xm);
-    gx[4] = ld<S, C>(src + 13 * P + rp + x);
-    gy[4] = ld<S, C>(src + 18 * P + rp + x);
+    f[4] = dec<S>(ld<S, C>(src + 4 * P + rp + x), Dp, 4);
+    f[7] = dec<S>(ld<S, C>(src + 7 * P + rp + xp), Dp, 7);
+    f[8] = dec<S>(ld<S, C>(src + 8 * P + rp + xm), Dp, 8);
+    gx[4] = dec<S>(ld<S, C>(src + 13 * P + rp + x), Dp, 13);
+    gy[4] = dec<S>(ld<S, C>(src + 18 * P + rp + x), Dp, 18);
   }
 
   NodeObs<C> &o_ = obs;
   S out[19];
-  node_finish<S, C, BC, MODE, SR>(g, k, src, x, y, f, gx, gy, o_, sseed, out);
+  node_finish<S, C, BC, MODE, SR>(g, k, src, ref, x, y, f, gx, gy, o_, sseed, out);
   if constexpr (MODE != MODE_MOMENTS) {
     const long long o = r0 + x;
 #pragma unroll

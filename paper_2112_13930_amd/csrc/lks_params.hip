@@ -52,7 +52,7 @@ int derive_channel(const lks_mhd_params *p, Channel *out) {
   if (p->ny < (p->bc == LKS_BC_LINK ? 2 : 3)) return bad("ny must be >= 2 (link) or >= 3 (moment)");
   if ((long long)p->nx * (long long)p->ny > (long long)(((1LL << 31) - 1) / 19))
     return bad("nx * ny too large (19 planes must index in 32 bits)");
-  if (p->precision < LKS_FP64 || p->precision > LKS_FP16_STORE) return bad("unknown precision");
+  if (!lks::valid_precision(p->precision)) return bad("unknown precision");
   if (!finite(p->tau_f) || p->tau_f <= 0.5) return bad("tau_f must be finite and > 1/2");
   if (!finite(p->tau_m) || p->tau_m <= 0.5) return bad("tau_m must be finite and > 1/2");
   if (std::isnan(p->c_lower) || p->c_lower < 0.0) return bad("c_lower must be in [0, inf]");
@@ -172,7 +172,7 @@ int lks_mhd_derive(const lks_mhd_params *p, lks_mhd_derived *out) {
 }
 
 int lks_mhd_bytes_per_node(int32_t precision) {
-  if (precision < LKS_FP64 || precision > LKS_FP16_STORE) return 0;
+  if (!lks::valid_precision(precision)) return 0;
   return (int)(2 * 19 * lks::elem_bytes(precision));
 }
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <new>
 
@@ -48,6 +49,7 @@ template <typename S, typename C, int BC, int MODE, int BX, int BY, bool REMAP>
 __global__ __launch_bounds__(BX *BY) void k_step(Geom g, Coef<C> k,
                                                  const S *__restrict__ src,
                                                  S *__restrict__ dst,
+                                                 const C *__restrict__ ref,
                                                  int tiles_x, int ntiles,
                                                  double *__restrict__ rec,
                                                  double *__restrict__ partials,
@@ -68,7 +70,7 @@ __global__ __launch_bounds__(BX *BY) void k_step(Geom g, Coef<C> k,
   const int y = ty * BY + (int)threadIdx.y;
   const bool act = (x < g.nx) && (y < g.ny);
   NodeObs<C> o{};
-  if (act) node_update<S, C, BC, MODE, SR>(g, k, src, dst, x, y, o, sseed);
+  if (act) node_update<S, C, BC, MODE, SR>(g, k, src, ref, dst, x, y, o, sseed);
   const long long n = (long long)g.nx * g.ny;
   const long long i = (long long)y * g.nx + x;
   if constexpr (MODE == MODE_RECORD) {
@@ -117,7 +119,8 @@ __global__ __launch_bounds__(BX *BY) void k_step(Geom g, Coef<C> k,
 // results are bitwise those of the scalar kernel.
 template <typename S, typename C, int BC, int VX>
 __global__ __launch_bounds__(256) void k_step_vec(Geom g, Coef<C> k, const S *__restrict__ src,
-                                                  S *__restrict__ dst, int tiles_x, int ntiles,
+                                                  S *__restrict__ dst, const C *__restrict__ ref,
+                                                  int tiles_x, int ntiles,
                                                   uint32_t *__restrict__ ctr, int parity) {
   using V = S __attribute__((ext_vector_type(VX)));
   constexpr bool SR = kUseSR<S, C>;
@@ -163,34 +166,37 @@ __global__ __launch_bounds__(256) void k_step_vec(Geom g, Coef<C> k, const S *__
     b4 = vld(13 * P + rp + x0);
     c4 = vld(18 * P + rp + x0);
   }
+  const C *__restrict__ Dy = ref + (long long)y * 19; // row references (binary16 only)
+  const C *__restrict__ Dm = lo ? Dy : Dy - 19;
+  const C *__restrict__ Dp = hi ? Dy : Dy + 19;
   V outv[19];
 #pragma unroll
   for (int v = 0; v < VX; ++v) {
     // pulled populations of node x0 + v: x - 1 planes take element v - 1
     // (or the extra scalar for v = 0), x + 1 planes element v + 1
     C f[9], gx[5], gy[5];
-    f[0] = (C)a0[v];
-    f[1] = (C)(v == 0 ? e1 : a1[v > 0 ? v - 1 : 0]);
-    f[3] = (C)(v == VX - 1 ? e3 : a3[v < VX - 1 ? v + 1 : 0]);
-    f[2] = (C)a2[v];
-    f[5] = (C)(v == 0 ? e5 : a5[v > 0 ? v - 1 : 0]);
-    f[6] = (C)(v == VX - 1 ? e6 : a6[v < VX - 1 ? v + 1 : 0]);
-    f[4] = (C)a4[v];
-    f[7] = (C)(v == VX - 1 ? e7 : a7[v < VX - 1 ? v + 1 : 0]);
-    f[8] = (C)(v == 0 ? e8 : a8[v > 0 ? v - 1 : 0]);
-    gx[0] = (C)b0[v];
-    gx[1] = (C)(v == 0 ? eb1 : b1[v > 0 ? v - 1 : 0]);
-    gx[3] = (C)(v == VX - 1 ? eb3 : b3[v < VX - 1 ? v + 1 : 0]);
-    gx[2] = (C)b2[v];
-    gx[4] = (C)b4[v];
-    gy[0] = (C)c0[v];
-    gy[1] = (C)(v == 0 ? ec1 : c1[v > 0 ? v - 1 : 0]);
-    gy[3] = (C)(v == VX - 1 ? ec3 : c3[v < VX - 1 ? v + 1 : 0]);
-    gy[2] = (C)c2[v];
-    gy[4] = (C)c4[v];
+    f[0] = dec<S>((C)a0[v], Dy, 0);
+    f[1] = dec<S>((C)(v == 0 ? e1 : a1[v > 0 ? v - 1 : 0]), Dy, 1);
+    f[3] = dec<S>((C)(v == VX - 1 ? e3 : a3[v < VX - 1 ? v + 1 : 0]), Dy, 3);
+    f[2] = dec<S>((C)a2[v], Dm, 2);
+    f[5] = dec<S>((C)(v == 0 ? e5 : a5[v > 0 ? v - 1 : 0]), Dm, 5);
+    f[6] = dec<S>((C)(v == VX - 1 ? e6 : a6[v < VX - 1 ? v + 1 : 0]), Dm, 6);
+    f[4] = dec<S>((C)a4[v], Dp, 4);
+    f[7] = dec<S>((C)(v == VX - 1 ? e7 : a7[v < VX - 1 ? v + 1 : 0]), Dp, 7);
+    f[8] = dec<S>((C)(v == 0 ? e8 : a8[v > 0 ? v - 1 : 0]), Dp, 8);
+    gx[0] = dec<S>((C)b0[v], Dy, 9);
+    gx[1] = dec<S>((C)(v == 0 ? eb1 : b1[v > 0 ? v - 1 : 0]), Dy, 10);
+    gx[3] = dec<S>((C)(v == VX - 1 ? eb3 : b3[v < VX - 1 ? v + 1 : 0]), Dy, 12);
+    gx[2] = dec<S>((C)b2[v], Dm, 11);
+    gx[4] = dec<S>((C)b4[v], Dp, 13);
+    gy[0] = dec<S>((C)c0[v], Dy, 14);
+    gy[1] = dec<S>((C)(v == 0 ? ec1 : c1[v > 0 ? v - 1 : 0]), Dy, 15);
+    gy[3] = dec<S>((C)(v == VX - 1 ? ec3 : c3[v < VX - 1 ? v + 1 : 0]), Dy, 17);
+    gy[2] = dec<S>((C)c2[v], Dm, 16);
+    gy[4] = dec<S>((C)c4[v], Dp, 18);
     NodeObs<C> o{};
     S out[19];
-    node_finish<S, C, BC, MODE_STEP, SR>(g, k, src, x0 + v, y, f, gx, gy, o, sseed, out);
+    node_finish<S, C, BC, MODE_STEP, SR>(g, k, src, ref, x0 + v, y, f, gx, gy, o, sseed, out);
 #pragma unroll
     for (int q = 0; q < 19; ++q) outv[q][v] = out[q];
   }
@@ -226,6 +232,7 @@ struct lks_mhd {
   double *partials = nullptr;
   double *result = nullptr;
   uint32_t *ctr = nullptr; // step counters [2] (device)
+  void *ref = nullptr;      // row references [ny][19] of the compute type (device)
   int cur = 0;
   int64_t steps = 0;
   int shape = 0;
@@ -233,6 +240,7 @@ struct lks_mhd {
   Coef<double> kd{};
   Coef<float> kf{};
   int graph_steps = 0;
+  int64_t rebase_every = 0; // plain stepping: rebase before steps at multiples of this
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
 };
 
@@ -240,7 +248,7 @@ namespace {
 
 struct Layout {
   long long plane;
-  size_t state_bytes, rec_bytes, part_bytes, total;
+  size_t state_bytes, rec_bytes, part_bytes, ref_bytes, total;
   int red_tiles_x, red_ntiles;
 };
 
@@ -254,11 +262,15 @@ Layout layout_of(const Channel &c) {
   L.red_tiles_x = (c.p.nx + s.bx - 1) / s.bx;
   L.red_ntiles = L.red_tiles_x * ((c.p.ny + s.by - 1) / s.by);
   L.part_bytes = align256((size_t)L.red_ntiles * 8 * sizeof(double));
-  L.total = 2 * L.state_bytes + L.rec_bytes + L.part_bytes + 256 + 256;
+  L.ref_bytes = align256((size_t)c.p.ny * 19 * sizeof(double));
+  L.total = 2 * L.state_bytes + L.rec_bytes + L.part_bytes + 256 + 256 + L.ref_bytes;
   return L;
 }
 
 int grid_for(int ntiles, bool remap) { return remap ? (ntiles + 7) / 8 * 8 : ntiles; }
+
+// Default rebase interval of plain stepping for binary16 states.
+constexpr int64_t kDefaultRebase = 1000;
 
 template <typename C> const Coef<C> &coef_of(const lks_mhd *h);
 template <> const Coef<double> &coef_of<double>(const lks_mhd *h) { return h->kd; }
@@ -272,8 +284,8 @@ hipError_t launch_shape(lks_mhd *h, const void *src, void *dst, ObsOut oo) {
     const int tiles_x = (h->geom.nx + s.bx * s.vx - 1) / (s.bx * s.vx);
     const int ntiles = tiles_x * h->geom.ny;
     hipLaunchKernelGGL((k_step_vec<S, C, BC, s.vx>), dim3(ntiles), dim3(s.bx), 0, h->stream,
-                       h->geom, k, static_cast<const S *>(src), static_cast<S *>(dst), tiles_x,
-                       ntiles, h->ctr, h->cur);
+                       h->geom, k, static_cast<const S *>(src), static_cast<S *>(dst),
+                       static_cast<const C *>(h->ref), tiles_x, ntiles, h->ctr, h->cur);
     return hipGetLastError();
   }
   const int tiles_x = (h->geom.nx + s.bx - 1) / s.bx;
@@ -281,8 +293,9 @@ hipError_t launch_shape(lks_mhd *h, const void *src, void *dst, ObsOut oo) {
   const int grid = grid_for(ntiles, s.remap);
   hipLaunchKernelGGL((k_step<S, C, BC, MODE, s.bx, s.by, s.remap>), dim3(grid),
                      dim3(s.bx, s.by), 0, h->stream, h->geom, k,
-                     static_cast<const S *>(src), static_cast<S *>(dst), tiles_x,
-                     ntiles, h->rec, h->partials, oo, h->ctr, h->cur);
+                     static_cast<const S *>(src), static_cast<S *>(dst),
+                     static_cast<const C *>(h->ref), tiles_x, ntiles, h->rec, h->partials, oo,
+                     h->ctr, h->cur);
   return hipGetLastError();
 }
 
@@ -302,17 +315,12 @@ hipError_t launch_bc(lks_mhd *h, int shape, const void *src, void *dst, ObsOut o
 template <int MODE>
 hipError_t launch_mode(lks_mhd *h, int shape, const void *src, void *dst, ObsOut oo) {
   const bool link = h->ch.p.bc == LKS_BC_LINK;
-  switch (h->ch.p.precision) {
-  case LKS_FP64:
-    return link ? launch_bc<double, double, BC_LINK, MODE>(h, shape, src, dst, oo)
-                : launch_bc<double, double, BC_MOMENT, MODE>(h, shape, src, dst, oo);
-  case LKS_FP32:
-    return link ? launch_bc<float, Fp32Compute, BC_LINK, MODE>(h, shape, src, dst, oo)
-                : launch_bc<float, Fp32Compute, BC_MOMENT, MODE>(h, shape, src, dst, oo);
-  default:
-    return link ? launch_bc<_Float16, float, BC_LINK, MODE>(h, shape, src, dst, oo)
-                : launch_bc<_Float16, float, BC_MOMENT, MODE>(h, shape, src, dst, oo);
-  }
+  return dispatch_precision(h->ch.p.precision, [&](auto t) -> hipError_t {
+    using S = typename decltype(t)::S;
+    using C = typename decltype(t)::C;
+    return link ? launch_bc<S, C, BC_LINK, MODE>(h, shape, src, dst, oo)
+                : launch_bc<S, C, BC_MOMENT, MODE>(h, shape, src, dst, oo);
+  });
 }
 
 // One step from buf[cur] into buf[cur^1].
@@ -391,6 +399,34 @@ int elementwise_grid(const lks_mhd *h) {
   return (int)((n + 255) / 256);
 }
 
+// Clear the row references (the stored values then hold the deviations).
+int zero_ref(lks_mhd *h) {
+  const long long n = (long long)h->geom.ny * 19;
+  hipLaunchKernelGGL(k_zero<double>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, h->stream,
+                     static_cast<double *>(h->ref), n);
+  LKS_HIP_CHECK(hipGetLastError());
+  return LKS_OK;
+}
+
+// Row rebase of a binary16 state (other storage keeps no row reference).
+int rebase_now(lks_mhd *h) {
+  return dispatch_precision(h->ch.p.precision, [&](auto t) -> int {
+    using S = typename decltype(t)::S;
+    using C = typename decltype(t)::C;
+    if constexpr (kRowRef<S>) {
+      hipLaunchKernelGGL((k_rebase_rows<S, C>), dim3(h->geom.ny), dim3(256), 0, h->stream, h->geom,
+                         static_cast<S *>(h->buf[h->cur]), static_cast<C *>(h->ref),
+                         (uint32_t)h->steps);
+      LKS_HIP_CHECK(hipGetLastError());
+    }
+    return LKS_OK;
+  });
+}
+
+bool rebase_due(const lks_mhd *h) {
+  return h->rebase_every > 0 && h->steps % h->rebase_every == 0;
+}
+
 } // namespace
 
 extern "C" {
@@ -438,26 +474,24 @@ int lks_mhd_create(const lks_mhd_params *p, void *dev_buf, size_t bytes,
   h->partials = reinterpret_cast<double *>(base + 2 * L.state_bytes + L.rec_bytes);
   h->result = reinterpret_cast<double *>(base + 2 * L.state_bytes + L.rec_bytes + L.part_bytes);
   h->ctr = reinterpret_cast<uint32_t *>(base + 2 * L.state_bytes + L.rec_bytes + L.part_bytes + 256);
+  h->ref = base + 2 * L.state_bytes + L.rec_bytes + L.part_bytes + 512;
   h->red_tiles_x = L.red_tiles_x;
   h->red_ntiles = L.red_ntiles;
   h->kd = make_coef<double>(c);
   h->kf = make_coef<float>(c);
   // binary16 planes: two nodes per thread (4-byte accesses) measured fastest
-  h->shape = (c.p.precision == LKS_FP16_STORE && c.p.nx % 2 == 0) ? 5 : 0;
+  h->shape = (is_binary16(c.p.precision) && c.p.nx % 2 == 0) ? 5 : 0;
+  h->rebase_every = is_binary16(c.p.precision) ? kDefaultRebase : 0;
   rc = with_device(h, [&]() -> int {
     const int grid = elementwise_grid(h);
-    switch (c.p.precision) {
-    case LKS_FP64:
-      hipLaunchKernelGGL(k_init<double>, dim3(grid), dim3(256), 0, h->stream, h->geom, c.p.rho0, (double *)h->buf[0]);
-      break;
-    case LKS_FP32:
-      hipLaunchKernelGGL(k_init<float>, dim3(grid), dim3(256), 0, h->stream, h->geom, c.p.rho0, (float *)h->buf[0]);
-      break;
-    default:
-      hipLaunchKernelGGL(k_init<_Float16>, dim3(grid), dim3(256), 0, h->stream, h->geom, c.p.rho0, (_Float16 *)h->buf[0]);
-    }
+    dispatch_precision(c.p.precision, [&](auto t) {
+      using S = typename decltype(t)::S;
+      hipLaunchKernelGGL(k_init<S>, dim3(grid), dim3(256), 0, h->stream, h->geom, c.p.rho0,
+                         static_cast<S *>(h->buf[0]));
+    });
     LKS_HIP_CHECK(hipGetLastError());
-    return set_counter(h, 0);
+    const int r = zero_ref(h);
+    return r != LKS_OK ? r : set_counter(h, 0);
   });
   if (rc != LKS_OK) {
     delete h;
@@ -517,7 +551,14 @@ int lks_mhd_step(lks_mhd_t *h, int64_t nsteps) {
   return with_device(h, [&]() -> int {
     int64_t n = nsteps;
     while (n > 0) {
-      if (h->graph_steps >= 2 && n >= h->graph_steps) {
+      if (rebase_due(h)) {
+        const int rc = rebase_now(h);
+        if (rc != LKS_OK) return rc;
+      }
+      // a graph replay must not step over a rebase point
+      const int64_t to_rebase =
+          h->rebase_every > 0 ? h->rebase_every - h->steps % h->rebase_every : INT64_MAX;
+      if (h->graph_steps >= 2 && n >= h->graph_steps && to_rebase >= h->graph_steps) {
         if (!h->gexec[h->cur]) {
           const int rc = capture_graph(h, h->cur);
           if (rc != LKS_OK) return rc;
@@ -545,12 +586,18 @@ int lks_mhd_run_to_steady(lks_mhd_t *h, double tol, int64_t check_every,
   }
   double res = NAN, q = NAN;
   int status = LKS_ENOTCONV;
+  // windows rebase at their start; the plain-stepping interval is off inside
+  const int64_t saved_rebase = h->rebase_every;
+  h->rebase_every = 0;
   const int rc = with_device(h, [&]() -> int {
     int64_t done = 0;
     while (done + check_every <= max_steps) {
       // window of check_every steps: the first records phi, the last
-      // compares phi with the record check_every - 1 steps later
-      int rc2 = one_step(h, MODE_RECORD);
+      // compares phi with the record check_every - 1 steps later; binary16
+      // states are rebased at the start of every window
+      int rc2 = rebase_now(h);
+      if (rc2 != LKS_OK) return rc2;
+      if ((rc2 = one_step(h, MODE_RECORD)) != LKS_OK) return rc2;
       if (rc2 != LKS_OK) return rc2;
       if ((rc2 = lks_mhd_step(h, check_every - 2)) != LKS_OK) return rc2;
       if ((rc2 = one_step(h, MODE_RESIDUAL)) != LKS_OK) return rc2;
@@ -580,6 +627,7 @@ int lks_mhd_run_to_steady(lks_mhd_t *h, double tol, int64_t check_every,
     set_error("residual %.3e above tolerance %.3e after %lld steps", res, tol, (long long)h->steps);
     return LKS_OK;
   });
+  h->rebase_every = saved_rebase;
   if (steps_done) *steps_done = h->steps;
   if (residual) *residual = res;
   if (flow_rate) *flow_rate = q;
@@ -612,11 +660,13 @@ int lks_mhd_save_state(lks_mhd_t *h, double *dev_pops) {
   }
   return with_device(h, [&]() -> int {
     const int grid = elementwise_grid(h);
-    switch (h->ch.p.precision) {
-    case LKS_FP64: hipLaunchKernelGGL(k_save<double>, dim3(grid), dim3(256), 0, h->stream, h->geom, h->ch.d.b0, (const double *)h->buf[h->cur], dev_pops); break;
-    case LKS_FP32: hipLaunchKernelGGL(k_save<float>, dim3(grid), dim3(256), 0, h->stream, h->geom, h->ch.d.b0, (const float *)h->buf[h->cur], dev_pops); break;
-    default: hipLaunchKernelGGL(k_save<_Float16>, dim3(grid), dim3(256), 0, h->stream, h->geom, h->ch.d.b0, (const _Float16 *)h->buf[h->cur], dev_pops);
-    }
+    dispatch_precision(h->ch.p.precision, [&](auto t) {
+      using S = typename decltype(t)::S;
+      using C = typename decltype(t)::C;
+      hipLaunchKernelGGL((k_save<S, C>), dim3(grid), dim3(256), 0, h->stream, h->geom, h->ch.d.b0,
+                         static_cast<const S *>(h->buf[h->cur]), static_cast<const C *>(h->ref),
+                         dev_pops);
+    });
     LKS_HIP_CHECK(hipGetLastError());
     return LKS_OK;
   });
@@ -630,15 +680,36 @@ int lks_mhd_load_state(lks_mhd_t *h, const double *dev_pops, int64_t steps) {
   }
   return with_device(h, [&]() -> int {
     const int grid = elementwise_grid(h);
-    switch (h->ch.p.precision) {
-    case LKS_FP64: hipLaunchKernelGGL(k_load<double>, dim3(grid), dim3(256), 0, h->stream, h->geom, h->ch.d.b0, dev_pops, (double *)h->buf[h->cur]); break;
-    case LKS_FP32: hipLaunchKernelGGL(k_load<float>, dim3(grid), dim3(256), 0, h->stream, h->geom, h->ch.d.b0, dev_pops, (float *)h->buf[h->cur]); break;
-    default: hipLaunchKernelGGL(k_load<_Float16>, dim3(grid), dim3(256), 0, h->stream, h->geom, h->ch.d.b0, dev_pops, (_Float16 *)h->buf[h->cur]);
-    }
+    dispatch_precision(h->ch.p.precision, [&](auto t) {
+      using S = typename decltype(t)::S;
+      hipLaunchKernelGGL(k_load<S>, dim3(grid), dim3(256), 0, h->stream, h->geom, h->ch.d.b0,
+                         dev_pops, static_cast<S *>(h->buf[h->cur]));
+    });
     LKS_HIP_CHECK(hipGetLastError());
+    const int r = zero_ref(h);
+    if (r != LKS_OK) return r;
     h->steps = steps;
     return set_counter(h, steps);
   });
+}
+
+int lks_mhd_rebase(lks_mhd_t *h) {
+  clear_error();
+  if (!h) {
+    set_error("invalid handle");
+    return LKS_EINVAL;
+  }
+  return with_device(h, [&]() -> int { return rebase_now(h); });
+}
+
+int lks_mhd_set_rebase(lks_mhd_t *h, int64_t every) {
+  clear_error();
+  if (!h || every < 0) {
+    set_error("invalid handle or negative rebase interval");
+    return LKS_EINVAL;
+  }
+  h->rebase_every = is_binary16(h->ch.p.precision) ? every : 0;
+  return LKS_OK;
 }
 
 } // extern "C"

@@ -182,7 +182,7 @@ def sequential_baseline(requests, precision="fp32", tol=1e-8, check_every=200,
     (status, steps, residual, latency) and the makespan."""
     import torch
 
-    from ._lib import LKS_EUNSTABLE
+    from ._lib import LKS_EUNSTABLE, PRECISIONS
     from .channel import Channel
     out = []
     t0 = time.perf_counter()
@@ -191,7 +191,7 @@ def sequential_baseline(requests, precision="fp32", tol=1e-8, check_every=200,
         if req.arrival > now:
             time.sleep(req.arrival - now)
         p = req.params
-        p.precision = {"fp64": 0, "fp32": 1, "fp16": 2}[precision]
+        p.precision = PRECISIONS[precision]
         ch = Channel(params=p, stream=torch.cuda.Stream())
         ch.set_graph(graph_steps)
         hist, status, steps, res = [], None, 0, math.nan

@@ -47,7 +47,9 @@ def to_numpy(d: dict) -> dict:
     return {k: v.detach().cpu().numpy() for k, v in d.items()}
 
 
-TOL = {"fp64": 1e-12, "fp32": 1e-5, "fp16": 2e-3}
+# relative L2 bars against the FP64 oracle; binary16 storage computed in FP32
+# ("fp16_f32") is held to the binary16 bar on short runs only
+TOL = {"fp64": 1e-12, "fp32": 1e-5, "fp16": 2e-3, "fp16_f32": 2e-3}
 
 
 def assert_close(errs: dict, tol: float, keys=("ux", "bx", "uy", "by", "rho")):

@@ -56,7 +56,8 @@ def _v(L, **kw):
     dict(nx=20000, ny=20000),
     dict(ha=10.0, b0=0.5),                       # inconsistent
     dict(u_max=0.05, c_lower=0.1, c_upper=0.2),  # fx from u_max needs equal walls
-    dict(u_upper=float("inf")), dict(rho0=0.0), dict(precision=7), dict(bc=5),
+    dict(u_upper=float("inf")), dict(rho0=0.0), dict(precision=7), dict(precision=4),
+    dict(bc=5),
 ])
 def test_validate_rejects(L, kw):
     rc, p = _v(L, **kw)
@@ -69,7 +70,7 @@ def test_validate_rejects(L, kw):
     dict(), dict(ny=2), dict(ny=3, bc="moment"), dict(c_lower=math.inf, c_upper=0.0),
     dict(ha=10.0, u_max=0.05, c_lower=0.1), dict(ha=0.0, u_max=0.05),
     dict(ha=5.0, c_lower=math.inf, u_max=0.01, bc="moment"),
-    dict(precision="fp64"), dict(precision="fp16"),
+    dict(precision="fp64"), dict(precision="fp16"), dict(precision="fp16_f32"),
 ])
 def test_validate_accepts(L, kw):
     rc, p = _v(L, **kw)
@@ -98,11 +99,11 @@ def test_derivation_agrees_with_oracle(L, bc, ha, c):
 
 def test_bytes_per_node(L):
     f = L.lib().lks_mhd_bytes_per_node
-    assert (f(0), f(1), f(2), f(9)) == (304, 152, 76, 0)
+    assert (f(0), f(1), f(2), f(3), f(4), f(9)) == (304, 152, 76, 76, 0, 0)
 
 
 def test_state_bytes_cover_two_buffers(L):
-    for prec, b in (("fp64", 8), ("fp32", 4), ("fp16", 2)):
+    for prec, b in (("fp64", 8), ("fp32", 4), ("fp16", 2), ("fp16_f32", 2)):
         p = L.make_params(4096, 4096, precision=prec)
         assert L.lib().lks_mhd_state_bytes(ctypes.byref(p)) >= 2 * 19 * 4096 * 4096 * b
 

@@ -46,11 +46,12 @@ def mix_params(i):
 def solo_state(p, precision, nsteps):
     from paper_2112_13930_amd.channel import Channel
     ch = Channel(p.nx, p.ny, **lib_kwargs(p, precision))
+    ch.set_rebase(0)  # batch steps outside check windows do not rebase
     ch.step(nsteps)
     return ch.save_state().cpu()
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp16", "fp64"])
+@pytest.mark.parametrize("precision", ["fp32", "fp16", "fp64", "fp16_f32"])
 def test_mixed_batch_equals_solo_runs(P, precision):
     from paper_2112_13930_amd._lib import make_params
     from paper_2112_13930_amd.batch import Batch

@@ -80,7 +80,7 @@ def test_4096_random_state_two_steps(P):
     assert_close(errs, TOL["fp32"], keys=("ux", "bx", "uy", "by", "rho"))
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+@pytest.mark.parametrize("precision", ["fp32", "fp16", "fp16_f32"])
 def test_config1_precisions(P, precision):
     p = derive.hartmann_params(8, 64, LINK, 0.8, 0.8, 10.0, 0.1, 0.05)
     ch = channel(p, precision)
@@ -94,7 +94,7 @@ def test_config1_precisions(P, precision):
     assert_close(errs, TOL[precision], keys=("ux", "bx"))
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+@pytest.mark.parametrize("precision", ["fp32", "fp16", "fp16_f32"])
 def test_512_precision_case(P, precision):
     p = derive.hartmann_params(1, 512, LINK, 0.8, 0.8, 50.0, 0.5, 0.003)
     ch = channel(p, precision, nx=512)
@@ -106,3 +106,32 @@ def test_512_precision_case(P, precision):
     errs = field_errors(g, o, p.b0)
     print(precision, errs)
     assert_close(errs, TOL[precision], keys=("ux", "bx"))
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+def test_config1_steady_state_matches_oracle_and_closed_form(P, precision):
+    """Config-1 channel (8 x 64, link, Ha = 10, c = 0.1, u_max = 0.05) run to
+    steady state through run_to_steady: fields within the precision's bar of
+    the oracle's steady state, and the discretisation error against the
+    Chang-Lundgren profile the same as the oracle's."""
+    from oracle import analytic, steady
+    p = derive.hartmann_params(8, 64, LINK, 0.8, 0.8, 10.0, 0.1, 0.05)
+    ch = channel(p, precision)
+    tol = 1e-10 if precision == "fp32" else 1e-8
+    rc, steps, res, q = ch.run_to_steady(tol=tol, check_every=1000, max_steps=400_000)
+    assert rc == 0, (rc, steps, res)
+    g = to_numpy(ch.moments())
+    ch.close()
+    p1 = derive.hartmann_params(1, 64, LINK, 0.8, 0.8, 10.0, 0.1, 0.05)
+    _, o, n, r = steady.run_to_steady(p1, tol=1e-13, check_every=1000, max_steps=1_000_000)
+    errs = field_errors(g, {k: np.repeat(v, 8, axis=1) for k, v in o.items()}, p.b0)
+    print(precision, steps, res, errs)
+    assert_close(errs, TOL[precision], keys=("ux", "bx"))
+    xi = analytic.node_xi(64, LINK)
+    ua, _ = analytic.chang_lundgren(xi, 10.0, 0.1)
+    u_ref = derive.u_ref_hartmann(p.fx, p.tau_f, p.a)
+    e_gpu = math.sqrt(np.mean((g["ux"][:, 0] / u_ref - ua) ** 2))
+    e_orc = math.sqrt(np.mean((o["ux"][:, 0] / u_ref - ua) ** 2))
+    rms = math.sqrt(np.mean((o["ux"][:, 0] / u_ref) ** 2))
+    assert abs(e_gpu - e_orc) <= TOL[precision] * rms, (e_gpu, e_orc)
+    assert e_gpu < 2e-3, e_gpu
