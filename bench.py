@@ -18,10 +18,13 @@ Printed as one JSON line with, besides the contract fields:
                 rocprofv3 counter summary when the kernel source is unchanged.
   cpu_baseline  the FP64 CPU oracle timed on the host cores over a bounded
                 sample of the same grid.
-  extras        the 30-case sweep (Ha x c x closure), FP16-storage and FP64
-                rates, the batched launch over 256 uneven channels against
-                sequential single-channel launches, and the continuous-
-                batching solve service against sequential solves.
+  extras        the 30-case sweep (Ha x c x closure); binary16-storage (FP64
+                and FP32 arithmetic) and FP64 rates with every reduced mode's
+                error against the FP64 oracle on the 512 x 512 precision
+                case; the batched launch over 256 uneven channels (FP32
+                against sequential single-channel launches, and binary16);
+                the continuous-batching solve service (FP32 and binary16)
+                against sequential plain FP32 solves at three arrival rates.
 
 Profiling helpers (used to write profiles/*):
   --profile-run     only warm-up + timed steps of the headline, plus a copy of
@@ -115,15 +118,48 @@ def sweep(torch, steps=100, warmup=10):
             "mlups_median": statistics.median(vals), "mlups_max": max(vals), "rows": rows}
 
 
-def other_precisions(torch, steps=200, warmup=20):
+PRECISION_CASE = os.path.join(ROOT, "tests", "golden", "precision_case_512.json")
+
+
+def other_precisions(torch, steps=200, warmup=20, err_steps=100_000):
+    """Rates of the other storage modes on the headline grid, and every
+    reduced-precision mode's error against the FP64 oracle on the 512 x 512
+    precision case (Ha = 50, c = 0.5) after err_steps steps (oracle columns
+    stored by tests/golden/make_golden.py)."""
+    import numpy as np
+
     from paper_2112_13930_amd.channel import Channel
     out = {}
-    for prec, bpn in (("fp16", 76), ("fp64", 304)):
+    for prec, bpn, comp in (("fp16", 76, "f64"), ("fp16_f32", 76, "f32"), ("fp64", 304, "f64")):
         _, per_step, ch = time_channel(torch, Channel, dict(HEADLINE, precision=prec), steps, warmup)
         ch.close()
         gbs = bpn * 4096 * 4096 / per_step / 1e9
         out[prec] = {"mlups": round(4096 * 4096 / per_step / 1e6, 1), "gbs": round(gbs, 1),
-                     "frac_hbm": round(gbs / PEAK_HBM_GBS, 3), "bytes_per_node": bpn}
+                     "frac_hbm": round(gbs / PEAK_HBM_GBS, 3), "bytes_per_node": bpn,
+                     "compute": comp}
+    if os.path.exists(PRECISION_CASE):
+        gold = json.load(open(PRECISION_CASE))
+        gp = gold["params"]
+        kw = dict(bc="link", tau_f=gp["tau_f"], tau_m=gp["tau_m"], ha=gp["ha"],
+                  c_lower=gp["c"], c_upper=gp["c"], u_max=gp["u_max"])
+        ru = np.asarray(gold[f"ux_{err_steps}"])[:, None]
+        rb = np.asarray(gold[f"bx_{err_steps}"])[:, None]
+        errs = {}
+        for prec in ("fp32", "fp16", "fp16_f32"):
+            ch = Channel(512, 512, precision=prec, stream=torch.cuda.Stream(), **kw)
+            ch.set_graph(40)
+            ch.step(err_steps)
+            m = ch.moments()
+            ux = m["ux"].cpu().numpy()
+            bx = m["bx"].cpu().numpy()
+            ch.close()
+            errs[prec] = {"ux": float(np.linalg.norm(ux - ru) / (np.linalg.norm(ru) * math.sqrt(512))),
+                          "bx": float(np.linalg.norm(bx - rb) / (np.linalg.norm(rb) * math.sqrt(512)))}
+        out["error_vs_fp64_oracle"] = {
+            "case": f"512x512 Hartmann channel, link, Ha=50, c=0.5, u_max=0.003, {err_steps} "
+                    "steps from rest; relative L2 of u_x and B_x (binary16 modes rebase every "
+                    "1000 steps)",
+            **errs}
     return out
 
 
@@ -147,15 +183,15 @@ def stable_mix(n, seed):
     return draws, rejected
 
 
-def batched(torch, steps=1000, warmup=20, seed=2024):
-    from paper_2112_13930_amd._lib import make_params
+def batched(torch, precision="fp32", steps=1000, warmup=20, seed=2024, sequential=True):
+    from paper_2112_13930_amd._lib import STORE_BYTES, make_params
     from paper_2112_13930_amd.batch import Batch
     from paper_2112_13930_amd.channel import Channel
     draws, rejected = stable_mix(256, seed)
     nodes = sum(d.nx * d.ny for d in draws)
-    b = Batch("fp32", max_channels=256, max_nodes=nodes + 1024)
+    b = Batch(precision, max_channels=256, max_nodes=nodes + 1024)
     for d in draws:
-        b.admit(make_params(d.nx, d.ny, precision="fp32", **d.kwargs()))
+        b.admit(make_params(d.nx, d.ny, precision=precision, **d.kwargs()))
     tiles = b.autotune(trial_steps=20)
     b.step(warmup, graph=True)
     torch.cuda.synchronize()
@@ -169,35 +205,37 @@ def batched(torch, steps=1000, warmup=20, seed=2024):
     wall = time.perf_counter() - t0
     per_step = e0.elapsed_time(e1) / 1e3 / steps
     b.close()
-    # baseline: the same channels advanced one after another by the plain
-    # single-channel path (each its own launches), same step count
-    seq_steps = max(10, steps // 10)
-    chans = [Channel(d.nx, d.ny, precision="fp32", stream=torch.cuda.current_stream(), **d.kwargs())
-             for d in draws]
-    for c in chans:
-        c.step(2)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for c in chans:
-        c.step(seq_steps)
-    torch.cuda.synchronize()
-    seq_wall = (time.perf_counter() - t0) / seq_steps
-    for c in chans:
-        c.close()
-    gbs = 152 * nodes / per_step / 1e9
-    return {"channels": len(draws), "rejected_draws": rejected, "nodes": nodes,
-            "steps": steps, "ms_per_step": round(per_step * 1e3, 4),
-            "mlups": round(nodes / per_step / 1e6, 1), "wall_mlups": round(nodes * steps / wall / 1e6, 1),
-            "gbs": round(gbs, 1), "frac_hbm": round(gbs / PEAK_HBM_GBS, 3),
-            "sequential_ms_per_step": round(seq_wall * 1e3, 3),
-            "sequential_mlups": round(nodes / seq_wall / 1e6, 1),
-            "speedup_vs_sequential": round(seq_wall / per_step, 2),
-            "tiles": tiles}
+    bpn = 2 * 19 * STORE_BYTES[precision]
+    gbs = bpn * nodes / per_step / 1e9
+    out = {"precision": precision, "channels": len(draws), "rejected_draws": rejected,
+           "nodes": nodes, "steps": steps, "ms_per_step": round(per_step * 1e3, 4),
+           "mlups": round(nodes / per_step / 1e6, 1), "wall_mlups": round(nodes * steps / wall / 1e6, 1),
+           "gbs": round(gbs, 1), "frac_hbm": round(gbs / PEAK_HBM_GBS, 3), "tiles": tiles}
+    if sequential:
+        # baseline: the same channels advanced one after another by the plain
+        # single-channel path (each its own launches), same step count
+        seq_steps = max(10, steps // 10)
+        chans = [Channel(d.nx, d.ny, precision=precision, stream=torch.cuda.current_stream(),
+                         **d.kwargs()) for d in draws]
+        for c in chans:
+            c.step(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for c in chans:
+            c.step(seq_steps)
+        torch.cuda.synchronize()
+        seq_wall = (time.perf_counter() - t0) / seq_steps
+        for c in chans:
+            c.close()
+        out.update({"sequential_ms_per_step": round(seq_wall * 1e3, 3),
+                    "sequential_mlups": round(nodes / seq_wall / 1e6, 1),
+                    "speedup_vs_sequential": round(seq_wall / per_step, 2)})
+    return out
 
 
-def serving(torch, n_requests=48, rate=200.0, seed=5):
+def serving(torch, rates=(50.0, 200.0, 2000.0), n_requests=48, seed=5):
     from paper_2112_13930_amd.serve import serve_benchmark
-    return serve_benchmark(n_requests=n_requests, rate=rate, seed=seed, log=log)
+    return [serve_benchmark(n_requests=n_requests, rate=r, seed=seed, log=log) for r in rates]
 
 
 def profile_run(torch, args):
@@ -384,7 +422,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": traffic,
-                     "kernel": "k_step<float,float,link,step,256,1>",
+                     "kernel": "k_step<float,double,link,step,256,1>",
                      "algorithmic_bytes_per_launch": 152 * nodes,
                      "avg_launch_ms": round(h["per_step"] * 1e3, 4)},
         "finite": h["finite"],
@@ -396,7 +434,8 @@ def main():
         log("precisions ...")
         extras["precisions"] = other_precisions(torch)
         log("batched ...")
-        extras["batched_256_channels"] = batched(torch)
+        extras["batched_256_channels"] = batched(torch, "fp32")
+        extras["batched_256_channels_fp16"] = batched(torch, "fp16", sequential=False)
         if not args.no_serve:
             log("serving ...")
             try:

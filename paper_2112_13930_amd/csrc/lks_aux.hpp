@@ -10,7 +10,7 @@
 namespace lks {
 
 // Rest state at density rho0 with B = (0, B0).  Stored deviations:
-// f' = w (rho0 - 1), g_x = 0, g'_y = 0.
+// f' = w (rho0 - 1), g_x = 0, g'_y = 0 (binary16: times its scale 2^12).
 template <typename S>
 __global__ void k_init(Geom g, double rho0, S *__restrict__ dst) {
   const long long n = (long long)g.nx * g.ny;
@@ -19,7 +19,8 @@ __global__ void k_init(Geom g, double rho0, S *__restrict__ dst) {
   const int y = (int)(i / g.nx), x = (int)(i - (long long)y * g.nx);
   const long long o = (long long)y * g.pitch + x;
   const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
-  for (int q = 0; q < 9; ++q) dst[q * g.plane + o] = (S)(w[q] * (rho0 - 1.0));
+  const double up = kRowRef<S> ? kStoreUp16 : 1.0;
+  for (int q = 0; q < 9; ++q) dst[q * g.plane + o] = (S)(w[q] * (rho0 - 1.0) * up);
   for (int q = 0; q < 5; ++q) {
     dst[(9 + q) * g.plane + o] = (S)0.0;
     dst[(14 + q) * g.plane + o] = (S)0.0;
@@ -52,9 +53,10 @@ __global__ void k_load(Geom g, double b0, const double *__restrict__ in, S *__re
   const long long o = (long long)y * g.pitch + x;
   const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
   const double Wm[5] = {1.0 / 3, 1.0 / 6, 1.0 / 6, 1.0 / 6, 1.0 / 6};
+  const double up = kRowRef<S> ? kStoreUp16 : 1.0;
   for (int q = 0; q < 19; ++q) {
     const double v = in[q * n + i];
-    dst[q * g.plane + o] = (S)(q < 9 ? v - w[q] : (q < 14 ? v : v - Wm[q - 14] * b0));
+    dst[q * g.plane + o] = (S)((q < 9 ? v - w[q] : (q < 14 ? v : v - Wm[q - 14] * b0)) * up);
   }
 }
 
@@ -65,11 +67,11 @@ __global__ void k_zero(T *__restrict__ p, long long n) {
 }
 
 // Rebase one row of a binary16 state: move the x-mean of every plane's
-// stored values into the row's reference (compute type) and re-encode the
-// row against it.  Decoded populations keep their values up to one rounding
-// of stored values that no longer carry the row's mean, so the storage
-// precision is spent on the x-variation alone.  One 256-thread block;
-// lds holds 4 * 19 + 19 doubles.
+// decoded-minus-reference values into the row's reference (compute type) and
+// re-encode the row against it.  Decoded populations keep their values up
+// to one rounding of stored values that no longer carry the row's mean, so
+// the storage precision is spent on the x-variation alone.  One 256-thread
+// block; lds holds 4 * 19 + 19 doubles.
 template <typename S, typename C, bool SR>
 __device__ __forceinline__ void rebase_row(S *__restrict__ buf, C *__restrict__ Drow,
                                            const Geom &g, int y, uint32_t seed, double *lds) {
@@ -88,7 +90,8 @@ __device__ __forceinline__ void rebase_row(S *__restrict__ buf, C *__restrict__ 
   __syncthreads();
   if (tid < 19) {
     // new reference and the shift it represents, both in the compute type
-    const C m = (C)(((lds[tid] + lds[19 + tid]) + (lds[38 + tid] + lds[57 + tid])) / g.nx);
+    const double mean = ((lds[tid] + lds[19 + tid]) + (lds[38 + tid] + lds[57 + tid])) / g.nx;
+    const C m = (C)(mean * kStoreDown16);
     const C Dn = Drow[tid] + m;
     const C shift = Dn - Drow[tid];
     Drow[tid] = Dn;
@@ -103,7 +106,7 @@ __device__ __forceinline__ void rebase_row(S *__restrict__ buf, C *__restrict__ 
 #pragma unroll
     for (int q = 0; q < 19; ++q) {
       S *p = buf + q * g.plane + r0 + x;
-      *p = to_store<S, C, SR>((C)*p - sh[q], ns, q);
+      *p = to_store<S, C, SR>(((C)*p * C(kStoreDown16) - sh[q]) * C(kStoreUp16), ns, q);
     }
   }
   __syncthreads(); // lds is reused by the next row

@@ -12,11 +12,12 @@
 // Storage: S is the stored type (double, float or _Float16), C the compute
 // type.  Every population is stored as its deviation from the rest state at
 // unit density and B = (0, B0) -- f_alpha - w_alpha, g_alpha,x and
-// g_alpha,y - W_alpha B0 -- minus a per-row reference D[y][plane] kept in the
-// compute type (zero until a rebase moves each row's x-mean into it), so the
-// stored values carry only what the flow, the induced field and their
-// x-variation put into them.  A pulled value is decoded with the reference of
-// the row it comes from; a stored value is encoded with its own row's.
+// g_alpha,y - W_alpha B0.  Binary16 storage further subtracts a per-row
+// reference D[y][plane] kept in the compute type (zero until a rebase moves
+// each row's x-mean into it) and scales by 2^12, so the stored values carry
+// only what the flow, the induced field and their x-variation put into
+// them.  A pulled value is decoded with the reference of the row it comes
+// from; a stored value is encoded with its own row's.
 //
 // Method references (Yahia & Premnath, arXiv 2112.13930):
 //   equilibria, source, moments: Secs. IV, V;  J_z: Sec. IV;  F = J x B: Sec. II
@@ -196,13 +197,20 @@ constexpr bool kUseSR = (sizeof(C) > sizeof(S)) &&
                         ((sizeof(S) == 4 && LKS_SR_FP32) || (sizeof(S) == 2 && LKS_SR_FP16));
 
 // Binary16 storage keeps a per-row reference D[y][plane] (compute type) that
-// a rebase fills with each row's x-mean; wider storage keeps none.
+// a rebase fills with each row's x-mean; wider storage keeps none.  It also
+// stores its values multiplied by 2^12 (exact): once rebased, a steady row's
+// stored values are far below binary16's normal range (2^-14), where the
+// grid would be a fixed 2^-24 and set the noise floor of stochastic
+// rounding; scaled, they keep 11 significant bits down to 2^-26.  Stored
+// magnitudes stay below 16 (deviations of order one), far from the binary16
+// limit 65504.
 template <typename S> constexpr bool kRowRef = sizeof(S) == 2;
+constexpr double kStoreUp16 = 4096.0, kStoreDown16 = 1.0 / 4096.0;
 
 // Decode a stored value with the reference row it belongs to.
 template <typename S, typename C>
 __device__ __forceinline__ C dec(C v, const C *__restrict__ row, int plane) {
-  if constexpr (kRowRef<S>) return v + row[plane];
+  if constexpr (kRowRef<S>) return v * C(kStoreDown16) + row[plane];
   else return v;
 }
 
@@ -342,7 +350,7 @@ __device__ __forceinline__ void node_finish(const Geom &g, const Coef<C> &k,
   const uint32_t ns = SR ? node_seed(sseed, (uint32_t)(y * g.nx + x)) : 0u;
   // encode a post-collision value against this row's reference
   auto put = [&](C v, int plane) -> S {
-    if constexpr (kRowRef<S>) v -= Dy[plane];
+    if constexpr (kRowRef<S>) v = (v - Dy[plane]) * C(kStoreUp16);
     return to_store<S, C, SR>(v, ns, plane);
   };
   const C om = k.omega_f, ka = k.kappa_f;

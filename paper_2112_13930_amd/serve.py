@@ -231,50 +231,57 @@ def serve_requests_from_mix(n, seed, nx_range=(4, 32), ny_range=(16, 48), ha_ran
     return reqs
 
 
-def serve_benchmark(n_requests=48, rate=200.0, seed=5, precision="fp32", tol=1e-8,
-                    check_every=200, max_steps=200_000, log=None):
-    """Serve a fixed number of Poisson-arriving requests with continuous
-    batching, then solve the same requests sequentially; report solves/s and
-    p50/p99 latency for both."""
+def _summary(lat, statuses, span, n):
+    return {"makespan_s": round(span, 3), "solves_per_s": round(n / span, 2),
+            "p50_latency_s": round(percentile(lat, 50), 4),
+            "p99_latency_s": round(percentile(lat, 99), 4), "statuses": statuses}
+
+
+def serve_benchmark(n_requests=48, rate=200.0, seed=5, precisions=("fp32", "fp16"),
+                    baseline_precision="fp32", tol=1e-8, check_every=200, max_steps=200_000,
+                    log=None):
+    """Serve a fixed set of Poisson-arriving requests with continuous batching
+    in each storage precision, then solve the same requests one after another
+    with the plain single-channel path in baseline_precision; report solves/s
+    and p50/p99 latency for each."""
     import torch
-    reqs = serve_requests_from_mix(n_requests, seed, precision=precision, rate=rate)
-    ex = GpuExecutor(precision, max_channels=max(64, n_requests), max_nodes=1 << 22)
-    srv = Server(ex, tol=tol, check_every=check_every, max_steps=max_steps)
-    for r in reqs:
-        srv.submit(r)
-    t0 = time.perf_counter()
-    done = srv.run()
-    torch.cuda.synchronize()
-    makespan = time.perf_counter() - t0
-    ex.close()
-    lat = [r.latency for r in done]
-    if log:
-        log(f"serving: batched makespan {makespan:.2f} s for {len(done)} requests")
-    seq_reqs = serve_requests_from_mix(n_requests, seed, precision=precision, rate=rate)
-    seq, seq_span = sequential_baseline(seq_reqs, precision=precision, tol=tol,
+    out = {"requests": n_requests, "arrival_rate_per_s": rate, "tol": tol,
+           "check_every": check_every, "max_steps": max_steps,
+           "workload": "uneven channels nx 4-32, ny 16-48, Ha 2-30, c = 0 (10%) or "
+                       "log-uniform in [1e-3, 1], body or shear driven, link or moment walls; "
+                       "Poisson arrivals",
+           "batched": {}}
+    steps_by = {}
+    for prec in precisions:
+        reqs = serve_requests_from_mix(n_requests, seed, precision=prec, rate=rate)
+        ex = GpuExecutor(prec, max_channels=max(64, n_requests), max_nodes=1 << 22)
+        srv = Server(ex, tol=tol, check_every=check_every, max_steps=max_steps)
+        for r in reqs:
+            srv.submit(r)
+        t0 = time.perf_counter()
+        done = srv.run()
+        torch.cuda.synchronize()
+        span = time.perf_counter() - t0
+        ex.close()
+        statuses = {}
+        for r in done:
+            statuses[r.status] = statuses.get(r.status, 0) + 1
+        out["batched"][prec] = _summary([r.latency for r in done], statuses, span, len(done))
+        out["batched"][prec]["mean_steps"] = round(statistics.mean(r.steps for r in done), 1)
+        steps_by[prec] = [r.steps for r in done]
+        if log:
+            log(f"serving: rate {rate}/s, batched {prec}: {span:.2f} s for {len(done)} requests")
+    seq_reqs = serve_requests_from_mix(n_requests, seed, precision=baseline_precision, rate=rate)
+    seq, seq_span = sequential_baseline(seq_reqs, precision=baseline_precision, tol=tol,
                                         check_every=check_every, max_steps=max_steps, log=log)
-    seq_lat = [s["latency"] for s in seq]
-    same_steps = sum(1 for a, b in zip(done, seq) if a.steps == b["steps"])
-    statuses, seq_statuses = {}, {}
-    for r in done:
-        statuses[r.status] = statuses.get(r.status, 0) + 1
+    statuses = {}
     for r in seq:
-        seq_statuses[r["status"]] = seq_statuses.get(r["status"], 0) + 1
-    return {
-        "requests": len(done), "arrival_rate_per_s": rate, "precision": precision,
-        "tol": tol, "check_every": check_every,
-        "workload": "uneven channels nx 4-32, ny 16-48, Ha 2-30, c = 0 (10%) or "
-                    "log-uniform in [1e-3, 1], body or shear driven, link or moment walls; "
-                    "Poisson arrivals",
-        "batched": {"makespan_s": round(makespan, 3), "solves_per_s": round(len(done) / makespan, 2),
-                    "p50_latency_s": round(percentile(lat, 50), 4),
-                    "p99_latency_s": round(percentile(lat, 99), 4), "statuses": statuses},
-        "sequential": {"makespan_s": round(seq_span, 3),
-                       "solves_per_s": round(len(seq) / seq_span, 2),
-                       "p50_latency_s": round(percentile(seq_lat, 50), 4),
-                       "p99_latency_s": round(percentile(seq_lat, 99), 4),
-                       "statuses": seq_statuses},
-        "speedup_solves_per_s": round(seq_span / makespan, 2),
-        "same_stop_step": f"{same_steps}/{len(done)}",
-        "mean_steps": round(statistics.mean(r.steps for r in done), 1),
-    }
+        statuses[r["status"]] = statuses.get(r["status"], 0) + 1
+    out["sequential_" + baseline_precision] = _summary([r["latency"] for r in seq], statuses,
+                                                       seq_span, len(seq))
+    out["speedup_solves_per_s"] = {
+        prec: round(seq_span / out["batched"][prec]["makespan_s"], 2) for prec in precisions}
+    if baseline_precision in steps_by:
+        same = sum(1 for a, b in zip(steps_by[baseline_precision], seq) if a == b["steps"])
+        out["same_stop_step_" + baseline_precision] = f"{same}/{len(seq)}"
+    return out

@@ -8,7 +8,15 @@ config1_hartmann_link.json
     column is identical, so one column is stored), plus the Chang-Lundgren
     profile at the same rows for reference.
 
-Run:  python tests/golden/make_golden.py
+precision_case_512.json
+    The binary16 precision case: 512 rows, link-based walls,
+    tau_f = tau_m = 0.8, Ha = 50, c = 0.5 on both walls, F_x set for
+    u_max = 0.003 (u_max = 0.05 drives the scheme non-finite at this size).
+    Stores the oracle's u_x and B_x rows after 20 000 and 100 000 steps and at
+    steady state (per-step relative change below 1e-12, checked every 1000
+    steps), and the Chang-Lundgren profile at the same rows.
+
+Run:  python tests/golden/make_golden.py [config1] [precision]
 """
 import json
 import os
@@ -46,8 +54,47 @@ def config1():
     }
 
 
+def precision_case(nthreads=8):
+    from oracle import steady
+    p = derive.hartmann_params(1, 512, oracle.LINK, 0.8, 0.8, 50.0, 0.5, 0.003)
+    out = {
+        "description": "Hartmann channel, 512 rows, link-based, tau_f=tau_m=0.8, Ha=50, c=0.5, "
+                       "u_max=0.003, from rest; oracle FP64 observables (one column)",
+        "params": {"ny": 512, "bc": "link", "tau_f": 0.8, "tau_m": 0.8, "ha": 50.0, "c": 0.5,
+                   "u_max": 0.003, "a": p.a, "b0": p.b0, "fx": p.fx},
+    }
+    s = oracle.init_state(p)
+    done = 0
+    for n in (20000, 100000):
+        oracle.run(p, s, n - done, nthreads=nthreads)
+        done = n
+        o = oracle.observe(p, s)
+        out[f"ux_{n}"] = o["ux"][:, 0].tolist()
+        out[f"bx_{n}"] = o["bx"][:, 0].tolist()
+    _, o, n, r = steady.run_to_steady(p, tol=1e-12, check_every=1000, max_steps=5_000_000,
+                                      nthreads=nthreads)
+    out["steady_steps"] = n
+    out["steady_residual"] = r
+    out["ux_steady"] = o["ux"][:, 0].tolist()
+    out["bx_steady"] = o["bx"][:, 0].tolist()
+    xi = analytic.node_xi(512, oracle.LINK)
+    ua, ba = analytic.chang_lundgren(xi, 50.0, 0.5)
+    out["chang_lundgren_u_star"] = ua.tolist()
+    out["chang_lundgren_b_star"] = ba.tolist()
+    out["u_ref"] = derive.u_ref_hartmann(p.fx, 0.8, p.a)
+    out["b_ref"] = derive.b_ref_hartmann(p.fx, 0.8, 0.8, p.a)
+    return out
+
+
 if __name__ == "__main__":
-    out = os.path.join(HERE, "config1_hartmann_link.json")
-    with open(out, "w") as fh:
-        json.dump(config1(), fh, indent=1)
-    print("wrote", out)
+    which = sys.argv[1:] or ["config1", "precision"]
+    if "config1" in which:
+        out = os.path.join(HERE, "config1_hartmann_link.json")
+        with open(out, "w") as fh:
+            json.dump(config1(), fh, indent=1)
+        print("wrote", out)
+    if "precision" in which:
+        out = os.path.join(HERE, "precision_case_512.json")
+        with open(out, "w") as fh:
+            json.dump(precision_case(), fh, indent=1)
+        print("wrote", out)

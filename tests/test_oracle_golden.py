@@ -37,3 +37,34 @@ def test_config1_close_to_chang_lundgren():
     # 20000 steps from rest at a = 32 is close to, not at, the steady state
     assert np.sqrt(np.mean((u - ua) ** 2)) / np.abs(ua).max() < 2e-2
     assert np.sqrt(np.mean((b - ba) ** 2)) / np.abs(ba).max() < 2e-2
+
+
+PREC = os.path.join(os.path.dirname(__file__), "golden", "precision_case_512.json")
+
+
+def test_precision_case_fixture_matches_oracle(orc):
+    """512-row precision case (Ha = 50, c = 0.5): the stored 20 000-step
+    columns are what the oracle computes now."""
+    g = json.load(open(PREC))
+    p = derive.hartmann_params(1, 512, oracle.LINK, 0.8, 0.8, 50.0, 0.5, 0.003)
+    assert p.b0 == g["params"]["b0"] and p.fx == g["params"]["fx"]
+    s = orc.init_state(p)
+    orc.run(p, s, 20000, nthreads=4)
+    o = orc.observe(p, s)
+    assert np.array_equal(o["ux"][:, 0], np.array(g["ux_20000"]))
+    assert np.array_equal(o["bx"][:, 0], np.array(g["bx_20000"]))
+
+
+def test_precision_case_steady_state_is_chang_lundgren():
+    """The stored steady state agrees with the closed form (Sec. VIII's
+    Chang-Lundgren profile) to the discretisation error at a = 256, Ha = 50
+    (second order: of order (Ha / a)^2 / 10 relative), and is symmetric."""
+    g = json.load(open(PREC))
+    assert g["steady_residual"] < 1e-12
+    u = np.array(g["ux_steady"]) / g["u_ref"]
+    b = np.array(g["bx_steady"]) / g["b_ref"]
+    ua, ba = np.array(g["chang_lundgren_u_star"]), np.array(g["chang_lundgren_b_star"])
+    assert np.sqrt(np.mean((u - ua) ** 2)) / np.sqrt(np.mean(ua ** 2)) < 2e-3
+    assert np.sqrt(np.mean((b - ba) ** 2)) / np.sqrt(np.mean(ba ** 2)) < 2e-3
+    assert np.abs(u - u[::-1]).max() < 1e-9 * np.abs(u).max()
+    assert np.abs(b + b[::-1]).max() < 1e-9 * np.abs(b).max()
