@@ -102,11 +102,12 @@ __device__ __forceinline__ void rebase_row(S *__restrict__ buf, C *__restrict__ 
 #pragma unroll
   for (int q = 0; q < 19; ++q) sh[q] = (C)lds[76 + q];
   for (int x = tid; x < g.nx; x += 256) {
-    const uint32_t ns = SR ? node_seed(seed, (uint32_t)(y * g.nx + x)) : 0u;
+    Rng rng(SR ? node_seed(seed, (uint32_t)(y * g.nx + x)) : 0u);
 #pragma unroll
     for (int q = 0; q < 19; ++q) {
       S *p = buf + q * g.plane + r0 + x;
-      *p = to_store<S, C, SR>(((C)*p * C(kStoreDown16) - sh[q]) * C(kStoreUp16), ns, q);
+      *p = to_store<S, C, SR>(((C)*p * C(kStoreDown16) - sh[q]) * C(kStoreUp16),
+                              SR ? rng.next() : 0u);
     }
   }
   __syncthreads(); // lds is reused by the next row

@@ -37,6 +37,11 @@ struct ChanDesc {
   int tile_first; // first tile of this channel in the list
   int tile_count;
   uint32_t step_base; // global step count at admission
+  // node index -> row without a hardware divide: y = (umulhi(i, m) + i) >> s
+  // with s = ceil(log2 nx), m = floor(2^32 (2^s - nx) / nx) + 1 (exact for
+  // every i < 2^31)
+  uint32_t nx_magic;
+  int nx_shift;
   Coef<float> kf;
   Coef<double> kd;
 };
@@ -119,7 +124,8 @@ __global__ __launch_bounds__(kTileThreads) void k_batch_step(
       for (int j = 0; j < tl.h; ++j) {
         const int i = tl.x0 + (int)threadIdx.x + j * kTileThreads;
         if (i < n) {
-          const int y = i / c.g.nx;
+          const uint32_t iu = (uint32_t)i;
+          const int y = (int)(((uint64_t)__umulhi(iu, c.nx_magic) + iu) >> c.nx_shift);
           one(i - y * c.g.nx, y);
         }
       }
@@ -679,6 +685,12 @@ int lks_mhd_batch_admit(lks_mhd_batch_t *b, const lks_mhd_params *p, int32_t *sl
   d.rec = reinterpret_cast<double *>(base + 2 * state);
   d.ref = base + 2 * state + align256((size_t)2 * q.nx * q.ny * sizeof(double));
   d.g = Geom{q.nx, q.ny, q.nx, plane};
+  {
+    int sh = 0;
+    while ((1LL << sh) < (long long)q.nx) ++sh;
+    d.nx_shift = sh;
+    d.nx_magic = (uint32_t)((((1ULL << 32) * ((1ULL << sh) - (uint64_t)q.nx)) / (uint64_t)q.nx) + 1ULL);
+  }
   d.bc = q.bc == LKS_BC_LINK ? BC_LINK : BC_MOMENT;
   // the initial state goes to buf[0]; at the next step the global parity is
   // b->parity, and the channel must read buf[0] then: phase = parity.

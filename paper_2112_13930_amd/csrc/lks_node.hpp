@@ -28,6 +28,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "lks_sr.hpp"
+
 // Arithmetic of the reduced-precision modes (compile-time; the defaults are
 // the product configuration):
 //   LKS_FP32_COMPUTE_DOUBLE  FP32-stored populations are computed in FP64.
@@ -101,93 +103,14 @@ __device__ __forceinline__ void st(S *__restrict__ p, C v) {
 // Round-to-nearest storage leaves the same rounding residual in every step
 // once the flow is steady, and slow modes integrate it; rounding to one of
 // the two neighbouring representable values with probabilities given by the
-// distances makes the residual change from step to step.  The random bits are
-// a counter-based hash of (channel-local step, node, plane), so a run is
-// reproducible bit for bit and independent of launch shape or batch mix.
-__device__ __forceinline__ uint32_t mix32(uint32_t x) {
-  x ^= x >> 16;
-  x *= 0x7feb352dU;
-  x ^= x >> 15;
-  x *= 0x846ca68bU;
-  x ^= x >> 16;
-  return x;
-}
-
-__device__ __forceinline__ uint32_t step_seed(uint32_t step) { return mix32(step * 0x9E3779B1U + 0x632BE5ABU); }
-
-// Seed of the re-encoding done by a rebase after `step` steps (a stream of
-// random bits distinct from the steps').
-__device__ __forceinline__ uint32_t rebase_seed(uint32_t step) { return mix32(step * 0x27D4EB2FU + 0x165667B1U); }
-
-__device__ __forceinline__ uint32_t node_seed(uint32_t sseed, uint32_t idx) {
-  return mix32(idx * 0x85EBCA77U ^ sseed);
-}
-
-__device__ __forceinline__ uint32_t plane_bits(uint32_t nseed, int plane) {
-  return mix32(nseed + (uint32_t)plane * 0xC2B2AE3DU);
-}
-
-template <typename T> struct BitsOf;
-template <> struct BitsOf<float> { using U = uint32_t; };
-template <> struct BitsOf<_Float16> { using U = uint16_t; };
-
-// Neighbour of h one unit in the last place up (+) or down (-).
-template <typename T>
-__device__ __forceinline__ T next_toward(T h, bool up) {
-  using U = typename BitsOf<T>::U;
-  constexpr U sign = U(U(1) << (sizeof(U) * 8 - 1));
-  U b = __builtin_bit_cast(U, h);
-  if (U(b & U(~sign)) == 0) return __builtin_bit_cast(T, U(up ? U(1) : U(sign | U(1))));
-  const bool neg = (b & sign) != 0;
-  b = (up != neg) ? U(b + 1) : U(b - 1);
-  return __builtin_bit_cast(T, b);
-}
-
-// A neighbour of v in T (v of the wider type W): the nearest, or for double
-// to binary16 the nearest to v rounded to binary32 first.  Every binary16
-// value is a binary32 value, so that rounding cannot cross a binary16 grid
-// point and the result is one of the two binary16 neighbours of v -- all that
-// stochastic rounding needs -- while hardware conversions replace the long
-// exact double-to-half sequence.
-template <typename T, typename W>
-__device__ __forceinline__ T neighbour(W v) {
-  if constexpr (sizeof(T) == 2 && sizeof(W) == 8) return static_cast<T>(static_cast<float>(v));
-  else return static_cast<T>(v);
-}
-
-// v (wider type W) rounded stochastically to T with 24 random bits of r.
-template <typename T, typename W>
-__device__ __forceinline__ T round_sr(W v, uint32_t r) {
-  const T h = neighbour<T, W>(v);
-  const W a = static_cast<W>(h);
-  if (a == v || !__builtin_isfinite(a)) return h;
-  const bool up = v > a;
-  const T o = next_toward(h, up);
-  const W g = __builtin_fabs(static_cast<W>(o) - a); // a power of two
-  const W d = __builtin_fabs(v - a);                  // exact (Sterbenz)
-  const W u = static_cast<W>(r >> 8) * W(1.0 / 16777216.0);
-  return (u * g < d) ? o : h;                         // P(o) = d / g
-}
-
+// distances makes the residual change from step to step (lks_sr.hpp).
 template <typename S, typename C, bool SR>
-__device__ __forceinline__ S to_store(C v, uint32_t nseed, int plane) {
+__device__ __forceinline__ S to_store(C v, uint32_t r) {
   if constexpr (SR) {
-    return round_sr<S, C>(v, plane_bits(nseed, plane));
+    return round_sr<S, C>(v, r);
   } else {
-    (void)nseed;
-    (void)plane;
+    (void)r;
     return static_cast<S>(v);
-  }
-}
-
-template <typename S, typename C, bool SR>
-__device__ __forceinline__ void store(S *__restrict__ p, C v, uint32_t nseed, int plane) {
-  if constexpr (SR) {
-    __builtin_nontemporal_store(round_sr<S, C>(v, plane_bits(nseed, plane)), p);
-  } else {
-    (void)nseed;
-    (void)plane;
-    __builtin_nontemporal_store(static_cast<S>(v), p);
   }
 }
 
@@ -347,11 +270,14 @@ __device__ __forceinline__ void node_finish(const Geom &g, const Coef<C> &k,
   if (MODE == MODE_MOMENTS) return;
 
   // ---- collide and store ----
-  const uint32_t ns = SR ? node_seed(sseed, (uint32_t)(y * g.nx + x)) : 0u;
+  // random words for the stochastic rounding of this node's 19 stores,
+  // drawn in plane order
+  Rng rng(SR ? node_seed(sseed, (uint32_t)(y * g.nx + x)) : 0u);
   // encode a post-collision value against this row's reference
   auto put = [&](C v, int plane) -> S {
+    (void)plane;
     if constexpr (kRowRef<S>) v = (v - Dy[plane]) * C(kStoreUp16);
-    return to_store<S, C, SR>(v, ns, plane);
+    return to_store<S, C, SR>(v, SR ? rng.next() : 0u);
   };
   const C om = k.omega_f, ka = k.kappa_f;
   const C usq15 = C(1.5) * (ux * ux + uy * uy);

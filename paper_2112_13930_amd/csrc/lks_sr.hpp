@@ -1,0 +1,114 @@
+// Stochastic rounding of computed populations to their storage type, and the
+// random bits it uses.  Host-compilable (the unit test checks it on the CPU).
+//
+// Rounding: the result is one of the two neighbours of v in the target
+// format, the farther one with probability |v - nearest lower-magnitude
+// neighbour| / spacing, resolved to 2^-32 of the spacing.  It is computed by
+// adding uniform random bits below the target's last place to the magnitude
+// bits of v and truncating there (a carry out of the kept bits rounds up,
+// across a binade too), or, from binary64 to binary16, as g floor(v/g + u)
+// with the target spacing g.  Values beyond the target's range become
+// infinite (and are reported as non-finite by the residual check).
+//
+// Random bits: one hashed seed per node and step (counter-based, so a run is
+// reproducible bit for bit and independent of launch shape or batch mix),
+// then one xorshift32 step (Marsaglia 2003) per stored value.
+#pragma once
+
+#include <stdint.h>
+
+#if defined(__HIPCC__) || defined(__HIP__)
+#define LKS_HD __host__ __device__
+#else
+#define LKS_HD
+#endif
+
+namespace lks {
+
+LKS_HD inline uint32_t mix32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352dU;
+  x ^= x >> 15;
+  x *= 0x846ca68bU;
+  x ^= x >> 16;
+  return x;
+}
+
+// Per-node stream of 32-bit random words.
+struct Rng {
+  uint32_t s;
+  LKS_HD explicit Rng(uint32_t seed) : s(seed | 1u) {} // xorshift needs s != 0
+  LKS_HD uint32_t next() {
+    s ^= s << 13;
+    s ^= s >> 17;
+    s ^= s << 5;
+    return s;
+  }
+};
+
+LKS_HD inline uint32_t step_seed(uint32_t step) { return mix32(step * 0x9E3779B1U + 0x632BE5ABU); }
+
+// Seed of the re-encoding done by a rebase after `step` steps (a stream
+// distinct from the steps').
+LKS_HD inline uint32_t rebase_seed(uint32_t step) { return mix32(step * 0x27D4EB2FU + 0x165667B1U); }
+
+LKS_HD inline uint32_t node_seed(uint32_t sseed, uint32_t idx) {
+  return mix32(idx * 0x85EBCA77U ^ sseed);
+}
+
+LKS_HD inline uint64_t bits64(double v) { return __builtin_bit_cast(uint64_t, v); }
+LKS_HD inline double dbl(uint64_t b) { return __builtin_bit_cast(double, b); }
+LKS_HD inline uint32_t bits32(float v) { return __builtin_bit_cast(uint32_t, v); }
+LKS_HD inline float flt(uint32_t b) { return __builtin_bit_cast(float, b); }
+
+// binary64 -> binary32: 29 bits below binary32's last place.  (Inputs below
+// binary32's normal range, |v| < 2^-126, are rounded once more to nearest.)
+LKS_HD inline float sr_f32(double v, uint32_t r) {
+  const uint64_t b = (bits64(v) + (uint64_t)(r >> 3)) & ~(uint64_t)0x1FFFFFFFu;
+  return (float)dbl(b); // exact: 24 significant bits left
+}
+
+// binary64 -> binary16: with the spacing g = 2^(E - 10) of binary16 at
+// v's exponent E (E held at -14 or above: the subnormal spacing is a fixed
+// 2^-24), the result is g floor(v / g + u) for u uniform in [0, 1), whose
+// expectation is v for either sign.  v / g has at most 11 integer bits, so
+// v / g + u is exact to 2^-42 and the scalings by powers of two are exact.
+LKS_HD inline _Float16 sr_f16(double v, uint32_t r) {
+  int e;
+  (void)__builtin_frexp(v, &e);           // v = m 2^e, 1/2 <= |m| < 1
+  const int E = e - 1 < -14 ? -14 : e - 1; // binary16 exponent of the spacing
+  const double z = __builtin_ldexp(v, 10 - E);
+  const double u = (double)r * 0x1p-32;
+  const double m = __builtin_ldexp(__builtin_floor(z + u), E - 10);
+  return (_Float16)(float)m;               // both conversions exact
+}
+
+// binary32 -> binary16 (binary16 storage with FP32 arithmetic).
+LKS_HD inline _Float16 sr_f16(float v, uint32_t r) {
+  const uint32_t b = bits32(v);
+  const uint32_t sign = b & 0x80000000u;
+  const uint32_t mag = b ^ sign;
+  const int e = (int)(mag >> 23) - 127;
+  if (e < -24) {
+    const float p = (float)(r >> 8) * 0x1p-48f; // uniform in [0, 2^-24)
+    return (_Float16)flt(sign | (p < flt(mag) ? 0x33800000u : 0u));
+  }
+  const int k = e >= -14 ? 13 : -1 - e;
+  const uint32_t t = (mag + (r >> (32 - k))) & ~((1u << k) - 1u);
+  return (_Float16)flt(sign | t); // exact
+}
+
+// Stochastic rounding of v (compute type C) to storage type S; identity for
+// equal types.
+template <typename S, typename C>
+LKS_HD inline S round_sr(C v, uint32_t r) {
+  if constexpr (sizeof(S) == sizeof(C)) {
+    (void)r;
+    return (S)v;
+  } else {
+    if constexpr (sizeof(S) == 4) return sr_f32(v, r);
+    else return sr_f16(v, r);
+  }
+}
+
+} // namespace lks

@@ -1,0 +1,114 @@
+// Host check of the stochastic rounding used for stored populations
+// (paper_2112_13930_amd/csrc/lks_sr.hpp): for each test value v the result
+// must be one of the two neighbours of v in the target format, and over a
+// stratified sweep of the random word the share of results on the larger
+// magnitude side must equal the exact probability
+//   (|v| - |lo|) / (|hi| - |lo|)
+// to within the sweep's resolution.  Exactly representable values must come
+// back unchanged.
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <random>
+
+#include "lks_sr.hpp"
+
+using lks::sr_f16;
+using lks::sr_f32;
+
+static int fails = 0;
+static long checks = 0;
+
+template <typename T> static uint32_t tbits(T x) {
+  if constexpr (sizeof(T) == 4) return __builtin_bit_cast(uint32_t, x);
+  else return __builtin_bit_cast(uint16_t, x);
+}
+template <typename T> static T from_bits(uint32_t b) {
+  if constexpr (sizeof(T) == 4) return __builtin_bit_cast(float, b);
+  else return __builtin_bit_cast(_Float16, (uint16_t)b);
+}
+
+// Neighbours lo (smaller magnitude) and hi (larger magnitude) of |v| in T,
+// found by stepping the bit pattern of the nearest value.
+template <typename T> static void neighbours(long double av, T &lo, T &hi) {
+  T h = (T)av;  // nearest (or the largest finite if av overflows: not tested)
+  if ((long double)h > av) {
+    hi = h;
+    lo = from_bits<T>(tbits(h) - 1);
+    if (tbits(h) == 0) lo = h;
+  } else {
+    lo = h;
+    hi = from_bits<T>(tbits(h) + 1);
+  }
+}
+
+template <typename T, typename W, typename F>
+static void check(W v, F round, int nsweep) {
+  const long double av = std::fabs((long double)v);
+  T lo, hi;
+  neighbours<T>(av, lo, hi);
+  const bool exact = (long double)lo == av;
+  int up = 0;
+  for (int i = 0; i < nsweep; ++i) {
+    const uint32_t r = (uint32_t)(((uint64_t)i << 32) / (uint64_t)nsweep) + 977u;
+    const T res = round(v, r);
+    const long double ar = std::fabs((long double)res);
+    const bool neg_ok = std::signbit((double)v) ? (std::signbit((double)res) || ar == 0) : !std::signbit((double)res);
+    ++checks;
+    if (!neg_ok || (ar != (long double)lo && ar != (long double)hi) || (exact && ar != av)) {
+      if (fails++ < 10)
+        printf("bad result: v=%.17Lg res=%.17Lg lo=%.17Lg hi=%.17Lg\n", (long double)v, (long double)res,
+               (long double)lo, (long double)hi);
+      return;
+    }
+    up += (ar == (long double)hi && !exact) ? 1 : 0;
+  }
+  if (!exact) {
+    const long double p = (av - (long double)lo) / ((long double)hi - (long double)lo);
+    const long double want = p * nsweep;
+    if (std::fabs((long double)up - want) > 1.5L) {
+      if (fails++ < 10)
+        printf("bad probability: v=%.17Lg p=%.9Lf got %d of %d (want %.2Lf)\n", (long double)v, p, up,
+               nsweep, want);
+    }
+  }
+}
+
+int main() {
+  std::mt19937_64 g(12345);
+  std::uniform_real_distribution<double> U(0.0, 1.0);
+  const int N = 4096;
+  auto f32 = [](double v, uint32_t r) { return sr_f32(v, r); };
+  auto f16d = [](double v, uint32_t r) { return sr_f16(v, r); };
+  auto f16f = [](float v, uint32_t r) { return sr_f16(v, r); };
+  for (int t = 0; t < 4000; ++t) {
+    // magnitudes spread over many binades, both signs
+    const double mag = std::exp2(-40.0 + 56.0 * U(g)) * (1.0 + U(g));
+    const double v = (t & 1) ? -mag : mag;
+    if (std::fabs(v) < 65504.0) {
+      check<_Float16>(v, f16d, N);
+      check<_Float16>((float)v, f16f, N);
+    }
+    if (std::fabs(v) > 1e-30) check<float>(v, f32, N);
+  }
+  // beyond binary16's range the result is infinite
+  for (double v : {65536.0, -70000.0, 1e6}) {
+    ++checks;
+    if (!std::isinf((double)sr_f16(v, 12345u)) || !std::isinf((double)sr_f16((float)v, 12345u))) {
+      ++fails;
+      printf("no overflow to inf for %g\n", v);
+    }
+  }
+  // binary16 subnormal range, the boundaries and exact values
+  const double special[] = {0.0, 0x1p-24, 0x1p-25, 0x1.8p-25, 0x1.fffp-25, 0x1.8p-24, 0x1p-14,
+                            0x1.ffcp-15, 0x1.ffdp-15, 0x1p-15 * 3, 1.0, 1.0 + 0x1p-11, 65504.0,
+                            0.1, 1.0 / 3, 0x1.0000001p0, -0x1p-20, -0.0};
+  for (double v : special) {
+    check<_Float16>(v, f16d, N);
+    check<_Float16>((float)v, f16f, N);
+    if (v == 0 || std::fabs(v) > 1e-30) check<float>(v, f32, N);
+  }
+  printf("%s: %ld results checked, %d failures\n", fails ? "FAIL" : "OK", checks, fails);
+  return fails ? 1 : 0;
+}
