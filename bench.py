@@ -24,7 +24,8 @@ Printed as one JSON line with, besides the contract fields:
                 case; the batched launch over 256 uneven channels (FP32
                 against sequential single-channel launches, and binary16);
                 the continuous-batching solve service (FP32 and binary16)
-                against sequential plain FP32 solves at three arrival rates.
+                against sequential plain FP32 solves at six arrival rates;
+                the headline step on a developed (random) state.
 
 Profiling helpers (used to write profiles/*):
   --profile-run     only warm-up + timed steps of the headline, plus a copy of
@@ -101,6 +102,33 @@ def headline(torch, args):
     return {"wall": wall, "per_step": per_step, "nodes": nodes, "finite": finite, "umax": umax}
 
 
+def developed_state_rate(torch, steps=200, warmup=10):
+    """The headline step on an x- and y-dependent random state (every value
+    away from rest, so no stored value is exact): the rate of a developed
+    flow, beside the from-rest rate the workload prescribes."""
+    from paper_2112_13930_amd.channel import Channel
+    from paper_2112_13930_amd.workloads import random_populations
+    out = {}
+    s0 = torch.from_numpy(random_populations(4096, 4096, seed=5, b0=0.0023))
+    for prec, bpn in (("fp32", 152), ("fp16", 76)):
+        ch = Channel(**dict(HEADLINE, precision=prec), stream=torch.cuda.Stream())
+        ch.load_state(s0)
+        ch.step(warmup)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(ch.stream)
+        ch.step(steps)
+        e1.record(ch.stream)
+        torch.cuda.synchronize()
+        per_step = e0.elapsed_time(e1) / 1e3 / steps
+        ch.close()
+        gbs = bpn * 4096 * 4096 / per_step / 1e9
+        out[prec] = {"mlups": round(4096 * 4096 / per_step / 1e6, 1), "gbs": round(gbs, 1),
+                     "frac_hbm": round(gbs / PEAK_HBM_GBS, 3)}
+    return out
+
+
 def sweep(torch, steps=100, warmup=10):
     """Config sweep: Ha in {10, 50, 100} x c in {0, 1e-2, 1, 1e2, inf} x link/moment."""
     from paper_2112_13930_amd.channel import Channel
@@ -160,6 +188,26 @@ def other_precisions(torch, steps=200, warmup=20, err_steps=100_000):
                     "steps from rest; relative L2 of u_x and B_x (binary16 modes rebase every "
                     "1000 steps)",
             **errs}
+        # binary16 (FP64 arithmetic) run to steady state against the oracle's
+        ch = Channel(512, 512, precision="fp16", stream=torch.cuda.Stream(), **kw)
+        ch.set_graph(40)
+        t0 = time.perf_counter()
+        rc, steps_done, res, _ = ch.run_to_steady(tol=1e-9, check_every=1000, max_steps=3_000_000)
+        dt = time.perf_counter() - t0
+        m = ch.moments()
+        ux = m["ux"].cpu().numpy()
+        bx = m["bx"].cpu().numpy()
+        ch.close()
+        ru = np.asarray(gold["ux_steady"])[:, None]
+        rb = np.asarray(gold["bx_steady"])[:, None]
+        out["steady_state_fp16_vs_fp64_oracle"] = {
+            "case": "the same channel run to steady state: binary16 through run_to_steady "
+                    "(windows of 1000 steps, tol 1e-9, rebase per window) against the oracle's "
+                    f"steady state ({gold['steady_steps']} steps, per-step change < 1e-12)",
+            "status": int(rc), "steps": int(steps_done), "residual": float(res),
+            "seconds": round(dt, 1),
+            "ux": float(np.linalg.norm(ux - ru) / (np.linalg.norm(ru) * math.sqrt(512))),
+            "bx": float(np.linalg.norm(bx - rb) / (np.linalg.norm(rb) * math.sqrt(512)))}
     return out
 
 
@@ -233,7 +281,7 @@ def batched(torch, precision="fp32", steps=1000, warmup=20, seed=2024, sequentia
     return out
 
 
-def serving(torch, rates=(50.0, 200.0, 2000.0), n_requests=48, seed=5):
+def serving(torch, rates=(50.0, 100.0, 200.0, 500.0, 1000.0, 2000.0), n_requests=48, seed=5):
     from paper_2112_13930_amd.serve import serve_benchmark
     return [serve_benchmark(n_requests=n_requests, rate=r, seed=seed, log=log) for r in rates]
 
@@ -429,6 +477,8 @@ def main():
     }
     if not args.quick:
         extras = {}
+        log("developed state ...")
+        extras["headline_on_developed_state"] = developed_state_rate(torch)
         log("sweep ...")
         extras["config_sweep_fp32"] = sweep(torch)
         log("precisions ...")
