@@ -322,6 +322,77 @@ int lks_mhd_batch_moments(lks_mhd_batch_t *b, int32_t slot, double *rho,
 int lks_mhd_batch_save_state(lks_mhd_batch_t *b, int32_t slot,
                              double *dev_pops);
 
+/* ------------------------------------------------------------------------ */
+/* Three-dimensional channel: x and z periodic, Shercliff walls at y = 0 and */
+/* y = ny - 1 (the paper's schemes, which it states extend readily to three  */
+/* dimensions, Sec. IX).                                                      */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Lattices: D3Q19 for f (weights 1/3, 1/18, 1/36, c_s^2 = 1/3) and D3Q7 for
+ * each of the three components of g with rest weight 0 and 1/6 on the six
+ * axis links (c_sm^2 = 1/3, the paper's value).  These are the weights whose
+ * e_z sums give the paper's D2Q9 and D2Q5, so a z-invariant run reproduces
+ * the two-dimensional scheme exactly.  Closures per component: the link-based
+ * theta closure (tangential B_x, B_z; the moving-wall term on B_x only, as
+ * walls move along x) and anti-bounce-back (normal B_y); the moment closure
+ * takes the paper's constraint set per tangential direction (Pi_y = 0,
+ * Pi_x = rho U, Pi_xx = rho (cs2 + U^2), Pi_z = 0, Pi_zz = rho cs2) and the
+ * discrete Shercliff relation for B_x and B_z, sum g_y = B0 for B_y.  J has
+ * three components, each from one antisymmetric pair of Lambda; u and J are
+ * solved together in closed form.
+ *
+ * base: the two-dimensional parameter set (nx, ny, bc, tau_f, tau_m, Ha or
+ * B0, c and U per wall, fx or u_max, fy, rho0; derived exactly as for one
+ * channel); precision LKS_FP64 or LKS_FP32 (binary32 storage, FP64
+ * arithmetic, stochastic rounding).  nz >= 1 periodic layers; fz the body
+ * force along z.  nx * ny * nz must be below 2^31.
+ */
+typedef struct lks_mhd3 lks_mhd3_t;
+typedef struct {
+  lks_mhd_params base;
+  int32_t nz;
+  int32_t reserved; /* 0 */
+  double fz;
+} lks_mhd3_params;
+
+/* Device bytes for create (0 and a message for invalid parameters); bytes
+ * of one step per node: 37 stored planes read and written, 592 (FP64) or
+ * 296 (FP32). */
+size_t lks_mhd3_state_bytes(const lks_mhd3_params *p);
+int lks_mhd3_bytes_per_node(int32_t precision);
+
+/* Create over a caller-owned, 256-byte aligned device buffer; initial state
+ * at rest with B = (0, B0, 0).  Asynchronous on hip_stream. */
+int lks_mhd3_create(const lks_mhd3_params *p, void *dev_buf, size_t bytes,
+                    void *hip_stream, lks_mhd3_t **out);
+int lks_mhd3_destroy(lks_mhd3_t *h);
+
+/* As lks_mhd_step / set_graph / steps_done / run_to_steady (residual over
+ * u_x and B_x of every node; flow_rate = sum u_x / (nx nz)). */
+int lks_mhd3_step(lks_mhd3_t *h, int64_t nsteps);
+int lks_mhd3_set_graph(lks_mhd3_t *h, int32_t steps_per_graph);
+int64_t lks_mhd3_steps_done(const lks_mhd3_t *h);
+int lks_mhd3_run_to_steady(lks_mhd3_t *h, double tol, int64_t check_every,
+                           int64_t max_steps, int64_t *steps_done,
+                           double *residual, double *flow_rate);
+
+/* Observables (device arrays of nx*ny*nz doubles, [z][y][x], or NULL):
+ * density, velocity, field and current density J = curl B. */
+int lks_mhd3_moments(lks_mhd3_t *h, double *rho, double *ux, double *uy,
+                     double *uz, double *bx, double *by, double *bz,
+                     double *jx, double *jy, double *jz);
+
+/* State exchange as raw FP64 populations [40][nz][ny][nx] (device):
+ * f_0..f_18 (D3Q19 order: rest; +x, +y, -x, -y; (1,1,0), (-1,1,0),
+ * (-1,-1,0), (1,-1,0); +z, -z; (1,0,1), (-1,0,-1), (1,0,-1), (-1,0,1);
+ * (0,1,1), (0,-1,-1), (0,1,-1), (0,-1,1)), then for B_x, B_y, B_z the seven
+ * D3Q7 populations (rest, +x, +y, -x, -y, +z, -z).  The rest populations
+ * of g have weight 0 and are zero; load_state ignores them.  load_state
+ * resets steps_done to `steps`.  Asynchronous. */
+int lks_mhd3_save_state(lks_mhd3_t *h, double *dev_pops);
+int lks_mhd3_load_state(lks_mhd3_t *h, const double *dev_pops, int64_t steps);
+
 #ifdef __cplusplus
 }
 #endif

@@ -38,6 +38,11 @@ class LksParams(ctypes.Structure):
     ]
 
 
+class LksParams3(ctypes.Structure):
+    _fields_ = [("base", LksParams), ("nz", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("fz", ctypes.c_double)]
+
+
 class LksDerived(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in
                 ("nu", "eta", "a", "b0", "fx", "fy", "theta_lower", "theta_upper",
@@ -96,6 +101,19 @@ SIGNATURES = {
     "lks_mhd_batch_steps_done": (_c.c_int64, [_vp, _c.c_int32]),
     "lks_mhd_batch_moments": (_c.c_int, [_vp, _c.c_int32, _vp, _vp, _vp, _vp, _vp, _vp]),
     "lks_mhd_batch_save_state": (_c.c_int, [_vp, _c.c_int32, _vp]),
+    "lks_mhd3_state_bytes": (_c.c_size_t, [ctypes.POINTER(LksParams3)]),
+    "lks_mhd3_bytes_per_node": (_c.c_int, [_c.c_int32]),
+    "lks_mhd3_create": (_c.c_int, [ctypes.POINTER(LksParams3), _vp, _c.c_size_t, _vp,
+                                   ctypes.POINTER(_vp)]),
+    "lks_mhd3_destroy": (_c.c_int, [_vp]),
+    "lks_mhd3_step": (_c.c_int, [_vp, _c.c_int64]),
+    "lks_mhd3_set_graph": (_c.c_int, [_vp, _c.c_int32]),
+    "lks_mhd3_steps_done": (_c.c_int64, [_vp]),
+    "lks_mhd3_run_to_steady": (_c.c_int, [_vp, _c.c_double, _c.c_int64, _c.c_int64, _i64p, _dp,
+                                          _dp]),
+    "lks_mhd3_moments": (_c.c_int, [_vp] + [_vp] * 10),
+    "lks_mhd3_save_state": (_c.c_int, [_vp, _vp]),
+    "lks_mhd3_load_state": (_c.c_int, [_vp, _vp, _c.c_int64]),
 }
 
 

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblks_mhd.so")
-SOURCES = ["lks_params.hip", "lks_single.hip", "lks_batch.hip"]
+SOURCES = ["lks_params.hip", "lks_single.hip", "lks_batch.hip", "lks_single3.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -1,0 +1,282 @@
+// Per-node update of the three-dimensional channel: pull streaming of the
+// D3Q19 flow and the three-component D3Q7 field populations, Shercliff
+// closures at the Hartmann walls y = 0 and y = ny - 1 (x and z periodic),
+// moments, the coupled u/J solve, collision and stochastically rounded store.
+//
+// Lattices (the three-dimensional extension of Secs. IV and V): D3Q19 with
+// weights 1/3, 1/18, 1/36 for f; D3Q7 for each field component with rest
+// weight 0 and 1/6 on the six axis links, so that c_sm^2 = 1/3 as in the
+// paper's D2Q5 and the e_z sums of a z-invariant state are exactly the
+// two-dimensional scheme.  The rest population of g is then identically zero
+// and is not stored.
+//
+// Stored planes (deviations from rest at unit density, B = (0, B0, 0)):
+//   0..18   f_q - w_q            D3Q19 (q as in the velocity table below)
+//   19..24  g_{a x}               a = +x, +y, -x, -y, +z, -z
+//   25..30  g_{a y} - B0/6
+//   31..36  g_{a z}
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lks_node.hpp"
+
+namespace lks {
+
+constexpr int kPlanes3 = 37;
+
+// D3Q19: 0 rest; 1..4 = +x, +y, -x, -y; 5..8 = (1,1,0), (-1,1,0), (-1,-1,0),
+// (1,-1,0); 9, 10 = +z, -z; 11..14 = (1,0,1), (-1,0,-1), (1,0,-1), (-1,0,1);
+// 15..18 = (0,1,1), (0,-1,-1), (0,1,-1), (0,-1,1).
+struct D3Q19 {
+  static constexpr int ex[19] = {0, 1, 0, -1, 0, 1, -1, -1, 1, 0, 0, 1, -1, 1, -1, 0, 0, 0, 0};
+  static constexpr int ey[19] = {0, 0, 1, 0, -1, 1, 1, -1, -1, 0, 0, 0, 0, 0, 0, 1, -1, 1, -1};
+  static constexpr int ez[19] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 1, -1, 1, -1, -1, 1, 1, -1, -1, 1};
+  static constexpr int opp[19] = {0, 3, 4, 1, 2, 7, 8, 5, 6, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+};
+// D3Q7 links without the rest: 0 = +x, 1 = +y, 2 = -x, 3 = -y, 4 = +z, 5 = -z.
+struct D3Q6 {
+  static constexpr int ex[6] = {1, 0, -1, 0, 0, 0};
+  static constexpr int ey[6] = {0, 1, 0, -1, 0, 0};
+  static constexpr int ez[6] = {0, 0, 0, 0, 1, -1};
+};
+
+template <typename C> struct W3 {
+  static constexpr C w(int q) {
+    return q == 0 ? C(1) / C(3) : ((q <= 4 || q == 9 || q == 10) ? C(1) / C(18) : C(1) / C(36));
+  }
+};
+
+struct Geom3 {
+  int nx, ny, nz;
+  long long plane; // elements per plane
+};
+
+struct NodeObs3 {
+  double rhop, ux, uy, uz, bx, by, bz, jx, jy, jz;
+};
+
+template <typename S, typename C, int BC, int MODE, bool SR>
+__device__ __forceinline__ void node3_update(const Geom3 &g, const Coef<C> &k, C fez,
+                                             const S *__restrict__ src, S *__restrict__ dst,
+                                             int x, int y, int z, NodeObs3 &obs, uint32_t sseed) {
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const long long P = g.plane;
+  const bool lo = (y == 0), hi = (y == ny - 1);
+  const int xs[3] = {x == 0 ? nx - 1 : x - 1, x, x == nx - 1 ? 0 : x + 1}; // x - e for e = 1, 0, -1
+  const int zs[3] = {z == 0 ? nz - 1 : z - 1, z, z == nz - 1 ? 0 : z + 1};
+  const long long own = ((long long)z * ny + y) * nx + x;
+  // source offset of a population moving along e (pull: from x - e)
+  auto srcoff = [&](int ex_, int ey_, int ez_) -> long long {
+    return ((long long)zs[1 - ez_] * ny + (y - ey_)) * nx + xs[1 - ex_];
+  };
+
+  // ---- pull streaming; populations entering from a wall are closed below ----
+  C f[19], gx[6], gy[6], gz[6];
+#pragma unroll
+  for (int q = 0; q < 19; ++q) {
+    const int ey_ = D3Q19::ey[q];
+    if ((ey_ == 1 && lo) || (ey_ == -1 && hi)) {
+      f[q] = C(0);
+      continue;
+    }
+    f[q] = ld<S, C>(src + q * P + srcoff(D3Q19::ex[q], ey_, D3Q19::ez[q]));
+  }
+#pragma unroll
+  for (int a = 0; a < 6; ++a) {
+    const int ey_ = D3Q6::ey[a];
+    if ((ey_ == 1 && lo) || (ey_ == -1 && hi)) {
+      gx[a] = gy[a] = gz[a] = C(0);
+      continue;
+    }
+    const long long o = srcoff(D3Q6::ex[a], ey_, D3Q6::ez[a]);
+    gx[a] = ld<S, C>(src + (19 + a) * P + o);
+    gy[a] = ld<S, C>(src + (25 + a) * P + o);
+    gz[a] = ld<S, C>(src + (31 + a) * P + o);
+  }
+
+  // ---- wall closures ----
+  if (BC == BC_LINK) {
+    // Half-way bounce-back with Ladd's term (+-U/6 on the in-plane diagonals);
+    // tangential field components by the theta-weighted Shercliff closure
+    // (moving-wall term on B_x only), the normal one by anti-bounce-back,
+    // all from the node's own post-collision values.
+    auto own_ = [&](int plane) { return ld<S, C>(src + plane * P + own); };
+    if (lo) {
+      f[2] = own_(4);
+      f[5] = own_(7) + k.lo.uw6;
+      f[6] = own_(8) - k.lo.uw6;
+      f[15] = own_(16);
+      f[17] = own_(18);
+      gx[1] = k.lo.r * own_(19 + 3) + k.lo.t;
+      gz[1] = k.lo.r * own_(31 + 3);
+      gy[1] = -own_(25 + 3);
+    }
+    if (hi) {
+      f[4] = own_(2);
+      f[7] = own_(5) - k.hi.uw6;
+      f[8] = own_(6) + k.hi.uw6;
+      f[16] = own_(15);
+      f[18] = own_(17);
+      gx[3] = k.hi.r * own_(19 + 1) + k.hi.t;
+      gz[3] = k.hi.r * own_(31 + 1);
+      gy[3] = -own_(25 + 1);
+    }
+  } else {
+    // On-node closures from the paper's constraint set taken per tangential
+    // direction (Pi_y = 0 fixes rho; Pi_x = rho U, Pi_xx = rho (cs2 + U^2),
+    // Pi_z = 0, Pi_zz = rho cs2), written for the deviations f' = f - w.
+    if (lo || hi) {
+      const int s = lo ? 1 : -1; // e_y of the unknowns
+      const C U = lo ? k.lo.u : k.hi.u;
+      // known sums (unknowns hold zero)
+      C k0 = C(0), kout = C(0), px = C(0), pxx = C(0), pz = C(0), pzz = C(0);
+#pragma unroll
+      for (int q = 0; q < 19; ++q) {
+        if (D3Q19::ey[q] == s) continue;
+        if (D3Q19::ey[q] == 0) k0 += f[q];
+        else kout += f[q];
+        px += C(D3Q19::ex[q]) * f[q];
+        pxx += C(D3Q19::ex[q] * D3Q19::ex[q]) * f[q];
+        pz += C(D3Q19::ez[q]) * f[q];
+        pzz += C(D3Q19::ez[q] * D3Q19::ez[q]) * f[q];
+      }
+      const C rhop = k0 + C(2) * kout;
+      const C sx = (C(1) + rhop) * U - px;
+      const C sxx = rhop * (C(1) / C(3)) + (C(1) + rhop) * U * U - pxx;
+      const C sz = -pz;
+      const C szz = rhop * (C(1) / C(3)) - pzz;
+      // lower: +x (1,1,0) = 5, -x (-1,1,0) = 6, +z (0,1,1) = 15, -z (0,1,-1) = 17, n = 2
+      // upper: +x (1,-1,0) = 8, -x (-1,-1,0) = 7, +z (0,-1,1) = 18, -z (0,-1,-1) = 16, n = 4
+      const C fxp = C(0.5) * (sxx + sx), fxm = C(0.5) * (sxx - sx);
+      const C fzp = C(0.5) * (szz + sz), fzm = C(0.5) * (szz - sz);
+      const C fn = kout - (fxp + fxm + fzp + fzm);
+      // field: tangential from the discrete Shercliff constraint, normal from
+      // sum g_y = B0 (for the deviations: sum g'_y = 0); in = +y link at the
+      // lower wall, -y at the upper
+      const C ox = gx[0] + gx[2] + gx[4] + gx[5];
+      const C oy = gy[0] + gy[2] + gy[4] + gy[5];
+      const C oz = gz[0] + gz[2] + gz[4] + gz[5];
+      if (lo) {
+        f[5] = fxp;
+        f[6] = fxm;
+        f[15] = fzp;
+        f[17] = fzm;
+        f[2] = fn;
+        gx[1] = k.lo.r * gx[3] - k.lo.s * ox + k.lo.t;
+        gz[1] = k.lo.r * gz[3] - k.lo.s * oz;
+        gy[1] = -(oy + gy[3]);
+      } else {
+        f[8] = fxp;
+        f[7] = fxm;
+        f[18] = fzp;
+        f[16] = fzm;
+        f[4] = fn;
+        gx[3] = k.hi.r * gx[1] - k.hi.s * ox + k.hi.t;
+        gz[3] = k.hi.r * gz[1] - k.hi.s * oz;
+        gy[3] = -(oy + gy[1]);
+      }
+    }
+  }
+
+  // ---- moments ----
+  C rhop = C(0), mx = C(0), my = C(0), mz = C(0);
+#pragma unroll
+  for (int q = 0; q < 19; ++q) {
+    rhop += f[q];
+    mx += C(D3Q19::ex[q]) * f[q];
+    my += C(D3Q19::ey[q]) * f[q];
+    mz += C(D3Q19::ez[q]) * f[q];
+  }
+  const C rho = C(1) + rhop;
+  const C bx = ((gx[0] + gx[1]) + (gx[2] + gx[3])) + (gx[4] + gx[5]);
+  const C byp = ((gy[0] + gy[1]) + (gy[2] + gy[3])) + (gy[4] + gy[5]);
+  const C by = k.b0 + byp;
+  const C bz = ((gz[0] + gz[1]) + (gz[2] + gz[3])) + (gz[4] + gz[5]);
+  // D = (L_yz - L_zy, L_zx - L_xz, L_xy - L_yx), L_ji = g_{+j,i} - g_{-j,i}
+  const C dyz = (gz[1] - gz[3]) - (gy[4] - gy[5]);
+  const C dzx = (gx[4] - gx[5]) - (gz[0] - gz[2]);
+  const C dxy = (gy[0] - gy[2]) - (gx[1] - gx[3]);
+
+  // ---- coupled local solve ----
+  const C kk = k.k_m;
+  C ux, uy, uz, jx, jy, jz, Fx, Fy, Fz;
+  const C inv_rho = C(1) / rho;
+  if (BC == BC_MOMENT && (lo || hi)) {
+    // wet wall node: velocity fixed by the closure, no force
+    ux = mx * inv_rho;
+    uy = my * inv_rho;
+    uz = mz * inv_rho;
+    jx = -kk * (dyz - C(2) * (uy * bz - uz * by));
+    jy = -kk * (dzx - C(2) * (uz * bx - ux * bz));
+    jz = -kk * (dxy - C(2) * (ux * by - uy * bx));
+    Fx = Fy = Fz = C(0);
+  } else {
+    // (rho + k|B|^2) J - k B (B.J) = R = k (2 p x B - rho D), p = m + F_ext/2,
+    // inverted exactly: J = (R + (k/rho) B (B.R)) / (rho + k|B|^2)
+    const C px = mx + C(0.5) * k.fex, py = my + C(0.5) * k.fey, pz = mz + C(0.5) * fez;
+    const C Rx = kk * (C(2) * (py * bz - pz * by) - rho * dyz);
+    const C Ry = kk * (C(2) * (pz * bx - px * bz) - rho * dzx);
+    const C Rz = kk * (C(2) * (px * by - py * bx) - rho * dxy);
+    const C bR = (bx * Rx + by * Ry + bz * Rz) * kk * inv_rho;
+    const C inv_a = C(1) / (rho + kk * (bx * bx + by * by + bz * bz));
+    jx = (Rx + bx * bR) * inv_a;
+    jy = (Ry + by * bR) * inv_a;
+    jz = (Rz + bz * bR) * inv_a;
+    Fx = k.fex + (jy * bz - jz * by);
+    Fy = k.fey + (jz * bx - jx * bz);
+    Fz = fez + (jx * by - jy * bx);
+    ux = (mx + C(0.5) * Fx) * inv_rho;
+    uy = (my + C(0.5) * Fy) * inv_rho;
+    uz = (mz + C(0.5) * Fz) * inv_rho;
+  }
+  obs.rhop = (double)rhop;
+  obs.ux = (double)ux;
+  obs.uy = (double)uy;
+  obs.uz = (double)uz;
+  obs.bx = (double)bx;
+  obs.by = (double)by;
+  obs.bz = (double)bz;
+  obs.jx = (double)jx;
+  obs.jy = (double)jy;
+  obs.jz = (double)jz;
+  if (MODE == MODE_MOMENTS) return;
+
+  // ---- collide and store ----
+  Rng rng(SR ? node_seed(sseed, (uint32_t)own) : 0u);
+  auto put = [&](long long plane, C v) {
+    __builtin_nontemporal_store(to_store<S, C, SR>(v, SR ? rng.next() : 0u), dst + plane * P + own);
+  };
+  const C om = k.omega_f, ka = k.kappa_f;
+  const C usq15 = C(1.5) * (ux * ux + uy * uy + uz * uz);
+  const C uF = ux * Fx + uy * Fy + uz * Fz;
+#pragma unroll
+  for (int q = 0; q < 19; ++q) {
+    const C ex_ = C(D3Q19::ex[q]), ey_ = C(D3Q19::ey[q]), ez_ = C(D3Q19::ez[q]);
+    const C w = W3<C>::w(q);
+    const C eu = ex_ * ux + ey_ * uy + ez_ * uz;
+    const C poly = C(3) * eu + C(4.5) * eu * eu - usq15;
+    const C feq = w * (rhop + rho * poly);
+    const C src_q = C(3) * w * ((ex_ * Fx + ey_ * Fy + ez_ * Fz) - uF) * (C(1) + poly);
+    put(q, f[q] + om * (feq - f[q]) + ka * src_q);
+  }
+  // g^eq_{a i} = W [B_i + 3 e_a (u_a B_i - B_a u_i)] along the link's axis a;
+  // the component along the axis keeps W B_a
+  const C wm = k.omega_m, W = C(1) / C(6);
+  const C exy = C(3) * (ux * by - uy * bx); // u_x B_y - B_x u_y
+  const C exz = C(3) * (ux * bz - uz * bx);
+  const C eyz = C(3) * (uy * bz - uz * by);
+  // deviations: the y component is stored minus W B0
+  const C gqx[6] = {W * bx, W * (bx - exy), W * bx, W * (bx + exy), W * (bx - exz), W * (bx + exz)};
+  const C gqy[6] = {W * (byp + exy), W * byp, W * (byp - exy), W * byp, W * (byp - eyz), W * (byp + eyz)};
+  const C gqz[6] = {W * (bz + exz), W * (bz + eyz), W * (bz - exz), W * (bz - eyz), W * bz, W * bz};
+#pragma unroll
+  for (int a = 0; a < 6; ++a) {
+    put(19 + a, gx[a] + wm * (gqx[a] - gx[a]));
+    put(25 + a, gy[a] + wm * (gqy[a] - gy[a]));
+    put(31 + a, gz[a] + wm * (gqz[a] - gz[a]));
+  }
+}
+
+} // namespace lks

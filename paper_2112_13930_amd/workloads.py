@@ -27,6 +27,33 @@ def random_populations(nx: int, ny: int, seed: int, b0: float = 0.05,
     return s
 
 
+# Typical magnitudes of the 40 raw planes of the three-dimensional channel
+# (D3Q19 f, then the seven D3Q7 populations of each field component) near
+# rest with unit density and unit imposed field along y.
+_F3_BASE = np.array([1 / 3] + [1 / 18] * 4 + [1 / 36] * 4 + [1 / 18] * 2 + [1 / 36] * 8)
+_G3_BASE = np.array([0.0] + [1 / 6] * 6)
+
+
+def random_populations3(nx: int, ny: int, nz: int, seed: int, b0: float = 0.05,
+                        rel_amp: float = 0.02, bt_amp: float = 0.002) -> np.ndarray:
+    """FP64 [40, nz, ny, nx] populations: typical magnitudes with uniform
+    random relative perturbations (x-, y- and z-dependent), random tangential
+    field populations (x and z components), the rest populations of the
+    field (weight 0) zero."""
+    rng = np.random.default_rng(seed)
+    s = np.zeros((40, nz, ny, nx), dtype=np.float64)
+    shape = (nz, ny, nx)
+    s[:19] = _F3_BASE[:, None, None, None] * (1.0 + rel_amp * rng.uniform(-1, 1, (19,) + shape))
+    for comp in range(3):
+        base = 19 + 7 * comp
+        if comp == 1:
+            s[base + 1:base + 7] = b0 * _G3_BASE[1:, None, None, None] * (
+                1.0 + rel_amp * rng.uniform(-1, 1, (6,) + shape))
+        else:
+            s[base + 1:base + 7] = bt_amp * rng.uniform(-1, 1, (6,) + shape)
+    return s
+
+
 @dataclass
 class ChannelDraw:
     nx: int

@@ -132,3 +132,25 @@ def test_batch_sizing(L):
                                     ctypes.byref(h)) == L.LKS_EINVAL
     assert lib.lks_mhd_batch_create(1, 4, 1000, ctypes.c_void_p(4096), 64, None,
                                     ctypes.byref(h)) == L.LKS_ENOMEM
+
+
+def test_3d_sizing_and_validation(L):
+    lib = L.lib()
+    p = L.LksParams3()
+    p.base = L.make_params(64, 32, precision="fp32")
+    p.nz = 16
+    assert lib.lks_mhd3_state_bytes(ctypes.byref(p)) >= 2 * 37 * 64 * 32 * 16 * 4
+    assert (lib.lks_mhd3_bytes_per_node(0), lib.lks_mhd3_bytes_per_node(1),
+            lib.lks_mhd3_bytes_per_node(2)) == (592, 296, 0)
+    p.nz = 0
+    assert lib.lks_mhd3_state_bytes(ctypes.byref(p)) == 0 and "nz" in L.last_error()
+    p.nz = 4
+    p.base = L.make_params(64, 32, precision="fp16")
+    assert lib.lks_mhd3_state_bytes(ctypes.byref(p)) == 0
+    p.base = L.make_params(2048, 2048, precision="fp32")
+    p.nz = 1024
+    assert lib.lks_mhd3_state_bytes(ctypes.byref(p)) == 0
+    h = ctypes.c_void_p()
+    p.base = L.make_params(8, 8, precision="fp64")
+    p.nz = 2
+    assert lib.lks_mhd3_create(ctypes.byref(p), None, 1 << 20, None, ctypes.byref(h)) == L.LKS_EINVAL
