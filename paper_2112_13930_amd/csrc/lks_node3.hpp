@@ -57,13 +57,20 @@ struct NodeObs3 {
   double rhop, ux, uy, uz, bx, by, bz, jx, jy, jz;
 };
 
+// Interior rows (no wall closure): the kernel for the rows 1..ny-2 keeps the
+// pulled values in the storage type and widens them at use, which halves the
+// registers they take in FP32 storage (the step is occupancy-bound).
+constexpr int BC_NONE = 2;
+
 template <typename S, typename C, int BC, int MODE, bool SR>
 __device__ __forceinline__ void node3_update(const Geom3 &g, const Coef<C> &k, C fez,
                                              const S *__restrict__ src, S *__restrict__ dst,
                                              int x, int y, int z, NodeObs3 &obs, uint32_t sseed) {
+  // register type of the pulled values
+  using R = typename ComputeSel<(BC != BC_NONE && sizeof(C) == 8) || sizeof(S) == 8>::type;
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const long long P = g.plane;
-  const bool lo = (y == 0), hi = (y == ny - 1);
+  const bool lo = (BC != BC_NONE) && (y == 0), hi = (BC != BC_NONE) && (y == ny - 1);
   const int xs[3] = {x == 0 ? nx - 1 : x - 1, x, x == nx - 1 ? 0 : x + 1}; // x - e for e = 1, 0, -1
   const int zs[3] = {z == 0 ? nz - 1 : z - 1, z, z == nz - 1 ? 0 : z + 1};
   const long long own = ((long long)z * ny + y) * nx + x;
@@ -73,31 +80,31 @@ __device__ __forceinline__ void node3_update(const Geom3 &g, const Coef<C> &k, C
   };
 
   // ---- pull streaming; populations entering from a wall are closed below ----
-  C f[19], gx[6], gy[6], gz[6];
+  R f[19], gx[6], gy[6], gz[6];
 #pragma unroll
   for (int q = 0; q < 19; ++q) {
     const int ey_ = D3Q19::ey[q];
     if ((ey_ == 1 && lo) || (ey_ == -1 && hi)) {
-      f[q] = C(0);
+      f[q] = R(0);
       continue;
     }
-    f[q] = ld<S, C>(src + q * P + srcoff(D3Q19::ex[q], ey_, D3Q19::ez[q]));
+    f[q] = ld<S, R>(src + q * P + srcoff(D3Q19::ex[q], ey_, D3Q19::ez[q]));
   }
 #pragma unroll
   for (int a = 0; a < 6; ++a) {
     const int ey_ = D3Q6::ey[a];
     if ((ey_ == 1 && lo) || (ey_ == -1 && hi)) {
-      gx[a] = gy[a] = gz[a] = C(0);
+      gx[a] = gy[a] = gz[a] = R(0);
       continue;
     }
     const long long o = srcoff(D3Q6::ex[a], ey_, D3Q6::ez[a]);
-    gx[a] = ld<S, C>(src + (19 + a) * P + o);
-    gy[a] = ld<S, C>(src + (25 + a) * P + o);
-    gz[a] = ld<S, C>(src + (31 + a) * P + o);
+    gx[a] = ld<S, R>(src + (19 + a) * P + o);
+    gy[a] = ld<S, R>(src + (25 + a) * P + o);
+    gz[a] = ld<S, R>(src + (31 + a) * P + o);
   }
 
   // ---- wall closures ----
-  if (BC == BC_LINK) {
+  if constexpr (BC == BC_LINK) {
     // Half-way bounce-back with Ladd's term (+-U/6 on the in-plane diagonals);
     // tangential field components by the theta-weighted Shercliff closure
     // (moving-wall term on B_x only), the normal one by anti-bounce-back,
@@ -123,7 +130,7 @@ __device__ __forceinline__ void node3_update(const Geom3 &g, const Coef<C> &k, C
       gz[3] = k.hi.r * own_(31 + 1);
       gy[3] = -own_(25 + 1);
     }
-  } else {
+  } else if constexpr (BC == BC_MOMENT) {
     // On-node closures from the paper's constraint set taken per tangential
     // direction (Pi_y = 0 fixes rho; Pi_x = rho U, Pi_xx = rho (cs2 + U^2),
     // Pi_z = 0, Pi_zz = rho cs2), written for the deviations f' = f - w.
@@ -184,20 +191,22 @@ __device__ __forceinline__ void node3_update(const Geom3 &g, const Coef<C> &k, C
   C rhop = C(0), mx = C(0), my = C(0), mz = C(0);
 #pragma unroll
   for (int q = 0; q < 19; ++q) {
-    rhop += f[q];
-    mx += C(D3Q19::ex[q]) * f[q];
-    my += C(D3Q19::ey[q]) * f[q];
-    mz += C(D3Q19::ez[q]) * f[q];
+    const C v = C(f[q]);
+    rhop += v;
+    mx += C(D3Q19::ex[q]) * v;
+    my += C(D3Q19::ey[q]) * v;
+    mz += C(D3Q19::ez[q]) * v;
   }
   const C rho = C(1) + rhop;
-  const C bx = ((gx[0] + gx[1]) + (gx[2] + gx[3])) + (gx[4] + gx[5]);
-  const C byp = ((gy[0] + gy[1]) + (gy[2] + gy[3])) + (gy[4] + gy[5]);
+  auto G = [](R v) { return C(v); };
+  const C bx = ((G(gx[0]) + G(gx[1])) + (G(gx[2]) + G(gx[3]))) + (G(gx[4]) + G(gx[5]));
+  const C byp = ((G(gy[0]) + G(gy[1])) + (G(gy[2]) + G(gy[3]))) + (G(gy[4]) + G(gy[5]));
   const C by = k.b0 + byp;
-  const C bz = ((gz[0] + gz[1]) + (gz[2] + gz[3])) + (gz[4] + gz[5]);
+  const C bz = ((G(gz[0]) + G(gz[1])) + (G(gz[2]) + G(gz[3]))) + (G(gz[4]) + G(gz[5]));
   // D = (L_yz - L_zy, L_zx - L_xz, L_xy - L_yx), L_ji = g_{+j,i} - g_{-j,i}
-  const C dyz = (gz[1] - gz[3]) - (gy[4] - gy[5]);
-  const C dzx = (gx[4] - gx[5]) - (gz[0] - gz[2]);
-  const C dxy = (gy[0] - gy[2]) - (gx[1] - gx[3]);
+  const C dyz = (G(gz[1]) - G(gz[3])) - (G(gy[4]) - G(gy[5]));
+  const C dzx = (G(gx[4]) - G(gx[5])) - (G(gz[0]) - G(gz[2]));
+  const C dxy = (G(gy[0]) - G(gy[2])) - (G(gx[1]) - G(gx[3]));
 
   // ---- coupled local solve ----
   const C kk = k.k_m;
@@ -244,6 +253,13 @@ __device__ __forceinline__ void node3_update(const Geom3 &g, const Coef<C> &k, C
   if (MODE == MODE_MOMENTS) return;
 
   // ---- collide and store ----
+  // Widen a pulled value again for its collision: the empty register
+  // constraint hides the earlier widening from common-subexpression
+  // elimination, so only the narrow value stays live across the solve.
+  auto rewiden = [](R v) -> C {
+    if constexpr (sizeof(R) < sizeof(C)) asm volatile("" : "+v"(v));
+    return C(v);
+  };
   Rng rng(SR ? node_seed(sseed, (uint32_t)own) : 0u);
   auto put = [&](long long plane, C v) {
     __builtin_nontemporal_store(to_store<S, C, SR>(v, SR ? rng.next() : 0u), dst + plane * P + own);
@@ -259,7 +275,8 @@ __device__ __forceinline__ void node3_update(const Geom3 &g, const Coef<C> &k, C
     const C poly = C(3) * eu + C(4.5) * eu * eu - usq15;
     const C feq = w * (rhop + rho * poly);
     const C src_q = C(3) * w * ((ex_ * Fx + ey_ * Fy + ez_ * Fz) - uF) * (C(1) + poly);
-    put(q, f[q] + om * (feq - f[q]) + ka * src_q);
+    const C fq = rewiden(f[q]);
+    put(q, fq + om * (feq - fq) + ka * src_q);
   }
   // g^eq_{a i} = W [B_i + 3 e_a (u_a B_i - B_a u_i)] along the link's axis a;
   // the component along the axis keeps W B_a
@@ -273,9 +290,10 @@ __device__ __forceinline__ void node3_update(const Geom3 &g, const Coef<C> &k, C
   const C gqz[6] = {W * (bz + exz), W * (bz + eyz), W * (bz - exz), W * (bz - eyz), W * bz, W * bz};
 #pragma unroll
   for (int a = 0; a < 6; ++a) {
-    put(19 + a, gx[a] + wm * (gqx[a] - gx[a]));
-    put(25 + a, gy[a] + wm * (gqy[a] - gy[a]));
-    put(31 + a, gz[a] + wm * (gqz[a] - gz[a]));
+    const C vx = rewiden(gx[a]), vy = rewiden(gy[a]), vz = rewiden(gz[a]);
+    put(19 + a, vx + wm * (gqx[a] - vx));
+    put(25 + a, vy + wm * (gqy[a] - vy));
+    put(31 + a, vz + wm * (gqz[a] - vz));
   }
 }
 

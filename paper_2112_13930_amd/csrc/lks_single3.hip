@@ -21,24 +21,39 @@ struct ObsOut3 {
 constexpr int NRED3 = 6; // du2, u2, db2, b2, sum_u, nonfinite
 
 // One block of 256 threads per tile of 256 consecutive x of one (y, z) line.
-// ctr[2]: step counters as in the two-dimensional kernel.
+// A step is two launches over disjoint rows, both reading the same state:
+// BC_NONE covers the interior rows 1..ny-2, BC_LINK / BC_MOMENT the two wall
+// rows.  Tiles are numbered interior first (tile_base offsets the wall
+// launch), so residual partial sums keep one fixed order.  ctr[2]: step
+// counters as in the two-dimensional kernel; only the launch with owner set
+// advances them.
+// Waves per SIMD: the step is bound by how many waves keep memory requests
+// in flight.  The binary32 interior kernel fits 5 waves (at most 102
+// registers) without spilling; the others take 4 (at most 128).
+#ifndef LKS_STEP3_WAVES_FP32_INTERIOR
+#define LKS_STEP3_WAVES_FP32_INTERIOR 5
+#endif
+template <typename S, int BC>
+constexpr int kWaves3 = (BC == BC_NONE && sizeof(S) == 4) ? LKS_STEP3_WAVES_FP32_INTERIOR : 4;
+
 template <typename S, typename C, int BC, int MODE>
-__global__ __launch_bounds__(256) void k_step3(Geom3 g, Coef<C> k, C fez, const S *__restrict__ src,
-                                               S *__restrict__ dst, int tiles_x,
-                                               double *__restrict__ rec,
-                                               double *__restrict__ partials, ObsOut3 oo,
-                                               uint32_t *__restrict__ ctr, int parity) {
+__global__ __launch_bounds__(256, (kWaves3<S, BC>)) void k_step3(
+    Geom3 g, Coef<C> k, C fez, const S *__restrict__ src, S *__restrict__ dst, int tiles_x,
+    int tile_base, double *__restrict__ rec, double *__restrict__ partials, ObsOut3 oo,
+    uint32_t *__restrict__ ctr, int parity, int owner) {
   constexpr bool SR = kUseSR<S, C> && MODE != MODE_MOMENTS;
   uint32_t sseed = 0;
   if constexpr (MODE != MODE_MOMENTS) {
     const uint32_t step = ctr[parity];
-    if (blockIdx.x == 0 && threadIdx.x == 0) ctr[parity ^ 1] = step + 1u;
+    if (owner && blockIdx.x == 0 && threadIdx.x == 0) ctr[parity ^ 1] = step + 1u;
     if constexpr (SR) sseed = step_seed(step);
   }
-  const int tile = blockIdx.x;
-  const int line = tile / tiles_x; // z * ny + y
-  const int tx = tile - line * tiles_x;
-  const int z = line / g.ny, y = line - z * g.ny;
+  const int nrows = BC == BC_NONE ? g.ny - 2 : 2;
+  const int line = (int)blockIdx.x / tiles_x; // z * nrows + row
+  const int tx = (int)blockIdx.x - line * tiles_x;
+  const int z = line / nrows, r = line - z * nrows;
+  const int y = BC == BC_NONE ? 1 + r : (r == 0 ? 0 : g.ny - 1);
+  const int tile = tile_base + (int)blockIdx.x;
   const int x = tx * 256 + (int)threadIdx.x;
   const bool act = x < g.nx;
   NodeObs3 o{};
@@ -214,9 +229,20 @@ Layout3 layout3(const lks_mhd3_params *p) {
 
 template <typename S, typename C, int BC, int MODE>
 hipError_t launch3_t(lks_mhd3 *h, const void *src, void *dst, ObsOut3 oo) {
-  hipLaunchKernelGGL((k_step3<S, C, BC, MODE>), dim3(h->ntiles), dim3(256), 0, h->stream, h->geom,
-                     coef3<C>(h), (C)h->fz, static_cast<const S *>(src),
-                     static_cast<S *>(dst), h->tiles_x, h->rec, h->partials, oo, h->ctr, h->cur);
+  const int interior = h->tiles_x * (h->geom.ny - 2) * h->geom.nz;
+  const int walls = h->tiles_x * 2 * h->geom.nz;
+  if (interior > 0) {
+    hipLaunchKernelGGL((k_step3<S, C, BC_NONE, MODE>), dim3(interior), dim3(256), 0, h->stream,
+                       h->geom, coef3<C>(h), (C)h->fz, static_cast<const S *>(src),
+                       static_cast<S *>(dst), h->tiles_x, 0, h->rec, h->partials, oo, h->ctr,
+                       h->cur, 1);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((k_step3<S, C, BC, MODE>), dim3(walls), dim3(256), 0, h->stream, h->geom,
+                     coef3<C>(h), (C)h->fz, static_cast<const S *>(src), static_cast<S *>(dst),
+                     h->tiles_x, interior, h->rec, h->partials, oo, h->ctr, h->cur,
+                     interior > 0 ? 0 : 1);
   return hipGetLastError();
 }
 

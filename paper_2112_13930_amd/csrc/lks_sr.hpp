@@ -3,7 +3,8 @@
 //
 // Rounding: the result is one of the two neighbours of v in the target
 // format, the farther one with probability |v - nearest lower-magnitude
-// neighbour| / spacing, resolved to 2^-32 of the spacing.  It is computed by
+// neighbour| / spacing, resolved to the random word's resolution (2^-32 of
+// the spacing for a full word; the kernels pass 16 random bits, 2^-16).  It is computed by
 // adding uniform random bits below the target's last place to the magnitude
 // bits of v and truncating there (a carry out of the kept bits rounds up,
 // across a binade too), or, from binary64 to binary16, as g floor(v/g + u)
@@ -12,7 +13,7 @@
 //
 // Random bits: one hashed seed per node and step (counter-based, so a run is
 // reproducible bit for bit and independent of launch shape or batch mix),
-// then one xorshift32 step (Marsaglia 2003) per stored value.
+// then one xorshift32 step (Marsaglia 2003) per two stored values.
 #pragma once
 
 #include <stdint.h>
@@ -34,15 +35,26 @@ LKS_HD inline uint32_t mix32(uint32_t x) {
   return x;
 }
 
-// Per-node stream of 32-bit random words.
+// Per-node stream of random words for stochastic rounding.  next() gives a
+// 32-bit word whose top 16 bits are random and whose bit 15 is set (the
+// middle of the 2^-16 bin the 16 bits select); two consecutive calls share
+// one xorshift32 step.  16 bits resolve the rounding probability to 2^-16
+// of the target spacing, far below any other error of the stored values.
 struct Rng {
-  uint32_t s;
+  uint32_t s, w = 0;
+  bool half = false;
   LKS_HD explicit Rng(uint32_t seed) : s(seed | 1u) {} // xorshift needs s != 0
   LKS_HD uint32_t next() {
+    if (half) {
+      half = false;
+      return (w << 16) | 0x8000u;
+    }
     s ^= s << 13;
     s ^= s >> 17;
     s ^= s << 5;
-    return s;
+    w = s;
+    half = true;
+    return (w & 0xFFFF0000u) | 0x8000u;
   }
 };
 

@@ -43,6 +43,10 @@ template <typename T> static void neighbours(long double av, T &lo, T &hi) {
   }
 }
 
+// Random words as the kernels draw them (lks::Rng): 16 random bits on top,
+// bit 15 set.  With bits16 the sweep covers the 2^16 possible words exactly.
+static bool g_bits16 = false;
+
 template <typename T, typename W, typename F>
 static void check(W v, F round, int nsweep) {
   const long double av = std::fabs((long double)v);
@@ -51,7 +55,8 @@ static void check(W v, F round, int nsweep) {
   const bool exact = (long double)lo == av;
   int up = 0;
   for (int i = 0; i < nsweep; ++i) {
-    const uint32_t r = (uint32_t)(((uint64_t)i << 32) / (uint64_t)nsweep) + 977u;
+    const uint32_t r = g_bits16 ? (((uint32_t)(((uint64_t)i << 16) / (uint64_t)nsweep) << 16) | 0x8000u)
+                                : (uint32_t)(((uint64_t)i << 32) / (uint64_t)nsweep) + 977u;
     const T res = round(v, r);
     const long double ar = std::fabs((long double)res);
     const bool neg_ok = std::signbit((double)v) ? (std::signbit((double)res) || ar == 0) : !std::signbit((double)res);
@@ -109,6 +114,32 @@ int main() {
     check<_Float16>((float)v, f16f, N);
     if (v == 0 || std::fabs(v) > 1e-30) check<float>(v, f32, N);
   }
+  // the kernels' 16-bit words: every word of the 2^16, probability to +-1.5/65536
+  g_bits16 = true;
+  std::mt19937_64 g2(777);
+  for (int t = 0; t < 300; ++t) {
+    const double mag = std::exp2(-40.0 + 56.0 * U(g2)) * (1.0 + U(g2));
+    const double v = (t & 1) ? -mag : mag;
+    if (std::fabs(v) < 65504.0) {
+      check<_Float16>(v, f16d, 65536);
+      check<_Float16>((float)v, f16f, 65536);
+    }
+    if (std::fabs(v) > 1e-30) check<float>(v, f32, 65536);
+  }
+  // the generator's words: top 16 bits spread over all values, bit 15 set
+  lks::Rng rng(12345u);
+  int hist[16] = {0};
+  for (int i = 0; i < 1 << 20; ++i) {
+    const uint32_t w = rng.next();
+    ++checks;
+    if ((w & 0xFFFFu) != 0x8000u) ++fails;
+    ++hist[w >> 28];
+  }
+  for (int b = 0; b < 16; ++b)
+    if (std::abs(hist[b] - (1 << 16)) > 2000) {
+      ++fails;
+      printf("random word histogram bin %d: %d\n", b, hist[b]);
+    }
   printf("%s: %ld results checked, %d failures\n", fails ? "FAIL" : "OK", checks, fails);
   return fails ? 1 : 0;
 }
