@@ -25,7 +25,8 @@ Printed as one JSON line with, besides the contract fields:
                 against sequential single-channel launches, and binary16);
                 the continuous-batching solve service (FP32 and binary16)
                 against sequential plain FP32 solves at six arrival rates;
-                the headline step on a developed (random) state.
+                the headline step on a developed (random) state; the 3D
+                channel (D3Q19 + D3Q7 field) on 256^3.
 
 Profiling helpers (used to write profiles/*):
   --profile-run     only warm-up + timed steps of the headline, plus a copy of
@@ -57,8 +58,9 @@ COPY_REF_BYTES = 1 << 30
 
 
 def kernel_source_hash() -> str:
+    """Hash of every source the FP32 step kernel is compiled from."""
     h = hashlib.sha256()
-    for f in ("lks_node.hpp", "lks_single.hip"):
+    for f in ("lks_sr.hpp", "lks_node.hpp", "lks_common.hpp", "lks_aux.hpp", "lks_single.hip"):
         with open(os.path.join(ROOT, "paper_2112_13930_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -126,6 +128,64 @@ def developed_state_rate(torch, steps=200, warmup=10):
         gbs = bpn * 4096 * 4096 / per_step / 1e9
         out[prec] = {"mlups": round(4096 * 4096 / per_step / 1e6, 1), "gbs": round(gbs, 1),
                      "frac_hbm": round(gbs / PEAK_HBM_GBS, 3)}
+    return out
+
+
+def three_d(torch, n=256, steps=200, warmup=10):
+    """The three-dimensional channel (x, z periodic, Shercliff walls in y) on
+    an n^3 grid with the headline physics (Ha 50, c_w 1, upper wall 0.05,
+    link walls, tau_f 0.7, tau_m 0.9): rates from rest and on a developed
+    random state, and the FP32 run's error against the 2D oracle (the
+    from-rest run is x- and z-invariant, so every node must equal the 2D
+    oracle's column)."""
+    import numpy as np
+
+    from paper_2112_13930_amd._lib import derive, make_params
+    from paper_2112_13930_amd.channel3 import Channel3
+    from paper_2112_13930_amd.workloads import random_populations3
+    kw = dict(bc="link", tau_f=0.7, tau_m=0.9, ha=50.0, c_lower=1.0, c_upper=1.0, u_upper=0.05)
+    out = {"grid": f"{n}x{n}x{n}", "steps": steps,
+           "bytes_per_node": {"fp32": 296, "fp64": 592}}
+
+    def rate(ch):
+        ch.step(warmup)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(ch.stream)
+        ch.step(steps)
+        e1.record(ch.stream)
+        torch.cuda.synchronize()
+        return n ** 3 / (e0.elapsed_time(e1) / 1e3 / steps)
+
+    for prec, bpn in (("fp32", 296), ("fp64", 592)):
+        ch = Channel3(n, n, n, precision=prec, stream=torch.cuda.Stream(), **kw)
+        r0 = rate(ch)
+        b0 = derive(make_params(n, n, precision=prec, **kw)).b0
+        ch.load_state(torch.from_numpy(random_populations3(n, n, n, seed=1, b0=b0)))
+        r1 = rate(ch)
+        ch.close()
+        out[prec] = {"mlups_from_rest": round(r0 / 1e6, 1),
+                     "gbs_from_rest": round(bpn * r0 / 1e9, 1),
+                     "frac_hbm_from_rest": round(bpn * r0 / 1e9 / PEAK_HBM_GBS, 3),
+                     "mlups_developed": round(r1 / 1e6, 1),
+                     "frac_hbm_developed": round(bpn * r1 / 1e9 / PEAK_HBM_GBS, 3)}
+    # the measured FP32 workload after 1000 steps from rest against the 2D
+    # oracle's columns (stored by tests/golden/make_golden.py)
+    gold_path = os.path.join(ROOT, "tests", "golden", "couette_256_link_1000.json")
+    if n == 256 and os.path.exists(gold_path):
+        gold = json.load(open(gold_path))
+        ch = Channel3(n, n, n, precision="fp32", stream=torch.cuda.Stream(), **kw)
+        ch.step(1000)
+        m = ch.moments()
+        g = {k: m[k].cpu().numpy() for k in ("ux", "bx")}
+        del m
+        ch.close()
+        errs = {}
+        for k in ("ux", "bx"):
+            ref = np.broadcast_to(np.asarray(gold[k])[None, :, None], g[k].shape)
+            errs[k] = float(np.linalg.norm(g[k] - ref) / np.linalg.norm(ref))
+        out["fp32_error_vs_2d_oracle_1000_steps"] = errs
     return out
 
 
@@ -286,6 +346,28 @@ def serving(torch, rates=(50.0, 100.0, 200.0, 500.0, 1000.0, 2000.0), n_requests
     return [serve_benchmark(n_requests=n_requests, rate=r, seed=seed, log=log) for r in rates]
 
 
+def profile_run_3d(torch, args):
+    """The 3D channel's FP32 steps only (256^3, headline physics), plus a
+    device copy of known size (counter scale)."""
+    from paper_2112_13930_amd.channel3 import Channel3
+    a = torch.empty(COPY_REF_BYTES // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    ch = Channel3(256, 256, 256, bc="link", precision="fp32", tau_f=0.7, tau_m=0.9, ha=50.0,
+                  c_lower=1.0, c_upper=1.0, u_upper=0.05, stream=torch.cuda.Stream())
+    ch.step(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ch.step(args.steps)
+    torch.cuda.synchronize()
+    ch.close()
+    print(json.dumps({"profile_run_3d": True, "steps": args.steps,
+                      "per_step_ms": (time.perf_counter() - t0) / args.steps * 1e3}))
+
+
 def profile_run(torch, args):
     """Headline steps only, plus a device copy of known size (counter scale)."""
     from paper_2112_13930_amd.channel import Channel
@@ -410,6 +492,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--profile-run", action="store_true")
+    ap.add_argument("--profile-3d", action="store_true", help="3D FP32 steps only (profiling)")
     ap.add_argument("--summarize", nargs="*")
     ap.add_argument("--command", default="")
     args = ap.parse_args()
@@ -437,6 +520,9 @@ def main():
 
     if args.profile_run:
         profile_run(torch, args)
+        return 0
+    if args.profile_3d:
+        profile_run_3d(torch, args)
         return 0
 
     h = headline(torch, args)
@@ -483,6 +569,8 @@ def main():
         extras["config_sweep_fp32"] = sweep(torch)
         log("precisions ...")
         extras["precisions"] = other_precisions(torch)
+        log("3D channel ...")
+        extras["channel_3d"] = three_d(torch)
         log("batched ...")
         extras["batched_256_channels"] = batched(torch, "fp32")
         extras["batched_256_channels_fp16"] = batched(torch, "fp16", sequential=False)

@@ -16,7 +16,14 @@ precision_case_512.json
     steady state (per-step relative change below 1e-12, checked every 1000
     steps), and the Chang-Lundgren profile at the same rows.
 
-Run:  python tests/golden/make_golden.py [config1] [precision]
+couette_256_link_1000.json
+    The shear-driven Hartmann-Couette channel of the benchmark on 256 rows:
+    link-based walls, tau_f = 0.7, tau_m = 0.9, Ha = 50, c = 1 on both
+    walls, upper wall moving at 0.05, 1000 steps from rest.  Stores the
+    oracle's u_x and B_x rows (the runs are x-invariant; the 3D benchmark
+    channel is also z-invariant, so each of its nodes must match the row).
+
+Run:  python tests/golden/make_golden.py [config1] [precision] [couette256]
 """
 import json
 import os
@@ -86,8 +93,24 @@ def precision_case(nthreads=8):
     return out
 
 
+def couette256():
+    p = derive.couette_params(4, 256, oracle.LINK, 0.7, 0.9, 50.0, 1.0, 1.0, 0.05)
+    s = oracle.init_state(p)
+    oracle.run(p, s, 1000, nthreads=4)
+    o = oracle.observe(p, s)
+    return {
+        "description": "Hartmann-Couette channel, 256 rows, link-based, tau_f=0.7, tau_m=0.9, "
+                       "Ha=50, c=1 both walls, upper wall U=0.05, 1000 steps from rest; oracle "
+                       "FP64 observables (one column)",
+        "params": {"ny": 256, "bc": "link", "tau_f": 0.7, "tau_m": 0.9, "ha": 50.0, "c": 1.0,
+                   "u_upper": 0.05, "steps": 1000, "a": p.a, "b0": p.b0},
+        "ux": o["ux"][:, 0].tolist(),
+        "bx": o["bx"][:, 0].tolist(),
+    }
+
+
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["config1", "precision"]
+    which = sys.argv[1:] or ["config1", "precision", "couette256"]
     if "config1" in which:
         out = os.path.join(HERE, "config1_hartmann_link.json")
         with open(out, "w") as fh:
@@ -97,4 +120,10 @@ if __name__ == "__main__":
         out = os.path.join(HERE, "precision_case_512.json")
         with open(out, "w") as fh:
             json.dump(precision_case(), fh, indent=1)
+        print("wrote", out)
+    if "couette256" in which:
+        out = os.path.join(HERE, "couette_256_link_1000.json")
+        data = couette256()
+        with open(out, "w") as fh:
+            json.dump(data, fh, indent=1)
         print("wrote", out)

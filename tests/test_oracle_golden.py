@@ -68,3 +68,19 @@ def test_precision_case_steady_state_is_chang_lundgren():
     assert np.sqrt(np.mean((b - ba) ** 2)) / np.sqrt(np.mean(ba ** 2)) < 2e-3
     assert np.abs(u - u[::-1]).max() < 1e-9 * np.abs(u).max()
     assert np.abs(b + b[::-1]).max() < 1e-9 * np.abs(b).max()
+
+
+COUETTE = os.path.join(os.path.dirname(__file__), "golden", "couette_256_link_1000.json")
+
+
+def test_couette256_fixture_matches_oracle(orc):
+    """The stored 256-row Hartmann-Couette columns (benchmark workload,
+    1000 steps from rest) are what the oracle computes now."""
+    g = json.load(open(COUETTE))
+    p = derive.couette_params(4, 256, oracle.LINK, 0.7, 0.9, 50.0, 1.0, 1.0, 0.05)
+    assert p.b0 == g["params"]["b0"]
+    s = orc.init_state(p)
+    orc.run(p, s, 1000, nthreads=4)
+    o = orc.observe(p, s)
+    assert np.array_equal(o["ux"][:, 0], np.array(g["ux"]))
+    assert np.array_equal(o["bx"][:, 0], np.array(g["bx"]))
