@@ -6,7 +6,7 @@ links or executes anything here, and this package imports nothing from it.
 
 Contents
   lks_oracle.c   plain C reference step (pull stream, wall closures, moments,
-                 coupled u/J solve, BGK collisions) -- built into
+                 coupled u/J solve, BGK or TRT collisions) -- built into
                  liblks_oracle.so by :func:`build`.
   analytic.py    closed-form Hartmann (Chang-Lundgren) and Hartmann-Couette
                  profiles of Sec. VIII and App. C.
@@ -29,6 +29,7 @@ SRC = os.path.join(HERE, "lks_oracle.c")
 LIB = os.path.join(HERE, "liblks_oracle.so")
 
 LINK, MOMENT = 0, 1
+BGK, TRT = 0, 1
 NPLANES = 19
 
 
@@ -47,12 +48,13 @@ def build(force: bool = False) -> str:
 class _Params(ctypes.Structure):
     _fields_ = [
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("bc", ctypes.c_int32),
-        ("pad_", ctypes.c_int32),
+        ("collision", ctypes.c_int32),
         ("tau_f", ctypes.c_double), ("tau_m", ctypes.c_double),
         ("b0", ctypes.c_double), ("fx", ctypes.c_double), ("fy", ctypes.c_double),
         ("c_lo", ctypes.c_double), ("c_hi", ctypes.c_double),
         ("u_lo", ctypes.c_double), ("u_hi", ctypes.c_double),
         ("a", ctypes.c_double),
+        ("tau_fm", ctypes.c_double), ("tau_mp", ctypes.c_double),
     ]
 
 
@@ -77,9 +79,10 @@ def lib():
         L.orc_run.argtypes = [pp, dp, dp, ctypes.c_int64, ctypes.c_int]
         L.orc_observe.argtypes = [pp, dp, dp, dp, dp, dp, dp, dp]
         L.orc_gather.argtypes = [pp, dp, ctypes.c_int, ctypes.c_int, dp]
+        L.orc_collide.argtypes = [pp, dp, dp, dp] + [ctypes.c_double] * 7 + [dp]
         for fn in ("orc_feq", "orc_geq", "orc_source", "orc_local_solve",
                    "orc_link_closure", "orc_moment_closure", "orc_init",
-                   "orc_step", "orc_run", "orc_observe", "orc_gather"):
+                   "orc_step", "orc_run", "orc_observe", "orc_gather", "orc_collide"):
             getattr(L, fn).restype = None
         _lib = L
     return _lib
@@ -97,6 +100,11 @@ class Params:
     ``c_lo``/``c_hi`` may be ``math.inf``; ``a`` is the half-width H = a used in
     the wall-conductance terms.  Use :mod:`oracle.derive` to obtain them from
     (Ha, c_w, u_max) the way Sec. VIII defines the problem.
+
+    ``collision`` selects BGK (the paper's operator) or TRT.  Under TRT,
+    ``tau_f`` relaxes the even part of f and ``tau_fm`` its odd part, ``tau_m``
+    the odd part of g and ``tau_mp`` its even part
+    (:func:`oracle.derive.trt_times` gives them from the magic parameters).
     """
     nx: int
     ny: int
@@ -112,6 +120,9 @@ class Params:
     u_hi: float = 0.0
     a: float = float("nan")
     rho0: float = 1.0
+    collision: int = BGK
+    tau_fm: float = float("nan")
+    tau_mp: float = float("nan")
     extra: dict = field(default_factory=dict)
 
     def half_width(self) -> float:
@@ -120,9 +131,11 @@ class Params:
         return self.ny / 2.0 if self.bc == LINK else (self.ny - 1) / 2.0
 
     def c_struct(self) -> _Params:
-        return _Params(self.nx, self.ny, self.bc, 0, self.tau_f, self.tau_m,
+        if self.collision == TRT:
+            assert self.tau_fm > 0.5 and self.tau_mp > 0.5, "TRT needs tau_fm and tau_mp > 1/2"
+        return _Params(self.nx, self.ny, self.bc, self.collision, self.tau_f, self.tau_m,
                        self.b0, self.fx, self.fy, self.c_lo, self.c_hi,
-                       self.u_lo, self.u_hi, self.half_width())
+                       self.u_lo, self.u_hi, self.half_width(), self.tau_fm, self.tau_mp)
 
 
 def init_state(p: Params) -> np.ndarray:
@@ -205,3 +218,13 @@ def moment_closure(p: Params, wall: int, f, gx, gy):
     cp = p.c_struct()
     lib().orc_moment_closure(ctypes.byref(cp), wall, _dp(f), _dp(gx), _dp(gy))
     return f, gx, gy
+
+
+def collide(p: Params, f, gx, gy, rho, ux, uy, bx, by, Fx, Fy) -> np.ndarray:
+    """Post-collision values (19, plane order) of one node's populations."""
+    f, gx, gy = (np.ascontiguousarray(v, dtype=np.float64) for v in (f, gx, gy))
+    out = np.empty(NPLANES)
+    cp = p.c_struct()
+    lib().orc_collide(ctypes.byref(cp), _dp(f), _dp(gx), _dp(gy), rho, ux, uy, bx, by, Fx,
+                      Fy, _dp(out))
+    return out

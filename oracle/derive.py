@@ -25,6 +25,17 @@ def eta_of(tau_m: float) -> float:
     return (tau_m - 0.5) / 3.0
 
 
+def trt_times(tau_f: float, tau_m: float, lambda_f: float, lambda_m: float):
+    """The free TRT relaxation times from the magic parameters.
+
+    Lambda = (tau+ - 1/2)(tau- - 1/2) for each distribution.  For f, tau_f is
+    the even-part time (it sets nu) and the odd-part time tau_fm follows; for
+    g, tau_m is the odd-part time (it sets eta) and the even-part time tau_mp
+    follows.  Returns (tau_fm, tau_mp).
+    """
+    return 0.5 + lambda_f / (tau_f - 0.5), 0.5 + lambda_m / (tau_m - 0.5)
+
+
 def half_width(ny: int, bc: int) -> float:
     return ny / 2.0 if bc == LINK else (ny - 1) / 2.0
 

@@ -55,15 +55,24 @@ static const double CSM2 = 1.0 / 3.0; /* c_sm^2, Sec. IV */
 
 enum { ORC_LINK = 0, ORC_MOMENT = 1 };
 enum { ORC_LOWER = 0, ORC_UPPER = 1 };
+/* Collision operator: the paper's single-relaxation-time (BGK) form, or the
+ * two-relaxation-time form it names as a drop-in replacement (Secs. V and
+ * IX).  Under TRT the rates that set the transport coefficients keep their
+ * meaning: tau_f relaxes the even (symmetric) part of f, giving nu, and
+ * tau_m the odd (antisymmetric) part of g, giving eta; tau_fm and tau_mp are
+ * the free rates of the other halves. */
+enum { ORC_BGK = 0, ORC_TRT = 1 };
 
 typedef struct {
-  int32_t nx, ny, bc, pad_;
+  int32_t nx, ny, bc, collision;
   double tau_f, tau_m; /* relaxation times of f and g */
   double b0;           /* imposed field, along +y */
   double fx, fy;       /* external body force F_ext */
   double c_lo, c_hi;   /* wall conductance ratios c_w (0 .. INFINITY) */
   double u_lo, u_hi;   /* wall velocities along x */
   double a;            /* half-width H = a entering theta and 1/(c_w a) */
+  double tau_fm;       /* TRT: relaxation time of the odd part of f */
+  double tau_mp;       /* TRT: relaxation time of the even part of g */
 } orc_params;
 
 /* ---------------------------------------------------------------------- */
@@ -358,24 +367,68 @@ static void gather_node(const orc_params *p, const double *in, int x, int y,
   n->Fy = p->fy + sol[2] * bx; /* (J x B)_y = +J_z B_x */
 }
 
+/* S5: collide one node (Eqs. LBMforflowfield and LKSformagneticfield).
+ * f, gx, gy are the post-streaming, post-closure populations; rho, u, B and
+ * F the fields of S3-S4.  out receives the 19 post-collision values in plane
+ * order.
+ *
+ * BGK: every population relaxes to its equilibrium at 1/tau, and the source
+ * enters with the weight 1 - 1/(2 tau) (Sec. V).
+ * TRT: each population splits into the parts even and odd under e -> -e,
+ *   h+_a = (h_a + h_abar)/2,  h-_a = (h_a - h_abar)/2,
+ * for h = f, f^eq, S (and g, g^eq), and each part relaxes at its own rate,
+ * the source part with the matching weight 1 - 1/(2 tau+-).  The rest
+ * population is even. */
+void orc_collide(const orc_params *p, const double *f, const double *gx,
+                 const double *gy, double rho, double ux, double uy, double bx,
+                 double by, double Fx, double Fy, double *out) {
+  double feq[NQ9], S[NQ9], geqx[NQ5], geqy[NQ5];
+  orc_feq(rho, ux, uy, feq);
+  orc_source(rho, ux, uy, Fx, Fy, feq, S);
+  orc_geq(bx, by, ux, uy, geqx, geqy);
+  if (p->collision != ORC_TRT) {
+    for (int q = 0; q < NQ9; ++q)
+      out[q] = f[q] - (f[q] - feq[q]) / p->tau_f +
+               (1.0 - 1.0 / (2.0 * p->tau_f)) * S[q];
+    for (int q = 0; q < NQ5; ++q) {
+      out[9 + q] = gx[q] - (gx[q] - geqx[q]) / p->tau_m;
+      out[14 + q] = gy[q] - (gy[q] - geqy[q]) / p->tau_m;
+    }
+    return;
+  }
+  /* f: even part at tau_f (viscosity), odd part at tau_fm. */
+  const double tfe = p->tau_f, tfo = p->tau_fm;
+  for (int q = 0; q < NQ9; ++q) {
+    const int r = OPP9[q];
+    const double fe = 0.5 * (f[q] + f[r]), fo = 0.5 * (f[q] - f[r]);
+    const double ee = 0.5 * (feq[q] + feq[r]), eo = 0.5 * (feq[q] - feq[r]);
+    const double se = 0.5 * (S[q] + S[r]), so = 0.5 * (S[q] - S[r]);
+    out[q] = f[q] - (fe - ee) / tfe - (fo - eo) / tfo +
+             (1.0 - 1.0 / (2.0 * tfe)) * se + (1.0 - 1.0 / (2.0 * tfo)) * so;
+  }
+  /* g: odd part at tau_m (magnetic diffusivity), even part at tau_mp. */
+  const double tme = p->tau_mp, tmo = p->tau_m;
+  for (int q = 0; q < NQ5; ++q) {
+    const int r = OPP5[q];
+    const double *g[2] = {gx, gy}, *ge[2] = {geqx, geqy};
+    for (int i = 0; i < 2; ++i) {
+      const double he = 0.5 * (g[i][q] + g[i][r]), ho = 0.5 * (g[i][q] - g[i][r]);
+      const double ee = 0.5 * (ge[i][q] + ge[i][r]), eo = 0.5 * (ge[i][q] - ge[i][r]);
+      out[9 + 5 * i + q] = g[i][q] - (he - ee) / tme - (ho - eo) / tmo;
+    }
+  }
+}
+
 static void step_rows(const orc_params *p, const double *in, double *out,
                       int y0, int y1) {
   for (int y = y0; y < y1; ++y) {
     for (int x = 0; x < p->nx; ++x) {
       node_t n;
       gather_node(p, in, x, y, &n);
-      /* S5: collide (Eqs. LBMforflowfield and LKSformagneticfield). */
-      double feq[NQ9], S[NQ9], geqx[NQ5], geqy[NQ5];
-      orc_feq(n.rho, n.ux, n.uy, feq);
-      orc_source(n.rho, n.ux, n.uy, n.Fx, n.Fy, feq, S);
-      orc_geq(n.bx, n.by, n.ux, n.uy, geqx, geqy);
-      for (int q = 0; q < NQ9; ++q)
-        out[idx(p, q, y, x)] = n.f[q] - (n.f[q] - feq[q]) / p->tau_f +
-                               (1.0 - 1.0 / (2.0 * p->tau_f)) * S[q];
-      for (int q = 0; q < NQ5; ++q) {
-        out[idx(p, 9 + q, y, x)] = n.gx[q] - (n.gx[q] - geqx[q]) / p->tau_m;
-        out[idx(p, 14 + q, y, x)] = n.gy[q] - (n.gy[q] - geqy[q]) / p->tau_m;
-      }
+      double o[NPLANES];
+      orc_collide(p, n.f, n.gx, n.gy, n.rho, n.ux, n.uy, n.bx, n.by, n.Fx,
+                  n.Fy, o);
+      for (int q = 0; q < NPLANES; ++q) out[idx(p, q, y, x)] = o[q];
     }
   }
 }
@@ -450,4 +503,4 @@ void orc_gather(const orc_params *p, const double *state, int x, int y,
   }
 }
 
-int orc_abi_version(void) { return 1; }
+int orc_abi_version(void) { return 2; }
