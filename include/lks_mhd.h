@@ -41,12 +41,27 @@
 extern "C" {
 #endif
 
-#define LKS_MHD_ABI_VERSION 1
+#define LKS_MHD_ABI_VERSION 2
 
 typedef struct lks_mhd lks_mhd_t;             /* one channel, library-owned */
 typedef struct lks_mhd_batch lks_mhd_batch_t; /* many channels, library-owned */
 
 enum lks_bc { LKS_BC_LINK = 0, LKS_BC_MOMENT = 1 };
+
+/* Collision operator.
+ *   BGK  the paper's single-relaxation-time operators (Secs. IV and V).
+ *   TRT  the two-relaxation-time form, one of the multiple-relaxation-time
+ *        replacements the paper names (Secs. V and IX).  Each population
+ *        splits into its parts even and odd under e -> -e, which relax at
+ *        separate rates.  tau_f keeps setting the viscosity (even part of
+ *        f) and tau_m the magnetic diffusivity (odd part of g), so the
+ *        wall coefficients and the current J_z are unchanged.  The free
+ *        rates come from the magic parameters
+ *          lambda_f = (tau_f - 1/2)(tau_f_odd - 1/2),
+ *          lambda_m = (tau_m_even - 1/2)(tau_m - 1/2).
+ *        lambda_f = 3/16 places half-way bounce-back walls exactly for
+ *        Poiseuille flow at every tau_f. */
+enum lks_collision { LKS_BGK = 0, LKS_TRT = 1 };
 
 /* Storage precision of the populations.
  *   FP64           stored as binary64, computed in FP64, rounded to nearest.
@@ -107,6 +122,9 @@ enum lks_status {
  *   u_max       target centreline velocity when fx is NaN.
  *   rho0        initial density [1]; the state starts at rest at rho0 with
  *               B = (0, B0) (zero induced field).
+ *   collision   lks_collision [LKS_BGK].
+ *   lambda_f,   TRT magic parameters, finite and > 0 [3/16, 1/4]; ignored
+ *   lambda_m    under BGK.
  */
 typedef struct {
   int32_t nx, ny;
@@ -120,6 +138,9 @@ typedef struct {
   double fx, fy;
   double u_max;
   double rho0;
+  int32_t collision;
+  int32_t reserved; /* 0 */
+  double lambda_f, lambda_m;
 } lks_mhd_params;
 
 /* Lattice quantities derived from a parameter set (host FP64). */
@@ -127,6 +148,7 @@ typedef struct {
   double nu, eta, a, b0, fx, fy;
   double theta_lower, theta_upper; /* link: theta = c_w a / (tau_m - 1/2), Eq. (weightingfactor) */
   double phi_lower, phi_upper;     /* moment: c_w a / (tau_m cs2m), from Eq. (momentbasedBCslowerboundary) */
+  double tau_f_odd, tau_m_even;    /* TRT: 1/2 + lambda / (tau - 1/2); BGK: tau_f, tau_m */
 } lks_mhd_derived;
 
 /* ABI version of the loaded library (LKS_MHD_ABI_VERSION). */

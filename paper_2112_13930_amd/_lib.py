@@ -23,6 +23,8 @@ PRECISIONS = {"fp64": LKS_FP64, "fp32": LKS_FP32, "fp16": LKS_FP16_STORE,
               "fp16_f32": LKS_FP16_STORE_F32}
 STORE_BYTES = {"fp64": 8, "fp32": 4, "fp16": 2, "fp16_f32": 2}
 BCS = {"link": LKS_BC_LINK, "moment": LKS_BC_MOMENT}
+LKS_BGK, LKS_TRT = 0, 1
+COLLISIONS = {"bgk": LKS_BGK, "trt": LKS_TRT}
 
 
 class LksParams(ctypes.Structure):
@@ -35,6 +37,8 @@ class LksParams(ctypes.Structure):
         ("u_lower", ctypes.c_double), ("u_upper", ctypes.c_double),
         ("fx", ctypes.c_double), ("fy", ctypes.c_double),
         ("u_max", ctypes.c_double), ("rho0", ctypes.c_double),
+        ("collision", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("lambda_f", ctypes.c_double), ("lambda_m", ctypes.c_double),
     ]
 
 
@@ -46,7 +50,7 @@ class LksParams3(ctypes.Structure):
 class LksDerived(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in
                 ("nu", "eta", "a", "b0", "fx", "fy", "theta_lower", "theta_upper",
-                 "phi_lower", "phi_upper")]
+                 "phi_lower", "phi_upper", "tau_f_odd", "tau_m_even")]
 
 
 class LksError(RuntimeError):
@@ -148,8 +152,11 @@ def check(code: int, what: str = "") -> int:
 
 def make_params(nx: int, ny: int, *, bc="link", precision="fp32", tau_f=0.8, tau_m=0.8,
                 ha=None, b0=None, c_lower=0.0, c_upper=None, u_lower=0.0, u_upper=0.0,
-                fx=None, fy=0.0, u_max=None, rho0=1.0) -> LksParams:
-    """Build a parameter struct.  ``ha`` derives B0; ``u_max`` derives F_x."""
+                fx=None, fy=0.0, u_max=None, rho0=1.0, collision="bgk", lambda_f=None,
+                lambda_m=None) -> LksParams:
+    """Build a parameter struct.  ``ha`` derives B0; ``u_max`` derives F_x;
+    ``collision`` is "bgk" or "trt" (magic parameters ``lambda_f``,
+    ``lambda_m``; the library's defaults when None)."""
     p = LksParams()
     lib().lks_mhd_default_params(ctypes.byref(p), int(nx), int(ny))
     p.bc = BCS[bc] if isinstance(bc, str) else int(bc)
@@ -169,6 +176,11 @@ def make_params(nx: int, ny: int, *, bc="link", precision="fp32", tau_f=0.8, tau
         p.fx = 0.0 if fx is None else float(fx)
     p.fy = float(fy)
     p.rho0 = float(rho0)
+    p.collision = COLLISIONS[collision] if isinstance(collision, str) else int(collision)
+    if lambda_f is not None:
+        p.lambda_f = float(lambda_f)
+    if lambda_m is not None:
+        p.lambda_m = float(lambda_m)
     return p
 
 

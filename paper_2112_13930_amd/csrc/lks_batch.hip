@@ -32,7 +32,7 @@ struct ChanDesc {
   double *rec;
   void *ref; // row references [ny][19] of the compute type
   Geom g;
-  int bc;
+  int bc;         // scheme: wall scheme | COLL_TRT for the TRT collision
   int phase;      // buffer holding the state when the global parity is 0
   int tile_first; // first tile of this channel in the list
   int tile_count;
@@ -98,10 +98,22 @@ __global__ __launch_bounds__(kTileThreads) void k_batch_step(
     auto one = [&](int x, int y) {
       NodeObs<C> o{};
       const C *ref = static_cast<const C *>(c.ref);
-      if (c.bc == BC_LINK)
+      switch (c.bc) { // uniform per block
+      case BC_LINK:
         node_update<S, C, BC_LINK, MODE, SR>(c.g, coef_of<C>(c), src, ref, dst, x, y, o, sseed);
-      else
+        break;
+      case BC_MOMENT:
         node_update<S, C, BC_MOMENT, MODE, SR>(c.g, coef_of<C>(c), src, ref, dst, x, y, o, sseed);
+        break;
+      case BC_LINK | COLL_TRT:
+        node_update<S, C, BC_LINK | COLL_TRT, MODE, SR>(c.g, coef_of<C>(c), src, ref, dst, x, y,
+                                                        o, sseed);
+        break;
+      default:
+        node_update<S, C, BC_MOMENT | COLL_TRT, MODE, SR>(c.g, coef_of<C>(c), src, ref, dst, x,
+                                                          y, o, sseed);
+        break;
+      }
       const long long i = (long long)y * c.g.nx + x;
       if constexpr (MODE == MODE_RECORD) {
         c.rec[i] = (double)o.ux;
@@ -691,7 +703,7 @@ int lks_mhd_batch_admit(lks_mhd_batch_t *b, const lks_mhd_params *p, int32_t *sl
     d.nx_shift = sh;
     d.nx_magic = (uint32_t)((((1ULL << 32) * ((1ULL << sh) - (uint64_t)q.nx)) / (uint64_t)q.nx) + 1ULL);
   }
-  d.bc = q.bc == LKS_BC_LINK ? BC_LINK : BC_MOMENT;
+  d.bc = scheme_of(q);
   // the initial state goes to buf[0]; at the next step the global parity is
   // b->parity, and the channel must read buf[0] then: phase = parity.
   d.phase = b->parity;
@@ -862,7 +874,7 @@ int lks_mhd_batch_moments(lks_mhd_batch_t *b, int32_t slot, double *rho, double 
   const long long n = (long long)d.g.nx * d.g.ny;
   const dim3 grid((unsigned)((n + 255) / 256));
   return with_device(b, [&]() -> int {
-    const bool link = d.bc == BC_LINK;
+    const bool link = wall_of(d.bc) == BC_LINK;
     dispatch_precision(b->precision, [&](auto t) {
       using S = typename decltype(t)::S;
       using C = typename decltype(t)::C;

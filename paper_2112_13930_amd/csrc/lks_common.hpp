@@ -56,7 +56,19 @@ Coef<C> make_coef(const Channel &c) {
   k.fey = C(c.d.fy);
   k.lo = Wall<C>{C(lo.r), C(lo.s), C(lo.t), C(lo.u), C(lo.uw6)};
   k.hi = Wall<C>{C(hi.r), C(hi.s), C(hi.t), C(hi.u), C(hi.uw6)};
+  // TRT pair coefficients (Trt<C>); under BGK they describe the same
+  // operator (pb = sb = 0) and go unused
+  const double fp = 1.0 / c.p.tau_f, fm = 1.0 / c.d.tau_f_odd;
+  const double gp = 1.0 / c.d.tau_m_even, gm = 1.0 / c.p.tau_m;
+  const double fa = 0.5 * (fp + fm), fb = 0.5 * (fp - fm);
+  k.trt = Trt<C>{C(fa), C(fb), C(1.0 - 0.5 * fa), C(-0.5 * fb),
+                 C(0.5 * (gp + gm)), C(0.5 * (gp - gm)), C(gp)};
   return k;
+}
+
+// The kernels' scheme parameter of a channel: wall scheme | collision.
+inline int scheme_of(const lks_mhd_params &p) {
+  return (p.bc == LKS_BC_LINK ? BC_LINK : BC_MOMENT) | (p.collision == LKS_TRT ? COLL_TRT : 0);
 }
 
 inline bool valid_precision(int precision) {

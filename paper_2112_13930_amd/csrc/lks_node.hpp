@@ -51,6 +51,11 @@
 namespace lks {
 
 enum { BC_LINK = 0, BC_MOMENT = 1 };
+// The kernels' scheme parameter is the wall scheme, optionally combined with
+// COLL_TRT for the two-relaxation-time collision (BGK otherwise).
+constexpr int COLL_TRT = 4;
+constexpr int wall_of(int scheme) { return scheme & 3; }
+constexpr bool trt_of(int scheme) { return (scheme & COLL_TRT) != 0; }
 enum { MODE_STEP = 0, MODE_RECORD = 1, MODE_RESIDUAL = 2, MODE_MOMENTS = 3 };
 
 // Closure coefficients of one wall (computed on the host in FP64).
@@ -65,6 +70,21 @@ struct Wall {
   C r, s, t, u, uw6;
 };
 
+// Two-relaxation-time coefficients.  With n = f^eq - f, the update of a
+// population whose opposite is abar (e_abar = -e_a),
+//   f~_a = f_a + pa n_a + pb n_abar + sa S_a + sb S_abar,
+// relaxes the even part (f_a + f_abar)/2 at w+ and the odd part at w-, and
+// adds the even and odd parts of the source with 1 - w+/2 and 1 - w-/2:
+//   pa = (w+ + w-)/2, pb = (w+ - w-)/2, sa = 1 - pa/2, sb = -pb/2.
+// f: w+ = 1/tau_f (viscosity), w- from the magic parameter Lambda_f;
+// g: w- = 1/tau_m (magnetic diffusivity), w+ = gp from Lambda_m; g has no
+// source.  Rest populations are even: f at omega_f/kappa_f, g at gp.
+template <typename C>
+struct Trt {
+  C fa, fb, fsa, fsb;
+  C ga, gb, gp;
+};
+
 template <typename C>
 struct Coef {
   C omega_f;  // 1/tau_f
@@ -74,6 +94,7 @@ struct Coef {
   C b0;       // imposed field (along +y)
   C fex, fey; // external body force
   Wall<C> lo, hi;
+  Trt<C> trt; // used by schemes with COLL_TRT
 };
 
 // Geometry of one channel's planes (element units).
@@ -162,6 +183,38 @@ __device__ __forceinline__ C collide_f(C f, C w, C ex, C ey, C rhop, C rho,
   return f + omega * (feq - f) + kappa * S;
 }
 
+// Two-relaxation-time update of the pair (a, abar) of opposite f
+// populations, e_a = (ex, ey), in deviation form (see Trt).
+template <typename C>
+__device__ __forceinline__ void collide_f_pair(C &fa, C &fb, C w, C ex, C ey, C rhop, C rho,
+                                               C ux, C uy, C usq15, C Fx, C Fy, C uF,
+                                               const Trt<C> &t) {
+  const C eu = ex * ux + ey * uy;
+  const C even = C(4.5) * eu * eu - usq15;
+  const C odd = C(3) * eu;
+  const C pa = even + odd, pb = even - odd; // poly of a and of abar
+  const C na = w * (rhop + rho * pa) - fa;
+  const C nb = w * (rhop + rho * pb) - fb;
+  const C eF = ex * Fx + ey * Fy;
+  const C Sa = C(3) * w * (eF - uF) * (C(1) + pa);
+  const C Sb = C(3) * w * (-eF - uF) * (C(1) + pb);
+  const C ra = fa + t.fa * na + t.fb * nb + t.fsa * Sa + t.fsb * Sb;
+  const C rb = fb + t.fa * nb + t.fb * na + t.fsa * Sb + t.fsb * Sa;
+  fa = ra;
+  fb = rb;
+}
+
+// Two-relaxation-time update of a pair of opposite g populations with
+// equilibria ea, eb.
+template <typename C>
+__device__ __forceinline__ void collide_g_pair(C &ga, C &gb, C ea, C eb, const Trt<C> &t) {
+  const C na = ea - ga, nb = eb - gb;
+  const C ra = ga + t.ga * na + t.gb * nb;
+  const C rb = gb + t.ga * nb + t.gb * na;
+  ga = ra;
+  gb = rb;
+}
+
 // Everything after streaming for one node: wall closure, moments, coupled
 // solve, collision.  f, gx, gy hold the pulled (post-streaming) populations;
 // those that would come from behind a wall are set by the closure (the
@@ -180,7 +233,7 @@ __device__ __forceinline__ void node_finish(const Geom &g, const Coef<C> &k,
   const long long r0 = (long long)y * g.pitch;
   const C *__restrict__ Dy = ref + (long long)y * 19; // reference of this row
   // ---- wall closures for the populations entering from a wall ----
-  if (BC == BC_LINK) {
+  if (wall_of(BC) == BC_LINK) {
     // Half-way bounce-back of f with Ladd's moving-wall term; theta-weighted
     // bounce-back/anti-bounce-back of g_x; anti-bounce-back to B_y = B0 for
     // g_y, which for the deviations g_y - W B0 is g'_in = -g~'_out.  All from
@@ -239,7 +292,7 @@ __device__ __forceinline__ void node_finish(const Geom &g, const Coef<C> &k,
   // ---- coupled local solve ----
   C ux, uy, jz, Fx, Fy;
   const C inv_rho = C(1) / rho;
-  if (BC == BC_MOMENT && (lo || hi)) {
+  if (wall_of(BC) == BC_MOMENT && (lo || hi)) {
     // wet wall node: velocity fixed by the closure, no force
     ux = mx * inv_rho;
     uy = my * inv_rho;
@@ -283,6 +336,34 @@ __device__ __forceinline__ void node_finish(const Geom &g, const Coef<C> &k,
   const C usq15 = C(1.5) * (ux * ux + uy * uy);
   const C uF = ux * Fx + uy * Fy;
   const C w0 = W<C>::w0, w1 = W<C>::w1, w5 = W<C>::w5;
+  // g^eq_{a i} = W_a [B_i + e_aj (u_j B_i - B_j u_i) / cs2m]  (Sec. IV):
+  // with E = u_x B_y - u_y B_x only g_2x, g_4x (-/+ 3E) and g_1y, g_3y (+/- 3E)
+  // carry the flux term.
+  const C E3 = C(3) * (ux * by - uy * bx);
+  const C W0 = W<C>::W0, W1 = W<C>::W1;
+  if constexpr (trt_of(BC)) {
+    // pairs (1,3), (2,4), (5,7), (6,8) of D2Q9 and (1,3), (2,4) of D2Q5;
+    // stores stay in plane order, so every plane keeps its random word
+    const Trt<C> &t = k.trt;
+    f[0] = collide_f(f[0], w0, C(0), C(0), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka);
+    collide_f_pair(f[1], f[3], w1, C(1), C(0), rhop, rho, ux, uy, usq15, Fx, Fy, uF, t);
+    collide_f_pair(f[2], f[4], w1, C(0), C(1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, t);
+    collide_f_pair(f[5], f[7], w5, C(1), C(1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, t);
+    collide_f_pair(f[6], f[8], w5, C(-1), C(1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, t);
+    gx[0] += t.gp * (W0 * bx - gx[0]);
+    collide_g_pair(gx[1], gx[3], W1 * bx, W1 * bx, t);
+    collide_g_pair(gx[2], gx[4], W1 * (bx - E3), W1 * (bx + E3), t);
+    gy[0] += t.gp * (W0 * byp - gy[0]);
+    collide_g_pair(gy[1], gy[3], W1 * (byp + E3), W1 * (byp - E3), t);
+    collide_g_pair(gy[2], gy[4], W1 * byp, W1 * byp, t);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) out[q] = put(f[q], q);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) out[9 + q] = put(gx[q], 9 + q);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) out[14 + q] = put(gy[q], 14 + q);
+    return;
+  }
   out[0] = put(collide_f(f[0], w0, C(0), C(0), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), 0);
   out[1] = put(collide_f(f[1], w1, C(1), C(0), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), 1);
   out[2] = put(collide_f(f[2], w1, C(0), C(1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), 2);
@@ -293,12 +374,7 @@ __device__ __forceinline__ void node_finish(const Geom &g, const Coef<C> &k,
   out[7] = put(collide_f(f[7], w5, C(-1), C(-1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), 7);
   out[8] = put(collide_f(f[8], w5, C(1), C(-1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), 8);
 
-  // g^eq_{a i} = W_a [B_i + e_aj (u_j B_i - B_j u_i) / cs2m]  (Sec. IV):
-  // with E = u_x B_y - u_y B_x only g_2x, g_4x (-/+ 3E) and g_1y, g_3y (+/- 3E)
-  // carry the flux term.
-  const C E3 = C(3) * (ux * by - uy * bx);
   const C wm = k.omega_m;
-  const C W0 = W<C>::W0, W1 = W<C>::W1;
   out[9] = put(gx[0] + wm * (W0 * bx - gx[0]), 9);
   out[10] = put(gx[1] + wm * (W1 * bx - gx[1]), 10);
   out[11] = put(gx[2] + wm * (W1 * (bx - E3) - gx[2]), 11);

@@ -6,6 +6,7 @@
 //   u*(0) = (K/Ha)(1 - 1/cosh Ha), K = (c+1)/(Ha c + tanh Ha)          (Sec. VIII)
 //   theta = c_w a / (tau_m - 1/2)                         (Eq. weightingfactor)
 //   phi = c_w a / (tau_m cs2m)     (ratio of the two coefficients of Sec. VII)
+//   TRT free rates: tau- = 1/2 + Lambda / (tau+ - 1/2) and conversely
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -60,6 +61,11 @@ int derive_channel(const lks_mhd_params *p, Channel *out) {
   if (!finite(p->u_lower) || !finite(p->u_upper)) return bad("wall velocities must be finite");
   if (!finite(p->rho0) || p->rho0 <= 0.0) return bad("rho0 must be finite and > 0");
   if (!finite(p->fy)) return bad("fy must be finite");
+  if (p->collision != LKS_BGK && p->collision != LKS_TRT)
+    return bad("collision must be LKS_BGK or LKS_TRT");
+  if (p->collision == LKS_TRT &&
+      (!finite(p->lambda_f) || p->lambda_f <= 0.0 || !finite(p->lambda_m) || p->lambda_m <= 0.0))
+    return bad("TRT needs finite lambda_f > 0 and lambda_m > 0");
 
   Channel c;
   c.p = *p;
@@ -91,6 +97,15 @@ int derive_channel(const lks_mhd_params *p, Channel *out) {
   d.theta_upper = std::isinf(p->c_upper) ? INFINITY : p->c_upper * d.a / (p->tau_m - 0.5);
   d.phi_lower = std::isinf(p->c_lower) ? INFINITY : p->c_lower * d.a * 3.0 / p->tau_m;
   d.phi_upper = std::isinf(p->c_upper) ? INFINITY : p->c_upper * d.a * 3.0 / p->tau_m;
+  // TRT: the free rate of each distribution from its magic parameter
+  // Lambda = (tau+ - 1/2)(tau- - 1/2)
+  if (p->collision == LKS_TRT) {
+    d.tau_f_odd = 0.5 + p->lambda_f / (p->tau_f - 0.5);
+    d.tau_m_even = 0.5 + p->lambda_m / (p->tau_m - 0.5);
+  } else {
+    d.tau_f_odd = p->tau_f;
+    d.tau_m_even = p->tau_m;
+  }
   if (out) *out = c;
   return LKS_OK;
 }
@@ -156,6 +171,9 @@ void lks_mhd_default_params(lks_mhd_params *p, int32_t nx, int32_t ny) {
   p->fy = 0.0;
   p->u_max = 0.0;
   p->rho0 = 1.0;
+  p->collision = LKS_BGK;
+  p->lambda_f = 3.0 / 16.0;
+  p->lambda_m = 0.25;
 }
 
 int lks_mhd_validate(const lks_mhd_params *p) {

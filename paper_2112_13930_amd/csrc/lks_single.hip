@@ -314,12 +314,24 @@ hipError_t launch_bc(lks_mhd *h, int shape, const void *src, void *dst, ObsOut o
 
 template <int MODE>
 hipError_t launch_mode(lks_mhd *h, int shape, const void *src, void *dst, ObsOut oo) {
-  const bool link = h->ch.p.bc == LKS_BC_LINK;
+  // observables do not depend on the collision operator
+  const int sch = MODE == MODE_MOMENTS ? wall_of(scheme_of(h->ch.p)) : scheme_of(h->ch.p);
   return dispatch_precision(h->ch.p.precision, [&](auto t) -> hipError_t {
     using S = typename decltype(t)::S;
     using C = typename decltype(t)::C;
-    return link ? launch_bc<S, C, BC_LINK, MODE>(h, shape, src, dst, oo)
-                : launch_bc<S, C, BC_MOMENT, MODE>(h, shape, src, dst, oo);
+    switch (sch) {
+    case BC_LINK: return launch_bc<S, C, BC_LINK, MODE>(h, shape, src, dst, oo);
+    case BC_MOMENT: return launch_bc<S, C, BC_MOMENT, MODE>(h, shape, src, dst, oo);
+    case BC_LINK | COLL_TRT:
+      if constexpr (MODE != MODE_MOMENTS)
+        return launch_bc<S, C, BC_LINK | COLL_TRT, MODE>(h, shape, src, dst, oo);
+      break;
+    default:
+      if constexpr (MODE != MODE_MOMENTS)
+        return launch_bc<S, C, BC_MOMENT | COLL_TRT, MODE>(h, shape, src, dst, oo);
+      break;
+    }
+    return hipErrorInvalidValue;
   });
 }
 

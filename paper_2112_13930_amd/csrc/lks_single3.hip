@@ -209,6 +209,10 @@ int validate3(const lks_mhd3_params *p, Channel *c) {
     set_error("invalid parameters: fz must be finite");
     return LKS_EINVAL;
   }
+  if (p->base.collision != LKS_BGK) {
+    set_error("invalid parameters: the three-dimensional channel collides with BGK only");
+    return LKS_EINVAL;
+  }
   return LKS_OK;
 }
 

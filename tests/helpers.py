@@ -12,9 +12,22 @@ from oracle import Params
 
 def lib_kwargs(p: Params, precision: str) -> dict:
     """make_params keywords giving the library exactly the oracle's inputs."""
-    return dict(bc="link" if p.bc == oracle.LINK else "moment", precision=precision,
-                tau_f=p.tau_f, tau_m=p.tau_m, b0=p.b0, fx=p.fx, fy=p.fy,
-                c_lower=p.c_lo, c_upper=p.c_hi, u_lower=p.u_lo, u_upper=p.u_hi)
+    kw = dict(bc="link" if p.bc == oracle.LINK else "moment", precision=precision,
+              tau_f=p.tau_f, tau_m=p.tau_m, b0=p.b0, fx=p.fx, fy=p.fy,
+              c_lower=p.c_lo, c_upper=p.c_hi, u_lower=p.u_lo, u_upper=p.u_hi)
+    if p.collision == oracle.TRT:
+        kw.update(collision="trt", lambda_f=p.extra["lambda_f"], lambda_m=p.extra["lambda_m"])
+    return kw
+
+
+def trt(p: Params, lambda_f: float = 3.0 / 16.0, lambda_m: float = 0.25) -> Params:
+    """The TRT variant of an oracle parameter set: both sides derive the free
+    relaxation times from the same magic parameters."""
+    from oracle import derive
+    tfm, tmp = derive.trt_times(p.tau_f, p.tau_m, lambda_f, lambda_m)
+    q = Params(**{**p.__dict__, "collision": oracle.TRT, "tau_fm": tfm, "tau_mp": tmp,
+                  "extra": {**p.extra, "lambda_f": lambda_f, "lambda_m": lambda_m}})
+    return q
 
 
 def rel_l2(a, b) -> float:

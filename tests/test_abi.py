@@ -39,7 +39,7 @@ def test_every_declared_symbol_is_exported(L):
 
 
 def test_abi_version(L):
-    assert L.lib().lks_mhd_abi_version() == 1
+    assert L.lib().lks_mhd_abi_version() == 2
 
 
 def _v(L, **kw):
@@ -57,7 +57,8 @@ def _v(L, **kw):
     dict(ha=10.0, b0=0.5),                       # inconsistent
     dict(u_max=0.05, c_lower=0.1, c_upper=0.2),  # fx from u_max needs equal walls
     dict(u_upper=float("inf")), dict(rho0=0.0), dict(precision=7), dict(precision=4),
-    dict(bc=5),
+    dict(bc=5), dict(collision=2), dict(collision="trt", lambda_f=0.0),
+    dict(collision="trt", lambda_m=float("inf")), dict(collision="trt", lambda_m=-1.0),
 ])
 def test_validate_rejects(L, kw):
     rc, p = _v(L, **kw)
@@ -71,6 +72,8 @@ def test_validate_rejects(L, kw):
     dict(ha=10.0, u_max=0.05, c_lower=0.1), dict(ha=0.0, u_max=0.05),
     dict(ha=5.0, c_lower=math.inf, u_max=0.01, bc="moment"),
     dict(precision="fp64"), dict(precision="fp16"), dict(precision="fp16_f32"),
+    dict(collision="trt"), dict(collision="trt", lambda_f=0.25, lambda_m=1.0 / 12.0),
+    dict(collision="bgk", lambda_f=float("nan")),  # magic parameters unused under BGK
 ])
 def test_validate_accepts(L, kw):
     rc, p = _v(L, **kw)
@@ -95,6 +98,19 @@ def test_derivation_agrees_with_oracle(L, bc, ha, c):
     assert math.isclose(d.eta, od.eta_of(0.9), rel_tol=1e-15)
     theta = math.inf if math.isinf(c) else c * q.a / (0.9 - 0.5)
     assert d.theta_lower == pytest.approx(theta, rel=1e-15)
+
+
+@pytest.mark.parametrize("tau_f,tau_m,lf,lm", [(0.8, 0.9, 3 / 16, 0.25), (0.55, 1.7, 0.01, 2.0)])
+def test_trt_times_agree_with_oracle(L, tau_f, tau_m, lf, lm):
+    p = L.make_params(8, 8, tau_f=tau_f, tau_m=tau_m, collision="trt", lambda_f=lf, lambda_m=lm)
+    d = L.derive(p)
+    assert (d.tau_f_odd, d.tau_m_even) == od.trt_times(tau_f, tau_m, lf, lm)
+    assert math.isclose((tau_f - 0.5) * (d.tau_f_odd - 0.5), lf, rel_tol=1e-14)
+    assert math.isclose((d.tau_m_even - 0.5) * (tau_m - 0.5), lm, rel_tol=1e-14)
+    q = L.make_params(8, 8, tau_f=tau_f, tau_m=tau_m)
+    assert q.collision == L.LKS_BGK and (q.lambda_f, q.lambda_m) == (3 / 16, 0.25)
+    e = L.derive(q)
+    assert (e.tau_f_odd, e.tau_m_even) == (tau_f, tau_m)
 
 
 def test_bytes_per_node(L):
@@ -150,6 +166,9 @@ def test_3d_sizing_and_validation(L):
     p.base = L.make_params(2048, 2048, precision="fp32")
     p.nz = 1024
     assert lib.lks_mhd3_state_bytes(ctypes.byref(p)) == 0
+    p.base = L.make_params(64, 32, precision="fp32", collision="trt")
+    p.nz = 4
+    assert lib.lks_mhd3_state_bytes(ctypes.byref(p)) == 0 and "BGK" in L.last_error()
     h = ctypes.c_void_p()
     p.base = L.make_params(8, 8, precision="fp64")
     p.nz = 2
