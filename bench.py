@@ -26,7 +26,9 @@ Printed as one JSON line with, besides the contract fields:
                 the continuous-batching solve service (FP32 and binary16)
                 against sequential plain FP32 solves at six arrival rates;
                 the headline step on a developed (random) state; the 3D
-                channel (D3Q19 + D3Q7 field) on 256^3.
+                channel (D3Q19 + D3Q7 field) on 256^3; the two-relaxation-time
+                collision's rates beside BGK's.
+  --only LEG    run one of the extra legs alone and print it (development).
 
 Profiling helpers (used to write profiles/*):
   --profile-run     only warm-up + timed steps of the headline, plus a copy of
@@ -271,6 +273,24 @@ def other_precisions(torch, steps=200, warmup=20, err_steps=100_000):
     return out
 
 
+def trt_rates(torch, steps=200, warmup=20):
+    """The two-relaxation-time collision on the headline grid: rates with
+    link-based and moment-based walls in FP32 and binary16 storage (magic
+    parameters 3/16 for f and 1/4 for g), beside BGK's."""
+    from paper_2112_13930_amd.channel import Channel
+    out = {}
+    for prec, bpn in (("fp32", 152), ("fp16", 76)):
+        for bc in ("link", "moment"):
+            for coll in ("bgk", "trt"):
+                kw = dict(HEADLINE, precision=prec, bc=bc, collision=coll)
+                _, per_step, ch = time_channel(torch, Channel, kw, steps, warmup)
+                ch.close()
+                gbs = bpn * 4096 * 4096 / per_step / 1e9
+                out[f"{prec}_{bc}_{coll}"] = {"mlups": round(4096 * 4096 / per_step / 1e6, 1),
+                                              "frac_hbm": round(gbs / PEAK_HBM_GBS, 3)}
+    return out
+
+
 def stable_mix(n, seed):
     """Config-4 channel draws, rejecting draws whose imposed field exceeds
     0.1 (Alfven speed near the lattice limit; equivalently a Hartmann layer
@@ -483,6 +503,12 @@ def write_summary(dirs, command):
 
 # ---------------------------------------------------------------------------
 
+LEGS = {"developed": developed_state_rate, "sweep": sweep, "precisions": other_precisions,
+        "channel_3d": three_d, "trt": trt_rates,
+        "batched": lambda torch: batched(torch, "fp32"),
+        "serving": serving}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -493,6 +519,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--profile-run", action="store_true")
     ap.add_argument("--profile-3d", action="store_true", help="3D FP32 steps only (profiling)")
+    ap.add_argument("--only", choices=sorted(LEGS), help="run one extra leg and print it")
     ap.add_argument("--summarize", nargs="*")
     ap.add_argument("--command", default="")
     args = ap.parse_args()
@@ -523,6 +550,9 @@ def main():
         return 0
     if args.profile_3d:
         profile_run_3d(torch, args)
+        return 0
+    if args.only:
+        print(json.dumps({args.only: LEGS[args.only](torch)}), flush=True)
         return 0
 
     h = headline(torch, args)
@@ -571,6 +601,8 @@ def main():
         extras["precisions"] = other_precisions(torch)
         log("3D channel ...")
         extras["channel_3d"] = three_d(torch)
+        log("TRT collision ...")
+        extras["trt_collision"] = trt_rates(torch)
         log("batched ...")
         extras["batched_256_channels"] = batched(torch, "fp32")
         extras["batched_256_channels_fp16"] = batched(torch, "fp16", sequential=False)
