@@ -24,6 +24,7 @@ SRC = os.path.join(HERE, "lks_oracle3.c")
 LIB = os.path.join(HERE, "liblks_oracle3.so")
 
 LINK, MOMENT = 0, 1
+BGK, TRT = 0, 1
 NPLANES = 40
 NF, NG = 19, 7
 
@@ -47,6 +48,8 @@ class _Params3(ctypes.Structure):
         ("fx", ctypes.c_double), ("fy", ctypes.c_double), ("fz", ctypes.c_double),
         ("c_lo", ctypes.c_double), ("c_hi", ctypes.c_double),
         ("u_lo", ctypes.c_double), ("u_hi", ctypes.c_double), ("a", ctypes.c_double),
+        ("collision", ctypes.c_int32), ("pad_", ctypes.c_int32),
+        ("tau_fm", ctypes.c_double), ("tau_mp", ctypes.c_double),
     ]
 
 
@@ -71,9 +74,10 @@ def lib():
         L.orc3_run.argtypes = [pp, dp, dp, ctypes.c_int64, ctypes.c_int]
         L.orc3_observe.argtypes = [pp, dp, dp]
         L.orc3_gather.argtypes = [pp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
+        L.orc3_collide.argtypes = [pp, dp, dp, ctypes.c_double, dp, dp, dp, dp]
         for name in ("orc3_feq", "orc3_geq", "orc3_source", "orc3_local_solve",
                      "orc3_link_closure", "orc3_moment_closure", "orc3_init", "orc3_step",
-                     "orc3_run", "orc3_observe", "orc3_gather"):
+                     "orc3_run", "orc3_observe", "orc3_gather", "orc3_collide"):
             getattr(L, name).restype = None
         _lib = L
     return _lib
@@ -101,6 +105,9 @@ class Params3:
     u_lo: float = 0.0
     u_hi: float = 0.0
     a: float | None = None
+    collision: int = BGK
+    tau_fm: float = float("nan")
+    tau_mp: float = float("nan")
 
     def half_width(self) -> float:
         if self.a is not None:
@@ -108,9 +115,11 @@ class Params3:
         return self.ny / 2.0 if self.bc == LINK else (self.ny - 1) / 2.0
 
     def c_struct(self) -> _Params3:
+        if self.collision == TRT:
+            assert self.tau_fm > 0.5 and self.tau_mp > 0.5, "TRT needs tau_fm and tau_mp > 1/2"
         return _Params3(self.nx, self.ny, self.nz, self.bc, self.tau_f, self.tau_m, self.b0,
                         self.fx, self.fy, self.fz, self.c_lo, self.c_hi, self.u_lo, self.u_hi,
-                        self.half_width())
+                        self.half_width(), self.collision, 0, self.tau_fm, self.tau_mp)
 
     @classmethod
     def from_2d(cls, p, nz: int) -> "Params3":
@@ -118,7 +127,8 @@ class Params3:
         periodic layers."""
         return cls(nx=p.nx, ny=p.ny, nz=nz, bc=p.bc, tau_f=p.tau_f, tau_m=p.tau_m, b0=p.b0,
                    fx=p.fx, fy=p.fy, fz=0.0, c_lo=p.c_lo, c_hi=p.c_hi, u_lo=p.u_lo,
-                   u_hi=p.u_hi, a=p.half_width())
+                   u_hi=p.u_hi, a=p.half_width(), collision=p.collision, tau_fm=p.tau_fm,
+                   tau_mp=p.tau_mp)
 
 
 def init_state(p: Params3, rho0: float = 1.0) -> np.ndarray:
@@ -192,6 +202,17 @@ def local_solve(rho, m, b, lam, tau_m, fext=(0.0, 0.0, 0.0)):
                            _dp(np.ascontiguousarray(lam, dtype=np.float64).reshape(9)), tau_m,
                            _dp(np.asarray(fext, dtype=np.float64)), _dp(out))
     return out[:3], out[3:]
+
+
+def collide(p: Params3, f, g, rho, u, b, F) -> np.ndarray:
+    """The 40 post-collision values of one node (g given as [7][3])."""
+    out = np.empty(NPLANES)
+    lib().orc3_collide(ctypes.byref(p.c_struct()),
+                       _dp(np.ascontiguousarray(f, dtype=np.float64)),
+                       _dp(np.ascontiguousarray(g, dtype=np.float64).reshape(21)), rho,
+                       _dp(np.asarray(u, dtype=np.float64)), _dp(np.asarray(b, dtype=np.float64)),
+                       _dp(np.asarray(F, dtype=np.float64)), _dp(out))
+    return out
 
 
 # Velocity sets, typed here for the tests only (the C file has its own).

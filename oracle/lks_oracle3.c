@@ -64,6 +64,10 @@ static const double CSM2 = 1.0 / 3.0;
 
 enum { O3_LINK = 0, O3_MOMENT = 1 };
 enum { O3_LOWER = 0, O3_UPPER = 1 };
+/* Collision: BGK, or two relaxation times with tau_f on the even part of f
+ * (viscosity) and tau_m on the odd part of g (magnetic diffusivity); tau_fm
+ * and tau_mp are the free times of the other parts. */
+enum { O3_BGK = 0, O3_TRT = 1 };
 
 typedef struct {
   int32_t nx, ny, nz, bc;
@@ -73,6 +77,9 @@ typedef struct {
   double c_lo, c_hi; /* wall conductance ratios c_w (0 .. INFINITY) */
   double u_lo, u_hi; /* wall velocities along x */
   double a;          /* half-width */
+  int32_t collision, pad_;
+  double tau_fm;     /* TRT: odd part of f */
+  double tau_mp;     /* TRT: even part of g */
 } orc3_params;
 
 static int opp3(int q) {
@@ -373,21 +380,54 @@ static void gather3(const orc3_params *p, const double *in, int x, int y, int z,
   n->F[2] = p->fz + (J[0] * b[1] - J[1] * b[0]);
 }
 
+/* Collision of one node: f[19] and g[7*3] (g[q*3+i]) post-streaming and
+ * post-closure, with the fields of the solve; out receives the 40 planes
+ * (f, then g per component).  BGK as in Sec. V; TRT relaxes the parts even
+ * and odd under e -> -e at their own rates, the source's parts with the
+ * matching weights 1 - 1/(2 tau). */
+void orc3_collide(const orc3_params *p, const double *f, const double *g, double rho,
+                  const double *u, const double *b, const double *F, double *out) {
+  double feq[NQF], S[NQF], geq[NQG * 3];
+  orc3_feq(rho, u, feq);
+  orc3_source(rho, u, F, feq, S);
+  orc3_geq(b, u, geq);
+  if (p->collision != O3_TRT) {
+    for (int q = 0; q < NQF; ++q)
+      out[q] = f[q] - (f[q] - feq[q]) / p->tau_f + (1.0 - 1.0 / (2.0 * p->tau_f)) * S[q];
+    for (int q = 0; q < NQG; ++q)
+      for (int i = 0; i < 3; ++i)
+        out[19 + i * 7 + q] = g[q * 3 + i] - (g[q * 3 + i] - geq[q * 3 + i]) / p->tau_m;
+    return;
+  }
+  const double tfe = p->tau_f, tfo = p->tau_fm;
+  for (int q = 0; q < NQF; ++q) {
+    const int r = opp3(q);
+    const double fe = 0.5 * (f[q] + f[r]), fo = 0.5 * (f[q] - f[r]);
+    const double ee = 0.5 * (feq[q] + feq[r]), eo = 0.5 * (feq[q] - feq[r]);
+    const double se = 0.5 * (S[q] + S[r]), so = 0.5 * (S[q] - S[r]);
+    out[q] = f[q] - (fe - ee) / tfe - (fo - eo) / tfo + (1.0 - 1.0 / (2.0 * tfe)) * se +
+             (1.0 - 1.0 / (2.0 * tfo)) * so;
+  }
+  const double tme = p->tau_mp, tmo = p->tau_m;
+  for (int q = 0; q < NQG; ++q) {
+    const int r = oppg(q);
+    for (int i = 0; i < 3; ++i) {
+      const double he = 0.5 * (g[q * 3 + i] + g[r * 3 + i]);
+      const double ho = 0.5 * (g[q * 3 + i] - g[r * 3 + i]);
+      const double ee = 0.5 * (geq[q * 3 + i] + geq[r * 3 + i]);
+      const double eo = 0.5 * (geq[q * 3 + i] - geq[r * 3 + i]);
+      out[19 + i * 7 + q] = g[q * 3 + i] - (he - ee) / tme - (ho - eo) / tmo;
+    }
+  }
+}
+
 static void step_line(const orc3_params *p, const double *in, double *out, int z, int y) {
   for (int x = 0; x < p->nx; ++x) {
     node3_t n;
     gather3(p, in, x, y, z, &n);
-    double feq[NQF], S[NQF], geq[NQG * 3];
-    orc3_feq(n.rho, n.u, feq);
-    orc3_source(n.rho, n.u, n.F, feq, S);
-    orc3_geq(n.b, n.u, geq);
-    for (int q = 0; q < NQF; ++q)
-      out[idx3(p, q, z, y, x)] =
-          n.f[q] - (n.f[q] - feq[q]) / p->tau_f + (1.0 - 1.0 / (2.0 * p->tau_f)) * S[q];
-    for (int q = 0; q < NQG; ++q)
-      for (int i = 0; i < 3; ++i)
-        out[idx3(p, 19 + i * 7 + q, z, y, x)] =
-            n.g[q * 3 + i] - (n.g[q * 3 + i] - geq[q * 3 + i]) / p->tau_m;
+    double o[NPL3];
+    orc3_collide(p, n.f, n.g, n.rho, n.u, n.b, n.F, o);
+    for (int q = 0; q < NPL3; ++q) out[idx3(p, q, z, y, x)] = o[q];
   }
 }
 

@@ -159,3 +159,102 @@ def test_thread_count_does_not_change_result():
     a = d3.run(p, s.copy(), 6, nthreads=1)
     b = d3.run(p, s.copy(), 6, nthreads=4)
     assert np.array_equal(a, b)
+
+
+# ---- two-relaxation-time collision ----
+
+def _basis3():
+    ex, ey, ez = (d3.EF[:, i].astype(float) for i in range(3))
+    even = [np.ones(19), ex**2, ey**2, ez**2, ex * ey, ex * ez, ey * ez, ex**2 * ey**2,
+            ex**2 * ez**2, ey**2 * ez**2]
+    odd = [ex, ey, ez, ex * ey**2, ex * ez**2, ey * ex**2, ey * ez**2, ez * ex**2, ez * ey**2]
+    gx, gy, gz = (d3.EG[:, i].astype(float) for i in range(3))
+    return (np.array(even), np.array(odd), np.array([np.ones(7), gx**2, gy**2, gz**2]),
+            np.array([gx, gy, gz]))
+
+
+def test_trt_moment_bases_span_d3q19_and_d3q7():
+    e9, o9, e7, o7 = _basis3()
+    assert np.linalg.matrix_rank(np.vstack([e9, o9])) == 19
+    assert np.linalg.matrix_rank(np.vstack([e7, o7])) == 7
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_trt_collision_moment_algebra_3d(seed):
+    """Every basis moment relaxes at the rate of its parity (the bases span
+    the population spaces, so this fixes the operator)."""
+    rng = np.random.default_rng(100 + seed)
+    tau_f, tau_fm, tau_m, tau_mp = rng.uniform(0.55, 2.0, 4)
+    p = d3.Params3(nx=1, ny=3, nz=1, tau_f=tau_f, tau_m=tau_m, collision=d3.TRT,
+                   tau_fm=tau_fm, tau_mp=tau_mp)
+    f = rng.uniform(0.0, 0.3, 19)
+    g = rng.uniform(-0.05, 0.05, (7, 3))
+    rho = 1 + 0.1 * rng.uniform(-1, 1)
+    u, b, F = 0.05 * rng.uniform(-1, 1, 3), 0.05 * rng.uniform(-1, 1, 3), 1e-3 * rng.uniform(-1, 1, 3)
+    out = d3.collide(p, f, g, rho, u, b, F)
+    feq = d3.feq(rho, u)
+    S = d3.source(rho, u, F, feq)
+    geq = d3.geq(b, u)  # [7][3]
+    e9, o9, e7, o7 = _basis3()
+
+    def relaxed(M, h, heq, tau, src=None):
+        v = M @ h - (M @ h - M @ heq) / tau
+        return v if src is None else v + (1 - 1 / (2 * tau)) * (M @ src)
+
+    assert np.allclose(e9 @ out[:19], relaxed(e9, f, feq, tau_f, S), rtol=0, atol=1e-15)
+    assert np.allclose(o9 @ out[:19], relaxed(o9, f, feq, tau_fm, S), rtol=0, atol=1e-15)
+    for i in range(3):
+        o = out[19 + 7 * i:26 + 7 * i]
+        assert np.allclose(e7 @ o, relaxed(e7, g[:, i], geq[:, i], tau_mp), rtol=0, atol=1e-16)
+        assert np.allclose(o7 @ o, relaxed(o7, g[:, i], geq[:, i], tau_m), rtol=0, atol=1e-16)
+
+
+def _trt3(p, lf=3 / 16, lm=1 / 4):
+    from oracle import derive
+    tfm, tmp = derive.trt_times(p.tau_f, p.tau_m, lf, lm)
+    return tfm, tmp
+
+
+@pytest.mark.parametrize("case", CASES_2D)
+def test_trt_z_invariant_run_reproduces_2d_trt_oracle(case):
+    """The even/odd split commutes with the e_z sums, so a z-invariant TRT run
+    is the 2D TRT run (the independent 2D oracle)."""
+    bc, cl, cu, ul, uu, fx, fy = case
+    p2 = Params(nx=7, ny=10, bc=bc, tau_f=0.7, tau_m=0.9, b0=0.05, fx=fx, fy=fy, c_lo=cl,
+                c_hi=cu, u_lo=ul, u_hi=uu)
+    tfm, tmp = _trt3(p2, 1 / 4, 1 / 12)
+    p2 = Params(**{**p2.__dict__, "collision": oracle.TRT, "tau_fm": tfm, "tau_mp": tmp})
+    s2 = random_state_2d(p2, seed=12)
+    p3 = d3.Params3.from_2d(p2, 3)
+    assert p3.collision == d3.TRT
+    s3 = d3.lift_from_2d(s2, 3)
+    a2 = oracle.run(p2, s2.copy(), 15)
+    d3.run(p3, s3, 15)
+    assert np.abs(d3.project_to_2d(s3) - a2).max() < 1e-14
+    o3, o2 = d3.observe(p3, s3), oracle.observe(p2, a2)
+    for k in ("rho", "ux", "uy", "bx", "by", "jz"):
+        assert np.abs(o3[k][0] - o2[k]).max() < 1e-14, k
+
+
+@pytest.mark.parametrize("bc,c", [(LINK, 0.4), (MOMENT, math.inf)])
+def test_trt_x_z_exchange(bc, c):
+    n = 6
+    kw = dict(nx=n, ny=8, nz=n, bc=bc, tau_f=0.75, tau_m=0.85, b0=0.04, c_lo=c, c_hi=c,
+              collision=d3.TRT, tau_fm=0.9, tau_mp=1.1)
+    p = d3.Params3(fx=3e-5, **kw)
+    q = d3.Params3(fz=3e-5, **kw)
+    s = random_state_3d(p, seed=6)
+    a = d3.run(p, s.copy(), 12)
+    b = swap_xz(d3.run(q, swap_xz(s), 12))
+    assert np.abs(a - b).max() < 1e-15
+
+
+def test_trt_equal_rates_is_bgk_3d():
+    kw = dict(nx=5, ny=7, nz=4, bc=MOMENT, tau_f=0.7, tau_m=0.9, b0=0.05, fx=2e-5, fz=1e-5,
+              c_lo=0.3, c_hi=math.inf, u_hi=0.03)
+    s = random_state_3d(d3.Params3(**kw), seed=8)
+    a = d3.run(d3.Params3(**kw), s.copy(), 10)
+    b = d3.run(d3.Params3(**kw, collision=d3.TRT, tau_fm=0.7, tau_mp=0.9), s.copy(), 10)
+    assert np.abs(a - b).max() < 1e-15
+    c = d3.run(d3.Params3(**kw, collision=d3.TRT, tau_fm=0.8, tau_mp=0.9), s.copy(), 10)
+    assert np.abs(c - a).max() > 1e-8
