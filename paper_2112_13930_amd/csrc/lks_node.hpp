@@ -184,18 +184,15 @@ __device__ __forceinline__ C collide_f(C f, C w, C ex, C ey, C rhop, C rho,
 }
 
 // Two-relaxation-time update of the pair (a, abar) of opposite f
-// populations, e_a = (ex, ey), in deviation form (see Trt).
+// populations in deviation form (see Trt); eu = e_a.u and eF = e_a.F.
 template <typename C>
-__device__ __forceinline__ void collide_f_pair(C &fa, C &fb, C w, C ex, C ey, C rhop, C rho,
-                                               C ux, C uy, C usq15, C Fx, C Fy, C uF,
-                                               const Trt<C> &t) {
-  const C eu = ex * ux + ey * uy;
+__device__ __forceinline__ void collide_f_pair(C &fa, C &fb, C w, C eu, C eF, C rhop, C rho,
+                                               C usq15, C uF, const Trt<C> &t) {
   const C even = C(4.5) * eu * eu - usq15;
   const C odd = C(3) * eu;
   const C pa = even + odd, pb = even - odd; // poly of a and of abar
   const C na = w * (rhop + rho * pa) - fa;
   const C nb = w * (rhop + rho * pb) - fb;
-  const C eF = ex * Fx + ey * Fy;
   const C Sa = C(3) * w * (eF - uF) * (C(1) + pa);
   const C Sb = C(3) * w * (-eF - uF) * (C(1) + pb);
   const C ra = fa + t.fa * na + t.fb * nb + t.fsa * Sa + t.fsb * Sb;
@@ -346,10 +343,10 @@ __device__ __forceinline__ void node_finish(const Geom &g, const Coef<C> &k,
     // stores stay in plane order, so every plane keeps its random word
     const Trt<C> &t = k.trt;
     f[0] = collide_f(f[0], w0, C(0), C(0), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka);
-    collide_f_pair(f[1], f[3], w1, C(1), C(0), rhop, rho, ux, uy, usq15, Fx, Fy, uF, t);
-    collide_f_pair(f[2], f[4], w1, C(0), C(1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, t);
-    collide_f_pair(f[5], f[7], w5, C(1), C(1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, t);
-    collide_f_pair(f[6], f[8], w5, C(-1), C(1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, t);
+    collide_f_pair(f[1], f[3], w1, ux, Fx, rhop, rho, usq15, uF, t);
+    collide_f_pair(f[2], f[4], w1, uy, Fy, rhop, rho, usq15, uF, t);
+    collide_f_pair(f[5], f[7], w5, ux + uy, Fx + Fy, rhop, rho, usq15, uF, t);
+    collide_f_pair(f[6], f[8], w5, uy - ux, Fy - Fx, rhop, rho, usq15, uF, t);
     gx[0] += t.gp * (W0 * bx - gx[0]);
     collide_g_pair(gx[1], gx[3], W1 * bx, W1 * bx, t);
     collide_g_pair(gx[2], gx[4], W1 * (bx - E3), W1 * (bx + E3), t);

@@ -66,11 +66,13 @@ template <typename S, typename C, int BC, int MODE, bool SR>
 __device__ __forceinline__ void node3_update(const Geom3 &g, const Coef<C> &k, C fez,
                                              const S *__restrict__ src, S *__restrict__ dst,
                                              int x, int y, int z, NodeObs3 &obs, uint32_t sseed) {
+  // BC: the wall scheme (BC_NONE for interior rows), optionally | COLL_TRT
+  constexpr int WB = wall_of(BC);
   // register type of the pulled values
-  using R = typename ComputeSel<(BC != BC_NONE && sizeof(C) == 8) || sizeof(S) == 8>::type;
+  using R = typename ComputeSel<(WB != BC_NONE && sizeof(C) == 8) || sizeof(S) == 8>::type;
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const long long P = g.plane;
-  const bool lo = (BC != BC_NONE) && (y == 0), hi = (BC != BC_NONE) && (y == ny - 1);
+  const bool lo = (WB != BC_NONE) && (y == 0), hi = (WB != BC_NONE) && (y == ny - 1);
   const int xs[3] = {x == 0 ? nx - 1 : x - 1, x, x == nx - 1 ? 0 : x + 1}; // x - e for e = 1, 0, -1
   const int zs[3] = {z == 0 ? nz - 1 : z - 1, z, z == nz - 1 ? 0 : z + 1};
   const long long own = ((long long)z * ny + y) * nx + x;
@@ -104,7 +106,7 @@ __device__ __forceinline__ void node3_update(const Geom3 &g, const Coef<C> &k, C
   }
 
   // ---- wall closures ----
-  if constexpr (BC == BC_LINK) {
+  if constexpr (WB == BC_LINK) {
     // Half-way bounce-back with Ladd's term (+-U/6 on the in-plane diagonals);
     // tangential field components by the theta-weighted Shercliff closure
     // (moving-wall term on B_x only), the normal one by anti-bounce-back,
@@ -130,7 +132,7 @@ __device__ __forceinline__ void node3_update(const Geom3 &g, const Coef<C> &k, C
       gz[3] = k.hi.r * own_(31 + 1);
       gy[3] = -own_(25 + 1);
     }
-  } else if constexpr (BC == BC_MOMENT) {
+  } else if constexpr (WB == BC_MOMENT) {
     // On-node closures from the paper's constraint set taken per tangential
     // direction (Pi_y = 0 fixes rho; Pi_x = rho U, Pi_xx = rho (cs2 + U^2),
     // Pi_z = 0, Pi_zz = rho cs2), written for the deviations f' = f - w.
@@ -212,7 +214,7 @@ __device__ __forceinline__ void node3_update(const Geom3 &g, const Coef<C> &k, C
   const C kk = k.k_m;
   C ux, uy, uz, jx, jy, jz, Fx, Fy, Fz;
   const C inv_rho = C(1) / rho;
-  if (BC == BC_MOMENT && (lo || hi)) {
+  if (WB == BC_MOMENT && (lo || hi)) {
     // wet wall node: velocity fixed by the closure, no force
     ux = mx * inv_rho;
     uy = my * inv_rho;
@@ -267,6 +269,63 @@ __device__ __forceinline__ void node3_update(const Geom3 &g, const Coef<C> &k, C
   const C om = k.omega_f, ka = k.kappa_f;
   const C usq15 = C(1.5) * (ux * ux + uy * uy + uz * uz);
   const C uF = ux * Fx + uy * Fy + uz * Fz;
+  // g^eq_{a i} = W [B_i + 3 e_a (u_a B_i - B_a u_i)] along the link's axis a;
+  // the component along the axis keeps W B_a.  Deviations: the y component
+  // is stored minus W B0.  (Formed after the f collisions, which keeps them
+  // out of the registers live there.)
+  struct GEq3 {
+    C x[6], y[6], z[6];
+  };
+  auto geq3 = [&]() -> GEq3 {
+    const C W = C(1) / C(6);
+    const C exy = C(3) * (ux * by - uy * bx); // u_x B_y - B_x u_y
+    const C exz = C(3) * (ux * bz - uz * bx);
+    const C eyz = C(3) * (uy * bz - uz * by);
+    return GEq3{{W * bx, W * (bx - exy), W * bx, W * (bx + exy), W * (bx - exz), W * (bx + exz)},
+                {W * (byp + exy), W * byp, W * (byp - exy), W * byp, W * (byp - eyz), W * (byp + eyz)},
+                {W * (bz + exz), W * (bz + eyz), W * (bz - exz), W * (bz - eyz), W * bz, W * bz}};
+  };
+  if constexpr (trt_of(BC)) {
+    // opposite pairs: D3Q19 (1,3) (2,4) (5,7) (6,8) (9,10) (11,12) (13,14)
+    // (15,16) (17,18); D3Q7 links (+x,-x) (+y,-y) (+z,-z)
+    const Trt<C> &t = k.trt;
+    {
+      const C fq = rewiden(f[0]);
+      const C feq = W3<C>::w(0) * (rhop - rho * usq15);
+      const C src_q = C(3) * W3<C>::w(0) * (-uF) * (C(1) - usq15);
+      put(0, fq + om * (feq - fq) + ka * src_q);
+    }
+    constexpr int first[9] = {1, 2, 5, 6, 9, 11, 13, 15, 17};
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const int q = first[i], r = D3Q19::opp[q];
+      const C ex_ = C(D3Q19::ex[q]), ey_ = C(D3Q19::ey[q]), ez_ = C(D3Q19::ez[q]);
+      C fa = rewiden(f[q]), fb = rewiden(f[r]);
+      collide_f_pair(fa, fb, W3<C>::w(q), ex_ * ux + ey_ * uy + ez_ * uz,
+                     ex_ * Fx + ey_ * Fy + ez_ * Fz, rhop, rho, usq15, uF, t);
+      put(q, fa);
+      put(r, fb);
+    }
+    const GEq3 ge = geq3();
+    constexpr int ga_[3] = {0, 1, 4}, gb_[3] = {2, 3, 5};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const int a = ga_[i], b = gb_[i];
+      C xa = rewiden(gx[a]), xb = rewiden(gx[b]);
+      C ya = rewiden(gy[a]), yb = rewiden(gy[b]);
+      C za = rewiden(gz[a]), zb = rewiden(gz[b]);
+      collide_g_pair(xa, xb, ge.x[a], ge.x[b], t);
+      collide_g_pair(ya, yb, ge.y[a], ge.y[b], t);
+      collide_g_pair(za, zb, ge.z[a], ge.z[b], t);
+      put(19 + a, xa);
+      put(19 + b, xb);
+      put(25 + a, ya);
+      put(25 + b, yb);
+      put(31 + a, za);
+      put(31 + b, zb);
+    }
+    return;
+  }
 #pragma unroll
   for (int q = 0; q < 19; ++q) {
     const C ex_ = C(D3Q19::ex[q]), ey_ = C(D3Q19::ey[q]), ez_ = C(D3Q19::ez[q]);
@@ -278,22 +337,14 @@ __device__ __forceinline__ void node3_update(const Geom3 &g, const Coef<C> &k, C
     const C fq = rewiden(f[q]);
     put(q, fq + om * (feq - fq) + ka * src_q);
   }
-  // g^eq_{a i} = W [B_i + 3 e_a (u_a B_i - B_a u_i)] along the link's axis a;
-  // the component along the axis keeps W B_a
-  const C wm = k.omega_m, W = C(1) / C(6);
-  const C exy = C(3) * (ux * by - uy * bx); // u_x B_y - B_x u_y
-  const C exz = C(3) * (ux * bz - uz * bx);
-  const C eyz = C(3) * (uy * bz - uz * by);
-  // deviations: the y component is stored minus W B0
-  const C gqx[6] = {W * bx, W * (bx - exy), W * bx, W * (bx + exy), W * (bx - exz), W * (bx + exz)};
-  const C gqy[6] = {W * (byp + exy), W * byp, W * (byp - exy), W * byp, W * (byp - eyz), W * (byp + eyz)};
-  const C gqz[6] = {W * (bz + exz), W * (bz + eyz), W * (bz - exz), W * (bz - eyz), W * bz, W * bz};
+  const C wm = k.omega_m;
+  const GEq3 ge = geq3();
 #pragma unroll
   for (int a = 0; a < 6; ++a) {
     const C vx = rewiden(gx[a]), vy = rewiden(gy[a]), vz = rewiden(gz[a]);
-    put(19 + a, vx + wm * (gqx[a] - vx));
-    put(25 + a, vy + wm * (gqy[a] - vy));
-    put(31 + a, vz + wm * (gqz[a] - vz));
+    put(19 + a, vx + wm * (ge.x[a] - vx));
+    put(25 + a, vy + wm * (ge.y[a] - vy));
+    put(31 + a, vz + wm * (ge.z[a] - vz));
   }
 }
 

@@ -34,7 +34,8 @@ constexpr int NRED3 = 6; // du2, u2, db2, b2, sum_u, nonfinite
 #define LKS_STEP3_WAVES_FP32_INTERIOR 5
 #endif
 template <typename S, int BC>
-constexpr int kWaves3 = (BC == BC_NONE && sizeof(S) == 4) ? LKS_STEP3_WAVES_FP32_INTERIOR : 4;
+constexpr int kWaves3 =
+    (wall_of(BC) == BC_NONE && sizeof(S) == 4) ? LKS_STEP3_WAVES_FP32_INTERIOR : 4;
 
 template <typename S, typename C, int BC, int MODE>
 __global__ __launch_bounds__(256, (kWaves3<S, BC>)) void k_step3(
@@ -48,11 +49,11 @@ __global__ __launch_bounds__(256, (kWaves3<S, BC>)) void k_step3(
     if (owner && blockIdx.x == 0 && threadIdx.x == 0) ctr[parity ^ 1] = step + 1u;
     if constexpr (SR) sseed = step_seed(step);
   }
-  const int nrows = BC == BC_NONE ? g.ny - 2 : 2;
+  const int nrows = wall_of(BC) == BC_NONE ? g.ny - 2 : 2;
   const int line = (int)blockIdx.x / tiles_x; // z * nrows + row
   const int tx = (int)blockIdx.x - line * tiles_x;
   const int z = line / nrows, r = line - z * nrows;
-  const int y = BC == BC_NONE ? 1 + r : (r == 0 ? 0 : g.ny - 1);
+  const int y = wall_of(BC) == BC_NONE ? 1 + r : (r == 0 ? 0 : g.ny - 1);
   const int tile = tile_base + (int)blockIdx.x;
   const int x = tx * 256 + (int)threadIdx.x;
   const bool act = x < g.nx;
@@ -209,10 +210,6 @@ int validate3(const lks_mhd3_params *p, Channel *c) {
     set_error("invalid parameters: fz must be finite");
     return LKS_EINVAL;
   }
-  if (p->base.collision != LKS_BGK) {
-    set_error("invalid parameters: the three-dimensional channel collides with BGK only");
-    return LKS_EINVAL;
-  }
   return LKS_OK;
 }
 
@@ -236,7 +233,8 @@ hipError_t launch3_t(lks_mhd3 *h, const void *src, void *dst, ObsOut3 oo) {
   const int interior = h->tiles_x * (h->geom.ny - 2) * h->geom.nz;
   const int walls = h->tiles_x * 2 * h->geom.nz;
   if (interior > 0) {
-    hipLaunchKernelGGL((k_step3<S, C, BC_NONE, MODE>), dim3(interior), dim3(256), 0, h->stream,
+    constexpr int kInterior = BC_NONE | (BC & COLL_TRT);
+    hipLaunchKernelGGL((k_step3<S, C, kInterior, MODE>), dim3(interior), dim3(256), 0, h->stream,
                        h->geom, coef3<C>(h), (C)h->fz, static_cast<const S *>(src),
                        static_cast<S *>(dst), h->tiles_x, 0, h->rec, h->partials, oo, h->ctr,
                        h->cur, 1);
@@ -250,14 +248,27 @@ hipError_t launch3_t(lks_mhd3 *h, const void *src, void *dst, ObsOut3 oo) {
   return hipGetLastError();
 }
 
+template <typename S, typename C, int MODE>
+hipError_t launch3_s(lks_mhd3 *h, const void *src, void *dst, ObsOut3 oo) {
+  // observables do not depend on the collision operator
+  const int sch = MODE == MODE_MOMENTS ? wall_of(scheme_of(h->ch.p)) : scheme_of(h->ch.p);
+  switch (sch) {
+  case BC_LINK: return launch3_t<S, C, BC_LINK, MODE>(h, src, dst, oo);
+  case BC_MOMENT: return launch3_t<S, C, BC_MOMENT, MODE>(h, src, dst, oo);
+  case BC_LINK | COLL_TRT:
+    if constexpr (MODE != MODE_MOMENTS) return launch3_t<S, C, BC_LINK | COLL_TRT, MODE>(h, src, dst, oo);
+    break;
+  default:
+    if constexpr (MODE != MODE_MOMENTS) return launch3_t<S, C, BC_MOMENT | COLL_TRT, MODE>(h, src, dst, oo);
+    break;
+  }
+  return hipErrorInvalidValue;
+}
+
 template <int MODE>
 hipError_t launch3(lks_mhd3 *h, const void *src, void *dst, ObsOut3 oo) {
-  const bool link = h->ch.p.bc == LKS_BC_LINK;
-  if (h->ch.p.precision == LKS_FP64)
-    return link ? launch3_t<double, double, BC_LINK, MODE>(h, src, dst, oo)
-                : launch3_t<double, double, BC_MOMENT, MODE>(h, src, dst, oo);
-  return link ? launch3_t<float, Fp32Compute, BC_LINK, MODE>(h, src, dst, oo)
-              : launch3_t<float, Fp32Compute, BC_MOMENT, MODE>(h, src, dst, oo);
+  if (h->ch.p.precision == LKS_FP64) return launch3_s<double, double, MODE>(h, src, dst, oo);
+  return launch3_s<float, Fp32Compute, MODE>(h, src, dst, oo);
 }
 
 int one_step3(lks_mhd3 *h, int mode) {

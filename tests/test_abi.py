@@ -168,7 +168,9 @@ def test_3d_sizing_and_validation(L):
     assert lib.lks_mhd3_state_bytes(ctypes.byref(p)) == 0
     p.base = L.make_params(64, 32, precision="fp32", collision="trt")
     p.nz = 4
-    assert lib.lks_mhd3_state_bytes(ctypes.byref(p)) == 0 and "BGK" in L.last_error()
+    assert lib.lks_mhd3_state_bytes(ctypes.byref(p)) > 0
+    p.base = L.make_params(64, 32, precision="fp32", collision="trt", lambda_f=-1.0)
+    assert lib.lks_mhd3_state_bytes(ctypes.byref(p)) == 0 and "lambda" in L.last_error()
     h = ctypes.c_void_p()
     p.base = L.make_params(8, 8, precision="fp64")
     p.nz = 2

@@ -26,12 +26,21 @@ def P():
     return P
 
 
-def channel3(p3, precision, stream=None):
+def channel3(p3, precision, stream=None, trt_lambdas=None):
     from paper_2112_13930_amd.channel3 import Channel3
     kw = dict(bc="link" if p3.bc == LINK else "moment", precision=precision, tau_f=p3.tau_f,
               tau_m=p3.tau_m, b0=p3.b0, fx=p3.fx, fy=p3.fy, c_lower=p3.c_lo, c_upper=p3.c_hi,
               u_lower=p3.u_lo, u_upper=p3.u_hi)
+    if trt_lambdas is not None:
+        kw.update(collision="trt", lambda_f=trt_lambdas[0], lambda_m=trt_lambdas[1])
     return Channel3(p3.nx, p3.ny, p3.nz, fz=p3.fz, stream=stream, **kw)
+
+
+def trt3(p3, lf, lm):
+    """The TRT variant of a 3D oracle parameter set (free times from the
+    magic parameters, derived as the library derives them)."""
+    tfm, tmp = derive.trt_times(p3.tau_f, p3.tau_m, lf, lm)
+    return d3.Params3(**{**p3.__dict__, "collision": d3.TRT, "tau_fm": tfm, "tau_mp": tmp})
 
 
 def errors3(g, o):
@@ -154,3 +163,65 @@ def test_bench_size_from_rest_matches_2d_oracle(P, bc, ha, c):
                                                g[k].shape))
         assert np.linalg.norm(g[k] - ref) / scale < TOL["fp32"], k
     assert np.abs(g["uz"]).max() < 1e-7 and np.abs(g["bz"]).max() < 1e-7
+
+
+@pytest.mark.parametrize("case", [CASES[1], CASES[2], CASES[4], CASES[5]])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_trt_random_3d_state_parity(P, case, precision):
+    """Two-relaxation-time collision on an x-, y- and z-dependent random
+    state, 10 steps."""
+    from paper_2112_13930_amd.workloads import random_populations3
+    bc, cl, cu, ul, uu, fx, fz = case
+    lam = (3 / 16, 1 / 4) if bc == LINK else (1 / 12, 1.0)
+    base = d3.Params3(nx=37, ny=11, nz=5, bc=bc, tau_f=0.7, tau_m=0.9, b0=0.05, fx=fx, fz=fz,
+                      c_lo=cl, c_hi=cu, u_lo=ul, u_hi=uu)
+    p3 = trt3(base, *lam)
+    s0 = random_populations3(p3.nx, p3.ny, p3.nz, seed=13, b0=p3.b0)
+    ch = channel3(p3, precision, trt_lambdas=lam)
+    ch.load_state(torch.from_numpy(s0))
+    ch.step(10)
+    g = {k: v.cpu().numpy() for k, v in ch.moments().items()}
+    st = ch.save_state().cpu().numpy()
+    ch.close()
+    s = d3.run(p3, s0.copy(), 10)
+    errs = errors3(g, d3.observe(p3, s))
+    keys = ("ux", "bx", "uy", "uz", "by", "bz", "rho") + (("jx", "jy", "jz") if precision == "fp64" else ())
+    assert_below(errs, TOL[precision], keys)
+    if precision == "fp64":
+        assert np.abs(st - s).max() < 1e-14
+        assert np.abs(d3.run(base, s0.copy(), 10) - s).max() > 1e-9  # TRT differs from BGK
+
+
+@pytest.mark.parametrize("bc", [LINK, MOMENT])
+def test_trt_nz1_reproduces_2d_trt_oracle(P, bc):
+    from paper_2112_13930_amd.workloads import random_populations
+    from tests.helpers import trt
+    p2 = trt(Params(nx=40, ny=12, bc=bc, tau_f=0.7, tau_m=0.9, b0=0.05, fx=1e-5, c_lo=0.3,
+                    c_hi=math.inf, u_hi=0.03), 1 / 4, 1 / 12)
+    s2 = random_populations(p2.nx, p2.ny, seed=6, b0=p2.b0)
+    ch = channel3(d3.Params3.from_2d(p2, 1), "fp64", trt_lambdas=(1 / 4, 1 / 12))
+    ch.load_state(torch.from_numpy(d3.lift_from_2d(s2, 1)))
+    ch.step(20)
+    g = {k: v.cpu().numpy()[0] for k, v in ch.moments().items()}
+    ch.close()
+    oracle.run(p2, s2, 20)
+    o = oracle.observe(p2, s2)
+    for k in ("ux", "uy", "bx", "by", "jz"):
+        assert rel_l2(g[k], o[k]) < 1e-12, k
+
+
+def test_trt_3d_graph_replay_bitwise(P):
+    from paper_2112_13930_amd.workloads import random_populations3
+    p3 = d3.Params3(nx=300, ny=9, nz=3, bc=MOMENT, tau_f=0.7, tau_m=0.9, b0=0.05, fx=1e-5,
+                    c_lo=0.2, c_hi=math.inf, u_hi=0.03)
+    s0 = torch.from_numpy(random_populations3(p3.nx, p3.ny, p3.nz, seed=9, b0=p3.b0))
+    a = channel3(p3, "fp32", stream=torch.cuda.Stream(), trt_lambdas=(3 / 16, 1 / 4))
+    a.load_state(s0)
+    a.step(9)
+    b = channel3(p3, "fp32", stream=torch.cuda.Stream(), trt_lambdas=(3 / 16, 1 / 4))
+    b.set_graph(4)
+    b.load_state(s0)
+    b.step(9)
+    assert torch.equal(a.save_state().cpu(), b.save_state().cpu())
+    a.close()
+    b.close()
