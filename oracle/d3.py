@@ -50,6 +50,8 @@ class _Params3(ctypes.Structure):
         ("u_lo", ctypes.c_double), ("u_hi", ctypes.c_double), ("a", ctypes.c_double),
         ("collision", ctypes.c_int32), ("pad_", ctypes.c_int32),
         ("tau_fm", ctypes.c_double), ("tau_mp", ctypes.c_double),
+        ("side_walls", ctypes.c_int32), ("pad2_", ctypes.c_int32),
+        ("cs_lo", ctypes.c_double), ("cs_hi", ctypes.c_double),
     ]
 
 
@@ -75,9 +77,11 @@ def lib():
         L.orc3_observe.argtypes = [pp, dp, dp]
         L.orc3_gather.argtypes = [pp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
         L.orc3_collide.argtypes = [pp, dp, dp, ctypes.c_double, dp, dp, dp, dp]
+        L.orc3_side_closure.argtypes = [pp, ctypes.c_int, dp, dp, dp]
         for name in ("orc3_feq", "orc3_geq", "orc3_source", "orc3_local_solve",
                      "orc3_link_closure", "orc3_moment_closure", "orc3_init", "orc3_step",
-                     "orc3_run", "orc3_observe", "orc3_gather", "orc3_collide"):
+                     "orc3_run", "orc3_observe", "orc3_gather", "orc3_collide",
+                     "orc3_side_closure"):
             getattr(L, name).restype = None
         _lib = L
     return _lib
@@ -108,6 +112,9 @@ class Params3:
     collision: int = BGK
     tau_fm: float = float("nan")
     tau_mp: float = float("nan")
+    side_walls: bool = False   # duct: stationary Shercliff walls bound z
+    cs_lo: float = 0.0         # their conductance ratios (z = 0 side, z = nz-1 side)
+    cs_hi: float = 0.0
 
     def half_width(self) -> float:
         if self.a is not None:
@@ -117,9 +124,12 @@ class Params3:
     def c_struct(self) -> _Params3:
         if self.collision == TRT:
             assert self.tau_fm > 0.5 and self.tau_mp > 0.5, "TRT needs tau_fm and tau_mp > 1/2"
+        if self.side_walls:
+            assert self.bc == LINK and self.nz >= 2, "side walls need link-based closures"
         return _Params3(self.nx, self.ny, self.nz, self.bc, self.tau_f, self.tau_m, self.b0,
                         self.fx, self.fy, self.fz, self.c_lo, self.c_hi, self.u_lo, self.u_hi,
-                        self.half_width(), self.collision, 0, self.tau_fm, self.tau_mp)
+                        self.half_width(), self.collision, 0, self.tau_fm, self.tau_mp,
+                        int(self.side_walls), 0, self.cs_lo, self.cs_hi)
 
     @classmethod
     def from_2d(cls, p, nz: int) -> "Params3":
@@ -213,6 +223,17 @@ def collide(p: Params3, f, g, rho, u, b, F) -> np.ndarray:
                        _dp(np.asarray(u, dtype=np.float64)), _dp(np.asarray(b, dtype=np.float64)),
                        _dp(np.asarray(F, dtype=np.float64)), _dp(out))
     return out
+
+
+def side_closure(p: Params3, wall: int, own, f, g):
+    """Apply the side-wall closure (wall 0: z = 0 side, 1: z = nz-1 side) to
+    one node's pulled populations f[19], g[7][3]; own are its 40 previous
+    post-collision values."""
+    f = np.array(f, dtype=np.float64)
+    g = np.array(g, dtype=np.float64).reshape(21)
+    lib().orc3_side_closure(ctypes.byref(p.c_struct()), wall,
+                            _dp(np.ascontiguousarray(own, dtype=np.float64)), _dp(f), _dp(g))
+    return f, g.reshape(7, 3)
 
 
 # Velocity sets, typed here for the tests only (the C file has its own).

@@ -3,7 +3,9 @@
  * MHD channel step (Yahia & Premnath, arXiv 2112.13930): a D3Q19 flow
  * distribution with the Lorentz force and a three-component vector magnetic
  * distribution on a D3Q7 lattice, closed at the Hartmann walls y = 0 and
- * y = ny-1 by the paper's two Shercliff schemes; x and z are periodic.
+ * y = ny-1 by the paper's two Shercliff schemes; x is periodic, z periodic
+ * (a channel) or bounded by stationary link-closed Shercliff side walls (a
+ * rectangular duct).
  *
  * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
  * call this file; only the test suite and the benchmark's CPU-baseline leg
@@ -80,6 +82,8 @@ typedef struct {
   int32_t collision, pad_;
   double tau_fm;     /* TRT: odd part of f */
   double tau_mp;     /* TRT: even part of g */
+  int32_t side_walls, pad2_; /* 1: stationary Shercliff walls at z = -1/2 and nz - 1/2 */
+  double cs_lo, cs_hi;       /* their wall conductance ratios (0 .. INFINITY) */
 } orc3_params;
 
 static int opp3(int q) {
@@ -217,6 +221,38 @@ void orc3_link_closure(const orc3_params *p, int wall, const double *own, double
 }
 
 /*
+ * Side walls of a duct (link-based only), stationary, half-way between the
+ * layers z = 0 and z = -1 (lower) or nz-1 and nz (upper), applied to every
+ * link whose source lies behind the wall:
+ *   f: half-way bounce-back;
+ *   g, tangential components x and y: the theta-weighted Shercliff closure of
+ *      Sec. VI on the induced field b = B - (0, B0, 0), i.e.
+ *        g_in,x = r g~_out,x,   g_in,y - W B0 = r (g~_out,y - W B0),
+ *      r = (theta-1)/(theta+1), theta = c_s a / (tau_m - 1/2) (the same
+ *      length a as at the Hartmann walls); c_s = INFINITY gives r = 1;
+ *   g, normal component z: anti-bounce-back to B_z = 0, g_in,z = -g~_out,z.
+ * A link crossing a Hartmann wall and a side wall at an edge is closed by
+ * both; for f the results coincide (bounce-back, no moving-wall term since
+ * such links have e_x = 0).
+ */
+void orc3_side_closure(const orc3_params *p, int wall, const double *own, double *f, double *g) {
+  const int ez_in = (wall == O3_LOWER) ? +1 : -1;
+  const double cw = (wall == O3_LOWER) ? p->cs_lo : p->cs_hi;
+  const double r = isinf(cw) ? 1.0 : (cw * p->a / (p->tau_m - 0.5) - 1.0) /
+                                         (cw * p->a / (p->tau_m - 0.5) + 1.0);
+  for (int q = 0; q < NQF; ++q)
+    if (E3Z[q] == ez_in) f[q] = own[opp3(q)];
+  for (int q = 0; q < NQG; ++q) {
+    if (G3Z[q] != ez_in) continue;
+    const int o = oppg(q);
+    const double wb0 = WG3[q] * p->b0;
+    g[q * 3 + 0] = r * own[19 + 0 * 7 + o];
+    g[q * 3 + 1] = r * (own[19 + 1 * 7 + o] - wb0) + wb0;
+    g[q * 3 + 2] = -own[19 + 2 * 7 + o];
+  }
+}
+
+/*
  * On-node moment-based closures (Sec. VII, App. A, App. B.2) extended to the
  * five unknown D3Q19 populations of a wall node (e_y into the fluid).  The
  * paper's constraint set is taken per tangential direction: with rho from
@@ -310,31 +346,42 @@ typedef struct {
 
 static int wrap(int v, int n) { return ((v % n) + n) % n; }
 
+/* source layer of a pull along e_z: periodic, or -1 behind a side wall */
+static int src_z(const orc3_params *p, int z, int ez) {
+  const int sz = z - ez;
+  if (p->side_walls) return (sz >= 0 && sz < p->nz) ? sz : -1;
+  return wrap(sz, p->nz);
+}
+
 static void gather3(const orc3_params *p, const double *in, int x, int y, int z, node3_t *n) {
-  /* pull streaming; x and z periodic */
+  /* pull streaming; x periodic, z periodic or bounded by side walls */
   for (int q = 0; q < NQF; ++q) {
-    const int sy = y - E3Y[q];
-    n->f[q] = (sy >= 0 && sy < p->ny)
-                  ? in[idx3(p, q, wrap(z - E3Z[q], p->nz), sy, wrap(x - E3X[q], p->nx))]
+    const int sy = y - E3Y[q], sz = src_z(p, z, E3Z[q]);
+    n->f[q] = (sy >= 0 && sy < p->ny && sz >= 0)
+                  ? in[idx3(p, q, sz, sy, wrap(x - E3X[q], p->nx))]
                   : NAN;
   }
   for (int q = 0; q < NQG; ++q) {
-    const int sy = y - G3Y[q];
+    const int sy = y - G3Y[q], sz = src_z(p, z, G3Z[q]);
     for (int i = 0; i < 3; ++i)
-      n->g[q * 3 + i] =
-          (sy >= 0 && sy < p->ny)
-              ? in[idx3(p, 19 + i * 7 + q, wrap(z - G3Z[q], p->nz), sy, wrap(x - G3X[q], p->nx))]
-              : NAN;
+      n->g[q * 3 + i] = (sy >= 0 && sy < p->ny && sz >= 0)
+                            ? in[idx3(p, 19 + i * 7 + q, sz, sy, wrap(x - G3X[q], p->nx))]
+                            : NAN;
   }
   const int wall = (y == 0) || (y == p->ny - 1);
-  if (wall) {
+  const int side = p->side_walls && ((z == 0) || (z == p->nz - 1));
+  if (wall || side) {
     double own[NPL3];
     for (int k = 0; k < NPL3; ++k) own[k] = in[idx3(p, k, z, y, x)];
-    for (int w = 0; w < 2; ++w) {
+    for (int w = 0; w < 2 && wall; ++w) {
       const int at = (w == O3_LOWER) ? (y == 0) : (y == p->ny - 1);
       if (!at) continue;
       if (p->bc == O3_LINK) orc3_link_closure(p, w, own, n->f, n->g);
       else orc3_moment_closure(p, w, n->f, n->g);
+    }
+    for (int w = 0; w < 2 && side; ++w) {
+      const int at = (w == O3_LOWER) ? (z == 0) : (z == p->nz - 1);
+      if (at) orc3_side_closure(p, w, own, n->f, n->g);
     }
   }
   double rho = 0.0, m[3] = {0, 0, 0}, b[3] = {0, 0, 0}, lam[9] = {0};
