@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define LKS_MHD_ABI_VERSION 2
+#define LKS_MHD_ABI_VERSION 3
 
 typedef struct lks_mhd lks_mhd_t;             /* one channel, library-owned */
 typedef struct lks_mhd_batch lks_mhd_batch_t; /* many channels, library-owned */
@@ -367,15 +367,27 @@ int lks_mhd_batch_save_state(lks_mhd_batch_t *b, int32_t slot,
  * base: the two-dimensional parameter set (nx, ny, bc, tau_f, tau_m, Ha or
  * B0, c and U per wall, fx or u_max, fy, rho0; derived exactly as for one
  * channel); precision LKS_FP64 or LKS_FP32 (binary32 storage, FP64
- * arithmetic, stochastic rounding).  nz >= 1 periodic layers; fz the body
- * force along z.  nx * ny * nz must be below 2^31.
+ * arithmetic, stochastic rounding).  nz >= 1 layers; fz the body force
+ * along z.  nx * ny * nz must be below 2^31.
+ *
+ * side_walls 0: z periodic (a channel).  1: a rectangular duct, z bounded
+ * by stationary thin conducting side walls half-way outside the layers
+ * z = 0 and z = nz-1 (nz >= 2, link-based closures only), with conductance
+ * ratios c_side_lower (z = 0 side) and c_side_upper in [0, INFINITY].  Their
+ * closure per link: bounce-back for f; for the field the theta-weighted
+ * Shercliff closure on the induced tangential components b_x and
+ * b_y = B_y - B0 (theta = c a / (tau_m - 1/2), a the Hartmann half-width as
+ * at the Hartmann walls) and anti-bounce-back to B_z = 0 for the normal one.
+ * The paper treats walls normal to the field only; the side walls apply its
+ * thin-wall condition to the walls parallel to it.
  */
 typedef struct lks_mhd3 lks_mhd3_t;
 typedef struct {
   lks_mhd_params base;
   int32_t nz;
-  int32_t reserved; /* 0 */
+  int32_t side_walls;
   double fz;
+  double c_side_lower, c_side_upper;
 } lks_mhd3_params;
 
 /* Device bytes for create (0 and a message for invalid parameters); bytes

@@ -43,8 +43,9 @@ class LksParams(ctypes.Structure):
 
 
 class LksParams3(ctypes.Structure):
-    _fields_ = [("base", LksParams), ("nz", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("fz", ctypes.c_double)]
+    _fields_ = [("base", LksParams), ("nz", ctypes.c_int32), ("side_walls", ctypes.c_int32),
+                ("fz", ctypes.c_double), ("c_side_lower", ctypes.c_double),
+                ("c_side_upper", ctypes.c_double)]
 
 
 class LksDerived(ctypes.Structure):

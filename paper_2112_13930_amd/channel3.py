@@ -1,7 +1,9 @@
-"""One three-dimensional channel on the GPU (thin owner of device memory).
+"""One three-dimensional channel or duct on the GPU (thin owner of device
+memory).
 
-x and z periodic, Shercliff walls at y = 0 and y = ny - 1; every step runs in
-liblks_mhd.so (lks_mhd3_*).
+x periodic, Shercliff walls at y = 0 and y = ny - 1, z periodic or (a duct)
+bounded by Shercliff side walls; every step runs in liblks_mhd.so
+(lks_mhd3_*).
 """
 from __future__ import annotations
 
@@ -19,15 +21,20 @@ def _ptr(t):
 
 
 class Channel3:
-    """Keyword arguments as for Channel (make_params), plus nz and fz."""
+    """Keyword arguments as for Channel (make_params), plus nz and fz; with
+    side_walls=True a duct whose side walls have the conductance ratios
+    c_side (both) or (c_side_lower, c_side_upper)."""
 
-    def __init__(self, nx: int, ny: int, nz: int, *, fz: float = 0.0,
-                 device: str | torch.device = "cuda", stream: torch.cuda.Stream | None = None,
-                 **kw):
+    def __init__(self, nx: int, ny: int, nz: int, *, fz: float = 0.0, side_walls: bool = False,
+                 c_side=0.0, device: str | torch.device = "cuda",
+                 stream: torch.cuda.Stream | None = None, **kw):
         self.params = LksParams3()
         self.params.base = make_params(nx, ny, **kw)
         self.params.nz = int(nz)
         self.params.fz = float(fz)
+        self.params.side_walls = int(bool(side_walls))
+        lo, hi = c_side if isinstance(c_side, (tuple, list)) else (c_side, c_side)
+        self.params.c_side_lower, self.params.c_side_upper = float(lo), float(hi)
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
         self.device = torch.device(device)
         nbytes = lib().lks_mhd3_state_bytes(ctypes.byref(self.params))

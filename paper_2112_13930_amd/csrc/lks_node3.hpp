@@ -1,6 +1,7 @@
-// Per-node update of the three-dimensional channel: pull streaming of the
-// D3Q19 flow and the three-component D3Q7 field populations, Shercliff
-// closures at the Hartmann walls y = 0 and y = ny - 1 (x and z periodic),
+// Per-node update of the three-dimensional channel or duct: pull streaming
+// of the D3Q19 flow and the three-component D3Q7 field populations,
+// Shercliff closures at the Hartmann walls y = 0 and y = ny - 1 (x periodic;
+// z periodic, or bounded by side walls in a duct),
 // moments, the coupled u/J solve, collision and stochastically rounded store.
 //
 // Lattices (the three-dimensional extension of Secs. IV and V): D3Q19 with
@@ -51,6 +52,14 @@ template <typename C> struct W3 {
 struct Geom3 {
   int nx, ny, nz;
   long long plane; // elements per plane
+  int side;        // 1: side walls bound z (a duct), 0: z periodic
+};
+
+// Side-wall closure coefficients of a duct: g_in,i = r g~_out,i for the
+// tangential induced components (x, and y as stored minus W B0), for the
+// z = 0 side (lo) and the z = nz-1 side (hi); r = (theta-1)/(theta+1).
+template <typename C> struct Side3 {
+  C r_lo, r_hi;
 };
 
 struct NodeObs3 {
@@ -64,8 +73,9 @@ constexpr int BC_NONE = 2;
 
 template <typename S, typename C, int BC, int MODE, bool SR>
 __device__ __forceinline__ void node3_update(const Geom3 &g, const Coef<C> &k, C fez,
-                                             const S *__restrict__ src, S *__restrict__ dst,
-                                             int x, int y, int z, NodeObs3 &obs, uint32_t sseed) {
+                                             const Side3<C> &sw, const S *__restrict__ src,
+                                             S *__restrict__ dst, int x, int y, int z,
+                                             NodeObs3 &obs, uint32_t sseed) {
   // BC: the wall scheme (BC_NONE for interior rows), optionally | COLL_TRT
   constexpr int WB = wall_of(BC);
   // register type of the pulled values
@@ -131,6 +141,31 @@ __device__ __forceinline__ void node3_update(const Geom3 &g, const Coef<C> &k, C
       gx[3] = k.hi.r * own_(19 + 1) + k.hi.t;
       gz[3] = k.hi.r * own_(31 + 1);
       gy[3] = -own_(25 + 1);
+    }
+    // Side walls of a duct (stationary): bounce-back of f, theta closure of
+    // the induced tangential components b_x and b_y, anti-bounce-back of
+    // B_z.  The values pulled across the wall (periodic addresses) are
+    // replaced here; at an edge the links crossing both walls get the same
+    // bounce-back value from either closure.
+    if (g.side && z == 0) {
+      f[9] = own_(10);
+      f[11] = own_(12);
+      f[14] = own_(13);
+      f[15] = own_(16);
+      f[18] = own_(17);
+      gx[4] = sw.r_lo * own_(19 + 5);
+      gy[4] = sw.r_lo * own_(25 + 5);
+      gz[4] = -own_(31 + 5);
+    }
+    if (g.side && z == nz - 1) {
+      f[10] = own_(9);
+      f[12] = own_(11);
+      f[13] = own_(14);
+      f[16] = own_(15);
+      f[17] = own_(18);
+      gx[5] = sw.r_hi * own_(19 + 4);
+      gy[5] = sw.r_hi * own_(25 + 4);
+      gz[5] = -own_(31 + 4);
     }
   } else if constexpr (WB == BC_MOMENT) {
     // On-node closures from the paper's constraint set taken per tangential

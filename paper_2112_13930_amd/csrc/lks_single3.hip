@@ -37,11 +37,15 @@ template <typename S, int BC>
 constexpr int kWaves3 =
     (wall_of(BC) == BC_NONE && sizeof(S) == 4) ? LKS_STEP3_WAVES_FP32_INTERIOR : 4;
 
+// Rows of a launch.  Interior: (y, z) with 1 <= y <= ny-2 and every z, or
+// 1 <= z <= nz-2 in a duct, numbered z-major.  Walls: the two Hartmann rows
+// y = 0, ny-1 of every z, then in a duct the side rows z = 0, nz-1 of every
+// interior y.
 template <typename S, typename C, int BC, int MODE>
 __global__ __launch_bounds__(256, (kWaves3<S, BC>)) void k_step3(
-    Geom3 g, Coef<C> k, C fez, const S *__restrict__ src, S *__restrict__ dst, int tiles_x,
-    int tile_base, double *__restrict__ rec, double *__restrict__ partials, ObsOut3 oo,
-    uint32_t *__restrict__ ctr, int parity, int owner) {
+    Geom3 g, Coef<C> k, C fez, Side3<C> sw, const S *__restrict__ src, S *__restrict__ dst,
+    int tiles_x, int tile_base, double *__restrict__ rec, double *__restrict__ partials,
+    ObsOut3 oo, uint32_t *__restrict__ ctr, int parity, int owner) {
   constexpr bool SR = kUseSR<S, C> && MODE != MODE_MOMENTS;
   uint32_t sseed = 0;
   if constexpr (MODE != MODE_MOMENTS) {
@@ -49,16 +53,26 @@ __global__ __launch_bounds__(256, (kWaves3<S, BC>)) void k_step3(
     if (owner && blockIdx.x == 0 && threadIdx.x == 0) ctr[parity ^ 1] = step + 1u;
     if constexpr (SR) sseed = step_seed(step);
   }
-  const int nrows = wall_of(BC) == BC_NONE ? g.ny - 2 : 2;
-  const int line = (int)blockIdx.x / tiles_x; // z * nrows + row
+  const int line = (int)blockIdx.x / tiles_x;
   const int tx = (int)blockIdx.x - line * tiles_x;
-  const int z = line / nrows, r = line - z * nrows;
-  const int y = wall_of(BC) == BC_NONE ? 1 + r : (r == 0 ? 0 : g.ny - 1);
+  int y, z;
+  if constexpr (wall_of(BC) == BC_NONE) {
+    const int nrows = g.ny - 2;
+    z = line / nrows + g.side;
+    y = 1 + (line - (z - g.side) * nrows);
+  } else if (line < 2 * g.nz) {
+    z = line >> 1;
+    y = (line & 1) ? g.ny - 1 : 0;
+  } else {
+    const int s = line - 2 * g.nz;
+    z = (s & 1) ? g.nz - 1 : 0;
+    y = 1 + (s >> 1);
+  }
   const int tile = tile_base + (int)blockIdx.x;
   const int x = tx * 256 + (int)threadIdx.x;
   const bool act = x < g.nx;
   NodeObs3 o{};
-  if (act) node3_update<S, C, BC, MODE, SR>(g, k, fez, src, dst, x, y, z, o, sseed);
+  if (act) node3_update<S, C, BC, MODE, SR>(g, k, fez, sw, src, dst, x, y, z, o, sseed);
   const long long n = (long long)g.nx * g.ny * g.nz;
   const long long i = ((long long)z * g.ny + y) * g.nx + x;
   if constexpr (MODE == MODE_RECORD) {
@@ -171,6 +185,8 @@ struct lks_mhd3 {
   int tiles_x = 0, ntiles = 0;
   Coef<double> kd{};
   Coef<float> kf{};
+  Side3<double> sd{};
+  Side3<float> sf{};
   int graph_steps = 0;
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
 };
@@ -180,6 +196,9 @@ namespace {
 template <typename C> const Coef<C> &coef3(const lks_mhd3 *h);
 template <> const Coef<double> &coef3<double>(const lks_mhd3 *h) { return h->kd; }
 template <> const Coef<float> &coef3<float>(const lks_mhd3 *h) { return h->kf; }
+template <typename C> Side3<C> side3(const lks_mhd3 *h);
+template <> Side3<double> side3<double>(const lks_mhd3 *h) { return h->sd; }
+template <> Side3<float> side3<float>(const lks_mhd3 *h) { return h->sf; }
 
 struct Layout3 {
   long long plane;
@@ -210,7 +229,33 @@ int validate3(const lks_mhd3_params *p, Channel *c) {
     set_error("invalid parameters: fz must be finite");
     return LKS_EINVAL;
   }
+  if (p->side_walls != 0 && p->side_walls != 1) {
+    set_error("invalid parameters: side_walls must be 0 or 1");
+    return LKS_EINVAL;
+  }
+  if (p->side_walls) {
+    if (p->base.bc != LKS_BC_LINK) {
+      set_error("invalid parameters: side walls need link-based closures");
+      return LKS_EINVAL;
+    }
+    if (p->nz < 2) {
+      set_error("invalid parameters: a duct needs nz >= 2");
+      return LKS_EINVAL;
+    }
+    if (std::isnan(p->c_side_lower) || p->c_side_lower < 0.0 || std::isnan(p->c_side_upper) ||
+        p->c_side_upper < 0.0) {
+      set_error("invalid parameters: side-wall conductance ratios must be in [0, inf]");
+      return LKS_EINVAL;
+    }
+  }
   return LKS_OK;
+}
+
+// (theta-1)/(theta+1) of a side wall, theta = c a / (tau_m - 1/2).
+double side_r(double c, const Channel &ch) {
+  if (std::isinf(c)) return 1.0;
+  const double th = c * ch.d.a / (ch.p.tau_m - 0.5);
+  return (th - 1.0) / (th + 1.0);
 }
 
 Layout3 layout3(const lks_mhd3_params *p) {
@@ -230,19 +275,21 @@ Layout3 layout3(const lks_mhd3_params *p) {
 
 template <typename S, typename C, int BC, int MODE>
 hipError_t launch3_t(lks_mhd3 *h, const void *src, void *dst, ObsOut3 oo) {
-  const int interior = h->tiles_x * (h->geom.ny - 2) * h->geom.nz;
-  const int walls = h->tiles_x * 2 * h->geom.nz;
+  const Geom3 &g = h->geom;
+  const int interior = h->tiles_x * (g.ny - 2) * (g.nz - 2 * g.side);
+  const int walls = h->tiles_x * (2 * g.nz + 2 * g.side * (g.ny - 2));
   if (interior > 0) {
     constexpr int kInterior = BC_NONE | (BC & COLL_TRT);
     hipLaunchKernelGGL((k_step3<S, C, kInterior, MODE>), dim3(interior), dim3(256), 0, h->stream,
-                       h->geom, coef3<C>(h), (C)h->fz, static_cast<const S *>(src),
+                       h->geom, coef3<C>(h), (C)h->fz, side3<C>(h), static_cast<const S *>(src),
                        static_cast<S *>(dst), h->tiles_x, 0, h->rec, h->partials, oo, h->ctr,
                        h->cur, 1);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL((k_step3<S, C, BC, MODE>), dim3(walls), dim3(256), 0, h->stream, h->geom,
-                     coef3<C>(h), (C)h->fz, static_cast<const S *>(src), static_cast<S *>(dst),
+                     coef3<C>(h), (C)h->fz, side3<C>(h), static_cast<const S *>(src),
+                     static_cast<S *>(dst),
                      h->tiles_x, interior, h->rec, h->partials, oo, h->ctr, h->cur,
                      interior > 0 ? 0 : 1);
   return hipGetLastError();
@@ -390,7 +437,9 @@ int lks_mhd3_create(const lks_mhd3_params *p, void *dev_buf, size_t bytes, void 
   h->fz = p->fz;
   if (hipGetDevice(&h->device) != hipSuccess) h->device = 0;
   h->stream = static_cast<hipStream_t>(hip_stream);
-  h->geom = Geom3{c.p.nx, c.p.ny, p->nz, L.plane};
+  h->geom = Geom3{c.p.nx, c.p.ny, p->nz, L.plane, p->side_walls};
+  h->sd = Side3<double>{side_r(p->c_side_lower, c), side_r(p->c_side_upper, c)};
+  h->sf = Side3<float>{(float)h->sd.r_lo, (float)h->sd.r_hi};
   char *base = static_cast<char *>(dev_buf);
   h->buf[0] = base;
   h->buf[1] = base + L.state_bytes;

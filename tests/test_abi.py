@@ -39,7 +39,7 @@ def test_every_declared_symbol_is_exported(L):
 
 
 def test_abi_version(L):
-    assert L.lib().lks_mhd_abi_version() == 2
+    assert L.lib().lks_mhd_abi_version() == 3
 
 
 def _v(L, **kw):
@@ -171,6 +171,20 @@ def test_3d_sizing_and_validation(L):
     assert lib.lks_mhd3_state_bytes(ctypes.byref(p)) > 0
     p.base = L.make_params(64, 32, precision="fp32", collision="trt", lambda_f=-1.0)
     assert lib.lks_mhd3_state_bytes(ctypes.byref(p)) == 0 and "lambda" in L.last_error()
+    # ducts: link walls only, nz >= 2, conductances in [0, inf]
+    p.base = L.make_params(64, 32, precision="fp32")
+    p.nz, p.side_walls, p.c_side_lower, p.c_side_upper = 8, 1, 0.5, math.inf
+    assert lib.lks_mhd3_state_bytes(ctypes.byref(p)) > 0
+    for bad in (dict(nz=1), dict(side_walls=2), dict(c_side_lower=-1.0),
+                dict(c_side_upper=float("nan"))):
+        q = L.LksParams3()
+        ctypes.pointer(q)[0] = p
+        for k, v in bad.items():
+            setattr(q, k, v)
+        assert lib.lks_mhd3_state_bytes(ctypes.byref(q)) == 0, bad
+    p.base = L.make_params(64, 32, precision="fp32", bc="moment")
+    assert lib.lks_mhd3_state_bytes(ctypes.byref(p)) == 0 and "link" in L.last_error()
+    p.side_walls = 0
     h = ctypes.c_void_p()
     p.base = L.make_params(8, 8, precision="fp64")
     p.nz = 2

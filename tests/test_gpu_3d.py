@@ -33,6 +33,8 @@ def channel3(p3, precision, stream=None, trt_lambdas=None):
               u_lower=p3.u_lo, u_upper=p3.u_hi)
     if trt_lambdas is not None:
         kw.update(collision="trt", lambda_f=trt_lambdas[0], lambda_m=trt_lambdas[1])
+    if p3.side_walls:
+        kw.update(side_walls=True, c_side=(p3.cs_lo, p3.cs_hi))
     return Channel3(p3.nx, p3.ny, p3.nz, fz=p3.fz, stream=stream, **kw)
 
 
@@ -225,3 +227,105 @@ def test_trt_3d_graph_replay_bitwise(P):
     assert torch.equal(a.save_state().cpu(), b.save_state().cpu())
     a.close()
     b.close()
+
+
+# ---- rectangular duct: Shercliff side walls at z = 0 and nz - 1 ----
+
+DUCTS = [
+    # c_lo, c_hi (Hartmann), cs_lo, cs_hi (side), u_hi, fx, fz
+    (0.0, 0.0, 0.0, 0.0, 0.0, 1e-4, 0.0),
+    (0.3, 2.0, 0.5, math.inf, 0.04, 0.0, 1e-5),
+    (math.inf, 0.1, math.inf, 0.0, 0.0, 2e-5, -1e-5),
+    (1e-3, math.inf, 1.0, 1.0, 0.02, 1e-5, 0.0),
+]
+
+
+@pytest.mark.parametrize("case", DUCTS)
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_duct_random_state_parity(P, case, precision):
+    from paper_2112_13930_amd.workloads import random_populations3
+    cl, cu, sl, sh, uu, fx, fz = case
+    p3 = d3.Params3(nx=37, ny=11, nz=6, bc=LINK, tau_f=0.7, tau_m=0.9, b0=0.05, fx=fx, fz=fz,
+                    c_lo=cl, c_hi=cu, u_hi=uu, side_walls=True, cs_lo=sl, cs_hi=sh)
+    s0 = random_populations3(p3.nx, p3.ny, p3.nz, seed=23, b0=p3.b0)
+    ch = channel3(p3, precision)
+    ch.load_state(torch.from_numpy(s0))
+    ch.step(10)
+    g = {k: v.cpu().numpy() for k, v in ch.moments().items()}
+    st = ch.save_state().cpu().numpy()
+    ch.close()
+    s = d3.run(p3, s0.copy(), 10)
+    errs = errors3(g, d3.observe(p3, s))
+    keys = ("ux", "bx", "uy", "uz", "by", "bz", "rho") + (("jx", "jy", "jz") if precision == "fp64" else ())
+    assert_below(errs, TOL[precision], keys)
+    if precision == "fp64":
+        assert np.abs(st - s).max() < 1e-14
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_duct_from_rest_matches_oracle(P, precision):
+    """Body-force driven duct (Hunt-type walls: conducting Hartmann walls,
+    insulating side walls), 2000 steps from rest, nz = 2 and 16."""
+    for nz in (2, 16):
+        p3 = d3.Params3(nx=4, ny=16, nz=nz, bc=LINK, tau_f=0.8, tau_m=0.8, b0=0.03, fx=2e-5,
+                        c_lo=1.0, c_hi=1.0, side_walls=True, cs_lo=0.0, cs_hi=0.0)
+        ch = channel3(p3, precision, stream=torch.cuda.Stream())
+        ch.set_graph(50)
+        ch.step(2000)
+        g = {k: v.cpu().numpy() for k, v in ch.moments().items()}
+        ch.close()
+        s = d3.run(p3, d3.init_state(p3), 2000, nthreads=8)
+        errs = errors3(g, d3.observe(p3, s))
+        # u_x and B_x at the bar; rho over 2000 steps carries the oracle's
+        # round-off on raw populations (~1e-14 per node), held by the short
+        # random-state runs instead
+        assert_below(errs, TOL[precision], ("ux", "bx"))
+
+
+def test_trt_duct_parity(P):
+    from paper_2112_13930_amd.workloads import random_populations3
+    base = d3.Params3(nx=37, ny=11, nz=6, bc=LINK, tau_f=0.7, tau_m=0.9, b0=0.05, fx=1e-5,
+                      c_lo=0.3, c_hi=math.inf, u_hi=0.03, side_walls=True, cs_lo=0.5,
+                      cs_hi=math.inf)
+    p3 = trt3(base, 3 / 16, 1 / 4)
+    s0 = random_populations3(p3.nx, p3.ny, p3.nz, seed=29, b0=p3.b0)
+    ch = channel3(p3, "fp64", trt_lambdas=(3 / 16, 1 / 4))
+    ch.load_state(torch.from_numpy(s0))
+    ch.step(10)
+    st = ch.save_state().cpu().numpy()
+    ch.close()
+    assert np.abs(st - d3.run(p3, s0.copy(), 10)).max() < 1e-14
+
+
+def test_duct_graph_replay_bitwise(P):
+    from paper_2112_13930_amd.workloads import random_populations3
+    p3 = d3.Params3(nx=300, ny=9, nz=5, bc=LINK, tau_f=0.7, tau_m=0.9, b0=0.05, fx=1e-5,
+                    c_lo=0.2, c_hi=math.inf, u_hi=0.03, side_walls=True, cs_lo=0.1, cs_hi=2.0)
+    s0 = torch.from_numpy(random_populations3(p3.nx, p3.ny, p3.nz, seed=31, b0=p3.b0))
+    a = channel3(p3, "fp32", stream=torch.cuda.Stream())
+    a.load_state(s0)
+    a.step(9)
+    b = channel3(p3, "fp32", stream=torch.cuda.Stream())
+    b.set_graph(4)
+    b.load_state(s0)
+    b.step(9)
+    assert torch.equal(a.save_state().cpu(), b.save_state().cpu())
+    a.close()
+    b.close()
+
+
+def test_duct_x_invariant_from_rest_matches_oracle_cross_section(P):
+    """A 300 x 48 x 40 FP32 duct (two ragged x tiles per line) from rest is
+    x-invariant: every x equals the oracle's cross-section (nx = 1)."""
+    kw = dict(ny=48, nz=40, bc=LINK, tau_f=0.7, tau_m=0.9, b0=0.004, u_hi=0.05, c_lo=1.0,
+              c_hi=1.0, side_walls=True, cs_lo=0.2, cs_hi=0.2)
+    ch = channel3(d3.Params3(nx=300, **kw), "fp32", stream=torch.cuda.Stream())
+    ch.set_graph(40)
+    ch.step(400)
+    g = {k: ch.moments()[k].cpu().numpy() for k in ("ux", "bx")}
+    ch.close()
+    p1 = d3.Params3(nx=1, **kw)
+    o = d3.observe(p1, d3.run(p1, d3.init_state(p1), 400, nthreads=8))
+    for k in ("ux", "bx"):
+        ref = np.broadcast_to(o[k], g[k].shape)
+        assert np.linalg.norm(g[k] - ref) / np.linalg.norm(ref) < TOL["fp32"], k
