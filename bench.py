@@ -26,7 +26,8 @@ Printed as one JSON line with, besides the contract fields:
                 the continuous-batching solve service (FP32 and binary16)
                 against sequential plain FP32 solves at six arrival rates;
                 the headline step on a developed (random) state; the 3D
-                channel (D3Q19 + D3Q7 field) on 256^3; the two-relaxation-time
+                channel (D3Q19 + D3Q7 field) on 256^3 and the duct with
+                Shercliff side walls; the two-relaxation-time
                 collision's rates beside BGK's.
   --only LEG    run one of the extra legs alone and print it (development).
 
@@ -194,6 +195,48 @@ def three_d(torch, n=256, steps=200, warmup=10):
             ref = np.broadcast_to(np.asarray(gold[k])[None, :, None], g[k].shape)
             errs[k] = float(np.linalg.norm(g[k] - ref) / np.linalg.norm(ref))
         out["fp32_error_vs_2d_oracle_1000_steps"] = errs
+    return out
+
+
+def duct_3d(torch, n=256, steps=200, warmup=10):
+    """The rectangular duct: the 3D channel's Hartmann walls and physics,
+    with stationary Shercliff side walls (c = 1) bounding z, on n^3 FP32:
+    the rate from rest, and the FP32 run's error against the 3D oracle's
+    rows stored by tests/golden/make_golden.py after 1000 steps."""
+    import numpy as np
+
+    from paper_2112_13930_amd.channel3 import Channel3
+    kw = dict(bc="link", tau_f=0.7, tau_m=0.9, ha=50.0, c_lower=1.0, c_upper=1.0, u_upper=0.05,
+              side_walls=True, c_side=1.0)
+    ch = Channel3(n, n, n, precision="fp32", stream=torch.cuda.Stream(), **kw)
+    ch.step(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(ch.stream)
+    ch.step(steps)
+    e1.record(ch.stream)
+    torch.cuda.synchronize()
+    r = n ** 3 / (e0.elapsed_time(e1) / 1e3 / steps)
+    ch.close()
+    out = {"grid": f"{n}x{n}x{n}", "side_walls": "c = 1 both", "steps": steps,
+           "mlups_from_rest": round(r / 1e6, 1),
+           "frac_hbm_from_rest": round(296 * r / 1e9 / PEAK_HBM_GBS, 3)}
+    gold_path = os.path.join(ROOT, "tests", "golden", "duct_256_link_1000.json")
+    if n == 256 and os.path.exists(gold_path):
+        gold = json.load(open(gold_path))
+        ch = Channel3(n, n, n, precision="fp32", stream=torch.cuda.Stream(), **kw)
+        ch.step(1000)
+        m = ch.moments()
+        g = {k: m[k].cpu().numpy() for k in ("ux", "bx")}
+        del m
+        ch.close()
+        errs = {}
+        for k in ("ux", "bx"):
+            got = np.stack([g[k][z] for z in gold["layers"]])        # [layer][y][x]
+            ref = np.asarray(gold[k])[:, :, None]                    # every x equal
+            errs[k] = float(np.linalg.norm(got - ref) / (np.linalg.norm(ref) * math.sqrt(n)))
+        out["fp32_error_vs_3d_oracle_1000_steps"] = errs
     return out
 
 
@@ -510,7 +553,7 @@ def write_summary(dirs, command):
 # ---------------------------------------------------------------------------
 
 LEGS = {"developed": developed_state_rate, "sweep": sweep, "precisions": other_precisions,
-        "channel_3d": three_d, "trt": trt_rates,
+        "channel_3d": three_d, "duct_3d": duct_3d, "trt": trt_rates,
         "batched": lambda torch: batched(torch, "fp32"),
         "serving": serving}
 
@@ -607,6 +650,8 @@ def main():
         extras["precisions"] = other_precisions(torch)
         log("3D channel ...")
         extras["channel_3d"] = three_d(torch)
+        log("duct ...")
+        extras["duct_3d"] = duct_3d(torch)
         log("TRT collision ...")
         extras["trt_collision"] = trt_rates(torch)
         log("batched ...")

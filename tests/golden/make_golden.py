@@ -23,7 +23,14 @@ couette_256_link_1000.json
     oracle's u_x and B_x rows (the runs are x-invariant; the 3D benchmark
     channel is also z-invariant, so each of its nodes must match the row).
 
-Run:  python tests/golden/make_golden.py [config1] [precision] [couette256]
+duct_256_link_1000.json
+    The benchmark's shear-driven flow in a rectangular duct: the same Hartmann
+    walls and physics on 256 rows, 256 layers between stationary side walls
+    with c = 1, 1000 steps from rest, run by the 3D oracle with nx = 1 (the
+    run is x-invariant).  Stores the u_x and B_x rows of the layers
+    z = 0, 1, 4, 16, 64 and 128.
+
+Run:  python tests/golden/make_golden.py [config1] [precision] [couette256] [duct256]
 """
 import json
 import os
@@ -109,8 +116,32 @@ def couette256():
     }
 
 
+DUCT_LAYERS = (0, 1, 4, 16, 64, 128)
+
+
+def duct256(nthreads=8):
+    from oracle import d3
+    p2 = derive.couette_params(1, 256, oracle.LINK, 0.7, 0.9, 50.0, 1.0, 1.0, 0.05)
+    p = d3.Params3(nx=1, ny=256, nz=256, bc=oracle.LINK, tau_f=0.7, tau_m=0.9, b0=p2.b0,
+                   c_lo=1.0, c_hi=1.0, u_hi=0.05, a=p2.a, side_walls=True, cs_lo=1.0, cs_hi=1.0)
+    s = d3.run(p, d3.init_state(p), 1000, nthreads=nthreads)
+    o = d3.observe(p, s)
+    return {
+        "description": "duct 256 rows x 256 layers, link-based Hartmann walls (tau_f=0.7, "
+                       "tau_m=0.9, Ha=50, c=1, upper wall U=0.05) and stationary side walls "
+                       "(c=1), 1000 steps from rest; 3D oracle FP64 u_x and B_x rows of the "
+                       "listed layers",
+        "params": {"ny": 256, "nz": 256, "bc": "link", "tau_f": 0.7, "tau_m": 0.9, "ha": 50.0,
+                   "c": 1.0, "c_side": 1.0, "u_upper": 0.05, "steps": 1000, "a": p2.a,
+                   "b0": p2.b0},
+        "layers": list(DUCT_LAYERS),
+        "ux": [o["ux"][z, :, 0].tolist() for z in DUCT_LAYERS],
+        "bx": [o["bx"][z, :, 0].tolist() for z in DUCT_LAYERS],
+    }
+
+
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["config1", "precision", "couette256"]
+    which = sys.argv[1:] or ["config1", "precision", "couette256", "duct256"]
     if "config1" in which:
         out = os.path.join(HERE, "config1_hartmann_link.json")
         with open(out, "w") as fh:
@@ -124,6 +155,12 @@ if __name__ == "__main__":
     if "couette256" in which:
         out = os.path.join(HERE, "couette_256_link_1000.json")
         data = couette256()
+        with open(out, "w") as fh:
+            json.dump(data, fh, indent=1)
+        print("wrote", out)
+    if "duct256" in which:
+        out = os.path.join(HERE, "duct_256_link_1000.json")
+        data = duct256()
         with open(out, "w") as fh:
             json.dump(data, fh, indent=1)
         print("wrote", out)

@@ -84,3 +84,20 @@ def test_couette256_fixture_matches_oracle(orc):
     o = orc.observe(p, s)
     assert np.array_equal(o["ux"][:, 0], np.array(g["ux"]))
     assert np.array_equal(o["bx"][:, 0], np.array(g["bx"]))
+
+
+def test_duct_far_from_its_side_walls_is_the_channel():
+    """The stored 256 x 256 duct (3D oracle) at its mid layer against the
+    stored 256-row channel (2D oracle), both 1000 steps from rest.  Side-wall
+    effects reach the mid layer in that time only acoustically (sound at
+    c_s = 0.58 nodes per step crosses 128 layers; diffusion and Alfven waves
+    do not), which leaves a few 1e-5; the layers near the wall differ at
+    order one."""
+    here = os.path.join(os.path.dirname(__file__), "golden")
+    duct = json.load(open(os.path.join(here, "duct_256_link_1000.json")))
+    chan = json.load(open(os.path.join(here, "couette_256_link_1000.json")))
+    for k in ("ux", "bx"):
+        ref = np.asarray(chan[k])
+        rows = dict(zip(duct["layers"], (np.asarray(r) for r in duct[k])))
+        assert np.linalg.norm(rows[128] - ref) / np.linalg.norm(ref) < 1e-4
+        assert np.linalg.norm(rows[0] - ref) / np.linalg.norm(ref) > 0.1
