@@ -55,6 +55,8 @@ class _Params(ctypes.Structure):
         ("u_lo", ctypes.c_double), ("u_hi", ctypes.c_double),
         ("a", ctypes.c_double),
         ("tau_fm", ctypes.c_double), ("tau_mp", ctypes.c_double),
+        ("x_walls", ctypes.c_int32), ("pad_", ctypes.c_int32),
+        ("cx_lo", ctypes.c_double), ("cx_hi", ctypes.c_double),
     ]
 
 
@@ -80,9 +82,11 @@ def lib():
         L.orc_observe.argtypes = [pp, dp, dp, dp, dp, dp, dp, dp]
         L.orc_gather.argtypes = [pp, dp, ctypes.c_int, ctypes.c_int, dp]
         L.orc_collide.argtypes = [pp, dp, dp, dp] + [ctypes.c_double] * 7 + [dp]
+        L.orc_xwall_closure.argtypes = [pp, ctypes.c_int, dp, dp, dp, dp]
         for fn in ("orc_feq", "orc_geq", "orc_source", "orc_local_solve",
                    "orc_link_closure", "orc_moment_closure", "orc_init",
-                   "orc_step", "orc_run", "orc_observe", "orc_gather", "orc_collide"):
+                   "orc_step", "orc_run", "orc_observe", "orc_gather", "orc_collide",
+                   "orc_xwall_closure"):
             getattr(L, fn).restype = None
         _lib = L
     return _lib
@@ -123,6 +127,9 @@ class Params:
     collision: int = BGK
     tau_fm: float = float("nan")
     tau_mp: float = float("nan")
+    x_walls: bool = False  # enclosure: stationary Shercliff walls bound x
+    cx_lo: float = 0.0     # their conductance ratios (x = 0 side, x = nx-1 side)
+    cx_hi: float = 0.0
     extra: dict = field(default_factory=dict)
 
     def half_width(self) -> float:
@@ -133,9 +140,12 @@ class Params:
     def c_struct(self) -> _Params:
         if self.collision == TRT:
             assert self.tau_fm > 0.5 and self.tau_mp > 0.5, "TRT needs tau_fm and tau_mp > 1/2"
+        if self.x_walls:
+            assert self.bc == LINK and self.nx >= 2, "enclosure walls need link-based closures"
         return _Params(self.nx, self.ny, self.bc, self.collision, self.tau_f, self.tau_m,
                        self.b0, self.fx, self.fy, self.c_lo, self.c_hi,
-                       self.u_lo, self.u_hi, self.half_width(), self.tau_fm, self.tau_mp)
+                       self.u_lo, self.u_hi, self.half_width(), self.tau_fm, self.tau_mp,
+                       int(self.x_walls), 0, self.cx_lo, self.cx_hi)
 
 
 def init_state(p: Params) -> np.ndarray:
@@ -228,3 +238,15 @@ def collide(p: Params, f, gx, gy, rho, ux, uy, bx, by, Fx, Fy) -> np.ndarray:
     lib().orc_collide(ctypes.byref(cp), _dp(f), _dp(gx), _dp(gy), rho, ux, uy, bx, by, Fx,
                       Fy, _dp(out))
     return out
+
+
+def xwall_closure(p: Params, wall: int, own, f, gx, gy):
+    """Apply the enclosure-wall closure (wall 0: x = 0 side, 1: x = nx-1
+    side) to one node's pulled populations; own: its 19 previous
+    post-collision values."""
+    f, gx, gy = (np.array(v, dtype=np.float64) for v in (f, gx, gy))
+    cp = p.c_struct()
+    lib().orc_xwall_closure(ctypes.byref(cp), wall,
+                            _dp(np.ascontiguousarray(own, dtype=np.float64)), _dp(f), _dp(gx),
+                            _dp(gy))
+    return f, gx, gy

@@ -18,8 +18,9 @@
  *   planes 0..8   f_alpha        (D2Q9, Sec. V)
  *   planes 9..13  g_{alpha x}    (D2Q5 vector distribution, x component)
  *   planes 14..18 g_{alpha y}    (D2Q5, y component)
- * x is periodic; the walls bound y: row 0 is the lower wall side (y = -a),
- * row ny-1 the upper wall side (y = +a).
+ * x is periodic (a channel) or bounded by stationary link-closed Shercliff
+ * walls at x = -1/2 and nx - 1/2 (an enclosure); the Hartmann walls bound
+ * y: row 0 is the lower wall side (y = -a), row ny-1 the upper (y = +a).
  */
 #include <math.h>
 #include <stdint.h>
@@ -73,6 +74,8 @@ typedef struct {
   double a;            /* half-width H = a entering theta and 1/(c_w a) */
   double tau_fm;       /* TRT: relaxation time of the odd part of f */
   double tau_mp;       /* TRT: relaxation time of the even part of g */
+  int32_t x_walls, pad_; /* 1: an enclosure, stationary walls at x = -1/2 and nx - 1/2 */
+  double cx_lo, cx_hi;   /* their wall conductance ratios (0 .. INFINITY) */
 } orc_params;
 
 /* ---------------------------------------------------------------------- */
@@ -220,6 +223,41 @@ void orc_link_closure(const orc_params *p, int wall, const double *own,
 }
 
 /*
+ * Walls of an enclosure at x = -1/2 (lower, wall = ORC_LOWER) and
+ * x = nx - 1/2 (upper), parallel to the imposed field: stationary,
+ * link-based, applied to every link whose source lies behind the wall:
+ *   f:   half-way bounce-back;
+ *   g_y: the tangential component; the theta-weighted Shercliff closure of
+ *        Sec. VI on the induced field b_y = B_y - B0,
+ *          g_in,y - W B0 = r (g~_out,y - W B0),  r = (theta-1)/(theta+1),
+ *        theta = c_w a / (tau_m - 1/2) with the Hartmann half-width a;
+ *        c_w = INFINITY gives r = 1;
+ *   g_x: the normal component; anti-bounce-back to B_x = 0,
+ *          g_in,x = -g~_out,x.
+ * At a corner the links that also cross a Hartmann wall are closed by that
+ * wall afterwards (its moving-wall term included), which keeps the moving
+ * wall's mass balance.
+ */
+void orc_xwall_closure(const orc_params *p, int wall, const double *own, double *f,
+                       double *gx, double *gy) {
+  const int ex_in = (wall == ORC_LOWER) ? +1 : -1;
+  const double cw = (wall == ORC_LOWER) ? p->cx_lo : p->cx_hi;
+  double r = 1.0;
+  if (!isinf(cw)) {
+    const double theta = cw * p->a / (p->tau_m - 0.5);
+    r = (theta - 1.0) / (theta + 1.0);
+  }
+  for (int q = 0; q < NQ9; ++q)
+    if (EX9[q] == ex_in) f[q] = own[OPP9[q]];
+  for (int q = 0; q < NQ5; ++q) {
+    if (EX5[q] != ex_in) continue;
+    const double wb0 = W5[q] * p->b0;
+    gy[q] = r * (own[14 + OPP5[q]] - wb0) + wb0;
+    gx[q] = -own[9 + OPP5[q]];
+  }
+}
+
+/*
  * On-node ("wet") moment-based closures (Sec. VII, App. A, App. B.2).
  * f, gx, gy hold the post-streaming populations at the wall node; the
  * unknowns are overwritten.
@@ -291,21 +329,34 @@ typedef struct {
 static void gather_node(const orc_params *p, const double *in, int x, int y,
                         node_t *n) {
   /* S1: pull streaming, f_alpha(x) = f~_alpha(x - e_alpha) (Eqs.
-   * LBMforflowfield, LKSformagneticfield); x periodic. */
+   * LBMforflowfield, LKSformagneticfield); x periodic, or bounded by walls
+   * in an enclosure. */
   for (int q = 0; q < NQ9; ++q) {
     const int sy = y - EY9[q];
-    const int sx = ((x - EX9[q]) % p->nx + p->nx) % p->nx;
-    n->f[q] = (sy >= 0 && sy < p->ny) ? in[idx(p, q, sy, sx)] : NAN;
+    const int rx = x - EX9[q];
+    const int inx = !p->x_walls || (rx >= 0 && rx < p->nx);
+    const int sx = (rx % p->nx + p->nx) % p->nx;
+    n->f[q] = (sy >= 0 && sy < p->ny && inx) ? in[idx(p, q, sy, sx)] : NAN;
   }
   for (int q = 0; q < NQ5; ++q) {
     const int sy = y - EY5[q];
-    const int sx = ((x - EX5[q]) % p->nx + p->nx) % p->nx;
-    const int ok = (sy >= 0 && sy < p->ny);
+    const int rx = x - EX5[q];
+    const int inx = !p->x_walls || (rx >= 0 && rx < p->nx);
+    const int sx = (rx % p->nx + p->nx) % p->nx;
+    const int ok = (sy >= 0 && sy < p->ny && inx);
     n->gx[q] = ok ? in[idx(p, 9 + q, sy, sx)] : NAN;
     n->gy[q] = ok ? in[idx(p, 14 + q, sy, sx)] : NAN;
   }
-  /* S2: wall closures. */
+  /* S2: wall closures; enclosure walls first, the Hartmann walls then take
+   * the corner links that cross them. */
+  const int xwall = p->x_walls && ((x == 0) || (x == p->nx - 1));
   const int nwall = (y == 0) + (y == p->ny - 1);
+  if (xwall) {
+    double own[NPLANES];
+    for (int k = 0; k < NPLANES; ++k) own[k] = in[idx(p, k, y, x)];
+    if (x == 0) orc_xwall_closure(p, ORC_LOWER, own, n->f, n->gx, n->gy);
+    if (x == p->nx - 1) orc_xwall_closure(p, ORC_UPPER, own, n->f, n->gx, n->gy);
+  }
   if (nwall) {
     double own[NPLANES];
     for (int k = 0; k < NPLANES; ++k) own[k] = in[idx(p, k, y, x)];
