@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define LKS_MHD_ABI_VERSION 3
+#define LKS_MHD_ABI_VERSION 4
 
 typedef struct lks_mhd lks_mhd_t;             /* one channel, library-owned */
 typedef struct lks_mhd_batch lks_mhd_batch_t; /* many channels, library-owned */
@@ -125,6 +125,17 @@ enum lks_status {
  *   collision   lks_collision [LKS_BGK].
  *   lambda_f,   TRT magic parameters, finite and > 0 [3/16, 1/4]; ignored
  *   lambda_m    under BGK.
+ *   x_walls     0: x periodic (a channel) [0].  1: an enclosure, x bounded by
+ *               stationary thin conducting walls half-way outside the
+ *               columns x = 0 and x = nx-1 (nx >= 2, link-based closures
+ *               only; single channels, not batches), conductance ratios
+ *               c_x_lower (x = 0 side) and c_x_upper in [0, INFINITY].  These
+ *               walls are parallel to the imposed field, which the paper's
+ *               closures do not cover: f bounces back; the induced tangential
+ *               component b_y = B_y - B0 takes the theta closure with the
+ *               same a as the Hartmann walls; the normal B_x anti-bounces to
+ *               zero.  Links crossing a Hartmann wall at a corner take that
+ *               wall's closure (with its moving-wall term).
  */
 typedef struct {
   int32_t nx, ny;
@@ -139,8 +150,9 @@ typedef struct {
   double u_max;
   double rho0;
   int32_t collision;
-  int32_t reserved; /* 0 */
+  int32_t x_walls;
   double lambda_f, lambda_m;
+  double c_x_lower, c_x_upper;
 } lks_mhd_params;
 
 /* Lattice quantities derived from a parameter set (host FP64). */

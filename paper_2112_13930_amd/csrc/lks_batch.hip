@@ -655,6 +655,10 @@ int lks_mhd_batch_admit(lks_mhd_batch_t *b, const lks_mhd_params *p, int32_t *sl
   Channel c;
   int rc = derive_channel(&q, &c);
   if (rc != LKS_OK) return rc;
+  if (q.x_walls) {
+    set_error("invalid parameters: batches hold x-periodic channels only (x_walls = 0)");
+    return LKS_EINVAL;
+  }
   const int64_t n = (int64_t)q.nx * q.ny;
   if (b->nodes + n > b->max_nodes) {
     set_error("batch node capacity %lld exceeded", (long long)b->max_nodes);

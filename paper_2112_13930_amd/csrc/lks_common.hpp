@@ -63,12 +63,21 @@ Coef<C> make_coef(const Channel &c) {
   const double fa = 0.5 * (fp + fm), fb = 0.5 * (fp - fm);
   k.trt = Trt<C>{C(fa), C(fb), C(1.0 - 0.5 * fa), C(-0.5 * fb),
                  C(0.5 * (gp + gm)), C(0.5 * (gp - gm)), C(gp)};
+  // enclosure walls: r = (theta-1)/(theta+1), theta = c a / (tau_m - 1/2)
+  auto xr = [&](double cw) {
+    if (std::isinf(cw)) return 1.0;
+    const double th = cw * c.d.a / (c.p.tau_m - 0.5);
+    return (th - 1.0) / (th + 1.0);
+  };
+  k.xr_lo = C(c.p.x_walls ? xr(c.p.c_x_lower) : 1.0);
+  k.xr_hi = C(c.p.x_walls ? xr(c.p.c_x_upper) : 1.0);
   return k;
 }
 
 // The kernels' scheme parameter of a channel: wall scheme | collision.
 inline int scheme_of(const lks_mhd_params &p) {
-  return (p.bc == LKS_BC_LINK ? BC_LINK : BC_MOMENT) | (p.collision == LKS_TRT ? COLL_TRT : 0);
+  return (p.bc == LKS_BC_LINK ? BC_LINK : BC_MOMENT) | (p.collision == LKS_TRT ? COLL_TRT : 0) |
+         (p.x_walls ? WALLS_X : 0);
 }
 
 inline bool valid_precision(int precision) {

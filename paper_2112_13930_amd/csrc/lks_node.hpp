@@ -54,8 +54,11 @@ enum { BC_LINK = 0, BC_MOMENT = 1 };
 // The kernels' scheme parameter is the wall scheme, optionally combined with
 // COLL_TRT for the two-relaxation-time collision (BGK otherwise).
 constexpr int COLL_TRT = 4;
+// ... and with WALLS_X for an enclosure (link-closed walls bounding x)
+constexpr int WALLS_X = 8;
 constexpr int wall_of(int scheme) { return scheme & 3; }
 constexpr bool trt_of(int scheme) { return (scheme & COLL_TRT) != 0; }
+constexpr bool xwalls_of(int scheme) { return (scheme & WALLS_X) != 0; }
 enum { MODE_STEP = 0, MODE_RECORD = 1, MODE_RESIDUAL = 2, MODE_MOMENTS = 3 };
 
 // Closure coefficients of one wall (computed on the host in FP64).
@@ -95,6 +98,7 @@ struct Coef {
   C fex, fey; // external body force
   Wall<C> lo, hi;
   Trt<C> trt; // used by schemes with COLL_TRT
+  C xr_lo, xr_hi; // enclosure walls (WALLS_X): (theta-1)/(theta+1) at x = 0, nx-1
 };
 
 // Geometry of one channel's planes (element units).
@@ -230,6 +234,27 @@ __device__ __forceinline__ void node_finish(const Geom &g, const Coef<C> &k,
   const long long r0 = (long long)y * g.pitch;
   const C *__restrict__ Dy = ref + (long long)y * 19; // reference of this row
   // ---- wall closures for the populations entering from a wall ----
+  if constexpr (xwalls_of(BC)) {
+    // Enclosure walls at x = -1/2 and nx - 1/2 (parallel to the imposed
+    // field, stationary): bounce-back of f, theta closure of the induced
+    // tangential b_y (stored as g_y - W B0), anti-bounce-back of B_x.  The
+    // values pulled across the wall (periodic addresses) are replaced; the
+    // Hartmann closure below then takes the corner links that cross it.
+    if (x == 0) {
+      f[1] = dec<S>(ld<S, C>(src + 3 * P + r0 + x), Dy, 3);
+      f[5] = dec<S>(ld<S, C>(src + 7 * P + r0 + x), Dy, 7);
+      f[8] = dec<S>(ld<S, C>(src + 6 * P + r0 + x), Dy, 6);
+      gx[1] = -dec<S>(ld<S, C>(src + 12 * P + r0 + x), Dy, 12);
+      gy[1] = k.xr_lo * dec<S>(ld<S, C>(src + 17 * P + r0 + x), Dy, 17);
+    }
+    if (x == g.nx - 1) {
+      f[3] = dec<S>(ld<S, C>(src + 1 * P + r0 + x), Dy, 1);
+      f[6] = dec<S>(ld<S, C>(src + 8 * P + r0 + x), Dy, 8);
+      f[7] = dec<S>(ld<S, C>(src + 5 * P + r0 + x), Dy, 5);
+      gx[3] = -dec<S>(ld<S, C>(src + 10 * P + r0 + x), Dy, 10);
+      gy[3] = k.xr_hi * dec<S>(ld<S, C>(src + 15 * P + r0 + x), Dy, 15);
+    }
+  }
   if (wall_of(BC) == BC_LINK) {
     // Half-way bounce-back of f with Ladd's moving-wall term; theta-weighted
     // bounce-back/anti-bounce-back of g_x; anti-bounce-back to B_y = B0 for

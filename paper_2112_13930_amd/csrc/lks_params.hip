@@ -63,6 +63,14 @@ int derive_channel(const lks_mhd_params *p, Channel *out) {
   if (!finite(p->fy)) return bad("fy must be finite");
   if (p->collision != LKS_BGK && p->collision != LKS_TRT)
     return bad("collision must be LKS_BGK or LKS_TRT");
+  if (p->x_walls != 0 && p->x_walls != 1) return bad("x_walls must be 0 or 1");
+  if (p->x_walls) {
+    if (p->bc != LKS_BC_LINK) return bad("enclosure walls need link-based closures");
+    if (p->nx < 2) return bad("an enclosure needs nx >= 2");
+    if (std::isnan(p->c_x_lower) || p->c_x_lower < 0.0 || std::isnan(p->c_x_upper) ||
+        p->c_x_upper < 0.0)
+      return bad("c_x_lower and c_x_upper must be in [0, inf]");
+  }
   if (p->collision == LKS_TRT &&
       (!finite(p->lambda_f) || p->lambda_f <= 0.0 || !finite(p->lambda_m) || p->lambda_m <= 0.0))
     return bad("TRT needs finite lambda_f > 0 and lambda_m > 0");

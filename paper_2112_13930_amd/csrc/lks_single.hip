@@ -314,22 +314,27 @@ hipError_t launch_bc(lks_mhd *h, int shape, const void *src, void *dst, ObsOut o
 
 template <int MODE>
 hipError_t launch_mode(lks_mhd *h, int shape, const void *src, void *dst, ObsOut oo) {
-  // observables do not depend on the collision operator
-  const int sch = MODE == MODE_MOMENTS ? wall_of(scheme_of(h->ch.p)) : scheme_of(h->ch.p);
+  // observables do not depend on the collision operator (the walls they do)
+  const int sch = MODE == MODE_MOMENTS ? scheme_of(h->ch.p) & ~COLL_TRT : scheme_of(h->ch.p);
+  constexpr bool kCollide = MODE != MODE_MOMENTS;
   return dispatch_precision(h->ch.p.precision, [&](auto t) -> hipError_t {
     using S = typename decltype(t)::S;
     using C = typename decltype(t)::C;
     switch (sch) {
     case BC_LINK: return launch_bc<S, C, BC_LINK, MODE>(h, shape, src, dst, oo);
     case BC_MOMENT: return launch_bc<S, C, BC_MOMENT, MODE>(h, shape, src, dst, oo);
+    case BC_LINK | WALLS_X: return launch_bc<S, C, BC_LINK | WALLS_X, MODE>(h, shape, src, dst, oo);
     case BC_LINK | COLL_TRT:
-      if constexpr (MODE != MODE_MOMENTS)
-        return launch_bc<S, C, BC_LINK | COLL_TRT, MODE>(h, shape, src, dst, oo);
+      if constexpr (kCollide) return launch_bc<S, C, BC_LINK | COLL_TRT, MODE>(h, shape, src, dst, oo);
       break;
-    default:
-      if constexpr (MODE != MODE_MOMENTS)
-        return launch_bc<S, C, BC_MOMENT | COLL_TRT, MODE>(h, shape, src, dst, oo);
+    case BC_MOMENT | COLL_TRT:
+      if constexpr (kCollide) return launch_bc<S, C, BC_MOMENT | COLL_TRT, MODE>(h, shape, src, dst, oo);
       break;
+    case BC_LINK | COLL_TRT | WALLS_X:
+      if constexpr (kCollide)
+        return launch_bc<S, C, BC_LINK | COLL_TRT | WALLS_X, MODE>(h, shape, src, dst, oo);
+      break;
+    default: break;
     }
     return hipErrorInvalidValue;
   });

@@ -229,6 +229,10 @@ int validate3(const lks_mhd3_params *p, Channel *c) {
     set_error("invalid parameters: fz must be finite");
     return LKS_EINVAL;
   }
+  if (p->base.x_walls) {
+    set_error("invalid parameters: x is periodic in three dimensions (base.x_walls = 0)");
+    return LKS_EINVAL;
+  }
   if (p->side_walls != 0 && p->side_walls != 1) {
     set_error("invalid parameters: side_walls must be 0 or 1");
     return LKS_EINVAL;

@@ -17,6 +17,8 @@ def lib_kwargs(p: Params, precision: str) -> dict:
               c_lower=p.c_lo, c_upper=p.c_hi, u_lower=p.u_lo, u_upper=p.u_hi)
     if p.collision == oracle.TRT:
         kw.update(collision="trt", lambda_f=p.extra["lambda_f"], lambda_m=p.extra["lambda_m"])
+    if p.x_walls:
+        kw.update(x_walls=True, c_x=(p.cx_lo, p.cx_hi))
     return kw
 
 

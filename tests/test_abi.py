@@ -39,7 +39,7 @@ def test_every_declared_symbol_is_exported(L):
 
 
 def test_abi_version(L):
-    assert L.lib().lks_mhd_abi_version() == 3
+    assert L.lib().lks_mhd_abi_version() == 4
 
 
 def _v(L, **kw):
@@ -59,6 +59,8 @@ def _v(L, **kw):
     dict(u_upper=float("inf")), dict(rho0=0.0), dict(precision=7), dict(precision=4),
     dict(bc=5), dict(collision=2), dict(collision="trt", lambda_f=0.0),
     dict(collision="trt", lambda_m=float("inf")), dict(collision="trt", lambda_m=-1.0),
+    dict(x_walls=True, bc="moment"), dict(x_walls=True, nx=1), dict(x_walls=True, c_x=-1.0),
+    dict(x_walls=True, c_x=(0.0, float("nan"))),
 ])
 def test_validate_rejects(L, kw):
     rc, p = _v(L, **kw)
@@ -74,6 +76,7 @@ def test_validate_rejects(L, kw):
     dict(precision="fp64"), dict(precision="fp16"), dict(precision="fp16_f32"),
     dict(collision="trt"), dict(collision="trt", lambda_f=0.25, lambda_m=1.0 / 12.0),
     dict(collision="bgk", lambda_f=float("nan")),  # magic parameters unused under BGK
+    dict(x_walls=True), dict(x_walls=True, nx=2, c_x=(0.0, math.inf), collision="trt"),
 ])
 def test_validate_accepts(L, kw):
     rc, p = _v(L, **kw)
