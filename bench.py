@@ -27,7 +27,7 @@ Printed as one JSON line with, besides the contract fields:
                 against sequential plain FP32 solves at six arrival rates;
                 the headline step on a developed (random) state; the 3D
                 channel (D3Q19 + D3Q7 field) on 256^3 and the duct with
-                Shercliff side walls; the two-relaxation-time
+                Shercliff side walls; the 2D lid-driven enclosure; the two-relaxation-time
                 collision's rates beside BGK's.
   --only LEG    run one of the extra legs alone and print it (development).
 
@@ -237,6 +237,41 @@ def duct_3d(torch, n=256, steps=200, warmup=10):
             ref = np.asarray(gold[k])[:, :, None]                    # every x equal
             errs[k] = float(np.linalg.norm(got - ref) / (np.linalg.norm(ref) * math.sqrt(n)))
         out["fp32_error_vs_3d_oracle_1000_steps"] = errs
+    return out
+
+
+def enclosure(torch, steps=200, warmup=20):
+    """The lid-driven enclosure (x bounded by Shercliff walls with c = 1,
+    the headline's Hartmann walls and physics): FP32 rates on 4096^2 from
+    rest, BGK and TRT, and the FP32 run of the 512^2 cavity against the
+    oracle's values stored by tests/golden/make_golden.py after 1000 steps."""
+    import numpy as np
+
+    from paper_2112_13930_amd.channel import Channel
+    out = {}
+    for coll in ("bgk", "trt"):
+        kw = dict(HEADLINE, x_walls=True, c_x=1.0, collision=coll)
+        _, per_step, ch = time_channel(torch, Channel, kw, steps, warmup)
+        ch.close()
+        gbs = 152 * 4096 * 4096 / per_step / 1e9
+        out[f"fp32_4096_{coll}"] = {"mlups": round(4096 * 4096 / per_step / 1e6, 1),
+                                    "frac_hbm": round(gbs / PEAK_HBM_GBS, 3)}
+    gold_path = os.path.join(ROOT, "tests", "golden", "cavity_512_link_1000.json")
+    if os.path.exists(gold_path):
+        gold = json.load(open(gold_path))
+        sl = slice(*gold["sample"])
+        kw = dict(HEADLINE, nx=512, ny=512, x_walls=True, c_x=1.0)
+        ch = Channel(**kw, stream=torch.cuda.Stream())
+        ch.set_graph(50)
+        ch.step(1000)
+        m = ch.moments()
+        errs = {}
+        for k in ("ux", "uy", "bx"):
+            got = m[k].cpu().numpy()[sl, sl]
+            ref = np.asarray(gold[k])
+            errs[k] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        ch.close()
+        out["fp32_512_error_vs_oracle_1000_steps"] = errs
     return out
 
 
@@ -553,7 +588,7 @@ def write_summary(dirs, command):
 # ---------------------------------------------------------------------------
 
 LEGS = {"developed": developed_state_rate, "sweep": sweep, "precisions": other_precisions,
-        "channel_3d": three_d, "duct_3d": duct_3d, "trt": trt_rates,
+        "channel_3d": three_d, "duct_3d": duct_3d, "enclosure": enclosure, "trt": trt_rates,
         "batched": lambda torch: batched(torch, "fp32"),
         "serving": serving}
 
@@ -652,6 +687,8 @@ def main():
         extras["channel_3d"] = three_d(torch)
         log("duct ...")
         extras["duct_3d"] = duct_3d(torch)
+        log("enclosure ...")
+        extras["enclosure"] = enclosure(torch)
         log("TRT collision ...")
         extras["trt_collision"] = trt_rates(torch)
         log("batched ...")

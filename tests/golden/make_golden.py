@@ -30,7 +30,13 @@ duct_256_link_1000.json
     run is x-invariant).  Stores the u_x and B_x rows of the layers
     z = 0, 1, 4, 16, 64 and 128.
 
-Run:  python tests/golden/make_golden.py [config1] [precision] [couette256] [duct256]
+cavity_512_link_1000.json
+    The lid-driven enclosure: 512 x 512 nodes, link-based Hartmann walls
+    (tau_f = 0.7, tau_m = 0.9, Ha = 50, c = 1, upper wall moving at 0.05) and
+    stationary x-walls with c = 1, 1000 steps from rest, 2D oracle.  Stores
+    u_x, u_y and B_x at the nodes (8 + 16 i, 8 + 16 j).
+
+Run:  python tests/golden/make_golden.py [config1] [precision] [couette256] [duct256] [cavity512]
 """
 import json
 import os
@@ -140,8 +146,29 @@ def duct256(nthreads=8):
     }
 
 
+CAVITY_SAMPLE = slice(8, 512, 16)
+
+
+def cavity512(nthreads=8):
+    p = derive.couette_params(512, 512, oracle.LINK, 0.7, 0.9, 50.0, 1.0, 1.0, 0.05)
+    p = oracle.Params(**{**p.__dict__, "x_walls": True, "cx_lo": 1.0, "cx_hi": 1.0})
+    s = oracle.init_state(p)
+    oracle.run(p, s, 1000, nthreads=nthreads)
+    o = oracle.observe(p, s)
+    return {
+        "description": "lid-driven enclosure 512x512, link-based, tau_f=0.7, tau_m=0.9, Ha=50, "
+                       "c=1 on all walls, upper wall U=0.05, 1000 steps from rest; oracle FP64 "
+                       "u_x, u_y, B_x at rows and columns 8, 24, ..., 504",
+        "params": {"nx": 512, "ny": 512, "bc": "link", "tau_f": 0.7, "tau_m": 0.9, "ha": 50.0,
+                   "c": 1.0, "c_x": 1.0, "u_upper": 0.05, "steps": 1000, "a": p.a,
+                   "b0": p.b0},
+        "sample": [CAVITY_SAMPLE.start, CAVITY_SAMPLE.stop, CAVITY_SAMPLE.step],
+        **{k: o[k][CAVITY_SAMPLE, CAVITY_SAMPLE].tolist() for k in ("ux", "uy", "bx")},
+    }
+
+
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["config1", "precision", "couette256", "duct256"]
+    which = sys.argv[1:] or ["config1", "precision", "couette256", "duct256", "cavity512"]
     if "config1" in which:
         out = os.path.join(HERE, "config1_hartmann_link.json")
         with open(out, "w") as fh:
@@ -161,6 +188,12 @@ if __name__ == "__main__":
     if "duct256" in which:
         out = os.path.join(HERE, "duct_256_link_1000.json")
         data = duct256()
+        with open(out, "w") as fh:
+            json.dump(data, fh, indent=1)
+        print("wrote", out)
+    if "cavity512" in which:
+        out = os.path.join(HERE, "cavity_512_link_1000.json")
+        data = cavity512()
         with open(out, "w") as fh:
             json.dump(data, fh, indent=1)
         print("wrote", out)

@@ -101,3 +101,15 @@ def test_duct_far_from_its_side_walls_is_the_channel():
         rows = dict(zip(duct["layers"], (np.asarray(r) for r in duct[k])))
         assert np.linalg.norm(rows[128] - ref) / np.linalg.norm(ref) < 1e-4
         assert np.linalg.norm(rows[0] - ref) / np.linalg.norm(ref) > 0.1
+
+
+def test_cavity_fixture_is_an_enclosure_flow():
+    """The stored cavity: the lid drags the top layer along +x, a return flow
+    runs along -x below it, and u_y changes sign across the cavity (the
+    recirculation); the field is induced (B_x non-zero)."""
+    here = os.path.join(os.path.dirname(__file__), "golden")
+    g = json.load(open(os.path.join(here, "cavity_512_link_1000.json")))
+    ux, uy, bx = (np.asarray(g[k]) for k in ("ux", "uy", "bx"))
+    assert ux[-1].mean() > 0.01 and ux[:-1].min() < 0
+    assert uy.max() > 0 > uy.min()
+    assert np.abs(bx).max() > 0
