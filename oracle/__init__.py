@@ -57,6 +57,7 @@ class _Params(ctypes.Structure):
         ("tau_fm", ctypes.c_double), ("tau_mp", ctypes.c_double),
         ("x_walls", ctypes.c_int32), ("pad_", ctypes.c_int32),
         ("cx_lo", ctypes.c_double), ("cx_hi", ctypes.c_double),
+        ("q_lo", ctypes.c_double), ("q_hi", ctypes.c_double),
     ]
 
 
@@ -130,22 +131,28 @@ class Params:
     x_walls: bool = False  # enclosure: stationary Shercliff walls bound x
     cx_lo: float = 0.0     # their conductance ratios (x = 0 side, x = nx-1 side)
     cx_hi: float = 0.0
+    q_lo: float = 0.5      # link scheme: Hartmann wall distance from its wall row
+    q_hi: float = 0.5
     extra: dict = field(default_factory=dict)
 
     def half_width(self) -> float:
         if not math.isnan(self.a):
             return self.a
-        return self.ny / 2.0 if self.bc == LINK else (self.ny - 1) / 2.0
+        if self.bc == LINK:
+            return (self.ny - 1 + self.q_lo + self.q_hi) / 2.0
+        return (self.ny - 1) / 2.0
 
     def c_struct(self) -> _Params:
         if self.collision == TRT:
             assert self.tau_fm > 0.5 and self.tau_mp > 0.5, "TRT needs tau_fm and tau_mp > 1/2"
         if self.x_walls:
             assert self.bc == LINK and self.nx >= 2, "enclosure walls need link-based closures"
+        if (self.q_lo, self.q_hi) != (0.5, 0.5):
+            assert self.bc == LINK and 0 < self.q_lo <= 1 and 0 < self.q_hi <= 1
         return _Params(self.nx, self.ny, self.bc, self.collision, self.tau_f, self.tau_m,
                        self.b0, self.fx, self.fy, self.c_lo, self.c_hi,
                        self.u_lo, self.u_hi, self.half_width(), self.tau_fm, self.tau_mp,
-                       int(self.x_walls), 0, self.cx_lo, self.cx_hi)
+                       int(self.x_walls), 0, self.cx_lo, self.cx_hi, self.q_lo, self.q_hi)
 
 
 def init_state(p: Params) -> np.ndarray:

@@ -76,6 +76,8 @@ typedef struct {
   double tau_mp;       /* TRT: relaxation time of the even part of g */
   int32_t x_walls, pad_; /* 1: an enclosure, stationary walls at x = -1/2 and nx - 1/2 */
   double cx_lo, cx_hi;   /* their wall conductance ratios (0 .. INFINITY) */
+  double q_lo, q_hi;     /* link scheme: distance of each Hartmann wall from its
+                            wall row, in (0, 1]; 1/2 is the paper's half-way wall */
 } orc_params;
 
 /* ---------------------------------------------------------------------- */
@@ -223,6 +225,113 @@ void orc_link_closure(const orc_params *p, int wall, const double *own,
 }
 
 /*
+ * Link-based closure with the Hartmann wall at a distance q (0 < q <= 1)
+ * from the wall row instead of half-way (the paper names link-based walls at
+ * other cut distances as future work, Sec. IX).  in is the whole
+ * post-collision state and (x, y) the wall-row node; the closure reads the
+ * node itself and the next nodes into the fluid along the wall normal.
+ *   f: linear interpolated bounce-back (Bouzidi, Firdaouss and Lallemand,
+ *      Phys. Fluids 13 (2001) 3452) with the moving-wall term scaled as in
+ *      Lallemand and Luo, J. Comput. Phys. 184 (2003) 406:
+ *        q <  1/2: f_a = 2q f~_abar + (1-2q) f~_abar(x + e_a) + 2 w e_ax U / cs2
+ *        q >= 1/2: f_a = f~_abar / (2q) + (1 - 1/(2q)) f~_a + w e_ax U / (q cs2)
+ *   g, a field component with the wall value zero (the normal component's
+ *      induced part, or any component at an insulating wall): interpolated
+ *      anti-bounce-back, exact for linear profiles,
+ *        q <  1/2: g_a = -2q g~_abar + (2q-1) g~_abar(x + e_a)
+ *        q >= 1/2: g_a = -g~_abar / (2q) + (1 - 1/(2q)) g~_a
+ *      (induced parts: g_y is taken minus W B0 on both sides).
+ *   g, the tangential component at a conducting wall (0 < c <= inf).  Its
+ *      outgoing post-collision populations at the wall row and the next two
+ *      nodes, o0, o1, o2, give the closure
+ *        g_a = r o0 + kappa (o2 - 2 o1 + o0) - (1 + r) W (e_ay/cs2m) B0 U.
+ *      With the first-order Chapman-Enskog populations
+ *      g~ = g^eq - (tau_m - 1) W e.grad b of a quadratic profile and the
+ *      thin-wall condition c a db/dn + b = 0 at the wall, the first two
+ *      Taylor orders fix
+ *        r = (C + q - tau_m) / (C + q + tau_m - 1),   C = c a (r = 1 at c = inf),
+ *        kappa = Bt - r B0 - (1 - r) K,
+ *        B0 = q^2/2 + (tau_m-1) q,  Bt = (1-q)^2/2 + (tau_m-1)(1-q),
+ *        K = 1/8 + (tau_m-1)/2,
+ *      which cancels the curvature term of order c a (1/2 - q) b'' that
+ *      would otherwise make the wall condition first order.  At q = 1/2,
+ *      kappa = 0 and r = (theta-1)/(theta+1), theta = c a / (tau_m - 1/2):
+ *      the paper's closure.  The moving-wall term is the paper's with the
+ *      factor 1 + r.
+ */
+static inline size_t idx(const orc_params *p, int plane, int y, int x);
+
+void orc_link_closure_q(const orc_params *p, int wall, const double *in, int x, int y,
+                        double *f, double *gx, double *gy) {
+  const int ey_in = (wall == ORC_LOWER) ? +1 : -1;
+  const double cw = (wall == ORC_LOWER) ? p->c_lo : p->c_hi;
+  const double uw = (wall == ORC_LOWER) ? p->u_lo : p->u_hi;
+  const double q = (wall == ORC_LOWER) ? p->q_lo : p->q_hi;
+  const double tau = p->tau_m;
+#define ST(plane, yy, xx) in[idx(p, (plane), (yy), ((xx) % p->nx + p->nx) % p->nx)]
+  double defect = 0.0, win = 0.0;
+  for (int a = 0; a < NQ9; ++a) {
+    if (EY9[a] != ey_in) continue;
+    const double ladd = 2.0 * W9[a] * EX9[a] * uw / CS2;
+    const double out0 = ST(OPP9[a], y, x);
+    if (q < 0.5)
+      f[a] = 2.0 * q * out0 + (1.0 - 2.0 * q) * ST(OPP9[a], y + EY9[a], x + EX9[a]) + ladd;
+    else
+      f[a] = out0 / (2.0 * q) + (1.0 - 1.0 / (2.0 * q)) * ST(a, y, x) + ladd / (2.0 * q);
+    defect += out0 - f[a];
+    win += W9[a];
+  }
+  /* the mass the wall would let through (non-zero when the post-collision
+   * populations are asymmetric about the wall normal, as under a normal
+   * force) goes back into the incoming populations in proportion to their
+   * weights, so that no mass crosses the wall, as with bounce-back */
+  for (int a = 0; a < NQ9; ++a)
+    if (EY9[a] == ey_in) f[a] += defect * W9[a] / win;
+  /* the D2Q5 link entering from the wall: a = 2 (lower) or 4 (upper) */
+  const int a = (wall == ORC_LOWER) ? 2 : 4, o = OPP5[a];
+  const double wb0 = W5[a] * p->b0;
+  /* interpolated anti-bounce-back of a field component with wall value 0;
+   * dev is subtracted from every population (W B0 for g_y) */
+  double zero_wall[2];
+  for (int i = 0; i < 2; ++i) {
+    const int base = 9 + 5 * i;
+    const double dev = (i == 1) ? wb0 : 0.0;
+    const double o0 = ST(base + o, y, x) - dev;
+    if (q < 0.5)
+      zero_wall[i] = -2.0 * q * o0 + (2.0 * q - 1.0) * (ST(base + o, y + ey_in, x) - dev) + dev;
+    else
+      zero_wall[i] = -o0 / (2.0 * q) + (1.0 - 1.0 / (2.0 * q)) * (ST(base + a, y, x) - dev) + dev;
+  }
+  gy[a] = zero_wall[1];
+  if (cw == 0.0) {
+    gx[a] = zero_wall[0];
+  } else {
+    const double C = cw * p->a;
+    const double r = isinf(cw) ? 1.0 : (C + q - tau) / (C + q + tau - 1.0);
+    const double B0c = 0.5 * q * q + (tau - 1.0) * q;
+    const double Btc = 0.5 * (1.0 - q) * (1.0 - q) + (tau - 1.0) * (1.0 - q);
+    const double K = 0.125 + 0.5 * (tau - 1.0);
+    const double kappa = Btc - r * B0c - (1.0 - r) * K;
+    const double o0 = ST(9 + o, y, x), o1 = ST(9 + o, y + ey_in, x),
+                 o2 = ST(9 + o, y + 2 * ey_in, x);
+    const double moving = W5[a] * (EY5[a] / CSM2) * p->b0 * uw;
+    /* the flux part 3 W e_y B0 u_x of the equilibria leaves, through the
+     * wall-normal shear du/dn = (u_x - U)/q, a mismatch (1/2 - q)(1 + r)
+     * times 3 W e_y B0 du/dn; u_x is the node's velocity from its
+     * post-collision momentum */
+    double rho_n = 0.0, mx_n = 0.0;
+    for (int b = 0; b < NQ9; ++b) {
+      rho_n += ST(b, y, x);
+      mx_n += EX9[b] * ST(b, y, x);
+    }
+    const double dudn = (mx_n / rho_n - uw) / q;
+    const double shear = (0.5 - q) * (1.0 + r) * W5[a] * (EY5[a] / CSM2) * p->b0 * dudn;
+    gx[a] = r * o0 + kappa * (o2 - 2.0 * o1 + o0) - (1.0 + r) * moving + shear;
+  }
+#undef ST
+}
+
+/*
  * Walls of an enclosure at x = -1/2 (lower, wall = ORC_LOWER) and
  * x = nx - 1/2 (upper), parallel to the imposed field: stationary,
  * link-based, applied to every link whose source lies behind the wall:
@@ -360,17 +469,16 @@ static void gather_node(const orc_params *p, const double *in, int x, int y,
   if (nwall) {
     double own[NPLANES];
     for (int k = 0; k < NPLANES; ++k) own[k] = in[idx(p, k, y, x)];
-    if (y == 0) {
-      if (p->bc == ORC_LINK)
-        orc_link_closure(p, ORC_LOWER, own, n->f, n->gx, n->gy);
-      else
-        orc_moment_closure(p, ORC_LOWER, n->f, n->gx, n->gy);
-    }
-    if (y == p->ny - 1) {
-      if (p->bc == ORC_LINK)
-        orc_link_closure(p, ORC_UPPER, own, n->f, n->gx, n->gy);
-      else
-        orc_moment_closure(p, ORC_UPPER, n->f, n->gx, n->gy);
+    for (int w = 0; w < 2; ++w) {
+      if (!(w == ORC_LOWER ? y == 0 : y == p->ny - 1)) continue;
+      const double qw = (w == ORC_LOWER) ? p->q_lo : p->q_hi;
+      if (p->bc != ORC_LINK) {
+        orc_moment_closure(p, w, n->f, n->gx, n->gy);
+      } else if (qw == 0.5) {
+        orc_link_closure(p, w, own, n->f, n->gx, n->gy);
+      } else {
+        orc_link_closure_q(p, w, in, x, y, n->f, n->gx, n->gy);
+      }
     }
   }
   /* S3: moments (Secs. IV, V). */
