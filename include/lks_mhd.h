@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define LKS_MHD_ABI_VERSION 4
+#define LKS_MHD_ABI_VERSION 5
 
 typedef struct lks_mhd lks_mhd_t;             /* one channel, library-owned */
 typedef struct lks_mhd_batch lks_mhd_batch_t; /* many channels, library-owned */
@@ -136,6 +136,17 @@ enum lks_status {
  *               same a as the Hartmann walls; the normal B_x anti-bounces to
  *               zero.  Links crossing a Hartmann wall at a corner take that
  *               wall's closure (with its moving-wall term).
+ *   q_lower,    link scheme: distance of each Hartmann wall from its wall row
+ *   q_upper     in (0, 1] [1/2, the paper's half-way wall].  Other values put
+ *               the walls q beyond the wall rows, so that the half-width is
+ *               a = (ny - 1 + q_lower + q_upper)/2, and close
+ *               them by interpolated bounce-back of f (with a correction that
+ *               keeps the wall impermeable), interpolated anti-bounce-back of
+ *               the field components with wall value zero, and, for the
+ *               tangential component at a conducting wall, a three-node
+ *               closure that reduces to the paper's at q = 1/2 (single
+ *               channels, not enclosures or batches; ny >= 3; a conducting
+ *               wall needs c a + q + tau_m - 1 >= 1/4).
  */
 typedef struct {
   int32_t nx, ny;
@@ -153,6 +164,7 @@ typedef struct {
   int32_t x_walls;
   double lambda_f, lambda_m;
   double c_x_lower, c_x_upper;
+  double q_lower, q_upper;
 } lks_mhd_params;
 
 /* Lattice quantities derived from a parameter set (host FP64). */

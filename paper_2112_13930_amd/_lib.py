@@ -40,6 +40,7 @@ class LksParams(ctypes.Structure):
         ("collision", ctypes.c_int32), ("x_walls", ctypes.c_int32),
         ("lambda_f", ctypes.c_double), ("lambda_m", ctypes.c_double),
         ("c_x_lower", ctypes.c_double), ("c_x_upper", ctypes.c_double),
+        ("q_lower", ctypes.c_double), ("q_upper", ctypes.c_double),
     ]
 
 
@@ -155,12 +156,13 @@ def check(code: int, what: str = "") -> int:
 def make_params(nx: int, ny: int, *, bc="link", precision="fp32", tau_f=0.8, tau_m=0.8,
                 ha=None, b0=None, c_lower=0.0, c_upper=None, u_lower=0.0, u_upper=0.0,
                 fx=None, fy=0.0, u_max=None, rho0=1.0, collision="bgk", lambda_f=None,
-                lambda_m=None, x_walls=False, c_x=0.0) -> LksParams:
+                lambda_m=None, x_walls=False, c_x=0.0, q=0.5) -> LksParams:
     """Build a parameter struct.  ``ha`` derives B0; ``u_max`` derives F_x;
     ``collision`` is "bgk" or "trt" (magic parameters ``lambda_f``,
     ``lambda_m``; the library's defaults when None); ``x_walls`` makes an
     enclosure whose x-walls have the conductance ratios ``c_x`` (both) or
-    (x = 0 side, x = nx-1 side)."""
+    (x = 0 side, x = nx-1 side); ``q`` puts the link-based Hartmann walls at
+    that distance from their wall rows (both, or (lower, upper))."""
     p = LksParams()
     lib().lks_mhd_default_params(ctypes.byref(p), int(nx), int(ny))
     p.bc = BCS[bc] if isinstance(bc, str) else int(bc)
@@ -185,6 +187,8 @@ def make_params(nx: int, ny: int, *, bc="link", precision="fp32", tau_f=0.8, tau
         p.lambda_f = float(lambda_f)
     if lambda_m is not None:
         p.lambda_m = float(lambda_m)
+    ql, qh = q if isinstance(q, (tuple, list)) else (q, q)
+    p.q_lower, p.q_upper = float(ql), float(qh)
     p.x_walls = int(bool(x_walls))
     lo, hi = c_x if isinstance(c_x, (tuple, list)) else (c_x, c_x)
     p.c_x_lower, p.c_x_upper = float(lo), float(hi)

@@ -659,6 +659,10 @@ int lks_mhd_batch_admit(lks_mhd_batch_t *b, const lks_mhd_params *p, int32_t *sl
     set_error("invalid parameters: batches hold x-periodic channels only (x_walls = 0)");
     return LKS_EINVAL;
   }
+  if (q.q_lower != 0.5 || q.q_upper != 0.5) {
+    set_error("invalid parameters: batches hold half-way walls only (q = 1/2)");
+    return LKS_EINVAL;
+  }
   const int64_t n = (int64_t)q.nx * q.ny;
   if (b->nodes + n > b->max_nodes) {
     set_error("batch node capacity %lld exceeded", (long long)b->max_nodes);

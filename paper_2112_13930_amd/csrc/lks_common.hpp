@@ -71,13 +71,39 @@ Coef<C> make_coef(const Channel &c) {
   };
   k.xr_lo = C(c.p.x_walls ? xr(c.p.c_x_lower) : 1.0);
   k.xr_hi = C(c.p.x_walls ? xr(c.p.c_x_upper) : 1.0);
+  // Hartmann walls at cut distances (Cut<C>)
+  auto cut = [&](double q, double cw, double U, int s) {
+    const bool near = q < 0.5;
+    const double tau = c.p.tau_m;
+    const double r = std::isinf(cw) ? 1.0 : (cw * c.d.a + q - tau) / (cw * c.d.a + q + tau - 1.0);
+    const double b0c = 0.5 * q * q + (tau - 1.0) * q;
+    const double btc = 0.5 * (1.0 - q) * (1.0 - q) + (tau - 1.0) * (1.0 - q);
+    const double kk = 0.125 + 0.5 * (tau - 1.0);
+    Cut<C> o;
+    o.near = near ? 1 : 0;
+    o.conducting = cw > 0.0 ? 1 : 0;
+    o.fa = C(near ? 2.0 * q : 0.5 / q);
+    o.fb = C(near ? 1.0 - 2.0 * q : 1.0 - 0.5 / q);
+    o.lscale = C(near ? 1.0 : 0.5 / q);
+    o.za = C(near ? -2.0 * q : -0.5 / q);
+    o.zb = C(near ? 2.0 * q - 1.0 : 1.0 - 0.5 / q);
+    o.r = C(r);
+    o.kappa = C(btc - r * b0c - (1.0 - r) * kk);
+    // W (e_y / cs2m) B0 = s B0 / 2 for the incoming D2Q5 link
+    o.tmove = C(-(1.0 + r) * 0.5 * s * c.d.b0 * U);
+    o.tshear = C((0.5 - q) * (1.0 + r) * 0.5 * s * c.d.b0 / q);
+    o.u = C(U);
+    return o;
+  };
+  k.clo = cut(c.p.q_lower, c.p.c_lower, c.p.u_lower, +1);
+  k.chi = cut(c.p.q_upper, c.p.c_upper, c.p.u_upper, -1);
   return k;
 }
 
 // The kernels' scheme parameter of a channel: wall scheme | collision.
 inline int scheme_of(const lks_mhd_params &p) {
   return (p.bc == LKS_BC_LINK ? BC_LINK : BC_MOMENT) | (p.collision == LKS_TRT ? COLL_TRT : 0) |
-         (p.x_walls ? WALLS_X : 0);
+         (p.x_walls ? WALLS_X : 0) | ((p.q_lower != 0.5 || p.q_upper != 0.5) ? WALLS_Q : 0);
 }
 
 inline bool valid_precision(int precision) {

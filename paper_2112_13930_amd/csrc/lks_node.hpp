@@ -56,9 +56,13 @@ enum { BC_LINK = 0, BC_MOMENT = 1 };
 constexpr int COLL_TRT = 4;
 // ... and with WALLS_X for an enclosure (link-closed walls bounding x)
 constexpr int WALLS_X = 8;
+// ... and with WALLS_Q for link-based Hartmann walls at a cut distance
+// q != 1/2 from their wall rows
+constexpr int WALLS_Q = 16;
 constexpr int wall_of(int scheme) { return scheme & 3; }
 constexpr bool trt_of(int scheme) { return (scheme & COLL_TRT) != 0; }
 constexpr bool xwalls_of(int scheme) { return (scheme & WALLS_X) != 0; }
+constexpr bool cut_of(int scheme) { return (scheme & WALLS_Q) != 0; }
 enum { MODE_STEP = 0, MODE_RECORD = 1, MODE_RESIDUAL = 2, MODE_MOMENTS = 3 };
 
 // Closure coefficients of one wall (computed on the host in FP64).
@@ -88,6 +92,25 @@ struct Trt {
   C ga, gb, gp;
 };
 
+// A link-based Hartmann wall at a cut distance q (0 < q <= 1) from its
+// wall row (host FP64 coefficients).  With o the outgoing post-collision
+// population at the wall row and X the same direction's population at the
+// next node into the fluid (near, q < 1/2) or the wall row's own incoming
+// post-collision population (q >= 1/2):
+//   f:   f_in = fa o + fb X + lscale * (moving-wall term), then the mass the
+//        wall would let through returns to the incoming populations
+//        (weights 4/6, 1/6, 1/6);
+//   g with wall value zero (normal component; tangential at c = 0):
+//        g_in = za o + zb X   (stored deviations);
+//   g_x at a conducting wall: g_in = r o0 + kappa (o2 - 2 o1 + o0) + tmove
+//        + tshear (u - U), with o1, o2 one and two nodes further in and u
+//        the wall row's velocity from its post-collision momentum.
+template <typename C>
+struct Cut {
+  int near, conducting;
+  C fa, fb, lscale, za, zb, r, kappa, tmove, tshear, u;
+};
+
 template <typename C>
 struct Coef {
   C omega_f;  // 1/tau_f
@@ -99,6 +122,7 @@ struct Coef {
   Wall<C> lo, hi;
   Trt<C> trt; // used by schemes with COLL_TRT
   C xr_lo, xr_hi; // enclosure walls (WALLS_X): (theta-1)/(theta+1) at x = 0, nx-1
+  Cut<C> clo, chi; // Hartmann walls at cut distances (WALLS_Q)
 };
 
 // Geometry of one channel's planes (element units).
@@ -255,7 +279,58 @@ __device__ __forceinline__ void node_finish(const Geom &g, const Coef<C> &k,
       gy[3] = k.xr_hi * dec<S>(ld<S, C>(src + 15 * P + r0 + x), Dy, 15);
     }
   }
-  if (wall_of(BC) == BC_LINK) {
+  if constexpr (wall_of(BC) == BC_LINK && cut_of(BC)) {
+    // Hartmann walls at cut distances (Cut<C>); s = +1 at the lower wall,
+    // -1 at the upper (the e_y of the incoming populations)
+    auto at = [&](int plane, int yy, int xx) -> C {
+      return dec<S>(ld<S, C>(src + plane * P + (long long)yy * g.pitch + xx),
+                    ref + (long long)yy * 19, plane);
+    };
+    const int xm = (x == 0) ? g.nx - 1 : x - 1, xp = (x == g.nx - 1) ? 0 : x + 1;
+    auto close = [&](const Cut<C> &c, int s, C uw6) {
+      // incoming f: normal a0, diagonals a1 (e_x = +1), a2 (e_x = -1), each
+      // with its opposite (outgoing) plane
+      const int a0 = s > 0 ? 2 : 4, a1 = s > 0 ? 5 : 8, a2 = s > 0 ? 6 : 7;
+      const int o0 = s > 0 ? 4 : 2, o1 = s > 0 ? 7 : 6, o2 = s > 0 ? 8 : 5;
+      const int yn = y + s;
+      const C out0 = at(o0, y, x), out1 = at(o1, y, x), out2 = at(o2, y, x);
+      const C X0 = c.near ? at(o0, yn, x) : at(a0, y, x);
+      const C X1 = c.near ? at(o1, yn, xp) : at(a1, y, x);
+      const C X2 = c.near ? at(o2, yn, xm) : at(a2, y, x);
+      const C n0 = c.fa * out0 + c.fb * X0;
+      const C n1 = c.fa * out1 + c.fb * X1 + c.lscale * uw6;
+      const C n2 = c.fa * out2 + c.fb * X2 - c.lscale * uw6;
+      const C defect = (out0 + out1 + out2) - (n0 + n1 + n2);
+      f[a0] = n0 + defect * (C(2) / C(3));
+      f[a1] = n1 + defect * (C(1) / C(6));
+      f[a2] = n2 + defect * (C(1) / C(6));
+      // field: the D2Q5 link entering from the wall and its outgoing one
+      const int gi = s > 0 ? 2 : 4, go = s > 0 ? 4 : 2;
+      const C yo = at(14 + go, y, x);
+      const C yX = c.near ? at(14 + go, yn, x) : at(14 + gi, y, x);
+      gy[gi] = c.za * yo + c.zb * yX;
+      const C xo = at(9 + go, y, x);
+      if (!c.conducting) {
+        const C xX = c.near ? at(9 + go, yn, x) : at(9 + gi, y, x);
+        gx[gi] = c.za * xo + c.zb * xX;
+      } else {
+        const C x1 = at(9 + go, yn, x), x2 = at(9 + go, yn + s, x);
+        C rhop = C(0), mx = C(0);
+#pragma unroll
+        for (int b = 0; b < 9; ++b) {
+          const C v = at(b, y, x);
+          rhop += v;
+          mx += C(b == 1 || b == 5 || b == 8 ? 1 : (b == 3 || b == 6 || b == 7 ? -1 : 0)) * v;
+        }
+        const C un = mx / (C(1) + rhop);
+        gx[gi] = c.r * xo + c.kappa * (x2 - C(2) * x1 + xo) + c.tmove + c.tshear * (un - c.u);
+      }
+    };
+    // upper wall: the diagonal a1 = 8 has e_x = +1, a2 = 7 has e_x = -1;
+    // Ladd's term is -U/6 on 7 and +U/6 on 8
+    if (lo) close(k.clo, +1, k.lo.uw6);
+    if (hi) close(k.chi, -1, k.hi.uw6);
+  } else if (wall_of(BC) == BC_LINK) {
     // Half-way bounce-back of f with Ladd's moving-wall term; theta-weighted
     // bounce-back/anti-bounce-back of g_x; anti-bounce-back to B_y = B0 for
     // g_y, which for the deviations g_y - W B0 is g'_in = -g~'_out.  All from

@@ -7,6 +7,7 @@
 //   theta = c_w a / (tau_m - 1/2)                         (Eq. weightingfactor)
 //   phi = c_w a / (tau_m cs2m)     (ratio of the two coefficients of Sec. VII)
 //   TRT free rates: tau- = 1/2 + Lambda / (tau+ - 1/2) and conversely
+//   link walls at cut distances q: a = (ny - 1 + q_lower + q_upper)/2
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -71,6 +72,14 @@ int derive_channel(const lks_mhd_params *p, Channel *out) {
         p->c_x_upper < 0.0)
       return bad("c_x_lower and c_x_upper must be in [0, inf]");
   }
+  if (!(p->q_lower > 0.0 && p->q_lower <= 1.0) || !(p->q_upper > 0.0 && p->q_upper <= 1.0))
+    return bad("q_lower and q_upper must be in (0, 1]");
+  const bool cut = p->q_lower != 0.5 || p->q_upper != 0.5;
+  if (cut) {
+    if (p->bc != LKS_BC_LINK) return bad("walls at cut distances need link-based closures");
+    if (p->x_walls) return bad("walls at cut distances are not available in enclosures");
+    if (p->ny < 3) return bad("walls at cut distances need ny >= 3");
+  }
   if (p->collision == LKS_TRT &&
       (!finite(p->lambda_f) || p->lambda_f <= 0.0 || !finite(p->lambda_m) || p->lambda_m <= 0.0))
     return bad("TRT needs finite lambda_f > 0 and lambda_m > 0");
@@ -80,7 +89,7 @@ int derive_channel(const lks_mhd_params *p, Channel *out) {
   lks_mhd_derived &d = c.d;
   d.nu = (p->tau_f - 0.5) / 3.0;
   d.eta = (p->tau_m - 0.5) / 3.0;
-  d.a = (p->bc == LKS_BC_LINK) ? 0.5 * p->ny : 0.5 * (p->ny - 1);
+  d.a = (p->bc == LKS_BC_LINK) ? 0.5 * (p->ny - 1 + p->q_lower + p->q_upper) : 0.5 * (p->ny - 1);
   if (std::isnan(p->ha)) {
     if (!finite(p->b0)) return bad("b0 must be finite when ha is NaN");
     d.b0 = p->b0;
@@ -105,6 +114,13 @@ int derive_channel(const lks_mhd_params *p, Channel *out) {
   d.theta_upper = std::isinf(p->c_upper) ? INFINITY : p->c_upper * d.a / (p->tau_m - 0.5);
   d.phi_lower = std::isinf(p->c_lower) ? INFINITY : p->c_lower * d.a * 3.0 / p->tau_m;
   d.phi_upper = std::isinf(p->c_upper) ? INFINITY : p->c_upper * d.a * 3.0 / p->tau_m;
+  // a conducting wall at a cut distance: the single-node coefficient
+  // (c a + q - tau_m)/(c a + q + tau_m - 1) needs a denominator away from 0
+  for (int w = 0; w < 2 && cut; ++w) {
+    const double c = w ? p->c_upper : p->c_lower, q = w ? p->q_upper : p->q_lower;
+    if (c > 0.0 && std::isfinite(c) && c * d.a + q + p->tau_m - 1.0 < 0.25)
+      return bad("a conducting wall at cut distance q needs c a + q + tau_m - 1 >= 1/4");
+  }
   // TRT: the free rate of each distribution from its magic parameter
   // Lambda = (tau+ - 1/2)(tau- - 1/2)
   if (p->collision == LKS_TRT) {
@@ -182,6 +198,8 @@ void lks_mhd_default_params(lks_mhd_params *p, int32_t nx, int32_t ny) {
   p->collision = LKS_BGK;
   p->lambda_f = 3.0 / 16.0;
   p->lambda_m = 0.25;
+  p->q_lower = 0.5;
+  p->q_upper = 0.5;
 }
 
 int lks_mhd_validate(const lks_mhd_params *p) {

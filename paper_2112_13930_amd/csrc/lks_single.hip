@@ -334,6 +334,11 @@ hipError_t launch_mode(lks_mhd *h, int shape, const void *src, void *dst, ObsOut
       if constexpr (kCollide)
         return launch_bc<S, C, BC_LINK | COLL_TRT | WALLS_X, MODE>(h, shape, src, dst, oo);
       break;
+    case BC_LINK | WALLS_Q: return launch_bc<S, C, BC_LINK | WALLS_Q, MODE>(h, shape, src, dst, oo);
+    case BC_LINK | COLL_TRT | WALLS_Q:
+      if constexpr (kCollide)
+        return launch_bc<S, C, BC_LINK | COLL_TRT | WALLS_Q, MODE>(h, shape, src, dst, oo);
+      break;
     default: break;
     }
     return hipErrorInvalidValue;

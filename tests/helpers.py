@@ -19,6 +19,8 @@ def lib_kwargs(p: Params, precision: str) -> dict:
         kw.update(collision="trt", lambda_f=p.extra["lambda_f"], lambda_m=p.extra["lambda_m"])
     if p.x_walls:
         kw.update(x_walls=True, c_x=(p.cx_lo, p.cx_hi))
+    if (p.q_lo, p.q_hi) != (0.5, 0.5):
+        kw.update(q=(p.q_lo, p.q_hi))
     return kw
 
 

@@ -39,7 +39,7 @@ def test_every_declared_symbol_is_exported(L):
 
 
 def test_abi_version(L):
-    assert L.lib().lks_mhd_abi_version() == 4
+    assert L.lib().lks_mhd_abi_version() == 5
 
 
 def _v(L, **kw):
@@ -61,6 +61,9 @@ def _v(L, **kw):
     dict(collision="trt", lambda_m=float("inf")), dict(collision="trt", lambda_m=-1.0),
     dict(x_walls=True, bc="moment"), dict(x_walls=True, nx=1), dict(x_walls=True, c_x=-1.0),
     dict(x_walls=True, c_x=(0.0, float("nan"))),
+    dict(q=0.0), dict(q=1.5), dict(q=(0.5, float("nan"))), dict(q=0.3, bc="moment"),
+    dict(q=0.3, x_walls=True), dict(q=0.3, ny=2),
+    dict(q=0.1, c_lower=1e-3, tau_m=0.55),         # c a + q + tau_m - 1 < 1/4
 ])
 def test_validate_rejects(L, kw):
     rc, p = _v(L, **kw)
@@ -77,6 +80,7 @@ def test_validate_rejects(L, kw):
     dict(collision="trt"), dict(collision="trt", lambda_f=0.25, lambda_m=1.0 / 12.0),
     dict(collision="bgk", lambda_f=float("nan")),  # magic parameters unused under BGK
     dict(x_walls=True), dict(x_walls=True, nx=2, c_x=(0.0, math.inf), collision="trt"),
+    dict(q=0.25), dict(q=(1.0, 0.3), c_lower=math.inf), dict(q=0.1, c_lower=0.0, tau_m=0.55),
 ])
 def test_validate_accepts(L, kw):
     rc, p = _v(L, **kw)
@@ -101,6 +105,11 @@ def test_derivation_agrees_with_oracle(L, bc, ha, c):
     assert math.isclose(d.eta, od.eta_of(0.9), rel_tol=1e-15)
     theta = math.inf if math.isinf(c) else c * q.a / (0.9 - 0.5)
     assert d.theta_lower == pytest.approx(theta, rel=1e-15)
+    if bc == oracle.LINK:   # walls at cut distances change the half-width
+        pq = L.make_params(8, ny, bc="link", tau_f=0.8, tau_m=0.9, ha=ha, u_max=0.05,
+                           c_lower=c, c_upper=c, q=(0.25, 1.0))
+        oq = oracle.Params(nx=8, ny=ny, bc=oracle.LINK, q_lo=0.25, q_hi=1.0)
+        assert L.derive(pq).a == oq.half_width() == (ny - 1 + 1.25) / 2
 
 
 @pytest.mark.parametrize("tau_f,tau_m,lf,lm", [(0.8, 0.9, 3 / 16, 0.25), (0.55, 1.7, 0.01, 2.0)])
