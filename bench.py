@@ -27,7 +27,8 @@ Printed as one JSON line with, besides the contract fields:
                 against sequential plain FP32 solves at six arrival rates;
                 the headline step on a developed (random) state; the 3D
                 channel (D3Q19 + D3Q7 field) on 256^3 and the duct with
-                Shercliff side walls; the 2D lid-driven enclosure; the two-relaxation-time
+                Shercliff side walls; the 2D lid-driven enclosure; link walls at
+                cut distances q != 1/2; the two-relaxation-time
                 collision's rates beside BGK's.
   --only LEG    run one of the extra legs alone and print it (development).
 
@@ -272,6 +273,48 @@ def enclosure(torch, steps=200, warmup=20):
             errs[k] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
         ch.close()
         out["fp32_512_error_vs_oracle_1000_steps"] = errs
+    return out
+
+
+def chang_lundgren_u(xi, ha, c):
+    """Chang-Lundgren centreline-normalised velocity u/U_ref at xi = y/a
+    (Sec. VIII): (K/Ha)(1 - cosh(Ha xi)/cosh Ha), K = (c+1)/(Ha c + tanh Ha)."""
+    import numpy as np
+    K = (c + 1.0) / (ha * c + math.tanh(ha))
+    return (K / ha) * (1.0 - np.cosh(ha * xi) / math.cosh(ha))
+
+
+def cut_walls(torch, steps=200, warmup=20):
+    """Link-based Hartmann walls at cut distances q != 1/2: the FP32 rate on
+    the headline grid (q = 0.3 below, 0.8 above), and steady FP32 Hartmann
+    flow (Ha 5, c 0.5, 64 rows) between walls at q = 0.25, 1/2 and 1 against
+    the Chang-Lundgren profile with the half-width (ny - 1)/2 + q."""
+    import numpy as np
+
+    from paper_2112_13930_amd._lib import derive, make_params
+    from paper_2112_13930_amd.channel import Channel
+    out = {}
+    _, per_step, ch = time_channel(torch, Channel, dict(HEADLINE, q=(0.3, 0.8)), steps, warmup)
+    ch.close()
+    gbs = 152 * 4096 * 4096 / per_step / 1e9
+    out["fp32_4096_q_0.3_0.8"] = {"mlups": round(4096 * 4096 / per_step / 1e6, 1),
+                                  "frac_hbm": round(gbs / PEAK_HBM_GBS, 3)}
+    ny, ha, c = 64, 5.0, 0.5
+    errs = {}
+    for q in (0.25, 0.5, 1.0):
+        kw = dict(bc="link", precision="fp32", tau_f=0.8, tau_m=0.8, ha=ha, u_max=0.02,
+                  c_lower=c, c_upper=c, q=q)
+        d = derive(make_params(8, ny, **kw))
+        ch = Channel(8, ny, stream=torch.cuda.Stream(), **kw)
+        ch.set_graph(50)
+        rc, n, res, _ = ch.run_to_steady(tol=1e-10, check_every=1000, max_steps=400_000)
+        ux = ch.moments()["ux"].cpu().numpy()[:, 0]
+        ch.close()
+        xi = (np.arange(ny) + q - d.a) / d.a
+        ref = d.a * d.a * d.fx / d.nu * chang_lundgren_u(xi, ha, c)
+        errs[f"q={q}"] = {"steps": int(n), "status": int(rc),
+                          "u_rel_l2_vs_closed_form": float(np.linalg.norm(ux - ref) / np.linalg.norm(ref))}
+    out["fp32_hartmann_64_rows_vs_chang_lundgren"] = errs
     return out
 
 
@@ -589,6 +632,7 @@ def write_summary(dirs, command):
 
 LEGS = {"developed": developed_state_rate, "sweep": sweep, "precisions": other_precisions,
         "channel_3d": three_d, "duct_3d": duct_3d, "enclosure": enclosure, "trt": trt_rates,
+        "cut_walls": cut_walls,
         "batched": lambda torch: batched(torch, "fp32"),
         "serving": serving}
 
@@ -689,6 +733,8 @@ def main():
         extras["duct_3d"] = duct_3d(torch)
         log("enclosure ...")
         extras["enclosure"] = enclosure(torch)
+        log("cut walls ...")
+        extras["cut_walls"] = cut_walls(torch)
         log("TRT collision ...")
         extras["trt_collision"] = trt_rates(torch)
         log("batched ...")
