@@ -138,9 +138,11 @@ struct NodeObs {
   C rho, rhop, ux, uy, bx, by, jz; // rhop = rho - 1 as accumulated from the deviations
 };
 
+// Every stored population is read once per step (pull), so loads stream
+// past the caches as the stores do.
 template <typename S, typename C>
 __device__ __forceinline__ C ld(const S *__restrict__ p) {
-  return static_cast<C>(*p);
+  return static_cast<C>(__builtin_nontemporal_load(p));
 }
 
 template <typename S, typename C>

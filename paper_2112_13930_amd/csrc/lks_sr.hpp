@@ -80,22 +80,7 @@ LKS_HD inline float sr_f32(double v, uint32_t r) {
   return (float)dbl(b); // exact: 24 significant bits left
 }
 
-// binary64 -> binary16: with the spacing g = 2^(E - 10) of binary16 at
-// v's exponent E (E held at -14 or above: the subnormal spacing is a fixed
-// 2^-24), the result is g floor(v / g + u) for u uniform in [0, 1), whose
-// expectation is v for either sign.  v / g has at most 11 integer bits, so
-// v / g + u is exact to 2^-42 and the scalings by powers of two are exact.
-LKS_HD inline _Float16 sr_f16(double v, uint32_t r) {
-  int e;
-  (void)__builtin_frexp(v, &e);           // v = m 2^e, 1/2 <= |m| < 1
-  const int E = e - 1 < -14 ? -14 : e - 1; // binary16 exponent of the spacing
-  const double z = __builtin_ldexp(v, 10 - E);
-  const double u = (double)r * 0x1p-32;
-  const double m = __builtin_ldexp(__builtin_floor(z + u), E - 10);
-  return (_Float16)(float)m;               // both conversions exact
-}
-
-// binary32 -> binary16 (binary16 storage with FP32 arithmetic).
+// binary32 -> binary16.
 LKS_HD inline _Float16 sr_f16(float v, uint32_t r) {
   const uint32_t b = bits32(v);
   const uint32_t sign = b & 0x80000000u;
@@ -119,7 +104,11 @@ LKS_HD inline S round_sr(C v, uint32_t r) {
     return (S)v;
   } else {
     if constexpr (sizeof(S) == 4) return sr_f32(v, r);
-    else return sr_f16(v, r);
+    // binary64 goes to the nearest binary32 first: that moves v by at most
+    // 2^-25 |v|, 2^-14 of a binary16 spacing, and costs a few integer
+    // instructions where rounding at v's binary16 spacing in FP64 took ten
+    // FP64 ones (the binary16 step is arithmetic-bound)
+    else return sr_f16((float)v, r);
   }
 }
 

@@ -85,14 +85,12 @@ int main() {
   std::uniform_real_distribution<double> U(0.0, 1.0);
   const int N = 4096;
   auto f32 = [](double v, uint32_t r) { return sr_f32(v, r); };
-  auto f16d = [](double v, uint32_t r) { return sr_f16(v, r); };
   auto f16f = [](float v, uint32_t r) { return sr_f16(v, r); };
   for (int t = 0; t < 4000; ++t) {
     // magnitudes spread over many binades, both signs
     const double mag = std::exp2(-40.0 + 56.0 * U(g)) * (1.0 + U(g));
     const double v = (t & 1) ? -mag : mag;
     if (std::fabs(v) < 65504.0) {
-      check<_Float16>(v, f16d, N);
       check<_Float16>((float)v, f16f, N);
     }
     if (std::fabs(v) > 1e-30) check<float>(v, f32, N);
@@ -100,7 +98,7 @@ int main() {
   // beyond binary16's range the result is infinite
   for (double v : {65536.0, -70000.0, 1e6}) {
     ++checks;
-    if (!std::isinf((double)sr_f16(v, 12345u)) || !std::isinf((double)sr_f16((float)v, 12345u))) {
+    if (!std::isinf((double)sr_f16((float)v, 12345u))) {
       ++fails;
       printf("no overflow to inf for %g\n", v);
     }
@@ -110,7 +108,6 @@ int main() {
                             0x1.ffcp-15, 0x1.ffdp-15, 0x1p-15 * 3, 1.0, 1.0 + 0x1p-11, 65504.0,
                             0.1, 1.0 / 3, 0x1.0000001p0, -0x1p-20, -0.0};
   for (double v : special) {
-    check<_Float16>(v, f16d, N);
     check<_Float16>((float)v, f16f, N);
     if (v == 0 || std::fabs(v) > 1e-30) check<float>(v, f32, N);
   }
@@ -121,7 +118,6 @@ int main() {
     const double mag = std::exp2(-40.0 + 56.0 * U(g2)) * (1.0 + U(g2));
     const double v = (t & 1) ? -mag : mag;
     if (std::fabs(v) < 65504.0) {
-      check<_Float16>(v, f16d, 65536);
       check<_Float16>((float)v, f16f, 65536);
     }
     if (std::fabs(v) > 1e-30) check<float>(v, f32, 65536);
