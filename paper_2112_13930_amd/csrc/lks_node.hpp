@@ -138,11 +138,18 @@ struct NodeObs {
   C rho, rhop, ux, uy, bx, by, jz; // rhop = rho - 1 as accumulated from the deviations
 };
 
-// Every stored population is read once per step (pull), so loads stream
-// past the caches as the stores do.
+// Every stored population is read once per step (pull).  A pull along x
+// shifts a block's row segment by one node, so one cache line at each end of
+// the segment is shared with the neighbouring block: those pulls (ldx) go
+// through the caches, where the neighbour finds the line.  The others (ld)
+// stream past them, as the stores do.
 template <typename S, typename C>
 __device__ __forceinline__ C ld(const S *__restrict__ p) {
   return static_cast<C>(__builtin_nontemporal_load(p));
+}
+template <typename S, typename C>
+__device__ __forceinline__ C ldx(const S *__restrict__ p) {
+  return static_cast<C>(*p);
 }
 
 template <typename S, typename C>
@@ -510,25 +517,25 @@ __device__ __forceinline__ void node_update(const Geom &g, const Coef<C> &k,
   const C *__restrict__ Dp = hi ? Dy : Dy + 19; // row y + 1 (used only off the upper wall)
   C f[9], gx[5], gy[5];
   f[0] = dec<S>(ld<S, C>(src + r0 + x), Dy, 0);
-  f[1] = dec<S>(ld<S, C>(src + 1 * P + r0 + xm), Dy, 1);
-  f[3] = dec<S>(ld<S, C>(src + 3 * P + r0 + xp), Dy, 3);
+  f[1] = dec<S>(ldx<S, C>(src + 1 * P + r0 + xm), Dy, 1);
+  f[3] = dec<S>(ldx<S, C>(src + 3 * P + r0 + xp), Dy, 3);
   gx[0] = dec<S>(ld<S, C>(src + 9 * P + r0 + x), Dy, 9);
-  gx[1] = dec<S>(ld<S, C>(src + 10 * P + r0 + xm), Dy, 10);
-  gx[3] = dec<S>(ld<S, C>(src + 12 * P + r0 + xp), Dy, 12);
+  gx[1] = dec<S>(ldx<S, C>(src + 10 * P + r0 + xm), Dy, 10);
+  gx[3] = dec<S>(ldx<S, C>(src + 12 * P + r0 + xp), Dy, 12);
   gy[0] = dec<S>(ld<S, C>(src + 14 * P + r0 + x), Dy, 14);
-  gy[1] = dec<S>(ld<S, C>(src + 15 * P + r0 + xm), Dy, 15);
-  gy[3] = dec<S>(ld<S, C>(src + 17 * P + r0 + xp), Dy, 17);
+  gy[1] = dec<S>(ldx<S, C>(src + 15 * P + r0 + xm), Dy, 15);
+  gy[3] = dec<S>(ldx<S, C>(src + 17 * P + r0 + xp), Dy, 17);
   if (!lo) {
     f[2] = dec<S>(ld<S, C>(src + 2 * P + rm + x), Dm, 2);
-    f[5] = dec<S>(ld<S, C>(src + 5 * P + rm + xm), Dm, 5);
-    f[6] = dec<S>(ld<S, C>(src + 6 * P + rm + xp), Dm, 6);
+    f[5] = dec<S>(ldx<S, C>(src + 5 * P + rm + xm), Dm, 5);
+    f[6] = dec<S>(ldx<S, C>(src + 6 * P + rm + xp), Dm, 6);
     gx[2] = dec<S>(ld<S, C>(src + 11 * P + rm + x), Dm, 11);
     gy[2] = dec<S>(ld<S, C>(src + 16 * P + rm + x), Dm, 16);
   }
   if (!hi) {
     f[4] = dec<S>(ld<S, C>(src + 4 * P + rp + x), Dp, 4);
-    f[7] = dec<S>(ld<S, C>(src + 7 * P + rp + xp), Dp, 7);
-    f[8] = dec<S>(ld<S, C>(src + 8 * P + rp + xm), Dp, 8);
+    f[7] = dec<S>(ldx<S, C>(src + 7 * P + rp + xp), Dp, 7);
+    f[8] = dec<S>(ldx<S, C>(src + 8 * P + rp + xm), Dp, 8);
     gx[4] = dec<S>(ld<S, C>(src + 13 * P + rp + x), Dp, 13);
     gy[4] = dec<S>(ld<S, C>(src + 18 * P + rp + x), Dp, 18);
   }

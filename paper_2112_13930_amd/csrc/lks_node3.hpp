@@ -100,7 +100,8 @@ __device__ __forceinline__ void node3_update(const Geom3 &g, const Coef<C> &k, C
       f[q] = R(0);
       continue;
     }
-    f[q] = ld<S, R>(src + q * P + srcoff(D3Q19::ex[q], ey_, D3Q19::ez[q]));
+    const S *p = src + q * P + srcoff(D3Q19::ex[q], ey_, D3Q19::ez[q]);
+    f[q] = D3Q19::ex[q] != 0 ? ldx<S, R>(p) : ld<S, R>(p);
   }
 #pragma unroll
   for (int a = 0; a < 6; ++a) {
@@ -110,9 +111,15 @@ __device__ __forceinline__ void node3_update(const Geom3 &g, const Coef<C> &k, C
       continue;
     }
     const long long o = srcoff(D3Q6::ex[a], ey_, D3Q6::ez[a]);
-    gx[a] = ld<S, R>(src + (19 + a) * P + o);
-    gy[a] = ld<S, R>(src + (25 + a) * P + o);
-    gz[a] = ld<S, R>(src + (31 + a) * P + o);
+    if (D3Q6::ex[a] != 0) {
+      gx[a] = ldx<S, R>(src + (19 + a) * P + o);
+      gy[a] = ldx<S, R>(src + (25 + a) * P + o);
+      gz[a] = ldx<S, R>(src + (31 + a) * P + o);
+    } else {
+      gx[a] = ld<S, R>(src + (19 + a) * P + o);
+      gy[a] = ld<S, R>(src + (25 + a) * P + o);
+      gz[a] = ld<S, R>(src + (31 + a) * P + o);
+    }
   }
 
   // ---- wall closures ----
