@@ -100,18 +100,20 @@ __global__ __launch_bounds__(kTileThreads) void k_batch_step(
       const C *ref = static_cast<const C *>(c.ref);
       switch (c.bc) { // uniform per block
       case BC_LINK:
-        node_update<S, C, BC_LINK, MODE, SR>(c.g, coef_of<C>(c), src, ref, dst, x, y, o, sseed);
+        node_update<S, C, BC_LINK | IN_BATCH, MODE, SR>(c.g, coef_of<C>(c), src, ref, dst, x,
+                                                        y, o, sseed);
         break;
       case BC_MOMENT:
-        node_update<S, C, BC_MOMENT, MODE, SR>(c.g, coef_of<C>(c), src, ref, dst, x, y, o, sseed);
+        node_update<S, C, BC_MOMENT | IN_BATCH, MODE, SR>(c.g, coef_of<C>(c), src, ref, dst, x,
+                                                          y, o, sseed);
         break;
       case BC_LINK | COLL_TRT:
-        node_update<S, C, BC_LINK | COLL_TRT, MODE, SR>(c.g, coef_of<C>(c), src, ref, dst, x, y,
-                                                        o, sseed);
+        node_update<S, C, BC_LINK | COLL_TRT | IN_BATCH, MODE, SR>(c.g, coef_of<C>(c), src, ref,
+                                                                   dst, x, y, o, sseed);
         break;
       default:
-        node_update<S, C, BC_MOMENT | COLL_TRT, MODE, SR>(c.g, coef_of<C>(c), src, ref, dst, x,
-                                                          y, o, sseed);
+        node_update<S, C, BC_MOMENT | COLL_TRT | IN_BATCH, MODE, SR>(c.g, coef_of<C>(c), src,
+                                                                     ref, dst, x, y, o, sseed);
         break;
       }
       const long long i = (long long)y * c.g.nx + x;

@@ -59,10 +59,15 @@ constexpr int WALLS_X = 8;
 // ... and with WALLS_Q for link-based Hartmann walls at a cut distance
 // q != 1/2 from their wall rows
 constexpr int WALLS_Q = 16;
+// ... and with IN_BATCH inside the batched kernel: its rows follow each
+// other without padding, so cache lines straddle rows, and it inlines every
+// scheme, so code length and divergent branches cost more than elsewhere
+constexpr int IN_BATCH = 32;
 constexpr int wall_of(int scheme) { return scheme & 3; }
 constexpr bool trt_of(int scheme) { return (scheme & COLL_TRT) != 0; }
 constexpr bool xwalls_of(int scheme) { return (scheme & WALLS_X) != 0; }
 constexpr bool cut_of(int scheme) { return (scheme & WALLS_Q) != 0; }
+constexpr bool in_batch(int scheme) { return (scheme & IN_BATCH) != 0; }
 enum { MODE_STEP = 0, MODE_RECORD = 1, MODE_RESIDUAL = 2, MODE_MOMENTS = 3 };
 
 // Closure coefficients of one wall (computed on the host in FP64).
@@ -142,10 +147,13 @@ struct NodeObs {
 // shifts a block's row segment by one node, so one cache line at each end of
 // the segment is shared with the neighbouring block: those pulls (ldx) go
 // through the caches, where the neighbour finds the line.  The others (ld)
-// stream past them, as the stores do.
-template <typename S, typename C>
+// stream past them, as the stores do, unless rows are packed (NT false,
+// the batched kernel): then a line at a row's end also holds the next
+// row's start.
+template <typename S, typename C, bool NT = true>
 __device__ __forceinline__ C ld(const S *__restrict__ p) {
-  return static_cast<C>(__builtin_nontemporal_load(p));
+  if constexpr (NT) return static_cast<C>(__builtin_nontemporal_load(p));
+  else return static_cast<C>(*p);
 }
 template <typename S, typename C>
 __device__ __forceinline__ C ldx(const S *__restrict__ p) {
@@ -162,10 +170,10 @@ __device__ __forceinline__ void st(S *__restrict__ p, C v) {
 // once the flow is steady, and slow modes integrate it; rounding to one of
 // the two neighbouring representable values with probabilities given by the
 // distances makes the residual change from step to step (lks_sr.hpp).
-template <typename S, typename C, bool SR>
+template <typename S, typename C, bool SR, bool SEL = false>
 __device__ __forceinline__ S to_store(C v, uint32_t r) {
   if constexpr (SR) {
-    return round_sr<S, C>(v, r);
+    return round_sr<S, C, SEL>(v, r);
   } else {
     (void)r;
     return static_cast<S>(v);
@@ -436,7 +444,7 @@ __device__ __forceinline__ void node_finish(const Geom &g, const Coef<C> &k,
   auto put = [&](C v, int plane) -> S {
     (void)plane;
     if constexpr (kRowRef<S>) v = (v - Dy[plane]) * C(kStoreUp16);
-    return to_store<S, C, SR>(v, SR ? rng.next() : 0u);
+    return to_store<S, C, SR, in_batch(BC)>(v, SR ? rng.next() : 0u);
   };
   const C om = k.omega_f, ka = k.kappa_f;
   const C usq15 = C(1.5) * (ux * ux + uy * uy);
@@ -515,29 +523,30 @@ __device__ __forceinline__ void node_update(const Geom &g, const Coef<C> &k,
   const C *__restrict__ Dy = ref + (long long)y * 19;
   const C *__restrict__ Dm = lo ? Dy : Dy - 19; // row y - 1 (used only off the lower wall)
   const C *__restrict__ Dp = hi ? Dy : Dy + 19; // row y + 1 (used only off the upper wall)
+  constexpr bool NT = !in_batch(BC);
   C f[9], gx[5], gy[5];
-  f[0] = dec<S>(ld<S, C>(src + r0 + x), Dy, 0);
+  f[0] = dec<S>(ld<S, C, NT>(src + r0 + x), Dy, 0);
   f[1] = dec<S>(ldx<S, C>(src + 1 * P + r0 + xm), Dy, 1);
   f[3] = dec<S>(ldx<S, C>(src + 3 * P + r0 + xp), Dy, 3);
-  gx[0] = dec<S>(ld<S, C>(src + 9 * P + r0 + x), Dy, 9);
+  gx[0] = dec<S>(ld<S, C, NT>(src + 9 * P + r0 + x), Dy, 9);
   gx[1] = dec<S>(ldx<S, C>(src + 10 * P + r0 + xm), Dy, 10);
   gx[3] = dec<S>(ldx<S, C>(src + 12 * P + r0 + xp), Dy, 12);
-  gy[0] = dec<S>(ld<S, C>(src + 14 * P + r0 + x), Dy, 14);
+  gy[0] = dec<S>(ld<S, C, NT>(src + 14 * P + r0 + x), Dy, 14);
   gy[1] = dec<S>(ldx<S, C>(src + 15 * P + r0 + xm), Dy, 15);
   gy[3] = dec<S>(ldx<S, C>(src + 17 * P + r0 + xp), Dy, 17);
   if (!lo) {
-    f[2] = dec<S>(ld<S, C>(src + 2 * P + rm + x), Dm, 2);
+    f[2] = dec<S>(ld<S, C, NT>(src + 2 * P + rm + x), Dm, 2);
     f[5] = dec<S>(ldx<S, C>(src + 5 * P + rm + xm), Dm, 5);
     f[6] = dec<S>(ldx<S, C>(src + 6 * P + rm + xp), Dm, 6);
-    gx[2] = dec<S>(ld<S, C>(src + 11 * P + rm + x), Dm, 11);
-    gy[2] = dec<S>(ld<S, C>(src + 16 * P + rm + x), Dm, 16);
+    gx[2] = dec<S>(ld<S, C, NT>(src + 11 * P + rm + x), Dm, 11);
+    gy[2] = dec<S>(ld<S, C, NT>(src + 16 * P + rm + x), Dm, 16);
   }
   if (!hi) {
-    f[4] = dec<S>(ld<S, C>(src + 4 * P + rp + x), Dp, 4);
+    f[4] = dec<S>(ld<S, C, NT>(src + 4 * P + rp + x), Dp, 4);
     f[7] = dec<S>(ldx<S, C>(src + 7 * P + rp + xp), Dp, 7);
     f[8] = dec<S>(ldx<S, C>(src + 8 * P + rp + xm), Dp, 8);
-    gx[4] = dec<S>(ld<S, C>(src + 13 * P + rp + x), Dp, 13);
-    gy[4] = dec<S>(ld<S, C>(src + 18 * P + rp + x), Dp, 18);
+    gx[4] = dec<S>(ld<S, C, NT>(src + 13 * P + rp + x), Dp, 13);
+    gy[4] = dec<S>(ld<S, C, NT>(src + 18 * P + rp + x), Dp, 18);
   }
 
   NodeObs<C> &o_ = obs;

@@ -80,7 +80,9 @@ LKS_HD inline float sr_f32(double v, uint32_t r) {
   return (float)dbl(b); // exact: 24 significant bits left
 }
 
-// binary32 -> binary16.
+// binary32 -> binary16.  Below 2^-24 the result is 0 or 2^-24 (binary16's
+// smallest subnormal) with probability |v| / 2^-24; above, random bits are
+// added below binary16's last place and truncated.
 LKS_HD inline _Float16 sr_f16(float v, uint32_t r) {
   const uint32_t b = bits32(v);
   const uint32_t sign = b & 0x80000000u;
@@ -95,9 +97,27 @@ LKS_HD inline _Float16 sr_f16(float v, uint32_t r) {
   return (_Float16)flt(sign | t); // exact
 }
 
+// The same result with both cases computed and one selected (no branch).
+// The branch suits kernels of one scheme, whose wavefronts mostly agree on
+// it and which lose occupancy to the registers of the select form; the
+// select suits the batched kernel, whose small channels mix both cases in a
+// wavefront and which inlines every scheme's stores.
+LKS_HD inline _Float16 sr_f16_sel(float v, uint32_t r) {
+  const uint32_t b = bits32(v);
+  const uint32_t sign = b & 0x80000000u;
+  const uint32_t mag = b ^ sign;
+  const int e = (int)(mag >> 23) - 127;
+  const float p = (float)(r >> 8) * 0x1p-48f;
+  const uint32_t tiny = p < flt(mag) ? 0x33800000u : 0u;
+  const int k = e >= -14 ? 13 : (e >= -24 ? -1 - e : 23);
+  const uint32_t t = (mag + (r >> (32 - k))) & ~((1u << k) - 1u);
+  return (_Float16)flt(sign | (e < -24 ? tiny : t));
+}
+
 // Stochastic rounding of v (compute type C) to storage type S; identity for
-// equal types.
-template <typename S, typename C>
+// equal types.  SEL picks the select form of the binary16 rounding (same
+// result).
+template <typename S, typename C, bool SEL = false>
 LKS_HD inline S round_sr(C v, uint32_t r) {
   if constexpr (sizeof(S) == sizeof(C)) {
     (void)r;
@@ -108,6 +128,7 @@ LKS_HD inline S round_sr(C v, uint32_t r) {
     // 2^-25 |v|, 2^-14 of a binary16 spacing, and costs a few integer
     // instructions where rounding at v's binary16 spacing in FP64 took ten
     // FP64 ones (the binary16 step is arithmetic-bound)
+    else if constexpr (SEL) return sr_f16_sel((float)v, r);
     else return sr_f16((float)v, r);
   }
 }

@@ -5,7 +5,8 @@
 // magnitude side must equal the exact probability
 //   (|v| - |lo|) / (|hi| - |lo|)
 // to within the sweep's resolution.  Exactly representable values must come
-// back unchanged.
+// back unchanged.  The select form of the binary32 -> binary16 rounding must
+// give the branching form's bits for every value and word.
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -15,6 +16,7 @@
 #include "lks_sr.hpp"
 
 using lks::sr_f16;
+using lks::sr_f16_sel;
 using lks::sr_f32;
 
 static int fails = 0;
@@ -122,6 +124,25 @@ int main() {
     }
     if (std::fabs(v) > 1e-30) check<float>(v, f32, 65536);
   }
+  // select form == branching form: random words on every binary32 pattern
+  // class (zero, binary32 subnormals, every exponent, infinities and the
+  // binary16 boundaries), both signs
+  std::mt19937_64 g3(4242);
+  auto same = [&](float v, uint32_t r) {
+    ++checks;
+    const _Float16 a = sr_f16(v, r), b = sr_f16_sel(v, r);
+    if (tbits(a) != tbits(b) && !(a != a && b != b)) {
+      if (fails++ < 10) printf("select form differs: v=%a r=%08x\n", (double)v, r);
+    }
+  };
+  for (int t = 0; t < 1 << 22; ++t) {
+    const uint32_t e = (uint32_t)(g3() % 256u), m = (uint32_t)(g3() & 0x7FFFFFu);
+    const uint32_t sgn = (uint32_t)(g3() & 1u) << 31;
+    same(__builtin_bit_cast(float, sgn | (e << 23) | (e == 255 ? 0u : m)), (uint32_t)g3());
+  }
+  for (float v : {0.0f, -0.0f, 0x1p-24f, 0x1p-25f, 0x1.fffffep-25f, 0x1p-14f, 0x1.fffffep-15f,
+                  0x1p-149f, 65504.0f, 65520.0f})
+    for (uint32_t r : {0u, 1u, 0x7FFFFFFFu, 0x80000000u, 0xFFFFFFFFu, 0x12345678u}) same(v, r);
   // the generator's words: top 16 bits spread over all values, bit 15 set
   lks::Rng rng(12345u);
   int hist[16] = {0};
