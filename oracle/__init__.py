@@ -6,7 +6,7 @@ links or executes anything here, and this package imports nothing from it.
 
 Contents
   lks_oracle.c   plain C reference step (pull stream, wall closures, moments,
-                 coupled u/J solve, BGK or TRT collisions) -- built into
+                 coupled u/J solve, BGK, TRT or MRT collisions) -- built into
                  liblks_oracle.so by :func:`build`.
   analytic.py    closed-form Hartmann (Chang-Lundgren) and Hartmann-Couette
                  profiles of Sec. VIII and App. C.
@@ -29,7 +29,7 @@ SRC = os.path.join(HERE, "lks_oracle.c")
 LIB = os.path.join(HERE, "liblks_oracle.so")
 
 LINK, MOMENT = 0, 1
-BGK, TRT = 0, 1
+BGK, TRT, MRT = 0, 1, 2
 NPLANES = 19
 
 
@@ -58,6 +58,8 @@ class _Params(ctypes.Structure):
         ("x_walls", ctypes.c_int32), ("pad_", ctypes.c_int32),
         ("cx_lo", ctypes.c_double), ("cx_hi", ctypes.c_double),
         ("q_lo", ctypes.c_double), ("q_hi", ctypes.c_double),
+        ("s_fe", ctypes.c_double), ("s_feps", ctypes.c_double), ("s_fq", ctypes.c_double),
+        ("s_me", ctypes.c_double), ("s_md", ctypes.c_double),
     ]
 
 
@@ -110,6 +112,9 @@ class Params:
     ``tau_f`` relaxes the even part of f and ``tau_fm`` its odd part, ``tau_m``
     the odd part of g and ``tau_mp`` its even part
     (:func:`oracle.derive.trt_times` gives them from the magic parameters).
+    Under MRT, f's moments p_xx and p_xy relax at 1/tau_f and e, epsilon and q
+    at ``s_fe``, ``s_feps`` and ``s_fq``; g's Lambda moments at 1/tau_m and its
+    epsilon and d moments at ``s_me`` and ``s_md`` (:func:`oracle.derive.mrt_rates`).
     """
     nx: int
     ny: int
@@ -133,6 +138,11 @@ class Params:
     cx_hi: float = 0.0
     q_lo: float = 0.5      # link scheme: Hartmann wall distance from its wall row
     q_hi: float = 0.5
+    s_fe: float = float("nan")    # MRT rates (collision == MRT)
+    s_feps: float = float("nan")
+    s_fq: float = float("nan")
+    s_me: float = float("nan")
+    s_md: float = float("nan")
     extra: dict = field(default_factory=dict)
 
     def half_width(self) -> float:
@@ -145,6 +155,9 @@ class Params:
     def c_struct(self) -> _Params:
         if self.collision == TRT:
             assert self.tau_fm > 0.5 and self.tau_mp > 0.5, "TRT needs tau_fm and tau_mp > 1/2"
+        if self.collision == MRT:
+            assert all(0 < r < 2 for r in (self.s_fe, self.s_feps, self.s_fq, self.s_me,
+                                           self.s_md)), "MRT needs rates in (0, 2)"
         if self.x_walls:
             assert self.bc == LINK and self.nx >= 2, "enclosure walls need link-based closures"
         if (self.q_lo, self.q_hi) != (0.5, 0.5):
@@ -152,7 +165,8 @@ class Params:
         return _Params(self.nx, self.ny, self.bc, self.collision, self.tau_f, self.tau_m,
                        self.b0, self.fx, self.fy, self.c_lo, self.c_hi,
                        self.u_lo, self.u_hi, self.half_width(), self.tau_fm, self.tau_mp,
-                       int(self.x_walls), 0, self.cx_lo, self.cx_hi, self.q_lo, self.q_hi)
+                       int(self.x_walls), 0, self.cx_lo, self.cx_hi, self.q_lo, self.q_hi,
+                       self.s_fe, self.s_feps, self.s_fq, self.s_me, self.s_md)
 
 
 def init_state(p: Params) -> np.ndarray:

@@ -36,6 +36,17 @@ def trt_times(tau_f: float, tau_m: float, lambda_f: float, lambda_m: float):
     return 0.5 + lambda_f / (tau_f - 0.5), 0.5 + lambda_m / (tau_m - 0.5)
 
 
+def mrt_rates(tau_f: float, tau_m: float, lambda_f: float, lambda_m: float,
+              s_e: float = 1.64, s_eps: float = 1.54):
+    """MRT rates (s_fe, s_feps, s_fq, s_me, s_md).  The energy modes of f take
+    s_e and s_eps (defaults: Lallemand & Luo 2000's stability choice); the
+    odd q modes of f and both second-order modes of g take the TRT rates of
+    the magic parameters, so that s_e = s_eps = 1/tau_f makes MRT the TRT of
+    (lambda_f, lambda_m)."""
+    tau_fm, tau_mp = trt_times(tau_f, tau_m, lambda_f, lambda_m)
+    return s_e, s_eps, 1.0 / tau_fm, 1.0 / tau_mp, 1.0 / tau_mp
+
+
 def half_width(ny: int, bc: int) -> float:
     return ny / 2.0 if bc == LINK else (ny - 1) / 2.0
 

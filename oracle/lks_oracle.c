@@ -62,7 +62,7 @@ enum { ORC_LOWER = 0, ORC_UPPER = 1 };
  * meaning: tau_f relaxes the even (symmetric) part of f, giving nu, and
  * tau_m the odd (antisymmetric) part of g, giving eta; tau_fm and tau_mp are
  * the free rates of the other halves. */
-enum { ORC_BGK = 0, ORC_TRT = 1 };
+enum { ORC_BGK = 0, ORC_TRT = 1, ORC_MRT = 2 };
 
 typedef struct {
   int32_t nx, ny, bc, collision;
@@ -78,6 +78,8 @@ typedef struct {
   double cx_lo, cx_hi;   /* their wall conductance ratios (0 .. INFINITY) */
   double q_lo, q_hi;     /* link scheme: distance of each Hartmann wall from its
                             wall row, in (0, 1]; 1/2 is the paper's half-way wall */
+  double s_fe, s_feps, s_fq; /* MRT rates of f's e, epsilon and q moments */
+  double s_me, s_md;         /* MRT rates of g's epsilon and d moments */
 } orc_params;
 
 /* ---------------------------------------------------------------------- */
@@ -537,7 +539,53 @@ static void gather_node(const orc_params *p, const double *in, int x, int y,
  *   h+_a = (h_a + h_abar)/2,  h-_a = (h_a - h_abar)/2,
  * for h = f, f^eq, S (and g, g^eq), and each part relaxes at its own rate,
  * the source part with the matching weight 1 - 1/(2 tau+-).  The rest
- * population is even. */
+ * population is even.
+ * MRT: populations map to moments (the bases above); each moment's
+ * non-equilibrium part relaxes at its own rate, the source's moment with the
+ * matching weight, and the moments map back.  The paper names multiple
+ * relaxation times as a replacement for BGK (Secs. V and IX) without fixing
+ * a basis; these are the usual orthogonal ones. */
+/* MRT moment bases.  f (D2Q9, Lallemand & Luo 2000): rows rho, e, epsilon,
+ * j_x, q_x, j_y, q_y, p_xx, p_xy.  g (D2Q5, each component): rows B,
+ * Lambda_x, Lambda_y, epsilon, d.  The rows of each are orthogonal, so
+ * M^-1 = M^T diag(1 / |row|^2). */
+static const double MRT9[NQ9][NQ9] = {{1, 1, 1, 1, 1, 1, 1, 1, 1},
+                                      {-4, -1, -1, -1, -1, 2, 2, 2, 2},
+                                      {4, -2, -2, -2, -2, 1, 1, 1, 1},
+                                      {0, 1, 0, -1, 0, 1, -1, -1, 1},
+                                      {0, -2, 0, 2, 0, 1, -1, -1, 1},
+                                      {0, 0, 1, 0, -1, 1, 1, -1, -1},
+                                      {0, 0, -2, 0, 2, 1, 1, -1, -1},
+                                      {0, 1, -1, 1, -1, 0, 0, 0, 0},
+                                      {0, 0, 0, 0, 0, 1, -1, 1, -1}};
+static const double MRT5[NQ5][NQ5] = {{1, 1, 1, 1, 1},
+                                      {0, 1, 0, -1, 0},
+                                      {0, 0, 1, 0, -1},
+                                      {-4, 1, 1, 1, 1},
+                                      {0, 1, -1, 1, -1}};
+
+/* One MRT update of n populations h with basis rows M (n x n, row-major):
+ * the non-equilibrium part of moment k relaxes at rate s[k] and the
+ * source's moment k (src may be NULL) enters with weight 1 - s[k]/2. */
+static void mrt_update(int n, const double *M, const double *s, const double *h,
+                       const double *heq, const double *src, double *out) {
+  double c[NQ9];
+  for (int k = 0; k < n; ++k) {
+    double neq = 0.0, ms = 0.0, norm = 0.0;
+    for (int a = 0; a < n; ++a) {
+      neq += M[k * n + a] * (h[a] - heq[a]);
+      if (src) ms += M[k * n + a] * src[a];
+      norm += M[k * n + a] * M[k * n + a];
+    }
+    c[k] = (-s[k] * neq + (1.0 - 0.5 * s[k]) * ms) / norm;
+  }
+  for (int a = 0; a < n; ++a) {
+    double d = 0.0;
+    for (int k = 0; k < n; ++k) d += M[k * n + a] * c[k];
+    out[a] = h[a] + d;
+  }
+}
+
 void orc_collide(const orc_params *p, const double *f, const double *gx,
                  const double *gy, double rho, double ux, double uy, double bx,
                  double by, double Fx, double Fy, double *out) {
@@ -545,6 +593,21 @@ void orc_collide(const orc_params *p, const double *f, const double *gx,
   orc_feq(rho, ux, uy, feq);
   orc_source(rho, ux, uy, Fx, Fy, feq, S);
   orc_geq(bx, by, ux, uy, geqx, geqy);
+  if (p->collision == ORC_MRT) {
+    /* f: p_xx and p_xy at s_nu = 1/tau_f (viscosity); e, epsilon, q at their
+     * own rates.  rho and j: their non-equilibrium parts are 0 and -F/2 and
+     * the forced j update is F at any rate, so their rates do not matter;
+     * they take s_nu and s_fq, with which s_fe = s_feps = s_nu is TRT. */
+    const double snu = 1.0 / p->tau_f;
+    const double sf[NQ9] = {snu, p->s_fe, p->s_feps, p->s_fq, p->s_fq, p->s_fq, p->s_fq, snu, snu};
+    mrt_update(NQ9, &MRT9[0][0], sf, f, feq, S, out);
+    /* g: Lambda at 1/tau_m (magnetic diffusivity); epsilon and d at their
+     * own rates; B (no non-equilibrium part) takes s_me. */
+    const double sm[NQ5] = {p->s_me, 1.0 / p->tau_m, 1.0 / p->tau_m, p->s_me, p->s_md};
+    mrt_update(NQ5, &MRT5[0][0], sm, gx, geqx, NULL, out + 9);
+    mrt_update(NQ5, &MRT5[0][0], sm, gy, geqy, NULL, out + 14);
+    return;
+  }
   if (p->collision != ORC_TRT) {
     for (int q = 0; q < NQ9; ++q)
       out[q] = f[q] - (f[q] - feq[q]) / p->tau_f +
@@ -662,4 +725,4 @@ void orc_gather(const orc_params *p, const double *state, int x, int y,
   }
 }
 
-int orc_abi_version(void) { return 2; }
+int orc_abi_version(void) { return 3; }
