@@ -78,9 +78,10 @@ def log(*a):
 # GPU legs
 # ---------------------------------------------------------------------------
 
-def time_channel(torch, Channel, kw, steps, warmup, shape=None):
-    """(wall seconds for `steps`, event seconds per step, channel)."""
-    ch = Channel(**kw)
+def time_channel(torch, Channel, kw, steps, warmup, shape=None, channel=None):
+    """(wall seconds for `steps`, event seconds per step, channel); an open
+    `channel` is timed as it is instead of a new one made from `kw`."""
+    ch = Channel(**kw) if channel is None else channel
     if shape is not None:
         ch.set_launch_shape(shape)
     ch.step(warmup)
@@ -418,6 +419,47 @@ def trt_rates(torch, steps=200, warmup=20):
     return out
 
 
+def mrt_rates(torch, steps=200, warmup=20):
+    """The multiple-relaxation-time collision (default rates: 1.64 and 1.54
+    for f's energy modes, the TRT rates of the magic parameters for the rest)
+    on the headline grid, FP32 and binary16 storage, link and moment walls,
+    from rest and on a developed random state; and steady FP32 Hartmann flow
+    (Ha 5, c 0.5, 64 rows, link walls) against the Chang-Lundgren profile."""
+    import numpy as np
+
+    from paper_2112_13930_amd._lib import derive, make_params
+    from paper_2112_13930_amd.channel import Channel
+    from paper_2112_13930_amd.workloads import random_populations
+    out = {}
+    s0 = torch.from_numpy(random_populations(4096, 4096, seed=5, b0=0.0023))
+    for prec, bpn in (("fp32", 152), ("fp16", 76)):
+        for bc in ("link", "moment"):
+            kw = dict(HEADLINE, precision=prec, bc=bc, collision="mrt")
+            _, per_step, ch = time_channel(torch, Channel, kw, steps, warmup)
+            ch.load_state(s0)
+            _, per_dev, _ = time_channel(torch, Channel, kw, steps, warmup, channel=ch)
+            ch.close()
+            gbs = bpn * 4096 * 4096 / per_step / 1e9
+            out[f"{prec}_{bc}"] = {"mlups": round(4096 * 4096 / per_step / 1e6, 1),
+                                   "frac_hbm": round(gbs / PEAK_HBM_GBS, 3),
+                                   "mlups_developed": round(4096 * 4096 / per_dev / 1e6, 1)}
+    ny, ha, c = 64, 5.0, 0.5
+    kw = dict(bc="link", precision="fp32", tau_f=0.8, tau_m=0.8, ha=ha, u_max=0.02, c_lower=c,
+              c_upper=c, collision="mrt")
+    d = derive(make_params(8, ny, **kw))
+    ch = Channel(8, ny, stream=torch.cuda.Stream(), **kw)
+    ch.set_graph(50)
+    rc, n, res, _ = ch.run_to_steady(tol=1e-10, check_every=1000, max_steps=400_000)
+    ux = ch.moments()["ux"].cpu().numpy()[:, 0]
+    ch.close()
+    xi = (np.arange(ny) + 0.5 - d.a) / d.a
+    ref = d.a * d.a * d.fx / d.nu * chang_lundgren_u(xi, ha, c)
+    out["fp32_hartmann_64_rows_vs_chang_lundgren"] = {
+        "steps": int(n), "status": int(rc),
+        "u_rel_l2_vs_closed_form": float(np.linalg.norm(ux - ref) / np.linalg.norm(ref))}
+    return out
+
+
 def stable_mix(n, seed):
     """Config-4 channel draws, rejecting draws whose imposed field exceeds
     0.1 (Alfven speed near the lattice limit; equivalently a Hartmann layer
@@ -632,6 +674,7 @@ def write_summary(dirs, command):
 
 LEGS = {"developed": developed_state_rate, "sweep": sweep, "precisions": other_precisions,
         "channel_3d": three_d, "duct_3d": duct_3d, "enclosure": enclosure, "trt": trt_rates,
+        "mrt": mrt_rates,
         "cut_walls": cut_walls,
         "batched": lambda torch: batched(torch, "fp32"),
         "serving": serving}
@@ -737,6 +780,8 @@ def main():
         extras["cut_walls"] = cut_walls(torch)
         log("TRT collision ...")
         extras["trt_collision"] = trt_rates(torch)
+        log("MRT collision ...")
+        extras["mrt_collision"] = mrt_rates(torch)
         log("batched ...")
         extras["batched_256_channels"] = batched(torch, "fp32")
         extras["batched_256_channels_fp16"] = batched(torch, "fp16", sequential=False)

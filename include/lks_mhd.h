@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define LKS_MHD_ABI_VERSION 5
+#define LKS_MHD_ABI_VERSION 6
 
 typedef struct lks_mhd lks_mhd_t;             /* one channel, library-owned */
 typedef struct lks_mhd_batch lks_mhd_batch_t; /* many channels, library-owned */
@@ -60,8 +60,21 @@ enum lks_bc { LKS_BC_LINK = 0, LKS_BC_MOMENT = 1 };
  *          lambda_f = (tau_f - 1/2)(tau_f_odd - 1/2),
  *          lambda_m = (tau_m_even - 1/2)(tau_m - 1/2).
  *        lambda_f = 3/16 places half-way bounce-back walls exactly for
- *        Poiseuille flow at every tau_f. */
-enum lks_collision { LKS_BGK = 0, LKS_TRT = 1 };
+ *        Poiseuille flow at every tau_f.
+ *   MRT  multiple relaxation times: populations map to orthogonal moments,
+ *        each of which relaxes at its own rate, the source's moments with
+ *        the weight 1 - s/2 of their rate.  f uses the D2Q9 basis of
+ *        Lallemand and Luo (Phys. Rev. E 61 (2000) 6546): rho, e, epsilon,
+ *        j_x, q_x, j_y, q_y, p_xx, p_xy, with p_xx and p_xy at 1/tau_f
+ *        (viscosity) and e, epsilon, q at s_fe, s_feps, s_fq.  Each
+ *        component of g uses the D2Q5 basis B, Lambda_x, Lambda_y,
+ *        epsilon = (-4, 1, 1, 1, 1) and d = (0, 1, -1, 1, -1) (over the
+ *        rest, +x, +y, -x, -y populations), with Lambda at 1/tau_m (magnetic
+ *        diffusivity) and epsilon, d at s_me, s_md.  With s_fe = s_feps =
+ *        1/tau_f and s_me = s_md it is the TRT operator.  Single channels
+ *        with half-way link or moment walls (not enclosures, walls at cut
+ *        distances, batches or 3D). */
+enum lks_collision { LKS_BGK = 0, LKS_TRT = 1, LKS_MRT = 2 };
 
 /* Storage precision of the populations.
  *   FP64           stored as binary64, computed in FP64, rounded to nearest.
@@ -136,6 +149,11 @@ enum lks_status {
  *               same a as the Hartmann walls; the normal B_x anti-bounces to
  *               zero.  Links crossing a Hartmann wall at a corner take that
  *               wall's closure (with its moving-wall term).
+ *   s_fe,       MRT rates of f's e, epsilon and q moments, finite in (0, 2)
+ *   s_feps,     [1.64, 1.54, NaN]; NaN for s_fq takes TRT's odd rate from
+ *   s_fq        lambda_f.  Ignored under BGK and TRT.
+ *   s_me, s_md  MRT rates of g's epsilon and d moments, finite in (0, 2)
+ *               [NaN, NaN]; NaN takes TRT's even rate from lambda_m.
  *   q_lower,    link scheme: distance of each Hartmann wall from its wall row
  *   q_upper     in (0, 1] [1/2, the paper's half-way wall].  Other values put
  *               the walls q beyond the wall rows, so that the half-width is
@@ -165,6 +183,8 @@ typedef struct {
   double lambda_f, lambda_m;
   double c_x_lower, c_x_upper;
   double q_lower, q_upper;
+  double s_fe, s_feps, s_fq;
+  double s_me, s_md;
 } lks_mhd_params;
 
 /* Lattice quantities derived from a parameter set (host FP64). */
@@ -173,6 +193,8 @@ typedef struct {
   double theta_lower, theta_upper; /* link: theta = c_w a / (tau_m - 1/2), Eq. (weightingfactor) */
   double phi_lower, phi_upper;     /* moment: c_w a / (tau_m cs2m), from Eq. (momentbasedBCslowerboundary) */
   double tau_f_odd, tau_m_even;    /* TRT: 1/2 + lambda / (tau - 1/2); BGK: tau_f, tau_m */
+  double s_fe, s_feps, s_fq;       /* MRT rates in use (NaNs resolved); else the TRT/BGK rates */
+  double s_me, s_md;
 } lks_mhd_derived;
 
 /* ABI version of the loaded library (LKS_MHD_ABI_VERSION). */

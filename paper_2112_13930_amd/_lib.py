@@ -23,8 +23,8 @@ PRECISIONS = {"fp64": LKS_FP64, "fp32": LKS_FP32, "fp16": LKS_FP16_STORE,
               "fp16_f32": LKS_FP16_STORE_F32}
 STORE_BYTES = {"fp64": 8, "fp32": 4, "fp16": 2, "fp16_f32": 2}
 BCS = {"link": LKS_BC_LINK, "moment": LKS_BC_MOMENT}
-LKS_BGK, LKS_TRT = 0, 1
-COLLISIONS = {"bgk": LKS_BGK, "trt": LKS_TRT}
+LKS_BGK, LKS_TRT, LKS_MRT = 0, 1, 2
+COLLISIONS = {"bgk": LKS_BGK, "trt": LKS_TRT, "mrt": LKS_MRT}
 
 
 class LksParams(ctypes.Structure):
@@ -41,6 +41,8 @@ class LksParams(ctypes.Structure):
         ("lambda_f", ctypes.c_double), ("lambda_m", ctypes.c_double),
         ("c_x_lower", ctypes.c_double), ("c_x_upper", ctypes.c_double),
         ("q_lower", ctypes.c_double), ("q_upper", ctypes.c_double),
+        ("s_fe", ctypes.c_double), ("s_feps", ctypes.c_double), ("s_fq", ctypes.c_double),
+        ("s_me", ctypes.c_double), ("s_md", ctypes.c_double),
     ]
 
 
@@ -53,7 +55,8 @@ class LksParams3(ctypes.Structure):
 class LksDerived(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in
                 ("nu", "eta", "a", "b0", "fx", "fy", "theta_lower", "theta_upper",
-                 "phi_lower", "phi_upper", "tau_f_odd", "tau_m_even")]
+                 "phi_lower", "phi_upper", "tau_f_odd", "tau_m_even",
+                 "s_fe", "s_feps", "s_fq", "s_me", "s_md")]
 
 
 class LksError(RuntimeError):
@@ -156,10 +159,12 @@ def check(code: int, what: str = "") -> int:
 def make_params(nx: int, ny: int, *, bc="link", precision="fp32", tau_f=0.8, tau_m=0.8,
                 ha=None, b0=None, c_lower=0.0, c_upper=None, u_lower=0.0, u_upper=0.0,
                 fx=None, fy=0.0, u_max=None, rho0=1.0, collision="bgk", lambda_f=None,
-                lambda_m=None, x_walls=False, c_x=0.0, q=0.5) -> LksParams:
+                lambda_m=None, x_walls=False, c_x=0.0, q=0.5, mrt=None) -> LksParams:
     """Build a parameter struct.  ``ha`` derives B0; ``u_max`` derives F_x;
-    ``collision`` is "bgk" or "trt" (magic parameters ``lambda_f``,
-    ``lambda_m``; the library's defaults when None); ``x_walls`` makes an
+    ``collision`` is "bgk", "trt" or "mrt" (magic parameters ``lambda_f``,
+    ``lambda_m``; the library's defaults when None); ``mrt`` is a dict of
+    MRT rates (``s_fe``, ``s_feps``, ``s_fq``, ``s_me``, ``s_md``) replacing
+    the library's defaults; ``x_walls`` makes an
     enclosure whose x-walls have the conductance ratios ``c_x`` (both) or
     (x = 0 side, x = nx-1 side); ``q`` puts the link-based Hartmann walls at
     that distance from their wall rows (both, or (lower, upper))."""
@@ -192,6 +197,10 @@ def make_params(nx: int, ny: int, *, bc="link", precision="fp32", tau_f=0.8, tau
     p.x_walls = int(bool(x_walls))
     lo, hi = c_x if isinstance(c_x, (tuple, list)) else (c_x, c_x)
     p.c_x_lower, p.c_x_upper = float(lo), float(hi)
+    for name, v in (mrt or {}).items():
+        if name not in ("s_fe", "s_feps", "s_fq", "s_me", "s_md"):
+            raise ValueError(f"unknown MRT rate {name!r}")
+        setattr(p, name, float(v))
     return p
 
 

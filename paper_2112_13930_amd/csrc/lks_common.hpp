@@ -63,6 +63,16 @@ Coef<C> make_coef(const Channel &c) {
   const double fa = 0.5 * (fp + fm), fb = 0.5 * (fp - fm);
   k.trt = Trt<C>{C(fa), C(fb), C(1.0 - 0.5 * fa), C(-0.5 * fb),
                  C(0.5 * (gp + gm)), C(0.5 * (gp - gm)), C(gp)};
+  // MRT coefficients (Mrt<C>): a_k = s_k / |M_k|^2, b_k = (1 - s_k/2) / |M_k|^2
+  {
+    const double snu = 1.0 / c.p.tau_f, sl = 1.0 / c.p.tau_m;
+    auto a = [](double s_, double norm) { return s_ / norm; };
+    auto b = [](double s_, double norm) { return (1.0 - 0.5 * s_) / norm; };
+    k.mrt = Mrt<C>{C(a(c.d.s_fe, 36.0)),   C(b(c.d.s_fe, 36.0)),  C(a(c.d.s_feps, 36.0)),
+                   C(b(c.d.s_feps, 36.0)), C(a(c.d.s_fq, 12.0)),  C(b(c.d.s_fq, 12.0)),
+                   C(a(snu, 4.0)),         C(b(snu, 4.0)),        C(a(sl, 2.0)),
+                   C(a(c.d.s_me, 20.0)),   C(a(c.d.s_md, 4.0))};
+  }
   // enclosure walls: r = (theta-1)/(theta+1), theta = c a / (tau_m - 1/2)
   auto xr = [&](double cw) {
     if (std::isinf(cw)) return 1.0;
@@ -103,6 +113,7 @@ Coef<C> make_coef(const Channel &c) {
 // The kernels' scheme parameter of a channel: wall scheme | collision.
 inline int scheme_of(const lks_mhd_params &p) {
   return (p.bc == LKS_BC_LINK ? BC_LINK : BC_MOMENT) | (p.collision == LKS_TRT ? COLL_TRT : 0) |
+         (p.collision == LKS_MRT ? COLL_MRT : 0) |
          (p.x_walls ? WALLS_X : 0) | ((p.q_lower != 0.5 || p.q_upper != 0.5) ? WALLS_Q : 0);
 }
 

@@ -63,11 +63,14 @@ constexpr int WALLS_Q = 16;
 // other without padding, so cache lines straddle rows, and it inlines every
 // scheme, so code length and divergent branches cost more than elsewhere
 constexpr int IN_BATCH = 32;
+// ... and with COLL_MRT for the multiple-relaxation-time collision
+constexpr int COLL_MRT = 64;
 constexpr int wall_of(int scheme) { return scheme & 3; }
 constexpr bool trt_of(int scheme) { return (scheme & COLL_TRT) != 0; }
 constexpr bool xwalls_of(int scheme) { return (scheme & WALLS_X) != 0; }
 constexpr bool cut_of(int scheme) { return (scheme & WALLS_Q) != 0; }
 constexpr bool in_batch(int scheme) { return (scheme & IN_BATCH) != 0; }
+constexpr bool mrt_of(int scheme) { return (scheme & COLL_MRT) != 0; }
 enum { MODE_STEP = 0, MODE_RECORD = 1, MODE_RESIDUAL = 2, MODE_MOMENTS = 3 };
 
 // Closure coefficients of one wall (computed on the host in FP64).
@@ -95,6 +98,21 @@ template <typename C>
 struct Trt {
   C fa, fb, fsa, fsb;
   C ga, gb, gp;
+};
+
+// Multiple-relaxation-time coefficients (host FP64).  With n = feq - f and
+// S the source per population, moment k of the update is
+//   c_k = (s_k M_k.n + (1 - s_k/2) M_k.S) / |M_k|^2 = a_k M_k.n + b_k M_k.S,
+// and f~ = f + sum_k M_k c_k.  f rows (D2Q9, Lallemand & Luo): e, epsilon,
+// q_x, q_y (rate sq), p_xx, p_xy (rate 1/tau_f); rho and j are not
+// relaxed: their c are 0 and F/6 (sum e n = rho u - m = F/2, so the j
+// update is F at any rate).  g rows (D2Q5, each component): Lambda_x,
+// Lambda_y (rate 1/tau_m), epsilon = (-4,1,1,1,1), d = (0,1,-1,1,-1); B is
+// not relaxed (sum n = 0).
+template <typename C>
+struct Mrt {
+  C ae, be, aeps, beps, aq, bq, anu, bnu; // f
+  C gl, geps, gd;                         // g: a_k (no source)
 };
 
 // A link-based Hartmann wall at a cut distance q (0 < q <= 1) from its
@@ -126,6 +144,7 @@ struct Coef {
   C fex, fey; // external body force
   Wall<C> lo, hi;
   Trt<C> trt; // used by schemes with COLL_TRT
+  Mrt<C> mrt; // used by schemes with COLL_MRT
   C xr_lo, xr_hi; // enclosure walls (WALLS_X): (theta-1)/(theta+1) at x = 0, nx-1
   Cut<C> clo, chi; // Hartmann walls at cut distances (WALLS_Q)
 };
@@ -455,6 +474,63 @@ __device__ __forceinline__ void node_finish(const Geom &g, const Coef<C> &k,
   // carry the flux term.
   const C E3 = C(3) * (ux * by - uy * bx);
   const C W0 = W<C>::W0, W1 = W<C>::W1;
+  if constexpr (mrt_of(BC)) {
+    const Mrt<C> &m = k.mrt;
+    // moments e, epsilon, q_x, q_y, p_xx, p_xy of n = feq - f and of the
+    // source, accumulated population by population (rows of the basis)
+    constexpr int ex9[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1}, ey9[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    constexpr int RE[9] = {-4, -1, -1, -1, -1, 2, 2, 2, 2}, REPS[9] = {4, -2, -2, -2, -2, 1, 1, 1, 1};
+    constexpr int RQX[9] = {0, -2, 0, 2, 0, 1, -1, -1, 1}, RQY[9] = {0, 0, -2, 0, 2, 1, 1, -1, -1};
+    constexpr int RXX[9] = {0, 1, -1, 1, -1, 0, 0, 0, 0}, RXY[9] = {0, 0, 0, 0, 0, 1, -1, 1, -1};
+    C ne = 0, neps = 0, nqx = 0, nqy = 0, npxx = 0, npxy = 0;
+    C se = 0, seps = 0, sqx = 0, sqy = 0, spxx = 0, spxy = 0;
+    auto acc = [](C &a, int r, C v) {
+      if (r == 1) a += v;
+      else if (r == -1) a -= v;
+      else if (r != 0) a += C(r) * v;
+    };
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      const C w = q == 0 ? w0 : (q < 5 ? w1 : w5);
+      const C eu = C(ex9[q]) * ux + C(ey9[q]) * uy;
+      const C poly = C(3) * eu + C(4.5) * eu * eu - usq15;
+      const C n = w * (rhop + rho * poly) - f[q];
+      const C sc = C(3) * w * (C(ex9[q]) * Fx + C(ey9[q]) * Fy - uF) * (C(1) + poly);
+      acc(ne, RE[q], n), acc(neps, REPS[q], n), acc(nqx, RQX[q], n), acc(nqy, RQY[q], n);
+      acc(npxx, RXX[q], n), acc(npxy, RXY[q], n);
+      acc(se, RE[q], sc), acc(seps, REPS[q], sc), acc(sqx, RQX[q], sc), acc(sqy, RQY[q], sc);
+      acc(spxx, RXX[q], sc), acc(spxy, RXY[q], sc);
+    }
+    const C ce = m.ae * ne + m.be * se, ceps = m.aeps * neps + m.beps * seps;
+    const C cqx = m.aq * nqx + m.bq * sqx, cqy = m.aq * nqy + m.bq * sqy;
+    const C cxx = m.anu * npxx + m.bnu * spxx, cxy = m.anu * npxy + m.bnu * spxy;
+    const C cjx = Fx * C(1.0 / 6.0), cjy = Fy * C(1.0 / 6.0);
+    const C axis = -ce - C(2) * ceps, diag = C(2) * ce + ceps;
+    out[0] = put(f[0] + C(4) * (ceps - ce), 0);
+    out[1] = put(f[1] + axis + cjx - C(2) * cqx + cxx, 1);
+    out[2] = put(f[2] + axis + cjy - C(2) * cqy - cxx, 2);
+    out[3] = put(f[3] + axis - cjx + C(2) * cqx + cxx, 3);
+    out[4] = put(f[4] + axis - cjy + C(2) * cqy - cxx, 4);
+    out[5] = put(f[5] + diag + (cjx + cqx) + (cjy + cqy) + cxy, 5);
+    out[6] = put(f[6] + diag - (cjx + cqx) + (cjy + cqy) - cxy, 6);
+    out[7] = put(f[7] + diag - (cjx + cqx) - (cjy + cqy) + cxy, 7);
+    out[8] = put(f[8] + diag + (cjx + cqx) - (cjy + cqy) - cxy, 8);
+    // g, one component at a time: equilibria e0 (rest), e1..e4
+    auto gmrt = [&](C (&h)[5], C e0, C e1, C e2, C e3, C e4, int plane) {
+      const C n0 = e0 - h[0], n1 = e1 - h[1], n2 = e2 - h[2], n3 = e3 - h[3], n4 = e4 - h[4];
+      const C cl_x = m.gl * (n1 - n3), cl_y = m.gl * (n2 - n4);
+      const C ce_ = m.geps * (C(-4) * n0 + n1 + n2 + n3 + n4);
+      const C cd = m.gd * (n1 - n2 + n3 - n4);
+      out[plane] = put(h[0] - C(4) * ce_, plane);
+      out[plane + 1] = put(h[1] + ce_ + cd + cl_x, plane + 1);
+      out[plane + 2] = put(h[2] + ce_ - cd + cl_y, plane + 2);
+      out[plane + 3] = put(h[3] + ce_ + cd - cl_x, plane + 3);
+      out[plane + 4] = put(h[4] + ce_ - cd - cl_y, plane + 4);
+    };
+    gmrt(gx, W0 * bx, W1 * bx, W1 * (bx - E3), W1 * bx, W1 * (bx + E3), 9);
+    gmrt(gy, W0 * byp, W1 * (byp + E3), W1 * byp, W1 * (byp - E3), W1 * byp, 14);
+    return;
+  }
   if constexpr (trt_of(BC)) {
     // pairs (1,3), (2,4), (5,7), (6,8) of D2Q9 and (1,3), (2,4) of D2Q5;
     // stores stay in plane order, so every plane keeps its random word

@@ -62,8 +62,8 @@ int derive_channel(const lks_mhd_params *p, Channel *out) {
   if (!finite(p->u_lower) || !finite(p->u_upper)) return bad("wall velocities must be finite");
   if (!finite(p->rho0) || p->rho0 <= 0.0) return bad("rho0 must be finite and > 0");
   if (!finite(p->fy)) return bad("fy must be finite");
-  if (p->collision != LKS_BGK && p->collision != LKS_TRT)
-    return bad("collision must be LKS_BGK or LKS_TRT");
+  if (p->collision != LKS_BGK && p->collision != LKS_TRT && p->collision != LKS_MRT)
+    return bad("collision must be LKS_BGK, LKS_TRT or LKS_MRT");
   if (p->x_walls != 0 && p->x_walls != 1) return bad("x_walls must be 0 or 1");
   if (p->x_walls) {
     if (p->bc != LKS_BC_LINK) return bad("enclosure walls need link-based closures");
@@ -80,9 +80,16 @@ int derive_channel(const lks_mhd_params *p, Channel *out) {
     if (p->x_walls) return bad("walls at cut distances are not available in enclosures");
     if (p->ny < 3) return bad("walls at cut distances need ny >= 3");
   }
-  if (p->collision == LKS_TRT &&
+  if (p->collision != LKS_BGK &&
       (!finite(p->lambda_f) || p->lambda_f <= 0.0 || !finite(p->lambda_m) || p->lambda_m <= 0.0))
-    return bad("TRT needs finite lambda_f > 0 and lambda_m > 0");
+    return bad("TRT and MRT need finite lambda_f > 0 and lambda_m > 0");
+  if (p->collision == LKS_MRT) {
+    if (p->x_walls || cut) return bad("MRT is available for channels with half-way or moment walls");
+    auto rate_ok = [](double s, bool nan_ok) { return (nan_ok && std::isnan(s)) || (s > 0.0 && s < 2.0); };
+    if (!rate_ok(p->s_fe, false) || !rate_ok(p->s_feps, false) || !rate_ok(p->s_fq, true) ||
+        !rate_ok(p->s_me, true) || !rate_ok(p->s_md, true))
+      return bad("MRT rates must be in (0, 2) (s_fq, s_me, s_md may be NaN)");
+  }
 
   Channel c;
   c.p = *p;
@@ -123,12 +130,24 @@ int derive_channel(const lks_mhd_params *p, Channel *out) {
   }
   // TRT: the free rate of each distribution from its magic parameter
   // Lambda = (tau+ - 1/2)(tau- - 1/2)
-  if (p->collision == LKS_TRT) {
+  if (p->collision != LKS_BGK) {
     d.tau_f_odd = 0.5 + p->lambda_f / (p->tau_f - 0.5);
     d.tau_m_even = 0.5 + p->lambda_m / (p->tau_m - 0.5);
   } else {
     d.tau_f_odd = p->tau_f;
     d.tau_m_even = p->tau_m;
+  }
+  // MRT rates in use; under BGK and TRT the ones those operators amount to
+  if (p->collision == LKS_MRT) {
+    d.s_fe = p->s_fe;
+    d.s_feps = p->s_feps;
+    d.s_fq = std::isnan(p->s_fq) ? 1.0 / d.tau_f_odd : p->s_fq;
+    d.s_me = std::isnan(p->s_me) ? 1.0 / d.tau_m_even : p->s_me;
+    d.s_md = std::isnan(p->s_md) ? 1.0 / d.tau_m_even : p->s_md;
+  } else {
+    d.s_fe = d.s_feps = 1.0 / p->tau_f;
+    d.s_fq = 1.0 / d.tau_f_odd;
+    d.s_me = d.s_md = 1.0 / d.tau_m_even;
   }
   if (out) *out = c;
   return LKS_OK;
@@ -200,6 +219,11 @@ void lks_mhd_default_params(lks_mhd_params *p, int32_t nx, int32_t ny) {
   p->lambda_m = 0.25;
   p->q_lower = 0.5;
   p->q_upper = 0.5;
+  p->s_fe = 1.64;  // Lallemand & Luo (2000)
+  p->s_feps = 1.54;
+  p->s_fq = NAN;
+  p->s_me = NAN;
+  p->s_md = NAN;
 }
 
 int lks_mhd_validate(const lks_mhd_params *p) {

@@ -315,7 +315,8 @@ hipError_t launch_bc(lks_mhd *h, int shape, const void *src, void *dst, ObsOut o
 template <int MODE>
 hipError_t launch_mode(lks_mhd *h, int shape, const void *src, void *dst, ObsOut oo) {
   // observables do not depend on the collision operator (the walls they do)
-  const int sch = MODE == MODE_MOMENTS ? scheme_of(h->ch.p) & ~COLL_TRT : scheme_of(h->ch.p);
+  const int sch =
+      MODE == MODE_MOMENTS ? scheme_of(h->ch.p) & ~(COLL_TRT | COLL_MRT) : scheme_of(h->ch.p);
   constexpr bool kCollide = MODE != MODE_MOMENTS;
   return dispatch_precision(h->ch.p.precision, [&](auto t) -> hipError_t {
     using S = typename decltype(t)::S;
@@ -338,6 +339,12 @@ hipError_t launch_mode(lks_mhd *h, int shape, const void *src, void *dst, ObsOut
     case BC_LINK | COLL_TRT | WALLS_Q:
       if constexpr (kCollide)
         return launch_bc<S, C, BC_LINK | COLL_TRT | WALLS_Q, MODE>(h, shape, src, dst, oo);
+      break;
+    case BC_LINK | COLL_MRT:
+      if constexpr (kCollide) return launch_bc<S, C, BC_LINK | COLL_MRT, MODE>(h, shape, src, dst, oo);
+      break;
+    case BC_MOMENT | COLL_MRT:
+      if constexpr (kCollide) return launch_bc<S, C, BC_MOMENT | COLL_MRT, MODE>(h, shape, src, dst, oo);
       break;
     default: break;
     }

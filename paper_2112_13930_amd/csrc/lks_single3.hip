@@ -237,6 +237,10 @@ int validate3(const lks_mhd3_params *p, Channel *c) {
     set_error("invalid parameters: the three-dimensional walls are half-way (q = 1/2)");
     return LKS_EINVAL;
   }
+  if (p->base.collision == LKS_MRT) {
+    set_error("invalid parameters: the three-dimensional channel collides with BGK or TRT");
+    return LKS_EINVAL;
+  }
   if (p->side_walls != 0 && p->side_walls != 1) {
     set_error("invalid parameters: side_walls must be 0 or 1");
     return LKS_EINVAL;

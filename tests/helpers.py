@@ -17,6 +17,9 @@ def lib_kwargs(p: Params, precision: str) -> dict:
               c_lower=p.c_lo, c_upper=p.c_hi, u_lower=p.u_lo, u_upper=p.u_hi)
     if p.collision == oracle.TRT:
         kw.update(collision="trt", lambda_f=p.extra["lambda_f"], lambda_m=p.extra["lambda_m"])
+    if p.collision == oracle.MRT:
+        kw.update(collision="mrt", mrt=dict(s_fe=p.s_fe, s_feps=p.s_feps, s_fq=p.s_fq,
+                                            s_me=p.s_me, s_md=p.s_md))
     if p.x_walls:
         kw.update(x_walls=True, c_x=(p.cx_lo, p.cx_hi))
     if (p.q_lo, p.q_hi) != (0.5, 0.5):
@@ -32,6 +35,15 @@ def trt(p: Params, lambda_f: float = 3.0 / 16.0, lambda_m: float = 0.25) -> Para
     q = Params(**{**p.__dict__, "collision": oracle.TRT, "tau_fm": tfm, "tau_mp": tmp,
                   "extra": {**p.extra, "lambda_f": lambda_f, "lambda_m": lambda_m}})
     return q
+
+
+def mrt(p: Params, rates=None) -> Params:
+    """The MRT variant of an oracle parameter set, with the given rates
+    (s_fe, s_feps, s_fq, s_me, s_md) or the library's defaults."""
+    from oracle import derive
+    r = derive.mrt_rates(p.tau_f, p.tau_m, 3.0 / 16.0, 0.25) if rates is None else rates
+    return Params(**{**p.__dict__, "collision": oracle.MRT, "s_fe": r[0], "s_feps": r[1],
+                     "s_fq": r[2], "s_me": r[3], "s_md": r[4]})
 
 
 def rel_l2(a, b) -> float:

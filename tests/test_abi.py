@@ -39,7 +39,7 @@ def test_every_declared_symbol_is_exported(L):
 
 
 def test_abi_version(L):
-    assert L.lib().lks_mhd_abi_version() == 5
+    assert L.lib().lks_mhd_abi_version() == 6
 
 
 def _v(L, **kw):
@@ -57,7 +57,11 @@ def _v(L, **kw):
     dict(ha=10.0, b0=0.5),                       # inconsistent
     dict(u_max=0.05, c_lower=0.1, c_upper=0.2),  # fx from u_max needs equal walls
     dict(u_upper=float("inf")), dict(rho0=0.0), dict(precision=7), dict(precision=4),
-    dict(bc=5), dict(collision=2), dict(collision="trt", lambda_f=0.0),
+    dict(bc=5), dict(collision=3), dict(collision="trt", lambda_f=0.0),
+    dict(collision="mrt", mrt=dict(s_fe=2.0)), dict(collision="mrt", mrt=dict(s_feps=0.0)),
+    dict(collision="mrt", mrt=dict(s_fe=float("nan"))), dict(collision="mrt", mrt=dict(s_fq=-0.5)),
+    dict(collision="mrt", mrt=dict(s_md=2.5)), dict(collision="mrt", lambda_m=0.0),
+    dict(collision="mrt", x_walls=True), dict(collision="mrt", q=0.3),
     dict(collision="trt", lambda_m=float("inf")), dict(collision="trt", lambda_m=-1.0),
     dict(x_walls=True, bc="moment"), dict(x_walls=True, nx=1), dict(x_walls=True, c_x=-1.0),
     dict(x_walls=True, c_x=(0.0, float("nan"))),
@@ -81,6 +85,8 @@ def test_validate_rejects(L, kw):
     dict(collision="bgk", lambda_f=float("nan")),  # magic parameters unused under BGK
     dict(x_walls=True), dict(x_walls=True, nx=2, c_x=(0.0, math.inf), collision="trt"),
     dict(q=0.25), dict(q=(1.0, 0.3), c_lower=math.inf), dict(q=0.1, c_lower=0.0, tau_m=0.55),
+    dict(collision="mrt"), dict(collision="mrt", bc="moment", ny=3),
+    dict(collision="mrt", mrt=dict(s_fe=1.9, s_feps=0.3, s_fq=1.99, s_me=0.01, s_md=1.5)),
 ])
 def test_validate_accepts(L, kw):
     rc, p = _v(L, **kw)
@@ -162,6 +168,25 @@ def test_batch_sizing(L):
                                     ctypes.byref(h)) == L.LKS_ENOMEM
 
 
+@pytest.mark.parametrize("tau_f,tau_m,lf,lm", [(0.8, 0.9, 3 / 16, 0.25), (0.55, 1.7, 0.01, 2.0)])
+def test_mrt_rates_agree_with_oracle(L, tau_f, tau_m, lf, lm):
+    """Unset (NaN) MRT rates resolve to TRT's from the magic parameters, as
+    the oracle's mrt_rates gives them; set ones are used as given; BGK and
+    TRT report the rates they amount to."""
+    p = L.make_params(8, 8, tau_f=tau_f, tau_m=tau_m, collision="mrt", lambda_f=lf, lambda_m=lm)
+    d = L.derive(p)
+    assert (d.s_fe, d.s_feps, d.s_fq, d.s_me, d.s_md) == od.mrt_rates(tau_f, tau_m, lf, lm)
+    r = dict(s_fe=1.1, s_feps=1.2, s_fq=1.3, s_me=1.4, s_md=1.5)
+    e = L.derive(L.make_params(8, 8, tau_f=tau_f, tau_m=tau_m, collision="mrt", mrt=r))
+    assert (e.s_fe, e.s_feps, e.s_fq, e.s_me, e.s_md) == tuple(r.values())
+    t = L.derive(L.make_params(8, 8, tau_f=tau_f, tau_m=tau_m, collision="trt", lambda_f=lf,
+                               lambda_m=lm))
+    assert (t.s_fe, t.s_feps, t.s_fq) == (1 / tau_f, 1 / tau_f, 1 / t.tau_f_odd)
+    assert (t.s_me, t.s_md) == (1 / t.tau_m_even, 1 / t.tau_m_even)
+    with pytest.raises(ValueError):
+        L.make_params(8, 8, collision="mrt", mrt=dict(s_nu=1.0))
+
+
 def test_3d_sizing_and_validation(L):
     lib = L.lib()
     p = L.LksParams3()
@@ -183,6 +208,8 @@ def test_3d_sizing_and_validation(L):
     assert lib.lks_mhd3_state_bytes(ctypes.byref(p)) > 0
     p.base = L.make_params(64, 32, precision="fp32", collision="trt", lambda_f=-1.0)
     assert lib.lks_mhd3_state_bytes(ctypes.byref(p)) == 0 and "lambda" in L.last_error()
+    p.base = L.make_params(64, 32, precision="fp32", collision="mrt")
+    assert lib.lks_mhd3_state_bytes(ctypes.byref(p)) == 0 and "BGK or TRT" in L.last_error()
     # ducts: link walls only, nz >= 2, conductances in [0, inf]
     p.base = L.make_params(64, 32, precision="fp32")
     p.nz, p.side_walls, p.c_side_lower, p.c_side_upper = 8, 1, 0.5, math.inf
