@@ -58,21 +58,16 @@ Coef<C> make_coef(const Channel &c) {
   k.hi = Wall<C>{C(hi.r), C(hi.s), C(hi.t), C(hi.u), C(hi.uw6)};
   // TRT pair coefficients (Trt<C>); under BGK they describe the same
   // operator (pb = sb = 0) and go unused
-  const double fp = 1.0 / c.p.tau_f, fm = 1.0 / c.d.tau_f_odd;
-  const double gp = 1.0 / c.d.tau_m_even, gm = 1.0 / c.p.tau_m;
+  // (MRT: the TRT step its corrections start from, odd rate s_fq for f and
+  // even rate s_me for g; under BGK and TRT these are 1/tau_f_odd, 1/tau_m_even)
+  const double fp = 1.0 / c.p.tau_f, fm = c.d.s_fq;
+  const double gp = c.d.s_me, gm = 1.0 / c.p.tau_m;
   const double fa = 0.5 * (fp + fm), fb = 0.5 * (fp - fm);
   k.trt = Trt<C>{C(fa), C(fb), C(1.0 - 0.5 * fa), C(-0.5 * fb),
                  C(0.5 * (gp + gm)), C(0.5 * (gp - gm)), C(gp)};
-  // MRT coefficients (Mrt<C>): a_k = s_k / |M_k|^2, b_k = (1 - s_k/2) / |M_k|^2
-  {
-    const double snu = 1.0 / c.p.tau_f, sl = 1.0 / c.p.tau_m;
-    auto a = [](double s_, double norm) { return s_ / norm; };
-    auto b = [](double s_, double norm) { return (1.0 - 0.5 * s_) / norm; };
-    k.mrt = Mrt<C>{C(a(c.d.s_fe, 36.0)),   C(b(c.d.s_fe, 36.0)),  C(a(c.d.s_feps, 36.0)),
-                   C(b(c.d.s_feps, 36.0)), C(a(c.d.s_fq, 12.0)),  C(b(c.d.s_fq, 12.0)),
-                   C(a(snu, 4.0)),         C(b(snu, 4.0)),        C(a(sl, 2.0)),
-                   C(a(c.d.s_me, 20.0)),   C(a(c.d.s_md, 4.0))};
-  }
+  // MRT corrections on top of that TRT step (Mrt<C>)
+  k.mrt = Mrt<C>{C((c.d.s_fe - fp) / 36.0), C((c.d.s_feps - fp) / 36.0),
+                 C((c.d.s_md - c.d.s_me) / 4.0)};
   // enclosure walls: r = (theta-1)/(theta+1), theta = c a / (tau_m - 1/2)
   auto xr = [&](double cw) {
     if (std::isinf(cw)) return 1.0;

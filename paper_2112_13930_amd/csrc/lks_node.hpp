@@ -100,19 +100,19 @@ struct Trt {
   C ga, gb, gp;
 };
 
-// Multiple-relaxation-time coefficients (host FP64).  With n = feq - f and
-// S the source per population, moment k of the update is
-//   c_k = (s_k M_k.n + (1 - s_k/2) M_k.S) / |M_k|^2 = a_k M_k.n + b_k M_k.S,
-// and f~ = f + sum_k M_k c_k.  f rows (D2Q9, Lallemand & Luo): e, epsilon,
-// q_x, q_y (rate sq), p_xx, p_xy (rate 1/tau_f); rho and j are not
-// relaxed: their c are 0 and F/6 (sum e n = rho u - m = F/2, so the j
-// update is F at any rate).  g rows (D2Q5, each component): Lambda_x,
-// Lambda_y (rate 1/tau_m), epsilon = (-4,1,1,1,1), d = (0,1,-1,1,-1); B is
-// not relaxed (sum n = 0).
+// Multiple-relaxation-time coefficients (host FP64).  MRT differs from the
+// TRT step whose even rates are 1/tau_f (f) and s_me (g) and whose odd
+// rates are s_fq (f) and 1/tau_m (g) only in the rates of f's moments e and
+// epsilon and of g's moment d; with M_k the basis row, n = feq - f and S the
+// source, the difference is
+//   f: M_k (s_k - 1/tau_f) (M_k.n - M_k.S / 2) / |M_k|^2   for k = e, epsilon,
+//   g: M_d (s_md - s_me) M_d.n / |M_d|^2,
+// rows e = (-4, -1 x4, 2 x4), epsilon = (4, -2 x4, 1 x4) over rest, axis and
+// diagonal populations, and d = (0, 1, -1, 1, -1) over D2Q5.
 template <typename C>
 struct Mrt {
-  C ae, be, aeps, beps, aq, bq, anu, bnu; // f
-  C gl, geps, gd;                         // g: a_k (no source)
+  C ke, keps; // (s - 1/tau_f) / 36
+  C kd;       // (s_md - s_me) / 4
 };
 
 // A link-based Hartmann wall at a cut distance q (0 < q <= 1) from its
@@ -263,6 +263,27 @@ __device__ __forceinline__ void collide_f_pair(C &fa, C &fb, C w, C eu, C eF, C 
   const C rb = fb + t.fa * nb + t.fb * na + t.fsa * Sb + t.fsb * Sa;
   fa = ra;
   fb = rb;
+}
+
+// The same, also returning (n_a + n_abar) and (S_a + S_abar), the pair's
+// parts of the even moments e and epsilon (MRT).
+template <typename C>
+__device__ __forceinline__ void collide_f_pair(C &fa, C &fb, C w, C eu, C eF, C rhop, C rho,
+                                               C usq15, C uF, const Trt<C> &t, C &nsum,
+                                               C &ssum) {
+  const C even = C(4.5) * eu * eu - usq15;
+  const C odd = C(3) * eu;
+  const C pa = even + odd, pb = even - odd;
+  const C na = w * (rhop + rho * pa) - fa;
+  const C nb = w * (rhop + rho * pb) - fb;
+  const C Sa = C(3) * w * (eF - uF) * (C(1) + pa);
+  const C Sb = C(3) * w * (-eF - uF) * (C(1) + pb);
+  const C ra = fa + t.fa * na + t.fb * nb + t.fsa * Sa + t.fsb * Sb;
+  const C rb = fb + t.fa * nb + t.fb * na + t.fsa * Sb + t.fsb * Sa;
+  fa = ra;
+  fb = rb;
+  nsum = na + nb;
+  ssum = Sa + Sb;
 }
 
 // Two-relaxation-time update of a pair of opposite g populations with
@@ -474,78 +495,43 @@ __device__ __forceinline__ void node_finish(const Geom &g, const Coef<C> &k,
   // carry the flux term.
   const C E3 = C(3) * (ux * by - uy * bx);
   const C W0 = W<C>::W0, W1 = W<C>::W1;
-  if constexpr (mrt_of(BC)) {
-    const Mrt<C> &m = k.mrt;
-    // moments e, epsilon, q_x, q_y, p_xx, p_xy of n = feq - f and of the
-    // source, accumulated population by population (rows of the basis)
-    constexpr int ex9[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1}, ey9[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
-    constexpr int RE[9] = {-4, -1, -1, -1, -1, 2, 2, 2, 2}, REPS[9] = {4, -2, -2, -2, -2, 1, 1, 1, 1};
-    constexpr int RQX[9] = {0, -2, 0, 2, 0, 1, -1, -1, 1}, RQY[9] = {0, 0, -2, 0, 2, 1, 1, -1, -1};
-    constexpr int RXX[9] = {0, 1, -1, 1, -1, 0, 0, 0, 0}, RXY[9] = {0, 0, 0, 0, 0, 1, -1, 1, -1};
-    C ne = 0, neps = 0, nqx = 0, nqy = 0, npxx = 0, npxy = 0;
-    C se = 0, seps = 0, sqx = 0, sqy = 0, spxx = 0, spxy = 0;
-    auto acc = [](C &a, int r, C v) {
-      if (r == 1) a += v;
-      else if (r == -1) a -= v;
-      else if (r != 0) a += C(r) * v;
-    };
-#pragma unroll
-    for (int q = 0; q < 9; ++q) {
-      const C w = q == 0 ? w0 : (q < 5 ? w1 : w5);
-      const C eu = C(ex9[q]) * ux + C(ey9[q]) * uy;
-      const C poly = C(3) * eu + C(4.5) * eu * eu - usq15;
-      const C n = w * (rhop + rho * poly) - f[q];
-      const C sc = C(3) * w * (C(ex9[q]) * Fx + C(ey9[q]) * Fy - uF) * (C(1) + poly);
-      acc(ne, RE[q], n), acc(neps, REPS[q], n), acc(nqx, RQX[q], n), acc(nqy, RQY[q], n);
-      acc(npxx, RXX[q], n), acc(npxy, RXY[q], n);
-      acc(se, RE[q], sc), acc(seps, REPS[q], sc), acc(sqx, RQX[q], sc), acc(sqy, RQY[q], sc);
-      acc(spxx, RXX[q], sc), acc(spxy, RXY[q], sc);
-    }
-    const C ce = m.ae * ne + m.be * se, ceps = m.aeps * neps + m.beps * seps;
-    const C cqx = m.aq * nqx + m.bq * sqx, cqy = m.aq * nqy + m.bq * sqy;
-    const C cxx = m.anu * npxx + m.bnu * spxx, cxy = m.anu * npxy + m.bnu * spxy;
-    const C cjx = Fx * C(1.0 / 6.0), cjy = Fy * C(1.0 / 6.0);
-    const C axis = -ce - C(2) * ceps, diag = C(2) * ce + ceps;
-    out[0] = put(f[0] + C(4) * (ceps - ce), 0);
-    out[1] = put(f[1] + axis + cjx - C(2) * cqx + cxx, 1);
-    out[2] = put(f[2] + axis + cjy - C(2) * cqy - cxx, 2);
-    out[3] = put(f[3] + axis - cjx + C(2) * cqx + cxx, 3);
-    out[4] = put(f[4] + axis - cjy + C(2) * cqy - cxx, 4);
-    out[5] = put(f[5] + diag + (cjx + cqx) + (cjy + cqy) + cxy, 5);
-    out[6] = put(f[6] + diag - (cjx + cqx) + (cjy + cqy) - cxy, 6);
-    out[7] = put(f[7] + diag - (cjx + cqx) - (cjy + cqy) + cxy, 7);
-    out[8] = put(f[8] + diag + (cjx + cqx) - (cjy + cqy) - cxy, 8);
-    // g, one component at a time: equilibria e0 (rest), e1..e4
-    auto gmrt = [&](C (&h)[5], C e0, C e1, C e2, C e3, C e4, int plane) {
-      const C n0 = e0 - h[0], n1 = e1 - h[1], n2 = e2 - h[2], n3 = e3 - h[3], n4 = e4 - h[4];
-      const C cl_x = m.gl * (n1 - n3), cl_y = m.gl * (n2 - n4);
-      const C ce_ = m.geps * (C(-4) * n0 + n1 + n2 + n3 + n4);
-      const C cd = m.gd * (n1 - n2 + n3 - n4);
-      out[plane] = put(h[0] - C(4) * ce_, plane);
-      out[plane + 1] = put(h[1] + ce_ + cd + cl_x, plane + 1);
-      out[plane + 2] = put(h[2] + ce_ - cd + cl_y, plane + 2);
-      out[plane + 3] = put(h[3] + ce_ + cd - cl_x, plane + 3);
-      out[plane + 4] = put(h[4] + ce_ - cd - cl_y, plane + 4);
-    };
-    gmrt(gx, W0 * bx, W1 * bx, W1 * (bx - E3), W1 * bx, W1 * (bx + E3), 9);
-    gmrt(gy, W0 * byp, W1 * (byp + E3), W1 * byp, W1 * (byp - E3), W1 * byp, 14);
-    return;
-  }
-  if constexpr (trt_of(BC)) {
+  if constexpr (trt_of(BC) || mrt_of(BC)) {
     // pairs (1,3), (2,4), (5,7), (6,8) of D2Q9 and (1,3), (2,4) of D2Q5;
-    // stores stay in plane order, so every plane keeps its random word
+    // stores stay in plane order, so every plane keeps its random word.
+    // MRT: the TRT step, then the corrections of e, epsilon and d (Mrt).
     const Trt<C> &t = k.trt;
+    const C n0 = w0 * (rhop - rho * usq15) - f[0];
+    const C s0 = C(3) * w0 * (-uF) * (C(1) - usq15);
     f[0] = collide_f(f[0], w0, C(0), C(0), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka);
-    collide_f_pair(f[1], f[3], w1, ux, Fx, rhop, rho, usq15, uF, t);
-    collide_f_pair(f[2], f[4], w1, uy, Fy, rhop, rho, usq15, uF, t);
-    collide_f_pair(f[5], f[7], w5, ux + uy, Fx + Fy, rhop, rho, usq15, uF, t);
-    collide_f_pair(f[6], f[8], w5, uy - ux, Fy - Fx, rhop, rho, usq15, uF, t);
+    C nx_, sx_, ny_, sy_, nd1, sd1, nd2, sd2;
+    collide_f_pair(f[1], f[3], w1, ux, Fx, rhop, rho, usq15, uF, t, nx_, sx_);
+    collide_f_pair(f[2], f[4], w1, uy, Fy, rhop, rho, usq15, uF, t, ny_, sy_);
+    collide_f_pair(f[5], f[7], w5, ux + uy, Fx + Fy, rhop, rho, usq15, uF, t, nd1, sd1);
+    collide_f_pair(f[6], f[8], w5, uy - ux, Fy - Fx, rhop, rho, usq15, uF, t, nd2, sd2);
+    C gdx = C(0), gdy = C(0);
+    if constexpr (mrt_of(BC)) {
+      const Mrt<C> &m = k.mrt;
+      const C na = nx_ + ny_, nd = nd1 + nd2, sa = sx_ + sy_, sd = sd1 + sd2;
+      const C de = m.ke * ((C(-4) * n0 - na + C(2) * nd) - C(0.5) * (C(-4) * s0 - sa + C(2) * sd));
+      const C dp = m.keps * ((C(4) * n0 - C(2) * na + nd) - C(0.5) * (C(4) * s0 - C(2) * sa + sd));
+      f[0] += C(4) * (dp - de);
+      const C dax = -de - C(2) * dp, ddg = C(2) * de + dp;
+      f[1] += dax, f[2] += dax, f[3] += dax, f[4] += dax;
+      f[5] += ddg, f[6] += ddg, f[7] += ddg, f[8] += ddg;
+      // d = (g1 + g3) - (g2 + g4) of n = geq - g, before the update
+      gdx = m.kd * ((C(2) * W1 * bx - gx[1] - gx[3]) - (C(2) * W1 * bx - gx[2] - gx[4]));
+      gdy = m.kd * ((C(2) * W1 * byp - gy[1] - gy[3]) - (C(2) * W1 * byp - gy[2] - gy[4]));
+    }
     gx[0] += t.gp * (W0 * bx - gx[0]);
     collide_g_pair(gx[1], gx[3], W1 * bx, W1 * bx, t);
     collide_g_pair(gx[2], gx[4], W1 * (bx - E3), W1 * (bx + E3), t);
     gy[0] += t.gp * (W0 * byp - gy[0]);
     collide_g_pair(gy[1], gy[3], W1 * (byp + E3), W1 * (byp - E3), t);
     collide_g_pair(gy[2], gy[4], W1 * byp, W1 * byp, t);
+    if constexpr (mrt_of(BC)) {
+      gx[1] += gdx, gx[3] += gdx, gx[2] -= gdx, gx[4] -= gdx;
+      gy[1] += gdy, gy[3] += gdy, gy[2] -= gdy, gy[4] -= gdy;
+    }
 #pragma unroll
     for (int q = 0; q < 9; ++q) out[q] = put(f[q], q);
 #pragma unroll
