@@ -7,9 +7,9 @@
 // the spacing for a full word; the kernels pass 16 random bits, 2^-16).  It is computed by
 // adding uniform random bits below the target's last place to the magnitude
 // bits of v and truncating there (a carry out of the kept bits rounds up,
-// across a binade too), or, from binary64 to binary16, as g floor(v/g + u)
-// with the target spacing g.  Values beyond the target's range become
-// infinite (and are reported as non-finite by the residual check).
+// across a binade too); binary64 reaches binary16 through the nearest
+// binary32.  Values beyond the target's range become infinite (and are
+// reported as non-finite by the residual check).
 //
 // Random bits: one hashed seed per node and step (counter-based, so a run is
 // reproducible bit for bit and independent of launch shape or batch mix),
@@ -85,6 +85,11 @@ LKS_HD inline float sr_f32(double v, uint32_t r) {
 // added below binary16's last place and truncated.
 LKS_HD inline _Float16 sr_f16(float v, uint32_t r) {
   const uint32_t b = bits32(v);
+  // |v| >= 2^-14 (binary16's normal range and above): binary16's last place
+  // is 13 bits above binary32's; adding to the magnitude bits of b leaves its
+  // sign alone.  Zeros come out unchanged the same way.
+  const uint32_t m = b & 0x7FFFFFFFu;
+  if (m >= 0x38800000u || m == 0u) return (_Float16)flt((b + (r >> 19)) & ~0x1FFFu);
   const uint32_t sign = b & 0x80000000u;
   const uint32_t mag = b ^ sign;
   const int e = (int)(mag >> 23) - 127;
