@@ -71,9 +71,10 @@ enum lks_bc { LKS_BC_LINK = 0, LKS_BC_MOMENT = 1 };
  *        epsilon = (-4, 1, 1, 1, 1) and d = (0, 1, -1, 1, -1) (over the
  *        rest, +x, +y, -x, -y populations), with Lambda at 1/tau_m (magnetic
  *        diffusivity) and epsilon, d at s_me, s_md.  With s_fe = s_feps =
- *        1/tau_f and s_me = s_md it is the TRT operator.  Single channels
- *        with half-way link or moment walls (not enclosures, walls at cut
- *        distances, batches or 3D). */
+ *        1/tau_f and s_me = s_md it is the TRT operator.  Channels and
+ *        batched channels with half-way link or moment walls (not
+ *        enclosures, walls at cut distances, 3D, or batches of
+ *        LKS_FP16_STORE_F32). */
 enum lks_collision { LKS_BGK = 0, LKS_TRT = 1, LKS_MRT = 2 };
 
 /* Storage precision of the populations.

@@ -68,6 +68,7 @@ Coef<C> make_coef(const Channel &c) {
   // MRT corrections on top of that TRT step (Mrt<C>)
   k.mrt = Mrt<C>{C((c.d.s_fe - fp) / 36.0), C((c.d.s_feps - fp) / 36.0),
                  C((c.d.s_md - c.d.s_me) / 4.0)};
+  k.mrt_on = c.p.collision == LKS_MRT ? 1 : 0;
   // enclosure walls: r = (theta-1)/(theta+1), theta = c a / (tau_m - 1/2)
   auto xr = [&](double cw) {
     if (std::isinf(cw)) return 1.0;

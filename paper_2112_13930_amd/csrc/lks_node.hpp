@@ -65,12 +65,17 @@ constexpr int WALLS_Q = 16;
 constexpr int IN_BATCH = 32;
 // ... and with COLL_MRT for the multiple-relaxation-time collision
 constexpr int COLL_MRT = 64;
+// ... and, with COLL_TRT, MRT_RT where the MRT corrections are applied when
+// the coefficients ask for them (Coef::mrt_on): the batched kernel runs TRT
+// and MRT channels through one inlined scheme
+constexpr int MRT_RT = 128;
 constexpr int wall_of(int scheme) { return scheme & 3; }
 constexpr bool trt_of(int scheme) { return (scheme & COLL_TRT) != 0; }
 constexpr bool xwalls_of(int scheme) { return (scheme & WALLS_X) != 0; }
 constexpr bool cut_of(int scheme) { return (scheme & WALLS_Q) != 0; }
 constexpr bool in_batch(int scheme) { return (scheme & IN_BATCH) != 0; }
 constexpr bool mrt_of(int scheme) { return (scheme & COLL_MRT) != 0; }
+constexpr bool mrt_rt_of(int scheme) { return (scheme & MRT_RT) != 0; }
 enum { MODE_STEP = 0, MODE_RECORD = 1, MODE_RESIDUAL = 2, MODE_MOMENTS = 3 };
 
 // Closure coefficients of one wall (computed on the host in FP64).
@@ -144,7 +149,8 @@ struct Coef {
   C fex, fey; // external body force
   Wall<C> lo, hi;
   Trt<C> trt; // used by schemes with COLL_TRT
-  Mrt<C> mrt; // used by schemes with COLL_MRT
+  Mrt<C> mrt; // used by schemes with COLL_MRT, or MRT_RT when mrt_on
+  int mrt_on; // 1 for an MRT channel
   C xr_lo, xr_hi; // enclosure walls (WALLS_X): (theta-1)/(theta+1) at x = 0, nx-1
   Cut<C> clo, chi; // Hartmann walls at cut distances (WALLS_Q)
 };
@@ -265,12 +271,11 @@ __device__ __forceinline__ void collide_f_pair(C &fa, C &fb, C w, C eu, C eF, C 
   fb = rb;
 }
 
-// The same, also returning (n_a + n_abar) and (S_a + S_abar), the pair's
-// parts of the even moments e and epsilon (MRT).
+// The same, also returning (n_a + n_abar) - (S_a + S_abar)/2, the pair's
+// part of what the MRT corrections of the even moments e and epsilon act on.
 template <typename C>
 __device__ __forceinline__ void collide_f_pair(C &fa, C &fb, C w, C eu, C eF, C rhop, C rho,
-                                               C usq15, C uF, const Trt<C> &t, C &nsum,
-                                               C &ssum) {
+                                               C usq15, C uF, const Trt<C> &t, C &tsum) {
   const C even = C(4.5) * eu * eu - usq15;
   const C odd = C(3) * eu;
   const C pa = even + odd, pb = even - odd;
@@ -282,8 +287,7 @@ __device__ __forceinline__ void collide_f_pair(C &fa, C &fb, C w, C eu, C eF, C 
   const C rb = fb + t.fa * nb + t.fb * na + t.fsa * Sb + t.fsb * Sa;
   fa = ra;
   fb = rb;
-  nsum = na + nb;
-  ssum = Sa + Sb;
+  tsum = (na + nb) - C(0.5) * (Sa + Sb);
 }
 
 // Two-relaxation-time update of a pair of opposite g populations with
@@ -500,24 +504,33 @@ __device__ __forceinline__ void node_finish(const Geom &g, const Coef<C> &k,
     // stores stay in plane order, so every plane keeps its random word.
     // MRT: the TRT step, then the corrections of e, epsilon and d (Mrt).
     const Trt<C> &t = k.trt;
-    const C n0 = w0 * (rhop - rho * usq15) - f[0];
-    const C s0 = C(3) * w0 * (-uF) * (C(1) - usq15);
+    // MRT: te, tp = the e and epsilon moments of n - S/2 (rows (-4, -1 x4,
+    // 2 x4) and (4, -2 x4, 1 x4)), accumulated pair by pair
+    constexpr bool kMrt = mrt_of(BC) || mrt_rt_of(BC);
+    const bool mrt_now = mrt_of(BC) || (mrt_rt_of(BC) && k.mrt_on != 0);
+    const C t0 = (w0 * (rhop - rho * usq15) - f[0]) - C(0.5) * (C(3) * w0 * (-uF) * (C(1) - usq15));
+    C te = C(-4) * t0, tp = C(4) * t0, tq;
     f[0] = collide_f(f[0], w0, C(0), C(0), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka);
-    C nx_, sx_, ny_, sy_, nd1, sd1, nd2, sd2;
-    collide_f_pair(f[1], f[3], w1, ux, Fx, rhop, rho, usq15, uF, t, nx_, sx_);
-    collide_f_pair(f[2], f[4], w1, uy, Fy, rhop, rho, usq15, uF, t, ny_, sy_);
-    collide_f_pair(f[5], f[7], w5, ux + uy, Fx + Fy, rhop, rho, usq15, uF, t, nd1, sd1);
-    collide_f_pair(f[6], f[8], w5, uy - ux, Fy - Fx, rhop, rho, usq15, uF, t, nd2, sd2);
+    collide_f_pair(f[1], f[3], w1, ux, Fx, rhop, rho, usq15, uF, t, tq);
+    te -= tq, tp -= C(2) * tq;
+    collide_f_pair(f[2], f[4], w1, uy, Fy, rhop, rho, usq15, uF, t, tq);
+    te -= tq, tp -= C(2) * tq;
+    collide_f_pair(f[5], f[7], w5, ux + uy, Fx + Fy, rhop, rho, usq15, uF, t, tq);
+    te += C(2) * tq, tp += tq;
+    collide_f_pair(f[6], f[8], w5, uy - ux, Fy - Fx, rhop, rho, usq15, uF, t, tq);
+    te += C(2) * tq, tp += tq;
+    // (selects rather than a branch where the flag is a run-time value: the
+    // branch cost the batched kernel 20 registers)
     C gdx = C(0), gdy = C(0);
-    if constexpr (mrt_of(BC)) {
+    if constexpr (kMrt) {
       const Mrt<C> &m = k.mrt;
-      const C na = nx_ + ny_, nd = nd1 + nd2, sa = sx_ + sy_, sd = sd1 + sd2;
-      const C de = m.ke * ((C(-4) * n0 - na + C(2) * nd) - C(0.5) * (C(-4) * s0 - sa + C(2) * sd));
-      const C dp = m.keps * ((C(4) * n0 - C(2) * na + nd) - C(0.5) * (C(4) * s0 - C(2) * sa + sd));
-      f[0] += C(4) * (dp - de);
-      const C dax = -de - C(2) * dp, ddg = C(2) * de + dp;
-      f[1] += dax, f[2] += dax, f[3] += dax, f[4] += dax;
-      f[5] += ddg, f[6] += ddg, f[7] += ddg, f[8] += ddg;
+      const C de = m.ke * te, dp = m.keps * tp;
+      const C d0 = C(4) * (dp - de), dax = -de - C(2) * dp, ddg = C(2) * de + dp;
+      f[0] = mrt_now ? f[0] + d0 : f[0];
+#pragma unroll
+      for (int q = 1; q < 5; ++q) f[q] = mrt_now ? f[q] + dax : f[q];
+#pragma unroll
+      for (int q = 5; q < 9; ++q) f[q] = mrt_now ? f[q] + ddg : f[q];
       // d = (g1 + g3) - (g2 + g4) of n = geq - g, before the update
       gdx = m.kd * ((C(2) * W1 * bx - gx[1] - gx[3]) - (C(2) * W1 * bx - gx[2] - gx[4]));
       gdy = m.kd * ((C(2) * W1 * byp - gy[1] - gy[3]) - (C(2) * W1 * byp - gy[2] - gy[4]));
@@ -528,9 +541,11 @@ __device__ __forceinline__ void node_finish(const Geom &g, const Coef<C> &k,
     gy[0] += t.gp * (W0 * byp - gy[0]);
     collide_g_pair(gy[1], gy[3], W1 * (byp + E3), W1 * (byp - E3), t);
     collide_g_pair(gy[2], gy[4], W1 * byp, W1 * byp, t);
-    if constexpr (mrt_of(BC)) {
-      gx[1] += gdx, gx[3] += gdx, gx[2] -= gdx, gx[4] -= gdx;
-      gy[1] += gdy, gy[3] += gdy, gy[2] -= gdy, gy[4] -= gdy;
+    if constexpr (kMrt) {
+      gx[1] = mrt_now ? gx[1] + gdx : gx[1], gx[3] = mrt_now ? gx[3] + gdx : gx[3];
+      gx[2] = mrt_now ? gx[2] - gdx : gx[2], gx[4] = mrt_now ? gx[4] - gdx : gx[4];
+      gy[1] = mrt_now ? gy[1] + gdy : gy[1], gy[3] = mrt_now ? gy[3] + gdy : gy[3];
+      gy[2] = mrt_now ? gy[2] - gdy : gy[2], gy[4] = mrt_now ? gy[4] - gdy : gy[4];
     }
 #pragma unroll
     for (int q = 0; q < 9; ++q) out[q] = put(f[q], q);

@@ -110,10 +110,39 @@ def test_mrt_run_to_steady_matches_oracle_residual(P):
     assert abs(res - r) < 1e-3 * r, (res, r)
 
 
-def test_batches_reject_mrt(P):
+@pytest.mark.parametrize("precision", ["fp32", "fp16", "fp64"])
+def test_mrt_trt_and_bgk_channels_in_one_batch_equal_solo_runs(P, precision):
+    """The batched kernel runs MRT channels through its TRT scheme with the
+    corrections switched on per channel: every channel of a mixed batch
+    equals its solo run bit for bit."""
+    from paper_2112_13930_amd._lib import make_params
+    from paper_2112_13930_amd.batch import Batch
+    from paper_2112_13930_amd.channel import Channel
+    from tests.helpers import trt
+    base = [Params(nx=33, ny=20, bc=LINK, tau_f=0.75, tau_m=0.85, b0=0.03, fx=1e-4,
+                   c_lo=0.5, c_hi=0.5),
+            Params(nx=70, ny=9, bc=MOMENT, tau_f=0.75, tau_m=0.85, b0=0.02, c_lo=0.0,
+                   c_hi=math.inf, u_hi=0.05)]
+    chans = [mrt(base[0]), base[0], trt(base[0]), mrt(base[1], OTHER), trt(base[1]), base[1],
+             mrt(base[0], OTHER)]
+    b = Batch(precision, max_channels=8, max_nodes=50_000)
+    slots = [b.admit(make_params(c.nx, c.ny, **lib_kwargs(c, precision))) for c in chans]
+    b.step(12, graph=True)
+    b.step(1, graph=False)
+    torch.cuda.synchronize()
+    for s, c in zip(slots, chans):
+        solo = Channel(c.nx, c.ny, **lib_kwargs(c, precision))
+        solo.set_rebase(0)
+        solo.step(13)
+        assert torch.equal(b.save_state(s).cpu(), solo.save_state().cpu()), c
+    b.close()
+
+
+def test_binary16_fp32_arithmetic_batches_reject_mrt(P):
     from paper_2112_13930_amd._lib import LksError, make_params
     from paper_2112_13930_amd.batch import Batch
-    b = Batch("fp32", max_channels=4, max_nodes=10_000)
+    b = Batch("fp16_f32", max_channels=4, max_nodes=10_000)
     with pytest.raises(LksError):
-        b.admit(make_params(16, 16, precision="fp32", collision="mrt"))
+        b.admit(make_params(16, 16, precision="fp16_f32", collision="mrt"))
+    b.admit(make_params(16, 16, precision="fp16_f32", collision="trt"))
     b.close()
