@@ -181,6 +181,12 @@ def three_d(torch, n=256, steps=200, warmup=10):
     ch.close()
     out["fp32_trt"] = {"mlups_from_rest": round(r / 1e6, 1),
                        "frac_hbm_from_rest": round(296 * r / 1e9 / PEAK_HBM_GBS, 3)}
+    # the multiple-relaxation-time collision (default rates), FP32, from rest
+    ch = Channel3(n, n, n, precision="fp32", collision="mrt", stream=torch.cuda.Stream(), **kw)
+    r = rate(ch)
+    ch.close()
+    out["fp32_mrt"] = {"mlups_from_rest": round(r / 1e6, 1),
+                       "frac_hbm_from_rest": round(296 * r / 1e9 / PEAK_HBM_GBS, 3)}
     # the measured FP32 workload after 1000 steps from rest against the 2D
     # oracle's columns (stored by tests/golden/make_golden.py)
     gold_path = os.path.join(ROOT, "tests", "golden", "couette_256_link_1000.json")

@@ -24,7 +24,7 @@ SRC = os.path.join(HERE, "lks_oracle3.c")
 LIB = os.path.join(HERE, "liblks_oracle3.so")
 
 LINK, MOMENT = 0, 1
-BGK, TRT = 0, 1
+BGK, TRT, MRT = 0, 1, 2
 NPLANES = 40
 NF, NG = 19, 7
 
@@ -52,6 +52,8 @@ class _Params3(ctypes.Structure):
         ("tau_fm", ctypes.c_double), ("tau_mp", ctypes.c_double),
         ("side_walls", ctypes.c_int32), ("pad2_", ctypes.c_int32),
         ("cs_lo", ctypes.c_double), ("cs_hi", ctypes.c_double),
+        ("s_fe", ctypes.c_double), ("s_feps", ctypes.c_double), ("s_fq", ctypes.c_double),
+        ("s_md", ctypes.c_double),
     ]
 
 
@@ -115,6 +117,10 @@ class Params3:
     side_walls: bool = False   # duct: stationary Shercliff walls bound z
     cs_lo: float = 0.0         # their conductance ratios (z = 0 side, z = nz-1 side)
     cs_hi: float = 0.0
+    s_fe: float = float("nan")     # MRT (collision == MRT): e at s_fe, epsilon and pi at
+    s_feps: float = float("nan")   # s_feps, q and m at s_fq; g's traceless second moments
+    s_fq: float = float("nan")     # at s_md
+    s_md: float = float("nan")
 
     def half_width(self) -> float:
         if self.a is not None:
@@ -124,12 +130,16 @@ class Params3:
     def c_struct(self) -> _Params3:
         if self.collision == TRT:
             assert self.tau_fm > 0.5 and self.tau_mp > 0.5, "TRT needs tau_fm and tau_mp > 1/2"
+        if self.collision == MRT:
+            assert all(0 < r < 2 for r in (self.s_fe, self.s_feps, self.s_fq, self.s_md)), \
+                "MRT needs rates in (0, 2)"
         if self.side_walls:
             assert self.bc == LINK and self.nz >= 2, "side walls need link-based closures"
         return _Params3(self.nx, self.ny, self.nz, self.bc, self.tau_f, self.tau_m, self.b0,
                         self.fx, self.fy, self.fz, self.c_lo, self.c_hi, self.u_lo, self.u_hi,
                         self.half_width(), self.collision, 0, self.tau_fm, self.tau_mp,
-                        int(self.side_walls), 0, self.cs_lo, self.cs_hi)
+                        int(self.side_walls), 0, self.cs_lo, self.cs_hi, self.s_fe,
+                        self.s_feps, self.s_fq, self.s_md)
 
     @classmethod
     def from_2d(cls, p, nz: int) -> "Params3":
@@ -138,7 +148,7 @@ class Params3:
         return cls(nx=p.nx, ny=p.ny, nz=nz, bc=p.bc, tau_f=p.tau_f, tau_m=p.tau_m, b0=p.b0,
                    fx=p.fx, fy=p.fy, fz=0.0, c_lo=p.c_lo, c_hi=p.c_hi, u_lo=p.u_lo,
                    u_hi=p.u_hi, a=p.half_width(), collision=p.collision, tau_fm=p.tau_fm,
-                   tau_mp=p.tau_mp)
+                   tau_mp=p.tau_mp, s_fe=p.s_fe, s_feps=p.s_feps, s_fq=p.s_fq, s_md=p.s_md)
 
 
 def init_state(p: Params3, rho0: float = 1.0) -> np.ndarray:

@@ -69,7 +69,7 @@ enum { O3_LOWER = 0, O3_UPPER = 1 };
 /* Collision: BGK, or two relaxation times with tau_f on the even part of f
  * (viscosity) and tau_m on the odd part of g (magnetic diffusivity); tau_fm
  * and tau_mp are the free times of the other parts. */
-enum { O3_BGK = 0, O3_TRT = 1 };
+enum { O3_BGK = 0, O3_TRT = 1, O3_MRT = 2 };
 
 typedef struct {
   int32_t nx, ny, nz, bc;
@@ -84,6 +84,8 @@ typedef struct {
   double tau_mp;     /* TRT: even part of g */
   int32_t side_walls, pad2_; /* 1: stationary Shercliff walls at z = -1/2 and nz - 1/2 */
   double cs_lo, cs_hi;       /* their wall conductance ratios (0 .. INFINITY) */
+  double s_fe, s_feps, s_fq; /* MRT rates of f's e, epsilon (and pi), q (and m) moments */
+  double s_md;               /* MRT rate of g's two traceless second moments */
 } orc3_params;
 
 static int opp3(int q) {
@@ -431,13 +433,97 @@ static void gather3(const orc3_params *p, const double *in, int x, int y, int z,
  * post-closure, with the fields of the solve; out receives the 40 planes
  * (f, then g per component).  BGK as in Sec. V; TRT relaxes the parts even
  * and odd under e -> -e at their own rates, the source's parts with the
- * matching weights 1 - 1/(2 tau). */
+ * matching weights 1 - 1/(2 tau); MRT relaxes the moments of the bases above
+ * at their own rates. */
+/* MRT rows.  f (D3Q19, d'Humieres, Ginzburg, Krafczyk, Lallemand and Luo,
+ * Phil. Trans. R. Soc. A 360 (2002) 437), as functions of e: rho = 1,
+ * e = 19|e|^2 - 30, epsilon = (21|e|^4 - 53|e|^2 + 24)/2, j_i = e_i,
+ * q_i = (5|e|^2 - 9) e_i, 3p_xx = 3e_x^2 - |e|^2, 3pi_xx = (3|e|^2 - 5)(3e_x^2 -
+ * |e|^2), p_ww = e_y^2 - e_z^2, pi_ww = (3|e|^2 - 5)(e_y^2 - e_z^2), p_xy =
+ * e_x e_y, p_yz, p_xz, m_x = (e_y^2 - e_z^2) e_x, m_y = (e_z^2 - e_x^2) e_y,
+ * m_z = (e_x^2 - e_y^2) e_z.  Rates: the five stresses at 1/tau_f; e at
+ * s_fe; epsilon and the fourth-order pi at s_feps; q and the third-order m
+ * at s_fq; rho and j (which do not matter) at 1/tau_f and s_fq.
+ * g (D3Q7 per component): B = 1, Lambda_i = e_i, epsilon = 7|e|^2 - 6 (over
+ * rest and axis links), and the traceless 2e_x^2 - e_y^2 - e_z^2 and
+ * e_y^2 - e_z^2; Lambda at 1/tau_m, the traceless pair at s_md, B and
+ * epsilon at s_md too (the rest weight is zero, so epsilon has no
+ * non-equilibrium part). */
+static void mrt3_rows(double M[NQF][NQF], double s[NQF], const orc3_params *p) {
+  const double snu = 1.0 / p->tau_f;
+  for (int a = 0; a < NQF; ++a) {
+    const double ex = E3X[a], ey = E3Y[a], ez = E3Z[a];
+    const double e2 = ex * ex + ey * ey + ez * ez;
+    const double r[NQF] = {1.0,
+                           19.0 * e2 - 30.0,
+                           (21.0 * e2 * e2 - 53.0 * e2 + 24.0) / 2.0,
+                           ex, (5.0 * e2 - 9.0) * ex,
+                           ey, (5.0 * e2 - 9.0) * ey,
+                           ez, (5.0 * e2 - 9.0) * ez,
+                           3.0 * ex * ex - e2, (3.0 * e2 - 5.0) * (3.0 * ex * ex - e2),
+                           ey * ey - ez * ez, (3.0 * e2 - 5.0) * (ey * ey - ez * ez),
+                           ex * ey, ey * ez, ex * ez,
+                           (ey * ey - ez * ez) * ex, (ez * ez - ex * ex) * ey,
+                           (ex * ex - ey * ey) * ez};
+    for (int k = 0; k < NQF; ++k) M[k][a] = r[k];
+  }
+  const double rates[NQF] = {snu, p->s_fe, p->s_feps, p->s_fq, p->s_fq, p->s_fq, p->s_fq,
+                             p->s_fq, p->s_fq, snu, p->s_feps, snu, p->s_feps, snu, snu, snu,
+                             p->s_fq, p->s_fq, p->s_fq};
+  for (int k = 0; k < NQF; ++k) s[k] = rates[k];
+}
+
+static void mrt3g_rows(double M[NQG][NQG], double s[NQG], const orc3_params *p) {
+  for (int a = 0; a < NQG; ++a) {
+    const double ex = G3X[a], ey = G3Y[a], ez = G3Z[a];
+    const double e2 = ex * ex + ey * ey + ez * ez;
+    const double r[NQG] = {1.0, ex, ey, ez, 7.0 * e2 - 6.0, 2.0 * ex * ex - ey * ey - ez * ez,
+                           ey * ey - ez * ez};
+    for (int k = 0; k < NQG; ++k) M[k][a] = r[k];
+  }
+  const double sl = 1.0 / p->tau_m;
+  const double rates[NQG] = {p->s_md, sl, sl, sl, p->s_md, p->s_md, p->s_md};
+  for (int k = 0; k < NQG; ++k) s[k] = rates[k];
+}
+
+/* One MRT update of n populations h (stride hs) with basis rows M (n x n,
+ * row-major): the non-equilibrium part of moment k relaxes at s[k], the
+ * source's moment k (src may be NULL) enters with 1 - s[k]/2, and the
+ * moments map back through M^T diag(1/|row|^2) (the rows are orthogonal). */
+static void mrt3_update(int n, const double *M, const double *s, const double *h, int hs,
+                        const double *heq, const double *src, double *out, int os) {
+  double c[NQF];
+  for (int k = 0; k < n; ++k) {
+    double neq = 0.0, ms = 0.0, norm = 0.0;
+    for (int a = 0; a < n; ++a) {
+      neq += M[k * n + a] * (h[a * hs] - heq[a * hs]);
+      if (src) ms += M[k * n + a] * src[a];
+      norm += M[k * n + a] * M[k * n + a];
+    }
+    c[k] = (-s[k] * neq + (1.0 - 0.5 * s[k]) * ms) / norm;
+  }
+  for (int a = 0; a < n; ++a) {
+    double d = 0.0;
+    for (int k = 0; k < n; ++k) d += M[k * n + a] * c[k];
+    out[a * os] = h[a * hs] + d;
+  }
+}
+
 void orc3_collide(const orc3_params *p, const double *f, const double *g, double rho,
                   const double *u, const double *b, const double *F, double *out) {
   double feq[NQF], S[NQF], geq[NQG * 3];
   orc3_feq(rho, u, feq);
   orc3_source(rho, u, F, feq, S);
   orc3_geq(b, u, geq);
+  if (p->collision == O3_MRT) {
+    double M[NQF][NQF], sf[NQF], Mg[NQG][NQG], sg[NQG];
+    mrt3_rows(M, sf, p);
+    mrt3_update(NQF, &M[0][0], sf, f, 1, feq, S, out, 1);
+    mrt3g_rows(Mg, sg, p);
+    for (int i = 0; i < 3; ++i)
+      mrt3_update(NQG, &Mg[0][0], sg, g + i, 3, geq + i, NULL, out + 19 + i * 7, 1);
+    return;
+  }
   if (p->collision != O3_TRT) {
     for (int q = 0; q < NQF; ++q)
       out[q] = f[q] - (f[q] - feq[q]) / p->tau_f + (1.0 - 1.0 / (2.0 * p->tau_f)) * S[q];

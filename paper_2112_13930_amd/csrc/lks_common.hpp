@@ -66,8 +66,10 @@ Coef<C> make_coef(const Channel &c) {
   k.trt = Trt<C>{C(fa), C(fb), C(1.0 - 0.5 * fa), C(-0.5 * fb),
                  C(0.5 * (gp + gm)), C(0.5 * (gp - gm)), C(gp)};
   // MRT corrections on top of that TRT step (Mrt<C>)
-  k.mrt = Mrt<C>{C((c.d.s_fe - fp) / 36.0), C((c.d.s_feps - fp) / 36.0),
-                 C((c.d.s_md - c.d.s_me) / 4.0)};
+  k.mrt = Mrt<C>{C((c.d.s_fe - fp) / 36.0),    C((c.d.s_feps - fp) / 36.0),
+                 C((c.d.s_md - c.d.s_me) / 4.0), C((c.d.s_fe - fp) / 2394.0),
+                 C((c.d.s_feps - fp) / 252.0),  C((c.d.s_feps - fp) / 72.0),
+                 C((c.d.s_feps - fp) / 24.0)};
   k.mrt_on = c.p.collision == LKS_MRT ? 1 : 0;
   // enclosure walls: r = (theta-1)/(theta+1), theta = c a / (tau_m - 1/2)
   auto xr = [&](double cw) {

@@ -114,10 +114,17 @@ struct Trt {
 //   g: M_d (s_md - s_me) M_d.n / |M_d|^2,
 // rows e = (-4, -1 x4, 2 x4), epsilon = (4, -2 x4, 1 x4) over rest, axis and
 // diagonal populations, and d = (0, 1, -1, 1, -1) over D2Q5.
+// In three dimensions (D3Q19, d'Humieres et al. 2002) the corrected even
+// rows are e = 19|e|^2 - 30 (s_fe), epsilon = (21|e|^4 - 53|e|^2 + 24)/2,
+// 3pi_xx = (3|e|^2 - 5)(3e_x^2 - |e|^2) and pi_ww = (3|e|^2 - 5)(e_y^2 - e_z^2)
+// (all at s_feps), with |M|^2 = 2394, 252, 72, 24; the odd rows q and m keep
+// TRT's odd rate, and g (D3Q7, zero rest weight) is the TRT step with even
+// rate s_md.
 template <typename C>
 struct Mrt {
   C ke, keps; // (s - 1/tau_f) / 36
   C kd;       // (s_md - s_me) / 4
+  C ke3, keps3, kpx3, kpw3; // (s - 1/tau_f) / |M|^2, three dimensions
 };
 
 // A link-based Hartmann wall at a cut distance q (0 < q <= 1) from its

@@ -66,6 +66,17 @@ struct NodeObs3 {
   double rhop, ux, uy, uz, bx, by, bz, jx, jy, jz;
 };
 
+// Even rows of the D3Q19 MRT basis (three-dimensional Mrt corrections).
+constexpr int mrt3_e2(int q) { return D3Q19::ex[q] * D3Q19::ex[q] + D3Q19::ey[q] * D3Q19::ey[q] + D3Q19::ez[q] * D3Q19::ez[q]; }
+constexpr int mrt3_e(int q) { return 19 * mrt3_e2(q) - 30; }
+constexpr int mrt3_eps(int q) { return (21 * mrt3_e2(q) * mrt3_e2(q) - 53 * mrt3_e2(q) + 24) / 2; }
+constexpr int mrt3_pixx(int q) {
+  return (3 * mrt3_e2(q) - 5) * (3 * D3Q19::ex[q] * D3Q19::ex[q] - mrt3_e2(q));
+}
+constexpr int mrt3_piww(int q) {
+  return (3 * mrt3_e2(q) - 5) * (D3Q19::ey[q] * D3Q19::ey[q] - D3Q19::ez[q] * D3Q19::ez[q]);
+}
+
 // Interior rows (no wall closure): the kernel for the rows 1..ny-2 keeps the
 // pulled values in the storage type and widens them at use, which halves the
 // registers they take in FP32 storage (the step is occupancy-bound).
@@ -327,17 +338,62 @@ __device__ __forceinline__ void node3_update(const Geom3 &g, const Coef<C> &k, C
                 {W * (byp + exy), W * byp, W * (byp - exy), W * byp, W * (byp - eyz), W * (byp + eyz)},
                 {W * (bz + exz), W * (bz + eyz), W * (bz - exz), W * (bz - eyz), W * bz, W * bz}};
   };
-  if constexpr (trt_of(BC)) {
+  if constexpr (trt_of(BC) || mrt_of(BC)) {
     // opposite pairs: D3Q19 (1,3) (2,4) (5,7) (6,8) (9,10) (11,12) (13,14)
     // (15,16) (17,18); D3Q7 links (+x,-x) (+y,-y) (+z,-z)
     const Trt<C> &t = k.trt;
+    const C rhop_ = rhop, rho_ = rho, usq15_ = usq15, uF_ = uF;
+    const C ux_ = ux, uy_ = uy, uz_ = uz, Fx_ = Fx, Fy_ = Fy, Fz_ = Fz;
+    (void)rhop_, (void)rho_, (void)usq15_, (void)uF_, (void)ux_, (void)uy_, (void)uz_;
+    (void)Fx_, (void)Fy_, (void)Fz_;
+    constexpr int first[9] = {1, 2, 5, 6, 9, 11, 13, 15, 17};
+    // MRT: corrections along the even rows e, epsilon, 3pi_xx, pi_ww (Mrt),
+    // from the moments of n - S/2 taken in a first pass over the pairs (the
+    // two populations of a pair share their even row values); the TRT step
+    // then adds them as it stores
+    C ce = C(0), cp = C(0), cpx = C(0), cpw = C(0);
+    if constexpr (mrt_of(BC)) {
+      // opaque copies of the fields: the equilibria and sources of this pass
+      // must not be shared with the collision's (kept live in between, they
+      // spilled)
+      auto opaque = [](C v) -> C {
+        asm volatile("" : "+v"(v));
+        return v;
+      };
+      const C rhop = opaque(rhop_), rho = opaque(rho_), usq15 = opaque(usq15_), uF = opaque(uF_);
+      const C ux = opaque(ux_), uy = opaque(uy_), uz = opaque(uz_);
+      const C Fx = opaque(Fx_), Fy = opaque(Fy_), Fz = opaque(Fz_);
+      const C t0 = (W3<C>::w(0) * (rhop - rho * usq15) - rewiden(f[0])) -
+                   C(0.5) * (C(3) * W3<C>::w(0) * (-uF) * (C(1) - usq15));
+      C te = C(-30) * t0, tp = C(12) * t0, tpx = C(0), tpw = C(0);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        const int q = first[i], r = D3Q19::opp[q];
+        const C ex_ = C(D3Q19::ex[q]), ey_ = C(D3Q19::ey[q]), ez_ = C(D3Q19::ez[q]);
+        const C w = W3<C>::w(q), eu = ex_ * ux + ey_ * uy + ez_ * uz;
+        const C eF = ex_ * Fx + ey_ * Fy + ez_ * Fz;
+        const C even = C(4.5) * eu * eu - usq15, odd = C(3) * eu;
+        const C pa = even + odd, pb = even - odd;
+        const C ts = (w * (rhop + rho * pa) - rewiden(f[q])) + (w * (rhop + rho * pb) - rewiden(f[r])) -
+                     C(0.5) * (C(3) * w * (eF - uF) * (C(1) + pa) + C(3) * w * (-eF - uF) * (C(1) + pb));
+        te += C(mrt3_e(q)) * ts, tp += C(mrt3_eps(q)) * ts;
+        tpx += C(mrt3_pixx(q)) * ts, tpw += C(mrt3_piww(q)) * ts;
+      }
+      const Mrt<C> &m = k.mrt;
+      ce = m.ke3 * te, cp = m.keps3 * tp, cpx = m.kpx3 * tpx, cpw = m.kpw3 * tpw;
+      __builtin_amdgcn_sched_barrier(0); // keep the two passes apart
+    }
+    auto corr = [&](int q) -> C {
+      return C(mrt3_e(q)) * ce + C(mrt3_eps(q)) * cp + C(mrt3_pixx(q)) * cpx + C(mrt3_piww(q)) * cpw;
+    };
     {
       const C fq = rewiden(f[0]);
       const C feq = W3<C>::w(0) * (rhop - rho * usq15);
       const C src_q = C(3) * W3<C>::w(0) * (-uF) * (C(1) - usq15);
-      put(0, fq + om * (feq - fq) + ka * src_q);
+      C v = fq + om * (feq - fq) + ka * src_q;
+      if constexpr (mrt_of(BC)) v += corr(0);
+      put(0, v);
     }
-    constexpr int first[9] = {1, 2, 5, 6, 9, 11, 13, 15, 17};
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       const int q = first[i], r = D3Q19::opp[q];
@@ -345,6 +401,10 @@ __device__ __forceinline__ void node3_update(const Geom3 &g, const Coef<C> &k, C
       C fa = rewiden(f[q]), fb = rewiden(f[r]);
       collide_f_pair(fa, fb, W3<C>::w(q), ex_ * ux + ey_ * uy + ez_ * uz,
                      ex_ * Fx + ey_ * Fy + ez_ * Fz, rhop, rho, usq15, uF, t);
+      if constexpr (mrt_of(BC)) {
+        const C cq = corr(q);
+        fa += cq, fb += cq;
+      }
       put(q, fa);
       put(r, fb);
     }

@@ -35,7 +35,7 @@ constexpr int NRED3 = 6; // du2, u2, db2, b2, sum_u, nonfinite
 #endif
 template <typename S, int BC>
 constexpr int kWaves3 =
-    (wall_of(BC) == BC_NONE && sizeof(S) == 4) ? LKS_STEP3_WAVES_FP32_INTERIOR : 4;
+    (wall_of(BC) == BC_NONE && sizeof(S) == 4 && !mrt_of(BC)) ? LKS_STEP3_WAVES_FP32_INTERIOR : 4;
 
 // Rows of a launch.  Interior: (y, z) with 1 <= y <= ny-2 and every z, or
 // 1 <= z <= nz-2 in a duct, numbered z-major.  Walls: the two Hartmann rows
@@ -237,10 +237,7 @@ int validate3(const lks_mhd3_params *p, Channel *c) {
     set_error("invalid parameters: the three-dimensional walls are half-way (q = 1/2)");
     return LKS_EINVAL;
   }
-  if (p->base.collision == LKS_MRT) {
-    set_error("invalid parameters: the three-dimensional channel collides with BGK or TRT");
-    return LKS_EINVAL;
-  }
+
   if (p->side_walls != 0 && p->side_walls != 1) {
     set_error("invalid parameters: side_walls must be 0 or 1");
     return LKS_EINVAL;
@@ -291,7 +288,7 @@ hipError_t launch3_t(lks_mhd3 *h, const void *src, void *dst, ObsOut3 oo) {
   const int interior = h->tiles_x * (g.ny - 2) * (g.nz - 2 * g.side);
   const int walls = h->tiles_x * (2 * g.nz + 2 * g.side * (g.ny - 2));
   if (interior > 0) {
-    constexpr int kInterior = BC_NONE | (BC & COLL_TRT);
+    constexpr int kInterior = BC_NONE | (BC & (COLL_TRT | COLL_MRT));
     hipLaunchKernelGGL((k_step3<S, C, kInterior, MODE>), dim3(interior), dim3(256), 0, h->stream,
                        h->geom, coef3<C>(h), (C)h->fz, side3<C>(h), static_cast<const S *>(src),
                        static_cast<S *>(dst), h->tiles_x, 0, h->rec, h->partials, oo, h->ctr,
@@ -317,9 +314,16 @@ hipError_t launch3_s(lks_mhd3 *h, const void *src, void *dst, ObsOut3 oo) {
   case BC_LINK | COLL_TRT:
     if constexpr (MODE != MODE_MOMENTS) return launch3_t<S, C, BC_LINK | COLL_TRT, MODE>(h, src, dst, oo);
     break;
-  default:
+  case BC_MOMENT | COLL_TRT:
     if constexpr (MODE != MODE_MOMENTS) return launch3_t<S, C, BC_MOMENT | COLL_TRT, MODE>(h, src, dst, oo);
     break;
+  case BC_LINK | COLL_MRT:
+    if constexpr (MODE != MODE_MOMENTS) return launch3_t<S, C, BC_LINK | COLL_MRT, MODE>(h, src, dst, oo);
+    break;
+  case BC_MOMENT | COLL_MRT:
+    if constexpr (MODE != MODE_MOMENTS) return launch3_t<S, C, BC_MOMENT | COLL_MRT, MODE>(h, src, dst, oo);
+    break;
+  default: break;
   }
   return hipErrorInvalidValue;
 }
@@ -463,6 +467,14 @@ int lks_mhd3_create(const lks_mhd3_params *p, void *dev_buf, size_t bytes, void 
   h->ntiles = L.ntiles;
   h->kd = make_coef<double>(c);
   h->kf = make_coef<float>(c);
+  if (c.p.collision == LKS_MRT) {
+    // D3Q7 has no rest weight, so g's isotropic second moment carries no
+    // non-equilibrium part and its TRT step takes the even rate s_md
+    const double gp = c.d.s_md, gm = 1.0 / c.p.tau_m;
+    h->kd.trt.ga = 0.5 * (gp + gm), h->kd.trt.gb = 0.5 * (gp - gm), h->kd.trt.gp = gp;
+    h->kf.trt.ga = (float)(0.5 * (gp + gm)), h->kf.trt.gb = (float)(0.5 * (gp - gm));
+    h->kf.trt.gp = (float)gp;
+  }
   rc = with_device3(h, [&]() -> int {
     if (c.p.precision == LKS_FP64)
       hipLaunchKernelGGL(k_init3<double>, dim3(elementwise_grid3(h)), dim3(256), 0, h->stream, h->geom,

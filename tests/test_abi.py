@@ -209,7 +209,9 @@ def test_3d_sizing_and_validation(L):
     p.base = L.make_params(64, 32, precision="fp32", collision="trt", lambda_f=-1.0)
     assert lib.lks_mhd3_state_bytes(ctypes.byref(p)) == 0 and "lambda" in L.last_error()
     p.base = L.make_params(64, 32, precision="fp32", collision="mrt")
-    assert lib.lks_mhd3_state_bytes(ctypes.byref(p)) == 0 and "BGK or TRT" in L.last_error()
+    assert lib.lks_mhd3_state_bytes(ctypes.byref(p)) > 0
+    p.base = L.make_params(64, 32, precision="fp32", collision="mrt", mrt=dict(s_md=2.0))
+    assert lib.lks_mhd3_state_bytes(ctypes.byref(p)) == 0
     # ducts: link walls only, nz >= 2, conductances in [0, inf]
     p.base = L.make_params(64, 32, precision="fp32")
     p.nz, p.side_walls, p.c_side_lower, p.c_side_upper = 8, 1, 0.5, math.inf

@@ -33,6 +33,9 @@ def channel3(p3, precision, stream=None, trt_lambdas=None):
               u_lower=p3.u_lo, u_upper=p3.u_hi)
     if trt_lambdas is not None:
         kw.update(collision="trt", lambda_f=trt_lambdas[0], lambda_m=trt_lambdas[1])
+    if p3.collision == d3.MRT:
+        kw.update(collision="mrt", mrt=dict(s_fe=p3.s_fe, s_feps=p3.s_feps, s_fq=p3.s_fq,
+                                            s_md=p3.s_md))
     if p3.side_walls:
         kw.update(side_walls=True, c_side=(p3.cs_lo, p3.cs_hi))
     return Channel3(p3.nx, p3.ny, p3.nz, fz=p3.fz, stream=stream, **kw)
@@ -43,6 +46,15 @@ def trt3(p3, lf, lm):
     magic parameters, derived as the library derives them)."""
     tfm, tmp = derive.trt_times(p3.tau_f, p3.tau_m, lf, lm)
     return d3.Params3(**{**p3.__dict__, "collision": d3.TRT, "tau_fm": tfm, "tau_mp": tmp})
+
+
+MRT3_RATES = dict(s_fe=1.19, s_feps=1.4, s_fq=1.2, s_md=1.6)
+
+
+def mrt3(p3, **rates):
+    """The MRT variant of a 3D oracle parameter set (explicit rates on both
+    sides)."""
+    return d3.Params3(**{**p3.__dict__, "collision": d3.MRT, **MRT3_RATES, **rates})
 
 
 def errors3(g, o):
@@ -326,6 +338,66 @@ def test_duct_x_invariant_from_rest_matches_oracle_cross_section(P):
     ch.close()
     p1 = d3.Params3(nx=1, **kw)
     o = d3.observe(p1, d3.run(p1, d3.init_state(p1), 400, nthreads=8))
+    for k in ("ux", "bx"):
+        ref = np.broadcast_to(o[k], g[k].shape)
+        assert np.linalg.norm(g[k] - ref) / np.linalg.norm(ref) < TOL["fp32"], k
+
+
+@pytest.mark.parametrize("case", [CASES[1], CASES[2], CASES[4], CASES[5]])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_mrt_random_3d_state_parity(P, case, precision):
+    """Multiple-relaxation-time collision on an x-, y- and z-dependent random
+    state, 10 steps."""
+    from paper_2112_13930_amd.workloads import random_populations3
+    bc, cl, cu, ul, uu, fx, fz = case
+    base = d3.Params3(nx=37, ny=11, nz=5, bc=bc, tau_f=0.7, tau_m=0.9, b0=0.05, fx=fx, fz=fz,
+                      c_lo=cl, c_hi=cu, u_lo=ul, u_hi=uu)
+    p3 = mrt3(base)
+    s0 = random_populations3(p3.nx, p3.ny, p3.nz, seed=17, b0=p3.b0)
+    ch = channel3(p3, precision)
+    ch.load_state(torch.from_numpy(s0))
+    ch.step(10)
+    g = {k: v.cpu().numpy() for k, v in ch.moments().items()}
+    st = ch.save_state().cpu().numpy()
+    ch.close()
+    s = d3.run(p3, s0.copy(), 10)
+    errs = errors3(g, d3.observe(p3, s))
+    keys = ("ux", "bx", "uy", "uz", "by", "bz", "rho") + (("jx", "jy", "jz") if precision == "fp64" else ())
+    assert_below(errs, TOL[precision], keys)
+    if precision == "fp64":
+        assert np.abs(st - s).max() < 1e-14
+
+
+def test_mrt_duct_parity(P):
+    from paper_2112_13930_amd.workloads import random_populations3
+    base = d3.Params3(nx=37, ny=11, nz=6, bc=LINK, tau_f=0.7, tau_m=0.9, b0=0.05, fx=1e-5,
+                      c_lo=0.3, c_hi=math.inf, u_hi=0.03, side_walls=True, cs_lo=0.5,
+                      cs_hi=math.inf)
+    p3 = mrt3(base, s_fe=1.5, s_md=1.1)
+    s0 = random_populations3(p3.nx, p3.ny, p3.nz, seed=37, b0=p3.b0)
+    ch = channel3(p3, "fp64")
+    ch.load_state(torch.from_numpy(s0))
+    ch.step(10)
+    st = ch.save_state().cpu().numpy()
+    ch.close()
+    assert np.abs(st - d3.run(p3, s0.copy(), 10)).max() < 1e-14
+
+
+def test_mrt_3d_hartmann_from_rest_matches_oracle(P):
+    """A 64 x 24 x 8 FP32 MRT channel from rest, 2000 steps: every (x, z)
+    column equals the 3D oracle's x- and z-invariant run."""
+    base = d3.Params3(nx=1, ny=24, nz=1, bc=LINK, tau_f=0.8, tau_m=0.8, b0=0.01, fx=2e-6,
+                      c_lo=0.5, c_hi=0.5, u_hi=0.01)
+    p1 = mrt3(base)
+    big = d3.Params3(**{**p1.__dict__, "nx": 64, "nz": 8})
+    ch = channel3(big, "fp32", stream=torch.cuda.Stream())
+    ch.set_graph(50)
+    ch.step(2000)
+    g = {k: v.cpu().numpy() for k, v in ch.moments().items()}
+    ch.close()
+    s = d3.init_state(p1)
+    d3.run(p1, s, 2000, nthreads=8)
+    o = d3.observe(p1, s)
     for k in ("ux", "bx"):
         ref = np.broadcast_to(o[k], g[k].shape)
         assert np.linalg.norm(g[k] - ref) / np.linalg.norm(ref) < TOL["fp32"], k
