@@ -84,7 +84,6 @@ int derive_channel(const lks_mhd_params *p, Channel *out) {
       (!finite(p->lambda_f) || p->lambda_f <= 0.0 || !finite(p->lambda_m) || p->lambda_m <= 0.0))
     return bad("TRT and MRT need finite lambda_f > 0 and lambda_m > 0");
   if (p->collision == LKS_MRT) {
-    if (p->x_walls || cut) return bad("MRT is available for channels with half-way or moment walls");
     auto rate_ok = [](double s, bool nan_ok) { return (nan_ok && std::isnan(s)) || (s > 0.0 && s < 2.0); };
     if (!rate_ok(p->s_fe, false) || !rate_ok(p->s_feps, false) || !rate_ok(p->s_fq, true) ||
         !rate_ok(p->s_me, true) || !rate_ok(p->s_md, true))

@@ -346,6 +346,14 @@ hipError_t launch_mode(lks_mhd *h, int shape, const void *src, void *dst, ObsOut
     case BC_MOMENT | COLL_MRT:
       if constexpr (kCollide) return launch_bc<S, C, BC_MOMENT | COLL_MRT, MODE>(h, shape, src, dst, oo);
       break;
+    case BC_LINK | COLL_MRT | WALLS_X:
+      if constexpr (kCollide)
+        return launch_bc<S, C, BC_LINK | COLL_MRT | WALLS_X, MODE>(h, shape, src, dst, oo);
+      break;
+    case BC_LINK | COLL_MRT | WALLS_Q:
+      if constexpr (kCollide)
+        return launch_bc<S, C, BC_LINK | COLL_MRT | WALLS_Q, MODE>(h, shape, src, dst, oo);
+      break;
     default: break;
     }
     return hipErrorInvalidValue;

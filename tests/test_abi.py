@@ -61,7 +61,7 @@ def _v(L, **kw):
     dict(collision="mrt", mrt=dict(s_fe=2.0)), dict(collision="mrt", mrt=dict(s_feps=0.0)),
     dict(collision="mrt", mrt=dict(s_fe=float("nan"))), dict(collision="mrt", mrt=dict(s_fq=-0.5)),
     dict(collision="mrt", mrt=dict(s_md=2.5)), dict(collision="mrt", lambda_m=0.0),
-    dict(collision="mrt", x_walls=True), dict(collision="mrt", q=0.3),
+
     dict(collision="trt", lambda_m=float("inf")), dict(collision="trt", lambda_m=-1.0),
     dict(x_walls=True, bc="moment"), dict(x_walls=True, nx=1), dict(x_walls=True, c_x=-1.0),
     dict(x_walls=True, c_x=(0.0, float("nan"))),
@@ -86,6 +86,7 @@ def test_validate_rejects(L, kw):
     dict(x_walls=True), dict(x_walls=True, nx=2, c_x=(0.0, math.inf), collision="trt"),
     dict(q=0.25), dict(q=(1.0, 0.3), c_lower=math.inf), dict(q=0.1, c_lower=0.0, tau_m=0.55),
     dict(collision="mrt"), dict(collision="mrt", bc="moment", ny=3),
+    dict(collision="mrt", x_walls=True), dict(collision="mrt", q=0.3),
     dict(collision="mrt", mrt=dict(s_fe=1.9, s_feps=0.3, s_fq=1.99, s_me=0.01, s_md=1.5)),
 ])
 def test_validate_accepts(L, kw):

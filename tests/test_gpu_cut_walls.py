@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 from oracle import LINK, Params
-from tests.helpers import TOL, assert_close, field_errors, lib_kwargs, to_numpy, trt
+from tests.helpers import TOL, assert_close, field_errors, lib_kwargs, mrt, to_numpy, trt
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -34,6 +34,7 @@ CASES = [
     (1.0, 0.3, math.inf, 2.0, -0.02, 0.0, 1e-5, False),
     (0.6, 0.4, 0.3, 0.0, 0.0, 0.04, 0.0, False),
     (0.2, 1.0, 1.0, math.inf, 0.01, 0.02, 1e-5, True),
+    (0.7, 0.25, 0.4, 1.5, 0.0, 0.03, 2e-5, "mrt"),
 ]
 
 
@@ -44,7 +45,9 @@ def test_cut_walls_random_state_parity(P, case, precision):
     ql, qh, cl, ch, ul, uh, fx, use_trt = case
     p = Params(nx=45, ny=19, bc=LINK, tau_f=0.7, tau_m=0.9, b0=0.05, fx=fx, fy=-1e-5, c_lo=cl,
                c_hi=ch, u_lo=ul, u_hi=uh, q_lo=ql, q_hi=qh)
-    if use_trt:
+    if use_trt == "mrt":
+        p = mrt(p, (1.2, 1.7, 1.3, 0.9, 1.6))
+    elif use_trt:
         p = trt(p)
     s0 = random_populations(p.nx, p.ny, seed=47, b0=p.b0)
     ch_ = gpu_channel(p, precision)

@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 from oracle import LINK, Params, derive
-from tests.helpers import TOL, assert_close, field_errors, lib_kwargs, to_numpy, trt
+from tests.helpers import TOL, assert_close, field_errors, lib_kwargs, mrt, to_numpy, trt
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -35,6 +35,7 @@ CASES = [
     (0.3, 2.0, 0.5, math.inf, -0.02, 0.03, 1e-5, -1e-5, False),
     (math.inf, 0.1, math.inf, 0.0, 0.0, 0.0, 2e-5, 1e-5, False),
     (1.0, 1.0, 0.2, 3.0, 0.0, 0.05, 0.0, 0.0, True),
+    (0.5, math.inf, 1.0, 0.0, 0.0, 0.04, 1e-5, 0.0, "mrt"),
 ]
 
 
@@ -45,7 +46,9 @@ def test_enclosure_random_state_parity(P, case, precision):
     cl, cu, xl, xh, ul, uu, fx, fy, use_trt = case
     p = Params(nx=45, ny=21, bc=LINK, tau_f=0.7, tau_m=0.9, b0=0.05, fx=fx, fy=fy, c_lo=cl,
                c_hi=cu, u_lo=ul, u_hi=uu, x_walls=True, cx_lo=xl, cx_hi=xh)
-    if use_trt:
+    if use_trt == "mrt":
+        p = mrt(p, (1.2, 1.7, 1.3, 0.9, 1.6))
+    elif use_trt:
         p = trt(p)
     s0 = random_populations(p.nx, p.ny, seed=41, b0=p.b0)
     ch = gpu_channel(p, precision)

@@ -183,3 +183,14 @@ def test_mrt_uniform_modes_decay_at_their_own_rates(plane0, rows):
                 want = amp * (1 - rate_of[name]) ** n if other == name else 0.0
                 assert abs(got - want) < 1e-14, (name, other, got, want)
             assert abs(d.sum()) < 1e-14
+
+
+@pytest.mark.parametrize("walls", [dict(x_walls=True, cx_lo=0.5, cx_hi=math.inf),
+                                   dict(q_lo=0.3, q_hi=0.8)], ids=["enclosure", "cut"])
+def test_mrt_with_trt_rates_is_trt_in_enclosures_and_at_cut_walls(walls):
+    tfm, tmp = derive.trt_times(0.7, 0.9, 3.0 / 16.0, 0.25)
+    kw = dict(KW, bc=LINK, **walls)
+    t = Params(tau_f=0.7, tau_m=0.9, collision=TRT, tau_fm=tfm, tau_mp=tmp, **kw)
+    m = mrt_params(rates=(1 / 0.7, 1 / 0.7, 1 / tfm, 1 / tmp, 1 / tmp), **kw)
+    s0 = random_state(t, seed=23)
+    assert np.abs(oracle.run(m, s0.copy(), 20) - oracle.run(t, s0.copy(), 20)).max() < 1e-14
