@@ -105,8 +105,12 @@ def headline(torch, args):
     torch.cuda.synchronize()
     finite = bool(torch.isfinite(m["ux"]).all().item())
     umax = float(m["ux"].abs().max().item())
+    # the weakly compressible scheme's density change (magnetic pressure
+    # B_x^2/2 is taken up by the lattice density)
+    drho = float((m["rho"] - 1.0).abs().max().item())
     ch.close()
-    return {"wall": wall, "per_step": per_step, "nodes": nodes, "finite": finite, "umax": umax}
+    return {"wall": wall, "per_step": per_step, "nodes": nodes, "finite": finite, "umax": umax,
+            "max_abs_drho": drho}
 
 
 def developed_state_rate(torch, steps=200, warmup=10):
@@ -767,6 +771,7 @@ def main():
                      "algorithmic_bytes_per_launch": 152 * nodes,
                      "avg_launch_ms": round(h["per_step"] * 1e3, 4)},
         "finite": h["finite"],
+        "max_abs_drho": h["max_abs_drho"],
     }
     if not args.quick:
         extras = {}
