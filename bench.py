@@ -567,6 +567,33 @@ def profile_run_3d(torch, args):
                       "per_step_ms": (time.perf_counter() - t0) / args.steps * 1e3}))
 
 
+def profile_run_batch(torch, args):
+    """The 256-channel FP32 batch's steps only (the batched leg's channel mix,
+    launched without a graph so that a tracer sees each step), plus a device
+    copy of known size (counter scale)."""
+    from paper_2112_13930_amd._lib import make_params
+    from paper_2112_13930_amd.batch import Batch
+    a = torch.empty(COPY_REF_BYTES // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    draws, _ = stable_mix(256, 2024)
+    nodes = sum(d.nx * d.ny for d in draws)
+    bt = Batch("fp32", max_channels=256, max_nodes=nodes + 1024)
+    for d in draws:
+        bt.admit(make_params(d.nx, d.ny, precision="fp32", **d.kwargs()))
+    bt.step(args.warmup, graph=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bt.step(args.steps, graph=False)
+    torch.cuda.synchronize()
+    bt.close()
+    print(json.dumps({"profile_run_batch": True, "steps": args.steps, "nodes": nodes,
+                      "per_step_ms": (time.perf_counter() - t0) / args.steps * 1e3}))
+
+
 def profile_run(torch, args):
     """Headline steps only, plus a device copy of known size (counter scale)."""
     from paper_2112_13930_amd.channel import Channel
@@ -700,6 +727,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--profile-run", action="store_true")
     ap.add_argument("--profile-3d", action="store_true", help="3D FP32 steps only (profiling)")
+    ap.add_argument("--profile-batch", action="store_true",
+                    help="256-channel FP32 batch steps only (profiling)")
     ap.add_argument("--only", choices=sorted(LEGS), help="run one extra leg and print it")
     ap.add_argument("--summarize", nargs="*")
     ap.add_argument("--command", default="")
@@ -728,6 +757,9 @@ def main():
 
     if args.profile_run:
         profile_run(torch, args)
+        return 0
+    if args.profile_batch:
+        profile_run_batch(torch, args)
         return 0
     if args.profile_3d:
         profile_run_3d(torch, args)
