@@ -1,0 +1,100 @@
+"""Degenerate and ragged sizes against the oracle: one column, two wall rows
+(link), three rows (moment, cut-distance walls), an enclosure of two
+columns, rows one node longer than a 256-node block, odd widths in binary16
+(no two-node vector shape), and the same channels in one batch and as a 3D
+channel of one layer.  Tolerances as for the channel: relative L2 against
+the FP64 oracle at equal step counts, 1e-12 (FP64), 1e-5 (FP32 storage),
+2e-3 (binary16 storage)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import LINK, MOMENT, Params
+from tests.helpers import TOL, assert_close, field_errors, lib_kwargs, to_numpy
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2112_13930_amd as P
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    P.lib()
+    return P
+
+
+BASE = dict(tau_f=0.7, tau_m=0.9, b0=0.05, fx=2e-5, fy=-1e-5, c_lo=0.3, c_hi=math.inf)
+CASES = {
+    "1x2_link": dict(nx=1, ny=2, bc=LINK, u_hi=0.03),
+    "3x2_link": dict(nx=3, ny=2, bc=LINK, u_lo=-0.02),
+    "257x5_link": dict(nx=257, ny=5, bc=LINK, u_hi=0.03),
+    "1x3_moment": dict(nx=1, ny=3, bc=MOMENT, u_hi=0.03),
+    "5x3_moment": dict(nx=5, ny=3, bc=MOMENT, u_lo=-0.02),
+    "2x4_enclosure": dict(nx=2, ny=4, bc=LINK, u_hi=0.03, x_walls=True, cx_lo=0.3,
+                          cx_hi=math.inf),
+    "7x3_cut": dict(nx=7, ny=3, bc=LINK, q_lo=0.3, q_hi=0.9),
+}
+
+
+def params(name):
+    return Params(**{**BASE, **CASES[name]})
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16", "fp16_f32"])
+def test_degenerate_sizes_match_oracle(P, name, precision):
+    from paper_2112_13930_amd.channel import Channel
+    from paper_2112_13930_amd.workloads import random_populations
+    p = params(name)
+    s0 = random_populations(p.nx, p.ny, seed=71, b0=p.b0)
+    ch = Channel(p.nx, p.ny, **lib_kwargs(p, precision))
+    ch.load_state(torch.from_numpy(s0))
+    ch.step(15)
+    m = to_numpy(ch.moments())
+    s = oracle.run(p, s0.copy(), 15)
+    keys = ("ux", "bx", "uy", "by", "rho") + (("jz",) if precision == "fp64" else ())
+    assert_close(field_errors(m, oracle.observe(p, s), p.b0), TOL[precision], keys=keys)
+    if precision == "fp64":
+        assert np.abs(ch.save_state().cpu().numpy() - s).max() < 1e-14
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+def test_degenerate_channels_in_one_batch_equal_solo_runs(P, precision):
+    from paper_2112_13930_amd._lib import make_params
+    from paper_2112_13930_amd.batch import Batch
+    from paper_2112_13930_amd.channel import Channel
+    names = ["1x2_link", "3x2_link", "257x5_link", "1x3_moment", "5x3_moment"]
+    b = Batch(precision, max_channels=8, max_nodes=10_000)
+    slots = [b.admit(make_params(params(n).nx, params(n).ny, **lib_kwargs(params(n), precision)))
+             for n in names]
+    b.step(9, graph=True)
+    torch.cuda.synchronize()
+    for s, n in zip(slots, names):
+        p = params(n)
+        solo = Channel(p.nx, p.ny, **lib_kwargs(p, precision))
+        solo.set_rebase(0)
+        solo.step(9)
+        assert torch.equal(b.save_state(s).cpu(), solo.save_state().cpu()), n
+    b.close()
+
+
+@pytest.mark.parametrize("name", ["1x2_link", "1x3_moment"])
+def test_one_layer_3d_channel_of_degenerate_size_matches_2d_oracle(P, name):
+    from oracle import d3
+    from paper_2112_13930_amd.channel3 import Channel3
+    from paper_2112_13930_amd.workloads import random_populations
+    p = params(name)
+    s2 = random_populations(p.nx, p.ny, seed=73, b0=p.b0)
+    kw = lib_kwargs(p, "fp64")
+    ch = Channel3(p.nx, p.ny, 1, **kw)
+    ch.load_state(torch.from_numpy(d3.lift_from_2d(s2, 1)))
+    ch.step(12)
+    g = {k: v.cpu().numpy()[0] for k, v in ch.moments().items()}
+    ch.close()
+    oracle.run(p, s2, 12)
+    o = oracle.observe(p, s2)
+    for k in ("ux", "bx"):
+        assert np.linalg.norm(g[k] - o[k]) <= 1e-12 * np.linalg.norm(o[k]), k
