@@ -98,3 +98,34 @@ def test_one_layer_3d_channel_of_degenerate_size_matches_2d_oracle(P, name):
     o = oracle.observe(p, s2)
     for k in ("ux", "bx"):
         assert np.linalg.norm(g[k] - o[k]) <= 1e-12 * np.linalg.norm(o[k]), k
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_largest_channel_matches_oracle_column(P, precision):
+    """The largest channel the library accepts (nx * ny * 19 within 32-bit
+    indices: 16384 x 6898, 113 M nodes, 17 GB of FP32 or 34 GB of FP64
+    populations), 20 steps of a shear-driven channel from rest: sampled
+    columns equal the oracle's x-invariant run; one more row is refused."""
+    import ctypes
+
+    from paper_2112_13930_amd._lib import LKS_EINVAL, lib, make_params
+    from paper_2112_13930_amd.channel import Channel
+    nx = 16384
+    ny = ((1 << 31) - 1) // 19 // nx
+    kw = dict(bc="link", precision=precision, tau_f=0.7, tau_m=0.9, b0=0.002, c_lower=1.0,
+              c_upper=1.0, u_upper=0.05)
+    assert lib().lks_mhd_validate(ctypes.byref(make_params(nx, ny + 1, **kw))) == LKS_EINVAL
+    ch = Channel(nx, ny, **kw)
+    ch.step(20)
+    m = ch.moments()
+    cols = [0, 1, nx // 2, nx - 1]
+    got = {k: m[k][:, cols].cpu().numpy() for k in ("ux", "bx")}
+    del m
+    ch.close()
+    p = Params(nx=4, ny=ny, bc=LINK, tau_f=0.7, tau_m=0.9, b0=0.002, c_lo=1.0, c_hi=1.0,
+               u_hi=0.05)
+    s = oracle.run(p, oracle.init_state(p), 20, nthreads=8)
+    o = oracle.observe(p, s)
+    for k, g in got.items():
+        ref = np.broadcast_to(o[k][:, :1], g.shape)
+        assert np.linalg.norm(g - ref) / np.linalg.norm(ref) < TOL[precision], k
