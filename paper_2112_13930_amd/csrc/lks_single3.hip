@@ -29,13 +29,17 @@ constexpr int NRED3 = 6; // du2, u2, db2, b2, sum_u, nonfinite
 // advances them.
 // Waves per SIMD: the step is bound by how many waves keep memory requests
 // in flight.  The binary32 interior kernel fits 5 waves (at most 102
-// registers) without spilling; the others take 4 (at most 128).
+// registers) without spilling; the others take 4 (at most 128), except the
+// MRT kernels in FP64, which spill at 4 and run as fast as TRT at 3 (154
+// registers).
 #ifndef LKS_STEP3_WAVES_FP32_INTERIOR
 #define LKS_STEP3_WAVES_FP32_INTERIOR 5
 #endif
 template <typename S, int BC>
 constexpr int kWaves3 =
-    (wall_of(BC) == BC_NONE && sizeof(S) == 4 && !mrt_of(BC)) ? LKS_STEP3_WAVES_FP32_INTERIOR : 4;
+    (wall_of(BC) == BC_NONE && sizeof(S) == 4 && !mrt_of(BC)) ? LKS_STEP3_WAVES_FP32_INTERIOR
+    : (mrt_of(BC) && sizeof(S) == 8)                           ? 3
+                                                               : 4;
 
 // Rows of a launch.  Interior: (y, z) with 1 <= y <= ny-2 and every z, or
 // 1 <= z <= nz-2 in a duct, numbered z-major.  Walls: the two Hartmann rows
