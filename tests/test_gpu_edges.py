@@ -129,3 +129,33 @@ def test_largest_channel_matches_oracle_column(P, precision):
     for k, g in got.items():
         ref = np.broadcast_to(o[k][:, :1], g.shape)
         assert np.linalg.norm(g - ref) / np.linalg.norm(ref) < TOL[precision], k
+
+
+def test_empty_batch_steps_and_refills(P):
+    """A batch with no channels steps (with and without a graph) as a no-op;
+    a channel admitted afterwards, and one admitted after every other was
+    retired, each equal their solo runs."""
+    from paper_2112_13930_amd._lib import make_params
+    from paper_2112_13930_amd.batch import Batch
+    from paper_2112_13930_amd.channel import Channel
+    p = params("257x5_link")
+    kw = lib_kwargs(p, "fp32")
+    b = Batch("fp32", max_channels=4, max_nodes=10_000)
+    b.step(3, graph=False)
+    b.step(4, graph=True)
+    torch.cuda.synchronize()
+    s1 = b.admit(make_params(p.nx, p.ny, **kw))
+    b.step(6, graph=True)
+    torch.cuda.synchronize()
+    solo = Channel(p.nx, p.ny, **kw)
+    solo.step(6)
+    assert torch.equal(b.save_state(s1).cpu(), solo.save_state().cpu())
+    b.retire(s1)
+    b.step(2, graph=True)
+    s2 = b.admit(make_params(p.nx, p.ny, **kw))
+    b.step(5, graph=False)
+    torch.cuda.synchronize()
+    solo = Channel(p.nx, p.ny, **kw)
+    solo.step(5)
+    assert torch.equal(b.save_state(s2).cpu(), solo.save_state().cpu())
+    b.close()
