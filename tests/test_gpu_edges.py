@@ -159,3 +159,35 @@ def test_empty_batch_steps_and_refills(P):
     solo.step(5)
     assert torch.equal(b.save_state(s2).cpu(), solo.save_state().cpu())
     b.close()
+
+
+@pytest.mark.parametrize("shape,side", [((1, 2, 3), False), ((3, 3, 2), True), ((257, 4, 2), True)],
+                         ids=["1x2x3", "3x3x2_duct", "257x4x2_duct"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_degenerate_3d_sizes_match_oracle(P, shape, side, precision):
+    """3D channels and ducts of the fewest rows and layers (two wall rows;
+    two layers that are both side walls) and rows one node past a block,
+    from a random x-, y- and z-dependent state."""
+    from oracle import d3
+    from paper_2112_13930_amd.channel3 import Channel3
+    from paper_2112_13930_amd.workloads import random_populations3
+    nx, ny, nz = shape
+    p3 = d3.Params3(nx=nx, ny=ny, nz=nz, bc=LINK, tau_f=0.7, tau_m=0.9, b0=0.05, fx=2e-5,
+                    fz=1e-5, c_lo=0.3, c_hi=math.inf, u_hi=0.03, side_walls=side, cs_lo=0.5,
+                    cs_hi=math.inf)
+    s0 = random_populations3(nx, ny, nz, seed=79, b0=p3.b0)
+    ch = Channel3(nx, ny, nz, fz=p3.fz, side_walls=side, c_side=(p3.cs_lo, p3.cs_hi), bc="link",
+                  precision=precision, tau_f=0.7, tau_m=0.9, b0=p3.b0, fx=p3.fx,
+                  c_lower=p3.c_lo, c_upper=p3.c_hi, u_upper=p3.u_hi)
+    ch.load_state(torch.from_numpy(s0))
+    ch.step(10)
+    g = {k: v.cpu().numpy() for k, v in ch.moments().items()}
+    st = ch.save_state().cpu().numpy()
+    ch.close()
+    s = d3.run(p3, s0.copy(), 10)
+    o = d3.observe(p3, s)
+    for k in ("ux", "bx", "uz", "bz"):
+        scale = np.linalg.norm(o["ux" if k[0] == "u" else "bx"])
+        assert np.linalg.norm(g[k] - o[k]) / scale < TOL[precision], k
+    if precision == "fp64":
+        assert np.abs(st - s).max() < 1e-14
