@@ -67,6 +67,8 @@ struct Tile {
 #endif
 
 constexpr int kTileThreads = 256;
+// Steps in the long captured graph (even: a graph starts and ends at parity 0).
+constexpr int kLongGraphSteps = 16;
 constexpr int kWidthClasses = 7;
 constexpr int NREDB = 6;
 
@@ -273,7 +275,8 @@ struct lks_mhd_batch {
   int nactive = 0;
   int grid = 0, grid_cap = 0;
   bool dirty = false;
-  hipGraphExec_t gexec = nullptr;
+  hipGraphExec_t gexec = nullptr;      // two steps
+  hipGraphExec_t gexec_long = nullptr; // kLongGraphSteps steps
 };
 
 namespace {
@@ -425,6 +428,10 @@ int rebuild(lks_mhd_batch *b) {
       (void)hipGraphExecDestroy(b->gexec);
       b->gexec = nullptr;
     }
+    if (b->gexec_long) {
+      (void)hipGraphExecDestroy(b->gexec_long);
+      b->gexec_long = nullptr;
+    }
   }
   return LKS_OK;
 }
@@ -456,14 +463,14 @@ int batch_one(lks_mhd_batch *b, int mode) {
   return LKS_OK;
 }
 
-int capture(lks_mhd_batch *b) {
+int capture(lks_mhd_batch *b, int nsteps, hipGraphExec_t *out) {
   hipGraph_t graph = nullptr;
   LKS_HIP_CHECK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
   const int p0 = b->parity;
   const int64_t s0 = b->global_steps;
   b->parity = 0;
-  int rc = batch_one(b, MODE_STEP);
-  if (rc == LKS_OK) rc = batch_one(b, MODE_STEP);
+  int rc = LKS_OK;
+  for (int i = 0; i < nsteps && rc == LKS_OK; ++i) rc = batch_one(b, MODE_STEP);
   b->parity = p0;
   b->global_steps = s0;
   hipError_t e = hipStreamEndCapture(b->stream, &graph);
@@ -472,7 +479,7 @@ int capture(lks_mhd_batch *b) {
     set_error("hipStreamEndCapture failed: %s", hipGetErrorString(e));
     return LKS_EDEVICE;
   }
-  e = hipGraphInstantiate(&b->gexec, graph, nullptr, nullptr, 0);
+  e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
   if (e != hipSuccess) {
     set_error("hipGraphInstantiate failed: %s", hipGetErrorString(e));
@@ -529,9 +536,17 @@ int batch_steps(lks_mhd_batch *b, int64_t n, bool use_graph) {
     return LKS_EINVAL;
   }
   while (n > 0) {
-    if (use_graph && n >= 2 && b->parity == 0) {
+    if (use_graph && n >= kLongGraphSteps && b->parity == 0) {
+      if (!b->gexec_long) {
+        const int rc = capture(b, kLongGraphSteps, &b->gexec_long);
+        if (rc != LKS_OK) return rc;
+      }
+      LKS_HIP_CHECK(hipGraphLaunch(b->gexec_long, b->stream));
+      b->global_steps += kLongGraphSteps;
+      n -= kLongGraphSteps;
+    } else if (use_graph && n >= 2 && b->parity == 0) {
       if (!b->gexec) {
-        const int rc = capture(b);
+        const int rc = capture(b, 2, &b->gexec);
         if (rc != LKS_OK) return rc;
       }
       LKS_HIP_CHECK(hipGraphLaunch(b->gexec, b->stream));
@@ -648,6 +663,7 @@ int lks_mhd_batch_destroy(lks_mhd_batch_t *b) {
   clear_error();
   if (!b) return LKS_OK;
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->gexec_long) (void)hipGraphExecDestroy(b->gexec_long);
   delete b;
   return LKS_OK;
 }
