@@ -72,7 +72,7 @@ enum lks_bc { LKS_BC_LINK = 0, LKS_BC_MOMENT = 1 };
  *        rest, +x, +y, -x, -y populations), with Lambda at 1/tau_m (magnetic
  *        diffusivity) and epsilon, d at s_me, s_md.  With s_fe = s_feps =
  *        1/tau_f and s_me = s_md it is the TRT operator.  Available
- *        wherever TRT is except batches of LKS_FP16_STORE_F32.  In 3D, f
+ *        wherever TRT is.  In 3D, f
  *        uses the D3Q19 basis of
  *        d'Humieres et al. (Phil. Trans. R. Soc. A 360 (2002) 437): e at
  *        s_fe, epsilon and the fourth-order pi at s_feps, q and the

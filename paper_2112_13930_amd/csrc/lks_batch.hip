@@ -73,19 +73,19 @@ constexpr int kWidthClasses = 7;
 constexpr int NREDB = 6;
 
 // MRT channels run through the TRT scheme with their corrections switched on
-// (MRT_RT) where the arithmetic is FP64.  The binary16 batch with FP32
-// arithmetic does not carry them: they slowed it by 7.5% with no MRT channel
-// in it.
-template <typename C> constexpr int kMrtRt = sizeof(C) == 8 ? MRT_RT : 0;
+// per channel (MRT_RT).
 
 template <typename C> __device__ __forceinline__ const Coef<C> &coef_of(const ChanDesc &c);
 template <> __device__ __forceinline__ const Coef<float> &coef_of<float>(const ChanDesc &c) { return c.kf; }
 template <> __device__ __forceinline__ const Coef<double> &coef_of<double>(const ChanDesc &c) { return c.kd; }
 
 // Waves per SIMD the step asks the compiler for.  Binary16 storage with FP32
-// arithmetic fits 7 without spilling (72 registers against 76 unconstrained):
-// 1.7% faster.  Asking 5 of the FP64-arithmetic binary16 step (or 8 of the
-// FP32 one) spills, and ran 30% (16%) slower.
+// arithmetic runs at 7 (72 registers and 12 bytes of spill, against 82
+// registers and 5 waves unconstrained).  With its MRT corrections it then
+// runs as fast as without them (43.5 GLUPS on 256 uneven channels, against
+// 43.2 without the corrections at their unconstrained 6 waves).
+// Asking 5 of the FP64-arithmetic binary16 step (or 8 of the FP32 one)
+// spills more, and ran 30% (16%) slower.
 template <typename S, typename C, int MODE>
 constexpr int kBatchWaves = (MODE == MODE_STEP && sizeof(S) == 2 && sizeof(C) == 4) ? 7 : 1;
 
@@ -123,11 +123,11 @@ __global__ __launch_bounds__(kTileThreads, (kBatchWaves<S, C, MODE>)) void k_bat
                                                           y, o, sseed);
         break;
       case BC_LINK | COLL_TRT:
-        node_update<S, C, BC_LINK | COLL_TRT | kMrtRt<C> | IN_BATCH, MODE, SR>(
+        node_update<S, C, BC_LINK | COLL_TRT | MRT_RT | IN_BATCH, MODE, SR>(
             c.g, coef_of<C>(c), src, ref, dst, x, y, o, sseed);
         break;
       default:
-        node_update<S, C, BC_MOMENT | COLL_TRT | kMrtRt<C> | IN_BATCH, MODE, SR>(
+        node_update<S, C, BC_MOMENT | COLL_TRT | MRT_RT | IN_BATCH, MODE, SR>(
             c.g, coef_of<C>(c), src, ref, dst, x, y, o, sseed);
         break;
       }
@@ -692,10 +692,6 @@ int lks_mhd_batch_admit(lks_mhd_batch_t *b, const lks_mhd_params *p, int32_t *sl
   }
   if (q.q_lower != 0.5 || q.q_upper != 0.5) {
     set_error("invalid parameters: batches hold half-way walls only (q = 1/2)");
-    return LKS_EINVAL;
-  }
-  if (q.collision == LKS_MRT && q.precision == LKS_FP16_STORE_F32) {
-    set_error("invalid parameters: binary16 batches with FP32 arithmetic collide with BGK or TRT");
     return LKS_EINVAL;
   }
 

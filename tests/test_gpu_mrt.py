@@ -110,7 +110,7 @@ def test_mrt_run_to_steady_matches_oracle_residual(P):
     assert abs(res - r) < 1e-3 * r, (res, r)
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp16", "fp64"])
+@pytest.mark.parametrize("precision", ["fp32", "fp16", "fp64", "fp16_f32"])
 def test_mrt_trt_and_bgk_channels_in_one_batch_equal_solo_runs(P, precision):
     """The batched kernel runs MRT channels through its TRT scheme with the
     corrections switched on per channel: every channel of a mixed batch
@@ -135,14 +135,4 @@ def test_mrt_trt_and_bgk_channels_in_one_batch_equal_solo_runs(P, precision):
         solo.set_rebase(0)
         solo.step(13)
         assert torch.equal(b.save_state(s).cpu(), solo.save_state().cpu()), c
-    b.close()
-
-
-def test_binary16_fp32_arithmetic_batches_reject_mrt(P):
-    from paper_2112_13930_amd._lib import LksError, make_params
-    from paper_2112_13930_amd.batch import Batch
-    b = Batch("fp16_f32", max_channels=4, max_nodes=10_000)
-    with pytest.raises(LksError):
-        b.admit(make_params(16, 16, precision="fp16_f32", collision="mrt"))
-    b.admit(make_params(16, 16, precision="fp16_f32", collision="trt"))
     b.close()
