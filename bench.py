@@ -742,7 +742,7 @@ def main():
         return 0
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the channel path does not "
-              "shard across GPUs in this build.", file=sys.stderr)
+              "shard across GPUs.", file=sys.stderr)
         return 2
     if os.environ.get("WORLD_SIZE", "1") not in ("", "1"):
         print("bench.py runs as a single process on one GPU", file=sys.stderr)
