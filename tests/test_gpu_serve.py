@@ -54,30 +54,34 @@ def test_alone_equals_in_mix(P, precision):
         {r.rid: r.status for r in mixed.values()}
 
 
-def test_trt_and_mrt_requests_alone_equal_in_mix(P):
+@pytest.mark.parametrize("precision", ["fp32", "fp16_f32"])
+def test_trt_and_mrt_requests_alone_equal_in_mix(P, precision):
     """Requests with the TRT and MRT collisions share the service with BGK
-    ones: each result is the same alone and in the mix, and equals the plain
-    single-channel path."""
+    ones: each result is the same alone and in the mix, and (FP32 storage,
+    whose state involves no row rebase) equals the plain single-channel
+    path."""
     from paper_2112_13930_amd._lib import LKS_BGK, LKS_MRT, LKS_TRT
     from paper_2112_13930_amd.channel import Channel
     from paper_2112_13930_amd.serve import serve_requests_from_mix
 
     def requests():
         mix = serve_requests_from_mix(9, seed=4, nx_range=(4, 16), ny_range=(12, 24),
-                                      ha_range=(2.0, 10.0), precision="fp32", rate=2000.0)
+                                      ha_range=(2.0, 10.0), precision=precision, rate=2000.0)
         for r in mix:
             r.params.collision = (LKS_BGK, LKS_TRT, LKS_MRT)[r.rid % 3]
         return mix
 
-    mixed = serve(requests(), "fp32")
+    mixed = serve(requests(), precision)
     assert all(r.status != "unstable" for r in mixed.values())
     for rid in (1, 2, 4, 8):
         req = requests()[rid]
         req.arrival = 0.0
-        alone = serve([req], "fp32")[rid]
+        alone = serve([req], precision)[rid]
         m = mixed[rid]
         assert alone.status == m.status and alone.steps == m.steps, rid
         assert torch.equal(alone.result["state"], m.result["state"])
+        if precision != "fp32":
+            continue
         ch = Channel(params=req.params)
         ch.step(m.steps)
         assert torch.equal(ch.save_state().cpu(), m.result["state"])
