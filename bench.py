@@ -358,7 +358,8 @@ def other_precisions(torch, steps=200, warmup=20, err_steps=100_000):
 
     from paper_2112_13930_amd.channel import Channel
     out = {}
-    for prec, bpn, comp in (("fp16", 76, "f64"), ("fp16_f32", 76, "f32"), ("fp64", 304, "f64")):
+    for prec, bpn, comp in (("fp16", 76, "f32 arithmetic, f64 accumulation"),
+                            ("fp16_f64", 76, "f64"), ("fp64", 304, "f64")):
         _, per_step, ch = time_channel(torch, Channel, dict(HEADLINE, precision=prec), steps, warmup)
         ch.close()
         gbs = bpn * 4096 * 4096 / per_step / 1e9
@@ -373,7 +374,7 @@ def other_precisions(torch, steps=200, warmup=20, err_steps=100_000):
         ru = np.asarray(gold[f"ux_{err_steps}"])[:, None]
         rb = np.asarray(gold[f"bx_{err_steps}"])[:, None]
         errs = {}
-        for prec in ("fp32", "fp16", "fp16_f32"):
+        for prec in ("fp32", "fp16", "fp16_f64"):
             ch = Channel(512, 512, precision=prec, stream=torch.cuda.Stream(), **kw)
             ch.set_graph(40)
             ch.step(err_steps)
@@ -388,7 +389,8 @@ def other_precisions(torch, steps=200, warmup=20, err_steps=100_000):
                     "steps from rest; relative L2 of u_x and B_x (binary16 modes rebase every "
                     "1000 steps)",
             **errs}
-        # binary16 (FP64 arithmetic) run to steady state against the oracle's
+        # binary16 (the default mode: FP32 arithmetic) run to steady state
+        # against the oracle's
         ch = Channel(512, 512, precision="fp16", stream=torch.cuda.Stream(), **kw)
         ch.set_graph(40)
         t0 = time.perf_counter()

@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define LKS_MHD_ABI_VERSION 6
+#define LKS_MHD_ABI_VERSION 7
 
 typedef struct lks_mhd lks_mhd_t;             /* one channel, library-owned */
 typedef struct lks_mhd_batch lks_mhd_batch_t; /* many channels, library-owned */
@@ -86,23 +86,26 @@ enum lks_collision { LKS_BGK = 0, LKS_TRT = 1, LKS_MRT = 2 };
  *   FP32           stored as binary32 and computed in FP64; each stored value
  *                  is rounded stochastically to one of its two binary32
  *                  neighbours.
- *   FP16_STORE     stored as binary16 and computed in FP64, rounded
- *                  stochastically to binary16.
- *   FP16_STORE_F32 stored as binary16 and computed in FP32 (faster; the FP32
- *                  arithmetic leaves a systematic residual that slow modes of
- *                  strongly coupled channels amplify beyond 2e-3 relative).
+ *   FP16_STORE     stored as binary16 and computed in FP32 (equilibria,
+ *                  sources, the coupled u/J solve, the relaxation), rounded
+ *                  stochastically to binary16.  The collision's increments
+ *                  have the moments it conserves restored in FP64 (mass and
+ *                  B unchanged, momentum + F) and are added to the state in
+ *                  FP64, so FP32 rounding leaves no residual that slow modes
+ *                  of a steady channel could integrate.  Observables and
+ *                  state exchange decode in FP64.
+ *   FP16_STORE_F64 stored as binary16 and computed in FP64.
  * Every population is stored as its deviation from the rest state at unit
  * density with B = (0, B0): f_alpha - w_alpha, g_alpha,x and
  * g_alpha,y - W_alpha B0.  Binary16 storage further subtracts a per-row
- * reference R[y][alpha] held in the compute type, zero until a rebase
- * (lks_mhd_rebase) moves each row's mean over x into it, so binary16 then
- * carries only the x-variation and the change since the last rebase.  The random bits of stochastic
- * rounding are a
- * counter-based hash of (step since create or load, node, plane): a run is
- * reproducible bit for bit and does not depend on launch shape or on the
- * other channels of a batch.  Steady-state reductions are FP64 in every
- * mode. */
-enum lks_precision { LKS_FP64 = 0, LKS_FP32 = 1, LKS_FP16_STORE = 2, LKS_FP16_STORE_F32 = 3 };
+ * reference R[y][alpha] (FP32 values), zero until a rebase (lks_mhd_rebase)
+ * moves each row's mean over x into it, so binary16 then carries only the
+ * x-variation and the change since the last rebase, scaled by 2^12.  The
+ * random bits of stochastic rounding are a counter-based hash of (step since
+ * create or load, node, plane): a run is reproducible bit for bit and does
+ * not depend on launch shape or on the other channels of a batch.
+ * Steady-state reductions are FP64 in every mode. */
+enum lks_precision { LKS_FP64 = 0, LKS_FP32 = 1, LKS_FP16_STORE = 2, LKS_FP16_STORE_F64 = 3 };
 
 enum lks_status {
   LKS_OK = 0,

@@ -9,7 +9,7 @@ memory through PyTorch.
   Server   continuous-batching solve service (``serve.py``)
 """
 from ._lib import (BCS, LKS_BC_LINK, LKS_BC_MOMENT, LKS_EDEVICE, LKS_EINVAL,  # noqa: F401
-                   LKS_ENOMEM, LKS_ENOTCONV, LKS_EUNSTABLE, LKS_FP16_STORE, LKS_FP16_STORE_F32, LKS_FP32,
+                   LKS_ENOMEM, LKS_ENOTCONV, LKS_EUNSTABLE, LKS_FP16_STORE, LKS_FP16_STORE_F64, LKS_FP32,
                    LKS_FP64, LKS_OK, PRECISIONS, LksError, LksParams, derive, lib,
                    make_params)
 

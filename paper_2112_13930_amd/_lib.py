@@ -14,14 +14,15 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblks_mhd.so")
 
 LKS_BC_LINK, LKS_BC_MOMENT = 0, 1
-LKS_FP64, LKS_FP32, LKS_FP16_STORE, LKS_FP16_STORE_F32 = 0, 1, 2, 3
+LKS_FP64, LKS_FP32, LKS_FP16_STORE, LKS_FP16_STORE_F64 = 0, 1, 2, 3
 LKS_OK, LKS_EINVAL, LKS_ENOMEM, LKS_EDEVICE, LKS_EUNSTABLE, LKS_ENOTCONV = 0, -1, -2, -3, -4, -5
 STATUS_NAMES = {0: "LKS_OK", -1: "LKS_EINVAL", -2: "LKS_ENOMEM", -3: "LKS_EDEVICE",
                 -4: "LKS_EUNSTABLE", -5: "LKS_ENOTCONV"}
-# binary16 storage computed in FP64 ("fp16") or in FP32 ("fp16_f32")
+# binary16 storage computed in FP32 with FP64 accumulation ("fp16") or in
+# FP64 ("fp16_f64")
 PRECISIONS = {"fp64": LKS_FP64, "fp32": LKS_FP32, "fp16": LKS_FP16_STORE,
-              "fp16_f32": LKS_FP16_STORE_F32}
-STORE_BYTES = {"fp64": 8, "fp32": 4, "fp16": 2, "fp16_f32": 2}
+              "fp16_f64": LKS_FP16_STORE_F64}
+STORE_BYTES = {"fp64": 8, "fp32": 4, "fp16": 2, "fp16_f64": 2}
 BCS = {"link": LKS_BC_LINK, "moment": LKS_BC_MOMENT}
 LKS_BGK, LKS_TRT, LKS_MRT = 0, 1, 2
 COLLISIONS = {"bgk": LKS_BGK, "trt": LKS_TRT, "mrt": LKS_MRT}

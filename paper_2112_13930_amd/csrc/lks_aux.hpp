@@ -39,7 +39,7 @@ __global__ void k_save(Geom g, double b0, const S *__restrict__ src, const C *__
   const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
   const double Wm[5] = {1.0 / 3, 1.0 / 6, 1.0 / 6, 1.0 / 6, 1.0 / 6};
   for (int q = 0; q < 19; ++q) {
-    const double v = (double)dec<S, C>((C)src[q * g.plane + o], D + (long long)y * 19, q);
+    const double v = (double)dec<S, C>((C)src[q * g.plane + o], D + (long long)y * kRefRow, q);
     out[q * n + i] = q < 9 ? v + w[q] : (q < 14 ? v : v + Wm[q - 14] * b0);
   }
 }
@@ -93,21 +93,22 @@ __device__ __forceinline__ void rebase_row(S *__restrict__ buf, C *__restrict__ 
     const double mean = ((lds[tid] + lds[19 + tid]) + (lds[38 + tid] + lds[57 + tid])) / g.nx;
     const C m = (C)(mean * kStoreDown16);
     const C Dn = Drow[tid] + m;
-    const C shift = Dn - Drow[tid];
+    const double shift = (double)Dn - (double)Drow[tid]; // exact
     Drow[tid] = Dn;
-    lds[76 + tid] = (double)shift;
+    lds[76 + tid] = shift;
   }
   __syncthreads();
-  C sh[19];
+  double sh[19];
 #pragma unroll
-  for (int q = 0; q < 19; ++q) sh[q] = (C)lds[76 + q];
+  for (int q = 0; q < 19; ++q) sh[q] = lds[76 + q];
   for (int x = tid; x < g.nx; x += 256) {
     Rng rng(SR ? node_seed(seed, (uint32_t)(y * g.nx + x)) : 0u);
 #pragma unroll
     for (int q = 0; q < 19; ++q) {
       S *p = buf + q * g.plane + r0 + x;
-      *p = to_store<S, C, SR>(((C)*p * C(kStoreDown16) - sh[q]) * C(kStoreUp16),
-                              SR ? rng.next() : 0u);
+      // re-encoded in FP64 (exact for these magnitudes), then rounded once
+      *p = to_store<S, double, SR>(((double)*p * kStoreDown16 - sh[q]) * kStoreUp16,
+                                   SR ? rng.next() : 0u);
     }
   }
   __syncthreads(); // lds is reused by the next row
@@ -118,8 +119,16 @@ template <typename S, typename C>
 __global__ __launch_bounds__(256) void k_rebase_rows(Geom g, S *__restrict__ buf,
                                                      C *__restrict__ D, uint32_t step) {
   __shared__ double lds[5 * 19];
-  rebase_row<S, C, kUseSR<S, C>>(buf, D + (long long)blockIdx.x * 19, g, (int)blockIdx.x,
+  rebase_row<S, C, kUseSR<S, C>>(buf, D + (long long)blockIdx.x * kRefRow, g, (int)blockIdx.x,
                                  rebase_seed(step), lds);
+}
+
+// Pre-collision tables (XTabs) of every row of one channel whose binary16
+// state is computed in FP32; run after every change of the row references.
+template <int BC>
+__global__ __launch_bounds__(256) void k_xtables(Geom g, Coef<double> k, void *base) {
+  const int y = blockIdx.x * blockDim.x + threadIdx.x;
+  if (y < g.ny) xtab_row<BC>(g, k, xtabs_of(base, g.ny), y);
 }
 
 } // namespace lks

@@ -20,6 +20,7 @@
 #include <cstring>
 #include <map>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "lks_aux.hpp"
@@ -79,15 +80,9 @@ template <typename C> __device__ __forceinline__ const Coef<C> &coef_of(const Ch
 template <> __device__ __forceinline__ const Coef<float> &coef_of<float>(const ChanDesc &c) { return c.kf; }
 template <> __device__ __forceinline__ const Coef<double> &coef_of<double>(const ChanDesc &c) { return c.kd; }
 
-// Waves per SIMD the step asks the compiler for.  Binary16 storage with FP32
-// arithmetic runs at 7 (72 registers and 12 bytes of spill, against 82
-// registers and 5 waves unconstrained).  With its MRT corrections it then
-// runs as fast as without them (43.5 GLUPS on 256 uneven channels, against
-// 43.2 without the corrections at their unconstrained 6 waves).
-// Asking 5 of the FP64-arithmetic binary16 step (or 8 of the FP32 one)
-// spills more, and ran 30% (16%) slower.
+// Waves per SIMD the step asks the compiler for (1: no constraint).
 template <typename S, typename C, int MODE>
-constexpr int kBatchWaves = (MODE == MODE_STEP && sizeof(S) == 2 && sizeof(C) == 4) ? 7 : 1;
+constexpr int kBatchWaves = 1;
 
 // gctr[2]: global step counters as in the single-channel kernel; a channel's
 // own step index is gctr[parity] - step_base.
@@ -226,8 +221,21 @@ __global__ __launch_bounds__(256) void k_batch_rebase(const ChanDesc *__restrict
   if (y >= c.g.ny) return;
   const int cur = parity ^ c.phase;
   rebase_row<S, C, kUseSR<S, C>>(static_cast<S *>(c.buf[cur]),
-                                 static_cast<C *>(c.ref) + (long long)y * 19, c.g, y,
+                                 static_cast<C *>(c.ref) + (long long)y * kRefRow, c.g, y,
                                  rebase_seed(gctr[parity] - c.step_base), lds);
+}
+
+// Pre-collision tables of every active channel after a rebase (binary16
+// computed in FP32): block (row group, slot).
+__global__ __launch_bounds__(256) void k_batch_xtables(const ChanDesc *__restrict__ chans,
+                                                       const int *__restrict__ active) {
+  const int slot = blockIdx.y;
+  if (!active[slot]) return;
+  const ChanDesc &c = chans[slot];
+  const int y = blockIdx.x * blockDim.x + threadIdx.x;
+  if (y >= c.g.ny) return;
+  if (wall_of(c.bc) == BC_LINK) xtab_row<BC_LINK>(c.g, c.kd, xtabs_of(c.ref, c.g.ny), y);
+  else xtab_row<BC_MOMENT>(c.g, c.kd, xtabs_of(c.ref, c.g.ny), y);
 }
 
 } // namespace lks
@@ -321,7 +329,7 @@ size_t channel_region_bytes(const Channel &c, int precision) {
   const long long plane = plane_elems(c.p.nx, c.p.ny, precision);
   const size_t state = align256((size_t)19 * plane * elem_bytes(precision));
   const size_t rec = align256((size_t)2 * c.p.nx * c.p.ny * sizeof(double));
-  const size_t ref = align256((size_t)c.p.ny * 19 * sizeof(double));
+  const size_t ref = ref_area_bytes(c.p.ny, precision);
   return 2 * state + rec + ref;
 }
 
@@ -525,6 +533,11 @@ int batch_rebase(lks_mhd_batch *b) {
                          b->d_chans, b->d_active, b->parity, b->d_gctr);
   });
   LKS_HIP_CHECK(hipGetLastError());
+  if (b->precision == LKS_FP16_STORE) {
+    hipLaunchKernelGGL(k_batch_xtables, dim3((max_ny + 255) / 256, top), dim3(256), 0, b->stream,
+                       b->d_chans, b->d_active);
+    LKS_HIP_CHECK(hipGetLastError());
+  }
   return LKS_OK;
 }
 
@@ -757,10 +770,19 @@ int lks_mhd_batch_admit(lks_mhd_batch_t *b, const lks_mhd_params *p, int32_t *sl
       launch_init<typename decltype(t)::S>(b, sl, d.buf[0]);
     });
     LKS_HIP_CHECK(hipGetLastError());
-    const long long nr = (long long)q.ny * 19;
+    const long long nr = (long long)(ref_area_bytes(q.ny, b->precision) / sizeof(double));
     hipLaunchKernelGGL(k_zero<double>, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, b->stream,
                        static_cast<double *>(d.ref), nr);
     LKS_HIP_CHECK(hipGetLastError());
+    if (b->precision == LKS_FP16_STORE) {
+      // pre-collision tables of the FP32-arithmetic binary16 mode
+      const dim3 tg((unsigned)((q.ny + 255) / 256));
+      if (wall_of(d.bc) == BC_LINK)
+        hipLaunchKernelGGL(k_xtables<BC_LINK>, tg, dim3(256), 0, b->stream, d.g, d.kd, d.ref);
+      else
+        hipLaunchKernelGGL(k_xtables<BC_MOMENT>, tg, dim3(256), 0, b->stream, d.g, d.kd, d.ref);
+      LKS_HIP_CHECK(hipGetLastError());
+    }
     return LKS_OK;
   });
   if (rc != LKS_OK) {
@@ -918,9 +940,12 @@ int lks_mhd_batch_moments(lks_mhd_batch_t *b, int32_t slot, double *rho, double 
     const bool link = wall_of(d.bc) == BC_LINK;
     dispatch_precision(b->precision, [&](auto t) {
       using S = typename decltype(t)::S;
-      using C = typename decltype(t)::C;
+      // binary16 computed in FP32: observables decode in FP64
+      using C0 = typename decltype(t)::C;
+      using C = std::conditional_t<kXA<S, C0>, double, C0>;
       const S *src = static_cast<const S *>(d.buf[cur]);
-      const C *ref = static_cast<const C *>(d.ref);
+      const C *ref = kXA<S, C0> ? reinterpret_cast<const C *>(xtabs_of(d.ref, d.g.ny).D64)
+                                : static_cast<const C *>(d.ref);
       if (link)
         hipLaunchKernelGGL((k_chan_moments<S, C, BC_LINK>), grid, dim3(256), 0, b->stream, d.g,
                            coef_host<C>(d), src, ref, oo);
@@ -946,10 +971,13 @@ int lks_mhd_batch_save_state(lks_mhd_batch_t *b, int32_t slot, double *dev_pops)
   return with_device(b, [&]() -> int {
     dispatch_precision(b->precision, [&](auto t) {
       using S = typename decltype(t)::S;
-      using C = typename decltype(t)::C;
+      using C0 = typename decltype(t)::C;
+      using C = std::conditional_t<kXA<S, C0>, double, C0>;
+      const C *ref = kXA<S, C0> ? reinterpret_cast<const C *>(xtabs_of(d.ref, d.g.ny).D64)
+                                : static_cast<const C *>(d.ref);
       hipLaunchKernelGGL((k_save<S, C>), grid, dim3(256), 0, b->stream, d.g,
-                         b->slots[slot].ch.d.b0, static_cast<const S *>(d.buf[cur]),
-                         static_cast<const C *>(d.ref), dev_pops);
+                         b->slots[slot].ch.d.b0, static_cast<const S *>(d.buf[cur]), ref,
+                         dev_pops);
     });
     LKS_HIP_CHECK(hipGetLastError());
     return LKS_OK;

@@ -116,11 +116,11 @@ inline int scheme_of(const lks_mhd_params &p) {
 }
 
 inline bool valid_precision(int precision) {
-  return precision >= LKS_FP64 && precision <= LKS_FP16_STORE_F32;
+  return precision >= LKS_FP64 && precision <= LKS_FP16_STORE_F64;
 }
 
 inline bool is_binary16(int precision) {
-  return precision == LKS_FP16_STORE || precision == LKS_FP16_STORE_F32;
+  return precision == LKS_FP16_STORE || precision == LKS_FP16_STORE_F64;
 }
 
 inline size_t elem_bytes(int precision) {
@@ -139,8 +139,8 @@ decltype(auto) dispatch_precision(int precision, F &&f) {
   switch (precision) {
   case LKS_FP64: return f(Types<double, double>{});
   case LKS_FP32: return f(Types<float, Fp32Compute>{});
-  case LKS_FP16_STORE: return f(Types<_Float16, double>{});
-  default: return f(Types<_Float16, float>{});
+  case LKS_FP16_STORE: return f(Types<_Float16, float>{});
+  default: return f(Types<_Float16, double>{});
   }
 }
 
@@ -152,5 +152,13 @@ inline long long plane_elems(int nx, int ny, int precision) {
 }
 
 inline size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+// Device bytes of a channel's row-reference area: the FP32-arithmetic
+// binary16 mode keeps its four tables (XTabs), the others one row reference
+// of doubles (used by binary16 storage only).
+inline size_t ref_area_bytes(int ny, int precision) {
+  return precision == LKS_FP16_STORE ? (size_t)xtabs_total_bytes(ny)
+                                     : align256((size_t)ny * kRefRow * sizeof(double));
+}
 
 } // namespace lks

@@ -28,6 +28,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "lks_sr.hpp"
 
 // Arithmetic of the reduced-precision modes (compile-time; the defaults are
@@ -173,6 +175,7 @@ struct Geom {
 template <typename C>
 struct NodeObs {
   C rho, rhop, ux, uy, bx, by, jz; // rhop = rho - 1 as accumulated from the deviations
+  C fx, fy;                        // total force the collision adds to the momentum
 };
 
 // Every stored population is read once per step (pull).  A pull along x
@@ -227,6 +230,9 @@ constexpr bool kUseSR = (sizeof(C) > sizeof(S)) &&
 // limit 65504.
 template <typename S> constexpr bool kRowRef = sizeof(S) == 2;
 constexpr double kStoreUp16 = 4096.0, kStoreDown16 = 1.0 / 4096.0;
+// Elements per row of the reference tables (19 planes, padded for aligned
+// vector loads).
+constexpr int kRefRow = 20;
 
 // Decode a stored value with the reference row it belongs to.
 template <typename S, typename C>
@@ -249,7 +255,8 @@ template <typename C> struct W {
 //   f~' = f' + omega (feq' - f') + kappa S,
 //   feq' = w (rho' + rho poly),  S = 3 w (e.F - u.F) (1 + poly),
 //   poly = 3 e.u + 4.5 (e.u)^2 - 1.5 u.u.
-template <typename C>
+// INC: the increment f~' - f' instead of the new value.
+template <typename C, bool INC = false>
 __device__ __forceinline__ C collide_f(C f, C w, C ex, C ey, C rhop, C rho,
                                        C ux, C uy, C usq15, C Fx, C Fy, C uF,
                                        C omega, C kappa) {
@@ -257,12 +264,13 @@ __device__ __forceinline__ C collide_f(C f, C w, C ex, C ey, C rhop, C rho,
   const C poly = C(3) * eu + C(4.5) * eu * eu - usq15;
   const C feq = w * (rhop + rho * poly);
   const C S = C(3) * w * (ex * Fx + ey * Fy - uF) * (C(1) + poly);
-  return f + omega * (feq - f) + kappa * S;
+  if constexpr (INC) return omega * (feq - f) + kappa * S;
+  else return f + omega * (feq - f) + kappa * S;
 }
 
 // Two-relaxation-time update of the pair (a, abar) of opposite f
 // populations in deviation form (see Trt); eu = e_a.u and eF = e_a.F.
-template <typename C>
+template <typename C, bool INC = false>
 __device__ __forceinline__ void collide_f_pair(C &fa, C &fb, C w, C eu, C eF, C rhop, C rho,
                                                C usq15, C uF, const Trt<C> &t) {
   const C even = C(4.5) * eu * eu - usq15;
@@ -272,15 +280,22 @@ __device__ __forceinline__ void collide_f_pair(C &fa, C &fb, C w, C eu, C eF, C 
   const C nb = w * (rhop + rho * pb) - fb;
   const C Sa = C(3) * w * (eF - uF) * (C(1) + pa);
   const C Sb = C(3) * w * (-eF - uF) * (C(1) + pb);
-  const C ra = fa + t.fa * na + t.fb * nb + t.fsa * Sa + t.fsb * Sb;
-  const C rb = fb + t.fa * nb + t.fb * na + t.fsa * Sb + t.fsb * Sa;
-  fa = ra;
-  fb = rb;
+  if constexpr (INC) {
+    const C ra = t.fa * na + t.fb * nb + t.fsa * Sa + t.fsb * Sb;
+    const C rb = t.fa * nb + t.fb * na + t.fsa * Sb + t.fsb * Sa;
+    fa = ra;
+    fb = rb;
+  } else {
+    const C ra = fa + t.fa * na + t.fb * nb + t.fsa * Sa + t.fsb * Sb;
+    const C rb = fb + t.fa * nb + t.fb * na + t.fsa * Sb + t.fsb * Sa;
+    fa = ra;
+    fb = rb;
+  }
 }
 
 // The same, also returning (n_a + n_abar) - (S_a + S_abar)/2, the pair's
 // part of what the MRT corrections of the even moments e and epsilon act on.
-template <typename C>
+template <typename C, bool INC = false>
 __device__ __forceinline__ void collide_f_pair(C &fa, C &fb, C w, C eu, C eF, C rhop, C rho,
                                                C usq15, C uF, const Trt<C> &t, C &tsum) {
   const C even = C(4.5) * eu * eu - usq15;
@@ -290,22 +305,191 @@ __device__ __forceinline__ void collide_f_pair(C &fa, C &fb, C w, C eu, C eF, C 
   const C nb = w * (rhop + rho * pb) - fb;
   const C Sa = C(3) * w * (eF - uF) * (C(1) + pa);
   const C Sb = C(3) * w * (-eF - uF) * (C(1) + pb);
-  const C ra = fa + t.fa * na + t.fb * nb + t.fsa * Sa + t.fsb * Sb;
-  const C rb = fb + t.fa * nb + t.fb * na + t.fsa * Sb + t.fsb * Sa;
-  fa = ra;
-  fb = rb;
+  if constexpr (INC) {
+    const C ra = t.fa * na + t.fb * nb + t.fsa * Sa + t.fsb * Sb;
+    const C rb = t.fa * nb + t.fb * na + t.fsa * Sb + t.fsb * Sa;
+    fa = ra;
+    fb = rb;
+  } else {
+    const C ra = fa + t.fa * na + t.fb * nb + t.fsa * Sa + t.fsb * Sb;
+    const C rb = fb + t.fa * nb + t.fb * na + t.fsa * Sb + t.fsb * Sa;
+    fa = ra;
+    fb = rb;
+  }
   tsum = (na + nb) - C(0.5) * (Sa + Sb);
 }
 
 // Two-relaxation-time update of a pair of opposite g populations with
 // equilibria ea, eb.
-template <typename C>
+template <typename C, bool INC = false>
 __device__ __forceinline__ void collide_g_pair(C &ga, C &gb, C ea, C eb, const Trt<C> &t) {
   const C na = ea - ga, nb = eb - gb;
-  const C ra = ga + t.ga * na + t.gb * nb;
-  const C rb = gb + t.ga * nb + t.gb * na;
-  ga = ra;
-  gb = rb;
+  if constexpr (INC) {
+    const C ra = t.ga * na + t.gb * nb;
+    const C rb = t.ga * nb + t.gb * na;
+    ga = ra;
+    gb = rb;
+  } else {
+    const C ra = ga + t.ga * na + t.gb * nb;
+    const C rb = gb + t.ga * nb + t.gb * na;
+    ga = ra;
+    gb = rb;
+  }
+}
+
+// ---- wall closures of the populations entering from a wall ----
+
+// Enclosure walls at x = -1/2 and nx - 1/2 (parallel to the imposed field,
+// stationary): bounce-back of f, theta closure of the induced tangential
+// b_y (stored as g_y - W B0), anti-bounce-back of B_x.  The values pulled
+// across the wall (periodic addresses) are replaced from the node's own
+// previous values; a Hartmann closure applied afterwards takes the corner
+// links that cross it.
+template <typename S, typename C>
+__device__ __forceinline__ void xwall_closure(const Geom &g, const Coef<C> &k,
+                                              const S *__restrict__ src,
+                                              const C *__restrict__ Dy, int x, int y,
+                                              C (&f)[9], C (&gx)[5], C (&gy)[5]) {
+  const long long P = g.plane;
+  const long long r0 = (long long)y * g.pitch;
+  if (x == 0) {
+    f[1] = dec<S>(ld<S, C>(src + 3 * P + r0 + x), Dy, 3);
+    f[5] = dec<S>(ld<S, C>(src + 7 * P + r0 + x), Dy, 7);
+    f[8] = dec<S>(ld<S, C>(src + 6 * P + r0 + x), Dy, 6);
+    gx[1] = -dec<S>(ld<S, C>(src + 12 * P + r0 + x), Dy, 12);
+    gy[1] = k.xr_lo * dec<S>(ld<S, C>(src + 17 * P + r0 + x), Dy, 17);
+  }
+  if (x == g.nx - 1) {
+    f[3] = dec<S>(ld<S, C>(src + 1 * P + r0 + x), Dy, 1);
+    f[6] = dec<S>(ld<S, C>(src + 8 * P + r0 + x), Dy, 8);
+    f[7] = dec<S>(ld<S, C>(src + 5 * P + r0 + x), Dy, 5);
+    gx[3] = -dec<S>(ld<S, C>(src + 10 * P + r0 + x), Dy, 10);
+    gy[3] = k.xr_hi * dec<S>(ld<S, C>(src + 15 * P + r0 + x), Dy, 15);
+  }
+}
+
+// Link-based Hartmann walls at cut distances (Cut<C>).
+template <typename S, typename C>
+__device__ __forceinline__ void cut_closure(const Geom &g, const Coef<C> &k,
+                                            const S *__restrict__ src,
+                                            const C *__restrict__ ref, int x, int y,
+                                            C (&f)[9], C (&gx)[5], C (&gy)[5]) {
+  const long long P = g.plane;
+  const bool lo = (y == 0);
+  const bool hi = (y == g.ny - 1);
+  // s = +1 at the lower wall, -1 at the upper (the e_y of the incoming
+  // populations)
+  auto at = [&](int plane, int yy, int xx) -> C {
+    return dec<S>(ld<S, C>(src + plane * P + (long long)yy * g.pitch + xx),
+                  ref + (long long)yy * kRefRow, plane);
+  };
+  const int xm = (x == 0) ? g.nx - 1 : x - 1, xp = (x == g.nx - 1) ? 0 : x + 1;
+  auto close = [&](const Cut<C> &c, int s, C uw6) {
+    // incoming f: normal a0, diagonals a1 (e_x = +1), a2 (e_x = -1), each
+    // with its opposite (outgoing) plane
+    const int a0 = s > 0 ? 2 : 4, a1 = s > 0 ? 5 : 8, a2 = s > 0 ? 6 : 7;
+    const int o0 = s > 0 ? 4 : 2, o1 = s > 0 ? 7 : 6, o2 = s > 0 ? 8 : 5;
+    const int yn = y + s;
+    const C out0 = at(o0, y, x), out1 = at(o1, y, x), out2 = at(o2, y, x);
+    const C X0 = c.near ? at(o0, yn, x) : at(a0, y, x);
+    const C X1 = c.near ? at(o1, yn, xp) : at(a1, y, x);
+    const C X2 = c.near ? at(o2, yn, xm) : at(a2, y, x);
+    const C n0 = c.fa * out0 + c.fb * X0;
+    const C n1 = c.fa * out1 + c.fb * X1 + c.lscale * uw6;
+    const C n2 = c.fa * out2 + c.fb * X2 - c.lscale * uw6;
+    const C defect = (out0 + out1 + out2) - (n0 + n1 + n2);
+    f[a0] = n0 + defect * (C(2) / C(3));
+    f[a1] = n1 + defect * (C(1) / C(6));
+    f[a2] = n2 + defect * (C(1) / C(6));
+    // field: the D2Q5 link entering from the wall and its outgoing one
+    const int gi = s > 0 ? 2 : 4, go = s > 0 ? 4 : 2;
+    const C yo = at(14 + go, y, x);
+    const C yX = c.near ? at(14 + go, yn, x) : at(14 + gi, y, x);
+    gy[gi] = c.za * yo + c.zb * yX;
+    const C xo = at(9 + go, y, x);
+    if (!c.conducting) {
+      const C xX = c.near ? at(9 + go, yn, x) : at(9 + gi, y, x);
+      gx[gi] = c.za * xo + c.zb * xX;
+    } else {
+      const C x1 = at(9 + go, yn, x), x2 = at(9 + go, yn + s, x);
+      C rhop = C(0), mx = C(0);
+#pragma unroll
+      for (int b = 0; b < 9; ++b) {
+        const C v = at(b, y, x);
+        rhop += v;
+        mx += C(b == 1 || b == 5 || b == 8 ? 1 : (b == 3 || b == 6 || b == 7 ? -1 : 0)) * v;
+      }
+      const C un = mx / (C(1) + rhop);
+      gx[gi] = c.r * xo + c.kappa * (x2 - C(2) * x1 + xo) + c.tmove + c.tshear * (un - c.u);
+    }
+  };
+  // upper wall: the diagonal a1 = 8 has e_x = +1, a2 = 7 has e_x = -1;
+  // Ladd's term is -U/6 on 7 and +U/6 on 8
+  if (lo) close(k.clo, +1, k.lo.uw6);
+  if (hi) close(k.chi, -1, k.hi.uw6);
+}
+
+// The paper's two Hartmann-wall closures (walls half-way between rows for
+// the link-based scheme, on the wall rows for the moment-based one) as
+// affine maps of the node's values: closed = A(values) + b.  For the link
+// scheme the values are the node's own post-collision populations leaving
+// through the wall, own[] = (f_4, f_7, f_8, g_4x, g_4y) at the lower wall and
+// (f_2, f_5, f_6, g_2x, g_2y) at the upper one; for the moment scheme they are
+// the node's known post-streaming populations in f, gx, gy.  AFF false
+// applies A alone, to deviations from a reference state whose closed values
+// carry b.
+//   link:   half-way bounce-back of f with Ladd's moving-wall term; the
+//           theta-weighted bounce-back/anti-bounce-back of g_x; anti-bounce-
+//           back to B_y = B0 of g_y, which for the deviations g_y - W B0 is
+//           g'_in = -g~'_out (Sec. VI Eq. linkbasedBCschemefinal, App. B.1).
+//   moment: f from the moment constraints Pi_10 = rho U, Pi_01 = 0,
+//           Pi_20 = rho (cs2 + U^2) written for the deviations f' = f - w;
+//           g_x from the discrete Shercliff relation; g_y from sum g_y = B0
+//           (Sec. VII, App. A, App. B.2).
+template <typename T, int WALL, bool AFF>
+__device__ __forceinline__ void hartmann_closure(bool lo, bool hi, T (&f)[9], T (&gx)[5],
+                                                 T (&gy)[5], const T (&own)[5],
+                                                 const Wall<T> &wl, const Wall<T> &wh) {
+  const T one = AFF ? T(1) : T(0);
+  if constexpr (WALL == BC_LINK) {
+    if (lo) {
+      f[2] = own[0];
+      f[5] = AFF ? own[1] + wl.uw6 : own[1];
+      f[6] = AFF ? own[2] - wl.uw6 : own[2];
+      gx[2] = AFF ? wl.r * own[3] + wl.t : wl.r * own[3];
+      gy[2] = -own[4];
+    }
+    if (hi) {
+      f[4] = own[0];
+      f[7] = AFF ? own[1] - wh.uw6 : own[1];
+      f[8] = AFF ? own[2] + wh.uw6 : own[2];
+      gx[4] = AFF ? wh.r * own[3] + wh.t : wh.r * own[3];
+      gy[4] = -own[4];
+    }
+  } else {
+    if (lo) {
+      const T U = wl.u;
+      const T rhop = f[0] + f[1] + f[3] + T(2) * (f[4] + f[7] + f[8]);
+      const T rho = one + rhop;
+      f[2] = -rhop * (T(1) / T(3)) - rho * U * U + (f[1] + f[3] + f[4] + T(2) * (f[7] + f[8]));
+      f[5] = rhop * (T(1) / T(6)) + T(0.5) * rho * (U * U + U) - (f[1] + f[8]);
+      f[6] = rhop * (T(1) / T(6)) + T(0.5) * rho * (U * U - U) - (f[3] + f[7]);
+      gx[2] = AFF ? wl.r * gx[4] - wl.s * (gx[0] + gx[1] + gx[3]) + wl.t
+                  : wl.r * gx[4] - wl.s * (gx[0] + gx[1] + gx[3]);
+      gy[2] = -(gy[0] + gy[1] + gy[3] + gy[4]); // sum g_y = B0
+    }
+    if (hi) {
+      const T U = wh.u;
+      const T rhop = f[0] + f[1] + f[3] + T(2) * (f[2] + f[5] + f[6]);
+      const T rho = one + rhop;
+      f[4] = -rhop * (T(1) / T(3)) - rho * U * U + (f[1] + f[2] + f[3] + T(2) * (f[5] + f[6]));
+      f[7] = rhop * (T(1) / T(6)) + T(0.5) * rho * (U * U - U) - (f[3] + f[6]);
+      f[8] = rhop * (T(1) / T(6)) + T(0.5) * rho * (U * U + U) - (f[1] + f[5]);
+      gx[4] = AFF ? wh.r * gx[2] - wh.s * (gx[0] + gx[1] + gx[3]) + wh.t
+                  : wh.r * gx[2] - wh.s * (gx[0] + gx[1] + gx[3]);
+      gy[4] = -(gy[0] + gy[1] + gy[2] + gy[3]); // sum g_y = B0
+    }
+  }
 }
 
 // Everything after streaming for one node: wall closure, moments, coupled
@@ -314,133 +498,39 @@ __device__ __forceinline__ void collide_g_pair(C &ga, C &gb, C ea, C eb, const T
 // link-based closure reads the node's own previous values from src).  The
 // 19 new stored values (rounded to S) are returned in out (not for
 // MODE_MOMENTS).
-template <typename S, typename C, int BC, int MODE, bool SR>
+// XA: the caller has applied every closure already, and the collision's
+// increments (new minus old value) are returned in f, gx, gy instead; the
+// caller accumulates and stores them (node_finish_x).
+template <typename S, typename C, int BC, int MODE, bool SR, bool XA = false>
 __device__ __forceinline__ void node_finish(const Geom &g, const Coef<C> &k,
                                             const S *__restrict__ src,
                                             const C *__restrict__ ref, int x, int y,
                                             C (&f)[9], C (&gx)[5], C (&gy)[5],
                                             NodeObs<C> &obs, uint32_t sseed, S (&out)[19]) {
-  const long long P = g.plane;
   const bool lo = (y == 0);
   const bool hi = (y == g.ny - 1);
-  const long long r0 = (long long)y * g.pitch;
-  const C *__restrict__ Dy = ref + (long long)y * 19; // reference of this row
+  const C *__restrict__ Dy = ref + (long long)y * kRefRow; // reference of this row
   // ---- wall closures for the populations entering from a wall ----
-  if constexpr (xwalls_of(BC)) {
-    // Enclosure walls at x = -1/2 and nx - 1/2 (parallel to the imposed
-    // field, stationary): bounce-back of f, theta closure of the induced
-    // tangential b_y (stored as g_y - W B0), anti-bounce-back of B_x.  The
-    // values pulled across the wall (periodic addresses) are replaced; the
-    // Hartmann closure below then takes the corner links that cross it.
-    if (x == 0) {
-      f[1] = dec<S>(ld<S, C>(src + 3 * P + r0 + x), Dy, 3);
-      f[5] = dec<S>(ld<S, C>(src + 7 * P + r0 + x), Dy, 7);
-      f[8] = dec<S>(ld<S, C>(src + 6 * P + r0 + x), Dy, 6);
-      gx[1] = -dec<S>(ld<S, C>(src + 12 * P + r0 + x), Dy, 12);
-      gy[1] = k.xr_lo * dec<S>(ld<S, C>(src + 17 * P + r0 + x), Dy, 17);
-    }
-    if (x == g.nx - 1) {
-      f[3] = dec<S>(ld<S, C>(src + 1 * P + r0 + x), Dy, 1);
-      f[6] = dec<S>(ld<S, C>(src + 8 * P + r0 + x), Dy, 8);
-      f[7] = dec<S>(ld<S, C>(src + 5 * P + r0 + x), Dy, 5);
-      gx[3] = -dec<S>(ld<S, C>(src + 10 * P + r0 + x), Dy, 10);
-      gy[3] = k.xr_hi * dec<S>(ld<S, C>(src + 15 * P + r0 + x), Dy, 15);
-    }
-  }
-  if constexpr (wall_of(BC) == BC_LINK && cut_of(BC)) {
-    // Hartmann walls at cut distances (Cut<C>); s = +1 at the lower wall,
-    // -1 at the upper (the e_y of the incoming populations)
-    auto at = [&](int plane, int yy, int xx) -> C {
-      return dec<S>(ld<S, C>(src + plane * P + (long long)yy * g.pitch + xx),
-                    ref + (long long)yy * 19, plane);
-    };
-    const int xm = (x == 0) ? g.nx - 1 : x - 1, xp = (x == g.nx - 1) ? 0 : x + 1;
-    auto close = [&](const Cut<C> &c, int s, C uw6) {
-      // incoming f: normal a0, diagonals a1 (e_x = +1), a2 (e_x = -1), each
-      // with its opposite (outgoing) plane
-      const int a0 = s > 0 ? 2 : 4, a1 = s > 0 ? 5 : 8, a2 = s > 0 ? 6 : 7;
-      const int o0 = s > 0 ? 4 : 2, o1 = s > 0 ? 7 : 6, o2 = s > 0 ? 8 : 5;
-      const int yn = y + s;
-      const C out0 = at(o0, y, x), out1 = at(o1, y, x), out2 = at(o2, y, x);
-      const C X0 = c.near ? at(o0, yn, x) : at(a0, y, x);
-      const C X1 = c.near ? at(o1, yn, xp) : at(a1, y, x);
-      const C X2 = c.near ? at(o2, yn, xm) : at(a2, y, x);
-      const C n0 = c.fa * out0 + c.fb * X0;
-      const C n1 = c.fa * out1 + c.fb * X1 + c.lscale * uw6;
-      const C n2 = c.fa * out2 + c.fb * X2 - c.lscale * uw6;
-      const C defect = (out0 + out1 + out2) - (n0 + n1 + n2);
-      f[a0] = n0 + defect * (C(2) / C(3));
-      f[a1] = n1 + defect * (C(1) / C(6));
-      f[a2] = n2 + defect * (C(1) / C(6));
-      // field: the D2Q5 link entering from the wall and its outgoing one
-      const int gi = s > 0 ? 2 : 4, go = s > 0 ? 4 : 2;
-      const C yo = at(14 + go, y, x);
-      const C yX = c.near ? at(14 + go, yn, x) : at(14 + gi, y, x);
-      gy[gi] = c.za * yo + c.zb * yX;
-      const C xo = at(9 + go, y, x);
-      if (!c.conducting) {
-        const C xX = c.near ? at(9 + go, yn, x) : at(9 + gi, y, x);
-        gx[gi] = c.za * xo + c.zb * xX;
-      } else {
-        const C x1 = at(9 + go, yn, x), x2 = at(9 + go, yn + s, x);
-        C rhop = C(0), mx = C(0);
-#pragma unroll
-        for (int b = 0; b < 9; ++b) {
-          const C v = at(b, y, x);
-          rhop += v;
-          mx += C(b == 1 || b == 5 || b == 8 ? 1 : (b == 3 || b == 6 || b == 7 ? -1 : 0)) * v;
-        }
-        const C un = mx / (C(1) + rhop);
-        gx[gi] = c.r * xo + c.kappa * (x2 - C(2) * x1 + xo) + c.tmove + c.tshear * (un - c.u);
+  if constexpr (!XA) {
+    if constexpr (xwalls_of(BC)) xwall_closure<S, C>(g, k, src, Dy, x, y, f, gx, gy);
+    if constexpr (wall_of(BC) == BC_LINK && cut_of(BC)) {
+      cut_closure<S, C>(g, k, src, ref, x, y, f, gx, gy);
+    } else if constexpr (wall_of(BC) == BC_LINK) {
+      if (lo || hi) {
+        const long long P = g.plane;
+        const long long r0 = (long long)y * g.pitch;
+        // the node's own post-collision values leaving through the wall
+        const int p0 = lo ? 4 : 2, p1 = lo ? 7 : 5, p2 = lo ? 8 : 6;
+        const C own[5] = {dec<S>(ld<S, C>(src + p0 * P + r0 + x), Dy, p0),
+                          dec<S>(ld<S, C>(src + p1 * P + r0 + x), Dy, p1),
+                          dec<S>(ld<S, C>(src + p2 * P + r0 + x), Dy, p2),
+                          dec<S>(ld<S, C>(src + (9 + p0) * P + r0 + x), Dy, 9 + p0),
+                          dec<S>(ld<S, C>(src + (14 + p0) * P + r0 + x), Dy, 14 + p0)};
+        hartmann_closure<C, BC_LINK, true>(lo, hi, f, gx, gy, own, k.lo, k.hi);
       }
-    };
-    // upper wall: the diagonal a1 = 8 has e_x = +1, a2 = 7 has e_x = -1;
-    // Ladd's term is -U/6 on 7 and +U/6 on 8
-    if (lo) close(k.clo, +1, k.lo.uw6);
-    if (hi) close(k.chi, -1, k.hi.uw6);
-  } else if (wall_of(BC) == BC_LINK) {
-    // Half-way bounce-back of f with Ladd's moving-wall term; theta-weighted
-    // bounce-back/anti-bounce-back of g_x; anti-bounce-back to B_y = B0 for
-    // g_y, which for the deviations g_y - W B0 is g'_in = -g~'_out.  All from
-    // the node's own post-collision values.
-    if (lo) {
-      f[2] = dec<S>(ld<S, C>(src + 4 * P + r0 + x), Dy, 4);
-      f[5] = dec<S>(ld<S, C>(src + 7 * P + r0 + x), Dy, 7) + k.lo.uw6;
-      f[6] = dec<S>(ld<S, C>(src + 8 * P + r0 + x), Dy, 8) - k.lo.uw6;
-      gx[2] = k.lo.r * dec<S>(ld<S, C>(src + 13 * P + r0 + x), Dy, 13) + k.lo.t;
-      gy[2] = -dec<S>(ld<S, C>(src + 18 * P + r0 + x), Dy, 18);
-    }
-    if (hi) {
-      f[4] = dec<S>(ld<S, C>(src + 2 * P + r0 + x), Dy, 2);
-      f[7] = dec<S>(ld<S, C>(src + 5 * P + r0 + x), Dy, 5) - k.hi.uw6;
-      f[8] = dec<S>(ld<S, C>(src + 6 * P + r0 + x), Dy, 6) + k.hi.uw6;
-      gx[4] = k.hi.r * dec<S>(ld<S, C>(src + 11 * P + r0 + x), Dy, 11) + k.hi.t;
-      gy[4] = -dec<S>(ld<S, C>(src + 16 * P + r0 + x), Dy, 16);
-    }
-  } else {
-    // On-node closures from the moment constraints, written for the
-    // deviations f' = f - w (the weights of each relation sum out).
-    if (lo) {
-      const C U = k.lo.u;
-      const C rhop = f[0] + f[1] + f[3] + C(2) * (f[4] + f[7] + f[8]);
-      const C rho = C(1) + rhop;
-      f[2] = -rhop * (C(1) / C(3)) - rho * U * U +
-             (f[1] + f[3] + f[4] + C(2) * (f[7] + f[8]));
-      f[5] = rhop * (C(1) / C(6)) + C(0.5) * rho * (U * U + U) - (f[1] + f[8]);
-      f[6] = rhop * (C(1) / C(6)) + C(0.5) * rho * (U * U - U) - (f[3] + f[7]);
-      gx[2] = k.lo.r * gx[4] - k.lo.s * (gx[0] + gx[1] + gx[3]) + k.lo.t;
-      gy[2] = -(gy[0] + gy[1] + gy[3] + gy[4]); // sum g_y = B0
-    }
-    if (hi) {
-      const C U = k.hi.u;
-      const C rhop = f[0] + f[1] + f[3] + C(2) * (f[2] + f[5] + f[6]);
-      const C rho = C(1) + rhop;
-      f[4] = -rhop * (C(1) / C(3)) - rho * U * U +
-             (f[1] + f[2] + f[3] + C(2) * (f[5] + f[6]));
-      f[7] = rhop * (C(1) / C(6)) + C(0.5) * rho * (U * U - U) - (f[3] + f[6]);
-      f[8] = rhop * (C(1) / C(6)) + C(0.5) * rho * (U * U + U) - (f[1] + f[5]);
-      gx[4] = k.hi.r * gx[2] - k.hi.s * (gx[0] + gx[1] + gx[3]) + k.hi.t;
-      gy[4] = -(gy[0] + gy[1] + gy[2] + gy[3]); // sum g_y = B0
+    } else {
+      const C none[5] = {C(0), C(0), C(0), C(0), C(0)};
+      hartmann_closure<C, BC_MOMENT, true>(lo, hi, f, gx, gy, none, k.lo, k.hi);
     }
   }
 
@@ -485,12 +575,14 @@ __device__ __forceinline__ void node_finish(const Geom &g, const Coef<C> &k,
   obs.bx = bx;
   obs.by = by;
   obs.jz = jz;
+  obs.fx = Fx;
+  obs.fy = Fy;
   if (MODE == MODE_MOMENTS) return;
 
   // ---- collide and store ----
   // random words for the stochastic rounding of this node's 19 stores,
   // drawn in plane order
-  Rng rng(SR ? node_seed(sseed, (uint32_t)(y * g.nx + x)) : 0u);
+  Rng rng(SR && !XA ? node_seed(sseed, (uint32_t)(y * g.nx + x)) : 0u);
   // encode a post-collision value against this row's reference
   auto put = [&](C v, int plane) -> S {
     (void)plane;
@@ -517,14 +609,14 @@ __device__ __forceinline__ void node_finish(const Geom &g, const Coef<C> &k,
     const bool mrt_now = mrt_of(BC) || (mrt_rt_of(BC) && k.mrt_on != 0);
     const C t0 = (w0 * (rhop - rho * usq15) - f[0]) - C(0.5) * (C(3) * w0 * (-uF) * (C(1) - usq15));
     C te = C(-4) * t0, tp = C(4) * t0, tq;
-    f[0] = collide_f(f[0], w0, C(0), C(0), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka);
-    collide_f_pair(f[1], f[3], w1, ux, Fx, rhop, rho, usq15, uF, t, tq);
+    f[0] = collide_f<C, XA>(f[0], w0, C(0), C(0), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka);
+    collide_f_pair<C, XA>(f[1], f[3], w1, ux, Fx, rhop, rho, usq15, uF, t, tq);
     te -= tq, tp -= C(2) * tq;
-    collide_f_pair(f[2], f[4], w1, uy, Fy, rhop, rho, usq15, uF, t, tq);
+    collide_f_pair<C, XA>(f[2], f[4], w1, uy, Fy, rhop, rho, usq15, uF, t, tq);
     te -= tq, tp -= C(2) * tq;
-    collide_f_pair(f[5], f[7], w5, ux + uy, Fx + Fy, rhop, rho, usq15, uF, t, tq);
+    collide_f_pair<C, XA>(f[5], f[7], w5, ux + uy, Fx + Fy, rhop, rho, usq15, uF, t, tq);
     te += C(2) * tq, tp += tq;
-    collide_f_pair(f[6], f[8], w5, uy - ux, Fy - Fx, rhop, rho, usq15, uF, t, tq);
+    collide_f_pair<C, XA>(f[6], f[8], w5, uy - ux, Fy - Fx, rhop, rho, usq15, uF, t, tq);
     te += C(2) * tq, tp += tq;
     // (selects rather than a branch where the flag is a run-time value: the
     // branch cost the batched kernel 20 registers)
@@ -542,49 +634,286 @@ __device__ __forceinline__ void node_finish(const Geom &g, const Coef<C> &k,
       gdx = m.kd * ((C(2) * W1 * bx - gx[1] - gx[3]) - (C(2) * W1 * bx - gx[2] - gx[4]));
       gdy = m.kd * ((C(2) * W1 * byp - gy[1] - gy[3]) - (C(2) * W1 * byp - gy[2] - gy[4]));
     }
-    gx[0] += t.gp * (W0 * bx - gx[0]);
-    collide_g_pair(gx[1], gx[3], W1 * bx, W1 * bx, t);
-    collide_g_pair(gx[2], gx[4], W1 * (bx - E3), W1 * (bx + E3), t);
-    gy[0] += t.gp * (W0 * byp - gy[0]);
-    collide_g_pair(gy[1], gy[3], W1 * (byp + E3), W1 * (byp - E3), t);
-    collide_g_pair(gy[2], gy[4], W1 * byp, W1 * byp, t);
+    if constexpr (XA) gx[0] = t.gp * (W0 * bx - gx[0]);
+    else gx[0] += t.gp * (W0 * bx - gx[0]);
+    collide_g_pair<C, XA>(gx[1], gx[3], W1 * bx, W1 * bx, t);
+    collide_g_pair<C, XA>(gx[2], gx[4], W1 * (bx - E3), W1 * (bx + E3), t);
+    if constexpr (XA) gy[0] = t.gp * (W0 * byp - gy[0]);
+    else gy[0] += t.gp * (W0 * byp - gy[0]);
+    collide_g_pair<C, XA>(gy[1], gy[3], W1 * (byp + E3), W1 * (byp - E3), t);
+    collide_g_pair<C, XA>(gy[2], gy[4], W1 * byp, W1 * byp, t);
     if constexpr (kMrt) {
       gx[1] = mrt_now ? gx[1] + gdx : gx[1], gx[3] = mrt_now ? gx[3] + gdx : gx[3];
       gx[2] = mrt_now ? gx[2] - gdx : gx[2], gx[4] = mrt_now ? gx[4] - gdx : gx[4];
       gy[1] = mrt_now ? gy[1] + gdy : gy[1], gy[3] = mrt_now ? gy[3] + gdy : gy[3];
       gy[2] = mrt_now ? gy[2] - gdy : gy[2], gy[4] = mrt_now ? gy[4] - gdy : gy[4];
     }
+    if constexpr (!XA) {
 #pragma unroll
-    for (int q = 0; q < 9; ++q) out[q] = put(f[q], q);
+      for (int q = 0; q < 9; ++q) out[q] = put(f[q], q);
 #pragma unroll
-    for (int q = 0; q < 5; ++q) out[9 + q] = put(gx[q], 9 + q);
+      for (int q = 0; q < 5; ++q) out[9 + q] = put(gx[q], 9 + q);
 #pragma unroll
-    for (int q = 0; q < 5; ++q) out[14 + q] = put(gy[q], 14 + q);
+      for (int q = 0; q < 5; ++q) out[14 + q] = put(gy[q], 14 + q);
+    }
     return;
   }
-  out[0] = put(collide_f(f[0], w0, C(0), C(0), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), 0);
-  out[1] = put(collide_f(f[1], w1, C(1), C(0), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), 1);
-  out[2] = put(collide_f(f[2], w1, C(0), C(1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), 2);
-  out[3] = put(collide_f(f[3], w1, C(-1), C(0), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), 3);
-  out[4] = put(collide_f(f[4], w1, C(0), C(-1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), 4);
-  out[5] = put(collide_f(f[5], w5, C(1), C(1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), 5);
-  out[6] = put(collide_f(f[6], w5, C(-1), C(1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), 6);
-  out[7] = put(collide_f(f[7], w5, C(-1), C(-1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), 7);
-  out[8] = put(collide_f(f[8], w5, C(1), C(-1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), 8);
-
   const C wm = k.omega_m;
-  out[9] = put(gx[0] + wm * (W0 * bx - gx[0]), 9);
-  out[10] = put(gx[1] + wm * (W1 * bx - gx[1]), 10);
-  out[11] = put(gx[2] + wm * (W1 * (bx - E3) - gx[2]), 11);
-  out[12] = put(gx[3] + wm * (W1 * bx - gx[3]), 12);
-  out[13] = put(gx[4] + wm * (W1 * (bx + E3) - gx[4]), 13);
-  out[14] = put(gy[0] + wm * (W0 * byp - gy[0]), 14);
-  out[15] = put(gy[1] + wm * (W1 * (byp + E3) - gy[1]), 15);
-  out[16] = put(gy[2] + wm * (W1 * byp - gy[2]), 16);
-  out[17] = put(gy[3] + wm * (W1 * (byp - E3) - gy[3]), 17);
-  out[18] = put(gy[4] + wm * (W1 * byp - gy[4]), 18);
+  if constexpr (XA) {
+    f[0] = collide_f<C, true>(f[0], w0, C(0), C(0), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka);
+    f[1] = collide_f<C, true>(f[1], w1, C(1), C(0), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka);
+    f[2] = collide_f<C, true>(f[2], w1, C(0), C(1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka);
+    f[3] = collide_f<C, true>(f[3], w1, C(-1), C(0), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka);
+    f[4] = collide_f<C, true>(f[4], w1, C(0), C(-1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka);
+    f[5] = collide_f<C, true>(f[5], w5, C(1), C(1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka);
+    f[6] = collide_f<C, true>(f[6], w5, C(-1), C(1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka);
+    f[7] = collide_f<C, true>(f[7], w5, C(-1), C(-1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka);
+    f[8] = collide_f<C, true>(f[8], w5, C(1), C(-1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka);
+    gx[0] = wm * (W0 * bx - gx[0]);
+    gx[1] = wm * (W1 * bx - gx[1]);
+    gx[2] = wm * (W1 * (bx - E3) - gx[2]);
+    gx[3] = wm * (W1 * bx - gx[3]);
+    gx[4] = wm * (W1 * (bx + E3) - gx[4]);
+    gy[0] = wm * (W0 * byp - gy[0]);
+    gy[1] = wm * (W1 * (byp + E3) - gy[1]);
+    gy[2] = wm * (W1 * byp - gy[2]);
+    gy[3] = wm * (W1 * (byp - E3) - gy[3]);
+    gy[4] = wm * (W1 * byp - gy[4]);
+    return;
+  } else {
+    out[0] = put(collide_f(f[0], w0, C(0), C(0), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), 0);
+    out[1] = put(collide_f(f[1], w1, C(1), C(0), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), 1);
+    out[2] = put(collide_f(f[2], w1, C(0), C(1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), 2);
+    out[3] = put(collide_f(f[3], w1, C(-1), C(0), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), 3);
+    out[4] = put(collide_f(f[4], w1, C(0), C(-1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), 4);
+    out[5] = put(collide_f(f[5], w5, C(1), C(1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), 5);
+    out[6] = put(collide_f(f[6], w5, C(-1), C(1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), 6);
+    out[7] = put(collide_f(f[7], w5, C(-1), C(-1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), 7);
+    out[8] = put(collide_f(f[8], w5, C(1), C(-1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka), 8);
+
+    out[9] = put(gx[0] + wm * (W0 * bx - gx[0]), 9);
+    out[10] = put(gx[1] + wm * (W1 * bx - gx[1]), 10);
+    out[11] = put(gx[2] + wm * (W1 * (bx - E3) - gx[2]), 11);
+    out[12] = put(gx[3] + wm * (W1 * bx - gx[3]), 12);
+    out[13] = put(gx[4] + wm * (W1 * (bx + E3) - gx[4]), 13);
+    out[14] = put(gy[0] + wm * (W0 * byp - gy[0]), 14);
+    out[15] = put(gy[1] + wm * (W1 * (byp + E3) - gy[1]), 15);
+    out[16] = put(gy[2] + wm * (W1 * byp - gy[2]), 16);
+    out[17] = put(gy[3] + wm * (W1 * (byp - E3) - gy[3]), 17);
+    out[18] = put(gy[4] + wm * (W1 * byp - gy[4]), 18);
+  }
 }
 
+// ---- binary16 storage with FP32 arithmetic and exact accumulation ----
+//
+// The stored value of plane q at row y is s = (v - D[y][q]) * 2^12, v the
+// post-collision deviation and D the row reference (FP32 values).  Per row
+// two more tables describe the pre-collision values a node of that row
+// collides with: v_pre[q] = V[y][q] + e[q], where e is the small part that
+// varies along the row -- a pulled binary16 value times 2^-12, or a linear
+// map of such values where a Hartmann-wall closure sets the population --
+// and V holds the rest: the reference of the row the population comes from,
+// or the closure applied to the references with its constant terms.  K[y][q]
+// = V[y][q] - D[y][q] in FP64 (exact), so v_pre - D[y][q] = K + e exactly.
+// The collision works in FP32 on V + e.  Its increments then have their
+// conserved moments restored in FP64 -- zero for mass and for B, the total
+// force F for momentum -- and the new stored value K + e + increment is
+// formed in FP64 before the stochastic rounding.  FP32 rounding then leaves
+// no residual in the moments the collision conserves, which the slow modes
+// of a steady channel would otherwise integrate step after step; what it
+// leaves in the other moments relaxes within a few steps.
+struct XTabs {
+  float *D;  // row references [ny][kRefRow] (FP32 values)
+  double *D64; // the same as doubles (FP64 decoding)
+  float *V;  // pre-collision references, FP32
+  double *K; // V - D, FP64
+};
+
+__host__ __device__ inline long long xtab_bytes(int ny, int elem) {
+  return ((long long)ny * kRefRow * elem + 255) / 256 * 256;
+}
+
+__host__ __device__ inline XTabs xtabs_of(void *base, int ny) {
+  char *p = static_cast<char *>(base);
+  const long long b4 = xtab_bytes(ny, 4), b8 = xtab_bytes(ny, 8);
+  return XTabs{reinterpret_cast<float *>(p), reinterpret_cast<double *>(p + b4),
+               reinterpret_cast<float *>(p + b4 + b8), reinterpret_cast<double *>(p + 2 * b4 + b8)};
+}
+
+__host__ __device__ inline long long xtabs_total_bytes(int ny) {
+  return 2 * xtab_bytes(ny, 4) + 2 * xtab_bytes(ny, 8);
+}
+
+// The precision mode that works this way: binary16 storage, FP32 compute.
+template <typename S, typename C>
+constexpr bool kXA = sizeof(S) == 2 && sizeof(C) == 4;
+
+// Pre-collision tables of one row y (FP64 arithmetic on the references).
+// Pulled planes take the reference of their source row; planes a Hartmann
+// closure sets take the closure of the references (moment scheme) or of the
+// row's own references (link scheme), with the constant terms.  Planes set by
+// the closures that stay in FP32 (cut-distance walls) take the row's own
+// reference, K = 0.
+template <int BC>
+__device__ __forceinline__ void xtab_row(const Geom &g, const Coef<double> &k, XTabs t, int y) {
+  const bool lo = (y == 0), hi = (y == g.ny - 1);
+  const float *Dy = t.D + (long long)y * kRefRow;
+  const float *Dm = lo ? Dy : Dy - kRefRow;
+  const float *Dp = hi ? Dy : Dy + kRefRow;
+  double v[19];
+  // source row of each plane: planes 2, 5, 6, 11, 16 move up (from y - 1),
+  // 4, 7, 8, 13, 18 down (from y + 1), the others along the row
+#pragma unroll
+  for (int q = 0; q < 19; ++q) {
+    const bool up = q == 2 || q == 5 || q == 6 || q == 11 || q == 16;
+    const bool dn = q == 4 || q == 7 || q == 8 || q == 13 || q == 18;
+    v[q] = (double)(up ? Dm[q] : (dn ? Dp[q] : Dy[q]));
+  }
+  if constexpr (wall_of(BC) == BC_LINK && cut_of(BC)) {
+    // set in FP32 by the cut-distance closure: e = v - V with V = D
+    if (lo) {
+      const int cl[5] = {2, 5, 6, 11, 16};
+#pragma unroll
+      for (int j = 0; j < 5; ++j) v[cl[j]] = (double)Dy[cl[j]];
+    }
+    if (hi) {
+      const int cl[5] = {4, 7, 8, 13, 18};
+#pragma unroll
+      for (int j = 0; j < 5; ++j) v[cl[j]] = (double)Dy[cl[j]];
+    }
+  } else if (lo || hi) {
+    double f[9], gx[5], gy[5];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) f[q] = v[q];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) gx[q] = v[9 + q], gy[q] = v[14 + q];
+    const int p0 = lo ? 4 : 2, p1 = lo ? 7 : 5, p2 = lo ? 8 : 6;
+    const double own[5] = {(double)Dy[p0], (double)Dy[p1], (double)Dy[p2], (double)Dy[9 + p0],
+                           (double)Dy[14 + p0]};
+    hartmann_closure<double, wall_of(BC), true>(lo, hi, f, gx, gy, own, k.lo, k.hi);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) v[q] = f[q];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) v[9 + q] = gx[q], v[14 + q] = gy[q];
+  }
+  const long long r = (long long)y * kRefRow;
+#pragma unroll
+  for (int q = 0; q < 19; ++q) {
+    const float v32 = (float)v[q];
+    t.V[r + q] = v32;
+    t.D64[r + q] = (double)Dy[q];
+    // pulled planes (and FP32-closed ones) have V = a reference, exact in
+    // FP32; a Hartmann closure's V keeps its FP64 value in K
+    t.K[r + q] = v[q] - (double)Dy[q];
+  }
+  t.V[r + 19] = 0.0f;
+  t.D64[r + 19] = 0.0;
+  t.K[r + 19] = 0.0;
+}
+
+// Collide one node of a binary16 state in FP32 with exact accumulation.
+// raw[] holds the 19 pulled stored values (unused where a wall closes the
+// population); the new stored values are returned in out (not for
+// MODE_MOMENTS, which this path does not serve).
+template <typename S, int BC, int MODE, bool SR>
+__device__ __forceinline__ void node_finish_x(const Geom &g, const Coef<float> &k,
+                                              const S *__restrict__ src, XTabs t, int x, int y,
+                                              const S (&raw)[19], NodeObs<float> &obs,
+                                              uint32_t sseed, S (&out)[19]) {
+  static_assert(MODE != MODE_MOMENTS, "observables decode in FP64");
+  const bool lo = (y == 0), hi = (y == g.ny - 1);
+  const long long row = (long long)y * kRefRow;
+  const float *__restrict__ Vy = t.V + row;
+  const double *__restrict__ Ky = t.K + row;
+  const float *__restrict__ Dy = t.D + row;
+  constexpr float down = float(kStoreDown16);
+  float e[19];
+#pragma unroll
+  for (int q = 0; q < 19; ++q) e[q] = (float)raw[q] * down;
+  float f[9], gx[5], gy[5];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) f[q] = Vy[q] + e[q];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) gx[q] = Vy[9 + q] + e[9 + q], gy[q] = Vy[14 + q] + e[14 + q];
+  // closures kept in FP32 (enclosure walls, cut-distance walls): e = v - V
+  // for the populations they set (exact: v and V are close)
+  if constexpr (xwalls_of(BC)) {
+    if (x == 0 || x == g.nx - 1) {
+      xwall_closure<S, float>(g, k, src, Dy, x, y, f, gx, gy);
+      if (x == 0) {
+        e[1] = f[1] - Vy[1], e[5] = f[5] - Vy[5], e[8] = f[8] - Vy[8];
+        e[10] = gx[1] - Vy[10], e[15] = gy[1] - Vy[15];
+      }
+      if (x == g.nx - 1) {
+        e[3] = f[3] - Vy[3], e[6] = f[6] - Vy[6], e[7] = f[7] - Vy[7];
+        e[12] = gx[3] - Vy[12], e[17] = gy[3] - Vy[17];
+      }
+    }
+  }
+  // (each wall written out with its own constant plane numbers, so that
+  // the arrays stay in registers)
+  auto wall_rows = [&](auto low) {
+    constexpr bool L = decltype(low)::value;
+    constexpr int a0 = L ? 2 : 4, a1 = L ? 5 : 8, a2 = L ? 6 : 7; // entering planes
+    if constexpr (wall_of(BC) == BC_LINK && cut_of(BC)) {
+      cut_closure<S, float>(g, k, src, t.D, x, y, f, gx, gy);
+      e[a0] = f[a0] - Vy[a0], e[a1] = f[a1] - Vy[a1], e[a2] = f[a2] - Vy[a2];
+      e[9 + a0] = gx[a0] - Vy[9 + a0], e[14 + a0] = gy[a0] - Vy[14 + a0];
+    } else {
+      // Hartmann walls: the closure's linear part on the small parts e; V
+      // holds the closure of the references with its constants
+      float ef[9], egx[5], egy[5], own[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int q = 0; q < 9; ++q) ef[q] = e[q];
+#pragma unroll
+      for (int q = 0; q < 5; ++q) egx[q] = e[9 + q], egy[q] = e[14 + q];
+      if constexpr (wall_of(BC) == BC_LINK) {
+        const long long P = g.plane, r0 = (long long)y * g.pitch;
+        constexpr int p0 = L ? 4 : 2, p1 = L ? 7 : 5, p2 = L ? 8 : 6; // leaving planes
+        own[0] = (float)ld<S, float>(src + p0 * P + r0 + x) * down;
+        own[1] = (float)ld<S, float>(src + p1 * P + r0 + x) * down;
+        own[2] = (float)ld<S, float>(src + p2 * P + r0 + x) * down;
+        own[3] = (float)ld<S, float>(src + (9 + p0) * P + r0 + x) * down;
+        own[4] = (float)ld<S, float>(src + (14 + p0) * P + r0 + x) * down;
+      }
+      hartmann_closure<float, wall_of(BC), false>(L, !L, ef, egx, egy, own, k.lo, k.hi);
+      e[a0] = ef[a0], e[a1] = ef[a1], e[a2] = ef[a2];
+      e[9 + a0] = egx[a0], e[14 + a0] = egy[a0];
+      f[a0] = Vy[a0] + e[a0], f[a1] = Vy[a1] + e[a1], f[a2] = Vy[a2] + e[a2];
+      gx[a0] = Vy[9 + a0] + e[9 + a0], gy[a0] = Vy[14 + a0] + e[14 + a0];
+    }
+  };
+  if (lo) wall_rows(std::true_type{});
+  else if (hi) wall_rows(std::false_type{});
+  S unused[19];
+  node_finish<S, float, BC, MODE, SR, true>(g, k, src, t.D, x, y, f, gx, gy, obs, sseed, unused);
+  // conserved moments of the increments, in FP64: mass and B are unchanged
+  // by the collision and momentum gains the force
+  double d[19];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) d[q] = (double)f[q];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) d[9 + q] = (double)gx[q], d[14 + q] = (double)gy[q];
+  const double m0 = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
+  const double mx = ((d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7])) - (double)obs.fx;
+  const double my = ((d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8])) - (double)obs.fy;
+  const double sx = (d[9] + d[10]) + (d[11] + d[12]) + d[13];
+  const double sy = (d[14] + d[15]) + (d[16] + d[17]) + d[18];
+  // removed on the rest population (mass), on the opposite axis pairs
+  // (momentum; their mass and second moments cancel) and on the rest
+  // populations of g (B)
+  d[0] -= m0;
+  d[1] -= 0.5 * mx, d[3] += 0.5 * mx;
+  d[2] -= 0.5 * my, d[4] += 0.5 * my;
+  d[9] -= sx;
+  d[14] -= sy;
+  Rng rng(SR ? node_seed(sseed, (uint32_t)(y * g.nx + x)) : 0u);
+#pragma unroll
+  for (int q = 0; q < 19; ++q) {
+    const double nv = (Ky[q] + (double)e[q]) + d[q]; // new value minus D[y][q]
+    out[q] = to_store<S, float, SR, in_batch(BC)>((float)(nv * kStoreUp16), SR ? rng.next() : 0u);
+  }
+}
 
 template <typename S, typename C, int BC, int MODE, bool SR>
 __device__ __forceinline__ void node_update(const Geom &g, const Coef<C> &k,
@@ -601,49 +930,93 @@ __device__ __forceinline__ void node_update(const Geom &g, const Coef<C> &k,
   const long long r0 = (long long)y * g.pitch;
   const long long rm = r0 - g.pitch;
   const long long rp = r0 + g.pitch;
-
-  // ---- pull streaming: f_a(x) = f~_a(x - e_a) ----
-  // stored values are decoded with the reference of the row they come from
-  const C *__restrict__ Dy = ref + (long long)y * 19;
-  const C *__restrict__ Dm = lo ? Dy : Dy - 19; // row y - 1 (used only off the lower wall)
-  const C *__restrict__ Dp = hi ? Dy : Dy + 19; // row y + 1 (used only off the upper wall)
   constexpr bool NT = !in_batch(BC);
-  C f[9], gx[5], gy[5];
-  f[0] = dec<S>(ld<S, C, NT>(src + r0 + x), Dy, 0);
-  f[1] = dec<S>(ldx<S, C>(src + 1 * P + r0 + xm), Dy, 1);
-  f[3] = dec<S>(ldx<S, C>(src + 3 * P + r0 + xp), Dy, 3);
-  gx[0] = dec<S>(ld<S, C, NT>(src + 9 * P + r0 + x), Dy, 9);
-  gx[1] = dec<S>(ldx<S, C>(src + 10 * P + r0 + xm), Dy, 10);
-  gx[3] = dec<S>(ldx<S, C>(src + 12 * P + r0 + xp), Dy, 12);
-  gy[0] = dec<S>(ld<S, C, NT>(src + 14 * P + r0 + x), Dy, 14);
-  gy[1] = dec<S>(ldx<S, C>(src + 15 * P + r0 + xm), Dy, 15);
-  gy[3] = dec<S>(ldx<S, C>(src + 17 * P + r0 + xp), Dy, 17);
-  if (!lo) {
-    f[2] = dec<S>(ld<S, C, NT>(src + 2 * P + rm + x), Dm, 2);
-    f[5] = dec<S>(ldx<S, C>(src + 5 * P + rm + xm), Dm, 5);
-    f[6] = dec<S>(ldx<S, C>(src + 6 * P + rm + xp), Dm, 6);
-    gx[2] = dec<S>(ld<S, C, NT>(src + 11 * P + rm + x), Dm, 11);
-    gy[2] = dec<S>(ld<S, C, NT>(src + 16 * P + rm + x), Dm, 16);
-  }
-  if (!hi) {
-    f[4] = dec<S>(ld<S, C, NT>(src + 4 * P + rp + x), Dp, 4);
-    f[7] = dec<S>(ldx<S, C>(src + 7 * P + rp + xp), Dp, 7);
-    f[8] = dec<S>(ldx<S, C>(src + 8 * P + rp + xm), Dp, 8);
-    gx[4] = dec<S>(ld<S, C, NT>(src + 13 * P + rp + x), Dp, 13);
-    gy[4] = dec<S>(ld<S, C, NT>(src + 18 * P + rp + x), Dp, 18);
-  }
 
-  NodeObs<C> &o_ = obs;
-  S out[19];
-  node_finish<S, C, BC, MODE, SR>(g, k, src, ref, x, y, f, gx, gy, o_, sseed, out);
-  if constexpr (MODE != MODE_MOMENTS) {
+  if constexpr (kXA<S, C> && MODE != MODE_MOMENTS) {
+    // binary16 with FP32 arithmetic: pull the stored values undecoded
+    // (x-shifted pulls through the caches, the others streamed: see ld)
+    auto lu = [&](long long off) -> S {
+      if constexpr (NT) return __builtin_nontemporal_load(src + off);
+      else return src[off];
+    };
+    S raw[19];
+#pragma unroll
+    for (int q = 0; q < 19; ++q) raw[q] = S(0);
+    raw[0] = lu(r0 + x);
+    raw[1] = src[1 * P + r0 + xm];
+    raw[3] = src[3 * P + r0 + xp];
+    raw[9] = lu(9 * P + r0 + x);
+    raw[10] = src[10 * P + r0 + xm];
+    raw[12] = src[12 * P + r0 + xp];
+    raw[14] = lu(14 * P + r0 + x);
+    raw[15] = src[15 * P + r0 + xm];
+    raw[17] = src[17 * P + r0 + xp];
+    if (!lo) {
+      raw[2] = lu(2 * P + rm + x);
+      raw[5] = src[5 * P + rm + xm];
+      raw[6] = src[6 * P + rm + xp];
+      raw[11] = lu(11 * P + rm + x);
+      raw[16] = lu(16 * P + rm + x);
+    }
+    if (!hi) {
+      raw[4] = lu(4 * P + rp + x);
+      raw[7] = src[7 * P + rp + xp];
+      raw[8] = src[8 * P + rp + xm];
+      raw[13] = lu(13 * P + rp + x);
+      raw[18] = lu(18 * P + rp + x);
+    }
+    S out[19];
+    NodeObs<float> &o_ = obs;
+    node_finish_x<S, BC, MODE, SR>(g, k, src, xtabs_of(const_cast<C *>(ref), g.ny), x, y, raw,
+                                   o_, sseed, out);
     const long long o = r0 + x;
 #pragma unroll
     for (int q = 0; q < 19; ++q) __builtin_nontemporal_store(out[q], dst + q * P + o);
+    return;
   } else {
-    (void)dst;
+    // ---- pull streaming: f_a(x) = f~_a(x - e_a) ----
+    // stored values are decoded with the reference of the row they come from
+    const C *__restrict__ Dy = ref + (long long)y * kRefRow;
+    const C *__restrict__ Dm = lo ? Dy : Dy - kRefRow; // row y - 1 (used only off the lower wall)
+    const C *__restrict__ Dp = hi ? Dy : Dy + kRefRow; // row y + 1 (used only off the upper wall)
+    C f[9], gx[5], gy[5];
+    f[0] = dec<S>(ld<S, C, NT>(src + r0 + x), Dy, 0);
+    f[1] = dec<S>(ldx<S, C>(src + 1 * P + r0 + xm), Dy, 1);
+    f[3] = dec<S>(ldx<S, C>(src + 3 * P + r0 + xp), Dy, 3);
+    gx[0] = dec<S>(ld<S, C, NT>(src + 9 * P + r0 + x), Dy, 9);
+    gx[1] = dec<S>(ldx<S, C>(src + 10 * P + r0 + xm), Dy, 10);
+    gx[3] = dec<S>(ldx<S, C>(src + 12 * P + r0 + xp), Dy, 12);
+    gy[0] = dec<S>(ld<S, C, NT>(src + 14 * P + r0 + x), Dy, 14);
+    gy[1] = dec<S>(ldx<S, C>(src + 15 * P + r0 + xm), Dy, 15);
+    gy[3] = dec<S>(ldx<S, C>(src + 17 * P + r0 + xp), Dy, 17);
+    if (!lo) {
+      f[2] = dec<S>(ld<S, C, NT>(src + 2 * P + rm + x), Dm, 2);
+      f[5] = dec<S>(ldx<S, C>(src + 5 * P + rm + xm), Dm, 5);
+      f[6] = dec<S>(ldx<S, C>(src + 6 * P + rm + xp), Dm, 6);
+      gx[2] = dec<S>(ld<S, C, NT>(src + 11 * P + rm + x), Dm, 11);
+      gy[2] = dec<S>(ld<S, C, NT>(src + 16 * P + rm + x), Dm, 16);
+    }
+    if (!hi) {
+      f[4] = dec<S>(ld<S, C, NT>(src + 4 * P + rp + x), Dp, 4);
+      f[7] = dec<S>(ldx<S, C>(src + 7 * P + rp + xp), Dp, 7);
+      f[8] = dec<S>(ldx<S, C>(src + 8 * P + rp + xm), Dp, 8);
+      gx[4] = dec<S>(ld<S, C, NT>(src + 13 * P + rp + x), Dp, 13);
+      gy[4] = dec<S>(ld<S, C, NT>(src + 18 * P + rp + x), Dp, 18);
+    }
+
+    NodeObs<C> &o_ = obs;
+    S out[19];
+    node_finish<S, C, BC, MODE, SR>(g, k, src, ref, x, y, f, gx, gy, o_, sseed, out);
+    if constexpr (MODE != MODE_MOMENTS) {
+      const long long o = r0 + x;
+#pragma unroll
+      for (int q = 0; q < 19; ++q) __builtin_nontemporal_store(out[q], dst + q * P + o);
+    } else {
+      (void)dst;
+    }
   }
 }
+
 
 // ---- FP64 block reduction (deterministic: fixed shuffle and LDS order) ----
 template <int NV>

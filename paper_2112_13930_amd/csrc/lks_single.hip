@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstring>
 #include <new>
+#include <type_traits>
 
 #include "lks_aux.hpp"
 #include "lks_common.hpp"
@@ -166,14 +167,42 @@ __global__ __launch_bounds__(256) void k_step_vec(Geom g, Coef<C> k, const S *__
     b4 = vld(13 * P + rp + x0);
     c4 = vld(18 * P + rp + x0);
   }
-  const C *__restrict__ Dy = ref + (long long)y * 19; // row references (binary16 only)
-  const C *__restrict__ Dm = lo ? Dy : Dy - 19;
-  const C *__restrict__ Dp = hi ? Dy : Dy + 19;
+  const C *__restrict__ Dy = ref + (long long)y * kRefRow; // row references (binary16 only)
+  const C *__restrict__ Dm = lo ? Dy : Dy - kRefRow;
+  const C *__restrict__ Dp = hi ? Dy : Dy + kRefRow;
   V outv[19];
 #pragma unroll
   for (int v = 0; v < VX; ++v) {
     // pulled populations of node x0 + v: x - 1 planes take element v - 1
     // (or the extra scalar for v = 0), x + 1 planes element v + 1
+    if constexpr (kXA<S, C>) {
+      // binary16 computed in FP32: the undecoded values in plane order
+      const S raw[19] = {a0[v],
+                         v == 0 ? e1 : a1[v > 0 ? v - 1 : 0],
+                         a2[v],
+                         v == VX - 1 ? e3 : a3[v < VX - 1 ? v + 1 : 0],
+                         a4[v],
+                         v == 0 ? e5 : a5[v > 0 ? v - 1 : 0],
+                         v == VX - 1 ? e6 : a6[v < VX - 1 ? v + 1 : 0],
+                         v == VX - 1 ? e7 : a7[v < VX - 1 ? v + 1 : 0],
+                         v == 0 ? e8 : a8[v > 0 ? v - 1 : 0],
+                         b0[v],
+                         v == 0 ? eb1 : b1[v > 0 ? v - 1 : 0],
+                         b2[v],
+                         v == VX - 1 ? eb3 : b3[v < VX - 1 ? v + 1 : 0],
+                         b4[v],
+                         c0[v],
+                         v == 0 ? ec1 : c1[v > 0 ? v - 1 : 0],
+                         c2[v],
+                         v == VX - 1 ? ec3 : c3[v < VX - 1 ? v + 1 : 0],
+                         c4[v]};
+      NodeObs<C> o{};
+      S out[19];
+      node_finish_x<S, BC, MODE_STEP, SR>(g, k, src, xtabs_of(const_cast<C *>(ref), g.ny), x0 + v,
+                                          y, raw, o, sseed, out);
+#pragma unroll
+      for (int q = 0; q < 19; ++q) outv[q][v] = out[q];
+    } else {
     C f[9], gx[5], gy[5];
     f[0] = dec<S>((C)a0[v], Dy, 0);
     f[1] = dec<S>((C)(v == 0 ? e1 : a1[v > 0 ? v - 1 : 0]), Dy, 1);
@@ -199,6 +228,7 @@ __global__ __launch_bounds__(256) void k_step_vec(Geom g, Coef<C> k, const S *__
     node_finish<S, C, BC, MODE_STEP, SR>(g, k, src, ref, x0 + v, y, f, gx, gy, o, sseed, out);
 #pragma unroll
     for (int q = 0; q < 19; ++q) outv[q][v] = out[q];
+    }
   }
 #pragma unroll
   for (int q = 0; q < 19; ++q)
@@ -262,7 +292,7 @@ Layout layout_of(const Channel &c) {
   L.red_tiles_x = (c.p.nx + s.bx - 1) / s.bx;
   L.red_ntiles = L.red_tiles_x * ((c.p.ny + s.by - 1) / s.by);
   L.part_bytes = align256((size_t)L.red_ntiles * 8 * sizeof(double));
-  L.ref_bytes = align256((size_t)c.p.ny * 19 * sizeof(double));
+  L.ref_bytes = ref_area_bytes(c.p.ny, prec);
   L.total = 2 * L.state_bytes + L.rec_bytes + L.part_bytes + 256 + 256 + L.ref_bytes;
   return L;
 }
@@ -276,6 +306,15 @@ template <typename C> const Coef<C> &coef_of(const lks_mhd *h);
 template <> const Coef<double> &coef_of<double>(const lks_mhd *h) { return h->kd; }
 template <> const Coef<float> &coef_of<float>(const lks_mhd *h) { return h->kf; }
 
+// Row references a kernel of (S, C) reads: the observables of the
+// FP32-arithmetic binary16 mode decode its FP32 references in FP64.
+template <typename S, typename C>
+const C *ref_of(const lks_mhd *h) {
+  if constexpr (kRowRef<S> && sizeof(C) == 8)
+    if (h->ch.p.precision == LKS_FP16_STORE) return xtabs_of(h->ref, h->geom.ny).D64;
+  return static_cast<const C *>(h->ref);
+}
+
 template <typename S, typename C, int BC, int MODE, int SH>
 hipError_t launch_shape(lks_mhd *h, const void *src, void *dst, ObsOut oo) {
   constexpr Shape s = kShapes[SH];
@@ -285,7 +324,7 @@ hipError_t launch_shape(lks_mhd *h, const void *src, void *dst, ObsOut oo) {
     const int ntiles = tiles_x * h->geom.ny;
     hipLaunchKernelGGL((k_step_vec<S, C, BC, s.vx>), dim3(ntiles), dim3(s.bx), 0, h->stream,
                        h->geom, k, static_cast<const S *>(src), static_cast<S *>(dst),
-                       static_cast<const C *>(h->ref), tiles_x, ntiles, h->ctr, h->cur);
+                       ref_of<S, C>(h), tiles_x, ntiles, h->ctr, h->cur);
     return hipGetLastError();
   }
   const int tiles_x = (h->geom.nx + s.bx - 1) / s.bx;
@@ -294,7 +333,7 @@ hipError_t launch_shape(lks_mhd *h, const void *src, void *dst, ObsOut oo) {
   hipLaunchKernelGGL((k_step<S, C, BC, MODE, s.bx, s.by, s.remap>), dim3(grid),
                      dim3(s.bx, s.by), 0, h->stream, h->geom, k,
                      static_cast<const S *>(src), static_cast<S *>(dst),
-                     static_cast<const C *>(h->ref), tiles_x, ntiles, h->rec, h->partials, oo,
+                     ref_of<S, C>(h), tiles_x, ntiles, h->rec, h->partials, oo,
                      h->ctr, h->cur);
   return hipGetLastError();
 }
@@ -320,7 +359,9 @@ hipError_t launch_mode(lks_mhd *h, int shape, const void *src, void *dst, ObsOut
   constexpr bool kCollide = MODE != MODE_MOMENTS;
   return dispatch_precision(h->ch.p.precision, [&](auto t) -> hipError_t {
     using S = typename decltype(t)::S;
-    using C = typename decltype(t)::C;
+    // observables of binary16 computed in FP32 are taken in FP64
+    using C0 = typename decltype(t)::C;
+    using C = std::conditional_t<MODE == MODE_MOMENTS && kXA<S, C0>, double, C0>;
     switch (sch) {
     case BC_LINK: return launch_bc<S, C, BC_LINK, MODE>(h, shape, src, dst, oo);
     case BC_MOMENT: return launch_bc<S, C, BC_MOMENT, MODE>(h, shape, src, dst, oo);
@@ -436,13 +477,29 @@ int elementwise_grid(const lks_mhd *h) {
   return (int)((n + 255) / 256);
 }
 
+// Pre-collision tables of the FP32-arithmetic binary16 mode, after every
+// change of its row references.
+int refresh_tables(lks_mhd *h) {
+  if (h->ch.p.precision != LKS_FP16_STORE) return LKS_OK;
+  const dim3 grid((unsigned)((h->geom.ny + 255) / 256));
+  const int sch = scheme_of(h->ch.p);
+  if (cut_of(sch))
+    hipLaunchKernelGGL(k_xtables<BC_LINK | WALLS_Q>, grid, dim3(256), 0, h->stream, h->geom, h->kd, h->ref);
+  else if (wall_of(sch) == BC_LINK)
+    hipLaunchKernelGGL(k_xtables<BC_LINK>, grid, dim3(256), 0, h->stream, h->geom, h->kd, h->ref);
+  else
+    hipLaunchKernelGGL(k_xtables<BC_MOMENT>, grid, dim3(256), 0, h->stream, h->geom, h->kd, h->ref);
+  LKS_HIP_CHECK(hipGetLastError());
+  return LKS_OK;
+}
+
 // Clear the row references (the stored values then hold the deviations).
 int zero_ref(lks_mhd *h) {
-  const long long n = (long long)h->geom.ny * 19;
+  const long long n = (long long)(ref_area_bytes(h->geom.ny, h->ch.p.precision) / sizeof(double));
   hipLaunchKernelGGL(k_zero<double>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, h->stream,
                      static_cast<double *>(h->ref), n);
   LKS_HIP_CHECK(hipGetLastError());
-  return LKS_OK;
+  return refresh_tables(h);
 }
 
 // Row rebase of a binary16 state (other storage keeps no row reference).
@@ -455,6 +512,7 @@ int rebase_now(lks_mhd *h) {
                          static_cast<S *>(h->buf[h->cur]), static_cast<C *>(h->ref),
                          (uint32_t)h->steps);
       LKS_HIP_CHECK(hipGetLastError());
+      return refresh_tables(h);
     }
     return LKS_OK;
   });
@@ -699,10 +757,11 @@ int lks_mhd_save_state(lks_mhd_t *h, double *dev_pops) {
     const int grid = elementwise_grid(h);
     dispatch_precision(h->ch.p.precision, [&](auto t) {
       using S = typename decltype(t)::S;
-      using C = typename decltype(t)::C;
+      // binary16 computed in FP32 decodes its FP32 references in FP64
+      using C0 = typename decltype(t)::C;
+      using C = std::conditional_t<kXA<S, C0>, double, C0>;
       hipLaunchKernelGGL((k_save<S, C>), dim3(grid), dim3(256), 0, h->stream, h->geom, h->ch.d.b0,
-                         static_cast<const S *>(h->buf[h->cur]), static_cast<const C *>(h->ref),
-                         dev_pops);
+                         static_cast<const S *>(h->buf[h->cur]), ref_of<S, C>(h), dev_pops);
     });
     LKS_HIP_CHECK(hipGetLastError());
     return LKS_OK;

@@ -39,7 +39,7 @@ def test_every_declared_symbol_is_exported(L):
 
 
 def test_abi_version(L):
-    assert L.lib().lks_mhd_abi_version() == 6
+    assert L.lib().lks_mhd_abi_version() == 7
 
 
 def _v(L, **kw):
@@ -80,7 +80,7 @@ def test_validate_rejects(L, kw):
     dict(), dict(ny=2), dict(ny=3, bc="moment"), dict(c_lower=math.inf, c_upper=0.0),
     dict(ha=10.0, u_max=0.05, c_lower=0.1), dict(ha=0.0, u_max=0.05),
     dict(ha=5.0, c_lower=math.inf, u_max=0.01, bc="moment"),
-    dict(precision="fp64"), dict(precision="fp16"), dict(precision="fp16_f32"),
+    dict(precision="fp64"), dict(precision="fp16"), dict(precision="fp16_f64"),
     dict(collision="trt"), dict(collision="trt", lambda_f=0.25, lambda_m=1.0 / 12.0),
     dict(collision="bgk", lambda_f=float("nan")),  # magic parameters unused under BGK
     dict(x_walls=True), dict(x_walls=True, nx=2, c_x=(0.0, math.inf), collision="trt"),
@@ -138,7 +138,7 @@ def test_bytes_per_node(L):
 
 
 def test_state_bytes_cover_two_buffers(L):
-    for prec, b in (("fp64", 8), ("fp32", 4), ("fp16", 2), ("fp16_f32", 2)):
+    for prec, b in (("fp64", 8), ("fp32", 4), ("fp16", 2), ("fp16_f64", 2)):
         p = L.make_params(4096, 4096, precision=prec)
         assert L.lib().lks_mhd_state_bytes(ctypes.byref(p)) >= 2 * 19 * 4096 * 4096 * b
 

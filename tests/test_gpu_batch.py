@@ -51,7 +51,7 @@ def solo_state(p, precision, nsteps):
     return ch.save_state().cpu()
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp16", "fp64", "fp16_f32"])
+@pytest.mark.parametrize("precision", ["fp32", "fp16", "fp64", "fp16_f64"])
 def test_mixed_batch_equals_solo_runs(P, precision):
     from paper_2112_13930_amd._lib import make_params
     from paper_2112_13930_amd.batch import Batch

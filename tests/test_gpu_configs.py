@@ -80,7 +80,7 @@ def test_4096_random_state_two_steps(P):
     assert_close(errs, TOL["fp32"], keys=("ux", "bx", "uy", "by", "rho"))
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp16", "fp16_f32"])
+@pytest.mark.parametrize("precision", ["fp32", "fp16", "fp16_f64"])
 def test_config1_precisions(P, precision):
     p = derive.hartmann_params(8, 64, LINK, 0.8, 0.8, 10.0, 0.1, 0.05)
     ch = channel(p, precision)
@@ -94,7 +94,7 @@ def test_config1_precisions(P, precision):
     assert_close(errs, TOL[precision], keys=("ux", "bx"))
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp16", "fp16_f32"])
+@pytest.mark.parametrize("precision", ["fp32", "fp16", "fp16_f64"])
 def test_512_precision_case(P, precision):
     p = derive.hartmann_params(1, 512, LINK, 0.8, 0.8, 50.0, 0.5, 0.003)
     ch = channel(p, precision, nx=512)

@@ -39,7 +39,7 @@ CASES = [
 
 
 @pytest.mark.parametrize("case", CASES)
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16", "fp16_f32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16", "fp16_f64"])
 def test_cut_walls_random_state_parity(P, case, precision):
     from paper_2112_13930_amd.workloads import random_populations
     ql, qh, cl, ch, ul, uh, fx, use_trt = case

@@ -44,7 +44,7 @@ def params(name):
 
 
 @pytest.mark.parametrize("name", sorted(CASES))
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16", "fp16_f32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16", "fp16_f64"])
 def test_degenerate_sizes_match_oracle(P, name, precision):
     from paper_2112_13930_amd.channel import Channel
     from paper_2112_13930_amd.workloads import random_populations

@@ -40,7 +40,7 @@ CASES = [
 
 
 @pytest.mark.parametrize("case", CASES)
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16", "fp16_f32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16", "fp16_f64"])
 def test_enclosure_random_state_parity(P, case, precision):
     from paper_2112_13930_amd.workloads import random_populations
     cl, cu, xl, xh, ul, uu, fx, fy, use_trt = case

@@ -39,7 +39,7 @@ CASES = [
 
 
 @pytest.mark.parametrize("case", CASES)
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16", "fp16_f32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16", "fp16_f64"])
 def test_mrt_random_state_parity(P, case, precision):
     from paper_2112_13930_amd.workloads import random_populations
     bc, cl, ch, ul, uh, fx, fy, rates = case
@@ -110,7 +110,7 @@ def test_mrt_run_to_steady_matches_oracle_residual(P):
     assert abs(res - r) < 1e-3 * r, (res, r)
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp16", "fp64", "fp16_f32"])
+@pytest.mark.parametrize("precision", ["fp32", "fp16", "fp64", "fp16_f64"])
 def test_mrt_trt_and_bgk_channels_in_one_batch_equal_solo_runs(P, precision):
     """The batched kernel runs MRT channels through its TRT scheme with the
     corrections switched on per channel: every channel of a mixed batch

@@ -45,7 +45,7 @@ def rest_offsets(b0):
     return np.concatenate([_W, np.zeros(5), _WM * b0])[:, None, None]
 
 
-@pytest.mark.parametrize("precision", ["fp16", "fp16_f32"])
+@pytest.mark.parametrize("precision", ["fp16", "fp16_f64"])
 def test_rebase_keeps_decoded_state(P, precision):
     from paper_2112_13930_amd.workloads import random_populations
     p = Params(nx=40, ny=24, bc=MOMENT, tau_f=0.7, tau_m=0.9, b0=0.03, fx=1e-5,
@@ -86,7 +86,7 @@ def test_rebase_is_a_no_op_for_wide_storage(P, precision):
     ref.close()
 
 
-@pytest.mark.parametrize("precision", ["fp16", "fp16_f32"])
+@pytest.mark.parametrize("precision", ["fp16", "fp16_f64"])
 def test_batch_windows_equal_run_to_steady_and_plain_steps(P, precision):
     from paper_2112_13930_amd._lib import make_params
     from paper_2112_13930_amd.batch import Batch
@@ -137,23 +137,23 @@ def run_512_case(precision, nx, steps, rebase):
     return field_errors(g, o, p.b0)
 
 
+@pytest.mark.parametrize("precision", ["fp16", "fp16_f64"])
 @pytest.mark.parametrize("nx", [8, 512])
-def test_fp16_rebased_100k_steps_match_oracle(P, nx):
+def test_fp16_rebased_100k_steps_match_oracle(P, nx, precision):
     """512-row Hartmann channel (Ha = 50, c = 0.5, u_max = 0.003; the
     precision case) for 100 000 steps with the default rebase every 1000
-    steps: binary16 storage computed in FP64 stays within the binary16 bar
-    (measured: about 1e-4)."""
-    errs = run_512_case("fp16", nx, 100_000, 1000)
-    print(nx, errs)
-    assert_close(errs, TOL["fp16"], keys=("ux", "bx"))
+    steps: binary16 storage, computed in FP32 with FP64 accumulation ("fp16")
+    or in FP64, stays within the binary16 bar on u_x and B_x."""
+    errs = run_512_case(precision, nx, 100_000, 1000)
+    print(precision, nx, errs)
+    assert_close(errs, TOL[precision], keys=("ux", "bx"))
 
 
-def test_fp16_f32_long_run_error_is_bounded(P):
-    """The same case with FP32 arithmetic: the systematic FP32 residual is
-    amplified by the slow modes of the strongly coupled channel (measured
-    about 4e-3 on u_x at 100 000 steps, 3e-3 at the steady state), above the
-    binary16 bar, which is why binary16 storage computes in FP64 by default."""
-    errs = run_512_case("fp16_f32", 512, 100_000, 1000)
+def test_fp16_fp32_arithmetic_300k_steps_match_oracle(P):
+    """The same case at 300 000 steps in the default binary16 mode (FP32
+    arithmetic): the slow wall modes of this channel (time constant
+    c a^2 / eta ~ 3e5 steps) integrate any systematic rounding residual, so
+    the error must not grow with the run length."""
+    errs = run_512_case("fp16", 512, 300_000, 1000)
     print(errs)
-    assert errs["bx"] <= TOL["fp16"]
-    assert errs["ux"] <= 1e-2
+    assert_close(errs, TOL["fp16"], keys=("ux", "bx"))

@@ -54,7 +54,7 @@ def test_alone_equals_in_mix(P, precision):
         {r.rid: r.status for r in mixed.values()}
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp16_f32"])
+@pytest.mark.parametrize("precision", ["fp32", "fp16_f64"])
 def test_trt_and_mrt_requests_alone_equal_in_mix(P, precision):
     """Requests with the TRT and MRT collisions share the service with BGK
     ones: each result is the same alone and in the mix, and (FP32 storage,

@@ -39,7 +39,7 @@ def test_initial_state_moments(P):
     o = oracle.observe(p, oracle.init_state(p))
     # B_y = B0 is stored as binary16 values W_a B0 in the FP16 mode (relative
     # rounding 2^-11 per value)
-    for prec, tol in (("fp64", 1e-14), ("fp32", 1e-6), ("fp16", 2e-3), ("fp16_f32", 2e-3)):
+    for prec, tol in (("fp64", 1e-14), ("fp32", 1e-6), ("fp16", 2e-3), ("fp16_f64", 2e-3)):
         ch = gpu_channel(P, p, prec)
         m = to_numpy(ch.moments())
         assert np.abs(m["rho"] - 1).max() == 0.0
@@ -73,7 +73,7 @@ CASES = [
 
 
 @pytest.mark.parametrize("case", CASES)
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16", "fp16_f32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16", "fp16_f64"])
 def test_random_state_parity(P, case, precision):
     """x- and y-dependent random state, 12 steps, odd nx (ragged tiles)."""
     from paper_2112_13930_amd.workloads import random_populations
@@ -110,7 +110,7 @@ def test_save_load_roundtrip_and_steps(P):
     assert np.array_equal(back, s0)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16", "fp16_f32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16", "fp16_f64"])
 def test_launch_shapes_and_graph_bitwise(P, precision):
     from paper_2112_13930_amd.workloads import random_populations
     p = Params(nx=300, ny=37, bc=LINK, tau_f=0.7, tau_m=0.9, b0=0.05, fx=1e-5,

@@ -44,7 +44,7 @@ CASES = [
 
 
 @pytest.mark.parametrize("case", CASES)
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16", "fp16_f32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16", "fp16_f64"])
 def test_trt_random_state_parity(P, case, precision):
     """x- and y-dependent random state, 12 steps, odd nx (ragged tiles)."""
     from paper_2112_13930_amd.workloads import random_populations
