@@ -597,16 +597,26 @@ def profile_run_batch(torch, args):
 
 
 def profile_run(torch, args):
-    """Headline steps only, plus a device copy of known size (counter scale)."""
+    """Headline steps only (in the storage precision --precision, from rest or
+    on the developed random state with --developed), plus a device copy of
+    known size (counter scale)."""
     from paper_2112_13930_amd.channel import Channel
+    from paper_2112_13930_amd.workloads import random_populations
     a = torch.empty(COPY_REF_BYTES // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
     for _ in range(3):
         b.copy_(a)
     torch.cuda.synchronize()
-    _, per_step, ch = time_channel(torch, Channel, HEADLINE, args.steps, args.warmup)
+    del a, b
+    kw = dict(HEADLINE, precision=args.precision)
+    ch = Channel(**kw, stream=torch.cuda.Stream())
+    if args.developed:
+        ch.load_state(torch.from_numpy(random_populations(4096, 4096, seed=5, b0=0.0023)))
+    _, per_step, ch = time_channel(torch, Channel, kw, args.steps, args.warmup, channel=ch)
     ch.close()
-    print(json.dumps({"profile_run": True, "steps": args.steps, "per_step_ms": per_step * 1e3}))
+    print(json.dumps({"profile_run": True, "precision": args.precision,
+                      "developed": bool(args.developed), "steps": args.steps,
+                      "per_step_ms": per_step * 1e3}))
 
 
 # ---------------------------------------------------------------------------
@@ -656,39 +666,56 @@ def _read_csv(path):
         return list(csv.DictReader(fh))
 
 
-def summarize(dirs):
-    """Write profiles/ summaries from rocprofv3 output directories:
-    kernel stats (--kernel-trace --stats) and counter runs (--pmc)."""
-    out = {"source_hash": kernel_source_hash()}
+def summarize(dirs, pattern=r"k_step"):
+    """Kernel statistics (--kernel-trace --stats) and counters (--pmc) of the
+    kernels whose names match `pattern` ("step") and of the reference copy
+    ("copy"), from rocprofv3 output directories."""
+    import re
+    rx = re.compile(pattern)
+    out = {"source_hash": kernel_source_hash(), "kernel_pattern": pattern}
     lines = []
+
+    def kind(name):
+        if rx.search(name) and "MODE" not in name:
+            return "step"
+        if "copy" in name.lower() or "elementwise" in name.lower():
+            return "copy"
+        return None
+
     for d in dirs:
         for f in sorted(glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)):
-            rows = _read_csv(f)
-            for r in rows:
+            for r in _read_csv(f):
                 name = r.get("Name", "")
-                if "k_step" in name or "copy" in name.lower() or "elementwise" in name.lower():
+                k = kind(name)
+                if k:
                     lines.append((name[:140], r.get("Calls"), r.get("AverageNs"), r.get("Percentage")))
-                    if "k_step" in name and "MODE" not in name:
-                        out.setdefault("step_avg_ns", float(r["AverageNs"]))
-                        out.setdefault("step_calls", int(r["Calls"]))
+                if k == "step":
+                    out.setdefault("step_avg_ns", float(r["AverageNs"]))
+                    out.setdefault("step_calls", int(r["Calls"]))
+                    out.setdefault("step_kernel", name[:200])
         for f in sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)):
-            rows = _read_csv(f)
             acc = {}
-            for r in rows:
+            for i, r in enumerate(_read_csv(f)):
                 name = r.get("Kernel_Name", r.get("Kernel-Name", ""))
                 cn = r.get("Counter_Name", r.get("Counter-Name", ""))
                 val = float(r.get("Counter_Value", r.get("Counter-Value", "nan")))
-                key = ("step" if "k_step" in name else "copy" if ("copy" in name.lower() or "elementwise" in name.lower()) else None)
-                if key is None:
+                k = kind(name)
+                if k is None:
                     continue
-                acc.setdefault((key, cn), []).append(val)
-            for (key, cn), vals in acc.items():
-                out[f"{key}_{cn}_kib_per_dispatch"] = statistics.median(vals)
+                # one row per dispatch and counter (summed over dimensions)
+                disp = (r.get("Dispatch_Id") or r.get("Dispatch-Id") or r.get("Correlation_Id")
+                        or f"row{i}")
+                acc.setdefault((k, cn), {}).setdefault(disp, 0.0)
+                acc[(k, cn)][disp] += val
+            for (k, cn), per in acc.items():
+                unit = "kib_per_dispatch" if cn in ("FETCH_SIZE", "WRITE_SIZE") else "per_dispatch"
+                out[f"{k}_{cn}_{unit}"] = statistics.median(per.values())
     return out, lines
 
 
-def write_summary(dirs, command):
-    out, lines = summarize(dirs)
+def write_summary(dirs, command, pattern=r"k_step", name="fp32_step_4096",
+                  algorithmic=152 * 4096 * 4096):
+    out, lines = summarize(dirs, pattern)
     fetch_s = out.get("step_FETCH_SIZE_kib_per_dispatch")
     write_s = out.get("step_WRITE_SIZE_kib_per_dispatch")
     fetch_c = out.get("copy_FETCH_SIZE_kib_per_dispatch")
@@ -700,11 +727,11 @@ def write_summary(dirs, command):
     if fetch_s and write_s and "fetch_scale" in out:
         out["step_hbm_bytes_per_dispatch"] = (fetch_s * 1024 / out["fetch_scale"] +
                                               write_s * 1024 / out["write_scale"])
-        out["algorithmic_bytes_per_dispatch"] = 152 * 4096 * 4096
+    out["algorithmic_bytes_per_dispatch"] = algorithmic
     out["command"] = command
     os.makedirs(PROFILE_DIR, exist_ok=True)
-    if fetch_s or write_s:
-        with open(TRAFFIC_FILE, "w") as fh:
+    if fetch_s or write_s or any(k.startswith("step_SQ_") for k in out):
+        with open(os.path.join(PROFILE_DIR, f"{name}_traffic.json"), "w") as fh:
             json.dump(out, fh, indent=1)
     return out, lines
 
@@ -728,16 +755,26 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--profile-run", action="store_true")
+    ap.add_argument("--precision", default="fp32", help="storage precision of --profile-run")
+    ap.add_argument("--developed", action="store_true",
+                    help="--profile-run on the developed random state instead of from rest")
     ap.add_argument("--profile-3d", action="store_true", help="3D FP32 steps only (profiling)")
     ap.add_argument("--profile-batch", action="store_true",
                     help="256-channel FP32 batch steps only (profiling)")
     ap.add_argument("--only", choices=sorted(LEGS), help="run one extra leg and print it")
     ap.add_argument("--summarize", nargs="*")
     ap.add_argument("--command", default="")
+    ap.add_argument("--kernel-pattern", default=r"k_step",
+                    help="--summarize: regular expression of the profiled kernel's name")
+    ap.add_argument("--profile-name", default="fp32_step_4096",
+                    help="--summarize: profiles/<name>_traffic.json is written")
+    ap.add_argument("--algorithmic-bytes", type=float, default=152 * 4096 * 4096,
+                    help="--summarize: algorithmic HBM bytes of one launch")
     args = ap.parse_args()
 
     if args.summarize:
-        out, lines = write_summary(args.summarize, args.command)
+        out, lines = write_summary(args.summarize, args.command, args.kernel_pattern,
+                                   args.profile_name, args.algorithmic_bytes)
         print(json.dumps(out, indent=1))
         for ln in lines:
             print(ln)

@@ -228,12 +228,19 @@ int lks_mhd_derive(const lks_mhd_params *p, lks_mhd_derived *out);
 size_t lks_mhd_state_bytes(const lks_mhd_params *p);
 
 /*
- * Create a channel on the current device.  dev_buf (>= lks_mhd_state_bytes,
- * 256-byte aligned) is caller-owned device memory that must outlive the
- * handle; the library carves its buffers from it and allocates no device
- * memory.  hip_stream is the hipStream_t all work is enqueued on (NULL: the
- * default stream).  The state is initialised (asynchronously) to the rest
- * equilibrium described above.  *out receives the handle.
+ * Create a channel on the current device: the two distributions of Secs. IV
+ * (D2Q5 vector field g) and V (D2Q9 flow f) on an nx x ny lattice, with the
+ * parameters the paper's channel flows take (relaxation times, Hartmann
+ * number and imposed field, wall conductance ratio c_w of the Shercliff
+ * condition of Sec. III per wall, wall velocities of App. B, body force;
+ * Sec. VIII and App. C).  dev_buf (>= lks_mhd_state_bytes, 256-byte aligned)
+ * is caller-owned device memory that must outlive the handle; the library
+ * carves its buffers from it and allocates no device memory.  hip_stream is
+ * the hipStream_t all work is enqueued on (NULL: the default stream).  The
+ * state is initialised (asynchronously) to the equilibrium at rest, density
+ * rho0, B = (0, B0).  *out receives the handle.  LKS_EINVAL for invalid
+ * parameters, a NULL or misaligned buffer or a NULL out; LKS_ENOMEM if bytes
+ * is below lks_mhd_state_bytes; LKS_EDEVICE if a HIP call fails.
  */
 int lks_mhd_create(const lks_mhd_params *p, void *dev_buf, size_t bytes,
                    void *hip_stream, lks_mhd_t **out);
@@ -241,8 +248,14 @@ int lks_mhd_create(const lks_mhd_params *p, void *dev_buf, size_t bytes,
 /* Release the handle (device memory stays the caller's).  NULL is a no-op. */
 int lks_mhd_destroy(lks_mhd_t *h);
 
-/* Enqueue nsteps >= 0 fused time steps (pull stream, wall closure, moments,
- * coupled J/u solve, collide, store).  Asynchronous. */
+/* Enqueue nsteps >= 0 fused time steps: pull streaming of f and g (Secs.
+ * IV and V), the wall closure of the populations entering from a wall
+ * (link-based, Sec. VI and App. B.1, or moment-based, Sec. VII, App. A and
+ * App. B.2), the moments and the coupled solve of u and J_z (Sec. IV's
+ * current from the field's non-equilibrium first moment, Sec. V's velocity
+ * with half the force), the collision of f with the force source (Sec. V)
+ * and of g (Sec. IV), and the store.  Asynchronous; LKS_EINVAL for a NULL
+ * handle or nsteps < 0, LKS_EDEVICE if a launch fails. */
 int lks_mhd_step(lks_mhd_t *h, int64_t nsteps);
 
 /* Replay step sequences from a captured HIP graph of steps_per_graph (even,
@@ -264,7 +277,9 @@ int lks_mhd_set_launch_shape(lks_mhd_t *h, int32_t shape);
 int64_t lks_mhd_steps_done(const lks_mhd_t *h);
 
 /*
- * Advance until the steady-state residual falls below tol.  Steps go in
+ * Advance until the steady-state residual falls below tol (the paper runs
+ * its channel flows to a steady state, Sec. VIII; the residual below is this
+ * library's definition of one).  Steps go in
  * windows of K = check_every (>= 2) steps; the first step of a window
  * records phi = (u_x, B_x), the last one compares and reduces in FP64 (fixed
  * order, deterministic)
@@ -284,13 +299,24 @@ int lks_mhd_run_to_steady(lks_mhd_t *h, double tol, int64_t check_every,
                           double *residual, double *flow_rate);
 
 /*
- * Observables of the current state: the density, velocity, magnetic field and
- * current density J_z that the next step collides with (after streaming and
- * wall closure), in FP64.  Each pointer is a device array of nx*ny doubles or
- * NULL to skip.  Asynchronous.
+ * Observables of the current state (Secs. IV and V): the density
+ * rho = sum f, the velocity u from rho u = sum f e + F/2 with the force F of
+ * the coupled solve, the field B = sum g and the current density J_z from
+ * the non-equilibrium part of the field's first moment -- the fields the
+ * next step collides with (after streaming and wall closure), in FP64.
+ * Each pointer is a HOST array of nx*ny doubles, row-major [ny][nx], or NULL
+ * to skip; the caller owns them.  Synchronous: waits for the handle's
+ * stream, then returns with the arrays filled.  Stages the values through
+ * the record buffer inside the handle's device memory (no allocation).
+ * LKS_EINVAL for a NULL handle, LKS_EDEVICE if a HIP call fails.
  */
 int lks_mhd_moments(lks_mhd_t *h, double *rho, double *ux, double *uy,
                     double *bx, double *by, double *jz);
+
+/* The same observables written to DEVICE arrays of nx*ny doubles (or NULL
+ * to skip), enqueued on the handle's stream.  Asynchronous. */
+int lks_mhd_moments_device(lks_mhd_t *h, double *rho, double *ux, double *uy,
+                           double *bx, double *by, double *jz);
 
 /* Copy the state out to / in from a device FP64 array [19][ny][nx] of raw
  * population values (checkpoint, resume, parity tests).  load_state resets

@@ -90,6 +90,7 @@ SIGNATURES = {
     "lks_mhd_steps_done": (_c.c_int64, [_vp]),
     "lks_mhd_run_to_steady": (_c.c_int, [_vp, _c.c_double, _c.c_int64, _c.c_int64, _i64p, _dp, _dp]),
     "lks_mhd_moments": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "lks_mhd_moments_device": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "lks_mhd_save_state": (_c.c_int, [_vp, _vp]),
     "lks_mhd_load_state": (_c.c_int, [_vp, _vp, _c.c_int64]),
     "lks_mhd_rebase": (_c.c_int, [_vp]),

@@ -39,6 +39,11 @@ class Channel:
         # torch allocations are at least 512-byte aligned
         self._buf = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self._h = ctypes.c_void_p()
+        # the buffer was allocated on torch's current stream; the library
+        # initialises it on self.stream
+        cur = torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            self.stream.wait_stream(cur)
         with torch.cuda.device(self.device):
             check(lib().lks_mhd_create(ctypes.byref(self.params), _ptr(self._buf), nbytes,
                                        ctypes.c_void_p(self.stream.cuda_stream),
@@ -47,6 +52,9 @@ class Channel:
     # ------------------------------------------------------------------
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
+            # work in flight on self.stream (steps, replayed graphs) still uses
+            # the buffer, which returns to torch's allocator after this
+            self.stream.synchronize()
             lib().lks_mhd_destroy(self._h)
             self._h = ctypes.c_void_p()
 
@@ -99,9 +107,21 @@ class Channel:
         out = {k: torch.empty((self.ny, self.nx), dtype=torch.float64, device=self.device)
                for k in ("rho", "ux", "uy", "bx", "by", "jz")}
         self._enter()
-        check(lib().lks_mhd_moments(self._h, *(_ptr(out[k]) for k in
-                                    ("rho", "ux", "uy", "bx", "by", "jz"))), "lks_mhd_moments")
+        check(lib().lks_mhd_moments_device(self._h, *(_ptr(out[k]) for k in
+                                           ("rho", "ux", "uy", "bx", "by", "jz"))),
+              "lks_mhd_moments_device")
         self._leave()
+        return out
+
+    def moments_host(self) -> dict:
+        """The same fields as NumPy arrays through the synchronous host-pointer
+        entry point lks_mhd_moments."""
+        import numpy as np
+        out = {k: np.empty((self.ny, self.nx), dtype=np.float64)
+               for k in ("rho", "ux", "uy", "bx", "by", "jz")}
+        self._enter()
+        check(lib().lks_mhd_moments(self._h, *(out[k].ctypes.data_as(ctypes.c_void_p) for k in
+                                    ("rho", "ux", "uy", "bx", "by", "jz"))), "lks_mhd_moments")
         return out
 
     def save_state(self) -> torch.Tensor:

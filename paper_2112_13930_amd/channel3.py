@@ -43,6 +43,11 @@ class Channel3:
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self._buf = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self._h = ctypes.c_void_p()
+        # the buffer was allocated on torch's current stream; the library
+        # initialises it on self.stream
+        cur = torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            self.stream.wait_stream(cur)
         with torch.cuda.device(self.device):
             check(lib().lks_mhd3_create(ctypes.byref(self.params), _ptr(self._buf), nbytes,
                                         ctypes.c_void_p(self.stream.cuda_stream),
@@ -50,6 +55,9 @@ class Channel3:
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
+            # work in flight on self.stream (steps, replayed graphs) still uses
+            # the buffer, which returns to torch's allocator after this
+            self.stream.synchronize()
             lib().lks_mhd3_destroy(self._h)
             self._h = ctypes.c_void_p()
 

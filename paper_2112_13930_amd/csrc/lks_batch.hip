@@ -140,7 +140,8 @@ __global__ __launch_bounds__(kTileThreads, (kBatchWaves<S, C, MODE>)) void k_bat
         v[3] += b * b;
         v[4] += u;
         const bool ok = isfinite((double)o.rho) && isfinite(u) && isfinite((double)o.uy) &&
-                        isfinite(b) && isfinite((double)o.by) && (double)o.rho > 0.0;
+                        isfinite(b) && isfinite((double)o.by) && (double)o.rho > 0.0 &&
+                        fabs(u) < 1.0 && fabs((double)o.uy) < 1.0;
         v[5] += ok ? 0.0 : 1.0;
       }
     };
@@ -762,7 +763,8 @@ int lks_mhd_batch_admit(lks_mhd_batch_t *b, const lks_mhd_params *p, int32_t *sl
   // b->parity, and the channel must read buf[0] then: phase = parity.
   d.phase = b->parity;
   d.step_base = (uint32_t)b->global_steps;
-  d.kf = make_coef<float>(c);
+  // binary16 computed in FP32 takes its increments in stored units
+  d.kf = make_coef<float>(c, b->precision == LKS_FP16_STORE ? kStoreUp16 : 1.0);
   d.kd = make_coef<double>(c);
   sl.admit_step = b->global_steps;
   rc = with_device(b, [&]() -> int {

@@ -42,14 +42,19 @@ struct WallD {
 };
 void wall_coefficients(const Channel &c, WallD *lo, WallD *hi);
 
+// inc_scale multiplies the coefficients that only ever scale collision
+// increments (relaxation rates and source weights): the FP32-arithmetic
+// binary16 mode takes its increments in stored units (x 2^12); a power of
+// two changes no rounding.
 template <typename C>
-Coef<C> make_coef(const Channel &c) {
+Coef<C> make_coef(const Channel &c, double inc_scale = 1.0) {
   WallD lo, hi;
   wall_coefficients(c, &lo, &hi);
   Coef<C> k;
-  k.omega_f = C(1.0 / c.p.tau_f);
-  k.kappa_f = C(1.0 - 0.5 / c.p.tau_f);
-  k.omega_m = C(1.0 / c.p.tau_m);
+  const double sc = inc_scale;
+  k.omega_f = C(sc * (1.0 / c.p.tau_f));
+  k.kappa_f = C(sc * (1.0 - 0.5 / c.p.tau_f));
+  k.omega_m = C(sc * (1.0 / c.p.tau_m));
   k.k_m = C(3.0 / c.p.tau_m);
   k.b0 = C(c.d.b0);
   k.fex = C(c.d.fx);
@@ -63,13 +68,13 @@ Coef<C> make_coef(const Channel &c) {
   const double fp = 1.0 / c.p.tau_f, fm = c.d.s_fq;
   const double gp = c.d.s_me, gm = 1.0 / c.p.tau_m;
   const double fa = 0.5 * (fp + fm), fb = 0.5 * (fp - fm);
-  k.trt = Trt<C>{C(fa), C(fb), C(1.0 - 0.5 * fa), C(-0.5 * fb),
-                 C(0.5 * (gp + gm)), C(0.5 * (gp - gm)), C(gp)};
+  k.trt = Trt<C>{C(sc * fa), C(sc * fb), C(sc * (1.0 - 0.5 * fa)), C(sc * (-0.5 * fb)),
+                 C(sc * (0.5 * (gp + gm))), C(sc * (0.5 * (gp - gm))), C(sc * gp)};
   // MRT corrections on top of that TRT step (Mrt<C>)
-  k.mrt = Mrt<C>{C((c.d.s_fe - fp) / 36.0),    C((c.d.s_feps - fp) / 36.0),
-                 C((c.d.s_md - c.d.s_me) / 4.0), C((c.d.s_fe - fp) / 2394.0),
-                 C((c.d.s_feps - fp) / 252.0),  C((c.d.s_feps - fp) / 72.0),
-                 C((c.d.s_feps - fp) / 24.0)};
+  k.mrt = Mrt<C>{C(sc * ((c.d.s_fe - fp) / 36.0)),    C(sc * ((c.d.s_feps - fp) / 36.0)),
+                 C(sc * ((c.d.s_md - c.d.s_me) / 4.0)), C(sc * ((c.d.s_fe - fp) / 2394.0)),
+                 C(sc * ((c.d.s_feps - fp) / 252.0)),  C(sc * ((c.d.s_feps - fp) / 72.0)),
+                 C(sc * ((c.d.s_feps - fp) / 24.0))};
   k.mrt_on = c.p.collision == LKS_MRT ? 1 : 0;
   // enclosure walls: r = (theta-1)/(theta+1), theta = c a / (tau_m - 1/2)
   auto xr = [&](double cw) {

@@ -319,6 +319,22 @@ __device__ __forceinline__ void collide_f_pair(C &fa, C &fb, C w, C eu, C eF, C 
   tsum = (na + nb) - C(0.5) * (Sa + Sb);
 }
 
+// BGK increments of the pair (a, abar) of opposite f populations
+// (f~ - f = omega (feq - f) + kappa S for each), written with the parts of
+// the equilibrium and the source even and odd under e -> -e.
+template <typename C>
+__device__ __forceinline__ void collide_f_pair_bgk(C &fa, C &fb, C w, C eu, C eF, C rhop, C rho,
+                                                   C usq15, C uF, C omega, C kappa) {
+  const C even = C(4.5) * eu * eu - usq15;
+  const C odd = C(3) * eu;
+  const C pa = even + odd, pb = even - odd;
+  const C na = w * (rhop + rho * pa) - fa;
+  const C nb = w * (rhop + rho * pb) - fb;
+  const C ks = C(3) * w * kappa;
+  fa = omega * na + ks * ((eF - uF) * (C(1) + pa));
+  fb = omega * nb + ks * ((-eF - uF) * (C(1) + pb));
+}
+
 // Two-relaxation-time update of a pair of opposite g populations with
 // equilibria ea, eb.
 template <typename C, bool INC = false>
@@ -546,7 +562,13 @@ __device__ __forceinline__ void node_finish(const Geom &g, const Coef<C> &k,
 
   // ---- coupled local solve ----
   C ux, uy, jz, Fx, Fy;
-  const C inv_rho = C(1) / rho;
+  // (the exact-accumulation mode takes the hardware reciprocal, 1 ulp: its
+  // error stays out of the conserved moments, which are restored in FP64)
+  auto recip = [](C v) -> C {
+    if constexpr (XA && sizeof(C) == 4) return __builtin_amdgcn_rcpf(v);
+    else return C(1) / v;
+  };
+  const C inv_rho = recip(rho);
   if (wall_of(BC) == BC_MOMENT && (lo || hi)) {
     // wet wall node: velocity fixed by the closure, no force
     ux = mx * inv_rho;
@@ -562,7 +584,8 @@ __device__ __forceinline__ void node_finish(const Geom &g, const Coef<C> &k,
     const C px = mx + C(0.5) * k.fex;
     const C py = my + C(0.5) * k.fey;
     const C Pm = px * by - py * bx;
-    jz = k.k_m * (C(2) * Pm - rho * D) / (rho + k.k_m * (bx * bx + by * by));
+    if constexpr (XA) jz = k.k_m * (C(2) * Pm - rho * D) * recip(rho + k.k_m * (bx * bx + by * by));
+    else jz = k.k_m * (C(2) * Pm - rho * D) / (rho + k.k_m * (bx * bx + by * by));
     Fx = k.fex - jz * by;
     Fy = k.fey + jz * bx;
     ux = (mx + C(0.5) * Fx) * inv_rho;
@@ -660,15 +683,12 @@ __device__ __forceinline__ void node_finish(const Geom &g, const Coef<C> &k,
   }
   const C wm = k.omega_m;
   if constexpr (XA) {
+    // the opposite pairs share e.u and the even part of the equilibrium
     f[0] = collide_f<C, true>(f[0], w0, C(0), C(0), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka);
-    f[1] = collide_f<C, true>(f[1], w1, C(1), C(0), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka);
-    f[2] = collide_f<C, true>(f[2], w1, C(0), C(1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka);
-    f[3] = collide_f<C, true>(f[3], w1, C(-1), C(0), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka);
-    f[4] = collide_f<C, true>(f[4], w1, C(0), C(-1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka);
-    f[5] = collide_f<C, true>(f[5], w5, C(1), C(1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka);
-    f[6] = collide_f<C, true>(f[6], w5, C(-1), C(1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka);
-    f[7] = collide_f<C, true>(f[7], w5, C(-1), C(-1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka);
-    f[8] = collide_f<C, true>(f[8], w5, C(1), C(-1), rhop, rho, ux, uy, usq15, Fx, Fy, uF, om, ka);
+    collide_f_pair_bgk(f[1], f[3], w1, ux, Fx, rhop, rho, usq15, uF, om, ka);
+    collide_f_pair_bgk(f[2], f[4], w1, uy, Fy, rhop, rho, usq15, uF, om, ka);
+    collide_f_pair_bgk(f[5], f[7], w5, ux + uy, Fx + Fy, rhop, rho, usq15, uF, om, ka);
+    collide_f_pair_bgk(f[6], f[8], w5, uy - ux, Fy - Fx, rhop, rho, usq15, uF, om, ka);
     gx[0] = wm * (W0 * bx - gx[0]);
     gx[1] = wm * (W1 * bx - gx[1]);
     gx[2] = wm * (W1 * (bx - E3) - gx[2]);
@@ -709,24 +729,25 @@ __device__ __forceinline__ void node_finish(const Geom &g, const Coef<C> &k,
 // The stored value of plane q at row y is s = (v - D[y][q]) * 2^12, v the
 // post-collision deviation and D the row reference (FP32 values).  Per row
 // two more tables describe the pre-collision values a node of that row
-// collides with: v_pre[q] = V[y][q] + e[q], where e is the small part that
-// varies along the row -- a pulled binary16 value times 2^-12, or a linear
-// map of such values where a Hartmann-wall closure sets the population --
-// and V holds the rest: the reference of the row the population comes from,
-// or the closure applied to the references with its constant terms.  K[y][q]
-// = V[y][q] - D[y][q] in FP64 (exact), so v_pre - D[y][q] = K + e exactly.
-// The collision works in FP32 on V + e.  Its increments then have their
-// conserved moments restored in FP64 -- zero for mass and for B, the total
-// force F for momentum -- and the new stored value K + e + increment is
-// formed in FP64 before the stochastic rounding.  FP32 rounding then leaves
-// no residual in the moments the collision conserves, which the slow modes
-// of a steady channel would otherwise integrate step after step; what it
-// leaves in the other moments relaxes within a few steps.
+// collides with: v_pre[q] = V[y][q] + e[q] 2^-12, where e is the small part
+// that varies along the row -- a pulled stored value, or a linear map of
+// such values where a Hartmann-wall closure sets the population -- and V
+// holds the rest: the reference of the row the population comes from, or
+// the closure applied to the references with its constant terms.
+// K[y][q] = (V[y][q] - D[y][q]) 2^12 in FP64, so that the new stored value
+// of a population with collision increment d is K + e + d 2^12, exactly.
+// The collision works in FP32 on V + e 2^-12.  Its increments then have
+// their conserved moments restored in FP64 -- zero for mass and for B, the
+// total force F for momentum -- and the new stored value is formed in FP64
+// before the stochastic rounding.  FP32 rounding then leaves no residual in
+// the moments the collision conserves, which the slow modes of a steady
+// channel would otherwise integrate step after step; what it leaves in the
+// other moments relaxes within a few steps.
 struct XTabs {
-  float *D;  // row references [ny][kRefRow] (FP32 values)
+  float *D;    // row references [ny][kRefRow] (FP32 values)
   double *D64; // the same as doubles (FP64 decoding)
-  float *V;  // pre-collision references, FP32
-  double *K; // V - D, FP64
+  float *V;    // pre-collision references, FP32
+  double *K;   // (V - D) 2^12, FP64
 };
 
 __host__ __device__ inline long long xtab_bytes(int ny, int elem) {
@@ -770,7 +791,7 @@ __device__ __forceinline__ void xtab_row(const Geom &g, const Coef<double> &k, X
     v[q] = (double)(up ? Dm[q] : (dn ? Dp[q] : Dy[q]));
   }
   if constexpr (wall_of(BC) == BC_LINK && cut_of(BC)) {
-    // set in FP32 by the cut-distance closure: e = v - V with V = D
+    // set in FP32 by the cut-distance closure: e = (v - V) 2^12 with V = D
     if (lo) {
       const int cl[5] = {2, 5, 6, 11, 16};
 #pragma unroll
@@ -799,16 +820,27 @@ __device__ __forceinline__ void xtab_row(const Geom &g, const Coef<double> &k, X
   const long long r = (long long)y * kRefRow;
 #pragma unroll
   for (int q = 0; q < 19; ++q) {
-    const float v32 = (float)v[q];
-    t.V[r + q] = v32;
+    t.V[r + q] = (float)v[q];
     t.D64[r + q] = (double)Dy[q];
     // pulled planes (and FP32-closed ones) have V = a reference, exact in
     // FP32; a Hartmann closure's V keeps its FP64 value in K
-    t.K[r + q] = v[q] - (double)Dy[q];
+    t.K[r + q] = (v[q] - (double)Dy[q]) * kStoreUp16;
   }
   t.V[r + 19] = 0.0f;
   t.D64[r + 19] = 0.0;
   t.K[r + 19] = 0.0;
+}
+
+// Two values rounded stochastically to binary16 (the random words of
+// lks::Rng): sr16_pre, then the hardware's round-toward-zero conversion of
+// the pair.
+__device__ __forceinline__ void sr_pair16(float a, float b, uint32_t ra, uint32_t rb,
+                                          _Float16 &oa, _Float16 &ob) {
+  typedef __fp16 hp2 __attribute__((ext_vector_type(2)));
+  const hp2 h = __builtin_amdgcn_cvt_pkrtz(sr16_pre(a, ra), sr16_pre(b, rb));
+  const uint32_t u = __builtin_bit_cast(uint32_t, h);
+  oa = __builtin_bit_cast(_Float16, (uint16_t)(u & 0xFFFFu));
+  ob = __builtin_bit_cast(_Float16, (uint16_t)(u >> 16));
 }
 
 // Collide one node of a binary16 state in FP32 with exact accumulation.
@@ -826,27 +858,36 @@ __device__ __forceinline__ void node_finish_x(const Geom &g, const Coef<float> &
   const float *__restrict__ Vy = t.V + row;
   const double *__restrict__ Ky = t.K + row;
   const float *__restrict__ Dy = t.D + row;
-  constexpr float down = float(kStoreDown16);
+  constexpr float up = float(kStoreUp16);
+  // the scales as vector registers: a VALU instruction reads at most one
+  // scalar register or literal, and the row tables are scalar where the row
+  // is uniform
+  float down = float(kStoreDown16);
+  asm volatile("" : "+v"(down));
+  // small parts in stored units (x 2^12)
   float e[19];
 #pragma unroll
-  for (int q = 0; q < 19; ++q) e[q] = (float)raw[q] * down;
+  for (int q = 0; q < 19; ++q) e[q] = (float)raw[q];
   float f[9], gx[5], gy[5];
 #pragma unroll
-  for (int q = 0; q < 9; ++q) f[q] = Vy[q] + e[q];
+  for (int q = 0; q < 9; ++q) f[q] = __builtin_fmaf(e[q], down, Vy[q]);
 #pragma unroll
-  for (int q = 0; q < 5; ++q) gx[q] = Vy[9 + q] + e[9 + q], gy[q] = Vy[14 + q] + e[14 + q];
-  // closures kept in FP32 (enclosure walls, cut-distance walls): e = v - V
-  // for the populations they set (exact: v and V are close)
+  for (int q = 0; q < 5; ++q) {
+    gx[q] = __builtin_fmaf(e[9 + q], down, Vy[9 + q]);
+    gy[q] = __builtin_fmaf(e[14 + q], down, Vy[14 + q]);
+  }
+  // closures kept in FP32 (enclosure walls, cut-distance walls): e = (v - V)
+  // 2^12 for the populations they set (exact: v and V are close)
   if constexpr (xwalls_of(BC)) {
     if (x == 0 || x == g.nx - 1) {
       xwall_closure<S, float>(g, k, src, Dy, x, y, f, gx, gy);
       if (x == 0) {
-        e[1] = f[1] - Vy[1], e[5] = f[5] - Vy[5], e[8] = f[8] - Vy[8];
-        e[10] = gx[1] - Vy[10], e[15] = gy[1] - Vy[15];
+        e[1] = (f[1] - Vy[1]) * up, e[5] = (f[5] - Vy[5]) * up, e[8] = (f[8] - Vy[8]) * up;
+        e[10] = (gx[1] - Vy[10]) * up, e[15] = (gy[1] - Vy[15]) * up;
       }
       if (x == g.nx - 1) {
-        e[3] = f[3] - Vy[3], e[6] = f[6] - Vy[6], e[7] = f[7] - Vy[7];
-        e[12] = gx[3] - Vy[12], e[17] = gy[3] - Vy[17];
+        e[3] = (f[3] - Vy[3]) * up, e[6] = (f[6] - Vy[6]) * up, e[7] = (f[7] - Vy[7]) * up;
+        e[12] = (gx[3] - Vy[12]) * up, e[17] = (gy[3] - Vy[17]) * up;
       }
     }
   }
@@ -857,8 +898,8 @@ __device__ __forceinline__ void node_finish_x(const Geom &g, const Coef<float> &
     constexpr int a0 = L ? 2 : 4, a1 = L ? 5 : 8, a2 = L ? 6 : 7; // entering planes
     if constexpr (wall_of(BC) == BC_LINK && cut_of(BC)) {
       cut_closure<S, float>(g, k, src, t.D, x, y, f, gx, gy);
-      e[a0] = f[a0] - Vy[a0], e[a1] = f[a1] - Vy[a1], e[a2] = f[a2] - Vy[a2];
-      e[9 + a0] = gx[a0] - Vy[9 + a0], e[14 + a0] = gy[a0] - Vy[14 + a0];
+      e[a0] = (f[a0] - Vy[a0]) * up, e[a1] = (f[a1] - Vy[a1]) * up, e[a2] = (f[a2] - Vy[a2]) * up;
+      e[9 + a0] = (gx[a0] - Vy[9 + a0]) * up, e[14 + a0] = (gy[a0] - Vy[14 + a0]) * up;
     } else {
       // Hartmann walls: the closure's linear part on the small parts e; V
       // holds the closure of the references with its constants
@@ -870,22 +911,27 @@ __device__ __forceinline__ void node_finish_x(const Geom &g, const Coef<float> &
       if constexpr (wall_of(BC) == BC_LINK) {
         const long long P = g.plane, r0 = (long long)y * g.pitch;
         constexpr int p0 = L ? 4 : 2, p1 = L ? 7 : 5, p2 = L ? 8 : 6; // leaving planes
-        own[0] = (float)ld<S, float>(src + p0 * P + r0 + x) * down;
-        own[1] = (float)ld<S, float>(src + p1 * P + r0 + x) * down;
-        own[2] = (float)ld<S, float>(src + p2 * P + r0 + x) * down;
-        own[3] = (float)ld<S, float>(src + (9 + p0) * P + r0 + x) * down;
-        own[4] = (float)ld<S, float>(src + (14 + p0) * P + r0 + x) * down;
+        own[0] = ld<S, float>(src + p0 * P + r0 + x);
+        own[1] = ld<S, float>(src + p1 * P + r0 + x);
+        own[2] = ld<S, float>(src + p2 * P + r0 + x);
+        own[3] = ld<S, float>(src + (9 + p0) * P + r0 + x);
+        own[4] = ld<S, float>(src + (14 + p0) * P + r0 + x);
       }
       hartmann_closure<float, wall_of(BC), false>(L, !L, ef, egx, egy, own, k.lo, k.hi);
       e[a0] = ef[a0], e[a1] = ef[a1], e[a2] = ef[a2];
       e[9 + a0] = egx[a0], e[14 + a0] = egy[a0];
-      f[a0] = Vy[a0] + e[a0], f[a1] = Vy[a1] + e[a1], f[a2] = Vy[a2] + e[a2];
-      gx[a0] = Vy[9 + a0] + e[9 + a0], gy[a0] = Vy[14 + a0] + e[14 + a0];
+      f[a0] = __builtin_fmaf(e[a0], down, Vy[a0]);
+      f[a1] = __builtin_fmaf(e[a1], down, Vy[a1]);
+      f[a2] = __builtin_fmaf(e[a2], down, Vy[a2]);
+      gx[a0] = __builtin_fmaf(e[9 + a0], down, Vy[9 + a0]);
+      gy[a0] = __builtin_fmaf(e[14 + a0], down, Vy[14 + a0]);
     }
   };
   if (lo) wall_rows(std::true_type{});
   else if (hi) wall_rows(std::false_type{});
   S unused[19];
+  // (k's relaxation coefficients carry the factor 2^12 of the stored units,
+  // so the increments come back in stored units)
   node_finish<S, float, BC, MODE, SR, true>(g, k, src, t.D, x, y, f, gx, gy, obs, sseed, unused);
   // conserved moments of the increments, in FP64: mass and B are unchanged
   // by the collision and momentum gains the force
@@ -895,8 +941,8 @@ __device__ __forceinline__ void node_finish_x(const Geom &g, const Coef<float> &
 #pragma unroll
   for (int q = 0; q < 5; ++q) d[9 + q] = (double)gx[q], d[14 + q] = (double)gy[q];
   const double m0 = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
-  const double mx = ((d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7])) - (double)obs.fx;
-  const double my = ((d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8])) - (double)obs.fy;
+  const double mx = ((d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7])) - (double)(obs.fx * up);
+  const double my = ((d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8])) - (double)(obs.fy * up);
   const double sx = (d[9] + d[10]) + (d[11] + d[12]) + d[13];
   const double sy = (d[14] + d[15]) + (d[16] + d[17]) + d[18];
   // removed on the rest population (mass), on the opposite axis pairs
@@ -907,11 +953,24 @@ __device__ __forceinline__ void node_finish_x(const Geom &g, const Coef<float> &
   d[2] -= 0.5 * my, d[4] += 0.5 * my;
   d[9] -= sx;
   d[14] -= sy;
-  Rng rng(SR ? node_seed(sseed, (uint32_t)(y * g.nx + x)) : 0u);
+  // new stored values (K + d) + e: K and d cancel to about the size of the
+  // stored values, exactly in FP64; that difference and then its sum with e
+  // round in binary32 at the stored values' own magnitude, before the
+  // stochastic rounding to binary16, two at a time
+  auto znew = [&](int q) -> float { return (float)(d[q] + Ky[q]) + e[q]; };
+  if constexpr (SR) {
+    Rng rng(node_seed(sseed, (uint32_t)(y * g.nx + x)));
 #pragma unroll
-  for (int q = 0; q < 19; ++q) {
-    const double nv = (Ky[q] + (double)e[q]) + d[q]; // new value minus D[y][q]
-    out[q] = to_store<S, float, SR, in_batch(BC)>((float)(nv * kStoreUp16), SR ? rng.next() : 0u);
+    for (int q = 0; q < 18; q += 2) {
+      const uint32_t ra = rng.next(), rb = rng.next();
+      sr_pair16(znew(q), znew(q + 1), ra, rb, out[q], out[q + 1]);
+    }
+    S spare;
+    sr_pair16(znew(18), 0.0f, rng.next(), 0x8000u, out[18], spare);
+    (void)spare;
+  } else {
+#pragma unroll
+    for (int q = 0; q < 19; ++q) out[q] = (S)znew(q);
   }
 }
 
@@ -933,45 +992,61 @@ __device__ __forceinline__ void node_update(const Geom &g, const Coef<C> &k,
   constexpr bool NT = !in_batch(BC);
 
   if constexpr (kXA<S, C> && MODE != MODE_MOMENTS) {
-    // binary16 with FP32 arithmetic: pull the stored values undecoded
-    // (x-shifted pulls through the caches, the others streamed: see ld)
-    auto lu = [&](long long off) -> S {
-      if constexpr (NT) return __builtin_nontemporal_load(src + off);
-      else return src[off];
+    // binary16 with FP32 arithmetic: pull the stored values undecoded.
+    // Addresses are a plane's base (uniform) plus a 32-bit offset within the
+    // plane, shared by every plane pulled from the same neighbour, so that
+    // each load and store takes a scalar base and one vector offset.
+    auto pl = [&](int q) -> const char * {
+      return reinterpret_cast<const char *>(src + (long long)q * P);
     };
+    // element i of a plane, the byte offset kept in 32 bits (planes hold
+    // fewer than 2^31 elements)
+    auto el = [](const char *plane, uint32_t i) -> const S * {
+      return reinterpret_cast<const S *>(plane + (uint32_t)(i * (uint32_t)sizeof(S)));
+    };
+    auto lu = [&](const char *plane, uint32_t i) -> S {
+      if constexpr (NT) return __builtin_nontemporal_load(el(plane, i));
+      else return *el(plane, i);
+    };
+    auto lc = [&](const char *plane, uint32_t i) -> S { return *el(plane, i); };
+    const uint32_t c0 = (uint32_t)(r0 + x), cm = (uint32_t)(r0 + xm), cp = (uint32_t)(r0 + xp);
+    const uint32_t d0 = (uint32_t)(rm + x), dm = (uint32_t)(rm + xm), dp = (uint32_t)(rm + xp);
+    const uint32_t u0 = (uint32_t)(rp + x), um = (uint32_t)(rp + xm), up = (uint32_t)(rp + xp);
     S raw[19];
 #pragma unroll
     for (int q = 0; q < 19; ++q) raw[q] = S(0);
-    raw[0] = lu(r0 + x);
-    raw[1] = src[1 * P + r0 + xm];
-    raw[3] = src[3 * P + r0 + xp];
-    raw[9] = lu(9 * P + r0 + x);
-    raw[10] = src[10 * P + r0 + xm];
-    raw[12] = src[12 * P + r0 + xp];
-    raw[14] = lu(14 * P + r0 + x);
-    raw[15] = src[15 * P + r0 + xm];
-    raw[17] = src[17 * P + r0 + xp];
+    raw[0] = lu(pl(0), c0);
+    raw[1] = lc(pl(1), cm);
+    raw[3] = lc(pl(3), cp);
+    raw[9] = lu(pl(9), c0);
+    raw[10] = lc(pl(10), cm);
+    raw[12] = lc(pl(12), cp);
+    raw[14] = lu(pl(14), c0);
+    raw[15] = lc(pl(15), cm);
+    raw[17] = lc(pl(17), cp);
     if (!lo) {
-      raw[2] = lu(2 * P + rm + x);
-      raw[5] = src[5 * P + rm + xm];
-      raw[6] = src[6 * P + rm + xp];
-      raw[11] = lu(11 * P + rm + x);
-      raw[16] = lu(16 * P + rm + x);
+      raw[2] = lu(pl(2), d0);
+      raw[5] = lc(pl(5), dm);
+      raw[6] = lc(pl(6), dp);
+      raw[11] = lu(pl(11), d0);
+      raw[16] = lu(pl(16), d0);
     }
     if (!hi) {
-      raw[4] = lu(4 * P + rp + x);
-      raw[7] = src[7 * P + rp + xp];
-      raw[8] = src[8 * P + rp + xm];
-      raw[13] = lu(13 * P + rp + x);
-      raw[18] = lu(18 * P + rp + x);
+      raw[4] = lu(pl(4), u0);
+      raw[7] = lc(pl(7), up);
+      raw[8] = lc(pl(8), um);
+      raw[13] = lu(pl(13), u0);
+      raw[18] = lu(pl(18), u0);
     }
     S out[19];
     NodeObs<float> &o_ = obs;
     node_finish_x<S, BC, MODE, SR>(g, k, src, xtabs_of(const_cast<C *>(ref), g.ny), x, y, raw,
                                    o_, sseed, out);
-    const long long o = r0 + x;
 #pragma unroll
-    for (int q = 0; q < 19; ++q) __builtin_nontemporal_store(out[q], dst + q * P + o);
+    for (int q = 0; q < 19; ++q) {
+      char *plane = reinterpret_cast<char *>(dst + (long long)q * P);
+      __builtin_nontemporal_store(out[q], reinterpret_cast<S *>(plane + (uint32_t)(c0 * (uint32_t)sizeof(S))));
+    }
     return;
   } else {
     // ---- pull streaming: f_a(x) = f~_a(x - e_a) ----

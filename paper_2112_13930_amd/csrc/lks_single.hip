@@ -68,7 +68,9 @@ __global__ __launch_bounds__(BX *BY) void k_step(Geom g, Coef<C> k,
   const int ty = tile / tiles_x;
   const int tx = tile - ty * tiles_x;
   const int x = tx * BX + (int)threadIdx.x;
-  const int y = ty * BY + (int)threadIdx.y;
+  // (one row per block when BY == 1: the row is then uniform, and the
+  // binary16 row tables are read as scalars)
+  const int y = BY == 1 ? ty : ty * BY + (int)threadIdx.y;
   const bool act = (x < g.nx) && (y < g.ny);
   NodeObs<C> o{};
   if (act) node_update<S, C, BC, MODE, SR>(g, k, src, ref, dst, x, y, o, sseed);
@@ -102,7 +104,8 @@ __global__ __launch_bounds__(BX *BY) void k_step(Geom g, Coef<C> k,
       v[3] = b * b;
       v[4] = u;
       const bool ok = isfinite((double)o.rho) && isfinite(u) && isfinite((double)o.uy) &&
-                      isfinite(b) && isfinite((double)o.by) && (double)o.rho > 0.0;
+                      isfinite(b) && isfinite((double)o.by) && (double)o.rho > 0.0 &&
+                        fabs(u) < 1.0 && fabs((double)o.uy) < 1.0;
       v[5] = ok ? 0.0 : 1.0;
     }
     block_sum<NRED, BX * BY>(v, lds);
@@ -573,7 +576,8 @@ int lks_mhd_create(const lks_mhd_params *p, void *dev_buf, size_t bytes,
   h->red_tiles_x = L.red_tiles_x;
   h->red_ntiles = L.red_ntiles;
   h->kd = make_coef<double>(c);
-  h->kf = make_coef<float>(c);
+  // binary16 computed in FP32 takes its increments in stored units
+  h->kf = make_coef<float>(c, c.p.precision == LKS_FP16_STORE ? kStoreUp16 : 1.0);
   // binary16 planes: two nodes per thread (4-byte accesses) measured fastest
   h->shape = (is_binary16(c.p.precision) && c.p.nx % 2 == 0) ? 5 : 0;
   h->rebase_every = is_binary16(c.p.precision) ? kDefaultRebase : 0;
@@ -729,8 +733,8 @@ int lks_mhd_run_to_steady(lks_mhd_t *h, double tol, int64_t check_every,
   return rc != LKS_OK ? rc : status;
 }
 
-int lks_mhd_moments(lks_mhd_t *h, double *rho, double *ux, double *uy,
-                    double *bx, double *by, double *jz) {
+int lks_mhd_moments_device(lks_mhd_t *h, double *rho, double *ux, double *uy,
+                           double *bx, double *by, double *jz) {
   clear_error();
   if (!h) {
     set_error("invalid handle");
@@ -742,6 +746,42 @@ int lks_mhd_moments(lks_mhd_t *h, double *rho, double *ux, double *uy,
     if (e != hipSuccess) {
       set_error("moments kernel launch failed: %s", hipGetErrorString(e));
       return LKS_EDEVICE;
+    }
+    return LKS_OK;
+  });
+}
+
+int lks_mhd_moments(lks_mhd_t *h, double *rho, double *ux, double *uy, double *bx,
+                    double *by, double *jz) {
+  clear_error();
+  if (!h) {
+    set_error("invalid handle");
+    return LKS_EINVAL;
+  }
+  return with_device(h, [&]() -> int {
+    // two fields at a time through the record buffer (2 nx ny doubles),
+    // which no step in flight uses between calls
+    const long long n = (long long)h->geom.nx * h->geom.ny;
+    double *host[6] = {rho, ux, uy, bx, by, jz};
+    for (int pair = 0; pair < 3; ++pair) {
+      double *a = host[2 * pair], *b = host[2 * pair + 1];
+      if (!a && !b) continue;
+      double *dev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+      if (a) dev[2 * pair] = h->rec;
+      if (b) dev[2 * pair + 1] = h->rec + n;
+      ObsOut oo{dev[0], dev[1], dev[2], dev[3], dev[4], dev[5]};
+      hipError_t e = launch_mode<MODE_MOMENTS>(h, kRedShape, h->buf[h->cur], nullptr, oo);
+      if (e != hipSuccess) {
+        set_error("moments kernel launch failed: %s", hipGetErrorString(e));
+        return LKS_EDEVICE;
+      }
+      if (a)
+        LKS_HIP_CHECK(hipMemcpyAsync(a, h->rec, n * sizeof(double), hipMemcpyDeviceToHost,
+                                     h->stream));
+      if (b)
+        LKS_HIP_CHECK(hipMemcpyAsync(b, h->rec + n, n * sizeof(double), hipMemcpyDeviceToHost,
+                                     h->stream));
+      LKS_HIP_CHECK(hipStreamSynchronize(h->stream));
     }
     return LKS_OK;
   });

@@ -26,6 +26,8 @@
 
 namespace lks {
 
+// 32-bit integer finalizer with the xorshift-multiply constants of the
+// "lowbias32" hash found by C. Wellons' hash-prospector search (2018).
 LKS_HD inline uint32_t mix32(uint32_t x) {
   x ^= x >> 16;
   x *= 0x7feb352dU;
@@ -117,6 +119,31 @@ LKS_HD inline _Float16 sr_f16_sel(float v, uint32_t r) {
   const int k = e >= -14 ? 13 : (e >= -24 ? -1 - e : 23);
   const uint32_t t = (mag + (r >> (32 - k))) & ~((1u << k) - 1u);
   return (_Float16)flt(sign | (e < -24 ? tiny : t));
+}
+
+// binary32 -> binary16 for a conversion that truncates (round toward zero):
+// zeros and binary16's normal range get the random bits of sr_f16's fast
+// path added below binary16's last place and leave the masking to the
+// truncation; the rest is sr_f16's exact binary16 result, which truncation
+// keeps.  Truncating the returned value gives sr_f16's bits, except that
+// magnitudes beyond binary16's range saturate at 65504 instead of becoming
+// infinite (and infinities may come back as NaN).  The kernels convert two
+// such values at once.
+LKS_HD inline float sr16_pre(float v, uint32_t r) {
+  const uint32_t b = bits32(v), m = b & 0x7FFFFFFFu;
+  if (m >= 0x38800000u || m == 0u) return flt(b + (r >> 19));
+  return (float)sr_f16(v, r);
+}
+
+// Round toward zero to binary16 (host model of the device conversion).
+LKS_HD inline _Float16 f16_rtz(float t) {
+  const uint32_t b = bits32(t);
+  const uint32_t mag = b & 0x7FFFFFFFu, sign = b & 0x80000000u;
+  if (mag >= 0x7F800000u) return (_Float16)t;                           // inf, NaN
+  if (mag >= 0x477FE000u) return (_Float16)flt(sign | 0x477FE000u);      // 65504
+  if (mag >= 0x38800000u) return (_Float16)flt(sign | (mag & ~0x1FFFu)); // exact
+  const float q = __builtin_truncf(flt(mag) * 0x1p24f) * 0x1p-24f;     // subnormal grid
+  return (_Float16)flt(sign | bits32(q));
 }
 
 // Stochastic rounding of v (compute type C) to storage type S; identity for

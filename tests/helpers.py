@@ -55,19 +55,20 @@ def rel_l2(a, b) -> float:
 def field_errors(gpu: dict, orc: dict, b0: float) -> dict:
     """Relative L2 errors of the observables: u_x, B_x, B_y and J_z against
     their own norms; u_y against ||u_x||; rho against its dynamic scale
-    max(||u_x||, ||rho - 1||, 1e-2 sqrt(N)) (rho itself is ~1 and would hide
-    errors)."""
+    max(||u_x||, ||rho - 1||) (rho itself is ~1 and would hide errors), and
+    rho_abs, the RMS of the absolute density error, which assert_close holds
+    to the precision's absolute density bar where the dynamic scale is tiny
+    (a channel near rest)."""
     nu = max(np.linalg.norm(orc["ux"]), 1e-300)
-    # floor: an RMS density deviation of 1e-2 (the oracle stores raw
-    # populations near 0.44 and accumulates a few 1e-15 of absolute rounding
-    # in rho over tens of steps, which a tiny early-time scale would magnify)
-    nr = max(nu, np.linalg.norm(orc["rho"] - 1.0), 1e-2 * np.sqrt(orc["rho"].size))
+    nr = max(nu, np.linalg.norm(orc["rho"] - 1.0))
+    drho = np.asarray(gpu["rho"], dtype=np.float64) - orc["rho"]
     return {
         "ux": rel_l2(gpu["ux"], orc["ux"]),
         "bx": rel_l2(gpu["bx"], orc["bx"]),
         "uy": float(np.linalg.norm(gpu["uy"] - orc["uy"]) / nu),
         "by": rel_l2(gpu["by"], orc["by"]),
-        "rho": float(np.linalg.norm(gpu["rho"] - orc["rho"]) / nr),
+        "rho": float(np.linalg.norm(drho) / nr),
+        "rho_abs": float(np.sqrt(np.mean(drho ** 2))),
         "jz": rel_l2(gpu["jz"], orc["jz"]) if np.linalg.norm(orc["jz"]) > 1e-30 else 0.0,
     }
 
@@ -82,9 +83,24 @@ def to_numpy(d: dict) -> dict:
 TOL = {"fp64": 1e-12, "fp32": 1e-5, "fp16": 2e-3, "fp16_f64": 2e-3}
 
 
+# Absolute RMS density error allowed where the density's dynamic scale is
+# tiny, per precision bar.  FP64: the oracle keeps raw populations of
+# 0.03-0.44 and the GPU their deviations from rest, so each step's
+# collision rounds the two differently by about one unit in the last place
+# of the populations; summed into a density near 1 and random-walking over
+# the few tens of steps of a parity run, this reaches ~14 ulp(1) (3.1e-15,
+# measured on a 40-step batch with moment walls).  The bar is 32 ulp(1) =
+# 7.1e-15.  FP32 storage: 1e-7; binary16 storage: 2e-5 (the relative bar
+# times a density deviation of 1e-2).
+RHO_ABS = {1e-12: 32 * 2.0 ** -52, 1e-5: 1e-7, 2e-3: 2e-5}
+
+
 def assert_close(errs: dict, tol: float, keys=("ux", "bx", "uy", "by", "rho")):
+    rho_abs = RHO_ABS.get(tol, 1e-2 * tol)
     bad = {k: v for k, v in errs.items() if k in keys and not (v <= tol)}
-    assert not bad, f"errors above {tol:g}: {bad} (all: {errs})"
+    if "rho" in bad and errs.get("rho_abs", math.inf) <= rho_abs:
+        del bad["rho"]
+    assert not bad, f"errors above {tol:g}: {bad} (all: {errs}; rho_abs bar {rho_abs:g})"
 
 
 def isinf(c):

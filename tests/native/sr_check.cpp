@@ -143,6 +143,40 @@ int main() {
   for (float v : {0.0f, -0.0f, 0x1p-24f, 0x1p-25f, 0x1.fffffep-25f, 0x1p-14f, 0x1.fffffep-15f,
                   0x1p-149f, 65504.0f, 65520.0f})
     for (uint32_t r : {0u, 1u, 0x7FFFFFFFu, 0x80000000u, 0xFFFFFFFFu, 0x12345678u}) same(v, r);
+  // the kernels' paired form (binary16 computed in FP32): sr16_pre and a
+  // truncating conversion give sr_f16's bits on every finite binary32
+  // pattern class below binary16's range, saturate at 65504 beyond it, and
+  // keep non-finite values non-finite
+  {
+    std::mt19937_64 g4(99);
+    auto paired = [&](float v, uint32_t r) {
+      ++checks;
+      const _Float16 a = lks::f16_rtz(lks::sr16_pre(v, r));
+      if (!std::isfinite(v)) { // infinities may come back as NaN: non-finite either way
+        if (std::isfinite((double)a) && fails++ < 10) printf("paired: finite from %a\n", (double)v);
+        return;
+      }
+      if (std::fabs(v) >= 65520.0f) {
+        // saturated, or non-finite where adding the bits overflows binary32
+        if (std::fabs((double)a) != 65504.0 && std::isfinite((double)a) && fails++ < 10)
+          printf("paired: no saturation %a\n", (double)v);
+        return;
+      }
+      const _Float16 b = sr_f16(v, r);
+      const bool saturated = std::isinf((double)b) && std::fabs((double)a) == 65504.0;
+      if (tbits(a) != tbits(b) && !(a != a && b != b) && !saturated && fails++ < 10)
+        printf("paired form differs: v=%a r=%08x\n", (double)v, r);
+    };
+    for (int t = 0; t < 1 << 22; ++t) {
+      const uint32_t e = (uint32_t)(g4() % 256u), m = (uint32_t)(g4() & 0x7FFFFFu);
+      const uint32_t sgn = (uint32_t)(g4() & 1u) << 31;
+      const uint32_t w = ((uint32_t)g4() & 0xFFFF0000u) | 0x8000u;
+      paired(__builtin_bit_cast(float, sgn | (e << 23) | (e == 255 ? 0u : m)), w);
+    }
+    for (float v : {0.0f, -0.0f, 0x1p-24f, 0x1p-25f, 0x1.fffffep-25f, 0x1p-14f, 0x1.fffffep-15f,
+                    0x1p-149f, 65504.0f, 65519.0f, 0x1.ffep15f})
+      for (uint32_t r : {0x8000u, 0xFFFF8000u, 0x12348000u, 0x80008000u}) paired(v, r);
+  }
   // the generator's words: top 16 bits spread over all values, bit 15 set
   lks::Rng rng(12345u);
   int hist[16] = {0};

@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 from oracle import LINK, MOMENT, Params, d3, derive
-from tests.helpers import TOL, lib_kwargs, rel_l2
+from tests.helpers import RHO_ABS, TOL, lib_kwargs, rel_l2
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -60,11 +60,12 @@ def mrt3(p3, **rates):
 def errors3(g, o):
     nu = max(np.linalg.norm(o["ux"]), 1e-300)
     nb = max(np.linalg.norm(o["bx"]), 1e-300)
-    nr = max(nu, np.linalg.norm(o["rho"] - 1.0), 1e-2 * math.sqrt(o["rho"].size))
+    nr = max(nu, np.linalg.norm(o["rho"] - 1.0))
+    drho = g["rho"] - o["rho"]
     e = {"ux": rel_l2(g["ux"], o["ux"]), "bx": rel_l2(g["bx"], o["bx"]),
          "uy": np.linalg.norm(g["uy"] - o["uy"]) / nu, "uz": np.linalg.norm(g["uz"] - o["uz"]) / nu,
          "by": rel_l2(g["by"], o["by"]), "bz": np.linalg.norm(g["bz"] - o["bz"]) / nb,
-         "rho": np.linalg.norm(g["rho"] - o["rho"]) / nr}
+         "rho": np.linalg.norm(drho) / nr, "rho_abs": float(np.sqrt(np.mean(drho ** 2)))}
     for k in ("jx", "jy", "jz"):
         n = np.linalg.norm(o[k])
         e[k] = rel_l2(g[k], o[k]) if n > 1e-30 else float(np.abs(g[k]).max())
@@ -72,7 +73,11 @@ def errors3(g, o):
 
 
 def assert_below(errs, tol, keys):
+    """As assert_close: the density also passes within the precision's
+    absolute density bar (RHO_ABS)."""
     bad = {k: v for k, v in errs.items() if k in keys and not v <= tol}
+    if "rho" in bad and errs["rho_abs"] <= RHO_ABS.get(tol, 1e-2 * tol):
+        del bad["rho"]
     assert not bad, f"above {tol:g}: {bad} (all {errs})"
 
 
