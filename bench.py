@@ -473,23 +473,10 @@ def mrt_rates(torch, steps=200, warmup=20):
 
 
 def stable_mix(n, seed):
-    """Config-4 channel draws, rejecting draws whose imposed field exceeds
-    0.1 (Alfven speed near the lattice limit; equivalently a Hartmann layer
-    thinner than one node at tau = 0.8).  Returns (draws, rejected)."""
-    from paper_2112_13930_amd._lib import derive, make_params
-    from paper_2112_13930_amd.workloads import channel_mix
-    draws, rejected, k = [], 0, 0
-    while len(draws) < n:
-        for d in channel_mix(n, seed + 7919 * k):
-            if len(draws) == n:
-                break
-            p = make_params(d.nx, d.ny, precision="fp32", **d.kwargs())
-            if derive(p).b0 > 0.1:
-                rejected += 1
-                continue
-            draws.append(d)
-        k += 1
-    return draws, rejected
+    """Config-4 channel draws with the stability screen (serve.screened_mix
+    over the full ranges).  Returns (draws, rejected)."""
+    from paper_2112_13930_amd.serve import screened_mix
+    return screened_mix(n, seed)
 
 
 def batched(torch, precision="fp32", steps=1000, warmup=20, seed=2024, sequential=True):
@@ -542,9 +529,13 @@ def batched(torch, precision="fp32", steps=1000, warmup=20, seed=2024, sequentia
     return out
 
 
-def serving(torch, rates=(50.0, 100.0, 200.0, 500.0, 1000.0, 2000.0), n_requests=48, seed=5):
-    from paper_2112_13930_amd.serve import serve_benchmark
-    return [serve_benchmark(n_requests=n_requests, rate=r, seed=seed, log=log) for r in rates]
+def serving(torch, rates=(50.0, 100.0, 200.0, 500.0, 1000.0, 2000.0), n_requests=256, seed=5):
+    """The continuous-batching service on 256 requests of the Ny <= 256
+    serving workload at six arrival rates, FP32 and binary16, from a pool
+    capped at a quarter of the requests' footprint, against sequential plain
+    FP32 solves (serve.serve_workload_benchmark)."""
+    from paper_2112_13930_amd.serve import serve_workload_benchmark
+    return serve_workload_benchmark(rates=rates, n_requests=n_requests, seed=seed, log=log)
 
 
 def profile_run_3d(torch, args):

@@ -29,7 +29,10 @@ class Batch:
         if pool_bytes is None:
             per_node = 2 * 19 * STORE_BYTES[precision] + 16
             pool_bytes = overhead + int(max_nodes) * per_node + self.max_channels * 4 * 256 * 19
-            pool_bytes += int(max_nodes) * 19 * 8 // 4 + self.max_channels * 256  # row references
+            # row references: [ny][20] doubles, or the four tables of binary16
+            # computed in FP32 (480 bytes a row); rows of 4 nodes and more
+            ref_row = 480 if precision == "fp16" else 160
+            pool_bytes += int(max_nodes) * ref_row // 4 + self.max_channels * 4 * ref_row
         self.pool_bytes = int(pool_bytes)
         self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
         self._pool = torch.empty(self.pool_bytes, dtype=torch.uint8, device=self.device)

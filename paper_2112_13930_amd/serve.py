@@ -42,6 +42,7 @@ class Request:
     slot: int = -1
     result: object = None
     history: list = field(default_factory=list)
+    draw: object = None      # the generator's draw the parameters come from
 
     @property
     def latency(self) -> float:
@@ -209,6 +210,28 @@ def sequential_baseline(requests, precision="fp32", tol=1e-8, check_every=200,
     return out, time.perf_counter() - t0
 
 
+def screened_mix(n, seed, b0_max=0.1, **ranges):
+    """n channels from the uneven-channel generator (workloads.channel_mix;
+    keyword ranges as there), rejecting draws whose imposed field exceeds
+    b0_max (the Alfven speed near the lattice limit; equivalently a Hartmann
+    layer thinner than one node at tau = 0.8).  Draws are taken in order
+    from the seeds seed, seed + 7919, ...  Returns (draws, rejected)."""
+    from ._lib import derive, make_params
+    from .workloads import channel_mix
+    draws, rejected, k = [], 0, 0
+    while len(draws) < n:
+        for d in channel_mix(n, seed + 7919 * k, **ranges):
+            if len(draws) == n:
+                break
+            p = make_params(d.nx, d.ny, precision="fp32", **d.kwargs())
+            if derive(p).b0 > b0_max:
+                rejected += 1
+                continue
+            draws.append(d)
+        k += 1
+    return draws, rejected
+
+
 def serve_requests_from_mix(n, seed, nx_range=(4, 32), ny_range=(16, 48), ha_range=(2.0, 30.0),
                             precision="fp32", rate=200.0, c_range=(1e-3, 1.0)):
     """Requests drawn with the uneven-channel generator on a sub-range whose
@@ -229,6 +252,22 @@ def serve_requests_from_mix(n, seed, nx_range=(4, 32), ny_range=(16, 48), ha_ran
             continue
         reqs.append(Request(rid=len(reqs), params=p, arrival=float(arr[len(reqs)])))
     return reqs
+
+
+def requests_from_draws(draws, rate, seed, precision="fp32"):
+    """Requests for the given channel draws (workloads.ChannelDraw), arriving
+    as a Poisson process of the given rate (seeded)."""
+    from ._lib import make_params
+    from .workloads import poisson_arrivals
+    arr = poisson_arrivals(rate, len(draws), seed)
+    return [Request(rid=i, params=make_params(d.nx, d.ny, precision=precision, **d.kwargs()),
+                    arrival=float(arr[i]), draw=d) for i, d in enumerate(draws)]
+
+
+# The serving workload: the uneven-channel generator restricted to Ny <= 256
+# (its other ranges unchanged: Nx 4-256, Ha 1-200 under the stability
+# screen, c = 0 or inf 10% each, else log-uniform in [1e-3, 1e3]).
+SERVE_RANGES = dict(ny_range=(32, 256))
 
 
 def _summary(lat, statuses, span, n):
@@ -284,4 +323,110 @@ def serve_benchmark(n_requests=48, rate=200.0, seed=5, precisions=("fp32", "fp16
     if baseline_precision in steps_by:
         same = sum(1 for a, b in zip(steps_by[baseline_precision], seq) if a == b["steps"])
         out["same_stop_step_" + baseline_precision] = f"{same}/{len(seq)}"
+    return out
+
+
+def fifo_from_service_times(arrivals, service):
+    """Latencies and makespan of one server taking requests in arrival order,
+    each for its own service time (a solve alone on the GPU)."""
+    t, lat = 0.0, []
+    for a, d in zip(arrivals, service):
+        t = max(t, a) + d
+        lat.append(t - a)
+    return lat, t
+
+
+def serve_workload_benchmark(rates=(50.0, 100.0, 200.0, 500.0, 1000.0, 2000.0),
+                             n_requests=256, seed=5, precisions=("fp32", "fp16"),
+                             tol=1e-8, check_every=200, max_steps=20_000,
+                             stagnation_checks=20, pool_fraction=0.25, log=None):
+    """The serving workload (SERVE_RANGES: the uneven-channel generator at
+    Ny <= 256, stability screen) at each arrival rate, served with continuous
+    batching in each storage precision from a pool capped at pool_fraction of
+    the requests' total footprint (so that admission by footprint queues
+    them), against the same requests solved one after another by the plain
+    FP32 single-channel path with the same stopping rule.  The sequential
+    solves are timed once, alone; their latencies at each rate follow from a
+    first-come-first-served queue of those service times."""
+    import torch
+
+    from ._lib import LKS_EUNSTABLE, PRECISIONS, lib, make_params
+    from .batch import Batch
+    from .channel import Channel
+    draws, rejected = screened_mix(n_requests, seed, **SERVE_RANGES)
+    probe = {}
+    for prec in precisions:
+        b = Batch(prec, max_channels=1, max_nodes=1 << 10, pool_bytes=1 << 20)
+        probe[prec] = [b.channel_bytes(make_params(d.nx, d.ny, precision=prec, **d.kwargs()))
+                       for d in draws]
+        b.close()
+    nodes = sum(d.nx * d.ny for d in draws)
+    out = {"workload": "uneven-channel generator at Ny <= 256: Nx 4-256, Ny log-uniform "
+                       "32-256, Ha log-uniform 1-200 (draws with B0 > 0.1 rejected), c = 0 or "
+                       "inf (10% each) else log-uniform 1e-3..1e3, body or shear driven at "
+                       "0.05, link or moment walls; Poisson arrivals",
+           "requests": n_requests, "rejected_draws": rejected, "nodes_total": nodes,
+           "tol": tol, "check_every": check_every, "max_steps": max_steps,
+           "stagnation_checks": stagnation_checks, "rates": list(rates), "batched": {}}
+    for prec in precisions:
+        total = sum(probe[prec])
+        cap_channels = max(int(pool_fraction * total), 2 * max(probe[prec]))
+        overhead = int(lib().lks_mhd_batch_overhead_bytes(n_requests, nodes))
+        pool = overhead + cap_channels
+        rows = []
+        for rate in rates:
+            reqs = requests_from_draws(draws, rate, seed + 1, precision=prec)
+            ex = GpuExecutor(prec, max_channels=n_requests, max_nodes=nodes, pool_bytes=pool)
+            srv = Server(ex, tol=tol, check_every=check_every, max_steps=max_steps,
+                         stagnation_checks=stagnation_checks)
+            for r in reqs:
+                srv.submit(r)
+            t0 = time.perf_counter()
+            done = srv.run()
+            torch.cuda.synchronize()
+            span = time.perf_counter() - t0
+            ex.close()
+            statuses = {}
+            for r in done:
+                statuses[r.status] = statuses.get(r.status, 0) + 1
+            row = {"rate": rate, **_summary([r.latency for r in done], statuses, span, len(done)),
+                   "mean_steps": round(statistics.mean(r.steps for r in done), 1),
+                   "max_queue_wait_s": round(max(r.t_admit - r.arrival for r in done), 4)}
+            rows.append(row)
+            if log:
+                log(f"serving workload: {prec} at {rate}/s: {span:.2f} s, {statuses}")
+        out["batched"][prec] = {"pool_bytes_for_channels": cap_channels,
+                                "requests_footprint_bytes": total, "runs": rows}
+    # sequential plain FP32 solves, each timed alone
+    service, seq_status, seq_steps = [], {}, []
+    for i, d in enumerate(draws):
+        p = make_params(d.nx, d.ny, precision="fp32", **d.kwargs())
+        p.precision = PRECISIONS["fp32"]
+        ch = Channel(params=p, stream=torch.cuda.Stream())
+        ch.set_graph(32)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hist, status, steps = [], None, 0
+        while status is None:
+            rc, steps, res, _ = ch.run_to_steady(tol=0.0, check_every=check_every,
+                                                 max_steps=check_every)
+            hist.append(math.nan if rc == LKS_EUNSTABLE else res)
+            status = stop_status(hist, steps, tol, max_steps, stagnation_checks)
+        service.append(time.perf_counter() - t0)
+        ch.close()
+        seq_status[status] = seq_status.get(status, 0) + 1
+        seq_steps.append(steps)
+        if log and i % 64 == 63:
+            log(f"serving workload: sequential {i + 1} solves, {sum(service):.1f} s")
+    seq_rows = []
+    for rate in rates:
+        arr = [r.arrival for r in requests_from_draws(draws, rate, seed + 1)]
+        lat, span = fifo_from_service_times(arr, service)
+        seq_rows.append({"rate": rate, **_summary(lat, seq_status, span, len(draws))})
+    out["sequential_fp32"] = {"solve_seconds_total": round(sum(service), 3),
+                              "mean_steps": round(statistics.mean(seq_steps), 1),
+                              "runs": seq_rows}
+    out["speedup_solves_per_s"] = {
+        prec: [round(b["solves_per_s"] / s["solves_per_s"], 2)
+               for b, s in zip(out["batched"][prec]["runs"], seq_rows)] for prec in precisions}
     return out

@@ -103,5 +103,18 @@ def assert_close(errs: dict, tol: float, keys=("ux", "bx", "uy", "by", "rho")):
     assert not bad, f"errors above {tol:g}: {bad} (all: {errs}; rho_abs bar {rho_abs:g})"
 
 
+def oracle_params_of_draw(d, nx: int = 1) -> Params:
+    """The oracle's parameters of a channel draw of the uneven-channel
+    generator (workloads.ChannelDraw): the Hartmann channel at centreline
+    velocity d.u, or the Hartmann-Couette channel with the upper wall at d.u,
+    both walls at conductance ratio d.c; nx columns (the draws start from
+    rest and are x-invariant, so one column is exact)."""
+    from oracle import derive
+    bc = oracle.LINK if d.bc == "link" else oracle.MOMENT
+    if d.drive == "body":
+        return derive.hartmann_params(nx, d.ny, bc, d.tau_f, d.tau_m, d.ha, d.c, d.u)
+    return derive.couette_params(nx, d.ny, bc, d.tau_f, d.tau_m, d.ha, d.c, d.c, d.u)
+
+
 def isinf(c):
     return math.isinf(c)

@@ -158,3 +158,33 @@ def test_pool_exhaustion_is_reported(P):
     assert b.try_admit(make_params(50, 50, precision="fp32")) is not None
     assert b.try_admit(make_params(100, 100, precision="fp32")) is None  # node budget
     b.close()
+
+
+def test_config4_mix_1000_batched_steps_match_oracle(P):
+    """The benchmark's 256 uneven channels (seed 2024, stability screen) in
+    one FP32 batch for 1000 graph-replayed steps from rest; 16 channels spread
+    over the mix against the oracle at the same step count (every column
+    against the oracle's column: the draws are x-invariant)."""
+    from paper_2112_13930_amd._lib import make_params
+    from paper_2112_13930_amd.batch import Batch
+    from paper_2112_13930_amd.serve import screened_mix
+    from tests.helpers import oracle_params_of_draw
+    draws, _ = screened_mix(256, 2024)
+    nodes = sum(d.nx * d.ny for d in draws)
+    b = Batch("fp32", max_channels=256, max_nodes=nodes + 1024)
+    slots = [b.admit(make_params(d.nx, d.ny, precision="fp32", **d.kwargs())) for d in draws]
+    b.step(1000, graph=True)
+    torch.cuda.synchronize()
+    checked = 0
+    for i in range(0, 256, 16):
+        d = draws[i]
+        m = to_numpy(b.moments(slots[i]))
+        q = oracle_params_of_draw(d)
+        st = oracle.init_state(q)
+        oracle.run(q, st, 1000)
+        o = {k: np.repeat(v, d.nx, axis=1) for k, v in oracle.observe(q, st).items()}
+        errs = field_errors(m, o, q.b0)
+        assert_close(errs, TOL["fp32"], keys=("ux", "bx", "uy", "by", "rho"))
+        checked += 1
+    b.close()
+    assert checked == 16

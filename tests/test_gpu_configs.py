@@ -40,7 +40,31 @@ def channel(p, precision, nx=None):
     return Channel(nx or p.nx, p.ny, **lib_kwargs(p, precision))
 
 
-FULL = [(LINK, 50.0, 1.0), (MOMENT, 100.0, math.inf), (LINK, 10.0, 0.0), (MOMENT, 50.0, 1e-2)]
+FULL = [(LINK, 50.0, 1.0), (MOMENT, 100.0, math.inf), (LINK, 10.0, 0.0), (MOMENT, 50.0, 1e-2),
+        (LINK, 50.0, 1e2), (MOMENT, 50.0, 1e2)]
+
+# every case of the 4096 x 4096 sweep: Ha x c x wall scheme
+SWEEP = [(bc, ha, c) for bc in (LINK, MOMENT) for ha in (10.0, 50.0, 100.0)
+         for c in (0.0, 1e-2, 1.0, 1e2, math.inf)]
+
+
+@pytest.mark.parametrize("bc,ha,c", SWEEP)
+def test_sweep_case_4096_rows_1000_steps_matches_oracle(P, bc, ha, c):
+    """Each of the 30 sweep cases with its 4096 rows and physics (shear-driven
+    Hartmann-Couette, upper wall 0.05, tau_f 0.7, tau_m 0.9), FP32, 1000 steps
+    from rest, on 4 columns: the run is x-invariant, so 4 columns are exact
+    for the 4096-wide channel; every column against the oracle's."""
+    q = derive.couette_params(1, 4096, bc, 0.7, 0.9, ha, c, c, 0.05)
+    from paper_2112_13930_amd.channel import Channel
+    ch = Channel(4, q.ny, stream=torch.cuda.Stream(), **lib_kwargs(q, "fp32"))
+    ch.set_graph(50)
+    ch.step(1000)
+    g = to_numpy(ch.moments())
+    ch.close()
+    s = oracle.init_state(q)
+    oracle.run(q, s, 1000)
+    o = {k: np.repeat(v, 4, axis=1) for k, v in oracle.observe(q, s).items()}
+    assert_close(field_errors(g, o, q.b0), TOL["fp32"], keys=("ux", "bx", "uy", "by", "rho"))
 
 
 @pytest.mark.parametrize("bc,ha,c", FULL)

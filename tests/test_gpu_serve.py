@@ -85,3 +85,47 @@ def test_trt_and_mrt_requests_alone_equal_in_mix(P, precision):
         ch = Channel(params=req.params)
         ch.step(m.steps)
         assert torch.equal(ch.save_state().cpu(), m.result["state"])
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+def test_served_results_match_oracle(P, precision):
+    """Requests of the serving workload (the uneven-channel generator at
+    Ny <= 256: Ha up to 200, c from 0 to infinity) served with continuous
+    batching and retired by the service's own rule (converged, stagnated or
+    a step budget of 6000): every retired request's u_x and B_x, against the
+    FP64 oracle run from rest to that request's step count, within the
+    precision's bar (every column against the oracle's: the channels are
+    x-invariant).  A request retired as unstable (the distribution holds
+    strongly driven channels whose induced field grows without bound) must
+    be diverging in the oracle too at that step: non-finite, or a velocity
+    above five times the driving one."""
+    import numpy as np
+
+    import oracle
+    from paper_2112_13930_amd.serve import (SERVE_RANGES, GpuExecutor, Server,
+                                            requests_from_draws, screened_mix)
+    from tests.helpers import TOL, oracle_params_of_draw, rel_l2
+    draws, _ = screened_mix(24, 11, **SERVE_RANGES)
+    reqs = requests_from_draws(draws, rate=2000.0, seed=12, precision=precision)
+    ex = GpuExecutor(precision, max_channels=32, max_nodes=1 << 21)
+    srv = Server(ex, tol=1e-8, check_every=200, max_steps=6000, keep_result=True)
+    for r in reqs:
+        srv.submit(r)
+    done = srv.run()
+    ex.close()
+    assert len(done) == 24
+    for r in done:
+        q = oracle_params_of_draw(r.draw)
+        st = oracle.init_state(q)
+        oracle.run(q, st, r.steps)
+        o = oracle.observe(q, st)
+        if r.status == "unstable":
+            u = np.abs(o["ux"]).max()
+            assert not np.isfinite(u) or u > 5 * r.draw.u, (r.rid, r.steps, u, r.draw)
+            continue
+        for k in ("ux", "bx"):
+            ref = np.repeat(o[k], r.draw.nx, axis=1)
+            if np.linalg.norm(ref) == 0.0:
+                continue
+            err = rel_l2(r.result[k], ref)
+            assert err <= TOL[precision], (r.rid, r.status, r.steps, k, err, r.draw)
