@@ -339,6 +339,28 @@ int lks_mhd_rebase(lks_mhd_t *h);
  * windows of K steps.  Ignored for FP64 and FP32 storage. */
 int lks_mhd_set_rebase(lks_mhd_t *h, int64_t every);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): advance
+ * a channel given as raw FP64 populations [19][ny][nx] on the device
+ * (dev_pops, the plane order of lks_mhd_save_state; read and overwritten in
+ * place) by nsteps >= 0 steps, step0 >= 0 being the steps the state has
+ * already taken (the stochastic-rounding stream index).  The result is bit
+ * for bit that of lks_mhd_create + lks_mhd_load_state(dev_pops, step0) +
+ * lks_mhd_step(nsteps) + lks_mhd_save_state(dev_pops) with the same
+ * parameters (plain launches, the default rebase interval of binary16).
+ * The working memory (two population buffers, row references, step
+ * counters) is a static 64 MiB device array of the library, one per GPU it
+ * runs on, held until the process ends; nothing is allocated.  LKS_ENOMEM
+ * if the channel needs more than that (about 200k nodes in FP64, 400k in
+ * FP32, 700k in binary16), LKS_EINVAL for invalid parameters or arguments,
+ * LKS_EDEVICE if a HIP call fails.  Asynchronous on hip_stream.  Every call
+ * on one GPU uses the same array: calls that overlap on a GPU (other
+ * streams, other host threads) race.
+ */
+int lks_mhd_advance_noalloc(const lks_mhd_params *p, double *dev_pops, int64_t step0,
+                            int64_t nsteps, void *hip_stream);
+
 /* Algorithmic HBM bytes of one step per node (19 populations read and
  * written) for a precision: 304, 152 or 76. */
 int lks_mhd_bytes_per_node(int32_t precision);

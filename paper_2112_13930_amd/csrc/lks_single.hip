@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <type_traits>
 
@@ -236,6 +237,11 @@ __global__ __launch_bounds__(256) void k_step_vec(Geom g, Coef<C> k, const S *__
 #pragma unroll
   for (int q = 0; q < 19; ++q)
     __builtin_nontemporal_store(outv[q], reinterpret_cast<V *>(dst + q * P + r0 + x0));
+}
+
+// Step counters of a channel set on the device (no host copy).
+__global__ void k_set_counter(uint32_t *__restrict__ ctr, uint32_t v) {
+  if (threadIdx.x < 2) ctr[threadIdx.x] = v;
 }
 
 // Fixed-order sum of per-tile partials (one block of 256 threads).
@@ -523,6 +529,40 @@ int rebase_now(lks_mhd *h) {
 
 bool rebase_due(const lks_mhd *h) {
   return h->rebase_every > 0 && h->steps % h->rebase_every == 0;
+}
+
+// Device memory of lks_mhd_advance_noalloc: one static array per device the
+// library runs on, held until the process ends.  In host code its name is
+// only a stand-in; kernels take the address hipGetSymbolAddress returns for
+// the current device.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// The scratch array's address on the current device (looked up once per
+// device); LKS_EDEVICE if the lookup fails.
+int scratch_address(void **out) {
+  int dev = 0;
+  LKS_HIP_CHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error("device %d beyond the %d the scratch table holds", dev, kMaxDevices);
+    return LKS_EDEVICE;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      set_error("hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+      return LKS_EDEVICE;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return LKS_OK;
 }
 
 } // namespace
@@ -836,6 +876,63 @@ int lks_mhd_rebase(lks_mhd_t *h) {
     return LKS_EINVAL;
   }
   return with_device(h, [&]() -> int { return rebase_now(h); });
+}
+
+int lks_mhd_advance_noalloc(const lks_mhd_params *p, double *dev_pops, int64_t step0,
+                            int64_t nsteps, void *hip_stream) {
+  clear_error();
+  if (!dev_pops || step0 < 0 || nsteps < 0) {
+    set_error("NULL populations or negative step count");
+    return LKS_EINVAL;
+  }
+  Channel c;
+  int rc = derive_channel(p, &c);
+  if (rc != LKS_OK) return rc;
+  const Layout L = layout_of(c);
+  if (L.total > kScratchBytes) {
+    set_error("channel needs %zu bytes of working memory, the scratch array holds %zu", L.total,
+              kScratchBytes);
+    return LKS_ENOMEM;
+  }
+  void *base_ptr = nullptr;
+  if ((rc = scratch_address(&base_ptr)) != LKS_OK) return rc;
+  // a handle on the stack over the scratch array, carved as lks_mhd_create
+  // carves the caller's buffer (no graphs: plain launches)
+  lks_mhd h;
+  h.ch = c;
+  if (hipGetDevice(&h.device) != hipSuccess) h.device = 0;
+  h.stream = static_cast<hipStream_t>(hip_stream);
+  h.geom = Geom{c.p.nx, c.p.ny, c.p.nx, L.plane};
+  char *base = static_cast<char *>(base_ptr);
+  h.buf[0] = base;
+  h.buf[1] = base + L.state_bytes;
+  h.rec = reinterpret_cast<double *>(base + 2 * L.state_bytes);
+  h.partials = reinterpret_cast<double *>(base + 2 * L.state_bytes + L.rec_bytes);
+  h.result = reinterpret_cast<double *>(base + 2 * L.state_bytes + L.rec_bytes + L.part_bytes);
+  h.ctr = reinterpret_cast<uint32_t *>(base + 2 * L.state_bytes + L.rec_bytes + L.part_bytes + 256);
+  h.ref = base + 2 * L.state_bytes + L.rec_bytes + L.part_bytes + 512;
+  h.red_tiles_x = L.red_tiles_x;
+  h.red_ntiles = L.red_ntiles;
+  h.kd = make_coef<double>(c);
+  h.kf = make_coef<float>(c, c.p.precision == LKS_FP16_STORE ? kStoreUp16 : 1.0);
+  h.shape = (is_binary16(c.p.precision) && c.p.nx % 2 == 0) ? 5 : 0;
+  h.rebase_every = is_binary16(c.p.precision) ? kDefaultRebase : 0;
+  // load (as lks_mhd_load_state), step (as lks_mhd_step), save
+  const int grid = elementwise_grid(&h);
+  dispatch_precision(c.p.precision, [&](auto t) {
+    using S = typename decltype(t)::S;
+    hipLaunchKernelGGL(k_load<S>, dim3(grid), dim3(256), 0, h.stream, h.geom, c.d.b0, dev_pops,
+                       static_cast<S *>(h.buf[0]));
+  });
+  LKS_HIP_CHECK(hipGetLastError());
+  if ((rc = zero_ref(&h)) != LKS_OK) return rc;
+  hipLaunchKernelGGL(k_set_counter, dim3(1), dim3(64), 0, h.stream, h.ctr, (uint32_t)step0);
+  LKS_HIP_CHECK(hipGetLastError());
+  h.steps = step0;
+  if ((rc = lks_mhd_step(&h, nsteps)) != LKS_OK) return rc;
+  rc = lks_mhd_save_state(&h, dev_pops);
+  drop_graphs(&h);
+  return rc;
 }
 
 int lks_mhd_set_rebase(lks_mhd_t *h, int64_t every) {
