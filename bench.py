@@ -561,9 +561,10 @@ def profile_run_3d(torch, args):
 
 
 def profile_run_batch(torch, args):
-    """The 256-channel FP32 batch's steps only (the batched leg's channel mix,
-    launched without a graph so that a tracer sees each step), plus a device
-    copy of known size (counter scale)."""
+    """The 256-channel batch's steps only, in the storage precision
+    --precision (the batched leg's channel mix, launched without a graph so
+    that a tracer sees each step), plus a device copy of known size (counter
+    scale)."""
     from paper_2112_13930_amd._lib import make_params
     from paper_2112_13930_amd.batch import Batch
     a = torch.empty(COPY_REF_BYTES // 4, dtype=torch.float32, device="cuda")
@@ -574,16 +575,17 @@ def profile_run_batch(torch, args):
     del a, b
     draws, _ = stable_mix(256, 2024)
     nodes = sum(d.nx * d.ny for d in draws)
-    bt = Batch("fp32", max_channels=256, max_nodes=nodes + 1024)
+    bt = Batch(args.precision, max_channels=256, max_nodes=nodes + 1024)
     for d in draws:
-        bt.admit(make_params(d.nx, d.ny, precision="fp32", **d.kwargs()))
+        bt.admit(make_params(d.nx, d.ny, precision=args.precision, **d.kwargs()))
     bt.step(args.warmup, graph=False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     bt.step(args.steps, graph=False)
     torch.cuda.synchronize()
     bt.close()
-    print(json.dumps({"profile_run_batch": True, "steps": args.steps, "nodes": nodes,
+    print(json.dumps({"profile_run_batch": True, "precision": args.precision,
+                      "steps": args.steps, "nodes": nodes,
                       "per_step_ms": (time.perf_counter() - t0) / args.steps * 1e3}))
 
 
@@ -734,6 +736,7 @@ LEGS = {"developed": developed_state_rate, "sweep": sweep, "precisions": other_p
         "mrt": mrt_rates,
         "cut_walls": cut_walls,
         "batched": lambda torch: batched(torch, "fp32"),
+        "batched_fp16": lambda torch: batched(torch, "fp16", sequential=False),
         "serving": serving}
 
 
@@ -751,7 +754,7 @@ def main():
                     help="--profile-run on the developed random state instead of from rest")
     ap.add_argument("--profile-3d", action="store_true", help="3D FP32 steps only (profiling)")
     ap.add_argument("--profile-batch", action="store_true",
-                    help="256-channel FP32 batch steps only (profiling)")
+                    help="256-channel batch steps only, in --precision (profiling)")
     ap.add_argument("--only", choices=sorted(LEGS), help="run one extra leg and print it")
     ap.add_argument("--summarize", nargs="*")
     ap.add_argument("--command", default="")

@@ -111,6 +111,41 @@ def test_save_load_roundtrip_and_steps(P):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16", "fp16_f64"])
+def test_checkpoint_resume(P, precision):
+    """run(n) against run(k) + save_state + load_state(steps=k) into a new
+    channel + run(n - k): bit for bit in FP32 storage (its values round-trip
+    through raw FP64 populations exactly, and the stochastic-rounding stream
+    resumes at step k); to round-off in FP64 (raw = deviation + weight is
+    rounded once); within the binary16 bar for binary16 (a load starts
+    without the saved channel's row references)."""
+    from paper_2112_13930_amd.workloads import random_populations
+    p = Params(nx=48, ny=30, bc=MOMENT, tau_f=0.7, tau_m=0.9, b0=0.04, fx=2e-5,
+               c_lo=0.4, c_hi=math.inf, u_hi=0.03)
+    s0 = torch.from_numpy(random_populations(48, 30, seed=21, b0=p.b0))
+    full = gpu_channel(P, p, precision, stream=torch.cuda.Stream())
+    full.load_state(s0)
+    full.step(300)
+    want_state, want = full.save_state().cpu(), to_numpy(full.moments())
+    first = gpu_channel(P, p, precision, stream=torch.cuda.Stream())
+    first.load_state(s0)
+    first.step(120)
+    saved = first.save_state().cpu()
+    resumed = gpu_channel(P, p, precision, stream=torch.cuda.Stream())
+    resumed.load_state(saved, steps=120)
+    assert resumed.steps_done == 120
+    resumed.step(180)
+    assert resumed.steps_done == 300
+    got_state, got = resumed.save_state().cpu(), to_numpy(resumed.moments())
+    if precision == "fp32":
+        assert torch.equal(got_state, want_state)
+    else:
+        assert_close(field_errors(got, want, p.b0), 1e-13 if precision == "fp64" else TOL[precision],
+                     keys=("ux", "bx", "uy", "by", "rho"))
+    for ch in (full, first, resumed):
+        ch.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16", "fp16_f64"])
 def test_launch_shapes_and_graph_bitwise(P, precision):
     from paper_2112_13930_amd.workloads import random_populations
     p = Params(nx=300, ny=37, bc=LINK, tau_f=0.7, tau_m=0.9, b0=0.05, fx=1e-5,
