@@ -48,16 +48,25 @@ struct ChanDesc {
 };
 
 // A tile is the work of one 256-thread block: either a w x h rectangle of a
-// channel (w * h == 256, x0/y0 its corner) or, with w == 0, a run of 256 * h
-// consecutive nodes of the channel's [ny][nx] planes starting at node x0
-// (each thread takes h nodes 256 apart).  Linear tiles keep every wavefront
-// on 64 consecutive addresses whatever the channel width.
+// channel (w * h == 256, x0/y0 its corner) or, with w == 0, a run of n <=
+// 256 * h consecutive nodes of the channel's [ny][nx] planes starting at node
+// x0 (thread t takes the nodes t, t + 256, ... below n).  Linear tiles keep
+// every wavefront on 64 consecutive addresses whatever the channel width.
 struct Tile {
   int chan;
   int x0, y0;
   int w, h;
-  int pad[3];
+  int n;
+  int pad[2];
 };
+
+// Binary16 storage with FP32 arithmetic reads 19 FP32 and 19 FP64 table
+// entries per node from its row (XTabs V and K).  The batched kernel copies
+// the rows a tile touches into LDS first: rows differ between the lanes of a
+// wavefront, and per-lane reads of the tables from memory would cost the
+// vector memory path more than the populations themselves.  A tile spans at
+// most kStageRows rows (linear tiles are cut to (kStageRows - 1) nx nodes).
+constexpr int kStageRows = 64;
 
 // Grid of the persistent launch: the next power of two above the tile count,
 // at most LKS_BATCH_BLOCKS_PER_CU blocks per CU (measured: more resident
@@ -92,10 +101,13 @@ __global__ __launch_bounds__(kTileThreads, (kBatchWaves<S, C, MODE>)) void k_bat
     const int *__restrict__ ntiles_dev, int parity, double *__restrict__ partials,
     uint32_t *__restrict__ gctr) {
   constexpr bool SR = kUseSR<S, C>;
+  constexpr bool XA = kXA<S, C>;
   const uint32_t gstep = gctr[parity];
   if (blockIdx.x == 0 && threadIdx.x == 0) gctr[parity ^ 1] = gstep + 1u;
   const int nt = *ntiles_dev;
   __shared__ double lds[(kTileThreads / 64) * NREDB];
+  __shared__ __align__(16) float sV[XA ? kStageRows * kRefRow : 4];
+  __shared__ __align__(16) double sK[XA ? kStageRows * kRefRow : 2];
   for (int t = blockIdx.x; t < nt; t += gridDim.x) { // uniform per block
     const Tile tl = tiles[t];
     const ChanDesc &c = chans[tl.chan];
@@ -103,30 +115,57 @@ __global__ __launch_bounds__(kTileThreads, (kBatchWaves<S, C, MODE>)) void k_bat
     const S *src = static_cast<const S *>(c.buf[cur]);
     S *dst = static_cast<S *>(c.buf[cur ^ 1]);
     const uint32_t sseed = SR ? step_seed(gstep - c.step_base) : 0u;
-    const long long n = (long long)c.g.nx * c.g.ny;
     double v[NREDB] = {0, 0, 0, 0, 0, 0};
+    auto row_of = [&](uint32_t i) -> int {
+      return (int)(((uint64_t)__umulhi(i, c.nx_magic) + i) >> c.nx_shift);
+    };
+    // first row of the tile's rows staged in LDS
+    int ya = 0;
+    if constexpr (XA) {
+      int yb;
+      if (tl.w == 0) {
+        ya = row_of((uint32_t)tl.x0);
+        yb = row_of((uint32_t)(tl.x0 + tl.n - 1));
+      } else {
+        ya = tl.y0;
+        yb = min(c.g.ny - 1, tl.y0 + tl.h - 1);
+      }
+      const int cnt = min(yb - ya + 1, kStageRows) * kRefRow;
+      const XTabs xt = xtabs_of(c.ref, c.g.ny);
+      const float *gV = xt.V + (long long)ya * kRefRow;
+      const double *gK = xt.K + (long long)ya * kRefRow;
+      __syncthreads(); // the previous tile's nodes have read their rows
+      for (int j = threadIdx.x; j < cnt; j += kTileThreads) {
+        sV[j] = gV[j];
+        sK[j] = gK[j];
+      }
+      __syncthreads();
+    }
     auto one = [&](int x, int y) {
       NodeObs<C> o{};
       const C *ref = static_cast<const C *>(c.ref);
+      const float *xV = XA ? sV + (y - ya) * kRefRow : nullptr;
+      const double *xK = XA ? sK + (y - ya) * kRefRow : nullptr;
       switch (c.bc) { // uniform per block
       case BC_LINK:
-        node_update<S, C, BC_LINK | IN_BATCH, MODE, SR>(c.g, coef_of<C>(c), src, ref, dst, x,
-                                                        y, o, sseed);
+        node_update<S, C, BC_LINK | IN_BATCH, MODE, SR, XA>(c.g, coef_of<C>(c), src, ref, dst, x,
+                                                        y, o, sseed, xV, xK);
         break;
       case BC_MOMENT:
-        node_update<S, C, BC_MOMENT | IN_BATCH, MODE, SR>(c.g, coef_of<C>(c), src, ref, dst, x,
-                                                          y, o, sseed);
+        node_update<S, C, BC_MOMENT | IN_BATCH, MODE, SR, XA>(c.g, coef_of<C>(c), src, ref, dst, x,
+                                                          y, o, sseed, xV, xK);
         break;
       case BC_LINK | COLL_TRT:
-        node_update<S, C, BC_LINK | COLL_TRT | MRT_RT | IN_BATCH, MODE, SR>(
-            c.g, coef_of<C>(c), src, ref, dst, x, y, o, sseed);
+        node_update<S, C, BC_LINK | COLL_TRT | MRT_RT | IN_BATCH, MODE, SR, XA>(
+            c.g, coef_of<C>(c), src, ref, dst, x, y, o, sseed, xV, xK);
         break;
       default:
-        node_update<S, C, BC_MOMENT | COLL_TRT | MRT_RT | IN_BATCH, MODE, SR>(
-            c.g, coef_of<C>(c), src, ref, dst, x, y, o, sseed);
+        node_update<S, C, BC_MOMENT | COLL_TRT | MRT_RT | IN_BATCH, MODE, SR, XA>(
+            c.g, coef_of<C>(c), src, ref, dst, x, y, o, sseed, xV, xK);
         break;
       }
       const long long i = (long long)y * c.g.nx + x;
+      const long long n = (long long)c.g.nx * c.g.ny;
       if constexpr (MODE == MODE_RECORD) {
         c.rec[i] = (double)o.ux;
         c.rec[n + i] = (double)o.bx;
@@ -147,10 +186,10 @@ __global__ __launch_bounds__(kTileThreads, (kBatchWaves<S, C, MODE>)) void k_bat
     };
     if (tl.w == 0) {
       for (int j = 0; j < tl.h; ++j) {
-        const int i = tl.x0 + (int)threadIdx.x + j * kTileThreads;
-        if (i < n) {
-          const uint32_t iu = (uint32_t)i;
-          const int y = (int)(((uint64_t)__umulhi(iu, c.nx_magic) + iu) >> c.nx_shift);
+        const int li = (int)threadIdx.x + j * kTileThreads;
+        if (li < tl.n) {
+          const int i = tl.x0 + li;
+          const int y = row_of((uint32_t)i);
           one(i - y * c.g.nx, y);
         }
       }
@@ -379,10 +418,17 @@ void pool_free(lks_mhd_batch *b, size_t off, size_t bytes) {
   }
 }
 
+// Nodes of a full linear tile of h nodes per thread.
+long long linear_tile_nodes(int precision, int nx, int h) {
+  const long long per = (long long)kTileThreads * h;
+  if (precision == LKS_FP16_STORE) return std::min(per, (long long)(kStageRows - 1) * nx);
+  return per;
+}
+
 // Tiles of one channel for a tile shape (w, h) (w == 0: linear).
-int count_tiles(int nx, int ny, int w, int h) {
+int count_tiles(int precision, int nx, int ny, int w, int h) {
   if (w == 0) {
-    const long long per = (long long)kTileThreads * h;
+    const long long per = linear_tile_nodes(precision, nx, h);
     return (int)(((long long)nx * ny + per - 1) / per);
   }
   return ((nx + w - 1) / w) * ((ny + h - 1) / h);
@@ -392,7 +438,8 @@ int total_tiles(const lks_mhd_batch *b, const int *tile_w, const int *tile_h) {
   long long t = 0;
   for (const Slot &s : b->slots)
     if (s.used)
-      t += count_tiles(s.ch.p.nx, s.ch.p.ny, tile_w[s.width_class], tile_h[s.width_class]);
+      t += count_tiles(b->precision, s.ch.p.nx, s.ch.p.ny, tile_w[s.width_class],
+                       tile_h[s.width_class]);
   return t > (1LL << 30) ? (1 << 30) : (int)t;
 }
 
@@ -412,11 +459,13 @@ int rebuild(lks_mhd_batch *b) {
     d.tile_first = (int)b->h_tiles.size();
     if (w == 0) {
       const long long nn = (long long)sl.ch.p.nx * sl.ch.p.ny;
-      for (long long i0 = 0; i0 < nn; i0 += (long long)kTileThreads * h)
-        b->h_tiles.push_back(Tile{s, (int)i0, 0, 0, h, {0, 0, 0}});
+      const long long per = linear_tile_nodes(b->precision, sl.ch.p.nx, h);
+      for (long long i0 = 0; i0 < nn; i0 += per)
+        b->h_tiles.push_back(Tile{s, (int)i0, 0, 0, h, (int)std::min(per, nn - i0), {0, 0}});
     } else {
       for (int y0 = 0; y0 < sl.ch.p.ny; y0 += h)
-        for (int x0 = 0; x0 < sl.ch.p.nx; x0 += w) b->h_tiles.push_back(Tile{s, x0, y0, w, h, {0, 0, 0}});
+        for (int x0 = 0; x0 < sl.ch.p.nx; x0 += w)
+          b->h_tiles.push_back(Tile{s, x0, y0, w, h, w * h, {0, 0}});
     }
     d.tile_count = (int)b->h_tiles.size() - d.tile_first;
   }
@@ -731,7 +780,8 @@ int lks_mhd_batch_admit(lks_mhd_batch_t *b, const lks_mhd_params *p, int32_t *sl
   // tile capacity check for the current shape table
   {
     if ((long long)total_tiles(b, b->tile_w, b->tile_h) +
-            count_tiles(q.nx, q.ny, b->tile_w[sl.width_class], b->tile_h[sl.width_class]) >
+            count_tiles(b->precision, q.nx, q.ny, b->tile_w[sl.width_class],
+                        b->tile_h[sl.width_class]) >
         b->max_tiles) {
       set_error("tile list capacity exceeded");
       return LKS_ENOMEM;

@@ -185,19 +185,25 @@ struct NodeObs {
 // stream past them, as the stores do, unless rows are packed (NT false,
 // the batched kernel): then a line at a row's end also holds the next
 // row's start.
+// Populations live in global memory.  Loads and stores go through pointers
+// of that address space, so that the compiler emits global (not flat)
+// instructions also where the base pointer was read from memory (the batched
+// kernel's channel descriptors) rather than passed as a kernel argument.
+template <typename T> using gptr = __attribute__((address_space(1))) T *;
+
 template <typename S, typename C, bool NT = true>
 __device__ __forceinline__ C ld(const S *__restrict__ p) {
-  if constexpr (NT) return static_cast<C>(__builtin_nontemporal_load(p));
-  else return static_cast<C>(*p);
+  if constexpr (NT) return static_cast<C>(__builtin_nontemporal_load((gptr<const S>)p));
+  else return static_cast<C>(*(gptr<const S>)p);
 }
 template <typename S, typename C>
 __device__ __forceinline__ C ldx(const S *__restrict__ p) {
-  return static_cast<C>(*p);
+  return static_cast<C>(*(gptr<const S>)p);
 }
 
 template <typename S, typename C>
 __device__ __forceinline__ void st(S *__restrict__ p, C v) {
-  __builtin_nontemporal_store(static_cast<S>(v), p);
+  __builtin_nontemporal_store(static_cast<S>(v), (gptr<S>)p);
 }
 
 // ---- stochastic rounding of the stored populations ----
@@ -847,17 +853,18 @@ __device__ __forceinline__ void sr_pair16(float a, float b, uint32_t ra, uint32_
 // raw[] holds the 19 pulled stored values (unused where a wall closes the
 // population); the new stored values are returned in out (not for
 // MODE_MOMENTS, which this path does not serve).
+// Vy and Ky are row y's entries of t.V and t.K, or a copy of them (the
+// batched kernel stages the rows of a tile in LDS).
 template <typename S, int BC, int MODE, bool SR>
 __device__ __forceinline__ void node_finish_x(const Geom &g, const Coef<float> &k,
-                                              const S *__restrict__ src, XTabs t, int x, int y,
+                                              const S *__restrict__ src, XTabs t,
+                                              const float *__restrict__ Vy,
+                                              const double *__restrict__ Ky, int x, int y,
                                               const S (&raw)[19], NodeObs<float> &obs,
                                               uint32_t sseed, S (&out)[19]) {
   static_assert(MODE != MODE_MOMENTS, "observables decode in FP64");
   const bool lo = (y == 0), hi = (y == g.ny - 1);
-  const long long row = (long long)y * kRefRow;
-  const float *__restrict__ Vy = t.V + row;
-  const double *__restrict__ Ky = t.K + row;
-  const float *__restrict__ Dy = t.D + row;
+  const float *__restrict__ Dy = t.D + (long long)y * kRefRow;
   constexpr float up = float(kStoreUp16);
   // the scales as vector registers: a VALU instruction reads at most one
   // scalar register or literal, and the row tables are scalar where the row
@@ -974,12 +981,16 @@ __device__ __forceinline__ void node_finish_x(const Geom &g, const Coef<float> &
   }
 }
 
-template <typename S, typename C, int BC, int MODE, bool SR>
+// STAGED, xV, xK: for binary16 storage with FP32 arithmetic, row y's
+// pre-collision tables come from the caller's copy xV, xK (else from ref).
+template <typename S, typename C, int BC, int MODE, bool SR, bool STAGED = false>
 __device__ __forceinline__ void node_update(const Geom &g, const Coef<C> &k,
                                             const S *__restrict__ src,
                                             const C *__restrict__ ref,
                                             S *__restrict__ dst, int x, int y,
-                                            NodeObs<C> &obs, uint32_t sseed) {
+                                            NodeObs<C> &obs, uint32_t sseed,
+                                            const float *xV = nullptr,
+                                            const double *xK = nullptr) {
   const int nx = g.nx;
   const long long P = g.plane;
   const int xm = (x == 0) ? nx - 1 : x - 1;
@@ -1001,8 +1012,8 @@ __device__ __forceinline__ void node_update(const Geom &g, const Coef<C> &k,
     };
     // element i of a plane, the byte offset kept in 32 bits (planes hold
     // fewer than 2^31 elements)
-    auto el = [](const char *plane, uint32_t i) -> const S * {
-      return reinterpret_cast<const S *>(plane + (uint32_t)(i * (uint32_t)sizeof(S)));
+    auto el = [](const char *plane, uint32_t i) -> gptr<const S> {
+      return (gptr<const S>)(plane + (uint32_t)(i * (uint32_t)sizeof(S)));
     };
     auto lu = [&](const char *plane, uint32_t i) -> S {
       if constexpr (NT) return __builtin_nontemporal_load(el(plane, i));
@@ -1040,12 +1051,14 @@ __device__ __forceinline__ void node_update(const Geom &g, const Coef<C> &k,
     }
     S out[19];
     NodeObs<float> &o_ = obs;
-    node_finish_x<S, BC, MODE, SR>(g, k, src, xtabs_of(const_cast<C *>(ref), g.ny), x, y, raw,
-                                   o_, sseed, out);
+    const XTabs t = xtabs_of(const_cast<C *>(ref), g.ny);
+    const long long row = (long long)y * kRefRow;
+    node_finish_x<S, BC, MODE, SR>(g, k, src, t, STAGED ? xV : t.V + row,
+                                   STAGED ? xK : t.K + row, x, y, raw, o_, sseed, out);
 #pragma unroll
     for (int q = 0; q < 19; ++q) {
       char *plane = reinterpret_cast<char *>(dst + (long long)q * P);
-      __builtin_nontemporal_store(out[q], reinterpret_cast<S *>(plane + (uint32_t)(c0 * (uint32_t)sizeof(S))));
+      __builtin_nontemporal_store(out[q], (gptr<S>)(plane + (uint32_t)(c0 * (uint32_t)sizeof(S))));
     }
     return;
   } else {
@@ -1085,7 +1098,7 @@ __device__ __forceinline__ void node_update(const Geom &g, const Coef<C> &k,
     if constexpr (MODE != MODE_MOMENTS) {
       const long long o = r0 + x;
 #pragma unroll
-      for (int q = 0; q < 19; ++q) __builtin_nontemporal_store(out[q], dst + q * P + o);
+      for (int q = 0; q < 19; ++q) st<S, S>(dst + q * P + o, out[q]);
     } else {
       (void)dst;
     }

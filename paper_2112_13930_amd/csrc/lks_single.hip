@@ -202,8 +202,10 @@ __global__ __launch_bounds__(256) void k_step_vec(Geom g, Coef<C> k, const S *__
                          c4[v]};
       NodeObs<C> o{};
       S out[19];
-      node_finish_x<S, BC, MODE_STEP, SR>(g, k, src, xtabs_of(const_cast<C *>(ref), g.ny), x0 + v,
-                                          y, raw, o, sseed, out);
+      const XTabs t = xtabs_of(const_cast<C *>(ref), g.ny);
+      const long long row = (long long)y * kRefRow;
+      node_finish_x<S, BC, MODE_STEP, SR>(g, k, src, t, t.V + row, t.K + row, x0 + v, y, raw, o,
+                                          sseed, out);
 #pragma unroll
       for (int q = 0; q < 19; ++q) outv[q][v] = out[q];
     } else {
