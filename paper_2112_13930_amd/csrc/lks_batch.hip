@@ -89,14 +89,18 @@ template <typename C> __device__ __forceinline__ const Coef<C> &coef_of(const Ch
 template <> __device__ __forceinline__ const Coef<float> &coef_of<float>(const ChanDesc &c) { return c.kf; }
 template <> __device__ __forceinline__ const Coef<double> &coef_of<double>(const ChanDesc &c) { return c.kd; }
 
-// Waves per SIMD the step asks the compiler for (1: no constraint).
-template <typename S, typename C, int MODE>
+// Waves per SIMD the step asks the compiler for (1: no constraint).  FP32
+// storage asks for what it reaches without spilling: 6 with the BGK schemes
+// alone, 5 with the TRT/MRT ones.
+template <typename S, typename C, int MODE, bool TRT>
 constexpr int kBatchWaves = 1;
 
 // gctr[2]: global step counters as in the single-channel kernel; a channel's
 // own step index is gctr[parity] - step_base.
-template <typename S, typename C, int MODE>
-__global__ __launch_bounds__(kTileThreads, (kBatchWaves<S, C, MODE>)) void k_batch_step(
+// TRT: the pool holds TRT or MRT channels (else only BGK ones, and the
+// kernel is built for those two schemes alone, with fewer registers).
+template <typename S, typename C, int MODE, bool TRT>
+__global__ __launch_bounds__(kTileThreads, (kBatchWaves<S, C, MODE, TRT>)) void k_batch_step(
     const ChanDesc *__restrict__ chans, const Tile *__restrict__ tiles,
     const int *__restrict__ ntiles_dev, int parity, double *__restrict__ partials,
     uint32_t *__restrict__ gctr) {
@@ -108,7 +112,17 @@ __global__ __launch_bounds__(kTileThreads, (kBatchWaves<S, C, MODE>)) void k_bat
   __shared__ double lds[(kTileThreads / 64) * NREDB];
   __shared__ __align__(16) float sV[XA ? kStageRows * kRefRow : 4];
   __shared__ __align__(16) double sK[XA ? kStageRows * kRefRow : 2];
-  for (int t = blockIdx.x; t < nt; t += gridDim.x) { // uniform per block
+  // Tiles of consecutive nodes share the cache lines at their boundaries.
+  // The hardware deals workgroups round-robin to the 8 XCDs, each with its
+  // own L2: within every group of 64 blocks, XCD j's 8 blocks take 8
+  // consecutive tiles, so that 7 of 8 tile boundaries stay within one L2
+  // while the whole grid still sweeps the tile list in order.
+  int t_first = blockIdx.x;
+  if ((gridDim.x & 63) == 0) {
+    const int b = blockIdx.x;
+    t_first = (b & ~63) | ((b & 7) << 3) | ((b >> 3) & 7);
+  }
+  for (int t = t_first; t < nt; t += gridDim.x) { // uniform per block
     const Tile tl = tiles[t];
     const ChanDesc &c = chans[tl.chan];
     const int cur = parity ^ c.phase;
@@ -146,23 +160,31 @@ __global__ __launch_bounds__(kTileThreads, (kBatchWaves<S, C, MODE>)) void k_bat
       const C *ref = static_cast<const C *>(c.ref);
       const float *xV = XA ? sV + (y - ya) * kRefRow : nullptr;
       const double *xK = XA ? sK + (y - ya) * kRefRow : nullptr;
-      switch (c.bc) { // uniform per block
-      case BC_LINK:
+      if constexpr (TRT) {
+        switch (c.bc) { // uniform per block
+        case BC_LINK:
+          node_update<S, C, BC_LINK | IN_BATCH, MODE, SR, XA>(c.g, coef_of<C>(c), src, ref, dst,
+                                                              x, y, o, sseed, xV, xK);
+          break;
+        case BC_MOMENT:
+          node_update<S, C, BC_MOMENT | IN_BATCH, MODE, SR, XA>(c.g, coef_of<C>(c), src, ref,
+                                                                dst, x, y, o, sseed, xV, xK);
+          break;
+        case BC_LINK | COLL_TRT:
+          node_update<S, C, BC_LINK | COLL_TRT | MRT_RT | IN_BATCH, MODE, SR, XA>(
+              c.g, coef_of<C>(c), src, ref, dst, x, y, o, sseed, xV, xK);
+          break;
+        default:
+          node_update<S, C, BC_MOMENT | COLL_TRT | MRT_RT | IN_BATCH, MODE, SR, XA>(
+              c.g, coef_of<C>(c), src, ref, dst, x, y, o, sseed, xV, xK);
+          break;
+        }
+      } else if (c.bc == BC_LINK) { // uniform per block
         node_update<S, C, BC_LINK | IN_BATCH, MODE, SR, XA>(c.g, coef_of<C>(c), src, ref, dst, x,
-                                                        y, o, sseed, xV, xK);
-        break;
-      case BC_MOMENT:
-        node_update<S, C, BC_MOMENT | IN_BATCH, MODE, SR, XA>(c.g, coef_of<C>(c), src, ref, dst, x,
-                                                          y, o, sseed, xV, xK);
-        break;
-      case BC_LINK | COLL_TRT:
-        node_update<S, C, BC_LINK | COLL_TRT | MRT_RT | IN_BATCH, MODE, SR, XA>(
-            c.g, coef_of<C>(c), src, ref, dst, x, y, o, sseed, xV, xK);
-        break;
-      default:
-        node_update<S, C, BC_MOMENT | COLL_TRT | MRT_RT | IN_BATCH, MODE, SR, XA>(
-            c.g, coef_of<C>(c), src, ref, dst, x, y, o, sseed, xV, xK);
-        break;
+                                                            y, o, sseed, xV, xK);
+      } else {
+        node_update<S, C, BC_MOMENT | IN_BATCH, MODE, SR, XA>(c.g, coef_of<C>(c), src, ref, dst,
+                                                              x, y, o, sseed, xV, xK);
       }
       const long long i = (long long)y * c.g.nx + x;
       const long long n = (long long)c.g.nx * c.g.ny;
@@ -184,20 +206,26 @@ __global__ __launch_bounds__(kTileThreads, (kBatchWaves<S, C, MODE>)) void k_bat
         v[5] += ok ? 0.0 : 1.0;
       }
     };
-    if (tl.w == 0) {
-      for (int j = 0; j < tl.h; ++j) {
+    // one call site of the node update for both tile kinds (a rectangle is
+    // one pass), so that each scheme's code is inlined once
+    const int passes = tl.w == 0 ? tl.h : 1;
+    for (int j = 0; j < passes; ++j) {
+      int x, y;
+      bool in;
+      if (tl.w == 0) {
         const int li = (int)threadIdx.x + j * kTileThreads;
-        if (li < tl.n) {
-          const int i = tl.x0 + li;
-          const int y = row_of((uint32_t)i);
-          one(i - y * c.g.nx, y);
-        }
+        const int i = tl.x0 + li;
+        y = row_of((uint32_t)i);
+        x = i - y * c.g.nx;
+        in = li < tl.n;
+      } else {
+        const int lx = (int)threadIdx.x % tl.w;
+        const int ly = (int)threadIdx.x / tl.w;
+        x = tl.x0 + lx;
+        y = tl.y0 + ly;
+        in = (ly < tl.h) && (x < c.g.nx) && (y < c.g.ny);
       }
-    } else {
-      const int lx = (int)threadIdx.x % tl.w;
-      const int ly = (int)threadIdx.x / tl.w;
-      const int x = tl.x0 + lx, y = tl.y0 + ly;
-      if ((ly < tl.h) && (x < c.g.nx) && (y < c.g.ny)) one(x, y);
+      if (in) one(x, y);
     }
     if constexpr (MODE == MODE_RESIDUAL) {
       block_sum<NREDB, kTileThreads>(v, lds);
@@ -330,6 +358,7 @@ struct lks_mhd_batch {
   int nactive = 0;
   int grid = 0, grid_cap = 0;
   bool dirty = false;
+  bool any_trt = false; // an active channel runs the TRT or MRT collision
   hipGraphExec_t gexec = nullptr;      // two steps
   hipGraphExec_t gexec_long = nullptr; // kLongGraphSteps steps
 };
@@ -487,8 +516,13 @@ int rebuild(lks_mhd_batch *b) {
   int grid = 1;
   while (grid < nt && grid < b->grid_cap) grid *= 2;
   if (grid > b->grid_cap) grid = b->grid_cap;
-  if (grid != b->grid) {
-    b->grid = grid; // the captured graph holds the old launch size
+  bool any_trt = false;
+  for (int s = 0; s < b->max_channels; ++s)
+    if (b->slots[s].used && (b->h_chans[s].bc & COLL_TRT)) any_trt = true;
+  if (grid != b->grid || any_trt != b->any_trt) {
+    // the captured graphs hold the old launch size and kernel
+    b->grid = grid;
+    b->any_trt = any_trt;
     if (b->gexec) {
       (void)hipGraphExecDestroy(b->gexec);
       b->gexec = nullptr;
@@ -506,8 +540,14 @@ hipError_t launch_batch(lks_mhd_batch *b, int parity) {
   dispatch_precision(b->precision, [&](auto t) {
     using S = typename decltype(t)::S;
     using C = typename decltype(t)::C;
-    hipLaunchKernelGGL((k_batch_step<S, C, MODE>), dim3(b->grid), dim3(kTileThreads), 0, b->stream,
-                       b->d_chans, b->d_tiles, b->d_ntiles, parity, b->d_partials, b->d_gctr);
+    if (b->any_trt)
+      hipLaunchKernelGGL((k_batch_step<S, C, MODE, true>), dim3(b->grid), dim3(kTileThreads), 0,
+                         b->stream, b->d_chans, b->d_tiles, b->d_ntiles, parity, b->d_partials,
+                         b->d_gctr);
+    else
+      hipLaunchKernelGGL((k_batch_step<S, C, MODE, false>), dim3(b->grid), dim3(kTileThreads), 0,
+                         b->stream, b->d_chans, b->d_tiles, b->d_ntiles, parity, b->d_partials,
+                         b->d_gctr);
   });
   return hipGetLastError();
 }

@@ -183,8 +183,9 @@ struct NodeObs {
 // the segment is shared with the neighbouring block: those pulls (ldx) go
 // through the caches, where the neighbour finds the line.  The others (ld)
 // stream past them, as the stores do, unless rows are packed (NT false,
-// the batched kernel): then a line at a row's end also holds the next
-// row's start.
+// the batched kernel in FP32 and FP64 storage): then a line at a row's end
+// also holds the next row's start.  (Binary16 storage in the batched
+// kernel streams them all the same: measured faster there.)
 // Populations live in global memory.  Loads and stores go through pointers
 // of that address space, so that the compiler emits global (not flat)
 // instructions also where the base pointer was read from memory (the batched
@@ -1000,7 +1001,7 @@ __device__ __forceinline__ void node_update(const Geom &g, const Coef<C> &k,
   const long long r0 = (long long)y * g.pitch;
   const long long rm = r0 - g.pitch;
   const long long rp = r0 + g.pitch;
-  constexpr bool NT = !in_batch(BC);
+  constexpr bool NT = !in_batch(BC) || sizeof(S) == 2;
 
   if constexpr (kXA<S, C> && MODE != MODE_MOMENTS) {
     // binary16 with FP32 arithmetic: pull the stored values undecoded.
@@ -1067,38 +1068,50 @@ __device__ __forceinline__ void node_update(const Geom &g, const Coef<C> &k,
     const C *__restrict__ Dy = ref + (long long)y * kRefRow;
     const C *__restrict__ Dm = lo ? Dy : Dy - kRefRow; // row y - 1 (used only off the lower wall)
     const C *__restrict__ Dp = hi ? Dy : Dy + kRefRow; // row y + 1 (used only off the upper wall)
+    // a plane's (uniform) base and a 32-bit element offset within it, as in
+    // the branch above (planes hold fewer than 2^31 / 19 elements of at most
+    // 8 bytes)
+    auto at = [&](int q, uint32_t i) -> const S * {
+      return reinterpret_cast<const S *>(reinterpret_cast<const char *>(src + (long long)q * P) +
+                                         (uint32_t)(i * (uint32_t)sizeof(S)));
+    };
+    const uint32_t c0 = (uint32_t)(r0 + x), cm = (uint32_t)(r0 + xm), cp = (uint32_t)(r0 + xp);
+    const uint32_t d0 = (uint32_t)(rm + x), dm = (uint32_t)(rm + xm), dp = (uint32_t)(rm + xp);
+    const uint32_t u0 = (uint32_t)(rp + x), um = (uint32_t)(rp + xm), up = (uint32_t)(rp + xp);
     C f[9], gx[5], gy[5];
-    f[0] = dec<S>(ld<S, C, NT>(src + r0 + x), Dy, 0);
-    f[1] = dec<S>(ldx<S, C>(src + 1 * P + r0 + xm), Dy, 1);
-    f[3] = dec<S>(ldx<S, C>(src + 3 * P + r0 + xp), Dy, 3);
-    gx[0] = dec<S>(ld<S, C, NT>(src + 9 * P + r0 + x), Dy, 9);
-    gx[1] = dec<S>(ldx<S, C>(src + 10 * P + r0 + xm), Dy, 10);
-    gx[3] = dec<S>(ldx<S, C>(src + 12 * P + r0 + xp), Dy, 12);
-    gy[0] = dec<S>(ld<S, C, NT>(src + 14 * P + r0 + x), Dy, 14);
-    gy[1] = dec<S>(ldx<S, C>(src + 15 * P + r0 + xm), Dy, 15);
-    gy[3] = dec<S>(ldx<S, C>(src + 17 * P + r0 + xp), Dy, 17);
+    f[0] = dec<S>(ld<S, C, NT>(at(0, c0)), Dy, 0);
+    f[1] = dec<S>(ldx<S, C>(at(1, cm)), Dy, 1);
+    f[3] = dec<S>(ldx<S, C>(at(3, cp)), Dy, 3);
+    gx[0] = dec<S>(ld<S, C, NT>(at(9, c0)), Dy, 9);
+    gx[1] = dec<S>(ldx<S, C>(at(10, cm)), Dy, 10);
+    gx[3] = dec<S>(ldx<S, C>(at(12, cp)), Dy, 12);
+    gy[0] = dec<S>(ld<S, C, NT>(at(14, c0)), Dy, 14);
+    gy[1] = dec<S>(ldx<S, C>(at(15, cm)), Dy, 15);
+    gy[3] = dec<S>(ldx<S, C>(at(17, cp)), Dy, 17);
     if (!lo) {
-      f[2] = dec<S>(ld<S, C, NT>(src + 2 * P + rm + x), Dm, 2);
-      f[5] = dec<S>(ldx<S, C>(src + 5 * P + rm + xm), Dm, 5);
-      f[6] = dec<S>(ldx<S, C>(src + 6 * P + rm + xp), Dm, 6);
-      gx[2] = dec<S>(ld<S, C, NT>(src + 11 * P + rm + x), Dm, 11);
-      gy[2] = dec<S>(ld<S, C, NT>(src + 16 * P + rm + x), Dm, 16);
+      f[2] = dec<S>(ld<S, C, NT>(at(2, d0)), Dm, 2);
+      f[5] = dec<S>(ldx<S, C>(at(5, dm)), Dm, 5);
+      f[6] = dec<S>(ldx<S, C>(at(6, dp)), Dm, 6);
+      gx[2] = dec<S>(ld<S, C, NT>(at(11, d0)), Dm, 11);
+      gy[2] = dec<S>(ld<S, C, NT>(at(16, d0)), Dm, 16);
     }
     if (!hi) {
-      f[4] = dec<S>(ld<S, C, NT>(src + 4 * P + rp + x), Dp, 4);
-      f[7] = dec<S>(ldx<S, C>(src + 7 * P + rp + xp), Dp, 7);
-      f[8] = dec<S>(ldx<S, C>(src + 8 * P + rp + xm), Dp, 8);
-      gx[4] = dec<S>(ld<S, C, NT>(src + 13 * P + rp + x), Dp, 13);
-      gy[4] = dec<S>(ld<S, C, NT>(src + 18 * P + rp + x), Dp, 18);
+      f[4] = dec<S>(ld<S, C, NT>(at(4, u0)), Dp, 4);
+      f[7] = dec<S>(ldx<S, C>(at(7, up)), Dp, 7);
+      f[8] = dec<S>(ldx<S, C>(at(8, um)), Dp, 8);
+      gx[4] = dec<S>(ld<S, C, NT>(at(13, u0)), Dp, 13);
+      gy[4] = dec<S>(ld<S, C, NT>(at(18, u0)), Dp, 18);
     }
 
     NodeObs<C> &o_ = obs;
     S out[19];
     node_finish<S, C, BC, MODE, SR>(g, k, src, ref, x, y, f, gx, gy, o_, sseed, out);
     if constexpr (MODE != MODE_MOMENTS) {
-      const long long o = r0 + x;
 #pragma unroll
-      for (int q = 0; q < 19; ++q) st<S, S>(dst + q * P + o, out[q]);
+      for (int q = 0; q < 19; ++q)
+        st<S, S>(reinterpret_cast<S *>(reinterpret_cast<char *>(dst + (long long)q * P) +
+                                       (uint32_t)(c0 * (uint32_t)sizeof(S))),
+                 out[q]);
     } else {
       (void)dst;
     }
