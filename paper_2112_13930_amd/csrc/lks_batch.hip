@@ -68,13 +68,14 @@ struct Tile {
 // most kStageRows rows (linear tiles are cut to (kStageRows - 1) nx nodes).
 constexpr int kStageRows = 64;
 
-// Grid of the persistent launch: the next power of two above the tile count,
-// at most LKS_BATCH_BLOCKS_PER_CU blocks per CU (measured: more resident
-// blocks balance uneven tiles better; power-of-two buckets keep a captured
-// graph valid while channels come and go).
-#ifndef LKS_BATCH_BLOCKS_PER_CU
-#define LKS_BATCH_BLOCKS_PER_CU 64
-#endif
+// Grid of the step launch: the next power of two above the tile count, at
+// most batch_blocks_per_cu blocks per CU (power-of-two buckets keep a
+// captured graph valid while channels come and go).  Measured on the
+// 256-channel mix: FP32 storage runs fastest with a block per tile (38.4
+// against 35.9 G node updates/s at 64 blocks per CU), binary16 with FP32
+// arithmetic, which stages row tables per tile, at 64 blocks per CU (46.5
+// against 45.4 at 32 and 45.2 at 256).
+int batch_blocks_per_cu(int precision) { return precision == LKS_FP16_STORE ? 64 : 1024; }
 
 constexpr int kTileThreads = 256;
 // Steps in the long captured graph (even: a graph starts and ends at parity 0).
@@ -754,7 +755,7 @@ int lks_mhd_batch_create(int32_t precision, int32_t max_channels, int64_t max_no
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, b->device) == hipSuccess && prop.multiProcessorCount > 0)
     cus = prop.multiProcessorCount;
-  b->grid_cap = cus * LKS_BATCH_BLOCKS_PER_CU; // persistent blocks of 256 threads
+  b->grid_cap = cus * batch_blocks_per_cu(precision); // blocks of 256 threads
   b->grid = 1;
   const int rc = with_device(b, [&]() -> int {
     const uint32_t z[2] = {0u, 0u};
