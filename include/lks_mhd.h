@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define LKS_MHD_ABI_VERSION 7
+#define LKS_MHD_ABI_VERSION 8
 
 typedef struct lks_mhd lks_mhd_t;             /* one channel, library-owned */
 typedef struct lks_mhd_batch lks_mhd_batch_t; /* many channels, library-owned */
@@ -364,6 +364,21 @@ int lks_mhd_advance_noalloc(const lks_mhd_params *p, double *dev_pops, int64_t s
 /* Algorithmic HBM bytes of one step per node (19 populations read and
  * written) for a precision: 304, 152 or 76. */
 int lks_mhd_bytes_per_node(int32_t precision);
+
+/*
+ * The stochastic rounding binary32 -> binary16 that the binary16 storage
+ * modes apply to every stored value (the paper fixes no storage precision;
+ * this is the library's own), exposed so that its bits can be checked:
+ * out[i] = the binary16 bits of v[i] rounded with the random word r[i].
+ * The top 13 bits of r[i] are added below binary16's last place (in the
+ * subnormal range, below 2^-24) to the magnitude of v[i], which is then
+ * truncated there; a carry past 65504 gives infinity.  v, r and out are
+ * device arrays of n elements (0 <= n < 2^31); LKS_EINVAL for a negative or
+ * too large n or a null array with n > 0, LKS_EDEVICE if the launch fails.
+ * Asynchronous on hip_stream.
+ */
+int lks_round_binary16(const float *v, const uint32_t *r, uint16_t *out, int64_t n,
+                       void *hip_stream);
 
 /* ------------------------------------------------------------------------ */
 /* Batched channels: many independent channels of any size in one launch.   */

@@ -97,6 +97,7 @@ SIGNATURES = {
     "lks_mhd_set_rebase": (_c.c_int, [_vp, _c.c_int64]),
     "lks_mhd_bytes_per_node": (_c.c_int, [_c.c_int32]),
     "lks_mhd_advance_noalloc": (_c.c_int, [_P, _vp, _c.c_int64, _c.c_int64, _vp]),
+    "lks_round_binary16": (_c.c_int, [_vp, _vp, _vp, _c.c_int64, _vp]),
     "lks_mhd_batch_overhead_bytes": (_c.c_size_t, [_c.c_int32, _c.c_int64]),
     "lks_mhd_batch_create": (_c.c_int, [_c.c_int32, _c.c_int32, _c.c_int64, _vp, _c.c_size_t, _vp,
                                         ctypes.POINTER(_vp)]),

@@ -212,10 +212,10 @@ __device__ __forceinline__ void st(S *__restrict__ p, C v) {
 // once the flow is steady, and slow modes integrate it; rounding to one of
 // the two neighbouring representable values with probabilities given by the
 // distances makes the residual change from step to step (lks_sr.hpp).
-template <typename S, typename C, bool SR, bool SEL = false>
+template <typename S, typename C, bool SR>
 __device__ __forceinline__ S to_store(C v, uint32_t r) {
   if constexpr (SR) {
-    return round_sr<S, C, SEL>(v, r);
+    return round_sr<S, C>(v, r);
   } else {
     (void)r;
     return static_cast<S>(v);
@@ -617,7 +617,7 @@ __device__ __forceinline__ void node_finish(const Geom &g, const Coef<C> &k,
   auto put = [&](C v, int plane) -> S {
     (void)plane;
     if constexpr (kRowRef<S>) v = (v - Dy[plane]) * C(kStoreUp16);
-    return to_store<S, C, SR, in_batch(BC)>(v, SR ? rng.next() : 0u);
+    return to_store<S, C, SR>(v, SR ? rng.next() : 0u);
   };
   const C om = k.omega_f, ka = k.kappa_f;
   const C usq15 = C(1.5) * (ux * ux + uy * uy);
@@ -838,31 +838,21 @@ __device__ __forceinline__ void xtab_row(const Geom &g, const Coef<double> &k, X
   t.K[r + 19] = 0.0;
 }
 
-// Two values rounded stochastically to binary16 (the random words of
-// lks::Rng): sr16_pre, then the hardware's round-toward-zero conversion of
-// the pair.
-__device__ __forceinline__ void sr_pair16(float a, float b, uint32_t ra, uint32_t rb,
-                                          _Float16 &oa, _Float16 &ob) {
-  typedef __fp16 hp2 __attribute__((ext_vector_type(2)));
-  const hp2 h = __builtin_amdgcn_cvt_pkrtz(sr16_pre(a, ra), sr16_pre(b, rb));
-  const uint32_t u = __builtin_bit_cast(uint32_t, h);
-  oa = __builtin_bit_cast(_Float16, (uint16_t)(u & 0xFFFFu));
-  ob = __builtin_bit_cast(_Float16, (uint16_t)(u >> 16));
-}
-
 // Collide one node of a binary16 state in FP32 with exact accumulation.
 // raw[] holds the 19 pulled stored values (unused where a wall closes the
 // population); the new stored values are returned in out (not for
 // MODE_MOMENTS, which this path does not serve).
 // Vy and Ky are row y's entries of t.V and t.K, or a copy of them (the
 // batched kernel stages the rows of a tile in LDS).
-template <typename S, int BC, int MODE, bool SR>
+// The new values before their rounding to binary16 go to emit(q, z_q), in
+// plane order (EmitX rounds them).
+template <typename S, int BC, int MODE, typename Emit>
 __device__ __forceinline__ void node_finish_x(const Geom &g, const Coef<float> &k,
                                               const S *__restrict__ src, XTabs t,
                                               const float *__restrict__ Vy,
                                               const double *__restrict__ Ky, int x, int y,
                                               const S (&raw)[19], NodeObs<float> &obs,
-                                              uint32_t sseed, S (&out)[19]) {
+                                              Emit &&emit) {
   static_assert(MODE != MODE_MOMENTS, "observables decode in FP64");
   const bool lo = (y == 0), hi = (y == g.ny - 1);
   const float *__restrict__ Dy = t.D + (long long)y * kRefRow;
@@ -940,7 +930,7 @@ __device__ __forceinline__ void node_finish_x(const Geom &g, const Coef<float> &
   S unused[19];
   // (k's relaxation coefficients carry the factor 2^12 of the stored units,
   // so the increments come back in stored units)
-  node_finish<S, float, BC, MODE, SR, true>(g, k, src, t.D, x, y, f, gx, gy, obs, sseed, unused);
+  node_finish<S, float, BC, MODE, false, true>(g, k, src, t.D, x, y, f, gx, gy, obs, 0u, unused);
   // conserved moments of the increments, in FP64: mass and B are unchanged
   // by the collision and momentum gains the force
   double d[19];
@@ -965,22 +955,31 @@ __device__ __forceinline__ void node_finish_x(const Geom &g, const Coef<float> &
   // stored values, exactly in FP64; that difference and then its sum with e
   // round in binary32 at the stored values' own magnitude, before the
   // stochastic rounding to binary16, two at a time
-  auto znew = [&](int q) -> float { return (float)(d[q] + Ky[q]) + e[q]; };
-  if constexpr (SR) {
-    Rng rng(node_seed(sseed, (uint32_t)(y * g.nx + x)));
+  // Planes pulled along the row (no y component: 0, 1, 3 of f, 0, 1, 3 of
+  // g_x and g_y) have K = 0 in every scheme: their source row is the node's
+  // own and no wall closure sets them.
 #pragma unroll
-    for (int q = 0; q < 18; q += 2) {
-      const uint32_t ra = rng.next(), rb = rng.next();
-      sr_pair16(znew(q), znew(q + 1), ra, rb, out[q], out[q + 1]);
-    }
-    S spare;
-    sr_pair16(znew(18), 0.0f, rng.next(), 0x8000u, out[18], spare);
-    (void)spare;
-  } else {
-#pragma unroll
-    for (int q = 0; q < 19; ++q) out[q] = (S)znew(q);
+  for (int q = 0; q < 19; ++q) {
+    const bool along_row = q == 0 || q == 1 || q == 3 || q == 9 || q == 10 || q == 12 ||
+                           q == 14 || q == 15 || q == 17;
+    emit(q, (along_row ? (float)d[q] : (float)(d[q] + Ky[q])) + e[q]);
   }
 }
+
+// The stochastic rounding of node_finish_x's values to binary16 (a plain
+// conversion without SR), in plane order: planes 2j and 2j + 1 take the top
+// 13 bits of the node stream's j-th xorshift word and of that word shifted
+// left by 16 -- those of Rng::next()'s words 2j and 2j + 1.  word(q) must be
+// called for q = 0, 1, ..., 18 in turn.
+template <bool SR>
+struct EmitWords {
+  uint32_t st, w = 0;
+  __device__ explicit EmitWords(uint32_t seed) : st(seed | 1u) {}
+  __device__ uint32_t word(int q) {
+    if (!(q & 1)) w = xorshift32(st);
+    return (q & 1) ? w << 16 : w;
+  }
+};
 
 // STAGED, xV, xK: for binary16 storage with FP32 arithmetic, row y's
 // pre-collision tables come from the caller's copy xV, xK (else from ref).
@@ -1054,8 +1053,12 @@ __device__ __forceinline__ void node_update(const Geom &g, const Coef<C> &k,
     NodeObs<float> &o_ = obs;
     const XTabs t = xtabs_of(const_cast<C *>(ref), g.ny);
     const long long row = (long long)y * kRefRow;
-    node_finish_x<S, BC, MODE, SR>(g, k, src, t, STAGED ? xV : t.V + row,
-                                   STAGED ? xK : t.K + row, x, y, raw, o_, sseed, out);
+    EmitWords<SR> ew(SR ? node_seed(sseed, (uint32_t)(y * g.nx + x)) : 0u);
+    node_finish_x<S, BC, MODE>(g, k, src, t, STAGED ? xV : t.V + row, STAGED ? xK : t.K + row, x,
+                               y, raw, o_, [&](int q, float zq) {
+                                 if constexpr (SR) out[q] = sr_f16(zq, ew.word(q));
+                                 else out[q] = (S)zq;
+                               });
 #pragma unroll
     for (int q = 0; q < 19; ++q) {
       char *plane = reinterpret_cast<char *>(dst + (long long)q * P);

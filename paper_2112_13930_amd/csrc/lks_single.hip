@@ -144,32 +144,39 @@ __global__ __launch_bounds__(256) void k_step_vec(Geom g, Coef<C> k, const S *__
   const long long r0 = (long long)y * g.pitch, rm = r0 - g.pitch, rp = r0 + g.pitch;
   const int xm0 = (x0 == 0) ? nx - 1 : x0 - 1;     // x - 1 of the first node
   const int xpe = (x0 + VX == nx) ? 0 : x0 + VX;    // x + 1 of the last node
-  auto vld = [&](long long off) { return *reinterpret_cast<const V *>(src + off); };
-  const V a0 = vld(r0 + x0), a1 = vld(P + r0 + x0), a3 = vld(3 * P + r0 + x0);
-  const S e1 = src[P + r0 + xm0], e3 = src[3 * P + r0 + xpe];
-  const V b0 = vld(9 * P + r0 + x0), b1 = vld(10 * P + r0 + x0), b3 = vld(12 * P + r0 + x0);
-  const S eb1 = src[10 * P + r0 + xm0], eb3 = src[12 * P + r0 + xpe];
-  const V c0 = vld(14 * P + r0 + x0), c1 = vld(15 * P + r0 + x0), c3 = vld(17 * P + r0 + x0);
-  const S ec1 = src[15 * P + r0 + xm0], ec3 = src[17 * P + r0 + xpe];
+  // a plane's base (uniform) plus a 32-bit byte offset within the plane
+  // (planes hold fewer than 2^31 / 19 elements of at most 8 bytes), so that
+  // each access takes a scalar base and one vector offset
+  auto at = [&](int q, long long e) -> const char * {
+    return reinterpret_cast<const char *>(src + (long long)q * P) + (uint32_t)(e * (long long)sizeof(S));
+  };
+  auto vld = [&](int q, long long e) { return *(gptr<const V>)at(q, e); };
+  auto sld = [&](int q, long long e) { return *(gptr<const S>)at(q, e); };
+  const V a0 = vld(0, r0 + x0), a1 = vld(1, r0 + x0), a3 = vld(3, r0 + x0);
+  const S e1 = sld(1, r0 + xm0), e3 = sld(3, r0 + xpe);
+  const V b0 = vld(9, r0 + x0), b1 = vld(10, r0 + x0), b3 = vld(12, r0 + x0);
+  const S eb1 = sld(10, r0 + xm0), eb3 = sld(12, r0 + xpe);
+  const V c0 = vld(14, r0 + x0), c1 = vld(15, r0 + x0), c3 = vld(17, r0 + x0);
+  const S ec1 = sld(15, r0 + xm0), ec3 = sld(17, r0 + xpe);
   V a2{}, a5{}, a6{}, b2{}, c2{}, a4{}, a7{}, a8{}, b4{}, c4{};
   S e5{}, e6{}, e7{}, e8{};
   if (!lo) {
-    a2 = vld(2 * P + rm + x0);
-    a5 = vld(5 * P + rm + x0);
-    a6 = vld(6 * P + rm + x0);
-    e5 = src[5 * P + rm + xm0];
-    e6 = src[6 * P + rm + xpe];
-    b2 = vld(11 * P + rm + x0);
-    c2 = vld(16 * P + rm + x0);
+    a2 = vld(2, rm + x0);
+    a5 = vld(5, rm + x0);
+    a6 = vld(6, rm + x0);
+    e5 = sld(5, rm + xm0);
+    e6 = sld(6, rm + xpe);
+    b2 = vld(11, rm + x0);
+    c2 = vld(16, rm + x0);
   }
   if (!hi) {
-    a4 = vld(4 * P + rp + x0);
-    a7 = vld(7 * P + rp + x0);
-    a8 = vld(8 * P + rp + x0);
-    e7 = src[7 * P + rp + xpe];
-    e8 = src[8 * P + rp + xm0];
-    b4 = vld(13 * P + rp + x0);
-    c4 = vld(18 * P + rp + x0);
+    a4 = vld(4, rp + x0);
+    a7 = vld(7, rp + x0);
+    a8 = vld(8, rp + x0);
+    e7 = sld(7, rp + xpe);
+    e8 = sld(8, rp + xm0);
+    b4 = vld(13, rp + x0);
+    c4 = vld(18, rp + x0);
   }
   const C *__restrict__ Dy = ref + (long long)y * kRefRow; // row references (binary16 only)
   const C *__restrict__ Dm = lo ? Dy : Dy - kRefRow;
@@ -201,13 +208,23 @@ __global__ __launch_bounds__(256) void k_step_vec(Geom g, Coef<C> k, const S *__
                          v == VX - 1 ? ec3 : c3[v < VX - 1 ? v + 1 : 0],
                          c4[v]};
       NodeObs<C> o{};
-      S out[19];
       const XTabs t = xtabs_of(const_cast<C *>(ref), g.ny);
       const long long row = (long long)y * kRefRow;
-      node_finish_x<S, BC, MODE_STEP, SR>(g, k, src, t, t.V + row, t.K + row, x0 + v, y, raw, o,
-                                          sseed, out);
-#pragma unroll
-      for (int q = 0; q < 19; ++q) outv[q][v] = out[q];
+      // the node stream's words (EmitWords), each rounding written straight
+      // into node v's half of the plane's vector
+      EmitWords<SR> ew(SR ? node_seed(sseed, (uint32_t)(y * nx + x0 + v)) : 0u);
+      const int v0 = v & ~1; // (the loop is unrolled: v is a constant)
+      node_finish_x<S, BC, MODE_STEP>(g, k, src, t, t.V + row, t.K + row, x0 + v, y, raw, o,
+                                      [&](int q, float zq) {
+                                        if constexpr (SR) {
+                                          S lo = outv[q][v0], hi = outv[q][v0 + 1];
+                                          if (v & 1) sr_f16_half<true>(lo, hi, zq, ew.word(q));
+                                          else sr_f16_half<false>(lo, hi, zq, ew.word(q));
+                                          outv[q][v0] = lo, outv[q][v0 + 1] = hi;
+                                        } else {
+                                          outv[q][v] = (S)zq;
+                                        }
+                                      });
     } else {
     C f[9], gx[5], gy[5];
     f[0] = dec<S>((C)a0[v], Dy, 0);
@@ -238,7 +255,9 @@ __global__ __launch_bounds__(256) void k_step_vec(Geom g, Coef<C> k, const S *__
   }
 #pragma unroll
   for (int q = 0; q < 19; ++q)
-    __builtin_nontemporal_store(outv[q], reinterpret_cast<V *>(dst + q * P + r0 + x0));
+    __builtin_nontemporal_store(
+        outv[q], (gptr<V>)(reinterpret_cast<char *>(dst + (long long)q * P) +
+                           (uint32_t)((r0 + x0) * (long long)sizeof(S))));
 }
 
 // Step counters of a channel set on the device (no host copy).
@@ -568,6 +587,14 @@ int scratch_address(void **out) {
 }
 
 } // namespace
+
+// The binary16 storage rounding, element by element (lks_round_binary16).
+__global__ __launch_bounds__(256) void k_round_binary16(const float *__restrict__ v,
+                                                        const uint32_t *__restrict__ r,
+                                                        uint16_t *__restrict__ out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) out[i] = __builtin_bit_cast(uint16_t, sr_f16(v[i], r[i]));
+}
 
 extern "C" {
 
@@ -935,6 +962,20 @@ int lks_mhd_advance_noalloc(const lks_mhd_params *p, double *dev_pops, int64_t s
   rc = lks_mhd_save_state(&h, dev_pops);
   drop_graphs(&h);
   return rc;
+}
+
+int lks_round_binary16(const float *v, const uint32_t *r, uint16_t *out, int64_t n,
+                       void *hip_stream) {
+  clear_error();
+  if (n < 0 || n > INT32_MAX || (n > 0 && (!v || !r || !out))) {
+    set_error("invalid arrays or element count");
+    return LKS_EINVAL;
+  }
+  if (n == 0) return LKS_OK;
+  hipLaunchKernelGGL(k_round_binary16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                     static_cast<hipStream_t>(hip_stream), v, r, out, n);
+  LKS_HIP_CHECK(hipGetLastError());
+  return LKS_OK;
 }
 
 int lks_mhd_set_rebase(lks_mhd_t *h, int64_t every) {

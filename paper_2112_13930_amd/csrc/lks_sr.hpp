@@ -3,13 +3,17 @@
 //
 // Rounding: the result is one of the two neighbours of v in the target
 // format, the farther one with probability |v - nearest lower-magnitude
-// neighbour| / spacing, resolved to the random word's resolution (2^-32 of
-// the spacing for a full word; the kernels pass 16 random bits, 2^-16).  It is computed by
-// adding uniform random bits below the target's last place to the magnitude
-// bits of v and truncating there (a carry out of the kept bits rounds up,
-// across a binade too); binary64 reaches binary16 through the nearest
-// binary32.  Values beyond the target's range become infinite (and are
-// reported as non-finite by the residual check).
+// neighbour| / spacing, resolved to the random bits used: 29 below binary32's
+// last place (binary64 -> binary32), 13 below binary16's (binary32 ->
+// binary16, also in binary16's subnormal range, whose spacing is 2^-24).
+// It is computed by adding uniform random bits below the target's last place
+// to the magnitude of v and truncating there (a carry out of the kept bits
+// rounds up, across a binade too); binary64 reaches binary16 through the
+// nearest binary32.  Values beyond the target's range become infinite (and
+// are reported as non-finite by the residual check).  On the GPU the
+// binary32 -> binary16 rounding is the hardware's stochastic conversion
+// (v_cvt_sr_f16_f32), which takes the top 13 bits of its random word; the
+// host form below gives the same bits.
 //
 // Random bits: one hashed seed per node and step (counter-based, so a run is
 // reproducible bit for bit and independent of launch shape or batch mix),
@@ -37,6 +41,15 @@ LKS_HD inline uint32_t mix32(uint32_t x) {
   return x;
 }
 
+// One step of Marsaglia's xorshift32 (shifts 13, 17, 5) on a nonzero state;
+// returns the new state.
+LKS_HD inline uint32_t xorshift32(uint32_t &s) {
+  s ^= s << 13;
+  s ^= s >> 17;
+  s ^= s << 5;
+  return s;
+}
+
 // Per-node stream of random words for stochastic rounding.  next() gives a
 // 32-bit word whose top 16 bits are random and whose bit 15 is set (the
 // middle of the 2^-16 bin the 16 bits select); two consecutive calls share
@@ -46,15 +59,16 @@ struct Rng {
   uint32_t s, w = 0;
   bool half = false;
   LKS_HD explicit Rng(uint32_t seed) : s(seed | 1u) {} // xorshift needs s != 0
+  // One xorshift32 step: the word two calls of next() are cut from (their top
+  // 13 bits are those of the word and of the word shifted left by 16, which
+  // is all the binary16 rounding takes).  Not to be mixed with next().
+  LKS_HD uint32_t draw() { return xorshift32(s); }
   LKS_HD uint32_t next() {
     if (half) {
       half = false;
       return (w << 16) | 0x8000u;
     }
-    s ^= s << 13;
-    s ^= s >> 17;
-    s ^= s << 5;
-    w = s;
+    w = xorshift32(s);
     half = true;
     return (w & 0xFFFF0000u) | 0x8000u;
   }
@@ -82,74 +96,66 @@ LKS_HD inline float sr_f32(double v, uint32_t r) {
   return (float)dbl(b); // exact: 24 significant bits left
 }
 
-// binary32 -> binary16.  Below 2^-24 the result is 0 or 2^-24 (binary16's
-// smallest subnormal) with probability |v| / 2^-24; above, random bits are
-// added below binary16's last place and truncated.
+// binary32 -> binary16 with the top 13 bits of r.  From binary16's normal
+// range up (|v| >= 2^-14, and zeros and non-finite values) the 13 bits are
+// added below binary16's last place, which lies 13 bits above binary32's,
+// and truncated there; a carry past 65504 gives infinity.  Below, binary16's
+// spacing is 2^-24: the result is sign(v) trunc(|v| 2^24 + r13 2^-13) 2^-24,
+// computed here in units of 2^-37 as trunc((trunc(|v| 2^37) + r13) 2^-13)
+// (equal, as r13 is an integer).
 LKS_HD inline _Float16 sr_f16(float v, uint32_t r) {
-  const uint32_t b = bits32(v);
-  // |v| >= 2^-14 (binary16's normal range and above): binary16's last place
-  // is 13 bits above binary32's; adding to the magnitude bits of b leaves its
-  // sign alone.  Zeros come out unchanged the same way.
-  const uint32_t m = b & 0x7FFFFFFFu;
-  if (m >= 0x38800000u || m == 0u) return (_Float16)flt((b + (r >> 19)) & ~0x1FFFu);
-  const uint32_t sign = b & 0x80000000u;
-  const uint32_t mag = b ^ sign;
-  const int e = (int)(mag >> 23) - 127;
-  if (e < -24) {
-    const float p = (float)(r >> 8) * 0x1p-48f; // uniform in [0, 2^-24)
-    return (_Float16)flt(sign | (p < flt(mag) ? 0x33800000u : 0u));
-  }
-  const int k = e >= -14 ? 13 : -1 - e;
-  const uint32_t t = (mag + (r >> (32 - k))) & ~((1u << k) - 1u);
-  return (_Float16)flt(sign | t); // exact
-}
-
-// The same result with both cases computed and one selected (no branch).
-// The branch suits kernels of one scheme, whose wavefronts mostly agree on
-// it and which lose occupancy to the registers of the select form; the
-// select suits the batched kernel, whose small channels mix both cases in a
-// wavefront and which inlines every scheme's stores.
-LKS_HD inline _Float16 sr_f16_sel(float v, uint32_t r) {
-  const uint32_t b = bits32(v);
-  const uint32_t sign = b & 0x80000000u;
-  const uint32_t mag = b ^ sign;
-  const int e = (int)(mag >> 23) - 127;
-  const float p = (float)(r >> 8) * 0x1p-48f;
-  const uint32_t tiny = p < flt(mag) ? 0x33800000u : 0u;
-  const int k = e >= -14 ? 13 : (e >= -24 ? -1 - e : 23);
-  const uint32_t t = (mag + (r >> (32 - k))) & ~((1u << k) - 1u);
-  return (_Float16)flt(sign | (e < -24 ? tiny : t));
-}
-
-// binary32 -> binary16 for a conversion that truncates (round toward zero):
-// zeros and binary16's normal range get the random bits of sr_f16's fast
-// path added below binary16's last place and leave the masking to the
-// truncation; the rest is sr_f16's exact binary16 result, which truncation
-// keeps.  Truncating the returned value gives sr_f16's bits, except that
-// magnitudes beyond binary16's range saturate at 65504 instead of becoming
-// infinite (and infinities may come back as NaN).  The kernels convert two
-// such values at once.
-LKS_HD inline float sr16_pre(float v, uint32_t r) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+  return __builtin_amdgcn_cvt_sr_f16_f32(h2{}, v, r, false)[0];
+#else
   const uint32_t b = bits32(v), m = b & 0x7FFFFFFFu;
-  if (m >= 0x38800000u || m == 0u) return flt(b + (r >> 19));
-  return (float)sr_f16(v, r);
+  if (m >= 0x38800000u || m == 0u) return (_Float16)flt((b + (r >> 19)) & ~0x1FFFu);
+  const uint32_t e8 = m >> 23; // biased exponent; 0 for binary32 subnormals
+  const uint32_t sig = e8 ? (m & 0x7FFFFFu) | 0x800000u : m;
+  // |v| = sig 2^(E - 23), E = e8 - 127 (or -126): in units of 2^-37 that is
+  // sig 2^(e8 - 113), a right shift of at least 1 here
+  const int rs = 113 - (int)(e8 ? e8 : 1);
+  const uint32_t u = rs < 32 ? sig >> rs : 0u;
+  const uint32_t t = (u + (r >> 19)) >> 13; // result in units of 2^-24, <= 2^10
+  const float mag = (float)t * 0x1p-24f;   // exact
+  return (_Float16)flt((b & 0x80000000u) | bits32(mag));
+#endif
 }
 
-// Round toward zero to binary16 (host model of the device conversion).
-LKS_HD inline _Float16 f16_rtz(float t) {
-  const uint32_t b = bits32(t);
-  const uint32_t mag = b & 0x7FFFFFFFu, sign = b & 0x80000000u;
-  if (mag >= 0x7F800000u) return (_Float16)t;                           // inf, NaN
-  if (mag >= 0x477FE000u) return (_Float16)flt(sign | 0x477FE000u);      // 65504
-  if (mag >= 0x38800000u) return (_Float16)flt(sign | (mag & ~0x1FFFu)); // exact
-  const float q = __builtin_truncf(flt(mag) * 0x1p24f) * 0x1p-24f;     // subnormal grid
-  return (_Float16)flt(sign | bits32(q));
+// v rounded stochastically to binary16 (sr_f16) into the low (HIGH false)
+// or high half of the pair (lo, hi); the other half is kept.
+template <bool HIGH>
+LKS_HD inline void sr_f16_half(_Float16 &lo, _Float16 &hi, float v, uint32_t r) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+  h2 p = {lo, hi};
+  p = __builtin_amdgcn_cvt_sr_f16_f32(p, v, r, HIGH);
+  lo = p[0];
+  hi = p[1];
+#else
+  (HIGH ? hi : lo) = sr_f16(v, r);
+#endif
+}
+
+// Two values rounded stochastically to binary16 (sr_f16 each), returned as
+// the low and high halves of one register's pair.
+LKS_HD inline void sr_f16_pair(float a, float b, uint32_t ra, uint32_t rb, _Float16 &oa,
+                               _Float16 &ob) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+  h2 p = __builtin_amdgcn_cvt_sr_f16_f32(h2{}, a, ra, false);
+  p = __builtin_amdgcn_cvt_sr_f16_f32(p, b, rb, true);
+  oa = p[0];
+  ob = p[1];
+#else
+  oa = sr_f16(a, ra);
+  ob = sr_f16(b, rb);
+#endif
 }
 
 // Stochastic rounding of v (compute type C) to storage type S; identity for
-// equal types.  SEL picks the select form of the binary16 rounding (same
-// result).
-template <typename S, typename C, bool SEL = false>
+// equal types.
+template <typename S, typename C>
 LKS_HD inline S round_sr(C v, uint32_t r) {
   if constexpr (sizeof(S) == sizeof(C)) {
     (void)r;
@@ -157,10 +163,9 @@ LKS_HD inline S round_sr(C v, uint32_t r) {
   } else {
     if constexpr (sizeof(S) == 4) return sr_f32(v, r);
     // binary64 goes to the nearest binary32 first: that moves v by at most
-    // 2^-25 |v|, 2^-14 of a binary16 spacing, and costs a few integer
-    // instructions where rounding at v's binary16 spacing in FP64 took ten
-    // FP64 ones (the binary16 step is arithmetic-bound)
-    else if constexpr (SEL) return sr_f16_sel((float)v, r);
+    // 2^-25 |v|, 2^-14 of a binary16 spacing, and leaves the rest to one
+    // hardware conversion where rounding at v's binary16 spacing in FP64 took
+    // ten FP64 instructions (the binary16 step is arithmetic-bound)
     else return sr_f16((float)v, r);
   }
 }

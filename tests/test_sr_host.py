@@ -5,7 +5,11 @@ are host-compilable; tests/native/sr_check.cpp sweeps the random word over a
 stratified grid for values across many binades (binary16 subnormals, binade
 edges, exact values, both signs) and requires neighbours only, exact values
 unchanged, and the exact rounding-up probability to within the sweep's
-resolution.
+resolution (2^-13 for binary16, which takes 13 random bits; in binary16's
+subnormal range the count of round-ups over all 2^13 words is checked
+exactly).  The device form of the binary16 rounding (the hardware's
+stochastic conversion) is checked against the same definition on the GPU
+(tests/test_gpu_rounding.py).
 """
 import os
 import shutil
