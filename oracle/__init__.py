@@ -45,6 +45,15 @@ def build(force: bool = False) -> str:
     return LIB
 
 
+DISC, BORE, BELOW, ABOVE = 1, 2, 3, 4  # solid bodies (curved walls)
+
+
+class _Solid(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("pad_", ctypes.c_int32), ("cx", ctypes.c_double),
+                ("cy", ctypes.c_double), ("r", ctypes.c_double), ("omega", ctypes.c_double),
+                ("u", ctypes.c_double)]
+
+
 class _Params(ctypes.Structure):
     _fields_ = [
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("bc", ctypes.c_int32),
@@ -60,6 +69,8 @@ class _Params(ctypes.Structure):
         ("q_lo", ctypes.c_double), ("q_hi", ctypes.c_double),
         ("s_fe", ctypes.c_double), ("s_feps", ctypes.c_double), ("s_fq", ctypes.c_double),
         ("s_me", ctypes.c_double), ("s_md", ctypes.c_double),
+        ("nsolid", ctypes.c_int32), ("pad2_", ctypes.c_int32),
+        ("solid", _Solid * 4),
     ]
 
 
@@ -86,6 +97,10 @@ def lib():
         L.orc_gather.argtypes = [pp, dp, ctypes.c_int, ctypes.c_int, dp]
         L.orc_collide.argtypes = [pp, dp, dp, dp] + [ctypes.c_double] * 7 + [dp]
         L.orc_xwall_closure.argtypes = [pp, ctypes.c_int, dp, dp, dp, dp]
+        L.orc_is_solid.argtypes = [pp, ctypes.c_int, ctypes.c_int]
+        L.orc_is_solid.restype = ctypes.c_int
+        L.orc_link_cut.argtypes = [pp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp, dp]
+        L.orc_link_cut.restype = ctypes.c_int
         for fn in ("orc_feq", "orc_geq", "orc_source", "orc_local_solve",
                    "orc_link_closure", "orc_moment_closure", "orc_init",
                    "orc_step", "orc_run", "orc_observe", "orc_gather", "orc_collide",
@@ -143,6 +158,11 @@ class Params:
     s_fq: float = float("nan")
     s_me: float = float("nan")
     s_md: float = float("nan")
+    # solid bodies (curved walls): (kind, cx, cy, r, omega, u) with kind DISC
+    # (solid inside the circle), BORE (solid outside), BELOW (y < cy) or
+    # ABOVE (y > cy); omega the circle's surface angular velocity, u a
+    # half-plane's velocity along x
+    solids: tuple = ()
     extra: dict = field(default_factory=dict)
 
     def half_width(self) -> float:
@@ -162,11 +182,20 @@ class Params:
             assert self.bc == LINK and self.nx >= 2, "enclosure walls need link-based closures"
         if (self.q_lo, self.q_hi) != (0.5, 0.5):
             assert self.bc == LINK and 0 < self.q_lo <= 1 and 0 < self.q_hi <= 1
+        assert len(self.solids) <= 4, "at most four solid bodies"
+        if self.solids:
+            assert not self.x_walls and (self.q_lo, self.q_hi) == (0.5, 0.5), \
+                "solid bodies need an x-periodic channel with half-way Hartmann walls"
+        bodies = (_Solid * 4)()
+        for k, b in enumerate(self.solids):
+            kind, cx, cy, r, omega, u = b
+            bodies[k] = _Solid(int(kind), 0, cx, cy, r, omega, u)
         return _Params(self.nx, self.ny, self.bc, self.collision, self.tau_f, self.tau_m,
                        self.b0, self.fx, self.fy, self.c_lo, self.c_hi,
                        self.u_lo, self.u_hi, self.half_width(), self.tau_fm, self.tau_mp,
                        int(self.x_walls), 0, self.cx_lo, self.cx_hi, self.q_lo, self.q_hi,
-                       self.s_fe, self.s_feps, self.s_fq, self.s_me, self.s_md)
+                       self.s_fe, self.s_feps, self.s_fq, self.s_me, self.s_md,
+                       len(self.solids), 0, bodies)
 
 
 def init_state(p: Params) -> np.ndarray:
@@ -271,3 +300,22 @@ def xwall_closure(p: Params, wall: int, own, f, gx, gy):
                             _dp(np.ascontiguousarray(own, dtype=np.float64)), _dp(f), _dp(gx),
                             _dp(gy))
     return f, gx, gy
+
+
+def solid_mask(p: Params) -> np.ndarray:
+    """(ny, nx) bool array of the solid nodes."""
+    cp = p.c_struct()
+    L = lib()
+    return np.array([[bool(L.orc_is_solid(ctypes.byref(cp), x, y)) for x in range(p.nx)]
+                     for y in range(p.ny)])
+
+
+def link_cut(p: Params, x: int, y: int, a: int):
+    """(q, u_wall_x, u_wall_y) of the link of fluid node (x, y) towards its
+    upstream node (x, y) - e_a (D2Q9 numbering) if a body contains that
+    node, else None."""
+    cp = p.c_struct()
+    q, ux, uy = (np.zeros(1) for _ in range(3))
+    if lib().orc_link_cut(ctypes.byref(cp), x, y, a, _dp(q), _dp(ux), _dp(uy)):
+        return float(q[0]), float(ux[0]), float(uy[0])
+    return None

@@ -80,7 +80,21 @@ typedef struct {
                             wall row, in (0, 1]; 1/2 is the paper's half-way wall */
   double s_fe, s_feps, s_fq; /* MRT rates of f's e, epsilon and q moments */
   double s_me, s_md;         /* MRT rates of g's epsilon and d moments */
+  int32_t nsolid, pad2_;     /* solid bodies (curved walls), at most ORC_MAX_SOLIDS */
+  struct orc_solid {
+    int32_t kind, pad_;      /* ORC_SOLID_* */
+    double cx, cy, r;        /* circle: centre and radius; half-plane: cy = its edge y0 */
+    double omega;            /* circle: angular velocity of its surface (counterclockwise) */
+    double u;                /* half-plane: its velocity along x */
+  } solid[4];
 } orc_params;
+
+/* Solid bodies, in lattice units with node (i, j) at the point (i, j); x is
+ * periodic, so a circle also covers its images one period away.  A node is
+ * solid if it lies strictly inside a body.  DISC: solid inside the circle;
+ * BORE: solid outside it; BELOW / ABOVE: solid where y < cy / y > cy. */
+enum { ORC_SOLID_DISC = 1, ORC_SOLID_BORE = 2, ORC_SOLID_BELOW = 3, ORC_SOLID_ABOVE = 4 };
+#define ORC_MAX_SOLIDS 4
 
 /* ---------------------------------------------------------------------- */
 /* Equilibria and source (Secs. IV and V)                                 */
@@ -425,20 +439,184 @@ void orc_moment_closure(const orc_params *p, int wall, double *f, double *gx,
 }
 
 /* ---------------------------------------------------------------------- */
-/* One node: stream, close, moments, solve; optionally collide            */
+/* Curved walls: link-based closures on the surfaces of solid bodies       */
 /* ---------------------------------------------------------------------- */
-
+/*
+ * The paper closes straight Hartmann walls only and names curved walls,
+ * walls that cut the links at distances other than one half, as future work
+ * (Sec. IX).  This is the reading taken here.  A fluid node's population f_a
+ * whose upstream node x - e_a is solid is closed on that link, with q the
+ * fraction of the link from the node to the surface (0 < q <= 1):
+ *   f: linear interpolated bounce-back (Bouzidi, Firdaouss and Lallemand
+ *      2001) with the moving-wall term 2 w_a e_a.u_w / cs2 at the crossing
+ *      point (scaled by 1/(2q) on the far branch, as for the straight walls
+ *      at a cut distance above):
+ *        q <  1/2: f_a = 2q f~_abar + (1-2q) f~_abar(x + e_a) + m_a
+ *        q >= 1/2: f_a = f~_abar / (2q) + (1 - 1/(2q)) f~_a + m_a / (2q)
+ *      and half-way bounce-back f~_abar + m_a where q < 1/2 but x + e_a is
+ *      solid too.  Unlike bounce-back (q = 1/2) the interpolation does not
+ *      conserve mass exactly; the straight cut walls above return the mass
+ *      defect to the closed populations, but on a curved surface that
+ *      correction acts as a spurious local source and spoils the order of
+ *      convergence (circular Couette flow: 2-6% errors that do not fall with
+ *      resolution, against 0.7%, 0.14%, 0.026% without it), so here none
+ *      is applied;
+ *   g: the body holds the induced field at zero, B = (0, B0) on its surface
+ *      (an insulating body that field lines cross undisturbed): interpolated
+ *      anti-bounce-back of each component's deviation from W_a B_wall on the
+ *      D2Q5 links, with the same branches.
+ * At q = 1/2 this is the paper's link-based closure of an insulating
+ * (c_w = 0) Hartmann wall (Sec. VI): half-way bounce-back with Ladd's term
+ * and anti-bounce-back of g to B_x = 0, B_y = B0.
+ */
 static inline size_t idx(const orc_params *p, int plane, int y, int x) {
   return ((size_t)plane * (size_t)p->ny + (size_t)y) * (size_t)p->nx + (size_t)x;
 }
+
+/* x offset of a point from a circle's centre, taken to the nearest image. */
+static double body_dx(const orc_params *p, double X, double cx) {
+  double dx = X - cx;
+  if (!p->x_walls) {
+    const double L = (double)p->nx;
+    dx -= L * floor(dx / L + 0.5);
+  }
+  return dx;
+}
+
+static int inside_body(const orc_params *p, const struct orc_solid *b, double X, double Y) {
+  switch (b->kind) {
+  case ORC_SOLID_DISC:
+  case ORC_SOLID_BORE: {
+    const double dx = body_dx(p, X, b->cx), dy = Y - b->cy;
+    const double d2 = dx * dx + dy * dy, r2 = b->r * b->r;
+    return b->kind == ORC_SOLID_DISC ? d2 < r2 : d2 > r2;
+  }
+  case ORC_SOLID_BELOW: return Y < b->cy;
+  case ORC_SOLID_ABOVE: return Y > b->cy;
+  default: return 0;
+  }
+}
+
+int orc_is_solid(const orc_params *p, int x, int y) {
+  for (int k = 0; k < p->nsolid; ++k)
+    if (inside_body(p, &p->solid[k], (double)x, (double)y)) return 1;
+  return 0;
+}
+
+/* The link from fluid node (x, y) towards its upstream node (x, y) - e_a:
+ * returns 1 and the surface distance q (fraction of the link) and the
+ * surface velocity where a body contains the upstream node, the nearest
+ * crossing if several do. */
+int orc_link_cut(const orc_params *p, int x, int y, int a, double *q, double *uwx,
+                 double *uwy) {
+  const double ex = EX9[a], ey = EY9[a];
+  const double ux = x - ex, uy = y - ey; /* upstream point */
+  int found = 0;
+  double best = 2.0;
+  for (int k = 0; k < p->nsolid; ++k) {
+    const struct orc_solid *b = &p->solid[k];
+    if (!inside_body(p, b, ux, uy)) continue;
+    double t, wx = 0.0, wy = 0.0;
+    if (b->kind == ORC_SOLID_DISC || b->kind == ORC_SOLID_BORE) {
+      /* |P - t e - c| = r along the link from the node (P) */
+      const double px = body_dx(p, (double)x, b->cx), py = (double)y - b->cy;
+      const double ee = ex * ex + ey * ey, pe = px * ex + py * ey;
+      const double disc = pe * pe - ee * (px * px + py * py - b->r * b->r);
+      const double sq = sqrt(disc > 0.0 ? disc : 0.0);
+      /* entering a disc: the first root; leaving a bore: the second */
+      t = (b->kind == ORC_SOLID_DISC ? pe - sq : pe + sq) / ee;
+      wx = -b->omega * (py - t * ey);
+      wy = b->omega * (px - t * ex);
+    } else {
+      t = ((double)y - b->cy) / ey;
+      wx = b->u;
+    }
+    if (t <= 0.0) t = 1e-12; /* a node on the surface itself */
+    if (t > 1.0) t = 1.0;
+    if (t < best) {
+      best = t;
+      *uwx = wx;
+      *uwy = wy;
+      found = 1;
+    }
+  }
+  if (found) *q = best;
+  return found;
+}
+
+/* Closure of every link of fluid node (x, y) that comes from a solid node;
+ * `in` is the whole post-collision state. */
+static void curved_closure(const orc_params *p, const double *in, int x, int y, double *f,
+                           double *gx, double *gy) {
+#define ST(plane, yy, xx) in[idx(p, (plane), (yy), ((xx) % p->nx + p->nx) % p->nx)]
+  int cut[NQ9] = {0};
+  double qa[NQ9] = {0.0};
+  int nearok[NQ9] = {0};
+  for (int a = 1; a < NQ9; ++a) {
+    double q, uwx = 0.0, uwy = 0.0;
+    if (!orc_link_cut(p, x, y, a, &q, &uwx, &uwy)) continue;
+    cut[a] = 1;
+    qa[a] = q;
+    const int nxp = x + EX9[a], nyp = y + EY9[a]; /* next node into the fluid */
+    nearok[a] = q < 0.5 && nyp >= 0 && nyp < p->ny &&
+                !orc_is_solid(p, ((nxp % p->nx) + p->nx) % p->nx, nyp);
+    const double m = 2.0 * W9[a] * (EX9[a] * uwx + EY9[a] * uwy) / CS2;
+    const double o = ST(OPP9[a], y, x);
+    if (nearok[a])
+      f[a] = 2.0 * q * o + (1.0 - 2.0 * q) * ST(OPP9[a], nyp, nxp) + m;
+    else if (q >= 0.5)
+      f[a] = o / (2.0 * q) + (1.0 - 1.0 / (2.0 * q)) * ST(a, y, x) + m / (2.0 * q);
+    else
+      f[a] = o + m;
+  }
+  /* D2Q5: the axis links 1..4 (same directions as D2Q9's) */
+  for (int a = 1; a < NQ5; ++a) {
+    if (!cut[a]) continue;
+    const double q = qa[a];
+    const int o = OPP5[a];
+    double *g[2] = {gx, gy};
+    for (int i = 0; i < 2; ++i) {
+      const int base = 9 + 5 * i;
+      const double dev = (i == 1) ? W5[a] * p->b0 : 0.0; /* W_a B_wall,i */
+      const double ov = ST(base + o, y, x) - dev;
+      double v;
+      if (nearok[a])
+        v = -2.0 * q * ov + (2.0 * q - 1.0) * (ST(base + o, y + EY5[a], x + EX5[a]) - dev);
+      else if (q >= 0.5)
+        v = -ov / (2.0 * q) + (1.0 - 1.0 / (2.0 * q)) * (ST(base + a, y, x) - dev);
+      else
+        v = -ov;
+      g[i][a] = v + dev;
+    }
+  }
+#undef ST
+}
+
+/* ---------------------------------------------------------------------- */
+/* One node: stream, close, moments, solve; optionally collide            */
+/* ---------------------------------------------------------------------- */
 
 typedef struct {
   double f[NQ9], gx[NQ5], gy[NQ5];
   double rho, ux, uy, bx, by, jz, Fx, Fy;
 } node_t;
 
+/* Rest state of a solid node: equilibrium at rho = 1, u = 0, B = (0, B0). */
+static void rest_node(const orc_params *p, node_t *n) {
+  orc_feq(1.0, 0.0, 0.0, n->f);
+  orc_geq(0.0, p->b0, 0.0, 0.0, n->gx, n->gy);
+  n->rho = 1.0;
+  n->ux = n->uy = n->jz = n->Fx = n->Fy = 0.0;
+  n->bx = 0.0;
+  n->by = p->b0;
+}
+
 static void gather_node(const orc_params *p, const double *in, int x, int y,
                         node_t *n) {
+  if (p->nsolid > 0 && orc_is_solid(p, x, y)) {
+    rest_node(p, n);
+    return;
+  }
   /* S1: pull streaming, f_alpha(x) = f~_alpha(x - e_alpha) (Eqs.
    * LBMforflowfield, LKSformagneticfield); x periodic, or bounded by walls
    * in an enclosure. */
@@ -483,6 +661,8 @@ static void gather_node(const orc_params *p, const double *in, int x, int y,
       }
     }
   }
+  /* S2b: links from solid bodies (curved walls) */
+  if (p->nsolid > 0) curved_closure(p, in, x, y, n->f, n->gx, n->gy);
   /* S3: moments (Secs. IV, V). */
   double rho = 0.0, mx = 0.0, my = 0.0;
   for (int q = 0; q < NQ9; ++q) {
@@ -648,22 +828,30 @@ static void step_rows(const orc_params *p, const double *in, double *out,
       node_t n;
       gather_node(p, in, x, y, &n);
       double o[NPLANES];
-      orc_collide(p, n.f, n.gx, n.gy, n.rho, n.ux, n.uy, n.bx, n.by, n.Fx,
-                  n.Fy, o);
+      if (p->nsolid > 0 && orc_is_solid(p, x, y)) {
+        /* a solid node keeps the rest state */
+        for (int q = 0; q < NQ9; ++q) o[q] = n.f[q];
+        for (int q = 0; q < NQ5; ++q) o[9 + q] = n.gx[q], o[14 + q] = n.gy[q];
+      } else {
+        orc_collide(p, n.f, n.gx, n.gy, n.rho, n.ux, n.uy, n.bx, n.by, n.Fx, n.Fy, o);
+      }
       for (int q = 0; q < NPLANES; ++q) out[idx(p, q, y, x)] = o[q];
     }
   }
 }
 
 /* Initial state: equilibrium at rest with density rho0 and B = (0, B0),
- * i.e. zero induced field; stored as post-collision populations. */
+ * i.e. zero induced field (solid nodes: rho = 1); stored as post-collision
+ * populations. */
 void orc_init(const orc_params *p, double rho0, double *state) {
-  double feq[NQ9], gex[NQ5], gey[NQ5];
+  double feq[NQ9], feq1[NQ9], gex[NQ5], gey[NQ5];
   orc_feq(rho0, 0.0, 0.0, feq);
+  orc_feq(1.0, 0.0, 0.0, feq1);
   orc_geq(0.0, p->b0, 0.0, 0.0, gex, gey);
   for (int y = 0; y < p->ny; ++y)
     for (int x = 0; x < p->nx; ++x) {
-      for (int q = 0; q < NQ9; ++q) state[idx(p, q, y, x)] = feq[q];
+      const int solid = p->nsolid > 0 && orc_is_solid(p, x, y);
+      for (int q = 0; q < NQ9; ++q) state[idx(p, q, y, x)] = solid ? feq1[q] : feq[q];
       for (int q = 0; q < NQ5; ++q) {
         state[idx(p, 9 + q, y, x)] = gex[q];
         state[idx(p, 14 + q, y, x)] = gey[q];
@@ -725,4 +913,4 @@ void orc_gather(const orc_params *p, const double *state, int x, int y,
   }
 }
 
-int orc_abi_version(void) { return 3; }
+int orc_abi_version(void) { return 4; }
