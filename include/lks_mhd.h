@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define LKS_MHD_ABI_VERSION 8
+#define LKS_MHD_ABI_VERSION 9
 
 typedef struct lks_mhd lks_mhd_t;             /* one channel, library-owned */
 typedef struct lks_mhd_batch lks_mhd_batch_t; /* many channels, library-owned */
@@ -173,7 +173,45 @@ enum lks_status {
  *               closure that reduces to the paper's at q = 1/2 (single
  *               channels, not enclosures or batches; ny >= 3; a conducting
  *               wall needs c a + q + tau_m - 1 >= 1/4).
+ *   nsolids,    solid bodies (lks_solid) in the channel [0]: curved walls,
+ *   solids      which the paper names as future work (Sec. IX).  A fluid
+ *               node's populations pulled from a solid node are closed on
+ *               that link at the surface distance q (0 < q <= 1, the
+ *               fraction of the link from the node): f by linear
+ *               interpolated bounce-back (Bouzidi, Firdaouss and Lallemand,
+ *               Phys. Fluids 13 (2001) 3452) with the surface velocity's
+ *               moving-wall term, g by interpolated anti-bounce-back that
+ *               holds the induced field at zero on the surface (B = (0, B0):
+ *               an insulating body that field lines cross undisturbed).  At
+ *               q = 1/2 this is the paper's link closure of an insulating
+ *               Hartmann wall; at other q interpolated bounce-back lets a
+ *               little mass through the surface.  Solid nodes hold the rest
+ *               state at unit density (their observables: rho = 1, u = 0,
+ *               B = (0, B0), J = 0).  Single channels in FP64 or FP32 storage,
+ *               x periodic with half-way Hartmann walls (q = 1/2), nodes
+ *               next to a body not on the rows 0 and ny - 1; plain launches
+ *               (shape 0) only.
  */
+/* Solid bodies inside a channel (curved walls), in lattice units with node
+ * (i, j) at the point (i, j); x is periodic, so a circle also covers its
+ * images one period away.  A node is solid if it lies strictly inside a
+ * body.
+ *   LKS_SOLID_DISC   solid inside the circle of centre (cx, cy), radius r
+ *   LKS_SOLID_BORE   solid outside that circle
+ *   LKS_SOLID_BELOW  solid where y < cy (a half-plane)
+ *   LKS_SOLID_ABOVE  solid where y > cy
+ * omega: a circle's surface turns at angular velocity omega
+ * (counterclockwise) about its centre; u: a half-plane slides along x. */
+#define LKS_MAX_SOLIDS 4
+enum lks_solid_kind { LKS_SOLID_DISC = 1, LKS_SOLID_BORE = 2, LKS_SOLID_BELOW = 3,
+                      LKS_SOLID_ABOVE = 4 };
+typedef struct {
+  int32_t kind, pad;
+  double cx, cy, r;
+  double omega;
+  double u;
+} lks_solid;
+
 typedef struct {
   int32_t nx, ny;
   int32_t bc;
@@ -193,6 +231,8 @@ typedef struct {
   double q_lower, q_upper;
   double s_fe, s_feps, s_fq;
   double s_me, s_md;
+  int32_t nsolids, pad_;
+  lks_solid solids[LKS_MAX_SOLIDS];
 } lks_mhd_params;
 
 /* Lattice quantities derived from a parameter set (host FP64). */

@@ -28,6 +28,16 @@ LKS_BGK, LKS_TRT, LKS_MRT = 0, 1, 2
 COLLISIONS = {"bgk": LKS_BGK, "trt": LKS_TRT, "mrt": LKS_MRT}
 
 
+class LksSolid(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("pad", ctypes.c_int32), ("cx", ctypes.c_double),
+                ("cy", ctypes.c_double), ("r", ctypes.c_double), ("omega", ctypes.c_double),
+                ("u", ctypes.c_double)]
+
+
+SOLID_KINDS = {"disc": 1, "bore": 2, "below": 3, "above": 4}
+MAX_SOLIDS = 4
+
+
 class LksParams(ctypes.Structure):
     _fields_ = [
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
@@ -44,6 +54,8 @@ class LksParams(ctypes.Structure):
         ("q_lower", ctypes.c_double), ("q_upper", ctypes.c_double),
         ("s_fe", ctypes.c_double), ("s_feps", ctypes.c_double), ("s_fq", ctypes.c_double),
         ("s_me", ctypes.c_double), ("s_md", ctypes.c_double),
+        ("nsolids", ctypes.c_int32), ("pad_", ctypes.c_int32),
+        ("solids", LksSolid * MAX_SOLIDS),
     ]
 
 
@@ -163,7 +175,7 @@ def check(code: int, what: str = "") -> int:
 def make_params(nx: int, ny: int, *, bc="link", precision="fp32", tau_f=0.8, tau_m=0.8,
                 ha=None, b0=None, c_lower=0.0, c_upper=None, u_lower=0.0, u_upper=0.0,
                 fx=None, fy=0.0, u_max=None, rho0=1.0, collision="bgk", lambda_f=None,
-                lambda_m=None, x_walls=False, c_x=0.0, q=0.5, mrt=None) -> LksParams:
+                lambda_m=None, x_walls=False, c_x=0.0, q=0.5, mrt=None, solids=()) -> LksParams:
     """Build a parameter struct.  ``ha`` derives B0; ``u_max`` derives F_x;
     ``collision`` is "bgk", "trt" or "mrt" (magic parameters ``lambda_f``,
     ``lambda_m``; the library's defaults when None); ``mrt`` is a dict of
@@ -171,7 +183,9 @@ def make_params(nx: int, ny: int, *, bc="link", precision="fp32", tau_f=0.8, tau
     the library's defaults; ``x_walls`` makes an
     enclosure whose x-walls have the conductance ratios ``c_x`` (both) or
     (x = 0 side, x = nx-1 side); ``q`` puts the link-based Hartmann walls at
-    that distance from their wall rows (both, or (lower, upper))."""
+    that distance from their wall rows (both, or (lower, upper)); ``solids``
+    lists solid bodies (curved walls) as (kind, cx, cy, r, omega, u) with kind
+    "disc", "bore", "below" or "above" (lks_solid)."""
     p = LksParams()
     lib().lks_mhd_default_params(ctypes.byref(p), int(nx), int(ny))
     p.bc = BCS[bc] if isinstance(bc, str) else int(bc)
@@ -205,6 +219,12 @@ def make_params(nx: int, ny: int, *, bc="link", precision="fp32", tau_f=0.8, tau
         if name not in ("s_fe", "s_feps", "s_fq", "s_me", "s_md"):
             raise ValueError(f"unknown MRT rate {name!r}")
         setattr(p, name, float(v))
+    if len(solids) > MAX_SOLIDS:
+        raise ValueError(f"at most {MAX_SOLIDS} solid bodies")
+    p.nsolids = len(solids)
+    for k, (kind, cx, cy, r, omega, u) in enumerate(solids):
+        kind = SOLID_KINDS[kind] if isinstance(kind, str) else int(kind)
+        p.solids[k] = LksSolid(kind, 0, float(cx), float(cy), float(r), float(omega), float(u))
     return p
 
 

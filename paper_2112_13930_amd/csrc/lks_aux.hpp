@@ -12,7 +12,8 @@ namespace lks {
 // Rest state at density rho0 with B = (0, B0).  Stored deviations:
 // f' = w (rho0 - 1), g_x = 0, g'_y = 0 (binary16: times its scale 2^12).
 template <typename S>
-__global__ void k_init(Geom g, double rho0, S *__restrict__ dst) {
+__global__ void k_init(Geom g, double rho0, S *__restrict__ dst,
+                       const int32_t *__restrict__ sidx = nullptr) {
   const long long n = (long long)g.nx * g.ny;
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -20,7 +21,9 @@ __global__ void k_init(Geom g, double rho0, S *__restrict__ dst) {
   const long long o = (long long)y * g.pitch + x;
   const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
   const double up = kRowRef<S> ? kStoreUp16 : 1.0;
-  for (int q = 0; q < 9; ++q) dst[q * g.plane + o] = (S)(w[q] * (rho0 - 1.0) * up);
+  // solid nodes (sidx, when given) rest at unit density
+  const double r0 = (sidx && sidx[i] == kSolidNode) ? 1.0 : rho0;
+  for (int q = 0; q < 9; ++q) dst[q * g.plane + o] = (S)(w[q] * (r0 - 1.0) * up);
   for (int q = 0; q < 5; ++q) {
     dst[(9 + q) * g.plane + o] = (S)0.0;
     dst[(14 + q) * g.plane + o] = (S)0.0;

@@ -798,6 +798,10 @@ int lks_mhd_batch_admit(lks_mhd_batch_t *b, const lks_mhd_params *p, int32_t *sl
     set_error("invalid parameters: batches hold half-way walls only (q = 1/2)");
     return LKS_EINVAL;
   }
+  if (q.nsolids > 0) {
+    set_error("invalid parameters: batches hold channels without solid bodies");
+    return LKS_EINVAL;
+  }
 
   const int64_t n = (int64_t)q.nx * q.ny;
   if (b->nodes + n > b->max_nodes) {

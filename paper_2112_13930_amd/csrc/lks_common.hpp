@@ -51,6 +51,8 @@ Coef<C> make_coef(const Channel &c, double inc_scale = 1.0) {
   WallD lo, hi;
   wall_coefficients(c, &lo, &hi);
   Coef<C> k;
+  k.sidx = nullptr; // solid-body tables: set where a channel's memory is laid out
+  k.snode = nullptr;
   const double sc = inc_scale;
   k.omega_f = C(sc * (1.0 / c.p.tau_f));
   k.kappa_f = C(sc * (1.0 - 0.5 / c.p.tau_f));
@@ -117,7 +119,8 @@ Coef<C> make_coef(const Channel &c, double inc_scale = 1.0) {
 inline int scheme_of(const lks_mhd_params &p) {
   return (p.bc == LKS_BC_LINK ? BC_LINK : BC_MOMENT) | (p.collision == LKS_TRT ? COLL_TRT : 0) |
          (p.collision == LKS_MRT ? COLL_MRT : 0) |
-         (p.x_walls ? WALLS_X : 0) | ((p.q_lower != 0.5 || p.q_upper != 0.5) ? WALLS_Q : 0);
+         (p.x_walls ? WALLS_X : 0) | ((p.q_lower != 0.5 || p.q_upper != 0.5) ? WALLS_Q : 0) |
+         (p.nsolids > 0 ? SOLIDS : 0);
 }
 
 inline bool valid_precision(int precision) {

@@ -30,6 +30,7 @@
 
 #include <type_traits>
 
+#include "lks_geometry.hpp"
 #include "lks_sr.hpp"
 
 // Arithmetic of the reduced-precision modes (compile-time; the defaults are
@@ -71,6 +72,8 @@ constexpr int COLL_MRT = 64;
 // the coefficients ask for them (Coef::mrt_on): the batched kernel runs TRT
 // and MRT channels through one inlined scheme
 constexpr int MRT_RT = 128;
+// ... and with SOLIDS where solid bodies (curved walls) lie in the channel
+constexpr int SOLIDS = 256;
 constexpr int wall_of(int scheme) { return scheme & 3; }
 constexpr bool trt_of(int scheme) { return (scheme & COLL_TRT) != 0; }
 constexpr bool xwalls_of(int scheme) { return (scheme & WALLS_X) != 0; }
@@ -78,6 +81,7 @@ constexpr bool cut_of(int scheme) { return (scheme & WALLS_Q) != 0; }
 constexpr bool in_batch(int scheme) { return (scheme & IN_BATCH) != 0; }
 constexpr bool mrt_of(int scheme) { return (scheme & COLL_MRT) != 0; }
 constexpr bool mrt_rt_of(int scheme) { return (scheme & MRT_RT) != 0; }
+constexpr bool solids_of(int scheme) { return (scheme & SOLIDS) != 0; }
 enum { MODE_STEP = 0, MODE_RECORD = 1, MODE_RESIDUAL = 2, MODE_MOMENTS = 3 };
 
 // Closure coefficients of one wall (computed on the host in FP64).
@@ -162,6 +166,8 @@ struct Coef {
   int mrt_on; // 1 for an MRT channel
   C xr_lo, xr_hi; // enclosure walls (WALLS_X): (theta-1)/(theta+1) at x = 0, nx-1
   Cut<C> clo, chi; // Hartmann walls at cut distances (WALLS_Q)
+  const int32_t *sidx;     // solid bodies (SOLIDS): per node kSolidFluid, kSolidNode or
+  const CurvedNode *snode; // an index into snode (device arrays, lks_geometry.hpp)
 };
 
 // Geometry of one channel's planes (element units).
@@ -361,6 +367,43 @@ __device__ __forceinline__ void collide_g_pair(C &ga, C &gb, C ea, C eb, const T
 }
 
 // ---- wall closures of the populations entering from a wall ----
+
+// Links of a fluid node that come from a solid body (curved walls, the
+// coefficients of lks_geometry.hpp): f_a = ca o + cb X + mw and, for the
+// D2Q5 links, g_a = za o + zb X per component, o the node's own population
+// leaving towards the surface and X the next node's (near) or the node's own
+// h_a.  Populations are in the stored deviation form, in which these maps
+// hold unchanged (ca + cb = 1; the surface holds g at its rest value).
+template <typename S, typename C>
+__device__ __forceinline__ void solid_closure(const Geom &g, const CurvedNode &cn,
+                                              const S *__restrict__ src,
+                                              const C *__restrict__ ref, int x, int y,
+                                              C (&f)[9], C (&gx)[5], C (&gy)[5]) {
+  constexpr int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+  constexpr int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+  constexpr int opp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+  const long long P = g.plane;
+  auto at = [&](int plane, int yy, int xx) -> C {
+    xx = xx < 0 ? xx + g.nx : (xx >= g.nx ? xx - g.nx : xx);
+    return dec<S>(ld<S, C>(src + plane * P + (long long)yy * g.pitch + xx),
+                  ref + (long long)yy * kRefRow, plane);
+  };
+  const uint32_t cut = cn.cut, near = cn.near;
+#pragma unroll
+  for (int a = 1; a < 9; ++a) {
+    if (!((cut >> a) & 1u)) continue;
+    const int b = opp[a];
+    const bool nr = (near >> a) & 1u;
+    const int xs = nr ? x + ex[a] : x, ys = nr ? y + ey[a] : y; // X's node
+    const int px = nr ? b : a;                                  // and plane
+    f[a] = C(cn.ca[a - 1]) * at(b, y, x) + C(cn.cb[a - 1]) * at(px, ys, xs) + C(cn.mw[a - 1]);
+    if (a <= 4) {
+      const C za = C(cn.za[a - 1]), zb = C(cn.zb[a - 1]);
+      gx[a] = za * at(9 + b, y, x) + zb * at(9 + px, ys, xs);
+      gy[a] = za * at(14 + b, y, x) + zb * at(14 + px, ys, xs);
+    }
+  }
+}
 
 // Enclosure walls at x = -1/2 and nx - 1/2 (parallel to the imposed field,
 // stationary): bounce-back of f, theta closure of the induced tangential
@@ -1066,6 +1109,24 @@ __device__ __forceinline__ void node_update(const Geom &g, const Coef<C> &k,
     }
     return;
   } else {
+    // solid bodies: a solid node keeps the rest state (stored deviations
+    // zero) and reports rho = 1, u = 0, B = (0, B0), J = 0
+    int32_t sid = kSolidFluid;
+    if constexpr (solids_of(BC)) {
+      sid = k.sidx[(long long)y * g.nx + x];
+      if (sid == kSolidNode) {
+        obs.rho = C(1);
+        obs.rhop = C(0);
+        obs.ux = obs.uy = obs.bx = obs.jz = obs.fx = obs.fy = C(0);
+        obs.by = k.b0;
+        if constexpr (MODE != MODE_MOMENTS) {
+          const long long o = r0 + x;
+#pragma unroll
+          for (int q = 0; q < 19; ++q) st<S, S>(dst + q * P + o, S(0));
+        }
+        return;
+      }
+    }
     // ---- pull streaming: f_a(x) = f~_a(x - e_a) ----
     // stored values are decoded with the reference of the row they come from
     const C *__restrict__ Dy = ref + (long long)y * kRefRow;
@@ -1106,6 +1167,8 @@ __device__ __forceinline__ void node_update(const Geom &g, const Coef<C> &k,
       gy[4] = dec<S>(ld<S, C, NT>(at(18, u0)), Dp, 18);
     }
 
+    if constexpr (solids_of(BC))
+      if (sid >= 0) solid_closure<S, C>(g, k.snode[sid], src, ref, x, y, f, gx, gy);
     NodeObs<C> &o_ = obs;
     S out[19];
     node_finish<S, C, BC, MODE, SR>(g, k, src, ref, x, y, f, gx, gy, o_, sseed, out);

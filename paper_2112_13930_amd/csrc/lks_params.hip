@@ -17,6 +17,7 @@
 #include <string>
 
 #include "lks_common.hpp"
+#include "lks_geometry.hpp"
 
 namespace lks {
 
@@ -79,6 +80,25 @@ int derive_channel(const lks_mhd_params *p, Channel *out) {
     if (p->bc != LKS_BC_LINK) return bad("walls at cut distances need link-based closures");
     if (p->x_walls) return bad("walls at cut distances are not available in enclosures");
     if (p->ny < 3) return bad("walls at cut distances need ny >= 3");
+  }
+  if (p->nsolids < 0 || p->nsolids > LKS_MAX_SOLIDS) return bad("nsolids must be in [0, 4]");
+  if (p->nsolids > 0) {
+    for (int k = 0; k < p->nsolids; ++k) {
+      const lks_solid &b = p->solids[k];
+      if (b.kind < LKS_SOLID_DISC || b.kind > LKS_SOLID_ABOVE) return bad("unknown solid kind");
+      if (!finite(b.cx) || !finite(b.cy) || !finite(b.omega) || !finite(b.u))
+        return bad("solid body parameters must be finite");
+      if ((b.kind == LKS_SOLID_DISC || b.kind == LKS_SOLID_BORE) && !(finite(b.r) && b.r > 0.0))
+        return bad("a circle needs a finite radius > 0");
+    }
+    if (p->precision != LKS_FP64 && p->precision != LKS_FP32)
+      return bad("solid bodies need FP64 or FP32 storage");
+    if (p->x_walls || cut)
+      return bad("solid bodies need an x-periodic channel with half-way Hartmann walls");
+    std::vector<int32_t> idx;
+    std::vector<CurvedNode> nodes;
+    const char *why = nullptr;
+    if (!build_solid_tables(*p, &idx, &nodes, &why)) return bad(why);
   }
   if (p->collision != LKS_BGK &&
       (!finite(p->lambda_f) || p->lambda_f <= 0.0 || !finite(p->lambda_m) || p->lambda_m <= 0.0))

@@ -3,12 +3,14 @@
 // reduction and hipGraph replay of step sequences.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
 #include <mutex>
 #include <new>
 #include <type_traits>
+#include <vector>
 
 #include "lks_aux.hpp"
 #include "lks_common.hpp"
@@ -310,6 +312,7 @@ struct Layout {
   long long plane;
   size_t state_bytes, rec_bytes, part_bytes, ref_bytes, total;
   int red_tiles_x, red_ntiles;
+  size_t sidx_bytes, snode_bytes; // solid bodies: per-node index, link table
 };
 
 Layout layout_of(const Channel &c) {
@@ -323,7 +326,17 @@ Layout layout_of(const Channel &c) {
   L.red_ntiles = L.red_tiles_x * ((c.p.ny + s.by - 1) / s.by);
   L.part_bytes = align256((size_t)L.red_ntiles * 8 * sizeof(double));
   L.ref_bytes = ref_area_bytes(c.p.ny, prec);
-  L.total = 2 * L.state_bytes + L.rec_bytes + L.part_bytes + 256 + 256 + L.ref_bytes;
+  L.sidx_bytes = L.snode_bytes = 0;
+  if (c.p.nsolids > 0) {
+    std::vector<int32_t> idx;
+    std::vector<CurvedNode> nodes;
+    const char *why = nullptr;
+    (void)build_solid_tables(c.p, &idx, &nodes, &why); // validated by derive_channel
+    L.sidx_bytes = align256((size_t)c.p.nx * c.p.ny * sizeof(int32_t));
+    L.snode_bytes = align256(std::max<size_t>(nodes.size(), 1) * sizeof(CurvedNode));
+  }
+  L.total = 2 * L.state_bytes + L.rec_bytes + L.part_bytes + 256 + 256 + L.ref_bytes +
+            L.sidx_bytes + L.snode_bytes;
   return L;
 }
 
@@ -426,6 +439,31 @@ hipError_t launch_mode(lks_mhd *h, int shape, const void *src, void *dst, ObsOut
         return launch_bc<S, C, BC_LINK | COLL_MRT | WALLS_Q, MODE>(h, shape, src, dst, oo);
       break;
     default: break;
+    }
+    // solid bodies: FP64 and FP32 storage, plain launches (shape 0)
+    if constexpr (!kRowRef<S>) {
+      switch (sch) {
+      case BC_LINK | SOLIDS: return launch_shape<S, C, BC_LINK | SOLIDS, MODE, 0>(h, src, dst, oo);
+      case BC_MOMENT | SOLIDS:
+        return launch_shape<S, C, BC_MOMENT | SOLIDS, MODE, 0>(h, src, dst, oo);
+      case BC_LINK | COLL_TRT | SOLIDS:
+        if constexpr (kCollide)
+          return launch_shape<S, C, BC_LINK | COLL_TRT | SOLIDS, MODE, 0>(h, src, dst, oo);
+        break;
+      case BC_MOMENT | COLL_TRT | SOLIDS:
+        if constexpr (kCollide)
+          return launch_shape<S, C, BC_MOMENT | COLL_TRT | SOLIDS, MODE, 0>(h, src, dst, oo);
+        break;
+      case BC_LINK | COLL_MRT | SOLIDS:
+        if constexpr (kCollide)
+          return launch_shape<S, C, BC_LINK | COLL_MRT | SOLIDS, MODE, 0>(h, src, dst, oo);
+        break;
+      case BC_MOMENT | COLL_MRT | SOLIDS:
+        if constexpr (kCollide)
+          return launch_shape<S, C, BC_MOMENT | COLL_MRT | SOLIDS, MODE, 0>(h, src, dst, oo);
+        break;
+      default: break;
+      }
     }
     return hipErrorInvalidValue;
   });
@@ -650,12 +688,32 @@ int lks_mhd_create(const lks_mhd_params *p, void *dev_buf, size_t bytes,
   // binary16 planes: two nodes per thread (4-byte accesses) measured fastest
   h->shape = (is_binary16(c.p.precision) && c.p.nx % 2 == 0) ? 5 : 0;
   h->rebase_every = is_binary16(c.p.precision) ? kDefaultRebase : 0;
+  // solid bodies: the per-node index and the link table after the rest
+  std::vector<int32_t> sidx;
+  std::vector<CurvedNode> snode;
+  if (c.p.nsolids > 0) {
+    const char *why = nullptr;
+    (void)build_solid_tables(c.p, &sidx, &snode, &why); // validated by derive_channel
+    char *sb = base + L.total - L.sidx_bytes - L.snode_bytes;
+    h->kd.sidx = h->kf.sidx = reinterpret_cast<const int32_t *>(sb);
+    h->kd.snode = h->kf.snode = reinterpret_cast<const CurvedNode *>(sb + L.sidx_bytes);
+  }
   rc = with_device(h, [&]() -> int {
+    if (!sidx.empty()) {
+      LKS_HIP_CHECK(hipMemcpyAsync(const_cast<int32_t *>(h->kd.sidx), sidx.data(),
+                                   sidx.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                                   h->stream));
+      if (!snode.empty())
+        LKS_HIP_CHECK(hipMemcpyAsync(const_cast<CurvedNode *>(h->kd.snode), snode.data(),
+                                     snode.size() * sizeof(CurvedNode), hipMemcpyHostToDevice,
+                                     h->stream));
+      LKS_HIP_CHECK(hipStreamSynchronize(h->stream)); // the host vectors go out of scope
+    }
     const int grid = elementwise_grid(h);
     dispatch_precision(c.p.precision, [&](auto t) {
       using S = typename decltype(t)::S;
       hipLaunchKernelGGL(k_init<S>, dim3(grid), dim3(256), 0, h->stream, h->geom, c.p.rho0,
-                         static_cast<S *>(h->buf[0]));
+                         static_cast<S *>(h->buf[0]), h->kd.sidx);
     });
     LKS_HIP_CHECK(hipGetLastError());
     const int r = zero_ref(h);
@@ -681,6 +739,10 @@ int lks_mhd_set_launch_shape(lks_mhd_t *h, int32_t shape) {
   clear_error();
   if (!h || shape < 0 || shape >= kNumShapes) {
     set_error("shape must be in [0, %d)", kNumShapes);
+    return LKS_EINVAL;
+  }
+  if (h->ch.p.nsolids > 0 && shape != 0) {
+    set_error("channels with solid bodies run launch shape 0 only");
     return LKS_EINVAL;
   }
   if (h->ch.p.nx % kShapes[shape].vx != 0) {
@@ -917,6 +979,10 @@ int lks_mhd_advance_noalloc(const lks_mhd_params *p, double *dev_pops, int64_t s
   Channel c;
   int rc = derive_channel(p, &c);
   if (rc != LKS_OK) return rc;
+  if (c.p.nsolids > 0) {
+    set_error("channels with solid bodies need lks_mhd_create (their tables are uploaded)");
+    return LKS_EINVAL;
+  }
   const Layout L = layout_of(c);
   if (L.total > kScratchBytes) {
     set_error("channel needs %zu bytes of working memory, the scratch array holds %zu", L.total,

@@ -233,6 +233,10 @@ int validate3(const lks_mhd3_params *p, Channel *c) {
     set_error("invalid parameters: fz must be finite");
     return LKS_EINVAL;
   }
+  if (p->base.nsolids > 0) {
+    set_error("invalid parameters: solid bodies are two-dimensional (base.nsolids = 0)");
+    return LKS_EINVAL;
+  }
   if (p->base.x_walls) {
     set_error("invalid parameters: x is periodic in three dimensions (base.x_walls = 0)");
     return LKS_EINVAL;

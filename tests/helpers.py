@@ -24,6 +24,8 @@ def lib_kwargs(p: Params, precision: str) -> dict:
         kw.update(x_walls=True, c_x=(p.cx_lo, p.cx_hi))
     if (p.q_lo, p.q_hi) != (0.5, 0.5):
         kw.update(q=(p.q_lo, p.q_hi))
+    if p.solids:  # the oracle's body kinds are the library's (lks_solid_kind)
+        kw.update(solids=tuple(tuple(b) for b in p.solids))
     return kw
 
 

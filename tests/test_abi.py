@@ -39,7 +39,7 @@ def test_every_declared_symbol_is_exported(L):
 
 
 def test_abi_version(L):
-    assert L.lib().lks_mhd_abi_version() == 8
+    assert L.lib().lks_mhd_abi_version() == 9
 
 
 def _v(L, **kw):
