@@ -329,6 +329,48 @@ def cut_walls(torch, steps=200, warmup=20):
     return out
 
 
+def curved_walls(torch, steps=200, warmup=20):
+    """Solid bodies (curved walls): the FP32 rate of the headline channel
+    with a disc of radius 256 on its axis (algorithmic bytes 152 per node
+    plus the 4-byte node index the kernel reads), and the steady circular
+    Couette flow (inner radius 24 turning, outer 48 still, no field) against
+    its closed form u_theta = A r + B / r."""
+    import numpy as np
+
+    from paper_2112_13930_amd.channel import Channel
+    out = {}
+    disc = (("disc", 2047.5, 2047.5, 256.0, 0.0, 0.0),)
+    _, per_step, ch = time_channel(torch, Channel, dict(HEADLINE, solids=disc), steps, warmup)
+    ch.close()
+    gbs = 156 * 4096 * 4096 / per_step / 1e9
+    out["fp32_4096_disc_r256"] = {"mlups": round(4096 * 4096 / per_step / 1e6, 1),
+                                  "gbs": round(gbs, 1), "frac_hbm": round(gbs / PEAK_HBM_GBS, 3),
+                                  "bytes_per_node": 156}
+    r1, r2, u0 = 24.0, 48.0, 0.01
+    size = 2 * int(r2) + 6
+    c = (size - 1) / 2.0
+    omega = u0 / r1
+    kw = dict(bc="link", precision="fp32", tau_f=0.8, tau_m=0.8, b0=0.0,
+              solids=(("bore", c, c, r2, 0.0, 0.0), ("disc", c, c, r1, omega, 0.0)))
+    ch = Channel(size, size, stream=torch.cuda.Stream(), **kw)
+    ch.set_graph(50)
+    rc, n, res, _ = ch.run_to_steady(tol=2e-7, check_every=1000, max_steps=400_000)
+    m = {k: v.cpu().numpy() for k, v in ch.moments().items()}
+    ch.close()
+    y, x = np.mgrid[0:size, 0:size].astype(float)
+    dx, dy = x - c, y - c
+    r = np.hypot(dx, dy)
+    fluid = (r > r1) & (r < r2)
+    A = -omega * r1 ** 2 / (r2 ** 2 - r1 ** 2)
+    B = omega * r1 ** 2 * r2 ** 2 / (r2 ** 2 - r1 ** 2)
+    ut = (-dy * m["ux"] + dx * m["uy"]) / np.where(r > 0, r, 1.0)
+    exact = A * r + B / np.where(r > 0, r, 1.0)
+    err = float(np.sqrt(((ut - exact)[fluid] ** 2).sum() / (exact[fluid] ** 2).sum()))
+    out["fp32_couette_r24_r48"] = {"steps": int(n), "status": int(rc),
+                                   "u_theta_rel_l2_vs_closed_form": err}
+    return out
+
+
 def sweep(torch, steps=100, warmup=10):
     """Config sweep: Ha in {10, 50, 100} x c in {0, 1e-2, 1, 1e2, inf} x link/moment."""
     from paper_2112_13930_amd.channel import Channel
@@ -753,6 +795,7 @@ LEGS = {"developed": developed_state_rate, "sweep": sweep, "precisions": other_p
         "channel_3d": three_d, "duct_3d": duct_3d, "enclosure": enclosure, "trt": trt_rates,
         "mrt": mrt_rates,
         "cut_walls": cut_walls,
+        "curved_walls": curved_walls,
         "batched": lambda torch: batched(torch, "fp32"),
         "batched_fp16": lambda torch: batched(torch, "fp16", sequential=False),
         "serving": serving}
@@ -872,6 +915,8 @@ def main():
         extras["enclosure"] = enclosure(torch)
         log("cut walls ...")
         extras["cut_walls"] = cut_walls(torch)
+        log("curved walls ...")
+        extras["curved_walls"] = curved_walls(torch)
         log("TRT collision ...")
         extras["trt_collision"] = trt_rates(torch)
         log("MRT collision ...")
