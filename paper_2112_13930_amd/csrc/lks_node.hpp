@@ -198,6 +198,21 @@ struct NodeObs {
 // kernel's channel descriptors) rather than passed as a kernel argument.
 template <typename T> using gptr = __attribute__((address_space(1))) T *;
 
+// A plane's base address pinned in scalar registers.  Where every plane is
+// accessed at one common per-thread offset (the stores), the compiler would
+// otherwise add that offset to the kernel's base once and then each plane's
+// stride to the result, in 64-bit vector arithmetic per plane; an opaque
+// scalar base keeps the scalar-base + 32-bit vector-offset form instead.
+template <typename T> __device__ __forceinline__ T *sbase(T *p) {
+  // (the value is uniform; reading it from the first lane lets the compiler
+  // know so where its analysis cannot tell)
+  const uint64_t a = reinterpret_cast<uint64_t>(p);
+  uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+  uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+  asm("" : "+s"(lo), "+s"(hi));
+  return reinterpret_cast<T *>(((uint64_t)hi << 32) | lo);
+}
+
 template <typename S, typename C, bool NT = true>
 __device__ __forceinline__ C ld(const S *__restrict__ p) {
   if constexpr (NT) return static_cast<C>(__builtin_nontemporal_load((gptr<const S>)p));
@@ -883,12 +898,12 @@ __device__ __forceinline__ void xtab_row(const Geom &g, const Coef<double> &k, X
 
 // Collide one node of a binary16 state in FP32 with exact accumulation.
 // raw[] holds the 19 pulled stored values (unused where a wall closes the
-// population); the new stored values are returned in out (not for
-// MODE_MOMENTS, which this path does not serve).
+// population); not for MODE_MOMENTS, which this path does not serve.
 // Vy and Ky are row y's entries of t.V and t.K, or a copy of them (the
 // batched kernel stages the rows of a tile in LDS).
 // The new values before their rounding to binary16 go to emit(q, z_q), in
-// plane order (EmitX rounds them).
+// plane order; the caller rounds and stores them (stochastically, with the
+// node's F16Words in that order).
 template <typename S, int BC, int MODE, typename Emit>
 __device__ __forceinline__ void node_finish_x(const Geom &g, const Coef<float> &k,
                                               const S *__restrict__ src, XTabs t,
@@ -1009,21 +1024,6 @@ __device__ __forceinline__ void node_finish_x(const Geom &g, const Coef<float> &
   }
 }
 
-// The stochastic rounding of node_finish_x's values to binary16 (a plain
-// conversion without SR), in plane order: planes 2j and 2j + 1 take the top
-// 13 bits of the node stream's j-th xorshift word and of that word shifted
-// left by 16 -- those of Rng::next()'s words 2j and 2j + 1.  word(q) must be
-// called for q = 0, 1, ..., 18 in turn.
-template <bool SR>
-struct EmitWords {
-  uint32_t st, w = 0;
-  __device__ explicit EmitWords(uint32_t seed) : st(seed | 1u) {}
-  __device__ uint32_t word(int q) {
-    if (!(q & 1)) w = xorshift32(st);
-    return (q & 1) ? w << 16 : w;
-  }
-};
-
 // STAGED, xV, xK: for binary16 storage with FP32 arithmetic, row y's
 // pre-collision tables come from the caller's copy xV, xK (else from ref).
 template <typename S, typename C, int BC, int MODE, bool SR, bool STAGED = false>
@@ -1044,6 +1044,10 @@ __device__ __forceinline__ void node_update(const Geom &g, const Coef<C> &k,
   const long long rm = r0 - g.pitch;
   const long long rp = r0 + g.pitch;
   constexpr bool NT = !in_batch(BC) || sizeof(S) == 2;
+  // the node's byte offset in a plane for the stores, formed in 32 bits so
+  // that it stays their 32-bit vector offset (against a scalar plane base)
+  uint32_t so = ((uint32_t)y * (uint32_t)g.pitch + (uint32_t)x) * (uint32_t)sizeof(S);
+  asm("" : "+v"(so)); // (kept as one 32-bit value: not re-widened into the address)
 
   if constexpr (kXA<S, C> && MODE != MODE_MOMENTS) {
     // binary16 with FP32 arithmetic: pull the stored values undecoded.
@@ -1096,17 +1100,16 @@ __device__ __forceinline__ void node_update(const Geom &g, const Coef<C> &k,
     NodeObs<float> &o_ = obs;
     const XTabs t = xtabs_of(const_cast<C *>(ref), g.ny);
     const long long row = (long long)y * kRefRow;
-    EmitWords<SR> ew(SR ? node_seed(sseed, (uint32_t)(y * g.nx + x)) : 0u);
+    F16Words ew(SR ? node_seed(sseed, (uint32_t)(y * g.nx + x)) : 0u);
     node_finish_x<S, BC, MODE>(g, k, src, t, STAGED ? xV : t.V + row, STAGED ? xK : t.K + row, x,
                                y, raw, o_, [&](int q, float zq) {
                                  if constexpr (SR) out[q] = sr_f16(zq, ew.word(q));
                                  else out[q] = (S)zq;
                                });
 #pragma unroll
-    for (int q = 0; q < 19; ++q) {
-      char *plane = reinterpret_cast<char *>(dst + (long long)q * P);
-      __builtin_nontemporal_store(out[q], (gptr<S>)(plane + (uint32_t)(c0 * (uint32_t)sizeof(S))));
-    }
+    for (int q = 0; q < 19; ++q)
+      __builtin_nontemporal_store(out[q],
+                                  (gptr<S>)(reinterpret_cast<char *>(sbase(dst + (long long)q * P)) + so));
     return;
   } else {
     // solid bodies: a solid node keeps the rest state (stored deviations
@@ -1175,8 +1178,7 @@ __device__ __forceinline__ void node_update(const Geom &g, const Coef<C> &k,
     if constexpr (MODE != MODE_MOMENTS) {
 #pragma unroll
       for (int q = 0; q < 19; ++q)
-        st<S, S>(reinterpret_cast<S *>(reinterpret_cast<char *>(dst + (long long)q * P) +
-                                       (uint32_t)(c0 * (uint32_t)sizeof(S))),
+        st<S, S>(reinterpret_cast<S *>(reinterpret_cast<char *>(sbase(dst + (long long)q * P)) + so),
                  out[q]);
     } else {
       (void)dst;

@@ -212,9 +212,9 @@ __global__ __launch_bounds__(256) void k_step_vec(Geom g, Coef<C> k, const S *__
       NodeObs<C> o{};
       const XTabs t = xtabs_of(const_cast<C *>(ref), g.ny);
       const long long row = (long long)y * kRefRow;
-      // the node stream's words (EmitWords), each rounding written straight
+      // the node's random words (F16Words), each rounding written straight
       // into node v's half of the plane's vector
-      EmitWords<SR> ew(SR ? node_seed(sseed, (uint32_t)(y * nx + x0 + v)) : 0u);
+      F16Words ew(SR ? node_seed(sseed, (uint32_t)(y * nx + x0 + v)) : 0u);
       const int v0 = v & ~1; // (the loop is unrolled: v is a constant)
       node_finish_x<S, BC, MODE_STEP>(g, k, src, t, t.V + row, t.K + row, x0 + v, y, raw, o,
                                       [&](int q, float zq) {
@@ -255,11 +255,14 @@ __global__ __launch_bounds__(256) void k_step_vec(Geom g, Coef<C> k, const S *__
     for (int q = 0; q < 19; ++q) outv[q][v] = out[q];
     }
   }
+  // byte offset in a plane, formed in 32 bits (so that it stays the store's
+  // 32-bit vector offset)
+  uint32_t so = ((uint32_t)y * (uint32_t)g.pitch + (uint32_t)x0) * (uint32_t)sizeof(S);
+  asm("" : "+v"(so));
 #pragma unroll
   for (int q = 0; q < 19; ++q)
-    __builtin_nontemporal_store(
-        outv[q], (gptr<V>)(reinterpret_cast<char *>(dst + (long long)q * P) +
-                           (uint32_t)((r0 + x0) * (long long)sizeof(S))));
+    __builtin_nontemporal_store(outv[q],
+                                (gptr<V>)(reinterpret_cast<char *>(sbase(dst + (long long)q * P)) + so));
 }
 
 // Step counters of a channel set on the device (no host copy).
