@@ -17,7 +17,9 @@
 //
 // Random bits: one hashed seed per node and step (counter-based, so a run is
 // reproducible bit for bit and independent of launch shape or batch mix),
-// then one xorshift32 step (Marsaglia 2003) per two stored values.
+// then xorshift32 steps (Marsaglia 2003) from it: one per two stored values
+// in binary32/binary64 storage (Rng); in binary16 storage four, whose XOR
+// combinations give the node's ten words (F16Words).
 #pragma once
 
 #include <stdint.h>
@@ -71,6 +73,50 @@ struct Rng {
     w = xorshift32(s);
     half = true;
     return (w & 0xFFFF0000u) | 0x8000u;
+  }
+};
+
+// Random words of the binary16 stores of one node: 19 values, each rounded
+// with 13 bits (sr_f16).  Four xorshift32 steps from the node's seed give
+// W1..W4; planes 2j and 2j + 1 take the top 13 bits of word j and of word j
+// shifted left by 16, the words j = 0..9 being
+//   W1, W3, W4, W1^W2, W1^W3, W1^W4, W3^W4, W1^W2^W4, W1^W3^W4, W2
+// (plane 18 takes word 9's top bits only).  Each 13-bit field is a linear
+// map over GF(2) of the 32-bit seed, and any two of the 19 fields are
+// jointly uniform over the seed (their stacked 26 x 32 map has full rank, as
+// it has for ten consecutive xorshift words): the rounding errors of a
+// node's values are pairwise independent, so a moment summed from them has
+// the variance it would have with independent errors.  That takes 32
+// integer instructions per node where ten xorshift steps took 60.  (The
+// seed keeps all 32 bits: only zero, which xorshift cannot take, is
+// replaced; forcing the low bit to one instead would leave 31 bits and
+// linear relations between some pairs of fields.)  word(q) must be called
+// for q = 0, 1, ..., 18 in turn.
+struct F16Words {
+  uint32_t w1, w2, w3, w4, w = 0;
+  LKS_HD explicit F16Words(uint32_t seed) {
+    uint32_t s = seed ? seed : 0x9E3779B9u;
+    w1 = xorshift32(s);
+    w2 = xorshift32(s);
+    w3 = xorshift32(s);
+    w4 = xorshift32(s);
+  }
+  LKS_HD uint32_t word(int q) {
+    if (!(q & 1)) {
+      switch (q >> 1) {
+      case 0: w = w1; break;
+      case 1: w = w3; break;
+      case 2: w = w4; break;
+      case 3: w = w1 ^ w2; break;
+      case 4: w = w1 ^ w3; break;
+      case 5: w = w1 ^ w4; break;
+      case 6: w = w3 ^ w4; break;
+      case 7: w = (w1 ^ w2) ^ w4; break;
+      case 8: w = (w1 ^ w3) ^ w4; break;
+      default: w = w2; break;
+      }
+    }
+    return (q & 1) ? w << 16 : w;
   }
 };
 
