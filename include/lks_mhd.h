@@ -525,7 +525,8 @@ int lks_mhd_batch_save_state(lks_mhd_batch_t *b, int32_t slot,
  * B0, c and U per wall, fx or u_max, fy, rho0; derived exactly as for one
  * channel); precision LKS_FP64 or LKS_FP32 (binary32 storage, FP64
  * arithmetic, stochastic rounding).  nz >= 1 layers; fz the body force
- * along z.  nx * ny * nz must be below 2^31.
+ * along z.  nx * ny * nz must be below 2^31, and one layer's plane of
+ * nx * ny values below 2^32 bytes.
  *
  * side_walls 0: z periodic (a channel).  1: a rectangular duct, z bounded
  * by stationary thin conducting side walls half-way outside the layers

@@ -49,11 +49,23 @@ template <typename C> struct W3 {
   }
 };
 
+// State layout in z slabs: layer z holds its 37 planes of ny * nx values
+// one after the other, each starting on a 256-byte boundary (slab
+// elements apart), so value (q, z, y, x) sits at
+//   (z * 37 + q) * slab + y * nx + x.
+// A block's 37 streams then fall into three neighbouring layers rather than
+// across 37 planes of the whole volume.
 struct Geom3 {
   int nx, ny, nz;
-  long long plane; // elements per plane
-  int side;        // 1: side walls bound z (a duct), 0: z periodic
+  long long slab; // elements from one (layer, plane) to the next
+  int side;       // 1: side walls bound z (a duct), 0: z periodic
 };
+
+__host__ __device__ inline long long at3(const Geom3 &g, int q, long long node) {
+  const long long layer = (long long)g.nx * g.ny;
+  const long long z = node / layer;
+  return (z * kPlanes3 + q) * g.slab + (node - z * layer);
+}
 
 // Side-wall closure coefficients of a duct: g_in,i = r g~_out,i for the
 // tangential induced components (x, and y as stored minus W B0), for the
@@ -92,14 +104,29 @@ __device__ __forceinline__ void node3_update(const Geom3 &g, const Coef<C> &k, C
   // register type of the pulled values
   using R = typename ComputeSel<(WB != BC_NONE && sizeof(C) == 8) || sizeof(S) == 8>::type;
   const int nx = g.nx, ny = g.ny, nz = g.nz;
-  const long long P = g.plane;
   const bool lo = (WB != BC_NONE) && (y == 0), hi = (WB != BC_NONE) && (y == ny - 1);
   const int xs[3] = {x == 0 ? nx - 1 : x - 1, x, x == nx - 1 ? 0 : x + 1}; // x - e for e = 1, 0, -1
   const int zs[3] = {z == 0 ? nz - 1 : z - 1, z, z == nz - 1 ? 0 : z + 1};
-  const long long own = ((long long)z * ny + y) * nx + x;
-  // source offset of a population moving along e (pull: from x - e)
-  auto srcoff = [&](int ex_, int ey_, int ez_) -> long long {
-    return ((long long)zs[1 - ez_] * ny + (y - ey_)) * nx + xs[1 - ex_];
+  const uint32_t own = ((uint32_t)z * (uint32_t)ny + (uint32_t)y) * (uint32_t)nx + (uint32_t)x;
+  // Addresses: the base of a (layer, plane), uniform over the block and
+  // pinned in scalar registers, plus a 32-bit byte offset in it (a layer's
+  // plane holds fewer than 2^32 bytes), so that every access takes the
+  // scalar-base + 32-bit vector-offset form instead of a 64-bit vector
+  // address per plane.  The store offset, shared by every plane, is kept as
+  // one 32-bit value (the empty register constraint).
+  auto base = [&](auto *p, int zz, int q) {
+    return sbase(p + ((long long)zz * kPlanes3 + q) * g.slab);
+  };
+  // population q arriving along e from layer zs[1 - ez] (pull: from x - e)
+  auto in_ = [&](int q, int ez_, uint32_t b) {
+    return reinterpret_cast<const S *>(reinterpret_cast<const char *>(base(src, zs[1 - ez_], q)) +
+                                       b);
+  };
+  uint32_t own_b = ((uint32_t)y * (uint32_t)nx + (uint32_t)x) * (uint32_t)sizeof(S);
+  asm("" : "+v"(own_b));
+  // in-layer byte offset of the source of a population moving along e
+  auto srcoff = [&](int ex_, int ey_) -> uint32_t {
+    return ((uint32_t)(y - ey_) * (uint32_t)nx + (uint32_t)xs[1 - ex_]) * (uint32_t)sizeof(S);
   };
 
   // ---- pull streaming; populations entering from a wall are closed below ----
@@ -111,7 +138,7 @@ __device__ __forceinline__ void node3_update(const Geom3 &g, const Coef<C> &k, C
       f[q] = R(0);
       continue;
     }
-    const S *p = src + q * P + srcoff(D3Q19::ex[q], ey_, D3Q19::ez[q]);
+    const S *p = in_(q, D3Q19::ez[q], srcoff(D3Q19::ex[q], ey_));
     f[q] = D3Q19::ex[q] != 0 ? ldx<S, R>(p) : ld<S, R>(p);
   }
 #pragma unroll
@@ -121,15 +148,16 @@ __device__ __forceinline__ void node3_update(const Geom3 &g, const Coef<C> &k, C
       gx[a] = gy[a] = gz[a] = R(0);
       continue;
     }
-    const long long o = srcoff(D3Q6::ex[a], ey_, D3Q6::ez[a]);
+    const uint32_t o = srcoff(D3Q6::ex[a], ey_);
+    const int ez_ = D3Q6::ez[a];
     if (D3Q6::ex[a] != 0) {
-      gx[a] = ldx<S, R>(src + (19 + a) * P + o);
-      gy[a] = ldx<S, R>(src + (25 + a) * P + o);
-      gz[a] = ldx<S, R>(src + (31 + a) * P + o);
+      gx[a] = ldx<S, R>(in_(19 + a, ez_, o));
+      gy[a] = ldx<S, R>(in_(25 + a, ez_, o));
+      gz[a] = ldx<S, R>(in_(31 + a, ez_, o));
     } else {
-      gx[a] = ld<S, R>(src + (19 + a) * P + o);
-      gy[a] = ld<S, R>(src + (25 + a) * P + o);
-      gz[a] = ld<S, R>(src + (31 + a) * P + o);
+      gx[a] = ld<S, R>(in_(19 + a, ez_, o));
+      gy[a] = ld<S, R>(in_(25 + a, ez_, o));
+      gz[a] = ld<S, R>(in_(31 + a, ez_, o));
     }
   }
 
@@ -139,7 +167,7 @@ __device__ __forceinline__ void node3_update(const Geom3 &g, const Coef<C> &k, C
     // tangential field components by the theta-weighted Shercliff closure
     // (moving-wall term on B_x only), the normal one by anti-bounce-back,
     // all from the node's own post-collision values.
-    auto own_ = [&](int plane) { return ld<S, C>(src + plane * P + own); };
+    auto own_ = [&](int plane) { return ld<S, C>(in_(plane, 0, own_b)); };
     if (lo) {
       f[2] = own_(4);
       f[5] = own_(7) + k.lo.uw6;
@@ -316,8 +344,9 @@ __device__ __forceinline__ void node3_update(const Geom3 &g, const Coef<C> &k, C
     return C(v);
   };
   Rng rng(SR ? node_seed(sseed, (uint32_t)own) : 0u);
-  auto put = [&](long long plane, C v) {
-    __builtin_nontemporal_store(to_store<S, C, SR>(v, SR ? rng.next() : 0u), dst + plane * P + own);
+  auto put = [&](int plane, C v) {
+    __builtin_nontemporal_store(to_store<S, C, SR>(v, SR ? rng.next() : 0u),
+                                (gptr<S>)(reinterpret_cast<char *>(base(dst, z, plane)) + own_b));
   };
   const C om = k.omega_f, ka = k.kappa_f;
   const C usq15 = C(1.5) * (ux * ux + uy * uy + uz * uz);

@@ -140,8 +140,8 @@ __global__ void k_init3(Geom3 g, double rho0, S *__restrict__ dst) {
   const long long n = (long long)g.nx * g.ny * g.nz;
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  for (int q = 0; q < 19; ++q) dst[q * g.plane + i] = (S)(W3<double>::w(q) * (rho0 - 1.0));
-  for (int q = 19; q < kPlanes3; ++q) dst[q * g.plane + i] = (S)0.0;
+  for (int q = 0; q < 19; ++q) dst[at3(g, q, i)] = (S)(W3<double>::w(q) * (rho0 - 1.0));
+  for (int q = 19; q < kPlanes3; ++q) dst[at3(g, q, i)] = (S)0.0;
 }
 
 template <typename S>
@@ -149,12 +149,12 @@ __global__ void k_save3(Geom3 g, double b0, const S *__restrict__ src, double *_
   const long long n = (long long)g.nx * g.ny * g.nz;
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  for (int q = 0; q < 19; ++q) out[q * n + i] = (double)src[q * g.plane + i] + W3<double>::w(q);
+  for (int q = 0; q < 19; ++q) out[q * n + i] = (double)src[at3(g, q, i)] + W3<double>::w(q);
   for (int c = 0; c < 3; ++c) {
     out[(19 + 7 * c) * n + i] = 0.0;
     const double off = c == 1 ? b0 / 6.0 : 0.0;
     for (int a = 0; a < 6; ++a)
-      out[(20 + 7 * c + a) * n + i] = (double)src[(19 + 6 * c + a) * g.plane + i] + off;
+      out[(20 + 7 * c + a) * n + i] = (double)src[at3(g, 19 + 6 * c + a, i)] + off;
   }
 }
 
@@ -163,11 +163,11 @@ __global__ void k_load3(Geom3 g, double b0, const double *__restrict__ in, S *__
   const long long n = (long long)g.nx * g.ny * g.nz;
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  for (int q = 0; q < 19; ++q) dst[q * g.plane + i] = (S)(in[q * n + i] - W3<double>::w(q));
+  for (int q = 0; q < 19; ++q) dst[at3(g, q, i)] = (S)(in[q * n + i] - W3<double>::w(q));
   for (int c = 0; c < 3; ++c) {
     const double off = c == 1 ? b0 / 6.0 : 0.0;
     for (int a = 0; a < 6; ++a)
-      dst[(19 + 6 * c + a) * g.plane + i] = (S)(in[(20 + 7 * c + a) * n + i] - off);
+      dst[at3(g, 19 + 6 * c + a, i)] = (S)(in[(20 + 7 * c + a) * n + i] - off);
   }
 }
 
@@ -205,7 +205,7 @@ template <> Side3<double> side3<double>(const lks_mhd3 *h) { return h->sd; }
 template <> Side3<float> side3<float>(const lks_mhd3 *h) { return h->sf; }
 
 struct Layout3 {
-  long long plane;
+  long long slab; // elements per (layer, plane), see Geom3
   size_t state_bytes, rec_bytes, part_bytes, total;
   int tiles_x, ntiles;
 };
@@ -227,6 +227,14 @@ int validate3(const lks_mhd3_params *p, Channel *c) {
   }
   if (p->base.precision != LKS_FP64 && p->base.precision != LKS_FP32) {
     set_error("invalid parameters: the three-dimensional channel stores FP64 or FP32 populations");
+    return LKS_EINVAL;
+  }
+  // the kernels address a layer's plane with 32-bit byte offsets (a
+  // state of 74 such planes would exceed any device's memory long before)
+  if ((long long)p->base.nx * p->base.ny * (long long)elem_bytes(p->base.precision) >
+      (long long)((1LL << 32) - 256)) {
+    set_error("invalid parameters: one layer's population plane (nx * ny values) must hold "
+              "fewer than 2^32 bytes");
     return LKS_EINVAL;
   }
   if (!std::isfinite(p->fz)) {
@@ -280,8 +288,9 @@ Layout3 layout3(const lks_mhd3_params *p) {
   const long long n = (long long)p->base.nx * p->base.ny * p->nz;
   const size_t eb = elem_bytes(p->base.precision);
   const long long per256 = 256 / (long long)eb;
-  L.plane = (n + per256 - 1) / per256 * per256;
-  L.state_bytes = align256((size_t)kPlanes3 * L.plane * eb);
+  const long long layer = (long long)p->base.nx * p->base.ny;
+  L.slab = (layer + per256 - 1) / per256 * per256;
+  L.state_bytes = align256((size_t)kPlanes3 * p->nz * L.slab * eb);
   L.rec_bytes = align256((size_t)2 * n * sizeof(double));
   L.tiles_x = (p->base.nx + 255) / 256;
   L.ntiles = L.tiles_x * p->base.ny * p->nz;
@@ -461,7 +470,7 @@ int lks_mhd3_create(const lks_mhd3_params *p, void *dev_buf, size_t bytes, void 
   h->fz = p->fz;
   if (hipGetDevice(&h->device) != hipSuccess) h->device = 0;
   h->stream = static_cast<hipStream_t>(hip_stream);
-  h->geom = Geom3{c.p.nx, c.p.ny, p->nz, L.plane, p->side_walls};
+  h->geom = Geom3{c.p.nx, c.p.ny, p->nz, L.slab, p->side_walls};
   h->sd = Side3<double>{side_r(p->c_side_lower, c), side_r(p->c_side_upper, c)};
   h->sf = Side3<float>{(float)h->sd.r_lo, (float)h->sd.r_hi};
   char *base = static_cast<char *>(dev_buf);
