@@ -121,7 +121,7 @@ enum lks_status {
  * mu_m = 1).  Defaults that the helper lks_mhd_default_params() fills are
  * given in brackets.
  *   nx, ny      nodes; x periodic; ny >= 2 (link) or >= 3 (moment);
- *               nx * ny <= 2^31 / 19.
+ *               nx * ny <= (2^31 - 1) / 19 - 8192 (19 padded planes index in 32 bits).
  *   bc          LKS_BC_LINK or LKS_BC_MOMENT.
  *   precision   lks_precision.
  *   tau_f       BGK relaxation time of f, > 1/2: nu = (tau_f - 1/2)/3 (Sec. V).

@@ -53,7 +53,8 @@ int derive_channel(const lks_mhd_params *p, Channel *out) {
   if (p->nx < 1) return bad("nx must be >= 1");
   if (p->bc != LKS_BC_LINK && p->bc != LKS_BC_MOMENT) return bad("bc must be LKS_BC_LINK or LKS_BC_MOMENT");
   if (p->ny < (p->bc == LKS_BC_LINK ? 2 : 3)) return bad("ny must be >= 2 (link) or >= 3 (moment)");
-  if ((long long)p->nx * (long long)p->ny > (long long)(((1LL << 31) - 1) / 19))
+  // (19 planes, each padded by up to 8192 values, index in 32 bits)
+  if ((long long)p->nx * (long long)p->ny > (long long)(((1LL << 31) - 1) / 19) - 8192)
     return bad("nx * ny too large (19 planes must index in 32 bits)");
   if (!lks::valid_precision(p->precision)) return bad("unknown precision");
   if (!finite(p->tau_f) || p->tau_f <= 0.5) return bad("tau_f must be finite and > 1/2");

@@ -321,7 +321,7 @@ struct Layout {
 Layout layout_of(const Channel &c) {
   Layout L;
   const int prec = c.p.precision;
-  L.plane = plane_elems(c.p.nx, c.p.ny, prec);
+  L.plane = single_plane_elems(c.p.nx, c.p.ny, prec);
   L.state_bytes = align256((size_t)19 * L.plane * elem_bytes(prec));
   L.rec_bytes = align256((size_t)2 * c.p.nx * c.p.ny * sizeof(double));
   const Shape s = kShapes[kRedShape];
