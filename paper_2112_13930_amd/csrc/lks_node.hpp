@@ -203,9 +203,11 @@ template <typename T> using gptr = __attribute__((address_space(1))) T *;
 // otherwise add that offset to the kernel's base once and then each plane's
 // stride to the result, in 64-bit vector arithmetic per plane; an opaque
 // scalar base keeps the scalar-base + 32-bit vector-offset form instead.
+// p must be the same in every active lane of the wavefront (a kernel
+// argument, or a channel's buffer where a block works on one channel).
 template <typename T> __device__ __forceinline__ T *sbase(T *p) {
-  // (the value is uniform; reading it from the first lane lets the compiler
-  // know so where its analysis cannot tell)
+  // (reading it from the first lane tells the compiler that it is uniform
+  // where its analysis cannot)
   const uint64_t a = reinterpret_cast<uint64_t>(p);
   uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
   uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
