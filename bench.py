@@ -595,8 +595,9 @@ def serving(torch, rates=(50.0, 100.0, 200.0, 500.0, 1000.0, 2000.0), n_requests
 
 
 def profile_run_3d(torch, args):
-    """The 3D channel's FP32 steps only (256^3, headline physics), plus a
-    device copy of known size (counter scale)."""
+    """The 3D channel's steps only (256^3, headline physics; storage
+    precision --precision, FP32 or FP64; with --duct, Shercliff side walls of
+    c = 1 bound z), plus a device copy of known size (counter scale)."""
     from paper_2112_13930_amd.channel3 import Channel3
     a = torch.empty(COPY_REF_BYTES // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
@@ -604,8 +605,10 @@ def profile_run_3d(torch, args):
         b.copy_(a)
     torch.cuda.synchronize()
     del a, b
-    ch = Channel3(256, 256, 256, bc="link", precision="fp32", tau_f=0.7, tau_m=0.9, ha=50.0,
-                  c_lower=1.0, c_upper=1.0, u_upper=0.05, stream=torch.cuda.Stream())
+    duct = dict(side_walls=True, c_side=1.0) if args.duct else {}
+    ch = Channel3(256, 256, 256, bc="link", precision=args.precision, tau_f=0.7, tau_m=0.9,
+                  ha=50.0, c_lower=1.0, c_upper=1.0, u_upper=0.05, stream=torch.cuda.Stream(),
+                  **duct)
     ch.step(args.warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -646,10 +649,23 @@ def profile_run_batch(torch, args):
                       "per_step_ms": (time.perf_counter() - t0) / args.steps * 1e3}))
 
 
+# The headline channel as the bench legs vary it (--profile-run --variant).
+PROFILE_VARIANTS = {
+    "headline": {},
+    "moment": dict(bc="moment"),
+    "trt": dict(collision="trt"),
+    "mrt": dict(collision="mrt"),
+    "enclosure": dict(x_walls=True, c_x=1.0),
+    "cut": dict(q=(0.3, 0.8)),
+    "disc": dict(solids=(("disc", 2047.5, 2047.5, 256.0, 0.0, 0.0),)),
+}
+
+
 def profile_run(torch, args):
     """Headline steps only (in the storage precision --precision, from rest or
-    on the developed random state with --developed), plus a device copy of
-    known size (counter scale)."""
+    on the developed random state with --developed; with --variant, the
+    scheme of another bench leg), plus a device copy of known size (counter
+    scale)."""
     from paper_2112_13930_amd.channel import Channel
     from paper_2112_13930_amd.workloads import random_populations
     a = torch.empty(COPY_REF_BYTES // 4, dtype=torch.float32, device="cuda")
@@ -658,13 +674,13 @@ def profile_run(torch, args):
         b.copy_(a)
     torch.cuda.synchronize()
     del a, b
-    kw = dict(HEADLINE, precision=args.precision)
+    kw = dict(HEADLINE, precision=args.precision, **PROFILE_VARIANTS[args.variant])
     ch = Channel(**kw, stream=torch.cuda.Stream())
     if args.developed:
         ch.load_state(torch.from_numpy(random_populations(4096, 4096, seed=5, b0=0.0023)))
     _, per_step, ch = time_channel(torch, Channel, kw, args.steps, args.warmup, channel=ch)
     ch.close()
-    print(json.dumps({"profile_run": True, "precision": args.precision,
+    print(json.dumps({"profile_run": True, "precision": args.precision, "variant": args.variant,
                       "developed": bool(args.developed), "steps": args.steps,
                       "per_step_ms": per_step * 1e3}))
 
@@ -813,7 +829,10 @@ def main():
     ap.add_argument("--precision", default="fp32", help="storage precision of --profile-run")
     ap.add_argument("--developed", action="store_true",
                     help="--profile-run on the developed random state instead of from rest")
-    ap.add_argument("--profile-3d", action="store_true", help="3D FP32 steps only (profiling)")
+    ap.add_argument("--variant", default="headline", choices=sorted(PROFILE_VARIANTS),
+                    help="--profile-run: the headline channel with this leg's scheme")
+    ap.add_argument("--profile-3d", action="store_true", help="3D steps only (profiling)")
+    ap.add_argument("--duct", action="store_true", help="--profile-3d: a duct (side walls)")
     ap.add_argument("--profile-batch", action="store_true",
                     help="256-channel batch steps only, in --precision (profiling)")
     ap.add_argument("--only", choices=sorted(LEGS), help="run one extra leg and print it")
