@@ -90,9 +90,11 @@ template <typename C> __device__ __forceinline__ const Coef<C> &coef_of(const Ch
 template <> __device__ __forceinline__ const Coef<float> &coef_of<float>(const ChanDesc &c) { return c.kf; }
 template <> __device__ __forceinline__ const Coef<double> &coef_of<double>(const ChanDesc &c) { return c.kd; }
 
-// Waves per SIMD the step asks the compiler for (1: no constraint).  FP32
-// storage asks for what it reaches without spilling: 6 with the BGK schemes
-// alone, 5 with the TRT/MRT ones.
+// Waves per SIMD the step asks the compiler for (1: no constraint).  Every
+// variant runs unconstrained: FP32 storage takes 82 registers (5 waves) with
+// the BGK schemes alone and 112 (4) with the TRT/MRT ones; binary16 with
+// FP32 arithmetic 93 (5), with FP64 arithmetic 104 (4).  Asking the FP32
+// BGK step for 6 waves spills.
 template <typename S, typename C, int MODE, bool TRT>
 constexpr int kBatchWaves = 1;
 
