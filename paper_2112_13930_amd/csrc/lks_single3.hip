@@ -27,13 +27,13 @@ constexpr int NRED3 = 6; // du2, u2, db2, b2, sum_u, nonfinite
 // launch), so residual partial sums keep one fixed order.  ctr[2]: step
 // counters as in the two-dimensional kernel; only the launch with owner set
 // advances them.
-// Waves per SIMD: the step is bound by how many waves keep memory requests
-// in flight.  The binary32 interior kernel fits 5 waves (at most 102
-// registers) without spilling; the others take 4 (at most 128), except the
-// MRT kernels in FP64, which spill at 4 and run as fast as TRT at 3 (154
-// registers).
+// Waves per SIMD: 4 (at most 128 registers), except the MRT kernels in FP64,
+// which spill at 4 and run as fast as TRT at 3 (154 registers).  The
+// binary32 interior kernel also fits 5 (at most 96 registers) with two
+// registers spilled, which ran 1% slower than 4 (20.6 against 20.8 G
+// node-updates/s at 256^3, one box, alternating builds).
 #ifndef LKS_STEP3_WAVES_FP32_INTERIOR
-#define LKS_STEP3_WAVES_FP32_INTERIOR 5
+#define LKS_STEP3_WAVES_FP32_INTERIOR 4
 #endif
 template <typename S, int BC>
 constexpr int kWaves3 =
